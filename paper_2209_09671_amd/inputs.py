@@ -1,0 +1,265 @@
+"""Seeded synthetic inputs: parameter sheets and initial fields.
+
+This module is shared by the GPU path, its tests, the benchmark and the
+oracle's tests.  It holds no arithmetic of the method itself: it only builds
+parameter dictionaries and initial states (smoothed indicator profiles, a
+temperature ramp, a prescribed divergence-free velocity for transport-only
+checks).
+
+The workloads stand in for the paper's two experiments (Section "Numerical
+experiments"): the thermocapillary droplet of Ma and Bothe (Table I) and the
+laser powder-bed single track (Table II).  The case files of those experiments
+are not available, so every field here is synthetic and seeded.
+
+Array layout (both solvers): C order with shape (nz, ny, nx) for cell fields
+(x fastest), (nz, ny, nx+1) for x-face velocity, (nz, ny+1, nx) for y-face,
+(nz+1, ny, nx) for z-face.  In 2D nz == 1 and there is no z-face array.
+Phase 1 (alpha = 0) is the ambient fluid, phase 2 (alpha = 1) the drop/metal.
+"""
+from __future__ import annotations
+
+import copy
+import math
+
+import numpy as np
+
+# Wall order for the temperature boundary arrays: -x, +x, -y, +y, -z, +z.
+NEUMANN, DIRICHLET = 0, 1
+
+_DEFAULTS = dict(
+    precision=0,          # 0 = FP64, 1 = FP32 stencils + FP64 refinement
+    flags=0,
+    weno_eps=1e-6,
+    p_rtol=1e-13,
+    p_maxit=200,
+    inner_rtol=1e-5,
+    refine_maxit=30,
+    mg_levels=0,          # 0 = as many as the grid allows
+    mg_nu=2,
+    q_power=0.0, q_radius=1.0, q_x0=0.0, q_y0=0.0, q_vx=0.0, q_vy=0.0,
+)
+
+
+def _droplet_2d(n, steps, dt, name):
+    h = 1.0 / n
+    c = dict(_DEFAULTS)
+    c.update(name=name, dim=2, nx=n, ny=n, nz=1, h=h,
+             rho1=1.0, rho2=2.0, mu1=0.01, mu2=0.02,
+             rhocp1=1.0, rhocp2=4.0, lambda1=1e-3, lambda2=2e-3,
+             sigma0=1.0, dsigma_dT=-0.1, T0=0.0,
+             T_bc=[NEUMANN, NEUMANN, DIRICHLET, DIRICHLET, NEUMANN, NEUMANN],
+             T_wall=[0.0, 0.0, 0.0, 1.0, 0.0, 0.0],
+             normal_eps=1e-6 / h, dt=dt, steps=steps)
+    return c
+
+
+def _meltpool_3d(nx, ny, nz, h, steps, dt, name, seed):
+    c = dict(_DEFAULTS)
+    lx, ly = nx * h, ny * h
+    c.update(name=name, dim=3, nx=nx, ny=ny, nz=nz, h=h,
+             rho1=1.0, rho2=7500.0, mu1=2e-5, mu2=5e-3,
+             rhocp1=1900.0, rhocp2=7500.0 * 790.0, lambda1=0.02, lambda2=6.6,
+             sigma0=1.908, dsigma_dT=-4e-4, T0=1700.0,
+             T_bc=[NEUMANN] * 6, T_wall=[0.0] * 6,
+             q_power=200.0, q_radius=40e-6, q_x0=lx / 4.0, q_y0=ly / 2.0,
+             q_vx=0.5, q_vy=0.0,
+             normal_eps=1e-6 / h, dt=dt, steps=steps, precision=1,
+             p_rtol=1e-10, seed=seed)
+    return c
+
+
+def config(idx: int) -> dict:
+    """Parameter sheet of workload ``idx`` (0..4); a fresh dict each call."""
+    if idx == 0:
+        c = _droplet_2d(64, 100, 1e-4, "droplet2d-64")
+        c.update(drop_centre=[0.5, 0.4], drop_radius=0.2)
+    elif idx == 1:
+        c = _droplet_2d(512, 1000, 2e-5, "droplet2d-512-perturbed")
+        c.update(drop_centre=[0.5, 0.4], drop_radius=0.2, perturb_seed=1,
+                 perturb_amp=0.01)
+    elif idx == 2:
+        c = _meltpool_3d(128, 64, 64, 5e-6, 2000, 1e-8, "meltpool-128x64x64", 2)
+    elif idx == 3:
+        n = 96
+        h = 1.0 / n
+        c = dict(_DEFAULTS)
+        c.update(name="droplet3d-96", dim=3, nx=n, ny=n, nz=n, h=h,
+                 rho1=1.0, rho2=2.0, mu1=0.01, mu2=0.02,
+                 rhocp1=1.0, rhocp2=4.0, lambda1=1e-3, lambda2=2e-3,
+                 sigma0=1.0, dsigma_dT=-0.2, T0=0.0,
+                 T_bc=[NEUMANN, NEUMANN, NEUMANN, NEUMANN, DIRICHLET, DIRICHLET],
+                 T_wall=[0.0, 0.0, 0.0, 0.0, 0.0, 1.0],
+                 normal_eps=1e-6 / h, dt=1e-4, steps=200,
+                 drop_centre=[0.5, 0.5, 0.4], drop_radius=0.25,
+                 checkpoint_every=20, target_seed=3)
+    elif idx == 4:
+        c = _meltpool_3d(256, 256, 256, 2.5e-6, 5000, 1e-8, "meltpool-256^3", 4)
+        c.update(adjoint_steps=200, checkpoint_every=25)
+    else:
+        raise ValueError(f"no workload {idx}")
+    c["index"] = idx
+    return c
+
+
+def custom(base: dict, **over) -> dict:
+    """Copy of ``base`` with fields replaced (grid changes keep h = 1/nx
+    for unit-box droplets unless h is given)."""
+    c = copy.deepcopy(base)
+    c.update(over)
+    if ("nx" in over or "ny" in over or "nz" in over) and "h" not in over \
+            and base.get("dim") and base.get("rho2", 0) < 100:
+        c["h"] = 1.0 / c["nx"]
+        c["normal_eps"] = 1e-6 / c["h"]
+    return c
+
+
+# ----------------------------------------------------------------------------
+# geometry helpers
+def cell_centres(c):
+    h = c["h"]
+    x = (np.arange(c["nx"]) + 0.5) * h
+    y = (np.arange(c["ny"]) + 0.5) * h
+    z = (np.arange(c["nz"]) + 0.5) * h
+    return x, y, z
+
+
+def shapes(c):
+    nx, ny, nz = c["nx"], c["ny"], c["nz"]
+    s = dict(cell=(nz, ny, nx), u=(nz, ny, nx + 1), v=(nz, ny + 1, nx))
+    s["w"] = (nz + 1, ny, nx) if c["dim"] == 3 else None
+    return s
+
+
+def _smooth_step(signed_dist, width):
+    """Indicator 1 on the positive side with a tanh edge of length scale width."""
+    return 0.5 * (1.0 + np.tanh(signed_dist / width))
+
+
+def _radius_perturbation(seed, amp, modes=range(2, 9)):
+    """Fourier series in the polar angle, modes 2..8, scaled so that its
+    maximum modulus over the angle is ``amp``; returns a callable."""
+    rng = np.random.default_rng(seed)
+    ms = np.array(list(modes))
+    a = rng.standard_normal(len(ms))
+    b = rng.standard_normal(len(ms))
+    th = np.linspace(0.0, 2 * np.pi, 20001)
+    raw = (a[:, None] * np.cos(ms[:, None] * th) + b[:, None] * np.sin(ms[:, None] * th)).sum(0)
+    scale = amp / np.abs(raw).max()
+
+    def f(theta):
+        return scale * (a[:, None, None] * np.cos(ms[:, None, None] * theta)
+                        + b[:, None, None] * np.sin(ms[:, None, None] * theta)).sum(0)
+    return f
+
+
+def _surface_roughness(seed, nx, ny, h, modes=range(2, 9)):
+    """Seeded Fourier sum in x and y (modes 2..8 along each axis) sampled at
+    cell centres, scaled to maximum modulus 1."""
+    rng = np.random.default_rng(seed)
+    lx, ly = nx * h, ny * h
+    x = (np.arange(nx) + 0.5) * h
+    y = (np.arange(ny) + 0.5) * h
+    r = np.zeros((ny, nx))
+    for m in modes:
+        a, b, cc, d = rng.standard_normal(4)
+        r += (a * np.cos(2 * np.pi * m * x / lx) + b * np.sin(2 * np.pi * m * x / lx))[None, :]
+        r += (cc * np.cos(2 * np.pi * m * y / ly) + d * np.sin(2 * np.pi * m * y / ly))[:, None]
+    return r / np.abs(r).max()
+
+
+def initial_state(c) -> dict:
+    """Initial (alpha, T, u, v, w, p) of a workload as float64 numpy arrays."""
+    s = shapes(c)
+    h = c["h"]
+    x, y, z = cell_centres(c)
+    width = 1.5 * h
+    if c["dim"] == 2:
+        Y, X = np.meshgrid(y, x, indexing="ij")
+        X, Y = X[None], Y[None]
+    else:
+        Z, Y, X = np.meshgrid(z, y, x, indexing="ij")
+    if "drop_radius" in c:
+        ctr = c["drop_centre"]
+        dx, dy = X - ctr[0], Y - ctr[1]
+        if c["dim"] == 2:
+            r = np.hypot(dx, dy)
+            R = c["drop_radius"] * np.ones_like(r)
+            if c.get("perturb_seed") is not None:
+                f = _radius_perturbation(c["perturb_seed"], c["perturb_amp"])
+                R = c["drop_radius"] * (1.0 + f(np.arctan2(dy, dx)))
+        else:
+            r = np.sqrt(dx * dx + dy * dy + (Z - ctr[2]) ** 2)
+            R = c["drop_radius"]
+        alpha = _smooth_step(R - r, width)
+        vert = Y if c["dim"] == 2 else Z
+        T = np.array(vert, dtype=np.float64)       # T equals the vertical coordinate
+    else:
+        lz = c["nz"] * h
+        zs = lz / 2.0 + h * _surface_roughness(c["seed"], c["nx"], c["ny"], h)
+        alpha = _smooth_step(zs[None, :, :] - Z, width)
+        T = np.full(s["cell"], c["T0"])
+    st = dict(alpha=np.ascontiguousarray(alpha.reshape(s["cell"]), dtype=np.float64),
+              T=np.ascontiguousarray(T.reshape(s["cell"]), dtype=np.float64),
+              u=np.zeros(s["u"]), v=np.zeros(s["v"]),
+              w=np.zeros(s["w"]) if s["w"] else None,
+              p=np.zeros(s["cell"]))
+    return st
+
+
+def stream_velocity(c, amp=1.0):
+    """Discretely divergence-free MAC velocity from face differences of the
+    corner stream function psi = sin^2(pi x) sin^2(pi y)/pi (times cos(pi z)
+    in 3D), zero on every wall face.  Used to drive transport-only checks."""
+    nx, ny, nz, h = c["nx"], c["ny"], c["nz"], c["h"]
+    lx, ly, lz = nx * h, ny * h, nz * h
+    xn = np.arange(nx + 1) * h
+    yn = np.arange(ny + 1) * h
+    psi = (np.sin(np.pi * xn / lx)[None, :] ** 2 * np.sin(np.pi * yn / ly)[:, None] ** 2) / np.pi
+    if c["dim"] == 3:
+        zc = (np.arange(nz) + 0.5) * h
+        g = (0.5 + 0.5 * np.cos(np.pi * zc / lz))[:, None, None]
+    else:
+        g = np.ones((1, 1, 1))
+    u = amp * g * (psi[1:, :] - psi[:-1, :])[None] / h          # (nz, ny, nx+1)
+    v = -amp * g * (psi[:, 1:] - psi[:, :-1])[None] / h         # (nz, ny+1, nx)
+    w = np.zeros((nz + 1, ny, nx)) if c["dim"] == 3 else None
+    return (np.ascontiguousarray(u), np.ascontiguousarray(v), w)
+
+
+def random_fields(c, seed, scale=1.0):
+    """Smooth-ish random fields for operator checks (not physical)."""
+    rng = np.random.default_rng(seed)
+    s = shapes(c)
+    out = {k: scale * rng.standard_normal(v) if v else None for k, v in s.items()}
+    return out
+
+
+def target_centroid(c):
+    """Seeded target for the droplet centroid loss: initial centroid of the
+    indicator plus a uniform offset in [-0.02, 0.02]^3."""
+    rng = np.random.default_rng(c.get("target_seed", 3))
+    return rng.uniform(-0.02, 0.02, 3)
+
+
+def t_directions(c, k=16, seed=3):
+    """Seeded unit directions in the space of initial temperature fields."""
+    rng = np.random.default_rng(seed + 1000)
+    d = rng.standard_normal((k,) + shapes(c)["cell"])
+    d /= np.sqrt((d.reshape(k, -1) ** 2).sum(1)).reshape((k,) + (1,) * 3)
+    return d
+
+
+def describe(c) -> str:
+    return f"{c['name']} ({c['nx']}x{c['ny']}x{c['nz']}, h={c['h']:.3g})"
+
+
+__all__ = ["config", "custom", "initial_state", "stream_velocity", "shapes",
+           "random_fields", "cell_centres", "target_centroid", "t_directions",
+           "describe", "NEUMANN", "DIRICHLET"]
+
+if __name__ == "__main__":  # pragma: no cover
+    for i in range(4):
+        c = config(i)
+        st = initial_state(c)
+        print(describe(c), {k: (None if v is None else v.shape) for k, v in st.items()},
+              float(st["alpha"].sum()), math.isfinite(float(st["T"].sum())))

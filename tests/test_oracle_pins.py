@@ -1,0 +1,609 @@
+"""Pins of the FP64 CPU oracle against what the mathematics and the paper fix.
+
+Each test names the property it pins and the part of the method it covers.
+None of them compares the oracle with itself: expected values come from
+closed forms, library routines (DCT, dense least squares, quadrature),
+convergence orders, conservation and symmetry invariants, and the signs the
+paper states (the droplet migrates toward hotter fluid, Section "Marangoni
+Flow around a droplet"; the Marangoni term vanishes iff surface-tension
+gradients exist, discussion of eq. 4).
+"""
+import math
+
+import numpy as np
+import pytest
+import scipy.fft
+import scipy.integrate
+
+from oracle import pyoracle as O
+from paper_2209_09671_amd import inputs as I
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / max(np.linalg.norm(np.ravel(b)), 1e-300))
+
+
+def box2d(n, **over):
+    c = I.custom(I.config(0), nx=n, ny=n)
+    c.update(over)
+    return c
+
+
+def box3d(n, **over):
+    c = I.custom(I.config(3), nx=n, ny=n, nz=n)
+    c.update(over)
+    return c
+
+
+# ---------------------------------------------------------------------------
+# WENO5-JS algebra (Jiang & Shu 1996), used for every convective term.
+def test_weno_equal_smoothness_gives_linear_formula():
+    # linear data: all three smoothness indicators equal 1 -> linear weights
+    a, b, c, d, e = 0.0, 1.0, 2.0, 3.0, 4.0
+    assert O.weno5(a, b, c, d, e) == pytest.approx((2 * a - 13 * b + 47 * c + 27 * d - 3 * e) / 60, abs=1e-15)
+    rng = np.random.default_rng(0)
+    for _ in range(20):
+        q = rng.standard_normal(5)
+        lin = (2 * q[0] - 13 * q[1] + 47 * q[2] + 27 * q[3] - 3 * q[4]) / 60
+        assert O.weno5(*q, eps=1e30) == pytest.approx(lin, rel=1e-12, abs=1e-14)
+
+
+@pytest.mark.parametrize("p", [0, 1, 2, 3, 4])
+def test_weno_linear_weights_exact_for_quartics(p):
+    # cell averages of x^p over unit cells centred at -2..2; value at x = 1/2
+    avg = [((m + 0.5) ** (p + 1) - (m - 0.5) ** (p + 1)) / (p + 1) for m in range(-2, 3)]
+    assert O.weno5(*avg, eps=1e30) == pytest.approx(0.5 ** p, abs=1e-13)
+
+
+def test_weno_essentially_non_oscillatory_at_a_jump():
+    assert abs(O.weno5(0, 0, 0, 1, 1)) < 1e-9
+    assert abs(O.weno5(0, 0, 1, 1, 1) - 1.0) < 1e-9
+
+
+def _periodic_advection_error(n):
+    c = box2d(n, ny=1, lambda1=0.0, lambda2=0.0)
+    c["T_bc"] = [0] * 6
+    h = c["h"]
+    x = np.arange(n + 1) * h
+    exact = ((np.cos(2 * np.pi * x[:-1]) - np.cos(2 * np.pi * x[1:])) / (2 * np.pi * h)).reshape(1, 1, n)
+    st = dict(alpha=exact.copy(), T=np.zeros((1, 1, n)), u=np.ones((1, 1, n + 1)),
+              v=np.zeros((1, 2, n)), w=None, p=np.zeros((1, 1, n)))
+    nsteps = int(math.ceil(1.0 / (0.4 * h ** (5.0 / 3.0))))
+    s, _, _ = O.step(c, st, 0.0, 1.0 / nsteps, nsteps, flags=O.F_TRANSPORT_ONLY | O.F_PERIODIC)
+    return h * np.abs(s["alpha"] - exact).sum()
+
+
+def test_weno_rk3_fifth_order_on_periodic_advection():
+    """Pin (a): WENO5 + SSP-RK3 on smooth periodic advection for one period."""
+    ns = [32, 64, 128, 256]
+    err = [_periodic_advection_error(n) for n in ns]
+    orders = [math.log2(err[i] / err[i + 1]) for i in range(len(ns) - 1)]
+    assert min(orders) >= 4.8, (err, orders)
+
+
+def test_upwind_mirror_symmetry():
+    """Advecting a profile to the right equals advecting its mirror image to
+    the left (catches index errors in the right-biased branch)."""
+    n = 32
+    c = box2d(n, ny=1, lambda1=0.0, lambda2=0.0)
+    c["T_bc"] = [0] * 6
+    rng = np.random.default_rng(1)
+    a0 = rng.random((1, 1, n))
+    mk = lambda a, u: dict(alpha=a, T=np.zeros((1, 1, n)), u=np.full((1, 1, n + 1), u),
+                           v=np.zeros((1, 2, n)), w=None, p=np.zeros((1, 1, n)))
+    f = O.F_TRANSPORT_ONLY | O.F_PERIODIC
+    s1, _, _ = O.step(c, mk(a0, 1.0), 0.0, 0.2 * c["h"], 5, flags=f)
+    s2, _, _ = O.step(c, mk(a0[..., ::-1].copy(), -1.0), 0.0, 0.2 * c["h"], 5, flags=f)
+    assert np.array_equal(s1["alpha"], s2["alpha"][..., ::-1])
+
+
+def test_uniform_field_stays_uniform_under_divergence_free_flow():
+    c = box2d(32)
+    u, v, _ = I.stream_velocity(c, 0.5)
+    st = dict(alpha=np.full((1, 32, 32), 0.3), T=np.full((1, 32, 32), 0.0), u=u, v=v, w=None,
+              p=np.zeros((1, 32, 32)))
+    c["T_bc"] = [0] * 6
+    s, _, _ = O.step(c, st, 0.0, 1e-3, 10, flags=O.F_TRANSPORT_ONLY)
+    assert np.abs(s["alpha"] - 0.3).max() < 1e-14
+
+
+# ---------------------------------------------------------------------------
+# Energy equation pieces (conduction, heat source).
+def test_conduction_cosine_mode_matches_rk3_amplification():
+    """cos(pi x) at cell centres is a discrete Neumann eigenvector; with u = 0
+    one RK3 step multiplies it by 1 + z + z^2/2 + z^3/6."""
+    n = 32
+    c = box2d(n, lambda1=2e-3, lambda2=2e-3, rhocp1=3.0, rhocp2=3.0)
+    c["T_bc"] = [0] * 6
+    h = c["h"]
+    x = (np.arange(n) + 0.5) * h
+    T0 = np.tile(np.cos(np.pi * x), (n, 1)).reshape(1, n, n)
+    st = dict(alpha=np.zeros((1, n, n)), T=T0, u=np.zeros((1, n, n + 1)), v=np.zeros((1, n + 1, n)),
+              w=None, p=np.zeros((1, n, n)))
+    dt = 0.05
+    s, _, _ = O.step(c, st, 0.0, dt, 1, flags=O.F_TRANSPORT_ONLY)
+    lam = -(4.0 / h ** 2) * np.sin(np.pi / (2 * n)) ** 2
+    z = dt * 2e-3 / 3.0 * lam
+    assert rel(s["T"], T0 * (1 + z + z * z / 2 + z ** 3 / 6)) < 1e-13
+
+
+def test_dirichlet_linear_profile_is_steady():
+    c = box2d(32)
+    st = I.initial_state(c)
+    st["alpha"][:] = 0.0
+    s, _, _ = O.step(c, st, 0.0, 1e-3, 5, flags=O.F_TRANSPORT_ONLY)
+    assert np.abs(s["T"] - st["T"]).max() < 1e-14
+
+
+def test_heat_source_energy_balance():
+    """With u = 0 and no conduction the source is constant over the step, so
+    sum(rho c_p dT) h^3 = dt sum(Q delta_s) h^3, and that sum approximates the
+    absorbed power P (flat interface, beam well inside the box)."""
+    c = I.custom(I.config(2), nx=48, ny=48, nz=24, lambda1=0.0, lambda2=0.0, q_x0=120e-6, q_y0=120e-6)
+    st = I.initial_state(c)
+    h, dt = c["h"], 1e-8
+    z = (np.arange(24) + 0.5) * h
+    a = 0.5 * (1 - np.tanh((z - 12.2 * h) / (1.5 * h)))
+    st["alpha"] = a = np.ascontiguousarray(np.broadcast_to(a[:, None, None], (24, 48, 48)))
+    s, _, _ = O.step(c, st, 0.0, dt, 1, flags=O.F_TRANSPORT_ONLY)
+    rhocp = c["rhocp1"] + np.clip(a, 0, 1) * (c["rhocp2"] - c["rhocp1"])
+    energy = float((rhocp * (s["T"] - st["T"])).sum() * h ** 3)
+    assert energy == pytest.approx(dt * c["q_power"], rel=2e-3)
+
+
+def test_heat_flux_gaussian_normalisation():
+    c = I.config(2)
+    r = c["q_radius"]
+    val = O.heat_flux(c, c["q_x0"], c["q_y0"], 0.0)
+    assert val == pytest.approx(2 * c["q_power"] / (np.pi * r * r), rel=1e-14)
+    # 1/e^2 radius
+    assert O.heat_flux(c, c["q_x0"] + r, c["q_y0"], 0.0) == pytest.approx(val * np.exp(-2), rel=1e-13)
+    # beam moves with the scan speed
+    assert O.heat_flux(c, c["q_x0"] + 0.5 * 1e-5, c["q_y0"], 1e-5) == pytest.approx(val, rel=1e-14)
+
+
+# ---------------------------------------------------------------------------
+# Pressure Poisson operator and solver.
+def _manufactured(n, dim):
+    c = box2d(n) if dim == 2 else box3d(n)
+    c["rho1"], c["rho2"] = 1.0, 3.0
+    h = c["h"]
+    x = (np.arange(n) + 0.5) * h
+    if dim == 2:
+        Y, X = np.meshgrid(x, x, indexing="ij")
+        Z = None
+        al = 0.5 + 0.4 * np.sin(np.pi * X) * np.cos(np.pi * Y)
+        gx = 0.4 * np.pi * np.cos(np.pi * X) * np.cos(np.pi * Y)
+        gy = -0.4 * np.pi * np.sin(np.pi * X) * np.sin(np.pi * Y)
+        p = np.cos(np.pi * X) * np.cos(np.pi * Y)
+        px = -np.pi * np.sin(np.pi * X) * np.cos(np.pi * Y)
+        py = -np.pi * np.cos(np.pi * X) * np.sin(np.pi * Y)
+        lap = -2 * np.pi ** 2 * p
+        grads = [(gx, px), (gy, py)]
+    else:
+        Z, Y, X = np.meshgrid(x, x, x, indexing="ij")
+        al = 0.5 + 0.4 * np.sin(np.pi * X) * np.cos(np.pi * Y) * np.cos(np.pi * Z)
+        gx = 0.4 * np.pi * np.cos(np.pi * X) * np.cos(np.pi * Y) * np.cos(np.pi * Z)
+        gy = -0.4 * np.pi * np.sin(np.pi * X) * np.sin(np.pi * Y) * np.cos(np.pi * Z)
+        gz = -0.4 * np.pi * np.sin(np.pi * X) * np.cos(np.pi * Y) * np.sin(np.pi * Z)
+        p = np.cos(np.pi * X) * np.cos(np.pi * Y) * np.cos(np.pi * Z)
+        px = -np.pi * np.sin(np.pi * X) * np.cos(np.pi * Y) * np.cos(np.pi * Z)
+        py = -np.pi * np.cos(np.pi * X) * np.sin(np.pi * Y) * np.cos(np.pi * Z)
+        pz = -np.pi * np.cos(np.pi * X) * np.cos(np.pi * Y) * np.sin(np.pi * Z)
+        lap = -3 * np.pi ** 2 * p
+        grads = [(gx, px), (gy, py), (gz, pz)]
+    rho = c["rho1"] + al * (c["rho2"] - c["rho1"])
+    beta = 1.0 / rho
+    # div(beta grad p) = beta lap p + grad(beta) . grad p, grad beta = -(rho2-rho1) grad(alpha)/rho^2
+    f = beta * lap
+    for ga, gp in grads:
+        f = f - (c["rho2"] - c["rho1"]) * ga / rho ** 2 * gp
+    shape = (1, n, n) if dim == 2 else (n, n, n)
+    return c, al.reshape(shape), f.reshape(shape), p.reshape(shape)
+
+
+@pytest.mark.parametrize("dim,ns", [(2, [16, 32, 64, 128]), (3, [8, 16, 32])])
+def test_poisson_second_order_manufactured(dim, ns):
+    """Pin (b): variable-coefficient Poisson with beta = 1/rho(alpha(x))."""
+    errs = []
+    for n in ns:
+        c, al, f, pex = _manufactured(n, dim)
+        p, st, info = O.solve_pressure(c, al, f, rtol=1e-12)
+        assert st == 0
+        pex = pex - pex.mean()
+        errs.append(np.sqrt(np.mean((p - pex) ** 2)))
+    orders = [math.log2(errs[i] / errs[i + 1]) for i in range(len(errs) - 1)]
+    assert min(orders) >= 1.9, (errs, orders)
+
+
+def _dct_solve(b, h, beta, dim):
+    bb = b.reshape(b.shape[-dim:]) if dim == 2 else b
+    bh = scipy.fft.dctn(bb, type=2, norm="ortho")
+    lam = 0.0
+    for ax, n in enumerate(bb.shape):
+        k = np.arange(n)
+        shp = [1] * bb.ndim
+        shp[ax] = n
+        lam = lam + (-(4.0 / h ** 2) * np.sin(np.pi * k / (2 * n)) ** 2).reshape(shp)
+    lam = beta * lam
+    ph = np.zeros_like(bh)
+    nz = lam != 0
+    ph[nz] = bh[nz] / lam[nz]
+    return scipy.fft.idctn(ph, type=2, norm="ortho").reshape(b.shape)
+
+
+@pytest.mark.parametrize("dim,n", [(2, 32), (2, 64), (3, 16)])
+def test_poisson_constant_beta_matches_dct_exact_solve(dim, n):
+    """Pin (P4): with constant beta the Neumann operator is diagonalised by the
+    DCT-II, so the discrete solution is known to round-off."""
+    c = box2d(n) if dim == 2 else box3d(n)
+    shape = (1, n, n) if dim == 2 else (n, n, n)
+    rng = np.random.default_rng(3)
+    b = rng.standard_normal(shape)
+    b -= b.mean()
+    al = np.zeros(shape)          # rho = rho1 everywhere
+    p, st, _ = O.solve_pressure(c, al, b, rtol=1e-14)
+    assert st == 0
+    pd = _dct_solve(b, c["h"], 1.0 / c["rho1"], dim)
+    pd -= pd.mean()
+    assert rel(p, pd) < 1e-11
+
+
+def test_poisson_tiny_grid_matches_dense_lstsq():
+    n = 8
+    c = box2d(n)
+    rng = np.random.default_rng(4)
+    al = rng.random((1, n, n))
+    N = n * n
+    Amat = np.zeros((N, N))
+    for j in range(N):
+        e = np.zeros(N)
+        e[j] = 1.0
+        Amat[:, j] = O.apply_A(c, al, e.reshape(1, n, n)).ravel()
+    # independent assembly of the same operator from its definition
+    h = c["h"]
+    rho = c["rho1"] + np.clip(al[0], 0, 1) * (c["rho2"] - c["rho1"])
+    B = np.zeros((N, N))
+    for j in range(n):
+        for i in range(n):
+            r = i + n * j
+            for (ii, jj) in [(i - 1, j), (i + 1, j), (i, j - 1), (i, j + 1)]:
+                if 0 <= ii < n and 0 <= jj < n:
+                    beta = 1.0 / (0.5 * (rho[j, i] + rho[jj, ii]))
+                    B[r, ii + n * jj] += beta / h ** 2
+                    B[r, r] -= beta / h ** 2
+    assert np.abs(Amat - B).max() < 1e-10 * np.abs(B).max()
+    b = rng.standard_normal(N)
+    b -= b.mean()
+    pl = np.linalg.lstsq(B, b, rcond=None)[0]
+    pl -= pl.mean()
+    p, st, _ = O.solve_pressure(c, al, b.reshape(1, n, n), rtol=1e-14)
+    assert st == 0 and rel(p.ravel(), pl) < 1e-12
+
+
+def test_operator_algebra_symmetry_and_adjoint_pair():
+    """Pin (P14): A symmetric, D = -G^T, V-cycle preconditioner symmetric and
+    positive on mean-free vectors."""
+    c = I.config(0)
+    st = I.initial_state(c)
+    al = st["alpha"]
+    rng = np.random.default_rng(5)
+    x, y = rng.standard_normal((2,) + al.shape)
+    Ax, Ay = O.apply_A(c, al, x), O.apply_A(c, al, y)
+    assert abs(np.vdot(Ax, y) - np.vdot(x, Ay)) < 1e-14 * np.linalg.norm(Ax) * np.linalg.norm(y)
+    # G p at interior faces: project a zero predictor with dt = 1 and rho = 1
+    cc = dict(c, rho1=1.0, rho2=1.0)
+    zero = np.zeros_like(al)
+    u, v, _ = O.project(cc, 1.0, zero, x, np.zeros_like(st["u"]), np.zeros_like(st["v"]))
+    Gx = (-u, -v)
+    uu = rng.standard_normal(st["u"].shape)
+    vv = rng.standard_normal(st["v"].shape)
+    uu[..., 0] = uu[..., -1] = 0.0
+    vv[:, 0, :] = vv[:, -1, :] = 0.0
+    Du = O.divergence(c, uu, vv)
+    lhs = np.vdot(Du, x)
+    rhs = -(np.vdot(uu, Gx[0]) + np.vdot(vv, Gx[1]))
+    assert abs(lhs - rhs) < 1e-12 * abs(lhs)
+    # A = D beta G with beta = 1
+    assert rel(O.divergence(c, *Gx), O.apply_A(cc, zero, x)) < 1e-13
+    xm, ym = x - x.mean(), y - y.mean()
+    Mx, My = O.apply_mg(c, al, xm), O.apply_mg(c, al, ym)
+    assert abs(np.vdot(Mx, ym) - np.vdot(xm, My)) < 1e-13 * np.linalg.norm(Mx) * np.linalg.norm(ym)
+    assert np.vdot(Mx, xm) > 0
+
+
+# ---------------------------------------------------------------------------
+# Projection and conservation.
+def test_projection_divergence_free_and_idempotent():
+    """Pin (c): ||D u^{n+1}|| / ||D u*|| <= 1e-12 and P(P u) = P u."""
+    c = I.config(0)
+    st = I.initial_state(c)
+    dt = c["dt"]
+    us, vs, _ = O.predictor(c, dt, st["alpha"], st["T"], st["u"], st["v"])
+    b = O.divergence(c, us, vs) / dt
+    p, stt, _ = O.solve_pressure(c, st["alpha"], b, rtol=1e-13)
+    u, v, _ = O.project(c, dt, st["alpha"], p, us, vs)
+    d0, d1 = O.divergence(c, us, vs), O.divergence(c, u, v)
+    assert np.linalg.norm(d1) <= 1e-12 * np.linalg.norm(d0)
+    b2 = O.divergence(c, u, v) / dt
+    p2, _, _ = O.solve_pressure(c, st["alpha"], b2, rtol=1e-13)
+    u2, v2, _ = O.project(c, dt, st["alpha"], p2, u, v)
+    assert rel(u2, u) < 1e-12 and rel(v2, v) < 1e-12
+
+
+def test_projection_3d_random_predictor():
+    c = box3d(16, rho2=500.0)
+    st = I.initial_state(c)
+    rng = np.random.default_rng(6)
+    us, vs, ws = (rng.standard_normal(st[k].shape) for k in ("u", "v", "w"))
+    us[..., 0] = us[..., -1] = 0.0
+    vs[:, 0, :] = vs[:, -1, :] = 0.0
+    ws[0] = ws[-1] = 0.0
+    b = O.divergence(c, us, vs, ws)
+    p, stt, _ = O.solve_pressure(c, st["alpha"], b, rtol=1e-13)
+    u, v, w = O.project(c, 1.0, st["alpha"], p, us, vs, ws)
+    assert np.linalg.norm(O.divergence(c, u, v, w)) <= 1e-12 * np.linalg.norm(b)
+
+
+def test_alpha_conservation_full_steps():
+    """Pin (d): sum(alpha) is conserved to round-off (telescoping fluxes,
+    zero wall velocity), here with a vigorous prescribed flow and full steps."""
+    c = I.config(0)
+    st = I.initial_state(c)
+    st["u"], st["v"], _ = I.stream_velocity(c, 0.5)
+    s0 = st["alpha"].sum()
+    s, info, _ = O.step(c, st, 0.0, 1e-3, 1, flags=O.F_TRANSPORT_ONLY)
+    assert abs(s["alpha"].sum() - s0) <= 1e-13 * s0
+    s, info, stt = O.step(c, I.initial_state(c), 0.0, c["dt"], 20)
+    assert stt == 0
+    assert abs(info["sum_alpha"] - s0) <= 20 * 1e-13 * s0
+
+
+def test_alpha_conservation_3d_transport():
+    c = box3d(24)
+    st = I.initial_state(c)
+    st["u"], st["v"], st["w"] = I.stream_velocity(c, 0.5)
+    s0 = st["alpha"].sum()
+    s, _, _ = O.step(c, st, 0.0, 2e-3, 3, flags=O.F_TRANSPORT_ONLY)
+    assert abs(s["alpha"].sum() - s0) <= 3e-13 * s0
+
+
+# ---------------------------------------------------------------------------
+# Surface tension: eqs. 4-7.
+def _static_drop(dim, n, R):
+    if dim == 2:
+        c = box2d(n, dsigma_dT=0.0, drop_centre=[0.5, 0.5], drop_radius=R)
+    else:
+        c = box3d(n, dsigma_dT=0.0, drop_centre=[0.5, 0.5, 0.5], drop_radius=R)
+    c["T_bc"] = [0] * 6
+    st = I.initial_state(c)
+    st["T"][:] = 0.0
+    return c, st
+
+
+def _laplace_expected(dim, R, h, sigma=1.0):
+    eps = 1.5 * h
+    # |alpha'(r)| for alpha = (1 + tanh((R - r)/eps))/2
+    f = lambda r: (dim - 1) / r * 0.5 / eps / np.cosh((R - r) / eps) ** 2
+    val, _ = scipy.integrate.quad(f, 1e-9, 2 * R, points=[R], limit=200)
+    return sigma * val
+
+
+@pytest.mark.parametrize("dim,n,R", [(2, 64, 0.2), (2, 128, 0.2), pytest.param(3, 96, 0.25, marks=pytest.mark.slow)])
+def test_static_drop_laplace_jump(dim, n, R):
+    """Pins (e) and P8: pressure jump of a static drop after one step equals
+    the smoothed-interface Laplace value sigma*int(kappa |alpha'|) within
+    0.5 %, and the pressure inside is higher."""
+    c, st = _static_drop(dim, n, R)
+    s, info, stt = O.step(c, st, 0.0, c["dt"], 1, rtol=1e-12)
+    assert stt == 0
+    a, p = st["alpha"], s["p"]
+    dp = p[a > 0.999].mean() - p[a < 0.001].mean()
+    expected = _laplace_expected(dim, R, c["h"])
+    naive = (dim - 1) / R
+    assert dp > 0
+    assert abs(dp / expected - 1) < 5e-3, (dp, expected, naive)
+
+
+def test_balanced_force_constant_sigma_kappa():
+    """Pin (P10): with sigma*kappa forced to a constant C and no Marangoni
+    term, the face force is C grad(alpha), which the pressure balances
+    exactly: p = C alpha + const and u^{n+1} = 0 to solver tolerance."""
+    c = I.config(0)
+    c["dsigma_dT"] = 0.0
+    st = I.initial_state(c)
+    C = 3.7
+    s, info, stt = O.step(c, st, 0.0, c["dt"], 1, flags=O.F_CONST_SIGKAP, sigkap_const=C, rtol=1e-14)
+    us, vs, _ = O.predictor(c, c["dt"], st["alpha"], st["T"], st["u"], st["v"],
+                            flags=O.F_CONST_SIGKAP, sigkap_const=C)
+    ref = C * st["alpha"]
+    assert rel(s["p"], ref - ref.mean()) < 1e-11
+    assert np.linalg.norm(np.concatenate([s["u"].ravel(), s["v"].ravel()])) < \
+        1e-11 * np.linalg.norm(np.concatenate([us.ravel(), vs.ravel()]))
+
+
+def test_null_cases_uniform_temperature_and_flat_interface():
+    """Pin (P11): uniform T -> Marangoni vector identically 0 (the tangential
+    force exists iff surface-tension gradients exist); a flat interface with
+    uniform T gives no tangential force and a curl-free normal force, so the
+    projected velocity vanishes."""
+    c = I.custom(I.config(2), nx=32, ny=16, nz=32)
+    c["seed"] = 2
+    st = I.initial_state(c)
+    g = O.geometry(c, st["alpha"], st["T"])
+    assert np.all(g["M"] == 0.0)
+    # flat interface: alpha depends on z only
+    z = (np.arange(32) + 0.5) * c["h"]
+    al = 0.5 * (1 - np.tanh((z - 16.3 * c["h"]) / (1.5 * c["h"])))
+    st["alpha"] = np.ascontiguousarray(np.broadcast_to(al[:, None, None], (32, 16, 32)))
+    us, vs, ws = O.predictor(c, 1e-8, st["alpha"], st["T"], st["u"], st["v"], st["w"])
+    assert np.all(us == 0.0) and np.all(vs == 0.0) and np.abs(ws).max() > 0
+    s, info, stt = O.step(c, st, 0.0, 1e-8, 1, rtol=1e-13, flags=0)
+    c2 = dict(c, q_power=0.0)
+    s, info, stt = O.step(c2, st, 0.0, 1e-8, 1, rtol=1e-13)
+    assert np.abs(s["w"]).max() < 1e-10 * np.abs(ws).max()
+
+
+def test_total_marangoni_force_on_flat_interface():
+    """Pin (P12): flat interface y = const with T = x: the summed tangential
+    force equals dsigma/dT * (interface length) (2D), since h sum_y delta_s
+    telescopes to about 1; a T gradient along the normal gives no tangential
+    force (catches the sign of the projection n n^T)."""
+    n = 64
+    c = box2d(n)
+    c["T_bc"] = [1, 1, 0, 0, 0, 0]
+    c["T_wall"] = [0.0, 1.0, 0, 0, 0, 0]
+    h = c["h"]
+    x = (np.arange(n) + 0.5) * h
+    al = 0.5 * (1 - np.tanh((x - 0.503) / (1.5 * h)))
+    alpha = np.ascontiguousarray(np.broadcast_to(al[:, None], (n, n)).reshape(1, n, n))
+    T = np.ascontiguousarray(np.broadcast_to(x[None, :], (n, n)).reshape(1, n, n))
+    g = O.geometry(c, alpha, T)
+    col = h * g["delta_s"][0, :, 0].sum()
+    assert col == pytest.approx(1.0, abs=1e-4)   # regularisation removes ~eps_n per interface cell
+    us, vs, _ = O.predictor(c, 1.0, alpha, T, np.zeros((1, n, n + 1)), np.zeros((1, n + 1, n)))
+    rho_f = 0.5 * (c["rho1"] + np.clip(alpha, 0, 1) * (c["rho2"] - c["rho1"]))
+    rho = c["rho1"] + np.clip(alpha, 0, 1) * (c["rho2"] - c["rho1"])
+    fx = us[0, :, 1:-1] * 0.5 * (rho[0, :, 1:] + rho[0, :, :-1])   # face force (dt = 1, u = 0)
+    total = fx.sum() * h * h
+    assert total == pytest.approx(c["dsigma_dT"] * (n - 1) * h * col, rel=1e-10)
+    # T along the interface normal (y): tangential part ~ 0
+    Ty = np.ascontiguousarray(np.broadcast_to(x[:, None], (n, n)).reshape(1, n, n))
+    c2 = box2d(n)
+    g2 = O.geometry(c2, alpha, Ty)
+    # delta_s (1 - |n|^2) <= eps_n / 2 bounds what the regularisation leaves
+    assert np.abs(g2["M"][:, 1]).max() <= 0.5 * abs(c2["dsigma_dT"]) * c2["normal_eps"]
+    assert np.abs(g2["M"][:, 0]).max() == 0.0
+
+
+def test_curvature_of_circle_and_sphere():
+    """kappa = -div(n) with n pointing into the drop is +1/R (2D), +2/R (3D)
+    at the interface (sign convention of eq. 4's normal force)."""
+    for dim, n, R in [(2, 128, 0.25), (3, 48, 0.3)]:
+        c, st = _static_drop(dim, n, R)
+        g = O.geometry(c, st["alpha"], st["T"])
+        a = st["alpha"].ravel()
+        band = (a > 0.3) & (a < 0.7)
+        k = g["kappa"].ravel()[band]
+        assert np.median(k) == pytest.approx((dim - 1) / R, rel=0.03)
+        # normals point toward alpha = 1 (the drop centre)
+        nvec = g["n"][band]
+        xs = [(np.arange(n) + 0.5) / n] * 3
+        if dim == 2:
+            Y, X = np.meshgrid(xs[1], xs[0], indexing="ij")
+            r = np.stack([X.ravel() - 0.5, Y.ravel() - 0.5], 1)[band]
+            assert np.all((nvec[:, :2] * r).sum(1) < 0)
+
+
+def test_marangoni_migration_toward_hot_side():
+    """Pin (P9): with d sigma/dT < 0 and T increasing upward, the drop's
+    alpha-weighted vertical velocity is positive: it moves toward the hotter
+    fluid (Section "Marangoni Flow around a droplet")."""
+    c = I.config(0)
+    st = I.initial_state(c)
+    s, info, stt = O.step(c, st, 0.0, c["dt"], 30)
+    vc = 0.5 * (s["v"][:, 1:, :] + s["v"][:, :-1, :])
+    assert (s["alpha"] * vc).sum() > 0
+    c["dsigma_dT"] = +0.1
+    s2, _, _ = O.step(c, st, 0.0, c["dt"], 30)
+    vc2 = 0.5 * (s2["v"][:, 1:, :] + s2["v"][:, :-1, :])
+    assert (s2["alpha"] * vc2).sum() < 0
+
+
+def test_mirror_symmetry_100_steps():
+    """Pin (P13): the droplet case is symmetric about x = 1/2, so
+    alpha(x) = alpha(1-x) and u(x) = -u(1-x) after 100 steps."""
+    c = I.config(0)
+    st = I.initial_state(c)
+    s, info, stt = O.step(c, st, 0.0, c["dt"], 100)
+    assert stt == 0
+    a = s["alpha"]
+    assert np.abs(a - a[..., ::-1]).max() <= 1e-12
+    u = s["u"]
+    assert np.abs(u + u[..., ::-1]).max() <= 1e-12 * np.abs(u).max()
+    v = s["v"]
+    assert np.abs(v - v[..., ::-1]).max() <= 1e-12 * np.abs(v).max()
+
+
+def test_restart_is_bitwise():
+    """Pin (P16): run(2N) equals run(N) followed by run(N)."""
+    c = I.config(0)
+    st = I.initial_state(c)
+    dt = c["dt"]
+    s2, _, _ = O.step(c, st, 0.0, dt, 4)
+    s1, _, _ = O.step(c, st, 0.0, dt, 2)
+    s1b, _, _ = O.step(c, s1, 2 * dt, dt, 2)
+    for k in ("alpha", "T", "u", "v", "p"):
+        assert np.array_equal(s2[k], s1b[k]), k
+
+
+# ---------------------------------------------------------------------------
+# Momentum operators against closed forms (tiny amplitude -> linear WENO weights).
+def _momentum_split(n):
+    c = box2d(n, rho1=1.0, rho2=1.0, mu1=0.01, mu2=0.01, sigma0=0.0, dsigma_dT=0.0)
+    h = c["h"]
+    zero = np.zeros((1, n, n))
+    res = []
+    for A in (1e-5, 2e-5):
+        u, v, _ = I.stream_velocity(c, A)
+        us, vs, _ = O.predictor(c, 1.0, zero, zero, u, v)
+        res.append(((us - u), (vs - v), u, v))
+    # (u*-u)/dt = -A^2 C1 + A V1  ->  solve the 2x2 system per entry
+    (du1, dv1, u1, v1), (du2, dv2, _, _) = res
+    A1 = 1e-5
+    C1u = -(du2 - 2 * du1) / (2 * A1 * A1)
+    V1u = (4 * du1 - du2) / (2 * A1)
+    return c, C1u, V1u
+
+
+def test_viscous_and_convective_terms_converge_to_closed_forms():
+    """Viscous term of a divergence-free field with constant mu equals
+    mu * Laplacian(u); the convective term equals div(u u).  Errors vs. the
+    analytic values of the stream-function flow must fall at order >= 1.8."""
+    errs_v, errs_c = [], []
+    for n in (32, 64, 128):
+        c, C1, V1 = _momentum_split(n)
+        h = c["h"]
+        # analytic fields for psi = sin^2(pi x) sin^2(pi y)/pi, u = psi_y, v = -psi_x
+        xf = np.arange(n + 1) * h
+        yc = (np.arange(n) + 0.5) * h
+        Y, X = np.meshgrid(yc, xf, indexing="ij")
+        s2x, s2y = np.sin(np.pi * X) ** 2, np.sin(2 * np.pi * Y)
+        u = s2x * s2y                                  # psi_y
+        uxx = 2 * np.pi ** 2 * np.cos(2 * np.pi * X) * s2y
+        uyy = -4 * np.pi ** 2 * s2x * s2y
+        v = -np.sin(2 * np.pi * X) * np.sin(np.pi * Y) ** 2
+        ux = np.pi * np.sin(2 * np.pi * X) * s2y
+        uy = 2 * np.pi * s2x * np.cos(2 * np.pi * Y)
+        conv = u * ux + v * uy                         # (u.grad)u = div(uu) for div-free u
+        visc = 0.01 * (uxx + uyy)
+        inner = (slice(None), slice(4, -4), slice(4, -4))
+        errs_v.append(np.abs(V1[0][inner[1:]] - visc[inner[1:]]).max())
+        errs_c.append(np.abs(C1[0][inner[1:]] - conv[inner[1:]]).max())
+    ov = [math.log2(errs_v[i] / errs_v[i + 1]) for i in range(2)]
+    oc = [math.log2(errs_c[i] / errs_c[i + 1]) for i in range(2)]
+    assert min(ov) >= 1.8, (errs_v, ov)
+    assert min(oc) >= 1.8, (errs_c, oc)
+
+
+def test_viscous_wall_shear_ghost():
+    """Near a no-slip wall the viscous term of u = f(y) is mu/rho times the
+    second difference with the odd ghost u_{-1} = -u_0 (no convection since
+    the flow is parallel)."""
+    n = 16
+    c = box2d(n, rho1=2.0, rho2=2.0, mu1=0.03, mu2=0.03, sigma0=0.0, dsigma_dT=0.0)
+    h = c["h"]
+    y = (np.arange(n) + 0.5) * h
+    f = np.sin(3 * y) + y
+    u = np.zeros((1, n, n + 1))
+    u[0, :, 1:-1] = f[:, None]
+    zero = np.zeros((1, n, n))
+    us, vs, _ = O.predictor(c, 1.0, zero, zero, u, np.zeros((1, n + 1, n)))
+    fg = np.concatenate([[-f[0]], f, [-f[-1]]])
+    d2 = (fg[2:] - 2 * fg[1:-1] + fg[:-2]) / h ** 2
+    ref = 0.03 / 2.0 * d2
+    # faces 4..n-4 along x: no normal-stress or convective contribution from the
+    # jump to the zero wall velocity at x = 0, 1
+    inner = slice(4, n - 3)
+    assert np.abs(us[0, :, inner] - u[0, :, inner] - ref[:, None]).max() < 1e-12 * np.abs(ref).max()
+    assert np.all(vs[:, :, 1:-1] == 0.0)
