@@ -1,0 +1,155 @@
+/*
+ * tcf.h - C ABI of the MI355X (gfx950) thermocapillary two-phase flow step.
+ *
+ * The library advances incompressible two-phase volume-of-fluid flow with
+ * temperature-dependent surface tension (Zimbrod, Schreter, Schilp 2022,
+ * arXiv 2209.09671) by one projection step on a uniform Cartesian MAC grid:
+ *
+ *   S1  WENO5 upwind transport of the volume fraction alpha (eq. 1) and the
+ *       temperature T (energy equation, named in Section "Theory"), SSP-RK3,
+ *       face velocity frozen at u^n;
+ *   S2  material laws from clamp(alpha, 0, 1); surface tension computed as a
+ *       field sigma(T) (Section "Implementation");
+ *   S3  interface geometry: delta_s = |grad alpha| (eq. 6), n = grad alpha /
+ *       delta_s (eq. 7), curvature kappa = -div n, Marangoni vector
+ *       M = delta_s (I - n n^T) grad sigma (eqs. 4, 5);
+ *   S4  face CSF force (eq. 4): normal part sigma kappa grad alpha plus the
+ *       tangential Marangoni part;
+ *   S5  momentum predictor u* (WENO5 convection, variable-viscosity stress,
+ *       CSF force divided by the face density);
+ *   S6  b = D u* / dt made mean-free;
+ *   S7  A p = b with A = D (1/rho_f) G, matrix free, solved by conjugate
+ *       gradients preconditioned by a geometric multigrid V-cycle, warm
+ *       started from p^n, gauge mean(p) = 0;
+ *   S8  projection u^{n+1} = u* - dt (1/rho_f) G p.
+ *
+ * Layout (every field): structure of arrays, C order, x fastest.
+ *   cell fields alpha, T, p : nx*ny*nz values, index i + nx*(j + ny*k)
+ *   x-face velocity u       : (nx+1)*ny*nz,   index i + (nx+1)*(j + ny*k)
+ *   y-face velocity v       : nx*(ny+1)*nz,   index i + nx*(j + (ny+1)*k)
+ *   z-face velocity w       : nx*ny*(nz+1),   index i + nx*(j + ny*k)   (3D only)
+ * Cell (i,j,k) has centre ((i+1/2)h, (j+1/2)h, (k+1/2)h).  Wall faces
+ * (index 0 and n along their own axis) carry zero velocity.  In 2D nz == 1
+ * and there is no w.  Phase 1 is alpha = 0, phase 2 alpha = 1.
+ *
+ * Pointers passed to tcf_set_fields / tcf_get_fields / tcf_solve_pressure /
+ * tcf_predictor / tcf_apply_A are DEVICE pointers to FP64 arrays in both
+ * precision modes (the FP32 mode converts internally).  The caller owns them
+ * and the workspace; the library never allocates device memory.
+ *
+ * Streams: all device work is enqueued on the hip_stream given at init.
+ * Calls synchronise that stream only where they must read a device value on
+ * the host (pressure-solver convergence tests, and info when requested).
+ *
+ * Errors: every call returns a tcf_status, never throws and never aborts;
+ * tcf_last_error() returns a message for the calling thread.  TCF_E_INVALID
+ * leaves the state unchanged.  TCF_E_NOT_CONVERGED completes the step with
+ * the best pressure iterate.  TCF_E_NONFINITE stops at the first step whose
+ * residual or fields are not finite and leaves that step's output in place.
+ */
+#ifndef TCF_H_
+#define TCF_H_
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  TCF_OK = 0,
+  TCF_E_INVALID = 1,       /* bad argument; nothing changed */
+  TCF_E_DEVICE = 2,        /* a HIP runtime call failed */
+  TCF_E_NOT_CONVERGED = 3, /* pressure solve reached its iteration limit */
+  TCF_E_NONFINITE = 4,     /* NaN/Inf in the residual or the fields */
+  TCF_E_STATE = 5,         /* fields not set yet */
+  TCF_E_WORKSPACE = 6      /* workspace too small or misaligned */
+} tcf_status;
+
+typedef enum {
+  TCF_FP64 = 0,        /* everything in FP64 */
+  TCF_FP32_REFINE = 1  /* FP32 stencils and inner Poisson solve; FP64 refinement
+                          residual, CG scalars, sums, and u, v, w, p storage */
+} tcf_precision;
+
+enum { TCF_TRANSPORT_ONLY = 1 /* tcf_step runs S1 only (velocity frozen, p kept) */ };
+
+typedef struct tcf_grid tcf_grid; /* opaque, host side */
+
+/* Plain parameter block, copied at init. */
+typedef struct tcf_config {
+  int dim, nx, ny, nz;     /* dim 2 => nz must be 1 */
+  double h;                /* uniform cell size */
+  int precision;           /* tcf_precision */
+  int flags;               /* TCF_TRANSPORT_ONLY or 0 */
+  double rho1, rho2, mu1, mu2, rhocp1, rhocp2, lambda1, lambda2; /* phase 1 (alpha=0), phase 2 */
+  double sigma0, dsigma_dT, T0;  /* sigma(T) = sigma0 + dsigma_dT (T - T0) */
+  int T_bc[6];             /* walls -x,+x,-y,+y,-z,+z : 0 Neumann, 1 Dirichlet */
+  double T_wall[6];        /* Dirichlet wall temperatures */
+  double q_power, q_radius, q_x0, q_y0, q_vx, q_vy; /* Gaussian surface heat flux, 0 power = off */
+  double weno_eps;         /* WENO smoothness epsilon (1e-6) */
+  double normal_eps;       /* regularisation of |grad alpha| (1e-6 / h) */
+  double p_rtol;           /* FP64 relative residual target of the pressure solve */
+  int p_maxit;             /* CG iteration limit (FP64 mode; per inner solve in FP32 mode) */
+  double inner_rtol;       /* FP32 inner solve relative tolerance */
+  int refine_maxit;        /* FP64 refinement sweeps limit (FP32 mode) */
+  int mg_levels;           /* 0 = automatic */
+  int mg_nu;               /* Jacobi sweeps before and after the coarse correction */
+} tcf_config;
+
+typedef struct tcf_step_info {
+  int cg_iters;      /* CG iterations of the last step (summed over refinements) */
+  int refine_iters;  /* FP64 refinement sweeps of the last step (FP32 mode) */
+  double p_relres;   /* ||b - A p|| / ||b|| in FP64 after the last step */
+  double div_rel;    /* ||D u^{n+1}|| / ||D u*|| of the last step */
+  double sum_alpha;  /* sum of alpha over cells (FP64) after the last step */
+  double alpha_min, alpha_max;
+  double cfl_max;    /* dt max|u_f| / h after the last step */
+  int nonfinite;     /* 1 if a non-finite value was seen */
+} tcf_step_info;
+
+/* Bytes of device workspace needed for this configuration (0 if invalid). */
+size_t tcf_workspace_bytes(const tcf_config* cfg);
+
+/* Validate cfg and carve the caller's workspace (device memory, 256-byte
+ * aligned, at least tcf_workspace_bytes bytes).  hip_stream is a hipStream_t
+ * (NULL = default stream).  *out receives a host-side handle. */
+tcf_status tcf_init_grid(const tcf_config* cfg, void* workspace, size_t bytes, void* hip_stream,
+                         tcf_grid** out);
+
+/* Copy the state in (device FP64 pointers, layout above).  w must be NULL in
+ * 2D; p may be NULL (zero pressure).  Wall-face velocities are forced to 0. */
+tcf_status tcf_set_fields(tcf_grid* g, double t, const double* alpha, const double* T, const double* u,
+                          const double* v, const double* w, const double* p);
+
+/* Copy the state out (device FP64 pointers; any may be NULL to skip). */
+tcf_status tcf_get_fields(const tcf_grid* g, double* t, double* alpha, double* T, double* u, double* v,
+                          double* w, double* p);
+
+/* Advance nsteps steps of size dt (S1..S8 each).  info may be NULL; when set
+ * it receives the diagnostics of the last step (forces a stream sync). */
+tcf_status tcf_step(tcf_grid* g, double dt, int nsteps, tcf_step_info* info);
+
+/* Solve A p = rhs (S7) with the operator built from the grid's current alpha.
+ * rhs is made mean-free first; p holds the initial guess on entry and the
+ * mean-free solution on exit.  Device FP64 pointers of nx*ny*nz values. */
+tcf_status tcf_solve_pressure(tcf_grid* g, const double* rhs, double* p, tcf_step_info* info);
+
+/* Diagnostics of single sub-steps (parity checks of the path's parts).
+ * tcf_predictor: S2..S5 with the grid's current alpha, T, u taken as
+ * (alpha^{n+1}, T^{n+1}, u^n); writes u* (device FP64, face layouts).
+ * tcf_apply_A: y = A x with the grid's current alpha. */
+tcf_status tcf_predictor(tcf_grid* g, double dt, double* us, double* vs, double* ws);
+tcf_status tcf_apply_A(tcf_grid* g, const double* x, double* y);
+
+/* Release the handle (the workspace stays the caller's). */
+void tcf_destroy(tcf_grid* g);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* tcf_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TCF_H_ */

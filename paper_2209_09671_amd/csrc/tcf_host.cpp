@@ -1,0 +1,772 @@
+// Host side of the thermocapillary step library: workspace carve-up, step
+// orchestration (S1..S8), the PCG / multigrid driver, FP64 iterative
+// refinement of the FP32 pressure solve, and the C ABI declared in tcf.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/tcf.h"
+#include "tcf_internal.h"
+
+using namespace tcf;
+
+namespace {
+
+thread_local std::string g_err;
+
+tcf_status fail(tcf_status st, const std::string& msg) {
+  g_err = msg;
+  return st;
+}
+
+#define HIPCHECK(expr)                                                                        \
+  do {                                                                                        \
+    hipError_t e_ = (expr);                                                                   \
+    if (e_ != hipSuccess)                                                                     \
+      return fail(TCF_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));           \
+  } while (0)
+
+constexpr size_t kAlign = 256;
+constexpr double kOmegaC = 1.9;  // over-correction of the piecewise-constant coarse correction
+constexpr int kCoarseSweeps = 30;
+
+// Bump allocator over the caller's workspace; with base == nullptr it only
+// counts bytes, so sizing and carving share one code path.
+struct Carver {
+  char* base;
+  size_t off = 0;
+  explicit Carver(void* b) : base((char*)b) {}
+  template <class T>
+  T* take(long n) {
+    off = (off + kAlign - 1) / kAlign * kAlign;
+    T* p = base ? (T*)(base + off) : nullptr;
+    off += sizeof(T) * (size_t)std::max(n, 1L);
+    return p;
+  }
+};
+
+template <class R>
+struct Fields {
+  R *a = nullptr, *T = nullptr;            // state alpha, T (precision R)
+  R *u = nullptr, *v = nullptr, *w = nullptr;  // velocity read by the stencils (alias of u64.. in FP64)
+  R *a1, *T1, *a2, *T2;                    // RK3 stage values
+  R *sk, *Mx, *My, *Mz;                    // sigma*kappa, Marangoni vector
+  R *us, *vs, *ws;                         // predictor
+  std::vector<Level<R>> lv;                // Poisson levels (level 0 = fine)
+  R *r, *z, *z2, *d, *q;                   // PCG vectors on the fine level
+  R* x;                                    // FP32 mode: inner correction e
+};
+
+struct Dims {
+  int dim, nx, ny, nz;
+  long N, Nu, Nv, Nw;
+};
+
+Dims dims_of(const tcf_config* c) {
+  Dims d;
+  d.dim = c->dim;
+  d.nx = c->nx;
+  d.ny = c->ny;
+  d.nz = c->dim == 2 ? 1 : c->nz;
+  d.N = (long)d.nx * d.ny * d.nz;
+  d.Nu = (long)(d.nx + 1) * d.ny * d.nz;
+  d.Nv = (long)d.nx * (d.ny + 1) * d.nz;
+  d.Nw = d.dim == 3 ? (long)d.nx * d.ny * (d.nz + 1) : 0;
+  return d;
+}
+
+std::vector<std::array<int, 3>> level_dims(const Dims& D, int max_levels) {
+  std::vector<std::array<int, 3>> v;
+  int nx = D.nx, ny = D.ny, nz = D.nz;
+  v.push_back({nx, ny, nz});
+  for (;;) {
+    if (max_levels > 0 && (int)v.size() >= max_levels) break;
+    long n = (long)nx * ny * nz;
+    bool can = nx % 2 == 0 && ny % 2 == 0 && nx >= 4 && ny >= 4 && (D.dim == 2 || (nz % 2 == 0 && nz >= 4)) && n > 64;
+    if (!can) break;
+    nx /= 2;
+    ny /= 2;
+    if (D.dim == 3) nz /= 2;
+    v.push_back({nx, ny, nz});
+  }
+  return v;
+}
+
+}  // namespace
+
+struct tcf_grid {
+  tcf_config cfg;
+  Dims D;
+  KParams P;
+  hipStream_t stream;
+  bool fp32;
+  bool has_fields = false;
+  double t = 0.0;
+  // FP64 state and scratch (both modes)
+  double *u64, *v64, *w64, *p64, *b64, *r64, *ax64, *ay64, *az64, *zero64;
+  Fields<double> f64;
+  Fields<float> f32;
+  float *ax32, *ay32, *az32;
+  double* part[6];
+  int nb;  // capacity of each partial array
+  double* scal;
+  int* iflag;
+  double* hscal;  // pinned host mirror
+  int* hflag;
+  size_t bytes;
+};
+
+namespace {
+
+template <class R>
+void carve_fields(Carver& cv, const Dims& D, Fields<R>& F, int mg_levels, bool alias_state, double* u64,
+                  double* v64, double* w64, double* ax64, double* ay64, double* az64) {
+  const long N = D.N;
+  F.a = cv.take<R>(N);
+  F.T = cv.take<R>(N);
+  if (alias_state) {
+    F.u = (R*)u64;
+    F.v = (R*)v64;
+    F.w = (R*)w64;
+  } else {
+    F.u = cv.take<R>(D.Nu);
+    F.v = cv.take<R>(D.Nv);
+    F.w = D.dim == 3 ? cv.take<R>(D.Nw) : nullptr;
+  }
+  F.a1 = cv.take<R>(N);
+  F.T1 = cv.take<R>(N);
+  F.a2 = cv.take<R>(N);
+  F.T2 = cv.take<R>(N);
+  F.sk = cv.take<R>(N);
+  F.Mx = cv.take<R>(N);
+  F.My = cv.take<R>(N);
+  F.Mz = D.dim == 3 ? cv.take<R>(N) : nullptr;
+  F.us = cv.take<R>(D.Nu);
+  F.vs = cv.take<R>(D.Nv);
+  F.ws = D.dim == 3 ? cv.take<R>(D.Nw) : nullptr;
+  F.r = cv.take<R>(N);
+  F.z = cv.take<R>(N);
+  F.z2 = cv.take<R>(N);
+  F.d = cv.take<R>(N);
+  F.q = cv.take<R>(N);
+  F.x = alias_state ? nullptr : cv.take<R>(N);
+  auto ld = level_dims(D, mg_levels);
+  F.lv.clear();
+  for (size_t l = 0; l < ld.size(); ++l) {
+    Level<R> L;
+    L.nx = ld[l][0];
+    L.ny = ld[l][1];
+    L.nz = ld[l][2];
+    const long n = L.n();
+    const long nu = (long)(L.nx + 1) * L.ny * L.nz, nv = (long)L.nx * (L.ny + 1) * L.nz,
+               nw = D.dim == 3 ? (long)L.nx * L.ny * (L.nz + 1) : 0;
+    if (l == 0 && alias_state) {
+      L.ax = (R*)ax64;
+      L.ay = (R*)ay64;
+      L.az = (R*)az64;
+    } else {
+      L.ax = cv.take<R>(nu);
+      L.ay = cv.take<R>(nv);
+      L.az = D.dim == 3 ? cv.take<R>(nw) : nullptr;
+    }
+    L.wdiag = cv.take<R>(n);
+    if (l > 0) {
+      L.x = cv.take<R>(n);
+      L.x2 = cv.take<R>(n);
+      L.b = cv.take<R>(n);
+    } else {
+      L.x = L.x2 = L.b = nullptr;
+    }
+    F.lv.push_back(L);
+  }
+  // the coarsest level needs x2 for its ping-pong even when it is level 0
+  if (F.lv.size() == 1) F.lv[0].x2 = cv.take<R>(N);
+}
+
+size_t carve(const tcf_config* c, void* base, tcf_grid* g) {
+  Dims D = dims_of(c);
+  Carver cv(base);
+  tcf_grid dummy;
+  tcf_grid* G = g ? g : &dummy;
+  G->u64 = cv.take<double>(D.Nu);
+  G->v64 = cv.take<double>(D.Nv);
+  G->w64 = D.dim == 3 ? cv.take<double>(D.Nw) : nullptr;
+  G->p64 = cv.take<double>(D.N);
+  G->b64 = cv.take<double>(D.N);
+  G->r64 = cv.take<double>(D.N);
+  G->zero64 = cv.take<double>(D.N);
+  G->ax64 = cv.take<double>(D.Nu);
+  G->ay64 = cv.take<double>(D.Nv);
+  G->az64 = D.dim == 3 ? cv.take<double>(D.Nw) : nullptr;
+  if (c->precision == TCF_FP32_REFINE)
+    carve_fields<float>(cv, D, G->f32, c->mg_levels, false, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
+  else
+    carve_fields<double>(cv, D, G->f64, c->mg_levels, true, G->u64, G->v64, G->w64, G->ax64, G->ay64, G->az64);
+  const int nb = (int)std::max<long>((D.N + 255) / 256, (long)nblocks_cells(D.nx, D.ny, D.nz));
+  G->nb = nb;
+  double* pbase = cv.take<double>(6L * nb);  // contiguous: diagnostics write 6 strided arrays
+  for (int k = 0; k < 6; ++k) G->part[k] = pbase ? pbase + (long)k * nb : nullptr;
+  G->scal = cv.take<double>(S_NSLOT);
+  G->iflag = cv.take<int>(I_NFLAG);
+  return cv.off + kAlign;
+}
+
+std::string validate(const tcf_config* c) {
+  if (!c) return "cfg is NULL";
+  if (c->dim != 2 && c->dim != 3) return "dim must be 2 or 3";
+  if (c->nx < 4 || c->ny < 4) return "nx and ny must be >= 4";
+  if (c->dim == 2 && c->nz != 1) return "nz must be 1 in 2D";
+  if (c->dim == 3 && c->nz < 4) return "nz must be >= 4 in 3D";
+  if ((double)c->nx * c->ny * (c->dim == 3 ? c->nz : 1) > 2.0e9) return "grid too large (more than 2e9 cells)";
+  if (!(c->h > 0.0) || !std::isfinite(c->h)) return "h must be positive";
+  if (c->precision != TCF_FP64 && c->precision != TCF_FP32_REFINE) return "unknown precision";
+  if (c->flags & ~TCF_TRANSPORT_ONLY) return "unknown flags";
+  if (!(c->rho1 > 0 && c->rho2 > 0)) return "densities must be positive";
+  if (!(c->mu1 >= 0 && c->mu2 >= 0)) return "viscosities must be non-negative";
+  if (!(c->rhocp1 > 0 && c->rhocp2 > 0)) return "rho*c_p must be positive";
+  if (!(c->lambda1 >= 0 && c->lambda2 >= 0)) return "conductivities must be non-negative";
+  for (int k = 0; k < 6; ++k)
+    if (c->T_bc[k] != 0 && c->T_bc[k] != 1) return "T_bc entries must be 0 or 1";
+  if (c->q_power != 0.0 && !(c->q_radius > 0)) return "q_radius must be positive";
+  if (!(c->weno_eps > 0)) return "weno_eps must be positive";
+  if (!(c->normal_eps > 0)) return "normal_eps must be positive";
+  if (!(c->p_rtol > 0)) return "p_rtol must be positive";
+  if (c->p_maxit < 1) return "p_maxit must be >= 1";
+  if (c->mg_nu < 1 || c->mg_nu > 8) return "mg_nu must be in 1..8";
+  if (c->mg_levels < 0) return "mg_levels must be >= 0";
+  if (c->precision == TCF_FP32_REFINE && (!(c->inner_rtol > 0 && c->inner_rtol < 1) || c->refine_maxit < 1))
+    return "FP32 mode needs 0 < inner_rtol < 1 and refine_maxit >= 1";
+  return "";
+}
+
+KParams make_params(const tcf_config* c) {
+  KParams P{};
+  Dims D = dims_of(c);
+  P.nx = D.nx;
+  P.ny = D.ny;
+  P.nz = D.nz;
+  P.dim = D.dim;
+  P.h = c->h;
+  P.ih = 1.0 / c->h;
+  P.rho1 = c->rho1;
+  P.rho2 = c->rho2;
+  P.mu1 = c->mu1;
+  P.mu2 = c->mu2;
+  P.rhocp1 = c->rhocp1;
+  P.rhocp2 = c->rhocp2;
+  P.lam1 = c->lambda1;
+  P.lam2 = c->lambda2;
+  P.sigma0 = c->sigma0;
+  P.s = c->dsigma_dT;
+  P.T0 = c->T0;
+  for (int k = 0; k < 6; ++k) {
+    P.Tbc[k] = c->T_bc[k];
+    P.Tw[k] = c->T_wall[k];
+  }
+  P.qP = c->q_power;
+  P.qr = c->q_radius;
+  P.qx0 = c->q_x0;
+  P.qy0 = c->q_y0;
+  P.qvx = c->q_vx;
+  P.qvy = c->q_vy;
+  P.weno_eps = c->weno_eps;
+  P.neps = c->normal_eps;
+  return P;
+}
+
+hipError_t read_back(tcf_grid* g) {
+  hipError_t e = hipMemcpyAsync(g->hscal, g->scal, sizeof(double) * S_NSLOT, hipMemcpyDeviceToHost, g->stream);
+  if (e != hipSuccess) return e;
+  e = hipMemcpyAsync(g->hflag, g->iflag, sizeof(int) * I_NFLAG, hipMemcpyDeviceToHost, g->stream);
+  if (e != hipSuccess) return e;
+  return hipStreamSynchronize(g->stream);
+}
+
+// Operator hierarchy from the fine face weights already in level 0.
+template <class R>
+void build_levels(tcf_grid* g, Fields<R>& F) {
+  const int dim = g->D.dim;
+  const double wj = dim == 2 ? 0.8 : 6.0 / 7.0;
+  make_wdiag<R>(g->stream, dim, F.lv[0], wj);
+  for (size_t l = 1; l < F.lv.size(); ++l) {
+    coarsen_weights<R>(g->stream, dim, F.lv[l - 1], F.lv[l]);
+    make_wdiag<R>(g->stream, dim, F.lv[l], wj);
+  }
+}
+
+// Symmetric V-cycle: out = M b on level l.  part (level 0 only) receives the
+// partials of b.out.  Buffers alternate so that the last write lands in out.
+template <class R>
+void vcycle(tcf_grid* g, Fields<R>& F, size_t l, const R* b, R* out, R* tmp, double* part) {
+  hipStream_t s = g->stream;
+  const int dim = g->D.dim;
+  const int nu = g->cfg.mg_nu;
+  const Level<R>& L = F.lv[l];
+  if (l + 1 == F.lv.size()) {
+    Level<R> Lc = L;
+    Lc.x2 = tmp;
+    mg_coarse_solve<R>(s, dim, Lc, b, out, kCoarseSweeps, g->iflag);
+    if (part) dot_partials<R>(s, L.n(), b, out, part);
+    return;
+  }
+  R* bufs[2] = {tmp, out};
+  int w = 0;  // next write goes to bufs[w & 1]
+  mg_smooth_first<R>(s, L, b, bufs[w & 1], g->iflag);
+  ++w;
+  for (int k = 1; k < nu; ++k, ++w) mg_smooth<R>(s, dim, L, b, bufs[(w - 1) & 1], bufs[w & 1], nullptr, g->iflag);
+  const R* cur = bufs[(w - 1) & 1];
+  Level<R>& C = F.lv[l + 1];
+  mg_resid_restrict<R>(s, dim, L, b, cur, C.b, g->iflag);
+  vcycle<R>(g, F, l + 1, C.b, C.x, C.x2, nullptr);
+  {
+    double* pp = (nu == 1) ? part : nullptr;
+    mg_prolong_smooth<R>(s, dim, L, C, b, cur, bufs[w & 1], kOmegaC, pp, g->iflag);
+    ++w;
+  }
+  for (int k = 1; k < nu; ++k, ++w) {
+    double* pp = (k == nu - 1) ? part : nullptr;
+    mg_smooth<R>(s, dim, L, b, bufs[(w - 1) & 1], bufs[w & 1], pp, g->iflag);
+  }
+}
+
+// PCG iterations on K x = rhs with r holding the initial residual and the
+// done flag / tolerance already set.  Returns iterations performed.
+template <class R>
+tcf_status pcg_iterate(tcf_grid* g, Fields<R>& F, R* x, R* r, int maxit, int* iters, bool* converged) {
+  hipStream_t s = g->stream;
+  const int dim = g->D.dim;
+  const long N = g->D.N;
+  const Level<R>& L0 = F.lv[0];
+  const int nbc = nblocks_cells(g->D.nx, g->D.ny, g->D.nz);
+  const int nb1 = (int)((N + 255) / 256);
+  *converged = false;
+  HIPCHECK(read_back(g));
+  if (g->hflag[I_DONE]) {
+    *iters = 0;
+    *converged = true;
+    return TCF_OK;
+  }
+  const int nbz = F.lv.size() == 1 ? nb1 : nbc;
+  vcycle<R>(g, F, 0, r, F.z, F.z2, g->part[0]);
+  finalize(s, g->part[0], nbz, g->scal, g->iflag, F_RZ_FIRST, 0, 0.0);
+  update_d<R>(s, N, g->scal, F.z, F.d, 1, g->iflag);
+  int it = 0;
+  for (it = 1; it <= maxit; ++it) {
+    spmv_dot<R>(s, dim, L0, F.d, F.q, g->part[0], g->iflag);
+    finalize(s, g->part[0], nbc, g->scal, g->iflag, F_ALPHA, 0, 0.0);
+    update_xr<R>(s, N, g->scal, x, r, F.d, F.q, g->part[0], g->iflag);
+    finalize(s, g->part[0], nb1, g->scal, g->iflag, F_RR, 0, 1.0);
+    vcycle<R>(g, F, 0, r, F.z, F.z2, g->part[0]);
+    finalize(s, g->part[0], nbz, g->scal, g->iflag, F_RZ, 0, 0.0);
+    update_d<R>(s, N, g->scal, F.z, F.d, 0, g->iflag);
+    HIPCHECK(read_back(g));
+    if (g->hflag[I_DONE]) break;
+  }
+  *iters = g->hflag[I_ITERS];
+  *converged = g->hflag[I_DONE] != 0 && std::isfinite(g->hscal[S_RR]);
+  return TCF_OK;
+}
+
+// FP64 solve of A p = b (b in b64, its mean in scal[S_MEAN]); p warm start.
+tcf_status solve_fp64(tcf_grid* g, double* p, int* iters, double* relres, bool* converged) {
+  hipStream_t s = g->stream;
+  Fields<double>& F = g->f64;
+  const Level<double>& L0 = F.lv[0];
+  const int nbc = nblocks_cells(g->D.nx, g->D.ny, g->D.nz);
+  init_flags(s, g->iflag);
+  rhs_resid<double>(s, g->D.dim, L0, g->b64, g->scal, p, F.r, g->part[0], g->part[1]);
+  const double rt = g->cfg.p_rtol;
+  finalize(s, g->part[0], nbc, g->scal, g->iflag, F_BB, 0, rt * rt);
+  finalize(s, g->part[1], nbc, g->scal, g->iflag, F_RR, 0, 0.0);
+  HIPCHECK(read_back(g));
+  const double bb = g->hscal[S_BB];
+  if (!std::isfinite(bb) || !std::isfinite(g->hscal[S_RR])) {
+    *iters = 0;
+    *relres = NAN;
+    *converged = false;
+    return TCF_E_NONFINITE;
+  }
+  if (bb == 0.0) {
+    fill_f64(s, g->D.N, p, 0.0);
+    *iters = 0;
+    *relres = 0.0;
+    *converged = true;
+    return TCF_OK;
+  }
+  tcf_status st = pcg_iterate<double>(g, F, p, F.r, g->cfg.p_maxit, iters, converged);
+  if (st != TCF_OK) return st;
+  *relres = std::sqrt(g->hscal[S_RR] / bb);
+  if (!std::isfinite(g->hscal[S_RR])) return TCF_E_NONFINITE;
+  return TCF_OK;
+}
+
+// FP32 inner MG-PCG inside FP64 iterative refinement.
+tcf_status solve_refined(tcf_grid* g, double* p, int* iters, int* nref, double* relres, bool* converged) {
+  hipStream_t s = g->stream;
+  Fields<float>& F = g->f32;
+  const long N = g->D.N;
+  const int dim = g->D.dim;
+  const int nbc = nblocks_cells(g->D.nx, g->D.ny, g->D.nz);
+  const int nb1 = (int)((N + 255) / 256);
+  const double rt = g->cfg.p_rtol, irt = g->cfg.inner_rtol;
+  *iters = 0;
+  *nref = 0;
+  *converged = false;
+  double bb = 0.0;
+  for (int ref = 0;; ++ref) {
+    resid64(s, dim, g->D.nx, g->D.ny, g->D.nz, g->ax64, g->ay64, g->az64, g->b64, g->scal, p, g->r64, g->part[0],
+            g->part[1]);
+    finalize(s, g->part[0], nbc, g->scal, g->iflag, F_STORE, S_BB64, 0.0);
+    finalize(s, g->part[1], nbc, g->scal, g->iflag, F_SCALE, 0, (double)N);
+    HIPCHECK(read_back(g));
+    bb = g->hscal[S_BB64];
+    const double rr = g->hscal[S_RR64];
+    if (!std::isfinite(bb) || !std::isfinite(rr)) {
+      *relres = NAN;
+      return TCF_E_NONFINITE;
+    }
+    if (bb == 0.0) {
+      fill_f64(s, N, p, 0.0);
+      *relres = 0.0;
+      *converged = true;
+      return TCF_OK;
+    }
+    *relres = std::sqrt(rr / bb);
+    if (rr <= rt * rt * bb) {
+      *converged = true;
+      break;
+    }
+    if (ref >= g->cfg.refine_maxit) break;
+    // inner solve of K e = r64 / scale in FP32 from e = 0
+    scale_to32(s, N, g->r64, g->scal, F.r);
+    fill<float>(s, N, F.x, 0.0);
+    init_flags(s, g->iflag);
+    dot_partials<float>(s, N, F.r, F.r, g->part[0]);
+    finalize(s, g->part[0], nb1, g->scal, g->iflag, F_BB, 0, irt * irt);
+    int it = 0;
+    bool conv = false;
+    tcf_status st = pcg_iterate<float>(g, F, F.x, F.r, g->cfg.p_maxit, &it, &conv);
+    if (st != TCF_OK) return st;
+    *iters += it;
+    add_scaled(s, N, F.x, g->scal, p);
+    *nref = ref + 1;
+  }
+  return TCF_OK;
+}
+
+template <class R>
+Fields<R>& fields(tcf_grid* g);
+template <>
+Fields<double>& fields<double>(tcf_grid* g) { return g->f64; }
+template <>
+Fields<float>& fields<float>(tcf_grid* g) { return g->f32; }
+
+// Fine face weights from the current alpha and the whole hierarchy.
+template <class R>
+void prepare_operator(tcf_grid* g) {
+  Fields<R>& F = fields<R>(g);
+  if (g->fp32)
+    face_weights<R>(g->P, g->stream, F.a, g->ax64, g->ay64, g->az64, g->f32.lv[0].ax, g->f32.lv[0].ay,
+                    g->f32.lv[0].az);
+  else
+    face_weights<R>(g->P, g->stream, F.a, g->ax64, g->ay64, g->az64, nullptr, nullptr, nullptr);
+  build_levels<R>(g, F);
+}
+
+tcf_status solve(tcf_grid* g, double* p, tcf_step_info* inf) {
+  int iters = 0, nref = 0;
+  double relres = 0.0;
+  bool conv = false;
+  tcf_status st;
+  if (g->fp32) st = solve_refined(g, p, &iters, &nref, &relres, &conv);
+  else st = solve_fp64(g, p, &iters, &relres, &conv);
+  if (st != TCF_OK) return st;
+  // gauge: mean(p) = 0
+  const int nbp = sum64_partials(g->stream, g->D.N, p, g->part[2]);
+  finalize(g->stream, g->part[2], nbp, g->scal, g->iflag, F_MEAN, S_PMEAN, (double)g->D.N);
+  subtract_mean(g->stream, g->D.N, g->scal, S_PMEAN, p);
+  if (inf) {
+    inf->cg_iters = iters;
+    inf->refine_iters = nref;
+    inf->p_relres = relres;
+  }
+  if (!conv) return fail(TCF_E_NOT_CONVERGED, "pressure solve did not reach p_rtol (relres " + std::to_string(relres) + ")");
+  return TCF_OK;
+}
+
+// One step S1..S8 in precision R.
+template <class R>
+tcf_status step_once(tcf_grid* g, double dt, tcf_step_info* inf, bool want_diag) {
+  hipStream_t s = g->stream;
+  Fields<R>& F = fields<R>(g);
+  KParams P = g->P;
+  P.dt = dt;
+  P.t = g->t;
+  const Dims& D = g->D;
+  // S1: SSP-RK3 with frozen u^n (stage 3 writes the state in place)
+  transport_stage<R>(P, s, F.a, F.T, F.a, F.T, F.u, F.v, F.w, F.a1, F.T1, 0.0, 1.0);
+  transport_stage<R>(P, s, F.a1, F.T1, F.a, F.T, F.u, F.v, F.w, F.a2, F.T2, 0.75, 0.25);
+  transport_stage<R>(P, s, F.a2, F.T2, F.a, F.T, F.u, F.v, F.w, F.a, F.T, 1.0 / 3.0, 2.0 / 3.0);
+  tcf_status st = TCF_OK;
+  if (!(g->cfg.flags & TCF_TRANSPORT_ONLY)) {
+    // S2-S5
+    geometry<R>(P, s, F.a, F.T, F.sk, F.Mx, F.My, F.Mz);
+    predictor<R>(P, s, F.a, F.sk, F.Mx, F.My, F.Mz, F.u, F.v, F.w, F.us, F.vs, F.ws);
+    // S6
+    const int nbc = nblocks_cells(D.nx, D.ny, D.nz);
+    divergence_rhs<R>(P, s, F.us, F.vs, F.ws, g->b64, g->part[0]);
+    finalize(s, g->part[0], nbc, g->scal, g->iflag, F_MEAN, S_MEAN, (double)D.N);
+    // S7
+    prepare_operator<R>(g);
+    st = solve(g, g->p64, inf);
+    if (st != TCF_OK && st != TCF_E_NOT_CONVERGED) return st;
+    // S8
+    project<R>(P, s, F.a, g->p64, F.us, F.vs, F.ws, g->u64, g->v64, g->w64, g->fp32 ? F.u : nullptr,
+               g->fp32 ? F.v : nullptr, g->fp32 ? F.w : nullptr);
+  }
+  g->t += dt;
+  if (want_diag) {
+    const int nbc = nblocks_cells(D.nx, D.ny, D.nz);
+    diagnostics<R>(P, s, F.a, g->u64, g->v64, g->w64, g->part[0], g->nb);
+    finalize(s, g->part[0], nbc, g->scal, g->iflag, F_STORE, S_SUMA, 0.0);
+    finalize(s, g->part[0] + g->nb, nbc, g->scal, g->iflag, F_MIN, S_AMIN, 0.0);
+    finalize(s, g->part[0] + 2 * g->nb, nbc, g->scal, g->iflag, F_MAX, S_AMAX, 0.0);
+    finalize(s, g->part[0] + 3 * g->nb, nbc, g->scal, g->iflag, F_STORE, S_DIV2, 0.0);
+    finalize(s, g->part[0] + 4 * g->nb, nbc, g->scal, g->iflag, F_MAX, S_UMAX, 0.0);
+    finalize(s, g->part[0] + 5 * g->nb, nbc, g->scal, g->iflag, F_MAX, S_NONFIN, 0.0);
+    HIPCHECK(read_back(g));
+    const double* h = g->hscal;
+    if (inf) {
+      inf->sum_alpha = h[S_SUMA];
+      inf->alpha_min = h[S_AMIN];
+      inf->alpha_max = h[S_AMAX];
+      inf->cfl_max = dt * h[S_UMAX] / g->cfg.h;
+      const double bb = g->fp32 ? h[S_BB64] : h[S_BB];
+      inf->div_rel = (g->cfg.flags & TCF_TRANSPORT_ONLY) || bb == 0.0 ? 0.0 : std::sqrt(h[S_DIV2] / bb) / dt;
+      inf->nonfinite = (h[S_NONFIN] > 0.0 || !std::isfinite(h[S_SUMA])) ? 1 : 0;
+    }
+    if (h[S_NONFIN] > 0.0 || !std::isfinite(h[S_SUMA])) return fail(TCF_E_NONFINITE, "non-finite fields after step");
+  }
+  return st;
+}
+
+template <class R>
+tcf_status predictor_only(tcf_grid* g, double dt, double* us, double* vs, double* ws) {
+  hipStream_t s = g->stream;
+  Fields<R>& F = fields<R>(g);
+  KParams P = g->P;
+  P.dt = dt;
+  P.t = g->t;
+  geometry<R>(P, s, F.a, F.T, F.sk, F.Mx, F.My, F.Mz);
+  predictor<R>(P, s, F.a, F.sk, F.Mx, F.My, F.Mz, F.u, F.v, F.w, F.us, F.vs, F.ws);
+  const Dims& D = g->D;
+  if (g->fp32) {
+    to_f64(s, D.Nu, (const float*)F.us, us);
+    to_f64(s, D.Nv, (const float*)F.vs, vs);
+    if (D.dim == 3) to_f64(s, D.Nw, (const float*)F.ws, ws);
+  } else {
+    copy_f64(s, D.Nu, (const double*)F.us, us);
+    copy_f64(s, D.Nv, (const double*)F.vs, vs);
+    if (D.dim == 3) copy_f64(s, D.Nw, (const double*)F.ws, ws);
+  }
+  HIPCHECK(hipGetLastError());
+  return TCF_OK;
+}
+
+}  // namespace
+
+// =============================================================================
+// C ABI
+extern "C" {
+
+size_t tcf_workspace_bytes(const tcf_config* cfg) {
+  if (!validate(cfg).empty()) return 0;
+  return carve(cfg, nullptr, nullptr);
+}
+
+tcf_status tcf_init_grid(const tcf_config* cfg, void* workspace, size_t bytes, void* hip_stream, tcf_grid** out) {
+  g_err.clear();
+  if (!out) return fail(TCF_E_INVALID, "out is NULL");
+  *out = nullptr;
+  std::string why = validate(cfg);
+  if (!why.empty()) return fail(TCF_E_INVALID, why);
+  const size_t need = carve(cfg, nullptr, nullptr);
+  if (!workspace) return fail(TCF_E_WORKSPACE, "workspace is NULL");
+  if ((uintptr_t)workspace % kAlign) return fail(TCF_E_WORKSPACE, "workspace must be 256-byte aligned");
+  if (bytes < need) return fail(TCF_E_WORKSPACE, "workspace too small: need " + std::to_string(need) + " bytes");
+  tcf_grid* g = new (std::nothrow) tcf_grid();
+  if (!g) return fail(TCF_E_INVALID, "host allocation failed");
+  g->cfg = *cfg;
+  if (g->cfg.dim == 2) g->cfg.nz = 1;
+  g->D = dims_of(&g->cfg);
+  g->P = make_params(&g->cfg);
+  g->stream = (hipStream_t)hip_stream;
+  g->fp32 = cfg->precision == TCF_FP32_REFINE;
+  g->bytes = bytes;
+  carve(&g->cfg, workspace, g);
+  if (hipHostMalloc((void**)&g->hscal, sizeof(double) * S_NSLOT, hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&g->hflag, sizeof(int) * I_NFLAG, hipHostMallocDefault) != hipSuccess) {
+    delete g;
+    return fail(TCF_E_DEVICE, "pinned host buffer allocation failed");
+  }
+  // zero scalars and flags, the zero vector, and the pressure
+  fill_f64(g->stream, S_NSLOT, g->scal, 0.0);
+  init_flags(g->stream, g->iflag);
+  fill_f64(g->stream, g->D.N, g->zero64, 0.0);
+  fill_f64(g->stream, g->D.N, g->p64, 0.0);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    hipHostFree(g->hscal);
+    hipHostFree(g->hflag);
+    delete g;
+    return fail(TCF_E_DEVICE, std::string("init kernels: ") + hipGetErrorString(e));
+  }
+  *out = g;
+  return TCF_OK;
+}
+
+tcf_status tcf_set_fields(tcf_grid* g, double t, const double* alpha, const double* T, const double* u,
+                          const double* v, const double* w, const double* p) {
+  g_err.clear();
+  if (!g) return fail(TCF_E_INVALID, "grid is NULL");
+  if (!alpha || !T || !u || !v) return fail(TCF_E_INVALID, "alpha, T, u, v must be non-NULL");
+  if (g->D.dim == 3 && !w) return fail(TCF_E_INVALID, "w must be non-NULL in 3D");
+  if (g->D.dim == 2 && w) return fail(TCF_E_INVALID, "w must be NULL in 2D");
+  if (!std::isfinite(t)) return fail(TCF_E_INVALID, "t must be finite");
+  hipStream_t s = g->stream;
+  const Dims& D = g->D;
+  copy_f64(s, D.Nu, u, g->u64);
+  copy_f64(s, D.Nv, v, g->v64);
+  if (D.dim == 3) copy_f64(s, D.Nw, w, g->w64);
+  zero_walls<double>(g->P, s, g->u64, g->v64, g->w64);
+  if (p) copy_f64(s, D.N, p, g->p64);
+  else fill_f64(s, D.N, g->p64, 0.0);
+  if (g->fp32) {
+    to_f32(s, D.N, alpha, g->f32.a);
+    to_f32(s, D.N, T, g->f32.T);
+    to_f32(s, D.Nu, g->u64, g->f32.u);
+    to_f32(s, D.Nv, g->v64, g->f32.v);
+    if (D.dim == 3) to_f32(s, D.Nw, g->w64, g->f32.w);
+  } else {
+    copy_f64(s, D.N, alpha, g->f64.a);
+    copy_f64(s, D.N, T, g->f64.T);
+  }
+  HIPCHECK(hipGetLastError());
+  g->t = t;
+  g->has_fields = true;
+  return TCF_OK;
+}
+
+tcf_status tcf_get_fields(const tcf_grid* gc, double* t, double* alpha, double* T, double* u, double* v, double* w,
+                          double* p) {
+  g_err.clear();
+  if (!gc) return fail(TCF_E_INVALID, "grid is NULL");
+  tcf_grid* g = const_cast<tcf_grid*>(gc);
+  if (!g->has_fields) return fail(TCF_E_STATE, "fields not set");
+  hipStream_t s = g->stream;
+  const Dims& D = g->D;
+  if (t) *t = g->t;
+  if (g->fp32) {
+    if (alpha) to_f64(s, D.N, g->f32.a, alpha);
+    if (T) to_f64(s, D.N, g->f32.T, T);
+  } else {
+    if (alpha) copy_f64(s, D.N, g->f64.a, alpha);
+    if (T) copy_f64(s, D.N, g->f64.T, T);
+  }
+  if (u) copy_f64(s, D.Nu, g->u64, u);
+  if (v) copy_f64(s, D.Nv, g->v64, v);
+  if (w && D.dim == 3) copy_f64(s, D.Nw, g->w64, w);
+  if (p) copy_f64(s, D.N, g->p64, p);
+  HIPCHECK(hipGetLastError());
+  return TCF_OK;
+}
+
+tcf_status tcf_step(tcf_grid* g, double dt, int nsteps, tcf_step_info* info) {
+  g_err.clear();
+  if (!g) return fail(TCF_E_INVALID, "grid is NULL");
+  if (!(dt > 0) || !std::isfinite(dt)) return fail(TCF_E_INVALID, "dt must be positive and finite");
+  if (nsteps < 0) return fail(TCF_E_INVALID, "nsteps must be >= 0");
+  if (!g->has_fields) return fail(TCF_E_STATE, "fields not set");
+  if (info) std::memset(info, 0, sizeof(*info));
+  tcf_status worst = TCF_OK;
+  for (int k = 0; k < nsteps; ++k) {
+    const bool last = k == nsteps - 1;
+    tcf_status st = g->fp32 ? step_once<float>(g, dt, last ? info : nullptr, last && info != nullptr)
+                            : step_once<double>(g, dt, last ? info : nullptr, last && info != nullptr);
+    if (st == TCF_E_NOT_CONVERGED) {
+      worst = st;
+      continue;
+    }
+    if (st != TCF_OK) {
+      if (st == TCF_E_NONFINITE && info) info->nonfinite = 1;
+      if (st == TCF_E_NONFINITE && g_err.empty()) g_err = "non-finite residual in step " + std::to_string(k);
+      return st;
+    }
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(TCF_E_DEVICE, std::string("step kernels: ") + hipGetErrorString(e));
+  if (worst != TCF_OK && g_err.empty()) g_err = "pressure solve did not converge";
+  return worst;
+}
+
+tcf_status tcf_solve_pressure(tcf_grid* g, const double* rhs, double* p, tcf_step_info* info) {
+  g_err.clear();
+  if (!g) return fail(TCF_E_INVALID, "grid is NULL");
+  if (!rhs || !p) return fail(TCF_E_INVALID, "rhs and p must be non-NULL");
+  if (!g->has_fields) return fail(TCF_E_STATE, "fields not set");
+  if (info) std::memset(info, 0, sizeof(*info));
+  hipStream_t s = g->stream;
+  const long N = g->D.N;
+  copy_f64(s, N, rhs, g->b64);
+  const int nbp = sum64_partials(s, N, g->b64, g->part[0]);
+  finalize(s, g->part[0], nbp, g->scal, g->iflag, F_MEAN, S_MEAN, (double)N);
+  if (g->fp32) prepare_operator<float>(g);
+  else prepare_operator<double>(g);
+  tcf_status st = solve(g, p, info);
+  hipError_t e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return fail(TCF_E_DEVICE, std::string("solve: ") + hipGetErrorString(e));
+  return st;
+}
+
+tcf_status tcf_predictor(tcf_grid* g, double dt, double* us, double* vs, double* ws) {
+  g_err.clear();
+  if (!g) return fail(TCF_E_INVALID, "grid is NULL");
+  if (!us || !vs || (g->D.dim == 3 && !ws)) return fail(TCF_E_INVALID, "output pointers must be non-NULL");
+  if (!(dt > 0) || !std::isfinite(dt)) return fail(TCF_E_INVALID, "dt must be positive and finite");
+  if (!g->has_fields) return fail(TCF_E_STATE, "fields not set");
+  return g->fp32 ? predictor_only<float>(g, dt, us, vs, ws) : predictor_only<double>(g, dt, us, vs, ws);
+}
+
+tcf_status tcf_apply_A(tcf_grid* g, const double* x, double* y) {
+  g_err.clear();
+  if (!g) return fail(TCF_E_INVALID, "grid is NULL");
+  if (!x || !y) return fail(TCF_E_INVALID, "x and y must be non-NULL");
+  if (!g->has_fields) return fail(TCF_E_STATE, "fields not set");
+  hipStream_t s = g->stream;
+  if (g->fp32) prepare_operator<float>(g);
+  else prepare_operator<double>(g);
+  // y = -(0 - 0) - K x = A x, with scal[S_MEAN] = 0 and a zero rhs
+  fill_f64(s, 1, g->scal + S_MEAN, 0.0);
+  resid64(s, g->D.dim, g->D.nx, g->D.ny, g->D.nz, g->ax64, g->ay64, g->az64, g->zero64, g->scal, x, y, g->part[0],
+          g->part[1]);
+  HIPCHECK(hipGetLastError());
+  return TCF_OK;
+}
+
+void tcf_destroy(tcf_grid* g) {
+  if (!g) return;
+  hipStreamSynchronize(g->stream);
+  hipHostFree(g->hscal);
+  hipHostFree(g->hflag);
+  delete g;
+}
+
+const char* tcf_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,123 @@
+// Internal declarations shared by the host library and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace tcf {
+
+// Constants of one launch, passed by value.  Material laws mix linearly in
+// clamp(alpha, 0, 1); sigma(T) = sigma0 + s (T - T0).
+struct KParams {
+  int nx, ny, nz, dim;
+  double h, ih, dt, t;
+  double rho1, rho2, mu1, mu2, rhocp1, rhocp2, lam1, lam2;
+  double sigma0, s, T0;
+  int Tbc[6];
+  double Tw[6];
+  double qP, qr, qx0, qy0, qvx, qvy;
+  double weno_eps, neps;
+};
+
+// One multigrid level: face weights of K (the positive semi-definite
+// negative of A), omega/diag, and work vectors.
+template <class R>
+struct Level {
+  int nx, ny, nz;
+  R *ax, *ay, *az, *wdiag;
+  R *x, *x2, *b;
+  __host__ __device__ long n() const { return (long)nx * ny * nz; }
+};
+
+// Slots of the device scalar block (FP64).
+enum Slot { S_MEAN = 0, S_BB, S_RR, S_RZ, S_DQ, S_ALPHA, S_BETA, S_TOL2, S_SCALE,
+            S_SUMA, S_AMIN, S_AMAX, S_UMAX, S_DIV2, S_NONFIN, S_RR64, S_BB64, S_PMEAN, S_NSLOT = 24 };
+// Integer flags: done, iteration count.
+enum IFlag { I_DONE = 0, I_ITERS = 1, I_NFLAG = 4 };
+enum FinOp { F_STORE = 0, F_MEAN, F_BB, F_ALPHA, F_RR, F_RZ_FIRST, F_RZ, F_MIN, F_MAX, F_SCALE };
+
+constexpr int kBlock = 256;
+inline int nblocks_cells(int nx, int ny, int nz) { return ((nx + 63) / 64) * ((ny + 3) / 4) * nz; }
+
+// ---- launchers (defined in tcf_kernels.hip) --------------------------------
+template <class R>
+void transport_stage(const KParams& P, hipStream_t s, const R* a, const R* T, const R* ab, const R* Tb,
+                     const R* u, const R* v, const R* w, R* ao, R* To, double cb, double ci);
+template <class R>
+void geometry(const KParams& P, hipStream_t s, const R* a, const R* T, R* sk, R* Mx, R* My, R* Mz);
+template <class R>
+void predictor(const KParams& P, hipStream_t s, const R* a, const R* sk, const R* Mx, const R* My,
+               const R* Mz, const R* u, const R* v, const R* w, R* us, R* vs, R* ws);
+// b = D u* / dt in FP64, per-block partial sums of b -> part
+template <class R>
+void divergence_rhs(const KParams& P, hipStream_t s, const R* us, const R* vs, const R* ws, double* b,
+                    double* part);
+// fine-level face weights (FP64) from alpha; optional FP32 copies
+template <class R>
+void face_weights(const KParams& P, hipStream_t s, const R* a, double* ax, double* ay, double* az,
+                  float* fx, float* fy, float* fz);
+template <class R>
+void make_wdiag(hipStream_t s, int dim, const Level<R>& L, double omega);
+template <class R>
+void coarsen_weights(hipStream_t s, int dim, const Level<R>& F, const Level<R>& C);
+
+// PCG / multigrid building blocks on a level; all partial sums in FP64
+template <class R>
+void rhs_resid(hipStream_t s, int dim, const Level<R>& L, const double* b, const double* scal, R* x, R* r,
+               double* part_bb, double* part_rr);
+template <class R>
+void spmv_dot(hipStream_t s, int dim, const Level<R>& L, const R* d, R* q, double* part,
+              const int* iflag);
+template <class R>
+void update_xr(hipStream_t s, long n, const double* scal, R* x, R* r, const R* d, const R* q, double* part, const int* iflag);
+template <class R>
+void update_d(hipStream_t s, long n, const double* scal, const R* z, R* d, int first, const int* iflag);
+template <class R>
+void mg_smooth_first(hipStream_t s, const Level<R>& L, const R* b, R* x, const int* iflag);
+template <class R>
+void mg_smooth(hipStream_t s, int dim, const Level<R>& L, const R* b, const R* x, R* xo, double* part_rz, const int* iflag);
+template <class R>
+void mg_resid_restrict(hipStream_t s, int dim, const Level<R>& F, const R* b, const R* x, R* bc,
+                       const int* iflag);
+template <class R>
+void mg_prolong_smooth(hipStream_t s, int dim, const Level<R>& F, const Level<R>& C, const R* b, const R* x,
+                       R* xo, double omega_c, double* part_rz, const int* iflag);
+template <class R>
+void mg_coarse_solve(hipStream_t s, int dim, const Level<R>& L, const R* b, R* x, int sweeps,
+                     const int* iflag);
+
+void finalize(hipStream_t s, const double* part, int nparts, double* scal, int* iflag, int op, int slot,
+              double arg);
+void init_flags(hipStream_t s, int* iflag);
+
+// FP64 refinement helpers (FP32 mode)
+void resid64(hipStream_t s, int dim, int nx, int ny, int nz, const double* ax, const double* ay,
+             const double* az, const double* b, const double* scal, const double* p, double* r,
+             double* part_bb, double* part_rr);
+void scale_to32(hipStream_t s, long n, const double* r, const double* scal, float* r32);
+void add_scaled(hipStream_t s, long n, const float* e, const double* scal, double* p);
+void subtract_mean(hipStream_t s, long n, const double* scal, int slot, double* p);
+int sum64_partials(hipStream_t s, long n, const double* x, double* part);
+template <class R>
+int dot_partials(hipStream_t s, long n, const R* x, const R* y, double* part);
+template <class R>
+void fill(hipStream_t s, long n, R* y, double v);
+
+template <class R>
+void project(const KParams& P, hipStream_t s, const R* a, const double* p, const R* us, const R* vs,
+             const R* ws, double* u, double* v, double* w, R* ur, R* vr, R* wr);
+template <class R>
+void diagnostics(const KParams& P, hipStream_t s, const R* a, const double* u, const double* v,
+                 const double* w, double* part, int stride);
+
+// conversions
+void to_f32(hipStream_t s, long n, const double* x, float* y);
+void to_f64(hipStream_t s, long n, const float* x, double* y);
+void copy_f64(hipStream_t s, long n, const double* x, double* y);
+void fill_f64(hipStream_t s, long n, double* y, double v);
+template <class R>
+void zero_walls(const KParams& P, hipStream_t s, R* u, R* v, R* w);
+
+}  // namespace tcf

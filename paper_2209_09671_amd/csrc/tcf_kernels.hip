@@ -1,0 +1,1126 @@
+// HIP kernels of the thermocapillary projection step for gfx950.
+//
+// Launch shape: blocks of 64 x 4 threads (one wavefront per x-row segment,
+// so every global access along x is a coalesced 64-lane transaction), grid
+// over (x tiles, y tiles, z planes).  Ghost values outside the walls are
+// produced on the fly by reflected indexing (see the ghost rules below), so
+// the arrays have exactly the ABI layout and need no padding or ghost-fill
+// pass.  Reductions are deterministic: wavefront shuffles, then LDS, then one
+// FP64 partial per block, summed in a fixed order by a one-block finalize.
+#include <cfloat>
+#include <cmath>
+
+#include "tcf_internal.h"
+
+namespace tcf {
+namespace {
+
+constexpr int BX = 64, BY = 4;
+
+// ---------------------------------------------------------------------------
+// Ghost rules.  alpha: even reflection.  T: even (Neumann) or 2 T_w - mirror
+// (Dirichlet).  Velocity component C: odd reflection about its wall faces
+// along C (normal), odd reflection about the wall along the other axes
+// (tangential, no slip).
+__device__ __forceinline__ int refl(int i, int n) { return i < 0 ? -1 - i : (i >= n ? 2 * n - 1 - i : i); }
+
+__device__ __forceinline__ long cidx(int i, int j, int k, int nx, int ny) {
+  return (long)i + (long)nx * ((long)j + (long)ny * k);
+}
+
+template <int DIM, class R>
+__device__ __forceinline__ R A_at(const R* __restrict__ a, int i, int j, int k, int nx, int ny, int nz) {
+  return a[cidx(refl(i, nx), refl(j, ny), DIM == 3 ? refl(k, nz) : 0, nx, ny)];
+}
+
+template <int DIM, class R>
+__device__ __forceinline__ R T_at(const R* __restrict__ T, int i, int j, int k, const KParams& P) {
+  R v = T[cidx(refl(i, P.nx), refl(j, P.ny), DIM == 3 ? refl(k, P.nz) : 0, P.nx, P.ny)];
+  if (i < 0 && P.Tbc[0]) v = R(2) * R(P.Tw[0]) - v;
+  if (i >= P.nx && P.Tbc[1]) v = R(2) * R(P.Tw[1]) - v;
+  if (j < 0 && P.Tbc[2]) v = R(2) * R(P.Tw[2]) - v;
+  if (j >= P.ny && P.Tbc[3]) v = R(2) * R(P.Tw[3]) - v;
+  if (DIM == 3) {
+    if (k < 0 && P.Tbc[4]) v = R(2) * R(P.Tw[4]) - v;
+    if (k >= P.nz && P.Tbc[5]) v = R(2) * R(P.Tw[5]) - v;
+  }
+  return v;
+}
+
+template <int C>
+__device__ __forceinline__ long fidx(int i, int j, int k, int nx, int ny) {
+  if (C == 0) return (long)i + (long)(nx + 1) * ((long)j + (long)ny * k);
+  if (C == 1) return (long)i + (long)nx * ((long)j + (long)(ny + 1) * k);
+  return (long)i + (long)nx * ((long)j + (long)ny * k);
+}
+
+template <int C, int DIM, class R>
+__device__ __forceinline__ R V_at(const R* __restrict__ uc, int i, int j, int k, int nx, int ny, int nz) {
+  R sg = R(1);
+  int id[3] = {i, j, k};
+  const int n[3] = {nx, ny, nz};
+#pragma unroll
+  for (int e = 0; e < DIM; ++e) {
+    if (e == C) {
+      if (id[e] < 0) { id[e] = -id[e]; sg = -sg; }
+      else if (id[e] > n[e]) { id[e] = 2 * n[e] - id[e]; sg = -sg; }
+    } else {
+      if (id[e] < 0) { id[e] = -1 - id[e]; sg = -sg; }
+      else if (id[e] >= n[e]) { id[e] = 2 * n[e] - 1 - id[e]; sg = -sg; }
+    }
+  }
+  if (DIM == 2) id[2] = 0;
+  return sg * uc[fidx<C>(id[0], id[1], id[2], nx, ny)];
+}
+
+template <class R>
+__device__ __forceinline__ R mixp(R a, double p1, double p2) {
+  a = a < R(0) ? R(0) : (a > R(1) ? R(1) : a);
+  return R(p1) + a * R(p2 - p1);
+}
+
+// WENO5-JS value at the right edge of the centre sample c of (a,b,c,d,e).
+template <class R>
+__device__ __forceinline__ R weno5(R a, R b, R c, R d, R e, R eps) {
+  const R q0 = (R(2) * a - R(7) * b + R(11) * c) * R(1.0 / 6.0);
+  const R q1 = (-b + R(5) * c + R(2) * d) * R(1.0 / 6.0);
+  const R q2 = (R(2) * c + R(5) * d - e) * R(1.0 / 6.0);
+  const R t0 = a - R(2) * b + c, u0 = a - R(4) * b + R(3) * c;
+  const R t1 = b - R(2) * c + d, u1 = b - d;
+  const R t2 = c - R(2) * d + e, u2 = R(3) * c - R(4) * d + e;
+  const R e0 = eps + (R(13.0 / 12.0) * t0 * t0 + R(0.25) * u0 * u0);
+  const R e1 = eps + (R(13.0 / 12.0) * t1 * t1 + R(0.25) * u1 * u1);
+  const R e2 = eps + (R(13.0 / 12.0) * t2 * t2 + R(0.25) * u2 * u2);
+  const R a0 = R(0.1) / (e0 * e0), a1 = R(0.6) / (e1 * e1), a2 = R(0.3) / (e2 * e2);
+  return (a0 * q0 + a1 * q1 + a2 * q2) / (a0 + a1 + a2);
+}
+
+// q[k] = Q(f-3+k), k = 0..5; value at face f (between Q(f-1) and Q(f)).
+template <class R>
+__device__ __forceinline__ R upwind(const R* q, R vel, R eps) {
+  return vel >= R(0) ? weno5(q[0], q[1], q[2], q[3], q[4], eps) : weno5(q[5], q[4], q[3], q[2], q[1], eps);
+}
+
+// ---------------------------------------------------------------------------
+// Deterministic block reduction (256 threads = 4 wavefronts of 64).
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_down(v, off, 64));
+  return v;
+}
+__device__ __forceinline__ double wave_min(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_down(v, off, 64));
+  return v;
+}
+
+template <int OP>  // 0 sum, 1 max, 2 min
+__device__ __forceinline__ double block_reduce(double v, double* sh) {
+  const int tid = threadIdx.x + blockDim.x * threadIdx.y;
+  const int lane = tid & 63, wid = tid >> 6;
+  v = OP == 0 ? wave_sum(v) : (OP == 1 ? wave_max(v) : wave_min(v));
+  __syncthreads();
+  if (lane == 0) sh[wid] = v;
+  __syncthreads();
+  double r = sh[0];
+  const int nw = (blockDim.x * blockDim.y + 63) >> 6;
+  for (int w = 1; w < nw; ++w) r = OP == 0 ? r + sh[w] : (OP == 1 ? fmax(r, sh[w]) : fmin(r, sh[w]));
+  return r;
+}
+
+__device__ __forceinline__ int block_linear() { return blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z); }
+
+// ---------------------------------------------------------------------------
+// S1: one SSP-RK3 stage for alpha and T.
+//   out = cb * base + ci * (in + dt * L(in))
+// L(alpha) = -div(u alpha), L(T) = -div(u T) + [div(lambda grad T) + Q delta_s]/(rho c_p)
+template <class R, int DIM>
+__global__ __launch_bounds__(256) void k_transport(KParams P, const R* __restrict__ a, const R* __restrict__ T,
+                                                   const R* ab, const R* Tb, const R* __restrict__ u,
+                                                   const R* __restrict__ v, const R* __restrict__ w, R* ao,
+                                                   R* To, R cb, R ci) {
+  const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
+  const int nx = P.nx, ny = P.ny, nz = P.nz;
+  if (i >= nx || j >= ny) return;
+  const R eps = R(P.weno_eps);
+  const long c = cidx(i, j, k, nx, ny);
+  R diva = R(0), divt = R(0);
+  // ---- x direction: faces i and i+1
+  {
+    R qa[7], qt[7];
+#pragma unroll
+    for (int m = 0; m < 7; ++m) {
+      qa[m] = A_at<DIM>(a, i - 3 + m, j, k, nx, ny, nz);
+      qt[m] = T_at<DIM>(T, i - 3 + m, j, k, P);
+    }
+    const R ulo = u[fidx<0>(i, j, k, nx, ny)], uhi = u[fidx<0>(i + 1, j, k, nx, ny)];
+    R Falo = R(0), Ftlo = R(0), Fahi = R(0), Fthi = R(0);
+    if (i > 0) { Falo = ulo * upwind(qa, ulo, eps); Ftlo = ulo * upwind(qt, ulo, eps); }
+    if (i < nx - 1) { Fahi = uhi * upwind(qa + 1, uhi, eps); Fthi = uhi * upwind(qt + 1, uhi, eps); }
+    diva += Fahi - Falo;
+    divt += Fthi - Ftlo;
+  }
+  // ---- y direction
+  {
+    R qa[7], qt[7];
+#pragma unroll
+    for (int m = 0; m < 7; ++m) {
+      qa[m] = A_at<DIM>(a, i, j - 3 + m, k, nx, ny, nz);
+      qt[m] = T_at<DIM>(T, i, j - 3 + m, k, P);
+    }
+    const R vlo = v[fidx<1>(i, j, k, nx, ny)], vhi = v[fidx<1>(i, j + 1, k, nx, ny)];
+    R Falo = R(0), Ftlo = R(0), Fahi = R(0), Fthi = R(0);
+    if (j > 0) { Falo = vlo * upwind(qa, vlo, eps); Ftlo = vlo * upwind(qt, vlo, eps); }
+    if (j < ny - 1) { Fahi = vhi * upwind(qa + 1, vhi, eps); Fthi = vhi * upwind(qt + 1, vhi, eps); }
+    diva += Fahi - Falo;
+    divt += Fthi - Ftlo;
+  }
+  if (DIM == 3) {
+    R qa[7], qt[7];
+#pragma unroll
+    for (int m = 0; m < 7; ++m) {
+      qa[m] = A_at<DIM>(a, i, j, k - 3 + m, nx, ny, nz);
+      qt[m] = T_at<DIM>(T, i, j, k - 3 + m, P);
+    }
+    const R wlo = w[fidx<2>(i, j, k, nx, ny)], whi = w[fidx<2>(i, j, k + 1, nx, ny)];
+    R Falo = R(0), Ftlo = R(0), Fahi = R(0), Fthi = R(0);
+    if (k > 0) { Falo = wlo * upwind(qa, wlo, eps); Ftlo = wlo * upwind(qt, wlo, eps); }
+    if (k < nz - 1) { Fahi = whi * upwind(qa + 1, whi, eps); Fthi = whi * upwind(qt + 1, whi, eps); }
+    diva += Fahi - Falo;
+    divt += Fthi - Ftlo;
+  }
+  const R ih = R(P.ih);
+  const R La = -diva * ih;
+  // conduction with arithmetic-mean face conductivity
+  const R ac = a[c], Tc = T[c];
+  const R lc = mixp(ac, P.lam1, P.lam2);
+  R cond = R(0);
+  {
+    const int di[6] = {-1, 1, 0, 0, 0, 0}, dj[6] = {0, 0, -1, 1, 0, 0}, dk[6] = {0, 0, 0, 0, -1, 1};
+#pragma unroll
+    for (int f = 0; f < 2 * DIM; ++f) {
+      const R an = A_at<DIM>(a, i + di[f], j + dj[f], k + dk[f], nx, ny, nz);
+      const R Tn = T_at<DIM>(T, i + di[f], j + dj[f], k + dk[f], P);
+      const R lf = R(0.5) * (lc + mixp(an, P.lam1, P.lam2));
+      cond += lf * (Tn - Tc);
+    }
+  }
+  cond *= ih * ih;
+  R src = R(0);
+  if (P.qP != 0.0) {
+    const R ih2 = R(0.5) * ih;
+    const R gx = (A_at<DIM>(a, i + 1, j, k, nx, ny, nz) - A_at<DIM>(a, i - 1, j, k, nx, ny, nz)) * ih2;
+    const R gy = (A_at<DIM>(a, i, j + 1, k, nx, ny, nz) - A_at<DIM>(a, i, j - 1, k, nx, ny, nz)) * ih2;
+    const R gz = DIM == 3 ? (A_at<DIM>(a, i, j, k + 1, nx, ny, nz) - A_at<DIM>(a, i, j, k - 1, nx, ny, nz)) * ih2 : R(0);
+    const R g2 = gx * gx + gy * gy + gz * gz;
+    const R ne = R(P.neps);
+    const R ds = g2 / (sqrt(g2 + ne * ne) + ne);
+    // Gaussian flux evaluated in FP64 (beam position and exponent)
+    const double xl = P.qx0 + P.qvx * P.t, yl = P.qy0 + P.qvy * P.t;
+    const double x = (i + 0.5) * P.h, y = (j + 0.5) * P.h;
+    const double r2 = (x - xl) * (x - xl) + (y - yl) * (y - yl);
+    const double R2 = P.qr * P.qr;
+    const double Q = 2.0 * P.qP / (M_PI * R2) * exp(-2.0 * r2 / R2);
+    src = R(Q) * ds;
+  }
+  const R LT = -divt * ih + (cond + src) / mixp(ac, P.rhocp1, P.rhocp2);
+  const R dt = R(P.dt);
+  ao[c] = cb * ab[c] + ci * (ac + dt * La);
+  To[c] = cb * Tb[c] + ci * (Tc + dt * LT);
+}
+
+// ---------------------------------------------------------------------------
+// S3: interface geometry per interior cell -> sigma*kappa, M.
+template <class R, int DIM>
+__device__ __forceinline__ void normal_at(const R* __restrict__ a, int i, int j, int k, int nx, int ny, int nz,
+                                          R ih2, R ne, R n[3]) {
+  const R gx = (A_at<DIM>(a, i + 1, j, k, nx, ny, nz) - A_at<DIM>(a, i - 1, j, k, nx, ny, nz)) * ih2;
+  const R gy = (A_at<DIM>(a, i, j + 1, k, nx, ny, nz) - A_at<DIM>(a, i, j - 1, k, nx, ny, nz)) * ih2;
+  const R gz = DIM == 3 ? (A_at<DIM>(a, i, j, k + 1, nx, ny, nz) - A_at<DIM>(a, i, j, k - 1, nx, ny, nz)) * ih2 : R(0);
+  const R inv = R(1) / sqrt(gx * gx + gy * gy + gz * gz + ne * ne);
+  n[0] = gx * inv;
+  n[1] = gy * inv;
+  n[2] = gz * inv;
+}
+
+template <class R, int DIM>
+__global__ __launch_bounds__(256) void k_geometry(KParams P, const R* __restrict__ a, const R* __restrict__ T,
+                                                  R* __restrict__ sk, R* __restrict__ Mx, R* __restrict__ My,
+                                                  R* __restrict__ Mz) {
+  const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
+  const int nx = P.nx, ny = P.ny, nz = P.nz;
+  if (i >= nx || j >= ny) return;
+  const R ih2 = R(0.5 * P.ih), ne = R(P.neps);
+  R nn[3], np[3];
+  normal_at<R, DIM>(a, i + 1, j, k, nx, ny, nz, ih2, ne, np);
+  normal_at<R, DIM>(a, i - 1, j, k, nx, ny, nz, ih2, ne, nn);
+  R divn = (np[0] - nn[0]) * ih2;
+  normal_at<R, DIM>(a, i, j + 1, k, nx, ny, nz, ih2, ne, np);
+  normal_at<R, DIM>(a, i, j - 1, k, nx, ny, nz, ih2, ne, nn);
+  divn += (np[1] - nn[1]) * ih2;
+  if (DIM == 3) {
+    normal_at<R, DIM>(a, i, j, k + 1, nx, ny, nz, ih2, ne, np);
+    normal_at<R, DIM>(a, i, j, k - 1, nx, ny, nz, ih2, ne, nn);
+    divn += (np[2] - nn[2]) * ih2;
+  }
+  const R kappa = -divn;
+  const R gx = (A_at<DIM>(a, i + 1, j, k, nx, ny, nz) - A_at<DIM>(a, i - 1, j, k, nx, ny, nz)) * ih2;
+  const R gy = (A_at<DIM>(a, i, j + 1, k, nx, ny, nz) - A_at<DIM>(a, i, j - 1, k, nx, ny, nz)) * ih2;
+  const R gz = DIM == 3 ? (A_at<DIM>(a, i, j, k + 1, nx, ny, nz) - A_at<DIM>(a, i, j, k - 1, nx, ny, nz)) * ih2 : R(0);
+  const R g2 = gx * gx + gy * gy + gz * gz;
+  const R ge = sqrt(g2 + ne * ne);
+  const R ds = g2 / (ge + ne);
+  const R n0 = gx / ge, n1 = gy / ge, n2 = gz / ge;
+  const long c = cidx(i, j, k, nx, ny);
+  const R s = R(P.s);
+  const R sigma = R(P.sigma0) + s * (T[c] - R(P.T0));
+  const R gs0 = s * (T_at<DIM>(T, i + 1, j, k, P) - T_at<DIM>(T, i - 1, j, k, P)) * ih2;
+  const R gs1 = s * (T_at<DIM>(T, i, j + 1, k, P) - T_at<DIM>(T, i, j - 1, k, P)) * ih2;
+  const R gs2 = DIM == 3 ? s * (T_at<DIM>(T, i, j, k + 1, P) - T_at<DIM>(T, i, j, k - 1, P)) * ih2 : R(0);
+  const R ndg = n0 * gs0 + n1 * gs1 + n2 * gs2;
+  sk[c] = sigma * kappa;
+  Mx[c] = ds * (gs0 - n0 * ndg);
+  My[c] = ds * (gs1 - n1 * ndg);
+  if (DIM == 3) Mz[c] = ds * (gs2 - n2 * ndg);
+}
+
+// ---------------------------------------------------------------------------
+// S4-S5: predictor for velocity component D on its interior faces.
+template <class R, int DIM, int D>
+__global__ __launch_bounds__(256) void k_predictor(KParams P, const R* __restrict__ a, const R* __restrict__ sk,
+                                                   const R* __restrict__ M, const R* __restrict__ u,
+                                                   const R* __restrict__ v, const R* __restrict__ w,
+                                                   R* __restrict__ out) {
+  const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
+  const int nx = P.nx, ny = P.ny, nz = P.nz;
+  const int fnx = nx + (D == 0), fny = ny + (D == 1);
+  if (i >= fnx || j >= fny) return;
+  const long fo = fidx<D>(i, j, k, nx, ny);
+  const int id[3] = {i, j, k};
+  const int nD = D == 0 ? nx : (D == 1 ? ny : nz);
+  if (id[D] == 0 || id[D] == nD) { out[fo] = R(0); return; }
+  const R* vel[3] = {u, v, w};
+  const R* ud = vel[D];
+  const R eps = R(P.weno_eps), ih = R(P.ih);
+  int L[3] = {i, j, k};
+  L[D] -= 1;
+  const long cL = cidx(L[0], L[1], L[2], nx, ny), cR = cidx(i, j, k, nx, ny);
+  R conv = R(0), visc = R(0);
+#pragma unroll
+  for (int e = 0; e < DIM; ++e) {
+    // 7 samples of component D along e at offsets -3..3
+    R q[7];
+#pragma unroll
+    for (int m = 0; m < 7; ++m) {
+      int o[3] = {0, 0, 0};
+      o[e] = m - 3;
+      q[m] = V_at<D, DIM>(ud, i + o[0], j + o[1], k + o[2], nx, ny, nz);
+    }
+    if (e == D) {
+      const R Ulo = R(0.5) * (q[2] + q[3]), Uhi = R(0.5) * (q[3] + q[4]);
+      const R Flo = Ulo * upwind(q, Ulo, eps), Fhi = Uhi * upwind(q + 1, Uhi, eps);
+      const R mL = mixp(a[cL], P.mu1, P.mu2), mR = mixp(a[cR], P.mu1, P.mu2);
+      const R tlo = R(2) * mL * (q[3] - q[2]) * ih, thi = R(2) * mR * (q[4] - q[3]) * ih;
+      conv += (Fhi - Flo) * ih;
+      visc += (thi - tlo) * ih;
+    } else {
+      R F[2], tau[2];
+#pragma unroll
+      for (int side = 0; side < 2; ++side) {
+        const int ef = id[e] + side;
+        int pL[3] = {L[0], L[1], L[2]}, pR[3] = {i, j, k};
+        pL[e] = ef;
+        pR[e] = ef;
+        R veL, veR;
+        if (e == 0) {
+          veL = V_at<0, DIM>(u, pL[0], pL[1], pL[2], nx, ny, nz);
+          veR = V_at<0, DIM>(u, pR[0], pR[1], pR[2], nx, ny, nz);
+        } else if (e == 1) {
+          veL = V_at<1, DIM>(v, pL[0], pL[1], pL[2], nx, ny, nz);
+          veR = V_at<1, DIM>(v, pR[0], pR[1], pR[2], nx, ny, nz);
+        } else {
+          veL = V_at<2, DIM>(w, pL[0], pL[1], pL[2], nx, ny, nz);
+          veR = V_at<2, DIM>(w, pR[0], pR[1], pR[2], nx, ny, nz);
+        }
+        const R Vb = R(0.5) * (veL + veR);
+        F[side] = Vb * upwind(q + side, Vb, eps);
+        const R dud = (q[3 + side] - q[2 + side]) * ih;
+        const R dve = (veR - veL) * ih;
+        int c1[3] = {L[0], L[1], L[2]}, c2[3] = {i, j, k}, c3[3] = {L[0], L[1], L[2]}, c4[3] = {i, j, k};
+        c1[e] = ef - 1;
+        c2[e] = ef - 1;
+        c3[e] = ef;
+        c4[e] = ef;
+        const R me = R(0.25) * (mixp(A_at<DIM>(a, c1[0], c1[1], c1[2], nx, ny, nz), P.mu1, P.mu2) +
+                                mixp(A_at<DIM>(a, c2[0], c2[1], c2[2], nx, ny, nz), P.mu1, P.mu2) +
+                                mixp(A_at<DIM>(a, c3[0], c3[1], c3[2], nx, ny, nz), P.mu1, P.mu2) +
+                                mixp(A_at<DIM>(a, c4[0], c4[1], c4[2], nx, ny, nz), P.mu1, P.mu2));
+        tau[side] = me * (dud + dve);
+      }
+      conv += (F[1] - F[0]) * ih;
+      visc += (tau[1] - tau[0]) * ih;
+    }
+  }
+  const R aL = a[cL], aR = a[cR];
+  const R fst = R(0.5) * (sk[cL] + sk[cR]) * (aR - aL) * ih + R(0.5) * (M[cL] + M[cR]);
+  const R rhof = R(0.5) * (mixp(aL, P.rho1, P.rho2) + mixp(aR, P.rho1, P.rho2));
+  out[fo] = ud[fo] + R(P.dt) * (-conv + (visc + fst) / rhof);
+}
+
+// ---------------------------------------------------------------------------
+// S6: b = D u* / dt (FP64), block partial sums of b.
+template <class R, int DIM>
+__global__ __launch_bounds__(256) void k_divergence(KParams P, const R* __restrict__ us, const R* __restrict__ vs,
+                                                    const R* __restrict__ ws, double* __restrict__ b,
+                                                    double* __restrict__ part) {
+  __shared__ double sh[8];
+  const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
+  const int nx = P.nx, ny = P.ny;
+  double val = 0.0;
+  if (i < nx && j < ny) {
+    double s = ((double)us[fidx<0>(i + 1, j, k, nx, ny)] - (double)us[fidx<0>(i, j, k, nx, ny)]) +
+               ((double)vs[fidx<1>(i, j + 1, k, nx, ny)] - (double)vs[fidx<1>(i, j, k, nx, ny)]);
+    if (DIM == 3) s += (double)ws[fidx<2>(i, j, k + 1, nx, ny)] - (double)ws[fidx<2>(i, j, k, nx, ny)];
+    val = s * P.ih / P.dt;
+    b[cidx(i, j, k, nx, ny)] = val;
+  }
+  const double r = block_reduce<0>(val, sh);
+  if (threadIdx.x == 0 && threadIdx.y == 0) part[block_linear()] = r;
+}
+
+// Fine-level face weights a_f = 1/(h^2 rho_f) on interior faces, 0 on walls.
+template <class R, int DIM, int D>
+__global__ __launch_bounds__(256) void k_face_weights(KParams P, const R* __restrict__ a, double* __restrict__ af,
+                                                      float* __restrict__ f32) {
+  const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
+  const int nx = P.nx, ny = P.ny, nz = P.nz;
+  const int fnx = nx + (D == 0), fny = ny + (D == 1);
+  if (i >= fnx || j >= fny) return;
+  const int id[3] = {i, j, k};
+  const int nD = D == 0 ? nx : (D == 1 ? ny : nz);
+  const long fo = fidx<D>(i, j, k, nx, ny);
+  double val = 0.0;
+  if (id[D] > 0 && id[D] < nD) {
+    int L[3] = {i, j, k};
+    L[D] -= 1;
+    const double rL = mixp((double)a[cidx(L[0], L[1], L[2], nx, ny)], P.rho1, P.rho2);
+    const double rR = mixp((double)a[cidx(i, j, k, nx, ny)], P.rho1, P.rho2);
+    val = (P.ih * P.ih) / (0.5 * (rL + rR));
+  }
+  af[fo] = val;
+  if (f32) f32[fo] = (float)val;
+}
+
+// Sum of the face weights of a cell -> omega / diag.
+template <class R, int DIM>
+__global__ __launch_bounds__(256) void k_wdiag(int nx, int ny, int nz, const R* __restrict__ ax,
+                                               const R* __restrict__ ay, const R* __restrict__ az,
+                                               R* __restrict__ wd, R omega) {
+  const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
+  if (i >= nx || j >= ny) return;
+  R d = ax[fidx<0>(i, j, k, nx, ny)] + ax[fidx<0>(i + 1, j, k, nx, ny)] + ay[fidx<1>(i, j, k, nx, ny)] +
+        ay[fidx<1>(i, j + 1, k, nx, ny)];
+  if (DIM == 3) d += az[fidx<2>(i, j, k, nx, ny)] + az[fidx<2>(i, j, k + 1, nx, ny)];
+  wd[cidx(i, j, k, nx, ny)] = d > R(0) ? omega / d : R(0);
+}
+
+// Galerkin coarse face weights for piecewise-constant P and R = P^T.
+template <class R, int DIM, int D>
+__global__ __launch_bounds__(256) void k_coarsen(int fnx_, int fny_, int fnz_, const R* __restrict__ ff,
+                                                 int cnx, int cny, int cnz, R* __restrict__ cf) {
+  const int I = blockIdx.x * BX + threadIdx.x, J = blockIdx.y * BY + threadIdx.y, K = blockIdx.z;
+  const int cfx = cnx + (D == 0), cfy = cny + (D == 1);
+  if (I >= cfx || J >= cfy) return;
+  const int kz = DIM == 3 ? 2 : 1;
+  R s = R(0);
+  if (D == 0) {
+    for (int dk = 0; dk < kz; ++dk)
+      for (int dj = 0; dj < 2; ++dj) s += ff[fidx<0>(2 * I, 2 * J + dj, kz * K + dk, fnx_, fny_)];
+  } else if (D == 1) {
+    for (int dk = 0; dk < kz; ++dk)
+      for (int di = 0; di < 2; ++di) s += ff[fidx<1>(2 * I + di, 2 * J, kz * K + dk, fnx_, fny_)];
+  } else {
+    for (int dj = 0; dj < 2; ++dj)
+      for (int di = 0; di < 2; ++di) s += ff[fidx<2>(2 * I + di, 2 * J + dj, 2 * K, fnx_, fny_)];
+  }
+  cf[fidx<D>(I, J, K, cnx, cny)] = s;
+}
+
+// (K x)_c = sum_f a_f (x_c - x_nb) on a level (walls carry a_f = 0).
+template <class R, int DIM>
+__device__ __forceinline__ R applyK(const R* __restrict__ x, const R* __restrict__ ax, const R* __restrict__ ay,
+                                    const R* __restrict__ az, int i, int j, int k, int nx, int ny, int nz) {
+  const long c = cidx(i, j, k, nx, ny);
+  const R xc = x[c];
+  R s = R(0);
+  if (i > 0) s += ax[fidx<0>(i, j, k, nx, ny)] * (xc - x[c - 1]);
+  if (i < nx - 1) s += ax[fidx<0>(i + 1, j, k, nx, ny)] * (xc - x[c + 1]);
+  if (j > 0) s += ay[fidx<1>(i, j, k, nx, ny)] * (xc - x[c - nx]);
+  if (j < ny - 1) s += ay[fidx<1>(i, j + 1, k, nx, ny)] * (xc - x[c + nx]);
+  if (DIM == 3) {
+    const long pl = (long)nx * ny;
+    if (k > 0) s += az[fidx<2>(i, j, k, nx, ny)] * (xc - x[c - pl]);
+    if (k < nz - 1) s += az[fidx<2>(i, j, k + 1, nx, ny)] * (xc - x[c + pl]);
+  }
+  return s;
+}
+
+// rhs = -(b - mean); r = rhs - K x (FP64 b, level precision vectors)
+template <class R, int DIM>
+__global__ __launch_bounds__(256) void k_rhs_resid(Level<R> L, const double* __restrict__ b,
+                                                   const double* __restrict__ scal, R* __restrict__ x,
+                                                   R* __restrict__ r, double* __restrict__ pbb,
+                                                   double* __restrict__ prr) {
+  __shared__ double sh[8];
+  const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
+  double vb = 0.0, vr = 0.0;
+  if (i < L.nx && j < L.ny) {
+    const long c = cidx(i, j, k, L.nx, L.ny);
+    const double rhs = -(b[c] - scal[S_MEAN]);
+    const R rr = R(rhs) - applyK<R, DIM>(x, L.ax, L.ay, L.az, i, j, k, L.nx, L.ny, L.nz);
+    r[c] = rr;
+    vb = rhs * rhs;
+    vr = (double)rr * (double)rr;
+  }
+  const double sb = block_reduce<0>(vb, sh);
+  const double sr = block_reduce<0>(vr, sh);
+  if (threadIdx.x == 0 && threadIdx.y == 0) {
+    pbb[block_linear()] = sb;
+    prr[block_linear()] = sr;
+  }
+}
+
+template <class R, int DIM>
+__global__ __launch_bounds__(256) void k_spmv_dot(Level<R> L, const R* __restrict__ d, R* __restrict__ q,
+                                                  double* __restrict__ part, const int* __restrict__ iflag) {
+  if (iflag[I_DONE]) return;
+  __shared__ double sh[8];
+  const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
+  double val = 0.0;
+  if (i < L.nx && j < L.ny) {
+    const long c = cidx(i, j, k, L.nx, L.ny);
+    const R qq = applyK<R, DIM>(d, L.ax, L.ay, L.az, i, j, k, L.nx, L.ny, L.nz);
+    q[c] = qq;
+    val = (double)d[c] * (double)qq;
+  }
+  const double s = block_reduce<0>(val, sh);
+  if (threadIdx.x == 0 && threadIdx.y == 0) part[block_linear()] = s;
+}
+
+template <class R>
+__global__ __launch_bounds__(256) void k_update_xr(long n, const double* __restrict__ scal, R* __restrict__ x,
+                                                   R* __restrict__ r, const R* __restrict__ d,
+                                                   const R* __restrict__ q, double* __restrict__ part,
+                                                   const int* __restrict__ iflag) {
+  if (iflag[I_DONE]) return;
+  __shared__ double sh[8];
+  const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  double val = 0.0;
+  if (c < n) {
+    const R al = R(scal[S_ALPHA]);
+    x[c] += al * d[c];
+    const R rr = r[c] - al * q[c];
+    r[c] = rr;
+    val = (double)rr * (double)rr;
+  }
+  const double s = block_reduce<0>(val, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+template <class R>
+__global__ __launch_bounds__(256) void k_update_d(long n, const double* __restrict__ scal, const R* __restrict__ z,
+                                                  R* __restrict__ d, int first, const int* __restrict__ iflag) {
+  if (iflag[I_DONE]) return;
+  const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  d[c] = first ? z[c] : z[c] + R(scal[S_BETA]) * d[c];
+}
+
+template <class R>
+__global__ __launch_bounds__(256) void k_smooth_first(long n, const R* __restrict__ wd, const R* __restrict__ b,
+                                                      R* __restrict__ x, const int* __restrict__ iflag) {
+  if (iflag[I_DONE]) return;
+  const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < n) x[c] = wd[c] * b[c];
+}
+
+// damped Jacobi: xo = x + wdiag (b - K x); optional partial of b.xo (= r.z on the finest level)
+template <class R, int DIM>
+__global__ __launch_bounds__(256) void k_smooth(Level<R> L, const R* __restrict__ b, const R* __restrict__ x,
+                                                R* __restrict__ xo, double* __restrict__ part,
+                                                const int* __restrict__ iflag) {
+  if (iflag[I_DONE]) return;
+  __shared__ double sh[8];
+  const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
+  double val = 0.0;
+  if (i < L.nx && j < L.ny) {
+    const long c = cidx(i, j, k, L.nx, L.ny);
+    const R Kx = applyK<R, DIM>(x, L.ax, L.ay, L.az, i, j, k, L.nx, L.ny, L.nz);
+    const R xn = x[c] + L.wdiag[c] * (b[c] - Kx);
+    xo[c] = xn;
+    val = (double)b[c] * (double)xn;
+  }
+  if (part) {
+    const double s = block_reduce<0>(val, sh);
+    if (threadIdx.x == 0 && threadIdx.y == 0) part[block_linear()] = s;
+  }
+}
+
+// bc = R (b - K x): each coarse cell sums the residuals of its children.
+template <class R, int DIM>
+__global__ __launch_bounds__(256) void k_resid_restrict(Level<R> F, int cnx, int cny, int cnz,
+                                                        const R* __restrict__ b, const R* __restrict__ x,
+                                                        R* __restrict__ bc, const int* __restrict__ iflag) {
+  if (iflag[I_DONE]) return;
+  const int I = blockIdx.x * BX + threadIdx.x, J = blockIdx.y * BY + threadIdx.y, K = blockIdx.z;
+  if (I >= cnx || J >= cny) return;
+  const int kz = DIM == 3 ? 2 : 1;
+  R s = R(0);
+  for (int dk = 0; dk < kz; ++dk)
+    for (int dj = 0; dj < 2; ++dj)
+      for (int di = 0; di < 2; ++di) {
+        const int i = 2 * I + di, j = 2 * J + dj, k = kz * K + dk;
+        const long c = cidx(i, j, k, F.nx, F.ny);
+        s += b[c] - applyK<R, DIM>(x, F.ax, F.ay, F.az, i, j, k, F.nx, F.ny, F.nz);
+      }
+  bc[cidx(I, J, K, cnx, cny)] = s;
+}
+
+// x' = x + omega_c P e (on the fly), xo = x' + wdiag (b - K x')
+template <class R, int DIM>
+__global__ __launch_bounds__(256) void k_prolong_smooth(Level<R> L, int cnx, int cny, const R* __restrict__ e,
+                                                        const R* __restrict__ b, const R* __restrict__ x,
+                                                        R* __restrict__ xo, R omc, double* __restrict__ part,
+                                                        const int* __restrict__ iflag) {
+  if (iflag[I_DONE]) return;
+  __shared__ double sh[8];
+  const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
+  const int kz = DIM == 3 ? 2 : 1;
+  double val = 0.0;
+  if (i < L.nx && j < L.ny) {
+    const int nx = L.nx, ny = L.ny, nz = L.nz;
+    auto xp = [&](int ii, int jj, int kk) {
+      return x[cidx(ii, jj, kk, nx, ny)] + omc * e[cidx(ii >> 1, jj >> 1, kk / kz, cnx, cny)];
+    };
+    const long c = cidx(i, j, k, nx, ny);
+    const R xc = xp(i, j, k);
+    R s = R(0);
+    if (i > 0) s += L.ax[fidx<0>(i, j, k, nx, ny)] * (xc - xp(i - 1, j, k));
+    if (i < nx - 1) s += L.ax[fidx<0>(i + 1, j, k, nx, ny)] * (xc - xp(i + 1, j, k));
+    if (j > 0) s += L.ay[fidx<1>(i, j, k, nx, ny)] * (xc - xp(i, j - 1, k));
+    if (j < ny - 1) s += L.ay[fidx<1>(i, j + 1, k, nx, ny)] * (xc - xp(i, j + 1, k));
+    if (DIM == 3) {
+      if (k > 0) s += L.az[fidx<2>(i, j, k, nx, ny)] * (xc - xp(i, j, k - 1));
+      if (k < nz - 1) s += L.az[fidx<2>(i, j, k + 1, nx, ny)] * (xc - xp(i, j, k + 1));
+    }
+    const R xn = xc + L.wdiag[c] * (b[c] - s);
+    xo[c] = xn;
+    val = (double)b[c] * (double)xn;
+  }
+  if (part) {
+    const double s = block_reduce<0>(val, sh);
+    if (threadIdx.x == 0 && threadIdx.y == 0) part[block_linear()] = s;
+  }
+}
+
+// Coarsest level: fixed number of damped-Jacobi sweeps from zero in one block
+// (x and x2 are ping-pong buffers; the result ends in x).
+template <class R, int DIM>
+__global__ __launch_bounds__(1024) void k_coarse(Level<R> L, const R* __restrict__ b, R* __restrict__ x,
+                                                 R* __restrict__ x2, int sweeps, const int* __restrict__ iflag) {
+  if (iflag[I_DONE]) return;
+  const long n = L.n();
+  for (long c = threadIdx.x; c < n; c += blockDim.x) x[c] = R(0);
+  __syncthreads();
+  R* src = x;
+  R* dst = x2;
+  for (int s = 0; s < sweeps; ++s) {
+    for (long c = threadIdx.x; c < n; c += blockDim.x) {
+      const int i = (int)(c % L.nx), j = (int)((c / L.nx) % L.ny), k = (int)(c / ((long)L.nx * L.ny));
+      const R Kx = applyK<R, DIM>(src, L.ax, L.ay, L.az, i, j, k, L.nx, L.ny, L.nz);
+      dst[c] = src[c] + L.wdiag[c] * (b[c] - Kx);
+    }
+    __syncthreads();
+    R* t = src;
+    src = dst;
+    dst = t;
+  }
+  if (src != x)
+    for (long c = threadIdx.x; c < n; c += blockDim.x) x[c] = src[c];
+}
+
+// One-block deterministic finalize of per-block partials.
+__global__ __launch_bounds__(256) void k_finalize(const double* __restrict__ part, int n,
+                                                  double* __restrict__ scal, int* __restrict__ iflag, int op,
+                                                  int slot, double arg) {
+  __shared__ double sh[8];
+  if ((op == F_ALPHA || op == F_RR || op == F_RZ) && iflag[I_DONE]) return;
+  double v;
+  if (op == F_MIN) {
+    v = DBL_MAX;
+    for (int t = threadIdx.x; t < n; t += blockDim.x) v = fmin(v, part[t]);
+    v = block_reduce<2>(v, sh);
+  } else if (op == F_MAX) {
+    v = -DBL_MAX;
+    for (int t = threadIdx.x; t < n; t += blockDim.x) v = fmax(v, part[t]);
+    v = block_reduce<1>(v, sh);
+  } else {
+    v = 0.0;
+    for (int t = threadIdx.x; t < n; t += blockDim.x) v += part[t];
+    v = block_reduce<0>(v, sh);
+  }
+  if (threadIdx.x != 0) return;
+  switch (op) {
+    case F_STORE: case F_MIN: case F_MAX: scal[slot] = v; break;
+    case F_MEAN: scal[slot] = v / arg; break;
+    case F_BB: scal[S_BB] = v; scal[S_TOL2] = arg * v; break;
+    case F_ALPHA: scal[S_DQ] = v; scal[S_ALPHA] = scal[S_RZ] / v; break;
+    case F_RR:
+      scal[S_RR] = v;
+      iflag[I_ITERS] += (int)arg;
+      if (!(v > scal[S_TOL2])) iflag[I_DONE] = 1;   // also stops on NaN
+      break;
+    case F_RZ_FIRST: scal[S_RZ] = v; scal[S_BETA] = 0.0; break;
+    case F_RZ: scal[S_BETA] = v / scal[S_RZ]; scal[S_RZ] = v; break;
+    case F_SCALE: scal[S_RR64] = v; scal[S_SCALE] = sqrt(v / arg); break;
+  }
+}
+
+__global__ void k_init_flags(int* iflag) {
+  if (threadIdx.x < I_NFLAG) iflag[threadIdx.x] = 0;
+}
+
+// ---- FP64 refinement helpers -------------------------------------------------
+template <int DIM>
+__global__ __launch_bounds__(256) void k_resid64(int nx, int ny, int nz, const double* __restrict__ ax,
+                                                 const double* __restrict__ ay, const double* __restrict__ az,
+                                                 const double* __restrict__ b, const double* __restrict__ scal,
+                                                 const double* __restrict__ p, double* __restrict__ r,
+                                                 double* __restrict__ pbb, double* __restrict__ prr) {
+  __shared__ double sh[8];
+  const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
+  double vb = 0.0, vr = 0.0;
+  if (i < nx && j < ny) {
+    const long c = cidx(i, j, k, nx, ny);
+    const double rhs = -(b[c] - scal[S_MEAN]);
+    const double rr = rhs - applyK<double, DIM>(p, ax, ay, az, i, j, k, nx, ny, nz);
+    r[c] = rr;
+    vb = rhs * rhs;
+    vr = rr * rr;
+  }
+  const double sb = block_reduce<0>(vb, sh);
+  const double sr = block_reduce<0>(vr, sh);
+  if (threadIdx.x == 0 && threadIdx.y == 0) {
+    pbb[block_linear()] = sb;
+    prr[block_linear()] = sr;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_scale_to32(long n, const double* __restrict__ r,
+                                                    const double* __restrict__ scal, float* __restrict__ r32) {
+  const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < n) r32[c] = (float)(r[c] / scal[S_SCALE]);
+}
+__global__ __launch_bounds__(256) void k_add_scaled(long n, const float* __restrict__ e,
+                                                    const double* __restrict__ scal, double* __restrict__ p) {
+  const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < n) p[c] += scal[S_SCALE] * (double)e[c];
+}
+__global__ __launch_bounds__(256) void k_sub_mean(long n, const double* __restrict__ scal, int slot,
+                                                  double* __restrict__ p) {
+  const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < n) p[c] -= scal[slot];
+}
+
+// per-block partial sums of x (FP64) and of x.y (level precision)
+__global__ __launch_bounds__(256) void k_sum64(long n, const double* __restrict__ x, double* __restrict__ part) {
+  __shared__ double sh[8];
+  const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const double v = c < n ? x[c] : 0.0;
+  const double s = block_reduce<0>(v, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+template <class R>
+__global__ __launch_bounds__(256) void k_dot(long n, const R* __restrict__ x, const R* __restrict__ y,
+                                             double* __restrict__ part) {
+  __shared__ double sh[8];
+  const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const double v = c < n ? (double)x[c] * (double)y[c] : 0.0;
+  const double s = block_reduce<0>(v, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+template <class R>
+__global__ __launch_bounds__(256) void k_fill(long n, R* __restrict__ y, R v) {
+  const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < n) y[c] = v;
+}
+
+// ---------------------------------------------------------------------------
+// S8: projection; in FP32 mode also refresh the FP32 mirror of the velocity.
+template <class R, int DIM, int D>
+__global__ __launch_bounds__(256) void k_project(KParams P, const R* __restrict__ a, const double* __restrict__ p,
+                                                 const R* __restrict__ us, double* __restrict__ u,
+                                                 R* __restrict__ ur) {
+  const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
+  const int nx = P.nx, ny = P.ny, nz = P.nz;
+  const int fnx = nx + (D == 0), fny = ny + (D == 1);
+  if (i >= fnx || j >= fny) return;
+  const int id[3] = {i, j, k};
+  const int nD = D == 0 ? nx : (D == 1 ? ny : nz);
+  const long fo = fidx<D>(i, j, k, nx, ny);
+  double val = 0.0;
+  if (id[D] > 0 && id[D] < nD) {
+    int L[3] = {i, j, k};
+    L[D] -= 1;
+    const long cL = cidx(L[0], L[1], L[2], nx, ny), cR = cidx(i, j, k, nx, ny);
+    const double rhof = 0.5 * (mixp((double)a[cL], P.rho1, P.rho2) + mixp((double)a[cR], P.rho1, P.rho2));
+    val = (double)us[fo] - P.dt * (1.0 / rhof) * (p[cR] - p[cL]) * P.ih;
+  }
+  u[fo] = val;
+  if (ur) ur[fo] = (R)val;
+}
+
+// Diagnostics per cell: alpha (sum/min/max), |D u|^2 and max |u_f| over the
+// cell's low faces (every interior face is some cell's low face).
+template <class R, int DIM>
+__global__ __launch_bounds__(256) void k_diag(KParams P, const R* __restrict__ a, const double* __restrict__ u,
+                                              const double* __restrict__ v, const double* __restrict__ w,
+                                              double* __restrict__ part, int stride) {
+  __shared__ double sh[8];
+  const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
+  const int nx = P.nx, ny = P.ny;
+  double s = 0.0, mn = DBL_MAX, mx = -DBL_MAX, d2 = 0.0, um = 0.0, fin = 0.0;
+  if (i < nx && j < ny) {
+    const double av = (double)a[cidx(i, j, k, nx, ny)];
+    s = av;
+    mn = av;
+    mx = av;
+    const double u0 = u[fidx<0>(i, j, k, nx, ny)], u1 = u[fidx<0>(i + 1, j, k, nx, ny)];
+    const double v0 = v[fidx<1>(i, j, k, nx, ny)], v1 = v[fidx<1>(i, j + 1, k, nx, ny)];
+    double dv = (u1 - u0) + (v1 - v0);
+    um = fmax(fabs(u0), fabs(v0));
+    double chk = av + u0 + v0;
+    if (DIM == 3) {
+      const double w0 = w[fidx<2>(i, j, k, nx, ny)], w1 = w[fidx<2>(i, j, k + 1, nx, ny)];
+      dv += w1 - w0;
+      um = fmax(um, fabs(w0));
+      chk += w0;
+    }
+    dv *= P.ih;
+    d2 = dv * dv;
+    fin = isfinite(chk) ? 0.0 : 1.0;
+  }
+  const int bl = block_linear();
+  double r;
+  r = block_reduce<0>(s, sh);
+  if (threadIdx.x == 0 && threadIdx.y == 0) part[bl] = r;
+  r = block_reduce<2>(mn, sh);
+  if (threadIdx.x == 0 && threadIdx.y == 0) part[stride + bl] = r;
+  r = block_reduce<1>(mx, sh);
+  if (threadIdx.x == 0 && threadIdx.y == 0) part[2 * stride + bl] = r;
+  r = block_reduce<0>(d2, sh);
+  if (threadIdx.x == 0 && threadIdx.y == 0) part[3 * stride + bl] = r;
+  r = block_reduce<1>(um, sh);
+  if (threadIdx.x == 0 && threadIdx.y == 0) part[4 * stride + bl] = r;
+  r = block_reduce<1>(fin, sh);
+  if (threadIdx.x == 0 && threadIdx.y == 0) part[5 * stride + bl] = r;
+}
+
+__global__ __launch_bounds__(256) void k_to_f32(long n, const double* __restrict__ x, float* __restrict__ y) {
+  const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < n) y[c] = (float)x[c];
+}
+__global__ __launch_bounds__(256) void k_to_f64(long n, const float* __restrict__ x, double* __restrict__ y) {
+  const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < n) y[c] = (double)x[c];
+}
+__global__ __launch_bounds__(256) void k_copy64(long n, const double* __restrict__ x, double* __restrict__ y) {
+  const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < n) y[c] = x[c];
+}
+__global__ __launch_bounds__(256) void k_fill64(long n, double* __restrict__ y, double v) {
+  const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < n) y[c] = v;
+}
+
+template <class R, int D>
+__global__ __launch_bounds__(256) void k_zero_walls(int nx, int ny, int nz, R* __restrict__ f) {
+  // threads cover the two wall planes of component D
+  const int nD = D == 0 ? nx : (D == 1 ? ny : nz);
+  const int a0 = D == 0 ? ny : nx, a1 = D == 2 ? ny : nz;  // extents of the plane
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long plane = (long)a0 * a1;
+  if (t >= 2 * plane) return;
+  const int side = (int)(t / plane);
+  const long q = t % plane;
+  const int p0 = (int)(q % a0), p1 = (int)(q / a0);
+  const int m = side ? nD : 0;
+  long idx;
+  if (D == 0) idx = fidx<0>(m, p0, p1, nx, ny);
+  else if (D == 1) idx = fidx<1>(p0, m, p1, nx, ny);
+  else idx = fidx<2>(p0, p1, m, nx, ny);
+  f[idx] = R(0);
+}
+
+inline dim3 grid_for(int fnx, int fny, int fnz) { return dim3((fnx + BX - 1) / BX, (fny + BY - 1) / BY, fnz); }
+inline dim3 blk() { return dim3(BX, BY, 1); }
+inline int nblk1(long n) { return (int)((n + 255) / 256); }
+
+}  // namespace
+
+// =============================================================================
+// Launchers
+template <class R>
+void transport_stage(const KParams& P, hipStream_t s, const R* a, const R* T, const R* ab, const R* Tb,
+                     const R* u, const R* v, const R* w, R* ao, R* To, double cb, double ci) {
+  dim3 g = grid_for(P.nx, P.ny, P.nz);
+  if (P.dim == 3)
+    hipLaunchKernelGGL((k_transport<R, 3>), g, blk(), 0, s, P, a, T, ab, Tb, u, v, w, ao, To, R(cb), R(ci));
+  else
+    hipLaunchKernelGGL((k_transport<R, 2>), g, blk(), 0, s, P, a, T, ab, Tb, u, v, w, ao, To, R(cb), R(ci));
+}
+
+template <class R>
+void geometry(const KParams& P, hipStream_t s, const R* a, const R* T, R* sk, R* Mx, R* My, R* Mz) {
+  dim3 g = grid_for(P.nx, P.ny, P.nz);
+  if (P.dim == 3) hipLaunchKernelGGL((k_geometry<R, 3>), g, blk(), 0, s, P, a, T, sk, Mx, My, Mz);
+  else hipLaunchKernelGGL((k_geometry<R, 2>), g, blk(), 0, s, P, a, T, sk, Mx, My, Mz);
+}
+
+template <class R>
+void predictor(const KParams& P, hipStream_t s, const R* a, const R* sk, const R* Mx, const R* My, const R* Mz,
+               const R* u, const R* v, const R* w, R* us, R* vs, R* ws) {
+  if (P.dim == 3) {
+    hipLaunchKernelGGL((k_predictor<R, 3, 0>), grid_for(P.nx + 1, P.ny, P.nz), blk(), 0, s, P, a, sk, Mx, u, v, w, us);
+    hipLaunchKernelGGL((k_predictor<R, 3, 1>), grid_for(P.nx, P.ny + 1, P.nz), blk(), 0, s, P, a, sk, My, u, v, w, vs);
+    hipLaunchKernelGGL((k_predictor<R, 3, 2>), grid_for(P.nx, P.ny, P.nz + 1), blk(), 0, s, P, a, sk, Mz, u, v, w, ws);
+  } else {
+    hipLaunchKernelGGL((k_predictor<R, 2, 0>), grid_for(P.nx + 1, P.ny, 1), blk(), 0, s, P, a, sk, Mx, u, v, w, us);
+    hipLaunchKernelGGL((k_predictor<R, 2, 1>), grid_for(P.nx, P.ny + 1, 1), blk(), 0, s, P, a, sk, My, u, v, w, vs);
+  }
+}
+
+template <class R>
+void divergence_rhs(const KParams& P, hipStream_t s, const R* us, const R* vs, const R* ws, double* b,
+                    double* part) {
+  dim3 g = grid_for(P.nx, P.ny, P.nz);
+  if (P.dim == 3) hipLaunchKernelGGL((k_divergence<R, 3>), g, blk(), 0, s, P, us, vs, ws, b, part);
+  else hipLaunchKernelGGL((k_divergence<R, 2>), g, blk(), 0, s, P, us, vs, ws, b, part);
+}
+
+template <class R>
+void face_weights(const KParams& P, hipStream_t s, const R* a, double* ax, double* ay, double* az, float* fx,
+                  float* fy, float* fz) {
+  if (P.dim == 3) {
+    hipLaunchKernelGGL((k_face_weights<R, 3, 0>), grid_for(P.nx + 1, P.ny, P.nz), blk(), 0, s, P, a, ax, fx);
+    hipLaunchKernelGGL((k_face_weights<R, 3, 1>), grid_for(P.nx, P.ny + 1, P.nz), blk(), 0, s, P, a, ay, fy);
+    hipLaunchKernelGGL((k_face_weights<R, 3, 2>), grid_for(P.nx, P.ny, P.nz + 1), blk(), 0, s, P, a, az, fz);
+  } else {
+    hipLaunchKernelGGL((k_face_weights<R, 2, 0>), grid_for(P.nx + 1, P.ny, 1), blk(), 0, s, P, a, ax, fx);
+    hipLaunchKernelGGL((k_face_weights<R, 2, 1>), grid_for(P.nx, P.ny + 1, 1), blk(), 0, s, P, a, ay, fy);
+  }
+}
+
+template <class R>
+void make_wdiag(hipStream_t s, int dim, const Level<R>& L, double omega) {
+  dim3 g = grid_for(L.nx, L.ny, L.nz);
+  if (dim == 3) hipLaunchKernelGGL((k_wdiag<R, 3>), g, blk(), 0, s, L.nx, L.ny, L.nz, L.ax, L.ay, L.az, L.wdiag, R(omega));
+  else hipLaunchKernelGGL((k_wdiag<R, 2>), g, blk(), 0, s, L.nx, L.ny, L.nz, L.ax, L.ay, L.az, L.wdiag, R(omega));
+}
+
+template <class R>
+void coarsen_weights(hipStream_t s, int dim, const Level<R>& F, const Level<R>& C) {
+  if (dim == 3) {
+    hipLaunchKernelGGL((k_coarsen<R, 3, 0>), grid_for(C.nx + 1, C.ny, C.nz), blk(), 0, s, F.nx, F.ny, F.nz, F.ax, C.nx, C.ny, C.nz, C.ax);
+    hipLaunchKernelGGL((k_coarsen<R, 3, 1>), grid_for(C.nx, C.ny + 1, C.nz), blk(), 0, s, F.nx, F.ny, F.nz, F.ay, C.nx, C.ny, C.nz, C.ay);
+    hipLaunchKernelGGL((k_coarsen<R, 3, 2>), grid_for(C.nx, C.ny, C.nz + 1), blk(), 0, s, F.nx, F.ny, F.nz, F.az, C.nx, C.ny, C.nz, C.az);
+  } else {
+    hipLaunchKernelGGL((k_coarsen<R, 2, 0>), grid_for(C.nx + 1, C.ny, 1), blk(), 0, s, F.nx, F.ny, F.nz, F.ax, C.nx, C.ny, C.nz, C.ax);
+    hipLaunchKernelGGL((k_coarsen<R, 2, 1>), grid_for(C.nx, C.ny + 1, 1), blk(), 0, s, F.nx, F.ny, F.nz, F.ay, C.nx, C.ny, C.nz, C.ay);
+  }
+}
+
+template <class R>
+void rhs_resid(hipStream_t s, int dim, const Level<R>& L, const double* b, const double* scal, R* x, R* r,
+               double* pbb, double* prr) {
+  dim3 g = grid_for(L.nx, L.ny, L.nz);
+  if (dim == 3) hipLaunchKernelGGL((k_rhs_resid<R, 3>), g, blk(), 0, s, L, b, scal, x, r, pbb, prr);
+  else hipLaunchKernelGGL((k_rhs_resid<R, 2>), g, blk(), 0, s, L, b, scal, x, r, pbb, prr);
+}
+
+template <class R>
+void spmv_dot(hipStream_t s, int dim, const Level<R>& L, const R* d, R* q, double* part,
+              const int* iflag) {
+  dim3 g = grid_for(L.nx, L.ny, L.nz);
+  if (dim == 3) hipLaunchKernelGGL((k_spmv_dot<R, 3>), g, blk(), 0, s, L, d, q, part, iflag);
+  else hipLaunchKernelGGL((k_spmv_dot<R, 2>), g, blk(), 0, s, L, d, q, part, iflag);
+}
+
+template <class R>
+void update_xr(hipStream_t s, long n, const double* scal, R* x, R* r, const R* d, const R* q, double* part, const int* iflag) {
+  hipLaunchKernelGGL((k_update_xr<R>), dim3(nblk1(n)), dim3(256), 0, s, n, scal, x, r, d, q, part, iflag);
+}
+
+template <class R>
+void update_d(hipStream_t s, long n, const double* scal, const R* z, R* d, int first, const int* iflag) {
+  hipLaunchKernelGGL((k_update_d<R>), dim3(nblk1(n)), dim3(256), 0, s, n, scal, z, d, first, iflag);
+}
+
+template <class R>
+void mg_smooth_first(hipStream_t s, const Level<R>& L, const R* b, R* x, const int* iflag) {
+  hipLaunchKernelGGL((k_smooth_first<R>), dim3(nblk1(L.n())), dim3(256), 0, s, L.n(), L.wdiag, b, x, iflag);
+}
+
+template <class R>
+void mg_smooth(hipStream_t s, int dim, const Level<R>& L, const R* b, const R* x, R* xo, double* part,
+               const int* iflag) {
+  dim3 g = grid_for(L.nx, L.ny, L.nz);
+  if (dim == 3) hipLaunchKernelGGL((k_smooth<R, 3>), g, blk(), 0, s, L, b, x, xo, part, iflag);
+  else hipLaunchKernelGGL((k_smooth<R, 2>), g, blk(), 0, s, L, b, x, xo, part, iflag);
+}
+
+template <class R>
+void mg_resid_restrict(hipStream_t s, int dim, const Level<R>& F, const R* b, const R* x, R* bc, const int* iflag) {
+  const int cnx = F.nx / 2, cny = F.ny / 2, cnz = dim == 3 ? F.nz / 2 : 1;
+  dim3 g = grid_for(cnx, cny, cnz);
+  if (dim == 3) hipLaunchKernelGGL((k_resid_restrict<R, 3>), g, blk(), 0, s, F, cnx, cny, cnz, b, x, bc, iflag);
+  else hipLaunchKernelGGL((k_resid_restrict<R, 2>), g, blk(), 0, s, F, cnx, cny, cnz, b, x, bc, iflag);
+}
+
+template <class R>
+void mg_prolong_smooth(hipStream_t s, int dim, const Level<R>& F, const Level<R>& C, const R* b, const R* x, R* xo,
+                       double omega_c, double* part, const int* iflag) {
+  dim3 g = grid_for(F.nx, F.ny, F.nz);
+  if (dim == 3)
+    hipLaunchKernelGGL((k_prolong_smooth<R, 3>), g, blk(), 0, s, F, C.nx, C.ny, C.x, b, x, xo, R(omega_c), part, iflag);
+  else
+    hipLaunchKernelGGL((k_prolong_smooth<R, 2>), g, blk(), 0, s, F, C.nx, C.ny, C.x, b, x, xo, R(omega_c), part, iflag);
+}
+
+template <class R>
+void mg_coarse_solve(hipStream_t s, int dim, const Level<R>& L, const R* b, R* x, int sweeps, const int* iflag) {
+  if (dim == 3) hipLaunchKernelGGL((k_coarse<R, 3>), dim3(1), dim3(1024), 0, s, L, b, x, L.x2, sweeps, iflag);
+  else hipLaunchKernelGGL((k_coarse<R, 2>), dim3(1), dim3(1024), 0, s, L, b, x, L.x2, sweeps, iflag);
+}
+
+void finalize(hipStream_t s, const double* part, int nparts, double* scal, int* iflag, int op, int slot,
+              double arg) {
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, part, nparts, scal, iflag, op, slot, arg);
+}
+
+void init_flags(hipStream_t s, int* iflag) { hipLaunchKernelGGL(k_init_flags, dim3(1), dim3(64), 0, s, iflag); }
+
+void resid64(hipStream_t s, int dim, int nx, int ny, int nz, const double* ax, const double* ay, const double* az,
+             const double* b, const double* scal, const double* p, double* r, double* pbb, double* prr) {
+  dim3 g = grid_for(nx, ny, nz);
+  if (dim == 3) hipLaunchKernelGGL((k_resid64<3>), g, blk(), 0, s, nx, ny, nz, ax, ay, az, b, scal, p, r, pbb, prr);
+  else hipLaunchKernelGGL((k_resid64<2>), g, blk(), 0, s, nx, ny, nz, ax, ay, az, b, scal, p, r, pbb, prr);
+}
+
+void scale_to32(hipStream_t s, long n, const double* r, const double* scal, float* r32) {
+  hipLaunchKernelGGL(k_scale_to32, dim3(nblk1(n)), dim3(256), 0, s, n, r, scal, r32);
+}
+void add_scaled(hipStream_t s, long n, const float* e, const double* scal, double* p) {
+  hipLaunchKernelGGL(k_add_scaled, dim3(nblk1(n)), dim3(256), 0, s, n, e, scal, p);
+}
+void subtract_mean(hipStream_t s, long n, const double* scal, int slot, double* p) {
+  hipLaunchKernelGGL(k_sub_mean, dim3(nblk1(n)), dim3(256), 0, s, n, scal, slot, p);
+}
+int sum64_partials(hipStream_t s, long n, const double* x, double* part) {
+  hipLaunchKernelGGL(k_sum64, dim3(nblk1(n)), dim3(256), 0, s, n, x, part);
+  return nblk1(n);
+}
+template <class R>
+int dot_partials(hipStream_t s, long n, const R* x, const R* y, double* part) {
+  hipLaunchKernelGGL((k_dot<R>), dim3(nblk1(n)), dim3(256), 0, s, n, x, y, part);
+  return nblk1(n);
+}
+template <class R>
+void fill(hipStream_t s, long n, R* y, double v) {
+  hipLaunchKernelGGL((k_fill<R>), dim3(nblk1(n)), dim3(256), 0, s, n, y, R(v));
+}
+template int dot_partials<double>(hipStream_t, long, const double*, const double*, double*);
+template int dot_partials<float>(hipStream_t, long, const float*, const float*, double*);
+template void fill<double>(hipStream_t, long, double*, double);
+template void fill<float>(hipStream_t, long, float*, double);
+
+template <class R>
+void project(const KParams& P, hipStream_t s, const R* a, const double* p, const R* us, const R* vs, const R* ws,
+             double* u, double* v, double* w, R* ur, R* vr, R* wr) {
+  if (P.dim == 3) {
+    hipLaunchKernelGGL((k_project<R, 3, 0>), grid_for(P.nx + 1, P.ny, P.nz), blk(), 0, s, P, a, p, us, u, ur);
+    hipLaunchKernelGGL((k_project<R, 3, 1>), grid_for(P.nx, P.ny + 1, P.nz), blk(), 0, s, P, a, p, vs, v, vr);
+    hipLaunchKernelGGL((k_project<R, 3, 2>), grid_for(P.nx, P.ny, P.nz + 1), blk(), 0, s, P, a, p, ws, w, wr);
+  } else {
+    hipLaunchKernelGGL((k_project<R, 2, 0>), grid_for(P.nx + 1, P.ny, 1), blk(), 0, s, P, a, p, us, u, ur);
+    hipLaunchKernelGGL((k_project<R, 2, 1>), grid_for(P.nx, P.ny + 1, 1), blk(), 0, s, P, a, p, vs, v, vr);
+  }
+}
+
+template <class R>
+void diagnostics(const KParams& P, hipStream_t s, const R* a, const double* u, const double* v, const double* w,
+                 double* part, int stride) {
+  dim3 g = grid_for(P.nx, P.ny, P.nz);
+  if (P.dim == 3) hipLaunchKernelGGL((k_diag<R, 3>), g, blk(), 0, s, P, a, u, v, w, part, stride);
+  else hipLaunchKernelGGL((k_diag<R, 2>), g, blk(), 0, s, P, a, u, v, w, part, stride);
+}
+
+void to_f32(hipStream_t s, long n, const double* x, float* y) {
+  hipLaunchKernelGGL(k_to_f32, dim3(nblk1(n)), dim3(256), 0, s, n, x, y);
+}
+void to_f64(hipStream_t s, long n, const float* x, double* y) {
+  hipLaunchKernelGGL(k_to_f64, dim3(nblk1(n)), dim3(256), 0, s, n, x, y);
+}
+void copy_f64(hipStream_t s, long n, const double* x, double* y) {
+  hipLaunchKernelGGL(k_copy64, dim3(nblk1(n)), dim3(256), 0, s, n, x, y);
+}
+void fill_f64(hipStream_t s, long n, double* y, double v) {
+  hipLaunchKernelGGL(k_fill64, dim3(nblk1(n)), dim3(256), 0, s, n, y, v);
+}
+
+template <class R>
+void zero_walls(const KParams& P, hipStream_t s, R* u, R* v, R* w) {
+  const int nx = P.nx, ny = P.ny, nz = P.nz;
+  hipLaunchKernelGGL((k_zero_walls<R, 0>), dim3(nblk1(2L * ny * nz)), dim3(256), 0, s, nx, ny, nz, u);
+  hipLaunchKernelGGL((k_zero_walls<R, 1>), dim3(nblk1(2L * nx * nz)), dim3(256), 0, s, nx, ny, nz, v);
+  if (P.dim == 3) hipLaunchKernelGGL((k_zero_walls<R, 2>), dim3(nblk1(2L * nx * ny)), dim3(256), 0, s, nx, ny, nz, w);
+}
+
+// explicit instantiations
+#define TCF_INST(R)                                                                                               \
+  template void transport_stage<R>(const KParams&, hipStream_t, const R*, const R*, const R*, const R*, const R*, \
+                                   const R*, const R*, R*, R*, double, double);                                   \
+  template void geometry<R>(const KParams&, hipStream_t, const R*, const R*, R*, R*, R*, R*);                     \
+  template void predictor<R>(const KParams&, hipStream_t, const R*, const R*, const R*, const R*, const R*,       \
+                             const R*, const R*, const R*, R*, R*, R*);                                           \
+  template void divergence_rhs<R>(const KParams&, hipStream_t, const R*, const R*, const R*, double*, double*);                                                                          \
+  template void face_weights<R>(const KParams&, hipStream_t, const R*, double*, double*, double*, float*, float*, \
+                                float*);                                                                          \
+  template void make_wdiag<R>(hipStream_t, int, const Level<R>&, double);                                         \
+  template void coarsen_weights<R>(hipStream_t, int, const Level<R>&, const Level<R>&);                           \
+  template void rhs_resid<R>(hipStream_t, int, const Level<R>&, const double*, const double*, R*, R*, double*,    \
+                             double*);                                                                      \
+  template void spmv_dot<R>(hipStream_t, int, const Level<R>&, const R*, R*, double*, const int*);          \
+  template void update_xr<R>(hipStream_t, long, const double*, R*, R*, const R*, const R*, double*, const int*);                                                                         \
+  template void update_d<R>(hipStream_t, long, const double*, const R*, R*, int, const int*);                     \
+  template void mg_smooth_first<R>(hipStream_t, const Level<R>&, const R*, R*, const int*);                       \
+  template void mg_smooth<R>(hipStream_t, int, const Level<R>&, const R*, const R*, R*, double*, const int*);                                                                         \
+  template void mg_resid_restrict<R>(hipStream_t, int, const Level<R>&, const R*, const R*, R*, const int*);      \
+  template void mg_prolong_smooth<R>(hipStream_t, int, const Level<R>&, const Level<R>&, const R*, const R*, R*,  \
+                                     double, double*, const int*);                                          \
+  template void mg_coarse_solve<R>(hipStream_t, int, const Level<R>&, const R*, R*, int, const int*);             \
+  template void project<R>(const KParams&, hipStream_t, const R*, const double*, const R*, const R*, const R*,    \
+                           double*, double*, double*, R*, R*, R*);                                                \
+  template void diagnostics<R>(const KParams&, hipStream_t, const R*, const double*, const double*,               \
+                               const double*, double*, int);                                                \
+  template void zero_walls<R>(const KParams&, hipStream_t, R*, R*, R*);
+
+TCF_INST(double)
+TCF_INST(float)
+
+}  // namespace tcf

@@ -208,13 +208,14 @@ def initial_state(c) -> dict:
 
 def stream_velocity(c, amp=1.0):
     """Discretely divergence-free MAC velocity from face differences of the
-    corner stream function psi = sin^2(pi x) sin^2(pi y)/pi (times cos(pi z)
-    in 3D), zero on every wall face.  Used to drive transport-only checks."""
+    corner stream function psi = L sin^2(pi x/Lx) sin^2(pi y/Ly)/pi (L = Ly,
+    so the speed is of order amp on any box; times a z profile in 3D), zero
+    on every wall face.  Used to drive transport-only checks."""
     nx, ny, nz, h = c["nx"], c["ny"], c["nz"], c["h"]
     lx, ly, lz = nx * h, ny * h, nz * h
     xn = np.arange(nx + 1) * h
     yn = np.arange(ny + 1) * h
-    psi = (np.sin(np.pi * xn / lx)[None, :] ** 2 * np.sin(np.pi * yn / ly)[:, None] ** 2) / np.pi
+    psi = ly * (np.sin(np.pi * xn / lx)[None, :] ** 2 * np.sin(np.pi * yn / ly)[:, None] ** 2) / np.pi
     if c["dim"] == 3:
         zc = (np.arange(nz) + 0.5) * h
         g = (0.5 + 0.5 * np.cos(np.pi * zc / lz))[:, None, None]

@@ -1,0 +1,83 @@
+"""C-ABI checks that need no GPU: the library loads, exports every entry
+point declared in include/tcf.h, sizes workspaces, and rejects bad
+arguments before touching the device."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_2209_09671_amd import inputs as I
+from paper_2209_09671_amd import tcf
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    src = open(os.path.join(ROOT, "include", "tcf.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(tcf_[a-z_A-Z0-9]+)\s*\(", src)))
+
+
+def test_header_lists_the_binding_exports():
+    assert set(declared_symbols()) == set(tcf.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = tcf.load()
+    for name in declared_symbols():
+        assert hasattr(lib, name), name
+
+
+@pytest.mark.parametrize("idx", [0, 1, 2, 3, 4])
+def test_workspace_sizes(idx):
+    c = I.config(idx)
+    n64 = tcf.workspace_bytes(c, precision=0)
+    n32 = tcf.workspace_bytes(c, precision=1)
+    N = c["nx"] * c["ny"] * c["nz"]
+    assert n64 > 20 * 8 * N and n32 > 20 * 4 * N
+    # the 256^3 box fits comfortably in one GPU's 288 GB
+    assert n64 < 60 * 8 * N + (1 << 20)
+
+
+@pytest.mark.parametrize("bad", [dict(dim=4), dict(nx=2), dict(nz=3), dict(h=-1.0), dict(precision=7),
+                                 dict(rho1=0.0), dict(p_maxit=0), dict(mg_nu=0), dict(flags=8),
+                                 dict(weno_eps=0.0)])
+def test_invalid_configs_rejected(bad):
+    c = dict(I.config(0))
+    if bad.get("nz") == 3:
+        c = dict(I.config(3))
+    c.update(bad)
+    assert tcf.workspace_bytes(c) == 0
+    lib = tcf.load()
+    cfg = tcf.make_config(c)
+    h = C.c_void_p()
+    st = lib.tcf_init_grid(C.byref(cfg), C.c_void_p(256), C.c_size_t(1 << 30), None, C.byref(h))
+    assert st == tcf.TCF_E_INVALID and h.value is None
+    assert lib.tcf_last_error().decode()
+
+
+def test_workspace_errors_before_device_use():
+    lib = tcf.load()
+    cfg = tcf.make_config(I.config(0))
+    h = C.c_void_p()
+    assert lib.tcf_init_grid(C.byref(cfg), None, C.c_size_t(1 << 30), None, C.byref(h)) == tcf.TCF_E_WORKSPACE
+    assert lib.tcf_init_grid(C.byref(cfg), C.c_void_p(256 + 8), C.c_size_t(1 << 30), None,
+                             C.byref(h)) == tcf.TCF_E_WORKSPACE
+    assert lib.tcf_init_grid(C.byref(cfg), C.c_void_p(256), C.c_size_t(16), None, C.byref(h)) == tcf.TCF_E_WORKSPACE
+    assert b"too small" in lib.tcf_last_error()
+
+
+def test_null_handles_rejected():
+    lib = tcf.load()
+    assert lib.tcf_step(None, C.c_double(1e-3), 1, None) == tcf.TCF_E_INVALID
+    assert lib.tcf_set_fields(None, C.c_double(0.0), None, None, None, None, None, None) == tcf.TCF_E_INVALID
+    assert lib.tcf_solve_pressure(None, None, None, None) == tcf.TCF_E_INVALID
+    lib.tcf_destroy(None)
+
+
+def test_binding_refuses_missing_library(monkeypatch, tmp_path):
+    monkeypatch.setattr(tcf, "_lib", None)
+    monkeypatch.setattr(tcf, "LIB_PATH", str(tmp_path / "nope.so"))
+    with pytest.raises(RuntimeError, match="no CPU fallback"):
+        tcf.load()
