@@ -1,0 +1,198 @@
+#!/usr/bin/env python
+"""Throughput of the thermocapillary projection step on one MI355X.
+
+A step is one pass of the whole path (WENO5-RK3 transport of alpha and T,
+geometry and CSF force, momentum predictor, MG-PCG pressure solve with FP64
+refinement, projection, FP64 diagnostics) over the 256^3 melt-pool workload
+(cell 2.5 um, density ratio 7500, moving 200 W Gaussian heat flux), all
+inputs resident in HBM.  The primary line is the FP32-stencil path with FP64
+iterative refinement at a divergence residual <= 1e-8; the plain FP64 path at
+the same accuracy is reported beside it.
+
+Prints ONE JSON line.  Options: --steps K --warmup W --gpus 1 --workload i
+--kernel FAMILY (kernel family for the roofline entry) --no-cpu --no-fp64.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+
+
+def algorithmic_bytes(family: str, c: dict, precision: int) -> float:
+    """Bytes one launch of a kernel family must move (each value once)."""
+    N = c["nx"] * c["ny"] * c["nz"]
+    w = 4 if precision == 1 else 8
+    nfaces_per_cell = 3 if c["dim"] == 3 else 2
+    if family == "smooth":
+        # x (read), b, omega/diag, one face weight per axis (read), x' (write)
+        return N * w * (3 + nfaces_per_cell + 1)
+    if family == "spmv":
+        # d, face weights, q (write)
+        return N * w * (1 + nfaces_per_cell + 1)
+    if family == "transport":
+        # averaged over the three stages: alpha, T, one velocity per axis,
+        # base alpha/T (stages 2, 3), outputs alpha, T
+        return N * w * (2 + nfaces_per_cell + 2 * 2 / 3 + 2)
+    if family == "predictor":
+        # per component launch: alpha, sigma*kappa, M_d, u, v, w, u*_d (write)
+        return N * w * (3 + nfaces_per_cell + 1)
+    if family == "resid64":
+        return N * 8 * (3 + nfaces_per_cell + 1)
+    raise ValueError(family)
+
+
+def kernel_source_hash() -> str:
+    src = os.path.join(ROOT, "paper_2209_09671_amd", "csrc", "tcf_kernels.hip")
+    return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+
+
+def measured_traffic(family: str, workload: str):
+    """HBM bytes per launch from committed rocprofv3 counter summaries, if
+    they were taken on the current kernel source (else None)."""
+    path = os.path.join(ROOT, "profiles", f"counters_{family}_{workload}.md")
+    if not os.path.exists(path):
+        return None
+    txt = open(path).read()
+    m = re.search(r"kernel_source_sha256_16:\s*([0-9a-f]+)", txt)
+    b = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", txt)
+    if not m or not b or m.group(1) != kernel_source_hash():
+        return None
+    return float(b.group(1))
+
+
+def cpu_baseline(c: dict, dt: float, rtol: float):
+    """One step of the same workload on the host cores with the FP64 oracle."""
+    from oracle import pyoracle as O
+    from paper_2209_09671_amd import inputs as I
+    st = I.initial_state(c)
+    t0 = time.perf_counter()
+    _, info, status = O.step(c, st, 0.0, dt, 1, rtol=rtol)
+    sec = time.perf_counter() - t0
+    N = c["nx"] * c["ny"] * c["nz"]
+    return {"value": N / sec / 1e6, "unit": "Mcell-steps/s", "cores": O.num_threads(), "kind": "oracle",
+            "sample": f"1 step of the {c['nx']}x{c['ny']}x{c['nz']} workload from its initial state, "
+                      f"FP64 oracle, pressure rtol {rtol:g} ({sec:.1f} s, {info['cg_iters']} CG iterations)"}
+
+
+def run_gpu(c, st, precision, steps, warmup, family=None):
+    import torch
+    from paper_2209_09671_amd import tcf
+    g = tcf.Grid(c, precision=precision)
+    g.set_state(st)
+    dt = c["dt"]
+    for _ in range(warmup):
+        g.step(dt, 1)
+    torch.cuda.synchronize()
+    if family:
+        g.profile(family)
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    iters, refs, worst_res, worst_div = 0, 0, 0.0, 0.0
+    e0.record(stream)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        info = g.step(dt, 1)
+        iters += info["cg_iters"]
+        refs += info["refine_iters"]
+        worst_res = max(worst_res, info["p_relres"])
+        worst_div = max(worst_div, info["div_rel"])
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ev_ms = e0.elapsed_time(e1)
+    kms, kn = g.profile_read() if family else (0.0, 0)
+    g.close()
+    del g
+    torch.cuda.empty_cache()
+    return dict(wall=wall, ev_ms=ev_ms, iters=iters / max(steps, 1), refs=refs / max(steps, 1),
+                relres=worst_res, div=worst_div, kernel_ms=kms, kernel_launches=kn, info=info)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", type=int, default=4)
+    ap.add_argument("--kernel", default="smooth")
+    ap.add_argument("--rtol", type=float, default=1e-8)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this path runs on one GPU; multi-GPU runs are not part of this build "
+              "(see the sharding notes in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2209_09671_amd import inputs as I
+
+    c = I.config(args.workload)
+    c["p_rtol"] = args.rtol
+    st = I.initial_state(c)
+    N = c["nx"] * c["ny"] * c["nz"]
+    wl = c["name"]
+
+    r32 = run_gpu(c, st, 1, args.steps, args.warmup, args.kernel)
+    sec = r32["ev_ms"] / 1e3
+    value = N * args.steps / sec / 1e6
+    fp64 = None
+    if not args.no_fp64:
+        r64 = run_gpu(c, st, 0, args.steps, args.warmup)
+        fp64 = {"value": N * args.steps / (r64["ev_ms"] / 1e3) / 1e6, "unit": "Mcell-steps/s",
+                "ms_per_step": r64["ev_ms"] / args.steps, "cg_iters_per_step": r64["iters"],
+                "max_div_rel": r64["div"], "max_p_relres": r64["relres"]}
+
+    roof = None
+    if r32["kernel_launches"]:
+        avg_ms = r32["kernel_ms"] / r32["kernel_launches"]
+        ab = algorithmic_bytes(args.kernel, c, 1)
+        ach = ab / (avg_ms / 1e3) / 1e9
+        traffic = measured_traffic(args.kernel, wl.replace("^", ""))
+        roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": args.kernel, "avg_launch_ms": round(avg_ms, 5),
+                "launches": r32["kernel_launches"], "algorithmic_bytes_per_launch": ab}
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(c, c["dt"], args.rtol)
+
+    out = {
+        "metric": "Mcell-steps/s (FP32 stencils + FP64 refinement, divergence residual <= 1e-8)",
+        "value": round(value, 3),
+        "unit": "Mcell-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(r32["ev_ms"] / args.steps, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": wl, "cells": N, "grid": [c["nx"], c["ny"], c["nz"]], "h_m": c["h"],
+                   "dt_s": c["dt"], "precision": "fp32 stencils/inner solve, fp64 refinement",
+                   "p_rtol": args.rtol, "cg_iters_per_step": round(r32["iters"], 2),
+                   "refine_iters_per_step": round(r32["refs"], 2), "max_p_relres": r32["relres"],
+                   "max_div_rel": r32["div"]},
+        "fp64_same_accuracy": fp64,
+        "wall_ms_per_step": round(r32["wall"] * 1e3 / args.steps, 4),
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

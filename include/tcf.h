@@ -142,6 +142,15 @@ tcf_status tcf_solve_pressure(tcf_grid* g, const double* rhs, double* p, tcf_ste
 tcf_status tcf_predictor(tcf_grid* g, double dt, double* us, double* vs, double* ws);
 tcf_status tcf_apply_A(tcf_grid* g, const double* x, double* y);
 
+/* Measurement: time every launch of one kernel family with HIP events on
+ * the grid's stream ("transport", "geometry", "predictor", "smooth" = the
+ * finest-level Jacobi sweeps, "spmv", "resid64", "project"; NULL or "" turns
+ * timing off and clears the totals).  tcf_profile_read synchronises on the
+ * last recorded event and returns the summed milliseconds and the number of
+ * timed launches since tcf_profile was called. */
+tcf_status tcf_profile(tcf_grid* g, const char* family);
+tcf_status tcf_profile_read(tcf_grid* g, double* total_ms, long* launches);
+
 /* Release the handle (the workspace stays the caller's). */
 void tcf_destroy(tcf_grid* g);
 

@@ -120,9 +120,50 @@ struct tcf_grid {
   double* hscal;  // pinned host mirror
   int* hflag;
   size_t bytes;
+  // optional event timing of one kernel family (measurement only)
+  int prof_family = -1;
+  std::vector<hipEvent_t> prof_ev;  // start/end pairs
+  size_t prof_used = 0;
+  double prof_ms = 0.0;
+  long prof_count = 0;
 };
 
 namespace {
+
+enum Family { FAM_TRANSPORT = 0, FAM_GEOMETRY, FAM_PREDICTOR, FAM_SMOOTH0, FAM_SPMV, FAM_RESID64, FAM_PROJECT, FAM_N };
+const char* kFamilyNames[FAM_N] = {"transport", "geometry", "predictor", "smooth", "spmv", "resid64", "project"};
+constexpr size_t kProfPairs = 512;
+
+hipError_t prof_flush(tcf_grid* g) {
+  if (g->prof_used == 0) return hipSuccess;
+  hipError_t e = hipEventSynchronize(g->prof_ev[2 * g->prof_used - 1]);
+  if (e != hipSuccess) return e;
+  for (size_t k = 0; k < g->prof_used; ++k) {
+    float ms = 0.f;
+    e = hipEventElapsedTime(&ms, g->prof_ev[2 * k], g->prof_ev[2 * k + 1]);
+    if (e != hipSuccess) return e;
+    g->prof_ms += ms;
+    g->prof_count += 1;
+  }
+  g->prof_used = 0;
+  return hipSuccess;
+}
+
+// Brackets the launches of one kernel family with events on the grid's stream.
+struct Prof {
+  tcf_grid* g;
+  bool on;
+  Prof(tcf_grid* gg, int fam) : g(gg), on(fam >= 0 && gg->prof_family == fam) {
+    if (!on) return;
+    if (g->prof_used == kProfPairs) prof_flush(g);
+    hipEventRecord(g->prof_ev[2 * g->prof_used], g->stream);
+  }
+  ~Prof() {
+    if (!on) return;
+    hipEventRecord(g->prof_ev[2 * g->prof_used + 1], g->stream);
+    g->prof_used += 1;
+  }
+};
 
 template <class R>
 void carve_fields(Carver& cv, const Dims& D, Fields<R>& F, int mg_levels, bool alias_state, double* u64,
@@ -319,7 +360,10 @@ void vcycle(tcf_grid* g, Fields<R>& F, size_t l, const R* b, R* out, R* tmp, dou
   int w = 0;  // next write goes to bufs[w & 1]
   mg_smooth_first<R>(s, L, b, bufs[w & 1], g->iflag);
   ++w;
-  for (int k = 1; k < nu; ++k, ++w) mg_smooth<R>(s, dim, L, b, bufs[(w - 1) & 1], bufs[w & 1], nullptr, g->iflag);
+  for (int k = 1; k < nu; ++k, ++w) {
+    Prof pr(g, l == 0 ? FAM_SMOOTH0 : -1);
+    mg_smooth<R>(s, dim, L, b, bufs[(w - 1) & 1], bufs[w & 1], nullptr, g->iflag);
+  }
   const R* cur = bufs[(w - 1) & 1];
   Level<R>& C = F.lv[l + 1];
   mg_resid_restrict<R>(s, dim, L, b, cur, C.b, g->iflag);
@@ -331,6 +375,7 @@ void vcycle(tcf_grid* g, Fields<R>& F, size_t l, const R* b, R* out, R* tmp, dou
   }
   for (int k = 1; k < nu; ++k, ++w) {
     double* pp = (k == nu - 1) ? part : nullptr;
+    Prof pr(g, l == 0 ? FAM_SMOOTH0 : -1);
     mg_smooth<R>(s, dim, L, b, bufs[(w - 1) & 1], bufs[w & 1], pp, g->iflag);
   }
 }
@@ -358,7 +403,10 @@ tcf_status pcg_iterate(tcf_grid* g, Fields<R>& F, R* x, R* r, int maxit, int* it
   update_d<R>(s, N, g->scal, F.z, F.d, 1, g->iflag);
   int it = 0;
   for (it = 1; it <= maxit; ++it) {
-    spmv_dot<R>(s, dim, L0, F.d, F.q, g->part[0], g->iflag);
+    {
+      Prof pr(g, FAM_SPMV);
+      spmv_dot<R>(s, dim, L0, F.d, F.q, g->part[0], g->iflag);
+    }
     finalize(s, g->part[0], nbc, g->scal, g->iflag, F_ALPHA, 0, 0.0);
     update_xr<R>(s, N, g->scal, x, r, F.d, F.q, g->part[0], g->iflag);
     finalize(s, g->part[0], nb1, g->scal, g->iflag, F_RR, 0, 1.0);
@@ -420,8 +468,11 @@ tcf_status solve_refined(tcf_grid* g, double* p, int* iters, int* nref, double* 
   *converged = false;
   double bb = 0.0;
   for (int ref = 0;; ++ref) {
-    resid64(s, dim, g->D.nx, g->D.ny, g->D.nz, g->ax64, g->ay64, g->az64, g->b64, g->scal, p, g->r64, g->part[0],
-            g->part[1]);
+    {
+      Prof pr(g, FAM_RESID64);
+      resid64(s, dim, g->D.nx, g->D.ny, g->D.nz, g->ax64, g->ay64, g->az64, g->b64, g->scal, p, g->r64, g->part[0],
+              g->part[1]);
+    }
     finalize(s, g->part[0], nbc, g->scal, g->iflag, F_STORE, S_BB64, 0.0);
     finalize(s, g->part[1], nbc, g->scal, g->iflag, F_SCALE, 0, (double)N);
     HIPCHECK(read_back(g));
@@ -510,14 +561,29 @@ tcf_status step_once(tcf_grid* g, double dt, tcf_step_info* inf, bool want_diag)
   P.t = g->t;
   const Dims& D = g->D;
   // S1: SSP-RK3 with frozen u^n (stage 3 writes the state in place)
-  transport_stage<R>(P, s, F.a, F.T, F.a, F.T, F.u, F.v, F.w, F.a1, F.T1, 0.0, 1.0);
-  transport_stage<R>(P, s, F.a1, F.T1, F.a, F.T, F.u, F.v, F.w, F.a2, F.T2, 0.75, 0.25);
-  transport_stage<R>(P, s, F.a2, F.T2, F.a, F.T, F.u, F.v, F.w, F.a, F.T, 1.0 / 3.0, 2.0 / 3.0);
+  {
+    Prof pr(g, FAM_TRANSPORT);
+    transport_stage<R>(P, s, F.a, F.T, F.a, F.T, F.u, F.v, F.w, F.a1, F.T1, 0.0, 1.0);
+  }
+  {
+    Prof pr(g, FAM_TRANSPORT);
+    transport_stage<R>(P, s, F.a1, F.T1, F.a, F.T, F.u, F.v, F.w, F.a2, F.T2, 0.75, 0.25);
+  }
+  {
+    Prof pr(g, FAM_TRANSPORT);
+    transport_stage<R>(P, s, F.a2, F.T2, F.a, F.T, F.u, F.v, F.w, F.a, F.T, 1.0 / 3.0, 2.0 / 3.0);
+  }
   tcf_status st = TCF_OK;
   if (!(g->cfg.flags & TCF_TRANSPORT_ONLY)) {
     // S2-S5
-    geometry<R>(P, s, F.a, F.T, F.sk, F.Mx, F.My, F.Mz);
-    predictor<R>(P, s, F.a, F.sk, F.Mx, F.My, F.Mz, F.u, F.v, F.w, F.us, F.vs, F.ws);
+    {
+      Prof pr(g, FAM_GEOMETRY);
+      geometry<R>(P, s, F.a, F.T, F.sk, F.Mx, F.My, F.Mz);
+    }
+    {
+      Prof pr(g, FAM_PREDICTOR);
+      predictor<R>(P, s, F.a, F.sk, F.Mx, F.My, F.Mz, F.u, F.v, F.w, F.us, F.vs, F.ws);
+    }
     // S6
     const int nbc = nblocks_cells(D.nx, D.ny, D.nz);
     divergence_rhs<R>(P, s, F.us, F.vs, F.ws, g->b64, g->part[0]);
@@ -527,6 +593,7 @@ tcf_status step_once(tcf_grid* g, double dt, tcf_step_info* inf, bool want_diag)
     st = solve(g, g->p64, inf);
     if (st != TCF_OK && st != TCF_E_NOT_CONVERGED) return st;
     // S8
+    Prof pr(g, FAM_PROJECT);
     project<R>(P, s, F.a, g->p64, F.us, F.vs, F.ws, g->u64, g->v64, g->w64, g->fp32 ? F.u : nullptr,
                g->fp32 ? F.v : nullptr, g->fp32 ? F.w : nullptr);
   }
@@ -762,9 +829,39 @@ tcf_status tcf_apply_A(tcf_grid* g, const double* x, double* y) {
 void tcf_destroy(tcf_grid* g) {
   if (!g) return;
   hipStreamSynchronize(g->stream);
+  for (hipEvent_t e : g->prof_ev) hipEventDestroy(e);
   hipHostFree(g->hscal);
   hipHostFree(g->hflag);
   delete g;
+}
+
+tcf_status tcf_profile(tcf_grid* g, const char* family) {
+  g_err.clear();
+  if (!g) return fail(TCF_E_INVALID, "grid is NULL");
+  HIPCHECK(prof_flush(g));
+  g->prof_ms = 0.0;
+  g->prof_count = 0;
+  g->prof_family = -1;
+  if (!family || !*family) return TCF_OK;
+  int fam = -1;
+  for (int k = 0; k < FAM_N; ++k)
+    if (std::strcmp(family, kFamilyNames[k]) == 0) fam = k;
+  if (fam < 0) return fail(TCF_E_INVALID, std::string("unknown kernel family ") + family);
+  if (g->prof_ev.empty()) {
+    g->prof_ev.resize(2 * kProfPairs);
+    for (auto& e : g->prof_ev) HIPCHECK(hipEventCreate(&e));
+  }
+  g->prof_family = fam;
+  return TCF_OK;
+}
+
+tcf_status tcf_profile_read(tcf_grid* g, double* total_ms, long* launches) {
+  g_err.clear();
+  if (!g || !total_ms || !launches) return fail(TCF_E_INVALID, "NULL argument");
+  HIPCHECK(prof_flush(g));
+  *total_ms = g->prof_ms;
+  *launches = g->prof_count;
+  return TCF_OK;
 }
 
 const char* tcf_last_error(void) { return g_err.c_str(); }

@@ -52,7 +52,8 @@ class TcfStepInfo(C.Structure):
 
 
 EXPORTS = ["tcf_workspace_bytes", "tcf_init_grid", "tcf_set_fields", "tcf_get_fields", "tcf_step",
-           "tcf_solve_pressure", "tcf_predictor", "tcf_apply_A", "tcf_destroy", "tcf_last_error"]
+           "tcf_solve_pressure", "tcf_predictor", "tcf_apply_A", "tcf_profile", "tcf_profile_read",
+           "tcf_destroy", "tcf_last_error"]
 
 _lib = None
 
@@ -83,6 +84,10 @@ def load():
     lib.tcf_predictor.argtypes = [vp, C.c_double, vp, vp, vp]
     lib.tcf_apply_A.restype = st
     lib.tcf_apply_A.argtypes = [vp, vp, vp]
+    lib.tcf_profile.restype = st
+    lib.tcf_profile.argtypes = [vp, C.c_char_p]
+    lib.tcf_profile_read.restype = st
+    lib.tcf_profile_read.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_long)]
     lib.tcf_destroy.restype = None
     lib.tcf_destroy.argtypes = [vp]
     lib.tcf_last_error.restype = C.c_char_p
@@ -213,6 +218,15 @@ class Grid:
         y = torch.empty_like(x)
         _check(load().tcf_apply_A(self.h, _ptr(x), _ptr(y)))
         return y
+
+    def profile(self, family):
+        """Start timing the launches of one kernel family (None stops)."""
+        _check(load().tcf_profile(self.h, None if family is None else family.encode()))
+
+    def profile_read(self):
+        ms, n = C.c_double(), C.c_long()
+        _check(load().tcf_profile_read(self.h, C.byref(ms), C.byref(n)))
+        return ms.value, n.value
 
     def close(self):
         if getattr(self, "h", None) is not None and self.h.value:
