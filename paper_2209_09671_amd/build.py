@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtcf.so")
-SOURCES = ["tcf_kernels.hip", "tcf_host.cpp"]
+SOURCES = ["tcf_kernels.hip", "tcf_fine.hip", "tcf_host.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          # keep the compiler from emitting packed FP32 instructions
@@ -29,7 +29,7 @@ def build(verbose: bool = False) -> str:
         subprocess.run(cmd, check=True, stderr=subprocess.PIPE if not verbose else None)
         objs.append(obj)
     tmp = LIB + ".tmp"
-    subprocess.run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs, check=True)
+    subprocess.run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-Wl,-z,defs", "-o", tmp] + objs, check=True)
     os.replace(tmp, LIB)
     for o in objs:
         os.remove(o)

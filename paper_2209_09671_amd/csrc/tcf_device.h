@@ -1,0 +1,137 @@
+// Device helpers shared by the HIP kernel files: index maps, ghost rules,
+// material mixing, WENO5, and deterministic block reductions.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cfloat>
+#include <cmath>
+
+#include "tcf_internal.h"
+
+namespace tcf {
+namespace dev {
+
+constexpr int BX = 64, BY = 4;
+
+// ---------------------------------------------------------------------------
+// Ghost rules.  alpha: even reflection.  T: even (Neumann) or 2 T_w - mirror
+// (Dirichlet).  Velocity component C: odd reflection about its wall faces
+// along C (normal), odd reflection about the wall along the other axes
+// (tangential, no slip).
+__device__ __forceinline__ int refl(int i, int n) { return i < 0 ? -1 - i : (i >= n ? 2 * n - 1 - i : i); }
+
+__device__ __forceinline__ long cidx(int i, int j, int k, int nx, int ny) {
+  return (long)i + (long)nx * ((long)j + (long)ny * k);
+}
+
+template <int DIM, class R>
+__device__ __forceinline__ R A_at(const R* __restrict__ a, int i, int j, int k, int nx, int ny, int nz) {
+  return a[cidx(refl(i, nx), refl(j, ny), DIM == 3 ? refl(k, nz) : 0, nx, ny)];
+}
+
+template <int DIM, class R>
+__device__ __forceinline__ R T_at(const R* __restrict__ T, int i, int j, int k, const KParams& P) {
+  R v = T[cidx(refl(i, P.nx), refl(j, P.ny), DIM == 3 ? refl(k, P.nz) : 0, P.nx, P.ny)];
+  if (i < 0 && P.Tbc[0]) v = R(2) * R(P.Tw[0]) - v;
+  if (i >= P.nx && P.Tbc[1]) v = R(2) * R(P.Tw[1]) - v;
+  if (j < 0 && P.Tbc[2]) v = R(2) * R(P.Tw[2]) - v;
+  if (j >= P.ny && P.Tbc[3]) v = R(2) * R(P.Tw[3]) - v;
+  if (DIM == 3) {
+    if (k < 0 && P.Tbc[4]) v = R(2) * R(P.Tw[4]) - v;
+    if (k >= P.nz && P.Tbc[5]) v = R(2) * R(P.Tw[5]) - v;
+  }
+  return v;
+}
+
+template <int C>
+__device__ __forceinline__ long fidx(int i, int j, int k, int nx, int ny) {
+  if (C == 0) return (long)i + (long)(nx + 1) * ((long)j + (long)ny * k);
+  if (C == 1) return (long)i + (long)nx * ((long)j + (long)(ny + 1) * k);
+  return (long)i + (long)nx * ((long)j + (long)ny * k);
+}
+
+template <int C, int DIM, class R>
+__device__ __forceinline__ R V_at(const R* __restrict__ uc, int i, int j, int k, int nx, int ny, int nz) {
+  R sg = R(1);
+  int id[3] = {i, j, k};
+  const int n[3] = {nx, ny, nz};
+#pragma unroll
+  for (int e = 0; e < DIM; ++e) {
+    if (e == C) {
+      if (id[e] < 0) { id[e] = -id[e]; sg = -sg; }
+      else if (id[e] > n[e]) { id[e] = 2 * n[e] - id[e]; sg = -sg; }
+    } else {
+      if (id[e] < 0) { id[e] = -1 - id[e]; sg = -sg; }
+      else if (id[e] >= n[e]) { id[e] = 2 * n[e] - 1 - id[e]; sg = -sg; }
+    }
+  }
+  if (DIM == 2) id[2] = 0;
+  return sg * uc[fidx<C>(id[0], id[1], id[2], nx, ny)];
+}
+
+template <class R>
+__device__ __forceinline__ R mixp(R a, double p1, double p2) {
+  a = a < R(0) ? R(0) : (a > R(1) ? R(1) : a);
+  return R(p1) + a * R(p2 - p1);
+}
+
+// WENO5-JS value at the right edge of the centre sample c of (a,b,c,d,e).
+template <class R>
+__device__ __forceinline__ R weno5(R a, R b, R c, R d, R e, R eps) {
+  const R q0 = (R(2) * a - R(7) * b + R(11) * c) * R(1.0 / 6.0);
+  const R q1 = (-b + R(5) * c + R(2) * d) * R(1.0 / 6.0);
+  const R q2 = (R(2) * c + R(5) * d - e) * R(1.0 / 6.0);
+  const R t0 = a - R(2) * b + c, u0 = a - R(4) * b + R(3) * c;
+  const R t1 = b - R(2) * c + d, u1 = b - d;
+  const R t2 = c - R(2) * d + e, u2 = R(3) * c - R(4) * d + e;
+  const R e0 = eps + (R(13.0 / 12.0) * t0 * t0 + R(0.25) * u0 * u0);
+  const R e1 = eps + (R(13.0 / 12.0) * t1 * t1 + R(0.25) * u1 * u1);
+  const R e2 = eps + (R(13.0 / 12.0) * t2 * t2 + R(0.25) * u2 * u2);
+  const R a0 = R(0.1) / (e0 * e0), a1 = R(0.6) / (e1 * e1), a2 = R(0.3) / (e2 * e2);
+  return (a0 * q0 + a1 * q1 + a2 * q2) / (a0 + a1 + a2);
+}
+
+// q[k] = Q(f-3+k), k = 0..5; value at face f (between Q(f-1) and Q(f)).
+template <class R>
+__device__ __forceinline__ R upwind(const R* q, R vel, R eps) {
+  return vel >= R(0) ? weno5(q[0], q[1], q[2], q[3], q[4], eps) : weno5(q[5], q[4], q[3], q[2], q[1], eps);
+}
+
+// ---------------------------------------------------------------------------
+// Deterministic block reduction (256 threads = 4 wavefronts of 64).
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_down(v, off, 64));
+  return v;
+}
+__device__ __forceinline__ double wave_min(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_down(v, off, 64));
+  return v;
+}
+
+template <int OP>  // 0 sum, 1 max, 2 min
+__device__ __forceinline__ double block_reduce(double v, double* sh) {
+  const int tid = threadIdx.x + blockDim.x * threadIdx.y;
+  const int lane = tid & 63, wid = tid >> 6;
+  v = OP == 0 ? wave_sum(v) : (OP == 1 ? wave_max(v) : wave_min(v));
+  __syncthreads();
+  if (lane == 0) sh[wid] = v;
+  __syncthreads();
+  double r = sh[0];
+  const int nw = (blockDim.x * blockDim.y + 63) >> 6;
+  for (int w = 1; w < nw; ++w) r = OP == 0 ? r + sh[w] : (OP == 1 ? fmax(r, sh[w]) : fmin(r, sh[w]));
+  return r;
+}
+
+__device__ __forceinline__ int block_linear() { return blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z); }
+
+
+}  // namespace dev
+}  // namespace tcf

@@ -1,0 +1,441 @@
+// Finest-level kernels of the pressure solver (PCG + multigrid on level 0).
+//
+// On the finest grid the face weights of K = -A are not stored: each kernel
+// recomputes a_f = 2 / (h^2 (rho_L + rho_R)) from the volume fraction it
+// already streams (one value per cell instead of one per face and axis).
+// Each block owns a 64 x 8 column tile and marches along z over a chunk of
+// planes, carrying the z-neighbours of the streamed arrays in registers; the
+// in-plane neighbours come from the same block's loads (L1) or the adjacent
+// tile's (L2).  Tiles are numbered so that the blocks one XCD receives (the
+// dispatcher deals blocks round-robin over the 8 XCDs) form a contiguous
+// slab, which keeps the y-halo rows in that XCD's L2.  The CG vector updates
+// are fused into the stencil passes: d <- z + beta d into the SpMV, and
+// x += alpha d, r -= alpha q plus the first Jacobi sweep into one pass.
+#include <algorithm>
+
+#include "tcf_device.h"
+#include "tcf_internal.h"
+
+namespace tcf {
+namespace {
+
+using namespace dev;
+
+constexpr int FX = 64, FY = 8;
+
+template <class R>
+struct Op0 {
+  const R* a;    // volume fraction
+  int nx, ny, nz;
+  double rho1, drho, c2;  // rho = rho1 + clamp(alpha) drho; a_f = c2 / (rho_L + rho_R), c2 = 2/h^2
+};
+
+template <class R>
+__device__ __forceinline__ R rho0(const Op0<R>& op, R a) {
+  a = a < R(0) ? R(0) : (a > R(1) ? R(1) : a);
+  return R(op.rho1) + a * R(op.drho);
+}
+__device__ __forceinline__ double coef(double c2, double s) { return c2 / s; }
+__device__ __forceinline__ float coef(float c2, float s) { return c2 * __builtin_amdgcn_rcpf(s); }
+__device__ __forceinline__ double recip(double s) { return 1.0 / s; }
+__device__ __forceinline__ float recip(float s) { return __builtin_amdgcn_rcpf(s); }
+
+struct Tile {
+  int i, j, k0, k1;
+  bool act;
+};
+
+// XCD-grouped tile numbering: block b runs on XCD b % 8; give that XCD the
+// contiguous tile range [x * nb/8, (x+1) * nb/8).
+__device__ __forceinline__ Tile tile_of(int nx, int ny, int nz, int ntx, int nty, int kz) {
+  const int nb = gridDim.x, b = blockIdx.x;
+  const int t = (nb % 8 == 0) ? (b % 8) * (nb / 8) + b / 8 : b;
+  const int tx = t % ntx, rr = t / ntx;
+  const int ty = rr % nty, tz = rr / nty;
+  Tile T;
+  T.i = tx * FX + threadIdx.x;
+  T.j = ty * FY + threadIdx.y;
+  T.k0 = tz * kz;
+  T.k1 = min(T.k0 + kz, nz);
+  T.act = T.i < nx && T.j < ny && T.k0 < nz;
+  return T;
+}
+
+constexpr int LX = FX + 2, LY = FY + 2;
+
+// face weight between cells with densities rc and rn
+template <class R>
+__device__ __forceinline__ R wface(const Op0<R>& op, R rc, R an) {
+  return coef(R(op.c2), rc + rho0(op, an));
+}
+
+// Plane march over a z-chunk with one streamed field x (loader X) and the
+// volume fraction.  Per plane: the tile and its one-cell halo go to a
+// double-buffered LDS plane (one barrier per plane), the z-neighbours stay
+// in registers, and the centre and halo values are prefetched two planes
+// ahead so that loads stay in flight across the barriers.  For each active
+// cell body(c, k, xc, Kx, dg) receives K0 x and the diagonal.  With POST, all
+// threads then pass a second barrier and post(k) runs (the restriction).
+template <class R, int DIM, bool HASX, bool POST, class XL, class BODY, class PST>
+__device__ __forceinline__ void march(const Op0<R>& op, const Tile& T, const XL& X, const BODY& body,
+                                      const PST& post) {
+  __shared__ R sx[2][LY][LX];
+  __shared__ R sa[2][LY][LX];
+  const int tx = threadIdx.x, ty = threadIdx.y;
+  const int nx = op.nx, ny = op.ny, nz = op.nz;
+  const long pl = (long)nx * ny;
+  const int yr = (ty == 0) ? -1 : (ty == FY - 1 ? 1 : 0);
+  const int xr = (tx == 0) ? -1 : (tx == FX - 1 ? 1 : 0);
+  const bool hasy = T.act && yr != 0 && T.j + yr >= 0 && T.j + yr < ny;
+  const bool hasx = T.act && xr != 0 && T.i + xr >= 0 && T.i + xr < nx;
+  const long col = T.act ? (long)T.i + (long)nx * T.j : 0;
+  const long oy = (long)yr * nx;
+  // plane slots: 0 = k-1, 1 = k, 2 = k+1, 3 = k+2 (centre); halo slots 1..3
+  R x0 = R(0), x1 = R(0), x2 = R(0), x3 = R(0), a0 = R(0), a1 = R(0), a2 = R(0), a3 = R(0);
+  R hy1 = R(0), hy2 = R(0), hy3 = R(0), hx1 = R(0), hx2 = R(0), hx3 = R(0);
+  R gy1 = R(0), gy2 = R(0), gy3 = R(0), gx1 = R(0), gx2 = R(0), gx3 = R(0);  // halo of alpha
+  auto load_centre = [&](int k, R& xv, R& av) {
+    if (T.act && k >= 0 && k < nz && (DIM == 3 || k == 0)) {
+      const long c = col + pl * k;
+      if (HASX) xv = X(c, T.i, T.j, k);
+      av = op.a[c];
+    } else {
+      xv = R(0);
+      av = R(0);
+    }
+  };
+  auto load_halo = [&](int k, R& hy, R& hx, R& gy, R& gx) {
+    if (k < T.k1) {
+      const long c = col + pl * k;
+      if (hasy) {
+        if (HASX) hy = X(c + oy, T.i, T.j + yr, k);
+        gy = op.a[c + oy];
+      }
+      if (hasx) {
+        if (HASX) hx = X(c + xr, T.i + xr, T.j, k);
+        gx = op.a[c + xr];
+      }
+    }
+  };
+  if (DIM == 3) load_centre(T.k0 - 1, x0, a0);
+  load_centre(T.k0, x1, a1);
+  load_halo(T.k0, hy1, hx1, gy1, gx1);
+  if (DIM == 3) {
+    load_centre(T.k0 + 1, x2, a2);
+    load_halo(T.k0 + 1, hy2, hx2, gy2, gx2);
+  }
+  int buf = 0;
+  for (int k = T.k0; k < T.k1; ++k) {
+    if (DIM == 3) {
+      load_centre(k + 2, x3, a3);
+      load_halo(k + 2, hy3, hx3, gy3, gx3);
+    }
+    if (T.act) {
+      if (HASX) sx[buf][ty + 1][tx + 1] = x1;
+      sa[buf][ty + 1][tx + 1] = a1;
+      if (hasy) {
+        if (HASX) sx[buf][ty + 1 + yr][tx + 1] = hy1;
+        sa[buf][ty + 1 + yr][tx + 1] = gy1;
+      }
+      if (hasx) {
+        if (HASX) sx[buf][ty + 1][tx + 1 + xr] = hx1;
+        sa[buf][ty + 1][tx + 1 + xr] = gx1;
+      }
+    }
+    __syncthreads();
+    if (T.act) {
+      const long c = col + pl * k;
+      const R rc = rho0(op, a1);
+      R s = R(0), d = R(0);
+      if (T.i > 0) {
+        const R w = wface(op, rc, sa[buf][ty + 1][tx]);
+        if (HASX) s += w * (x1 - sx[buf][ty + 1][tx]);
+        d += w;
+      }
+      if (T.i < nx - 1) {
+        const R w = wface(op, rc, sa[buf][ty + 1][tx + 2]);
+        if (HASX) s += w * (x1 - sx[buf][ty + 1][tx + 2]);
+        d += w;
+      }
+      if (T.j > 0) {
+        const R w = wface(op, rc, sa[buf][ty][tx + 1]);
+        if (HASX) s += w * (x1 - sx[buf][ty][tx + 1]);
+        d += w;
+      }
+      if (T.j < ny - 1) {
+        const R w = wface(op, rc, sa[buf][ty + 2][tx + 1]);
+        if (HASX) s += w * (x1 - sx[buf][ty + 2][tx + 1]);
+        d += w;
+      }
+      if (DIM == 3) {
+        if (k > 0) {
+          const R w = wface(op, rc, a0);
+          if (HASX) s += w * (x1 - x0);
+          d += w;
+        }
+        if (k < nz - 1) {
+          const R w = wface(op, rc, a2);
+          if (HASX) s += w * (x1 - x2);
+          d += w;
+        }
+      }
+      body(c, k, x1, s, d);
+    }
+    if (POST) {
+      __syncthreads();
+      post(k);
+    }
+    x0 = x1; x1 = x2; x2 = x3;
+    a0 = a1; a1 = a2; a2 = a3;
+    hy1 = hy2; hy2 = hy3; hx1 = hx2; hx2 = hx3;
+    gy1 = gy2; gy2 = gy3; gx1 = gx2; gx2 = gx3;
+    buf ^= 1;
+  }
+}
+
+struct NoPost {
+  __device__ void operator()(int) const {}
+};
+
+__device__ __forceinline__ void write_partial(double acc, double* part) {
+  __shared__ double sh[16];
+  const double s = block_reduce<0>(acc, sh);
+  if (threadIdx.x == 0 && threadIdx.y == 0) part[blockIdx.x] = s;
+}
+
+// d' = z + beta d (d' = z on the first iteration); q = K0 d'; partial d'.q
+template <class R, int DIM>
+__global__ __launch_bounds__(512) void k0_spmv_upd(Op0<R> op, int kz, int ntx, int nty, const R* __restrict__ z,
+                                                   const R* __restrict__ dold, R* __restrict__ dnew,
+                                                   R* __restrict__ q, const double* __restrict__ scal, int first,
+                                                   double* __restrict__ part, const int* __restrict__ iflag) {
+  if (iflag[I_DONE]) return;
+  const Tile T = tile_of(op.nx, op.ny, op.nz, ntx, nty, kz);
+  const R beta = first ? R(0) : R(scal[S_BETA]);
+  auto X = [&](long c, int, int, int) { return first ? z[c] : z[c] + beta * dold[c]; };
+  double acc = 0.0;
+  auto body = [&](long c, int, R xc, R Kx, R) {
+    dnew[c] = xc;
+    q[c] = Kx;
+    acc += (double)xc * (double)Kx;
+  };
+  march<R, DIM, true, false>(op, T, X, body, NoPost());
+  write_partial(acc, part);
+}
+
+// x += alpha d; r -= alpha q (partial r.r); z1 = omega r / diag (first sweep
+// of the next V-cycle from a zero guess)
+template <class R, int DIM>
+__global__ __launch_bounds__(512) void k0_update_smooth(Op0<R> op, int kz, int ntx, int nty, R omega,
+                                                        const double* __restrict__ scal, R* __restrict__ x,
+                                                        R* __restrict__ r, const R* __restrict__ d,
+                                                        const R* __restrict__ q, R* __restrict__ z1,
+                                                        double* __restrict__ part, const int* __restrict__ iflag) {
+  if (iflag[I_DONE]) return;
+  const Tile T = tile_of(op.nx, op.ny, op.nz, ntx, nty, kz);
+  const R al = R(scal[S_ALPHA]);
+  double acc = 0.0;
+  auto X = [&](long, int, int, int) { return R(0); };
+  auto body = [&](long c, int, R, R, R dg) {
+    x[c] += al * d[c];
+    const R rn = r[c] - al * q[c];
+    r[c] = rn;
+    acc += (double)rn * (double)rn;
+    z1[c] = omega * recip(dg) * rn;
+  };
+  march<R, DIM, false, false>(op, T, X, body, NoPost());
+  write_partial(acc, part);
+}
+
+// z1 = omega b / diag
+template <class R, int DIM>
+__global__ __launch_bounds__(512) void k0_smooth_first(Op0<R> op, int kz, int ntx, int nty, R omega,
+                                                       const R* __restrict__ b, R* __restrict__ z1,
+                                                       const int* __restrict__ iflag) {
+  if (iflag[I_DONE]) return;
+  const Tile T = tile_of(op.nx, op.ny, op.nz, ntx, nty, kz);
+  auto X = [&](long, int, int, int) { return R(0); };
+  auto body = [&](long c, int, R, R, R dg) { z1[c] = omega * recip(dg) * b[c]; };
+  march<R, DIM, false, false>(op, T, X, body, NoPost());
+}
+
+// damped Jacobi xo = x + omega (b - K0 x) / diag; optional partial b.xo.
+// PRO: the sweep acts on x' = x + omc * P e, the coarse correction applied on
+// the fly (e is the next-coarser level's solution).
+template <class R, int DIM, bool PRO>
+__global__ __launch_bounds__(512) void k0_smooth(Op0<R> op, int kz, int ntx, int nty, R omega,
+                                                 const R* __restrict__ b, const R* __restrict__ x,
+                                                 R* __restrict__ xo, const R* __restrict__ e, int cnx, int cny,
+                                                 R omc, double* __restrict__ part, const int* __restrict__ iflag) {
+  if (iflag[I_DONE]) return;
+  const Tile T = tile_of(op.nx, op.ny, op.nz, ntx, nty, kz);
+  double acc = 0.0;
+  auto body = [&](long c, int, R xc, R Kx, R dg) {
+    const R bc = b[c];
+    const R xn = xc + omega * recip(dg) * (bc - Kx);
+    xo[c] = xn;
+    acc += (double)bc * (double)xn;
+  };
+  auto X = [&](long c, int ii, int jj, int kk) {
+    if (!PRO) return x[c];
+    return x[c] + omc * e[(long)(ii >> 1) + (long)cnx * ((long)(jj >> 1) + (long)cny * (DIM == 3 ? (kk >> 1) : 0))];
+  };
+  march<R, DIM, true, false>(op, T, X, body, NoPost());
+  if (part) write_partial(acc, part);
+}
+
+// bc = R (b - K0 x): fine cells marched like the sweeps; the 2x2 in-plane
+// sum goes through LDS, the pair of planes is summed in a register, and the
+// thread at the even corner of each 2x2(x2) group writes the coarse value.
+template <class R, int DIM>
+__global__ __launch_bounds__(512) void k0_resid_restrict(Op0<R> op, int kz, int ntx, int nty, int cnx, int cny,
+                                                         const R* __restrict__ b, const R* __restrict__ x,
+                                                         R* __restrict__ bc, const int* __restrict__ iflag) {
+  if (iflag[I_DONE]) return;
+  __shared__ R sres[FY][FX];
+  const Tile T = tile_of(op.nx, op.ny, op.nz, ntx, nty, kz);
+  const int tx = threadIdx.x, ty = threadIdx.y;
+  R zsum = R(0);
+  auto X = [&](long c, int, int, int) { return x[c]; };
+  auto body = [&](long c, int, R, R Kx, R) { sres[ty][tx] = b[c] - Kx; };
+  auto post = [&](int k) {
+    if (T.act && !(tx & 1) && !(ty & 1)) {
+      // the partner cells of an even corner lie inside the tile (nx, ny even)
+      zsum += (sres[ty][tx] + sres[ty][tx + 1]) + (sres[ty + 1][tx] + sres[ty + 1][tx + 1]);
+      if (DIM == 2 || (k & 1)) {
+        const int K = DIM == 3 ? (k >> 1) : 0;
+        bc[(long)(T.i >> 1) + (long)cnx * ((long)(T.j >> 1) + (long)cny * K)] = zsum;
+        zsum = R(0);
+      }
+    }
+  };
+  march<R, DIM, true, true>(op, T, X, body, post);
+}
+
+struct Launch {
+  int ntx, nty, kz, nblocks;
+};
+
+Launch plan(int nx, int ny, int nz) {
+  Launch L;
+  L.ntx = (nx + FX - 1) / FX;
+  L.nty = (ny + FY - 1) / FY;
+  const int cols = L.ntx * L.nty;
+  // aim for >= 1024 blocks (4 per CU) with chunks of at least 8 planes
+  int ntz = std::max(1, std::min(nz, (1024 + cols - 1) / cols));
+  int kz = (nz + ntz - 1) / ntz;
+  if (kz < 8 && nz >= 8) kz = 8;
+  if (nz > 1 && (kz & 1)) kz += 1;  // plane pairs of the restriction stay in one chunk
+  L.kz = std::max(1, kz);
+  ntz = (nz + L.kz - 1) / L.kz;
+  L.nblocks = cols * ntz;
+  return L;
+}
+
+template <class R>
+Op0<R> op_of(const Fine<R>& F) {
+  Op0<R> o;
+  o.a = F.a;
+  o.nx = F.nx;
+  o.ny = F.ny;
+  o.nz = F.nz;
+  o.rho1 = F.rho1;
+  o.drho = F.drho;
+  o.c2 = F.c2;
+  return o;
+}
+
+}  // namespace
+
+int fine_blocks(int nx, int ny, int nz) { return plan(nx, ny, nz).nblocks; }
+
+template <class R>
+int fine_spmv_upd(hipStream_t s, int dim, const Fine<R>& F, const R* z, const R* dold, R* dnew, R* q,
+                  const double* scal, int first, double* part, const int* iflag) {
+  const Launch L = plan(F.nx, F.ny, F.nz);
+  const Op0<R> op = op_of(F);
+  if (dim == 3)
+    hipLaunchKernelGGL((k0_spmv_upd<R, 3>), dim3(L.nblocks), dim3(FX, FY), 0, s, op, L.kz, L.ntx, L.nty, z, dold, dnew,
+                       q, scal, first, part, iflag);
+  else
+    hipLaunchKernelGGL((k0_spmv_upd<R, 2>), dim3(L.nblocks), dim3(FX, FY), 0, s, op, L.kz, L.ntx, L.nty, z, dold, dnew,
+                       q, scal, first, part, iflag);
+  return L.nblocks;
+}
+
+template <class R>
+int fine_update_smooth(hipStream_t s, int dim, const Fine<R>& F, double omega, const double* scal, R* x, R* r,
+                       const R* d, const R* q, R* z1, double* part, const int* iflag) {
+  const Launch L = plan(F.nx, F.ny, F.nz);
+  const Op0<R> op = op_of(F);
+  if (dim == 3)
+    hipLaunchKernelGGL((k0_update_smooth<R, 3>), dim3(L.nblocks), dim3(FX, FY), 0, s, op, L.kz, L.ntx, L.nty, R(omega),
+                       scal, x, r, d, q, z1, part, iflag);
+  else
+    hipLaunchKernelGGL((k0_update_smooth<R, 2>), dim3(L.nblocks), dim3(FX, FY), 0, s, op, L.kz, L.ntx, L.nty, R(omega),
+                       scal, x, r, d, q, z1, part, iflag);
+  return L.nblocks;
+}
+
+template <class R>
+void fine_smooth_first(hipStream_t s, int dim, const Fine<R>& F, double omega, const R* b, R* z1, const int* iflag) {
+  const Launch L = plan(F.nx, F.ny, F.nz);
+  const Op0<R> op = op_of(F);
+  if (dim == 3)
+    hipLaunchKernelGGL((k0_smooth_first<R, 3>), dim3(L.nblocks), dim3(FX, FY), 0, s, op, L.kz, L.ntx, L.nty, R(omega),
+                       b, z1, iflag);
+  else
+    hipLaunchKernelGGL((k0_smooth_first<R, 2>), dim3(L.nblocks), dim3(FX, FY), 0, s, op, L.kz, L.ntx, L.nty, R(omega),
+                       b, z1, iflag);
+}
+
+template <class R>
+int fine_smooth(hipStream_t s, int dim, const Fine<R>& F, double omega, const R* b, const R* x, R* xo, const R* e,
+                int cnx, int cny, double omc, double* part, const int* iflag) {
+  const Launch L = plan(F.nx, F.ny, F.nz);
+  const Op0<R> op = op_of(F);
+  if (dim == 3) {
+    if (e)
+      hipLaunchKernelGGL((k0_smooth<R, 3, true>), dim3(L.nblocks), dim3(FX, FY), 0, s, op, L.kz, L.ntx, L.nty,
+                         R(omega), b, x, xo, e, cnx, cny, R(omc), part, iflag);
+    else
+      hipLaunchKernelGGL((k0_smooth<R, 3, false>), dim3(L.nblocks), dim3(FX, FY), 0, s, op, L.kz, L.ntx, L.nty,
+                         R(omega), b, x, xo, e, cnx, cny, R(omc), part, iflag);
+  } else {
+    if (e)
+      hipLaunchKernelGGL((k0_smooth<R, 2, true>), dim3(L.nblocks), dim3(FX, FY), 0, s, op, L.kz, L.ntx, L.nty,
+                         R(omega), b, x, xo, e, cnx, cny, R(omc), part, iflag);
+    else
+      hipLaunchKernelGGL((k0_smooth<R, 2, false>), dim3(L.nblocks), dim3(FX, FY), 0, s, op, L.kz, L.ntx, L.nty,
+                         R(omega), b, x, xo, e, cnx, cny, R(omc), part, iflag);
+  }
+  return L.nblocks;
+}
+
+template <class R>
+void fine_resid_restrict(hipStream_t s, int dim, const Fine<R>& F, const R* b, const R* x, R* bc, const int* iflag) {
+  const int cnx = F.nx / 2, cny = F.ny / 2;
+  const Launch L = plan(F.nx, F.ny, F.nz);
+  const Op0<R> op = op_of(F);
+  if (dim == 3)
+    hipLaunchKernelGGL((k0_resid_restrict<R, 3>), dim3(L.nblocks), dim3(FX, FY), 0, s, op, L.kz, L.ntx, L.nty, cnx, cny,
+                       b, x, bc, iflag);
+  else
+    hipLaunchKernelGGL((k0_resid_restrict<R, 2>), dim3(L.nblocks), dim3(FX, FY), 0, s, op, L.kz, L.ntx, L.nty, cnx, cny,
+                       b, x, bc, iflag);
+}
+
+#define TCF_FINE_INST(R)                                                                                          \
+  template int fine_spmv_upd<R>(hipStream_t, int, const Fine<R>&, const R*, const R*, R*, R*, const double*, int, \
+                                double*, const int*);                                                             \
+  template int fine_update_smooth<R>(hipStream_t, int, const Fine<R>&, double, const double*, R*, R*, const R*,   \
+                                     const R*, R*, double*, const int*);                                          \
+  template void fine_smooth_first<R>(hipStream_t, int, const Fine<R>&, double, const R*, R*, const int*);         \
+  template int fine_smooth<R>(hipStream_t, int, const Fine<R>&, double, const R*, const R*, R*, const R*, int,    \
+                              int, double, double*, const int*);                                                  \
+  template void fine_resid_restrict<R>(hipStream_t, int, const Fine<R>&, const R*, const R*, R*, const int*);
+
+TCF_FINE_INST(double)
+TCF_FINE_INST(float)
+
+}  // namespace tcf

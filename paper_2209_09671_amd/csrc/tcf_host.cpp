@@ -59,8 +59,10 @@ struct Fields {
   R *sk, *Mx, *My, *Mz;                    // sigma*kappa, Marangoni vector
   R *us, *vs, *ws;                         // predictor
   std::vector<Level<R>> lv;                // Poisson levels (level 0 = fine)
-  R *r, *z, *z2, *d, *q;                   // PCG vectors on the fine level
+  R *r, *z, *z2, *d, *d2, *q;              // PCG vectors on the fine level (d ping-pong)
   R* x;                                    // FP32 mode: inner correction e
+  R* cinv = nullptr;                       // dense inverse of the coarsest level (if small)
+  double* cfac = nullptr;                  // FP64 scratch of its factorisation
 };
 
 struct Dims {
@@ -195,6 +197,7 @@ void carve_fields(Carver& cv, const Dims& D, Fields<R>& F, int mg_levels, bool a
   F.z = cv.take<R>(N);
   F.z2 = cv.take<R>(N);
   F.d = cv.take<R>(N);
+  F.d2 = cv.take<R>(N);
   F.q = cv.take<R>(N);
   F.x = alias_state ? nullptr : cv.take<R>(N);
   auto ld = level_dims(D, mg_levels);
@@ -228,6 +231,14 @@ void carve_fields(Carver& cv, const Dims& D, Fields<R>& F, int mg_levels, bool a
   }
   // the coarsest level needs x2 for its ping-pong even when it is level 0
   if (F.lv.size() == 1) F.lv[0].x2 = cv.take<R>(N);
+  const long nc = F.lv.back().n();
+  if (nc <= kCoarseDenseMax && F.lv.size() > 1) {
+    F.cinv = cv.take<R>(nc * nc);
+    F.cfac = cv.take<double>(nc * nc);
+  } else {
+    F.cinv = nullptr;
+    F.cfac = nullptr;
+  }
 }
 
 size_t carve(const tcf_config* c, void* base, tcf_grid* g) {
@@ -339,57 +350,96 @@ void build_levels(tcf_grid* g, Fields<R>& F) {
     coarsen_weights<R>(g->stream, dim, F.lv[l - 1], F.lv[l]);
     make_wdiag<R>(g->stream, dim, F.lv[l], wj);
   }
+  if (F.cinv) coarse_factor<R>(g->stream, dim, F.lv.back(), F.cfac, F.cinv);
 }
 
-// Symmetric V-cycle: out = M b on level l.  part (level 0 only) receives the
-// partials of b.out.  Buffers alternate so that the last write lands in out.
 template <class R>
-void vcycle(tcf_grid* g, Fields<R>& F, size_t l, const R* b, R* out, R* tmp, double* part) {
+Fields<R>& fields(tcf_grid* g);
+template <>
+Fields<double>& fields<double>(tcf_grid* g) { return g->f64; }
+template <>
+Fields<float>& fields<float>(tcf_grid* g) { return g->f32; }
+
+template <class R>
+Fine<R> fine_desc(tcf_grid* g) {
+  Fine<R> F;
+  F.a = fields<R>(g).a;
+  F.nx = g->D.nx;
+  F.ny = g->D.ny;
+  F.nz = g->D.nz;
+  F.rho1 = g->cfg.rho1;
+  F.drho = g->cfg.rho2 - g->cfg.rho1;
+  F.c2 = 2.0 / (g->cfg.h * g->cfg.h);
+  return F;
+}
+
+inline double jacobi_omega(int dim) { return dim == 2 ? 0.8 : 6.0 / 7.0; }
+
+// Symmetric V-cycle: out = M b on level l (zero initial guess).  part (level
+// 0 only) receives the partials of b.out and *np their count.  Buffers
+// alternate so that the last write lands in out.  With first_done the first
+// Jacobi sweep (omega b / diag) is already in tmp.
+template <class R>
+void vcycle(tcf_grid* g, Fields<R>& F, size_t l, const R* b, R* out, R* tmp, double* part, bool first_done, int* np) {
   hipStream_t s = g->stream;
   const int dim = g->D.dim;
   const int nu = g->cfg.mg_nu;
+  const double wj = jacobi_omega(dim);
   const Level<R>& L = F.lv[l];
   if (l + 1 == F.lv.size()) {
     Level<R> Lc = L;
     Lc.x2 = tmp;
-    mg_coarse_solve<R>(s, dim, Lc, b, out, kCoarseSweeps, g->iflag);
-    if (part) dot_partials<R>(s, L.n(), b, out, part);
+    if (F.cinv) coarse_apply<R>(s, (int)L.n(), F.cinv, b, out, g->iflag);
+    else mg_coarse_solve<R>(s, dim, Lc, b, out, kCoarseSweeps, g->iflag);
+    if (part) *np = dot_partials<R>(s, L.n(), b, out, part);
     return;
   }
   R* bufs[2] = {tmp, out};
+  Level<R>& C = F.lv[l + 1];
+  if (l == 0) {
+    const Fine<R> Fd = fine_desc<R>(g);
+    int w = 1;
+    if (!first_done) fine_smooth_first<R>(s, dim, Fd, wj, b, bufs[0], g->iflag);
+    for (int k = 1; k < nu; ++k, ++w) {
+      Prof pr(g, FAM_SMOOTH0);
+      fine_smooth<R>(s, dim, Fd, wj, b, bufs[(w - 1) & 1], bufs[w & 1], nullptr, 0, 0, 0.0, nullptr, g->iflag);
+    }
+    const R* cur = bufs[(w - 1) & 1];
+    fine_resid_restrict<R>(s, dim, Fd, b, cur, C.b, g->iflag);
+    vcycle<R>(g, F, 1, C.b, C.x, C.x2, nullptr, false, nullptr);
+    int n = fine_smooth<R>(s, dim, Fd, wj, b, cur, bufs[w & 1], C.x, C.nx, C.ny, kOmegaC, nu == 1 ? part : nullptr,
+                           g->iflag);
+    ++w;
+    for (int k = 1; k < nu; ++k, ++w) {
+      Prof pr(g, FAM_SMOOTH0);
+      n = fine_smooth<R>(s, dim, Fd, wj, b, bufs[(w - 1) & 1], bufs[w & 1], nullptr, 0, 0, 0.0,
+                         k == nu - 1 ? part : nullptr, g->iflag);
+    }
+    if (np) *np = n;
+    return;
+  }
   int w = 0;  // next write goes to bufs[w & 1]
   mg_smooth_first<R>(s, L, b, bufs[w & 1], g->iflag);
   ++w;
-  for (int k = 1; k < nu; ++k, ++w) {
-    Prof pr(g, l == 0 ? FAM_SMOOTH0 : -1);
-    mg_smooth<R>(s, dim, L, b, bufs[(w - 1) & 1], bufs[w & 1], nullptr, g->iflag);
-  }
+  for (int k = 1; k < nu; ++k, ++w) mg_smooth<R>(s, dim, L, b, bufs[(w - 1) & 1], bufs[w & 1], nullptr, g->iflag);
   const R* cur = bufs[(w - 1) & 1];
-  Level<R>& C = F.lv[l + 1];
   mg_resid_restrict<R>(s, dim, L, b, cur, C.b, g->iflag);
-  vcycle<R>(g, F, l + 1, C.b, C.x, C.x2, nullptr);
-  {
-    double* pp = (nu == 1) ? part : nullptr;
-    mg_prolong_smooth<R>(s, dim, L, C, b, cur, bufs[w & 1], kOmegaC, pp, g->iflag);
-    ++w;
-  }
-  for (int k = 1; k < nu; ++k, ++w) {
-    double* pp = (k == nu - 1) ? part : nullptr;
-    Prof pr(g, l == 0 ? FAM_SMOOTH0 : -1);
-    mg_smooth<R>(s, dim, L, b, bufs[(w - 1) & 1], bufs[w & 1], pp, g->iflag);
-  }
+  vcycle<R>(g, F, l + 1, C.b, C.x, C.x2, nullptr, false, nullptr);
+  mg_prolong_smooth<R>(s, dim, L, C, b, cur, bufs[w & 1], kOmegaC, nullptr, g->iflag);
+  ++w;
+  for (int k = 1; k < nu; ++k, ++w) mg_smooth<R>(s, dim, L, b, bufs[(w - 1) & 1], bufs[w & 1], nullptr, g->iflag);
 }
 
 // PCG iterations on K x = rhs with r holding the initial residual and the
-// done flag / tolerance already set.  Returns iterations performed.
+// done flag / tolerance already set.  The search direction ping-pongs
+// between d and d2; the first Jacobi sweep of each preconditioner
+// application is fused into the x/r update.
 template <class R>
 tcf_status pcg_iterate(tcf_grid* g, Fields<R>& F, R* x, R* r, int maxit, int* iters, bool* converged) {
   hipStream_t s = g->stream;
   const int dim = g->D.dim;
-  const long N = g->D.N;
-  const Level<R>& L0 = F.lv[0];
-  const int nbc = nblocks_cells(g->D.nx, g->D.ny, g->D.nz);
-  const int nb1 = (int)((N + 255) / 256);
+  const Fine<R> Fd = fine_desc<R>(g);
+  const double wj = jacobi_omega(dim);
   *converged = false;
   HIPCHECK(read_back(g));
   if (g->hflag[I_DONE]) {
@@ -397,22 +447,22 @@ tcf_status pcg_iterate(tcf_grid* g, Fields<R>& F, R* x, R* r, int maxit, int* it
     *converged = true;
     return TCF_OK;
   }
-  const int nbz = F.lv.size() == 1 ? nb1 : nbc;
-  vcycle<R>(g, F, 0, r, F.z, F.z2, g->part[0]);
-  finalize(s, g->part[0], nbz, g->scal, g->iflag, F_RZ_FIRST, 0, 0.0);
-  update_d<R>(s, N, g->scal, F.z, F.d, 1, g->iflag);
-  int it = 0;
-  for (it = 1; it <= maxit; ++it) {
+  int np = 0;
+  vcycle<R>(g, F, 0, r, F.z, F.z2, g->part[0], false, &np);
+  finalize(s, g->part[0], np, g->scal, g->iflag, F_RZ_FIRST, 0, 0.0);
+  R* dcur = F.d;
+  R* dnext = F.d2;
+  for (int it = 1; it <= maxit; ++it) {
     {
       Prof pr(g, FAM_SPMV);
-      spmv_dot<R>(s, dim, L0, F.d, F.q, g->part[0], g->iflag);
+      np = fine_spmv_upd<R>(s, dim, Fd, F.z, dcur, dnext, F.q, g->scal, it == 1 ? 1 : 0, g->part[0], g->iflag);
     }
-    finalize(s, g->part[0], nbc, g->scal, g->iflag, F_ALPHA, 0, 0.0);
-    update_xr<R>(s, N, g->scal, x, r, F.d, F.q, g->part[0], g->iflag);
-    finalize(s, g->part[0], nb1, g->scal, g->iflag, F_RR, 0, 1.0);
-    vcycle<R>(g, F, 0, r, F.z, F.z2, g->part[0]);
-    finalize(s, g->part[0], nbz, g->scal, g->iflag, F_RZ, 0, 0.0);
-    update_d<R>(s, N, g->scal, F.z, F.d, 0, g->iflag);
+    finalize(s, g->part[0], np, g->scal, g->iflag, F_ALPHA, 0, 0.0);
+    std::swap(dcur, dnext);
+    np = fine_update_smooth<R>(s, dim, Fd, wj, g->scal, x, r, dcur, F.q, F.z2, g->part[0], g->iflag);
+    finalize(s, g->part[0], np, g->scal, g->iflag, F_RR, 0, 1.0);
+    vcycle<R>(g, F, 0, r, F.z, F.z2, g->part[0], true, &np);
+    finalize(s, g->part[0], np, g->scal, g->iflag, F_RZ, 0, 0.0);
     HIPCHECK(read_back(g));
     if (g->hflag[I_DONE]) break;
   }
@@ -498,8 +548,11 @@ tcf_status solve_refined(tcf_grid* g, double* p, int* iters, int* nref, double* 
     scale_to32(s, N, g->r64, g->scal, F.r);
     fill<float>(s, N, F.x, 0.0);
     init_flags(s, g->iflag);
+    // reduce the scaled residual only as far as this sweep needs to reach
+    // the FP64 target (never below inner_rtol)
+    const double tau = std::min(0.5, std::max(irt, 0.5 * rt * std::sqrt(bb / rr)));
     dot_partials<float>(s, N, F.r, F.r, g->part[0]);
-    finalize(s, g->part[0], nb1, g->scal, g->iflag, F_BB, 0, irt * irt);
+    finalize(s, g->part[0], nb1, g->scal, g->iflag, F_BB, 0, tau * tau);
     int it = 0;
     bool conv = false;
     tcf_status st = pcg_iterate<float>(g, F, F.x, F.r, g->cfg.p_maxit, &it, &conv);
@@ -510,13 +563,6 @@ tcf_status solve_refined(tcf_grid* g, double* p, int* iters, int* nref, double* 
   }
   return TCF_OK;
 }
-
-template <class R>
-Fields<R>& fields(tcf_grid* g);
-template <>
-Fields<double>& fields<double>(tcf_grid* g) { return g->f64; }
-template <>
-Fields<float>& fields<float>(tcf_grid* g) { return g->f32; }
 
 // Fine face weights from the current alpha and the whole hierarchy.
 template <class R>

@@ -31,6 +31,15 @@ struct Level {
   __host__ __device__ long n() const { return (long)nx * ny * nz; }
 };
 
+// Finest level of the pressure operator: face weights recomputed from alpha,
+// a_f = c2 / (rho_L + rho_R) with rho = rho1 + clamp(alpha, 0, 1) drho.
+template <class R>
+struct Fine {
+  const R* a;
+  int nx, ny, nz;
+  double rho1, drho, c2;
+};
+
 // Slots of the device scalar block (FP64).
 enum Slot { S_MEAN = 0, S_BB, S_RR, S_RZ, S_DQ, S_ALPHA, S_BETA, S_TOL2, S_SCALE,
             S_SUMA, S_AMIN, S_AMAX, S_UMAX, S_DIV2, S_NONFIN, S_RR64, S_BB64, S_PMEAN, S_NSLOT = 24 };
@@ -39,6 +48,7 @@ enum IFlag { I_DONE = 0, I_ITERS = 1, I_NFLAG = 4 };
 enum FinOp { F_STORE = 0, F_MEAN, F_BB, F_ALPHA, F_RR, F_RZ_FIRST, F_RZ, F_MIN, F_MAX, F_SCALE };
 
 constexpr int kBlock = 256;
+constexpr int kCoarseDenseMax = 512;  // coarsest levels up to this size are solved exactly
 inline int nblocks_cells(int nx, int ny, int nz) { return ((nx + 63) / 64) * ((ny + 3) / 4) * nz; }
 
 // ---- launchers (defined in tcf_kernels.hip) --------------------------------
@@ -87,6 +97,28 @@ void mg_prolong_smooth(hipStream_t s, int dim, const Level<R>& F, const Level<R>
 template <class R>
 void mg_coarse_solve(hipStream_t s, int dim, const Level<R>& L, const R* b, R* x, int sweeps,
                      const int* iflag);
+
+// finest-level fused kernels (tcf_fine.hip); return the number of partials
+int fine_blocks(int nx, int ny, int nz);
+template <class R>
+int fine_spmv_upd(hipStream_t s, int dim, const Fine<R>& F, const R* z, const R* dold, R* dnew, R* q,
+                  const double* scal, int first, double* part, const int* iflag);
+template <class R>
+int fine_update_smooth(hipStream_t s, int dim, const Fine<R>& F, double omega, const double* scal, R* x, R* r,
+                       const R* d, const R* q, R* z1, double* part, const int* iflag);
+template <class R>
+void fine_smooth_first(hipStream_t s, int dim, const Fine<R>& F, double omega, const R* b, R* z1, const int* iflag);
+template <class R>
+int fine_smooth(hipStream_t s, int dim, const Fine<R>& F, double omega, const R* b, const R* x, R* xo, const R* e,
+                int cnx, int cny, double omc, double* part, const int* iflag);
+template <class R>
+void fine_resid_restrict(hipStream_t s, int dim, const Fine<R>& F, const R* b, const R* x, R* bc, const int* iflag);
+
+// exact coarsest-level solve (levels with at most kCoarseDenseMax cells)
+template <class R>
+void coarse_factor(hipStream_t s, int dim, const Level<R>& L, double* A, R* Minv);
+template <class R>
+void coarse_apply(hipStream_t s, int n, const R* Minv, const R* b, R* out, const int* iflag);
 
 void finalize(hipStream_t s, const double* part, int nparts, double* scal, int* iflag, int op, int slot,
               double arg);

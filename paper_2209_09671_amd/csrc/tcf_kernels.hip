@@ -10,130 +10,13 @@
 #include <cfloat>
 #include <cmath>
 
+#include "tcf_device.h"
 #include "tcf_internal.h"
 
 namespace tcf {
 namespace {
 
-constexpr int BX = 64, BY = 4;
-
-// ---------------------------------------------------------------------------
-// Ghost rules.  alpha: even reflection.  T: even (Neumann) or 2 T_w - mirror
-// (Dirichlet).  Velocity component C: odd reflection about its wall faces
-// along C (normal), odd reflection about the wall along the other axes
-// (tangential, no slip).
-__device__ __forceinline__ int refl(int i, int n) { return i < 0 ? -1 - i : (i >= n ? 2 * n - 1 - i : i); }
-
-__device__ __forceinline__ long cidx(int i, int j, int k, int nx, int ny) {
-  return (long)i + (long)nx * ((long)j + (long)ny * k);
-}
-
-template <int DIM, class R>
-__device__ __forceinline__ R A_at(const R* __restrict__ a, int i, int j, int k, int nx, int ny, int nz) {
-  return a[cidx(refl(i, nx), refl(j, ny), DIM == 3 ? refl(k, nz) : 0, nx, ny)];
-}
-
-template <int DIM, class R>
-__device__ __forceinline__ R T_at(const R* __restrict__ T, int i, int j, int k, const KParams& P) {
-  R v = T[cidx(refl(i, P.nx), refl(j, P.ny), DIM == 3 ? refl(k, P.nz) : 0, P.nx, P.ny)];
-  if (i < 0 && P.Tbc[0]) v = R(2) * R(P.Tw[0]) - v;
-  if (i >= P.nx && P.Tbc[1]) v = R(2) * R(P.Tw[1]) - v;
-  if (j < 0 && P.Tbc[2]) v = R(2) * R(P.Tw[2]) - v;
-  if (j >= P.ny && P.Tbc[3]) v = R(2) * R(P.Tw[3]) - v;
-  if (DIM == 3) {
-    if (k < 0 && P.Tbc[4]) v = R(2) * R(P.Tw[4]) - v;
-    if (k >= P.nz && P.Tbc[5]) v = R(2) * R(P.Tw[5]) - v;
-  }
-  return v;
-}
-
-template <int C>
-__device__ __forceinline__ long fidx(int i, int j, int k, int nx, int ny) {
-  if (C == 0) return (long)i + (long)(nx + 1) * ((long)j + (long)ny * k);
-  if (C == 1) return (long)i + (long)nx * ((long)j + (long)(ny + 1) * k);
-  return (long)i + (long)nx * ((long)j + (long)ny * k);
-}
-
-template <int C, int DIM, class R>
-__device__ __forceinline__ R V_at(const R* __restrict__ uc, int i, int j, int k, int nx, int ny, int nz) {
-  R sg = R(1);
-  int id[3] = {i, j, k};
-  const int n[3] = {nx, ny, nz};
-#pragma unroll
-  for (int e = 0; e < DIM; ++e) {
-    if (e == C) {
-      if (id[e] < 0) { id[e] = -id[e]; sg = -sg; }
-      else if (id[e] > n[e]) { id[e] = 2 * n[e] - id[e]; sg = -sg; }
-    } else {
-      if (id[e] < 0) { id[e] = -1 - id[e]; sg = -sg; }
-      else if (id[e] >= n[e]) { id[e] = 2 * n[e] - 1 - id[e]; sg = -sg; }
-    }
-  }
-  if (DIM == 2) id[2] = 0;
-  return sg * uc[fidx<C>(id[0], id[1], id[2], nx, ny)];
-}
-
-template <class R>
-__device__ __forceinline__ R mixp(R a, double p1, double p2) {
-  a = a < R(0) ? R(0) : (a > R(1) ? R(1) : a);
-  return R(p1) + a * R(p2 - p1);
-}
-
-// WENO5-JS value at the right edge of the centre sample c of (a,b,c,d,e).
-template <class R>
-__device__ __forceinline__ R weno5(R a, R b, R c, R d, R e, R eps) {
-  const R q0 = (R(2) * a - R(7) * b + R(11) * c) * R(1.0 / 6.0);
-  const R q1 = (-b + R(5) * c + R(2) * d) * R(1.0 / 6.0);
-  const R q2 = (R(2) * c + R(5) * d - e) * R(1.0 / 6.0);
-  const R t0 = a - R(2) * b + c, u0 = a - R(4) * b + R(3) * c;
-  const R t1 = b - R(2) * c + d, u1 = b - d;
-  const R t2 = c - R(2) * d + e, u2 = R(3) * c - R(4) * d + e;
-  const R e0 = eps + (R(13.0 / 12.0) * t0 * t0 + R(0.25) * u0 * u0);
-  const R e1 = eps + (R(13.0 / 12.0) * t1 * t1 + R(0.25) * u1 * u1);
-  const R e2 = eps + (R(13.0 / 12.0) * t2 * t2 + R(0.25) * u2 * u2);
-  const R a0 = R(0.1) / (e0 * e0), a1 = R(0.6) / (e1 * e1), a2 = R(0.3) / (e2 * e2);
-  return (a0 * q0 + a1 * q1 + a2 * q2) / (a0 + a1 + a2);
-}
-
-// q[k] = Q(f-3+k), k = 0..5; value at face f (between Q(f-1) and Q(f)).
-template <class R>
-__device__ __forceinline__ R upwind(const R* q, R vel, R eps) {
-  return vel >= R(0) ? weno5(q[0], q[1], q[2], q[3], q[4], eps) : weno5(q[5], q[4], q[3], q[2], q[1], eps);
-}
-
-// ---------------------------------------------------------------------------
-// Deterministic block reduction (256 threads = 4 wavefronts of 64).
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-  return v;
-}
-__device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_down(v, off, 64));
-  return v;
-}
-__device__ __forceinline__ double wave_min(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_down(v, off, 64));
-  return v;
-}
-
-template <int OP>  // 0 sum, 1 max, 2 min
-__device__ __forceinline__ double block_reduce(double v, double* sh) {
-  const int tid = threadIdx.x + blockDim.x * threadIdx.y;
-  const int lane = tid & 63, wid = tid >> 6;
-  v = OP == 0 ? wave_sum(v) : (OP == 1 ? wave_max(v) : wave_min(v));
-  __syncthreads();
-  if (lane == 0) sh[wid] = v;
-  __syncthreads();
-  double r = sh[0];
-  const int nw = (blockDim.x * blockDim.y + 63) >> 6;
-  for (int w = 1; w < nw; ++w) r = OP == 0 ? r + sh[w] : (OP == 1 ? fmax(r, sh[w]) : fmin(r, sh[w]));
-  return r;
-}
-
-__device__ __forceinline__ int block_linear() { return blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z); }
+using namespace dev;
 
 // ---------------------------------------------------------------------------
 // S1: one SSP-RK3 stage for alpha and T.
@@ -654,27 +537,121 @@ __global__ __launch_bounds__(1024) void k_coarse(Level<R> L, const R* __restrict
     for (long c = threadIdx.x; c < n; c += blockDim.x) x[c] = src[c];
 }
 
-// One-block deterministic finalize of per-block partials.
-__global__ __launch_bounds__(256) void k_finalize(const double* __restrict__ part, int n,
-                                                  double* __restrict__ scal, int* __restrict__ iflag, int op,
-                                                  int slot, double arg) {
-  __shared__ double sh[8];
-  if ((op == F_ALPHA || op == F_RR || op == F_RZ) && iflag[I_DONE]) return;
-  double v;
-  if (op == F_MIN) {
-    v = DBL_MAX;
-    for (int t = threadIdx.x; t < n; t += blockDim.x) v = fmin(v, part[t]);
-    v = block_reduce<2>(v, sh);
-  } else if (op == F_MAX) {
-    v = -DBL_MAX;
-    for (int t = threadIdx.x; t < n; t += blockDim.x) v = fmax(v, part[t]);
-    v = block_reduce<1>(v, sh);
-  } else {
-    v = 0.0;
-    for (int t = threadIdx.x; t < n; t += blockDim.x) v += part[t];
-    v = block_reduce<0>(v, sh);
+// Coarsest level, exact solve: assemble K_c + (gamma/n) 1 1^T (gamma = mean
+// diagonal; K_c is singular with the constants as null space, the rank-one
+// term makes the matrix SPD and acts as the pseudo-inverse on mean-free
+// data), invert it in FP64 by Gauss-Jordan without pivoting (valid for SPD),
+// and store the symmetrised inverse in level precision.  One block.
+template <class R, int DIM>
+__global__ __launch_bounds__(1024) void k_coarse_factor(Level<R> L, double* __restrict__ A, R* __restrict__ Minv) {
+  __shared__ double col[kCoarseDenseMax];
+  __shared__ double sh[16];
+  const int n = (int)L.n();
+  const int t = threadIdx.x, nt = blockDim.x;
+  const long nn = (long)n * n;
+  for (long e = t; e < nn; e += nt) A[e] = 0.0;
+  __syncthreads();
+  double dsum = 0.0;
+  for (int c = t; c < n; c += nt) {
+    const int i = c % L.nx, j = (c / L.nx) % L.ny, k = c / (L.nx * L.ny);
+    double d = 0.0;
+    auto off = [&](int nb, double w) {
+      A[(long)c * n + nb] = -w;
+      d += w;
+    };
+    if (i > 0) off(c - 1, (double)L.ax[fidx<0>(i, j, k, L.nx, L.ny)]);
+    if (i < L.nx - 1) off(c + 1, (double)L.ax[fidx<0>(i + 1, j, k, L.nx, L.ny)]);
+    if (j > 0) off(c - L.nx, (double)L.ay[fidx<1>(i, j, k, L.nx, L.ny)]);
+    if (j < L.ny - 1) off(c + L.nx, (double)L.ay[fidx<1>(i, j + 1, k, L.nx, L.ny)]);
+    if (DIM == 3) {
+      const int pl = L.nx * L.ny;
+      if (k > 0) off(c - pl, (double)L.az[fidx<2>(i, j, k, L.nx, L.ny)]);
+      if (k < L.nz - 1) off(c + pl, (double)L.az[fidx<2>(i, j, k + 1, L.nx, L.ny)]);
+    }
+    A[(long)c * n + c] = d;
+    dsum += d;
   }
-  if (threadIdx.x != 0) return;
+  const double gamma = block_reduce<0>(dsum, sh) / n;
+  __syncthreads();
+  for (long e = t; e < nn; e += nt) A[e] += gamma / n;
+  __syncthreads();
+  // in-place Gauss-Jordan inversion
+  for (int p = 0; p < n; ++p) {
+    for (int i = t; i < n; i += nt) col[i] = A[(long)i * n + p];
+    __syncthreads();
+    const double piv = 1.0 / col[p];
+    for (int j = t; j < n; j += nt) A[(long)p * n + j] = (j == p ? 1.0 : A[(long)p * n + j]) * piv;
+    __syncthreads();
+    for (long e = t; e < nn; e += nt) {
+      const int i = (int)(e / n), j = (int)(e % n);
+      if (i == p) continue;
+      const double prow = A[(long)p * n + j];
+      A[e] = (j == p ? 0.0 : A[e]) - col[i] * prow;
+    }
+    __syncthreads();
+  }
+  for (long e = t; e < nn; e += nt) {
+    const int i = (int)(e / n), j = (int)(e % n);
+    Minv[e] = R(0.5 * (A[e] + A[(long)j * n + i]));
+  }
+}
+
+// out = Minv b on the coarsest level (one block, one row per thread).
+template <class R>
+__global__ __launch_bounds__(1024) void k_coarse_apply(int n, const R* __restrict__ Minv, const R* __restrict__ b,
+                                                       R* __restrict__ out, const int* __restrict__ iflag) {
+  if (iflag[I_DONE]) return;
+  __shared__ R sb[kCoarseDenseMax];
+  for (int j = threadIdx.x; j < n; j += blockDim.x) sb[j] = b[j];
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const R* row = Minv + (long)i * n;
+    R s0 = R(0), s1 = R(0);
+    int j = 0;
+    for (; j + 1 < n; j += 2) {
+      s0 += row[j] * sb[j];
+      s1 += row[j + 1] * sb[j + 1];
+    }
+    if (j < n) s0 += row[j] * sb[j];
+    out[i] = s0 + s1;
+  }
+}
+
+// One-block deterministic finalize of per-block partials: each of the 1024
+// threads folds a fixed strided subset with four independent accumulators,
+// then the block reduces in a fixed order.
+__global__ __launch_bounds__(1024) void k_finalize(const double* __restrict__ part, int n,
+                                                   double* __restrict__ scal, int* __restrict__ iflag, int op,
+                                                   int slot, double arg) {
+  __shared__ double sh[16];
+  if ((op == F_ALPHA || op == F_RR || op == F_RZ) && iflag[I_DONE]) return;
+  const int t = threadIdx.x, nt = blockDim.x;
+  double v;
+  if (op == F_MIN || op == F_MAX) {
+    const double init = op == F_MIN ? DBL_MAX : -DBL_MAX;
+    double a0 = init, a1 = init;
+    int q = t;
+    for (; q + nt < n; q += 2 * nt) {
+      const double p0 = part[q], p1 = part[q + nt];
+      a0 = op == F_MIN ? fmin(a0, p0) : fmax(a0, p0);
+      a1 = op == F_MIN ? fmin(a1, p1) : fmax(a1, p1);
+    }
+    if (q < n) a0 = op == F_MIN ? fmin(a0, part[q]) : fmax(a0, part[q]);
+    v = op == F_MIN ? fmin(a0, a1) : fmax(a0, a1);
+    v = op == F_MIN ? block_reduce<2>(v, sh) : block_reduce<1>(v, sh);
+  } else {
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int q = t;
+    for (; q + 3 * nt < n; q += 4 * nt) {
+      a0 += part[q];
+      a1 += part[q + nt];
+      a2 += part[q + 2 * nt];
+      a3 += part[q + 3 * nt];
+    }
+    for (; q < n; q += nt) a0 += part[q];
+    v = block_reduce<0>((a0 + a1) + (a2 + a3), sh);
+  }
+  if (t != 0) return;
   switch (op) {
     case F_STORE: case F_MIN: case F_MAX: scal[slot] = v; break;
     case F_MEAN: scal[slot] = v / arg; break;
@@ -1008,9 +985,24 @@ void mg_coarse_solve(hipStream_t s, int dim, const Level<R>& L, const R* b, R* x
   else hipLaunchKernelGGL((k_coarse<R, 2>), dim3(1), dim3(1024), 0, s, L, b, x, L.x2, sweeps, iflag);
 }
 
+template <class R>
+void coarse_factor(hipStream_t s, int dim, const Level<R>& L, double* A, R* Minv) {
+  if (dim == 3) hipLaunchKernelGGL((k_coarse_factor<R, 3>), dim3(1), dim3(1024), 0, s, L, A, Minv);
+  else hipLaunchKernelGGL((k_coarse_factor<R, 2>), dim3(1), dim3(1024), 0, s, L, A, Minv);
+}
+
+template <class R>
+void coarse_apply(hipStream_t s, int n, const R* Minv, const R* b, R* out, const int* iflag) {
+  hipLaunchKernelGGL((k_coarse_apply<R>), dim3(1), dim3(1024), 0, s, n, Minv, b, out, iflag);
+}
+template void coarse_factor<double>(hipStream_t, int, const Level<double>&, double*, double*);
+template void coarse_factor<float>(hipStream_t, int, const Level<float>&, double*, float*);
+template void coarse_apply<double>(hipStream_t, int, const double*, const double*, double*, const int*);
+template void coarse_apply<float>(hipStream_t, int, const float*, const float*, float*, const int*);
+
 void finalize(hipStream_t s, const double* part, int nparts, double* scal, int* iflag, int op, int slot,
               double arg) {
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, part, nparts, scal, iflag, op, slot, arg);
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, s, part, nparts, scal, iflag, op, slot, arg);
 }
 
 void init_flags(hipStream_t s, int* iflag) { hipLaunchKernelGGL(k_init_flags, dim3(1), dim3(64), 0, s, iflag); }
