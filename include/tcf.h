@@ -72,7 +72,10 @@ typedef enum {
                           residual, CG scalars, sums, and u, v, w, p storage */
 } tcf_precision;
 
-enum { TCF_TRANSPORT_ONLY = 1 /* tcf_step runs S1 only (velocity frozen, p kept) */ };
+enum {
+  TCF_TRANSPORT_ONLY = 1, /* tcf_step runs S1 only (velocity frozen, p kept) */
+  TCF_WITH_ADJOINT = 2    /* reserve adjoint workspace (needs precision TCF_FP64) */
+};
 
 typedef struct tcf_grid tcf_grid; /* opaque, host side */
 
@@ -141,6 +144,36 @@ tcf_status tcf_solve_pressure(tcf_grid* g, const double* rhs, double* p, tcf_ste
  * tcf_apply_A: y = A x with the grid's current alpha. */
 tcf_status tcf_predictor(tcf_grid* g, double dt, double* us, double* vs, double* ws);
 tcf_status tcf_apply_A(tcf_grid* g, const double* x, double* y);
+
+/* Adjoint of one step (the transposed linearisation of S1..S8 at state n),
+ * row "adjoint" of the path; needs a grid created with TCF_WITH_ADJOINT.
+ *   state_n  : alpha, T, u, v, w, p at step n (device FP64; w NULL in 2D; p
+ *              may be NULL - it is only the warm start of the recomputed solve)
+ *   adj_np1  : dL/d(alpha, T, u, v, w) at step n+1 (wall-face entries ignored)
+ *   adj_n    : written with dL/d(alpha, T, u, v, w) at step n (wall faces 0)
+ *   dL_dsigmaT: device FP64 scalar, incremented by dL/d(dsigma_dT) of this step
+ * The forward step is recomputed from state_n inside the call (WENO weights
+ * and interface geometry are recomputed, not stored).  The pressure adjoint
+ * reuses the symmetric operator of S7 (one extra solve at p_rtol).  The
+ * derivative of clamp(alpha,0,1) is taken as 1 inside (0,1) and 0 outside,
+ * and the upwind side follows the sign of the advecting velocity.  Adjoint
+ * sums use FP64 atomics: results agree to rounding, not bitwise, run to run.
+ * Afterwards the grid's fields are unspecified: call tcf_set_fields again
+ * before tcf_step.  Entries of adj_n must not alias adj_np1 or state_n. */
+tcf_status tcf_step_backward(tcf_grid* g, double t_n, double dt, const double* const state_n[6],
+                             const double* const adj_np1[5], double* const adj_n[5], double* dL_dsigmaT);
+
+/* Adjoints of single sub-steps at the grid's current fields (checks of the
+ * adjoint against finite differences of tcf_step(TCF_TRANSPORT_ONLY) and
+ * tcf_predictor).  tcf_adjoint_transport: (ab_in, Tb_in) is dL/d(alpha, T)
+ * after S1; writes dL/d(alpha, T) before it and dL/d(u, v, w) (all device
+ * FP64, no aliasing of in and out).  tcf_adjoint_predictor: (usb, vsb, wsb)
+ * is dL/du*; writes dL/d(alpha, T, u, v, w) and sbar = dL/d(dsigma_dT)
+ * (device scalar, overwritten). */
+tcf_status tcf_adjoint_transport(tcf_grid* g, double dt, const double* ab_in, const double* Tb_in, double* ab_out,
+                                 double* Tb_out, double* ub, double* vb, double* wb);
+tcf_status tcf_adjoint_predictor(tcf_grid* g, double dt, const double* usb, const double* vsb, const double* wsb,
+                                 double* ab, double* Tb, double* ub, double* vb, double* wb, double* sbar);
 
 /* Measurement: time every launch of one kernel family with HIP events on
  * the grid's stream ("transport", "geometry", "predictor", "smooth" = the

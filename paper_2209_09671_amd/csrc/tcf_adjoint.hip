@@ -1,0 +1,751 @@
+// Discrete adjoint of one projection step (FP64).
+//
+// Each kernel recomputes the forward local quantities it needs (WENO5 weights
+// and smoothness indicators included; nothing of the forward stencils is
+// stored) and applies the transposed local Jacobian.  Contributions that
+// several outputs make to one input are accumulated with FP64 vector atomics,
+// so adjoint sums are not bitwise reproducible run to run (rounding order).
+// Non-smooth points take a fixed branch: the upwind choice follows the sign
+// of the advecting velocity (zero takes the left-biased stencil, as in the
+// forward step) and the derivative of clamp(alpha, 0, 1) is 1 inside (0, 1)
+// and 0 elsewhere.
+#include "tcf_device.h"
+#include "tcf_internal.h"
+
+namespace tcf {
+namespace {
+
+using namespace dev;
+
+__device__ __forceinline__ double dclamp(double a) { return (a > 0.0 && a < 1.0) ? 1.0 : 0.0; }
+__device__ __forceinline__ void aadd(double* p, double v) {
+  if (v != 0.0) atomicAdd(p, v);
+}
+
+// ---- ghost-aware index maps: value = sign * array[index] (+ a constant) ----
+template <int DIM>
+__device__ __forceinline__ long a_idx(int i, int j, int k, int nx, int ny, int nz) {
+  return cidx(refl(i, nx), refl(j, ny), DIM == 3 ? refl(k, nz) : 0, nx, ny);
+}
+template <int DIM>
+__device__ __forceinline__ long t_idx(int i, int j, int k, const KParams& P, double& sg) {
+  sg = 1.0;
+  if (i < 0 && P.Tbc[0]) sg = -sg;
+  if (i >= P.nx && P.Tbc[1]) sg = -sg;
+  if (j < 0 && P.Tbc[2]) sg = -sg;
+  if (j >= P.ny && P.Tbc[3]) sg = -sg;
+  if (DIM == 3) {
+    if (k < 0 && P.Tbc[4]) sg = -sg;
+    if (k >= P.nz && P.Tbc[5]) sg = -sg;
+  }
+  return a_idx<DIM>(i, j, k, P.nx, P.ny, P.nz);
+}
+template <int C, int DIM>
+__device__ __forceinline__ long v_idx(int i, int j, int k, int nx, int ny, int nz, double& sg) {
+  sg = 1.0;
+  int id[3] = {i, j, k};
+  const int n[3] = {nx, ny, nz};
+#pragma unroll
+  for (int e = 0; e < DIM; ++e) {
+    if (e == C) {
+      if (id[e] < 0) { id[e] = -id[e]; sg = -sg; }
+      else if (id[e] > n[e]) { id[e] = 2 * n[e] - id[e]; sg = -sg; }
+    } else {
+      if (id[e] < 0) { id[e] = -1 - id[e]; sg = -sg; }
+      else if (id[e] >= n[e]) { id[e] = 2 * n[e] - 1 - id[e]; sg = -sg; }
+    }
+  }
+  if (DIM == 2) id[2] = 0;
+  return fidx<C>(id[0], id[1], id[2], nx, ny);
+}
+
+// WENO5-JS value at the right edge of c and its gradient w.r.t. (a,b,c,d,e):
+// dW/dx = sum_k w_k dq_k/dx - (2/S) sum_k (q_k - W) a_k/(eps+beta_k) dbeta_k/dx
+__device__ double weno5_g(double a, double b, double c, double d, double e, double eps, double g[5]) {
+  const double q0 = (2.0 * a - 7.0 * b + 11.0 * c) * (1.0 / 6.0);
+  const double q1 = (-b + 5.0 * c + 2.0 * d) * (1.0 / 6.0);
+  const double q2 = (2.0 * c + 5.0 * d - e) * (1.0 / 6.0);
+  const double t0 = a - 2.0 * b + c, u0 = a - 4.0 * b + 3.0 * c;
+  const double t1 = b - 2.0 * c + d, u1 = b - d;
+  const double t2 = c - 2.0 * d + e, u2 = 3.0 * c - 4.0 * d + e;
+  const double e0 = eps + ((13.0 / 12.0) * t0 * t0 + 0.25 * u0 * u0);
+  const double e1 = eps + ((13.0 / 12.0) * t1 * t1 + 0.25 * u1 * u1);
+  const double e2 = eps + ((13.0 / 12.0) * t2 * t2 + 0.25 * u2 * u2);
+  const double a0 = 0.1 / (e0 * e0), a1 = 0.6 / (e1 * e1), a2 = 0.3 / (e2 * e2);
+  const double S = a0 + a1 + a2;
+  const double W = (a0 * q0 + a1 * q1 + a2 * q2) / S;
+  const double w0 = a0 / S, w1 = a1 / S, w2 = a2 / S;
+  // coefficients c_k = -(2/S)(q_k - W) a_k / e_k multiply dbeta_k/dx
+  const double c0 = -2.0 / S * (q0 - W) * a0 / e0;
+  const double c1 = -2.0 / S * (q1 - W) * a1 / e1;
+  const double c2 = -2.0 / S * (q2 - W) * a2 / e2;
+  // dbeta0/d(a,b,c) = 13/6 t0 (1,-2,1) + 1/2 u0 (1,-4,3)
+  const double b0a = (13.0 / 6.0) * t0 + 0.5 * u0, b0b = -(13.0 / 3.0) * t0 - 2.0 * u0,
+               b0c = (13.0 / 6.0) * t0 + 1.5 * u0;
+  // dbeta1/d(b,c,d) = 13/6 t1 (1,-2,1) + 1/2 u1 (1,0,-1)
+  const double b1b = (13.0 / 6.0) * t1 + 0.5 * u1, b1c = -(13.0 / 3.0) * t1, b1d = (13.0 / 6.0) * t1 - 0.5 * u1;
+  // dbeta2/d(c,d,e) = 13/6 t2 (1,-2,1) + 1/2 u2 (3,-4,1)
+  const double b2c = (13.0 / 6.0) * t2 + 1.5 * u2, b2d = -(13.0 / 3.0) * t2 - 2.0 * u2,
+               b2e = (13.0 / 6.0) * t2 + 0.5 * u2;
+  g[0] = w0 * (2.0 / 6.0) + c0 * b0a;
+  g[1] = w0 * (-7.0 / 6.0) + w1 * (-1.0 / 6.0) + c0 * b0b + c1 * b1b;
+  g[2] = w0 * (11.0 / 6.0) + w1 * (5.0 / 6.0) + w2 * (2.0 / 6.0) + c0 * b0c + c1 * b1c + c2 * b2c;
+  g[3] = w1 * (2.0 / 6.0) + w2 * (5.0 / 6.0) + c1 * b1d + c2 * b2d;
+  g[4] = w2 * (-1.0 / 6.0) + c2 * b2e;
+  return W;
+}
+
+// q[k] = Q(f-3+k), k = 0..5; upwind value at face f and its gradient gq[0..5]
+__device__ __forceinline__ double upwind_g(const double* q, double vel, double eps, double gq[6]) {
+  double g[5];
+  if (vel >= 0.0) {
+    const double W = weno5_g(q[0], q[1], q[2], q[3], q[4], eps, g);
+    gq[0] = g[0]; gq[1] = g[1]; gq[2] = g[2]; gq[3] = g[3]; gq[4] = g[4]; gq[5] = 0.0;
+    return W;
+  }
+  const double W = weno5_g(q[5], q[4], q[3], q[2], q[1], eps, g);
+  gq[0] = 0.0; gq[1] = g[4]; gq[2] = g[3]; gq[3] = g[2]; gq[4] = g[1]; gq[5] = g[0];
+  return W;
+}
+
+__device__ __forceinline__ double mix1(double a, double p1, double p2) {
+  const double ac = a < 0.0 ? 0.0 : (a > 1.0 ? 1.0 : a);
+  return p1 + ac * (p2 - p1);
+}
+
+// ===========================================================================
+// S8^T: projection.  Per cell (gather over its faces): pbar = dU'/dp^T ubar',
+// abar += d(beta_f)/d(alpha) terms.  u'_f = u*_f - dt beta_f (p_R - p_L)/h.
+template <int DIM>
+__global__ __launch_bounds__(256) void ka_project(KParams P, const double* __restrict__ a, const double* __restrict__ p,
+                                                  const double* __restrict__ ub, const double* __restrict__ vb,
+                                                  const double* __restrict__ wb, double* __restrict__ pbar,
+                                                  double* __restrict__ abar) {
+  const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
+  const int nx = P.nx, ny = P.ny, nz = P.nz;
+  if (i >= nx || j >= ny) return;
+  const long c = cidx(i, j, k, nx, ny);
+  const double ac = a[c], rc = mix1(ac, P.rho1, P.rho2), drc = (P.rho2 - P.rho1) * dclamp(ac);
+  double pb = 0.0, ab = 0.0;
+  const int id[3] = {i, j, k};
+  const int nn[3] = {nx, ny, nz};
+  const double* ubs[3] = {ub, vb, wb};
+  for (int d = 0; d < DIM; ++d) {
+    for (int side = 0; side < 2; ++side) {
+      // side 0: low face (c is R), side 1: high face (c is L)
+      const int fpos = id[d] + side;
+      if (fpos == 0 || fpos == nn[d]) continue;
+      int o[3] = {0, 0, 0};
+      o[d] = side ? 1 : -1;
+      const long cn = cidx(i + o[0], j + o[1], k + o[2], nx, ny);
+      int fi[3] = {i, j, k};
+      fi[d] = fpos;
+      long f;
+      if (d == 0) f = fidx<0>(fi[0], fi[1], fi[2], nx, ny);
+      else if (d == 1) f = fidx<1>(fi[0], fi[1], fi[2], nx, ny);
+      else f = fidx<2>(fi[0], fi[1], fi[2], nx, ny);
+      const double ubar = ubs[d][f];
+      const double rn = mix1(a[cn], P.rho1, P.rho2);
+      const double beta = 1.0 / (0.5 * (rc + rn));
+      // c is R on its low face, L on its high face
+      const double pR = side ? p[cn] : p[c], pL = side ? p[c] : p[cn];
+      pb += (side ? 1.0 : -1.0) * P.dt * beta * ubar * P.ih;
+      const double dbeta = -beta * beta * 0.5 * drc;
+      ab += ubar * (-P.dt * (pR - pL) * P.ih) * dbeta;
+    }
+  }
+  pbar[c] = pb;
+  abar[c] += ab;
+}
+
+// Poisson operator term: abar += sum_f dbeta_f/dalpha (p_R - p_L)(y_R - y_L)/h^2
+template <int DIM>
+__global__ __launch_bounds__(256) void ka_poisson_alpha(KParams P, const double* __restrict__ a,
+                                                        const double* __restrict__ p, const double* __restrict__ y,
+                                                        double* __restrict__ abar) {
+  const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
+  const int nx = P.nx, ny = P.ny, nz = P.nz;
+  if (i >= nx || j >= ny) return;
+  const long c = cidx(i, j, k, nx, ny);
+  const double ac = a[c], rc = mix1(ac, P.rho1, P.rho2), drc = (P.rho2 - P.rho1) * dclamp(ac);
+  const int id[3] = {i, j, k};
+  const int nn[3] = {nx, ny, nz};
+  double ab = 0.0;
+  for (int d = 0; d < DIM; ++d)
+    for (int side = 0; side < 2; ++side) {
+      const int fpos = id[d] + side;
+      if (fpos == 0 || fpos == nn[d]) continue;
+      int o[3] = {0, 0, 0};
+      o[d] = side ? 1 : -1;
+      const long cn = cidx(i + o[0], j + o[1], k + o[2], nx, ny);
+      const double rn = mix1(a[cn], P.rho1, P.rho2);
+      const double beta = 1.0 / (0.5 * (rc + rn));
+      const double dbeta = -beta * beta * 0.5 * drc;
+      // (p_R - p_L)(y_R - y_L) is the same product from either side
+      ab += dbeta * (p[cn] - p[c]) * (y[cn] - y[c]) * P.ih * P.ih;
+    }
+  abar[c] += ab;
+}
+
+// ubar* on interior faces: ubar' + (y_L - y_R)/(h dt); zero on walls
+template <int DIM, int D>
+__global__ __launch_bounds__(256) void ka_rhs_face(KParams P, const double* __restrict__ ubp,
+                                                   const double* __restrict__ y, double* __restrict__ usb) {
+  const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
+  const int nx = P.nx, ny = P.ny, nz = P.nz;
+  const int fnx = nx + (D == 0), fny = ny + (D == 1);
+  if (i >= fnx || j >= fny) return;
+  const int id[3] = {i, j, k};
+  const int nD = D == 0 ? nx : (D == 1 ? ny : nz);
+  const long f = fidx<D>(i, j, k, nx, ny);
+  if (id[D] == 0 || id[D] == nD) {
+    usb[f] = 0.0;
+    return;
+  }
+  int L[3] = {i, j, k};
+  L[D] -= 1;
+  const long cL = cidx(L[0], L[1], L[2], nx, ny), cR = cidx(i, j, k, nx, ny);
+  usb[f] = ubp[f] + (y[cL] - y[cR]) * P.ih / P.dt;
+}
+
+// ===========================================================================
+// (S4-S5)^T: predictor for component D on interior faces (scatter).
+template <int DIM, int D>
+__global__ __launch_bounds__(256) void ka_predictor(KParams P, const double* __restrict__ a,
+                                                    const double* __restrict__ sk, const double* __restrict__ M,
+                                                    const double* __restrict__ u, const double* __restrict__ v,
+                                                    const double* __restrict__ w, const double* __restrict__ usb,
+                                                    double* __restrict__ ubar, double* __restrict__ vbar,
+                                                    double* __restrict__ wbar, double* __restrict__ abar,
+                                                    double* __restrict__ skbar, double* __restrict__ Mbar) {
+  const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
+  const int nx = P.nx, ny = P.ny, nz = P.nz;
+  const int fnx = nx + (D == 0), fny = ny + (D == 1);
+  if (i >= fnx || j >= fny) return;
+  const int id[3] = {i, j, k};
+  const int nD = D == 0 ? nx : (D == 1 ? ny : nz);
+  if (id[D] == 0 || id[D] == nD) return;
+  const long fo = fidx<D>(i, j, k, nx, ny);
+  const double ob = usb[fo];
+  if (ob == 0.0) return;
+  const double* vel[3] = {u, v, w};
+  double* velb[3] = {ubar, vbar, wbar};
+  const double* ud = vel[D];
+  double* udb = velb[D];
+  const double eps = P.weno_eps, ih = P.ih, dt = P.dt;
+  int L[3] = {i, j, k};
+  L[D] -= 1;
+  const long cL = cidx(L[0], L[1], L[2], nx, ny), cR = cidx(i, j, k, nx, ny);
+  // ---- forward recompute of the face quantities
+  const double aL = a[cL], aR = a[cR];
+  const double fst = 0.5 * (sk[cL] + sk[cR]) * (aR - aL) * ih + 0.5 * (M[cL] + M[cR]);
+  const double rhof = 0.5 * (mix1(aL, P.rho1, P.rho2) + mix1(aR, P.rho1, P.rho2));
+  // viscous term needs a forward pass
+  double visc = 0.0;
+  for (int e = 0; e < DIM; ++e) {
+    double q[7];
+    double qs[7];
+    long qi[7];
+    for (int m = 0; m < 7; ++m) {
+      int o[3] = {0, 0, 0};
+      o[e] = m - 3;
+      if (D == 0) qi[m] = v_idx<0, DIM>(i + o[0], j + o[1], k + o[2], nx, ny, nz, qs[m]);
+      else if (D == 1) qi[m] = v_idx<1, DIM>(i + o[0], j + o[1], k + o[2], nx, ny, nz, qs[m]);
+      else qi[m] = v_idx<2, DIM>(i + o[0], j + o[1], k + o[2], nx, ny, nz, qs[m]);
+      q[m] = qs[m] * ud[qi[m]];
+    }
+    if (e == D) {
+      const double mL = mix1(aL, P.mu1, P.mu2), mR = mix1(aR, P.mu1, P.mu2);
+      visc += (2.0 * mR * (q[4] - q[3]) * ih - 2.0 * mL * (q[3] - q[2]) * ih) * ih;
+    } else {
+      double tau[2];
+      for (int side = 0; side < 2; ++side) {
+        const int ef = id[e] + side;
+        int pL[3] = {L[0], L[1], L[2]}, pR[3] = {i, j, k};
+        pL[e] = ef;
+        pR[e] = ef;
+        double sL, sR;
+        long iL, iR;
+        const double* ve = vel[e];
+        if (e == 0) { iL = v_idx<0, DIM>(pL[0], pL[1], pL[2], nx, ny, nz, sL); iR = v_idx<0, DIM>(pR[0], pR[1], pR[2], nx, ny, nz, sR); }
+        else if (e == 1) { iL = v_idx<1, DIM>(pL[0], pL[1], pL[2], nx, ny, nz, sL); iR = v_idx<1, DIM>(pR[0], pR[1], pR[2], nx, ny, nz, sR); }
+        else { iL = v_idx<2, DIM>(pL[0], pL[1], pL[2], nx, ny, nz, sL); iR = v_idx<2, DIM>(pR[0], pR[1], pR[2], nx, ny, nz, sR); }
+        const double veL = sL * ve[iL], veR = sR * ve[iR];
+        int c1[3] = {L[0], L[1], L[2]}, c2[3] = {i, j, k}, c3[3] = {L[0], L[1], L[2]}, c4[3] = {i, j, k};
+        c1[e] = ef - 1; c2[e] = ef - 1; c3[e] = ef; c4[e] = ef;
+        const double me = 0.25 * (mix1(a[a_idx<DIM>(c1[0], c1[1], c1[2], nx, ny, nz)], P.mu1, P.mu2) +
+                                  mix1(a[a_idx<DIM>(c2[0], c2[1], c2[2], nx, ny, nz)], P.mu1, P.mu2) +
+                                  mix1(a[a_idx<DIM>(c3[0], c3[1], c3[2], nx, ny, nz)], P.mu1, P.mu2) +
+                                  mix1(a[a_idx<DIM>(c4[0], c4[1], c4[2], nx, ny, nz)], P.mu1, P.mu2));
+        tau[side] = me * ((q[3 + side] - q[2 + side]) * ih + (veR - veL) * ih);
+      }
+      visc += (tau[1] - tau[0]) * ih;
+    }
+  }
+  // ---- reverse
+  aadd(&udb[fo], ob);  // direct term u*_f = u_f + ...
+  const double convb = -dt * ob;
+  const double viscb = dt * ob / rhof, fstb = dt * ob / rhof;
+  const double rhofb = -dt * ob * (visc + fst) / (rhof * rhof);
+  double aLb = rhofb * 0.5 * (P.rho2 - P.rho1) * dclamp(aL);
+  double aRb = rhofb * 0.5 * (P.rho2 - P.rho1) * dclamp(aR);
+  // CSF force
+  aadd(&skbar[cL], fstb * 0.5 * (aR - aL) * ih);
+  aadd(&skbar[cR], fstb * 0.5 * (aR - aL) * ih);
+  aRb += fstb * 0.5 * (sk[cL] + sk[cR]) * ih;
+  aLb -= fstb * 0.5 * (sk[cL] + sk[cR]) * ih;
+  aadd(&Mbar[cL], 0.5 * fstb);
+  aadd(&Mbar[cR], 0.5 * fstb);
+  const double dmu = P.mu2 - P.mu1;
+  for (int e = 0; e < DIM; ++e) {
+    double q[7], qs[7], qb[7];
+    long qi[7];
+    for (int m = 0; m < 7; ++m) {
+      int o[3] = {0, 0, 0};
+      o[e] = m - 3;
+      if (D == 0) qi[m] = v_idx<0, DIM>(i + o[0], j + o[1], k + o[2], nx, ny, nz, qs[m]);
+      else if (D == 1) qi[m] = v_idx<1, DIM>(i + o[0], j + o[1], k + o[2], nx, ny, nz, qs[m]);
+      else qi[m] = v_idx<2, DIM>(i + o[0], j + o[1], k + o[2], nx, ny, nz, qs[m]);
+      q[m] = qs[m] * ud[qi[m]];
+      qb[m] = 0.0;
+    }
+    const double Fhib = convb * ih, Flob = -convb * ih;
+    const double thib = viscb * ih, tlob = -viscb * ih;
+    if (e == D) {
+      const double Ulo = 0.5 * (q[2] + q[3]), Uhi = 0.5 * (q[3] + q[4]);
+      double g[6];
+      double W = upwind_g(q, Ulo, eps, g);
+      double Ub = Flob * W;
+      for (int m = 0; m < 6; ++m) qb[m] += Flob * Ulo * g[m];
+      qb[2] += 0.5 * Ub;
+      qb[3] += 0.5 * Ub;
+      W = upwind_g(q + 1, Uhi, eps, g);
+      Ub = Fhib * W;
+      for (int m = 0; m < 6; ++m) qb[m + 1] += Fhib * Uhi * g[m];
+      qb[3] += 0.5 * Ub;
+      qb[4] += 0.5 * Ub;
+      const double mL = mix1(aL, P.mu1, P.mu2), mR = mix1(aR, P.mu1, P.mu2);
+      // tlo = 2 mL (q3 - q2) ih ; thi = 2 mR (q4 - q3) ih
+      aLb += tlob * 2.0 * (q[3] - q[2]) * ih * dmu * dclamp(aL);
+      aRb += thib * 2.0 * (q[4] - q[3]) * ih * dmu * dclamp(aR);
+      qb[3] += tlob * 2.0 * mL * ih;
+      qb[2] -= tlob * 2.0 * mL * ih;
+      qb[4] += thib * 2.0 * mR * ih;
+      qb[3] -= thib * 2.0 * mR * ih;
+    } else {
+      double* veb = velb[e];
+      const double* ve = vel[e];
+      for (int side = 0; side < 2; ++side) {
+        const double Fb = side ? Fhib : Flob, tb = side ? thib : tlob;
+        const int ef = id[e] + side;
+        int pL[3] = {L[0], L[1], L[2]}, pR[3] = {i, j, k};
+        pL[e] = ef;
+        pR[e] = ef;
+        double sL, sR;
+        long iL, iR;
+        if (e == 0) { iL = v_idx<0, DIM>(pL[0], pL[1], pL[2], nx, ny, nz, sL); iR = v_idx<0, DIM>(pR[0], pR[1], pR[2], nx, ny, nz, sR); }
+        else if (e == 1) { iL = v_idx<1, DIM>(pL[0], pL[1], pL[2], nx, ny, nz, sL); iR = v_idx<1, DIM>(pR[0], pR[1], pR[2], nx, ny, nz, sR); }
+        else { iL = v_idx<2, DIM>(pL[0], pL[1], pL[2], nx, ny, nz, sL); iR = v_idx<2, DIM>(pR[0], pR[1], pR[2], nx, ny, nz, sR); }
+        const double veL = sL * ve[iL], veR = sR * ve[iR];
+        const double Vb = 0.5 * (veL + veR);
+        double g[6];
+        const double W = upwind_g(q + side, Vb, eps, g);
+        double Vbb = Fb * W;
+        for (int m = 0; m < 6; ++m) qb[m + side] += Fb * Vb * g[m];
+        double veLb = 0.5 * Vbb, veRb = 0.5 * Vbb;
+        int cc[4][3] = {{L[0], L[1], L[2]}, {i, j, k}, {L[0], L[1], L[2]}, {i, j, k}};
+        cc[0][e] = ef - 1; cc[1][e] = ef - 1; cc[2][e] = ef; cc[3][e] = ef;
+        long ci[4];
+        double me = 0.0;
+        for (int q4 = 0; q4 < 4; ++q4) {
+          ci[q4] = a_idx<DIM>(cc[q4][0], cc[q4][1], cc[q4][2], nx, ny, nz);
+          me += 0.25 * mix1(a[ci[q4]], P.mu1, P.mu2);
+        }
+        const double dud = (q[3 + side] - q[2 + side]) * ih, dve = (veR - veL) * ih;
+        const double meb = tb * (dud + dve);
+        const double dudb = tb * me, dveb = tb * me;
+        qb[3 + side] += dudb * ih;
+        qb[2 + side] -= dudb * ih;
+        veRb += dveb * ih;
+        veLb -= dveb * ih;
+        for (int q4 = 0; q4 < 4; ++q4) aadd(&abar[ci[q4]], 0.25 * meb * dmu * dclamp(a[ci[q4]]));
+        aadd(&veb[iL], sL * veLb);
+        aadd(&veb[iR], sR * veRb);
+      }
+    }
+    for (int m = 0; m < 7; ++m) aadd(&udb[qi[m]], qs[m] * qb[m]);
+  }
+  aadd(&abar[cL], aLb);
+  aadd(&abar[cR], aRb);
+}
+
+// ===========================================================================
+// S3^T, part 1 (interior cells): from skbar, Mbar -> Tbar, sbar partials, and
+// nbar / dsbar on the ghost-extended grid.
+template <int DIM>
+__device__ __forceinline__ void normal_of(const double* __restrict__ a, int i, int j, int k, int nx, int ny, int nz,
+                                          double ih2, double ne, double n[3]) {
+  const double gx = (A_at<DIM>(a, i + 1, j, k, nx, ny, nz) - A_at<DIM>(a, i - 1, j, k, nx, ny, nz)) * ih2;
+  const double gy = (A_at<DIM>(a, i, j + 1, k, nx, ny, nz) - A_at<DIM>(a, i, j - 1, k, nx, ny, nz)) * ih2;
+  const double gz = DIM == 3 ? (A_at<DIM>(a, i, j, k + 1, nx, ny, nz) - A_at<DIM>(a, i, j, k - 1, nx, ny, nz)) * ih2 : 0.0;
+  const double inv = 1.0 / sqrt(gx * gx + gy * gy + gz * gz + ne * ne);
+  n[0] = gx * inv;
+  n[1] = gy * inv;
+  n[2] = gz * inv;
+}
+
+__device__ __forceinline__ long eidx(int i, int j, int k, int nx, int ny, int oz) {
+  return (long)(i + 1) + (long)(nx + 2) * ((long)(j + 1) + (long)(ny + 2) * (k + oz));
+}
+
+template <int DIM>
+__global__ __launch_bounds__(256) void ka_geom_cell(KParams P, const double* __restrict__ a,
+                                                    const double* __restrict__ T, const double* __restrict__ skb,
+                                                    const double* __restrict__ Mxb, const double* __restrict__ Myb,
+                                                    const double* __restrict__ Mzb, double* __restrict__ Tbar,
+                                                    double* __restrict__ nbx, double* __restrict__ nby,
+                                                    double* __restrict__ nbz, double* __restrict__ dsb,
+                                                    double* __restrict__ spart) {
+  __shared__ double sh[8];
+  const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
+  const int nx = P.nx, ny = P.ny, nz = P.nz;
+  const int oz = DIM == 3 ? 1 : 0;
+  double sacc = 0.0;
+  if (i < nx && j < ny) {
+    const double ih2 = 0.5 * P.ih, ne = P.neps, s = P.s;
+    const long c = cidx(i, j, k, nx, ny);
+    // forward recompute
+    double nn[3], np[3];
+    normal_of<DIM>(a, i + 1, j, k, nx, ny, nz, ih2, ne, np);
+    normal_of<DIM>(a, i - 1, j, k, nx, ny, nz, ih2, ne, nn);
+    double divn = (np[0] - nn[0]) * ih2;
+    normal_of<DIM>(a, i, j + 1, k, nx, ny, nz, ih2, ne, np);
+    normal_of<DIM>(a, i, j - 1, k, nx, ny, nz, ih2, ne, nn);
+    divn += (np[1] - nn[1]) * ih2;
+    if (DIM == 3) {
+      normal_of<DIM>(a, i, j, k + 1, nx, ny, nz, ih2, ne, np);
+      normal_of<DIM>(a, i, j, k - 1, nx, ny, nz, ih2, ne, nn);
+      divn += (np[2] - nn[2]) * ih2;
+    }
+    const double kappa = -divn;
+    const double gx = (A_at<DIM>(a, i + 1, j, k, nx, ny, nz) - A_at<DIM>(a, i - 1, j, k, nx, ny, nz)) * ih2;
+    const double gy = (A_at<DIM>(a, i, j + 1, k, nx, ny, nz) - A_at<DIM>(a, i, j - 1, k, nx, ny, nz)) * ih2;
+    const double gz = DIM == 3 ? (A_at<DIM>(a, i, j, k + 1, nx, ny, nz) - A_at<DIM>(a, i, j, k - 1, nx, ny, nz)) * ih2 : 0.0;
+    const double g2 = gx * gx + gy * gy + gz * gz;
+    const double ge = sqrt(g2 + ne * ne);
+    const double ds = g2 / (ge + ne);
+    const double n[3] = {gx / ge, gy / ge, gz / ge};
+    const double sigma = P.sigma0 + s * (T[c] - P.T0);
+    double dT[3];  // T(c+e) - T(c-e)
+    dT[0] = T_at<DIM>(T, i + 1, j, k, P) - T_at<DIM>(T, i - 1, j, k, P);
+    dT[1] = T_at<DIM>(T, i, j + 1, k, P) - T_at<DIM>(T, i, j - 1, k, P);
+    dT[2] = DIM == 3 ? T_at<DIM>(T, i, j, k + 1, P) - T_at<DIM>(T, i, j, k - 1, P) : 0.0;
+    const double gs[3] = {s * dT[0] * ih2, s * dT[1] * ih2, s * dT[2] * ih2};
+    const double ndg = n[0] * gs[0] + n[1] * gs[1] + n[2] * gs[2];
+    // reverse of sk = sigma kappa
+    const double skbar = skb[c];
+    const double sigb = skbar * kappa, kapb = skbar * sigma;
+    aadd(&Tbar[c], s * sigb);
+    sacc += sigb * (T[c] - P.T0);
+    // reverse of M = ds (gs - n (n.gs))
+    const double Mb[3] = {Mxb[c], Myb[c], DIM == 3 ? Mzb[c] : 0.0};
+    const double nMb = n[0] * Mb[0] + n[1] * Mb[1] + n[2] * Mb[2];
+    const double dsbar = Mb[0] * (gs[0] - n[0] * ndg) + Mb[1] * (gs[1] - n[1] * ndg) + Mb[2] * (gs[2] - n[2] * ndg);
+    double gsb[3], nb[3];
+    for (int d = 0; d < 3; ++d) {
+      gsb[d] = ds * (Mb[d] - n[d] * nMb);
+      nb[d] = -ds * (Mb[d] * ndg + nMb * gs[d]);
+    }
+    // gs_d = s (T(c+e_d) - T(c-e_d))/(2h)
+    for (int d = 0; d < DIM; ++d) {
+      sacc += gsb[d] * dT[d] * ih2;
+      int o[3] = {0, 0, 0};
+      o[d] = 1;
+      double sgp, sgm;
+      const long ip = t_idx<DIM>(i + o[0], j + o[1], k + o[2], P, sgp);
+      const long im = t_idx<DIM>(i - o[0], j - o[1], k - o[2], P, sgm);
+      aadd(&Tbar[ip], sgp * s * gsb[d] * ih2);
+      aadd(&Tbar[im], -sgm * s * gsb[d] * ih2);
+    }
+    // kappa = -sum_d (n_d(c+e_d) - n_d(c-e_d))/(2h)
+    double* nbs[3] = {nbx, nby, nbz};
+    for (int d = 0; d < DIM; ++d) {
+      int o[3] = {0, 0, 0};
+      o[d] = 1;
+      aadd(&nbs[d][eidx(i + o[0], j + o[1], k + o[2], nx, ny, oz)], -kapb * ih2);
+      aadd(&nbs[d][eidx(i - o[0], j - o[1], k - o[2], nx, ny, oz)], kapb * ih2);
+    }
+    const long ec = eidx(i, j, k, nx, ny, oz);
+    for (int d = 0; d < DIM; ++d) aadd(&nbs[d][ec], nb[d]);
+    aadd(&dsb[ec], dsbar);
+  }
+  const double r = block_reduce<0>(sacc, sh);
+  if (threadIdx.x == 0 && threadIdx.y == 0) spart[block_linear()] = r;
+}
+
+// S3^T, part 2 (ghost-extended cells): nbar, dsbar -> gbar -> abar.
+template <int DIM>
+__global__ __launch_bounds__(256) void ka_geom_ext(KParams P, const double* __restrict__ a,
+                                                   const double* __restrict__ nbx, const double* __restrict__ nby,
+                                                   const double* __restrict__ nbz, const double* __restrict__ dsb,
+                                                   double* __restrict__ abar) {
+  const int oz = DIM == 3 ? 1 : 0;
+  const int i = blockIdx.x * BX + threadIdx.x - 1, j = blockIdx.y * BY + threadIdx.y - 1, k = blockIdx.z - oz;
+  const int nx = P.nx, ny = P.ny, nz = P.nz;
+  if (i > nx || j > ny) return;
+  const long ec = eidx(i, j, k, nx, ny, oz);
+  const double nb[3] = {nbx[ec], nby[ec], DIM == 3 ? nbz[ec] : 0.0};
+  const double db = dsb[ec];
+  if (nb[0] == 0.0 && nb[1] == 0.0 && nb[2] == 0.0 && db == 0.0) return;
+  const double ih2 = 0.5 * P.ih, ne = P.neps;
+  const double gx = (A_at<DIM>(a, i + 1, j, k, nx, ny, nz) - A_at<DIM>(a, i - 1, j, k, nx, ny, nz)) * ih2;
+  const double gy = (A_at<DIM>(a, i, j + 1, k, nx, ny, nz) - A_at<DIM>(a, i, j - 1, k, nx, ny, nz)) * ih2;
+  const double gz = DIM == 3 ? (A_at<DIM>(a, i, j, k + 1, nx, ny, nz) - A_at<DIM>(a, i, j, k - 1, nx, ny, nz)) * ih2 : 0.0;
+  const double ge = sqrt(gx * gx + gy * gy + gz * gz + ne * ne);
+  const double n[3] = {gx / ge, gy / ge, gz / ge};
+  const double nnb = n[0] * nb[0] + n[1] * nb[1] + n[2] * nb[2];
+  for (int d = 0; d < DIM; ++d) {
+    // n = g/ge: gbar = (nbar - n (n.nbar))/ge ; delta_s = ge - eps_n: gbar += dsbar n
+    const double gb = (nb[d] - n[d] * nnb) / ge + db * n[d];
+    int o[3] = {0, 0, 0};
+    o[d] = 1;
+    aadd(&abar[a_idx<DIM>(i + o[0], j + o[1], k + o[2], nx, ny, nz)], gb * ih2);
+    aadd(&abar[a_idx<DIM>(i - o[0], j - o[1], k - o[2], nx, ny, nz)], -gb * ih2);
+  }
+}
+
+// ===========================================================================
+// S1^T: one RK stage G(a, T) = (a + dt La(a), T + dt LT(a, T)) transposed,
+// applied to w = (wa, wT) and accumulated into (ab, Tb) and the face-velocity
+// adjoints.  Face part: advective fluxes and conduction across interior faces.
+template <int DIM, int D>
+__global__ __launch_bounds__(256) void ka_transport_face(KParams P, const double* __restrict__ a,
+                                                         const double* __restrict__ T, const double* __restrict__ uD,
+                                                         const double* __restrict__ wa,
+                                                         const double* __restrict__ wT, double* __restrict__ ab,
+                                                         double* __restrict__ Tb, double* __restrict__ uDb) {
+  const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
+  const int nx = P.nx, ny = P.ny, nz = P.nz;
+  const int fnx = nx + (D == 0), fny = ny + (D == 1);
+  if (i >= fnx || j >= fny) return;
+  const int id[3] = {i, j, k};
+  const int nD = D == 0 ? nx : (D == 1 ? ny : nz);
+  if (id[D] == 0 || id[D] == nD) return;
+  const long f = fidx<D>(i, j, k, nx, ny);
+  int L[3] = {i, j, k};
+  L[D] -= 1;
+  const long cL = cidx(L[0], L[1], L[2], nx, ny), cR = cidx(i, j, k, nx, ny);
+  const double ih = P.ih, dt = P.dt, eps = P.weno_eps;
+  // advective fluxes: La_L -= F/h, La_R += F/h (same for T)
+  const double Fab = dt * (wa[cR] - wa[cL]) * ih;
+  const double FTb = dt * (wT[cR] - wT[cL]) * ih;
+  const double uf = uD[f];
+  double qa[6], qt[6], sgt[6];
+  long ia[6], it[6];
+  for (int m = 0; m < 6; ++m) {
+    int o[3] = {i, j, k};
+    o[D] = id[D] - 3 + m;
+    ia[m] = a_idx<DIM>(o[0], o[1], o[2], nx, ny, nz);
+    qa[m] = a[ia[m]];
+    it[m] = t_idx<DIM>(o[0], o[1], o[2], P, sgt[m]);
+    qt[m] = T_at<DIM>(T, o[0], o[1], o[2], P);
+  }
+  double ga[6], gt[6];
+  const double Wa = upwind_g(qa, uf, eps, ga);
+  const double Wt = upwind_g(qt, uf, eps, gt);
+  uDb[f] += Fab * Wa + FTb * Wt;
+  for (int m = 0; m < 6; ++m) {
+    aadd(&ab[ia[m]], Fab * uf * ga[m]);
+    aadd(&Tb[it[m]], FTb * uf * gt[m] * sgt[m]);
+  }
+  // conduction: Phi = lambda_f (T_R - T_L)/h^2 ; cond_L += Phi, cond_R -= Phi
+  const double aL = a[cL], aR = a[cR];
+  const double rcL = mix1(aL, P.rhocp1, P.rhocp2), rcR = mix1(aR, P.rhocp1, P.rhocp2);
+  const double Phib = dt * (wT[cL] / rcL - wT[cR] / rcR);
+  const double lf = 0.5 * (mix1(aL, P.lam1, P.lam2) + mix1(aR, P.lam1, P.lam2));
+  const double ih2 = ih * ih;
+  aadd(&Tb[cR], Phib * lf * ih2);
+  aadd(&Tb[cL], -Phib * lf * ih2);
+  const double dTf = (T[cR] - T[cL]) * ih2;
+  const double dl = P.lam2 - P.lam1;
+  aadd(&ab[cL], Phib * dTf * 0.5 * dl * dclamp(aL));
+  aadd(&ab[cR], Phib * dTf * 0.5 * dl * dclamp(aR));
+}
+
+// Cell part: identity, wall conduction faces, rho c_p, heat source.
+template <int DIM>
+__global__ __launch_bounds__(256) void ka_transport_cell(KParams P, const double* __restrict__ a,
+                                                         const double* __restrict__ T, const double* __restrict__ wa,
+                                                         const double* __restrict__ wT, double* __restrict__ ab,
+                                                         double* __restrict__ Tb) {
+  const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
+  const int nx = P.nx, ny = P.ny, nz = P.nz;
+  if (i >= nx || j >= ny) return;
+  const long c = cidx(i, j, k, nx, ny);
+  const double dt = P.dt, ih = P.ih, ih2 = ih * ih;
+  aadd(&ab[c], wa[c]);
+  aadd(&Tb[c], wT[c]);
+  const double ac = a[c], Tc = T[c];
+  const double rcp = mix1(ac, P.rhocp1, P.rhocp2);
+  const double lc = mix1(ac, P.lam1, P.lam2);
+  const double dl = (P.lam2 - P.lam1) * dclamp(ac);
+  const double wc = dt * wT[c] / rcp;  // adjoint weight of cond_c and src_c
+  double cond = 0.0, abc = 0.0, Tbc = 0.0;
+  const int di[6] = {-1, 1, 0, 0, 0, 0}, dj[6] = {0, 0, -1, 1, 0, 0}, dk[6] = {0, 0, 0, 0, -1, 1};
+  for (int f = 0; f < 2 * DIM; ++f) {
+    const int ii = i + di[f], jj = j + dj[f], kk = k + dk[f];
+    const double an = A_at<DIM>(a, ii, jj, kk, nx, ny, nz);
+    const double Tn = T_at<DIM>(T, ii, jj, kk, P);
+    const double lf = 0.5 * (lc + mix1(an, P.lam1, P.lam2));
+    cond += lf * (Tn - Tc);
+    const bool wall = ii < 0 || ii >= nx || jj < 0 || jj >= ny || (DIM == 3 && (kk < 0 || kk >= nz));
+    if (wall) {
+      // ghost neighbour mirrors this cell: a_g = a_c, T_g = sg T_c (+ const)
+      double sg;
+      (void)t_idx<DIM>(ii, jj, kk, P, sg);
+      Tbc += wc * lf * (sg - 1.0) * ih2;
+      abc += wc * (Tn - Tc) * ih2 * dl;  // lambda_f = lambda(a_c): d/da_c = lambda'
+    }
+  }
+  cond *= ih2;
+  double src = 0.0;
+  if (P.qP != 0.0) {
+    const double h2 = 0.5 * ih;
+    const double gx = (A_at<DIM>(a, i + 1, j, k, nx, ny, nz) - A_at<DIM>(a, i - 1, j, k, nx, ny, nz)) * h2;
+    const double gy = (A_at<DIM>(a, i, j + 1, k, nx, ny, nz) - A_at<DIM>(a, i, j - 1, k, nx, ny, nz)) * h2;
+    const double gz = DIM == 3 ? (A_at<DIM>(a, i, j, k + 1, nx, ny, nz) - A_at<DIM>(a, i, j, k - 1, nx, ny, nz)) * h2 : 0.0;
+    const double g2 = gx * gx + gy * gy + gz * gz;
+    const double ne = P.neps;
+    const double ge = sqrt(g2 + ne * ne);
+    const double xl = P.qx0 + P.qvx * P.t, yl = P.qy0 + P.qvy * P.t;
+    const double x = (i + 0.5) * P.h, y = (j + 0.5) * P.h;
+    const double r2 = (x - xl) * (x - xl) + (y - yl) * (y - yl);
+    const double R2 = P.qr * P.qr;
+    const double Q = 2.0 * P.qP / (M_PI * R2) * exp(-2.0 * r2 / R2);
+    src = Q * g2 / (ge + ne);
+    // d delta_s / d g = g / ge
+    const double gb[3] = {wc * Q * gx / ge, wc * Q * gy / ge, wc * Q * gz / ge};
+    for (int d = 0; d < DIM; ++d) {
+      int o[3] = {0, 0, 0};
+      o[d] = 1;
+      aadd(&ab[a_idx<DIM>(i + o[0], j + o[1], k + o[2], nx, ny, nz)], gb[d] * h2);
+      aadd(&ab[a_idx<DIM>(i - o[0], j - o[1], k - o[2], nx, ny, nz)], -gb[d] * h2);
+    }
+  }
+  // rho c_p in the denominator
+  abc += -wc * (cond + src) * (P.rhocp2 - P.rhocp1) * dclamp(ac) / rcp;
+  aadd(&ab[c], abc);
+  aadd(&Tb[c], Tbc);
+}
+
+// y = s * x ; y += s * x
+__global__ __launch_bounds__(256) void ka_scale(long n, double s, const double* __restrict__ x, double* __restrict__ y) {
+  const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < n) y[c] = s * x[c];
+}
+__global__ __launch_bounds__(256) void ka_axpy(long n, double s, const double* __restrict__ x, double* __restrict__ y) {
+  const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < n) y[c] += s * x[c];
+}
+// accumulate a device scalar (one thread)
+__global__ void ka_add_scalar(double* dst, const double* src) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) dst[0] += src[0];
+}
+
+inline dim3 grid_of(int fnx, int fny, int fnz) { return dim3((fnx + BX - 1) / BX, (fny + BY - 1) / BY, fnz); }
+inline int nb1(long n) { return (int)((n + 255) / 256); }
+
+}  // namespace
+
+// ---- launchers -------------------------------------------------------------
+void adj_project(const KParams& P, hipStream_t s, const double* a, const double* p, const double* ub,
+                 const double* vb, const double* wb, double* pbar, double* abar) {
+  dim3 g = grid_of(P.nx, P.ny, P.nz), b(BX, BY);
+  if (P.dim == 3) hipLaunchKernelGGL((ka_project<3>), g, b, 0, s, P, a, p, ub, vb, wb, pbar, abar);
+  else hipLaunchKernelGGL((ka_project<2>), g, b, 0, s, P, a, p, ub, vb, wb, pbar, abar);
+}
+
+void adj_poisson_alpha(const KParams& P, hipStream_t s, const double* a, const double* p, const double* y,
+                       double* abar) {
+  dim3 g = grid_of(P.nx, P.ny, P.nz), b(BX, BY);
+  if (P.dim == 3) hipLaunchKernelGGL((ka_poisson_alpha<3>), g, b, 0, s, P, a, p, y, abar);
+  else hipLaunchKernelGGL((ka_poisson_alpha<2>), g, b, 0, s, P, a, p, y, abar);
+}
+
+void adj_rhs(const KParams& P, hipStream_t s, const double* ubp, const double* vbp, const double* wbp,
+             const double* y, double* usb, double* vsb, double* wsb) {
+  dim3 b(BX, BY);
+  if (P.dim == 3) {
+    hipLaunchKernelGGL((ka_rhs_face<3, 0>), grid_of(P.nx + 1, P.ny, P.nz), b, 0, s, P, ubp, y, usb);
+    hipLaunchKernelGGL((ka_rhs_face<3, 1>), grid_of(P.nx, P.ny + 1, P.nz), b, 0, s, P, vbp, y, vsb);
+    hipLaunchKernelGGL((ka_rhs_face<3, 2>), grid_of(P.nx, P.ny, P.nz + 1), b, 0, s, P, wbp, y, wsb);
+  } else {
+    hipLaunchKernelGGL((ka_rhs_face<2, 0>), grid_of(P.nx + 1, P.ny, 1), b, 0, s, P, ubp, y, usb);
+    hipLaunchKernelGGL((ka_rhs_face<2, 1>), grid_of(P.nx, P.ny + 1, 1), b, 0, s, P, vbp, y, vsb);
+  }
+}
+
+void adj_predictor(const KParams& P, hipStream_t s, const double* a, const double* sk, const double* Mx,
+                   const double* My, const double* Mz, const double* u, const double* v, const double* w,
+                   const double* usb, const double* vsb, const double* wsb, double* ubar, double* vbar,
+                   double* wbar, double* abar, double* skbar, double* Mxb, double* Myb, double* Mzb) {
+  dim3 b(BX, BY);
+  if (P.dim == 3) {
+    hipLaunchKernelGGL((ka_predictor<3, 0>), grid_of(P.nx + 1, P.ny, P.nz), b, 0, s, P, a, sk, Mx, u, v, w, usb, ubar,
+                       vbar, wbar, abar, skbar, Mxb);
+    hipLaunchKernelGGL((ka_predictor<3, 1>), grid_of(P.nx, P.ny + 1, P.nz), b, 0, s, P, a, sk, My, u, v, w, vsb, ubar,
+                       vbar, wbar, abar, skbar, Myb);
+    hipLaunchKernelGGL((ka_predictor<3, 2>), grid_of(P.nx, P.ny, P.nz + 1), b, 0, s, P, a, sk, Mz, u, v, w, wsb, ubar,
+                       vbar, wbar, abar, skbar, Mzb);
+  } else {
+    hipLaunchKernelGGL((ka_predictor<2, 0>), grid_of(P.nx + 1, P.ny, 1), b, 0, s, P, a, sk, Mx, u, v, w, usb, ubar,
+                       vbar, wbar, abar, skbar, Mxb);
+    hipLaunchKernelGGL((ka_predictor<2, 1>), grid_of(P.nx, P.ny + 1, 1), b, 0, s, P, a, sk, My, u, v, w, vsb, ubar,
+                       vbar, wbar, abar, skbar, Myb);
+  }
+}
+
+int adj_geometry(const KParams& P, hipStream_t s, const double* a, const double* T, const double* skb,
+                 const double* Mxb, const double* Myb, const double* Mzb, double* Tbar, double* nbx, double* nby,
+                 double* nbz, double* dsb, double* abar, double* spart) {
+  dim3 b(BX, BY);
+  dim3 g = grid_of(P.nx, P.ny, P.nz);
+  const int oz = P.dim == 3 ? 1 : 0;
+  dim3 ge = grid_of(P.nx + 2, P.ny + 2, P.nz + 2 * oz);
+  if (P.dim == 3) {
+    hipLaunchKernelGGL((ka_geom_cell<3>), g, b, 0, s, P, a, T, skb, Mxb, Myb, Mzb, Tbar, nbx, nby, nbz, dsb, spart);
+    hipLaunchKernelGGL((ka_geom_ext<3>), ge, b, 0, s, P, a, nbx, nby, nbz, dsb, abar);
+  } else {
+    hipLaunchKernelGGL((ka_geom_cell<2>), g, b, 0, s, P, a, T, skb, Mxb, Myb, Mzb, Tbar, nbx, nby, nbz, dsb, spart);
+    hipLaunchKernelGGL((ka_geom_ext<2>), ge, b, 0, s, P, a, nbx, nby, nbz, dsb, abar);
+  }
+  return (int)(g.x * g.y * g.z);
+}
+
+void adj_transport_stage(const KParams& P, hipStream_t s, const double* a, const double* T, const double* u,
+                         const double* v, const double* w, const double* wa, const double* wT, double* ab,
+                         double* Tb, double* ub, double* vb, double* wb) {
+  dim3 b(BX, BY);
+  if (P.dim == 3) {
+    hipLaunchKernelGGL((ka_transport_face<3, 0>), grid_of(P.nx + 1, P.ny, P.nz), b, 0, s, P, a, T, u, wa, wT, ab, Tb, ub);
+    hipLaunchKernelGGL((ka_transport_face<3, 1>), grid_of(P.nx, P.ny + 1, P.nz), b, 0, s, P, a, T, v, wa, wT, ab, Tb, vb);
+    hipLaunchKernelGGL((ka_transport_face<3, 2>), grid_of(P.nx, P.ny, P.nz + 1), b, 0, s, P, a, T, w, wa, wT, ab, Tb, wb);
+    hipLaunchKernelGGL((ka_transport_cell<3>), grid_of(P.nx, P.ny, P.nz), b, 0, s, P, a, T, wa, wT, ab, Tb);
+  } else {
+    hipLaunchKernelGGL((ka_transport_face<2, 0>), grid_of(P.nx + 1, P.ny, 1), b, 0, s, P, a, T, u, wa, wT, ab, Tb, ub);
+    hipLaunchKernelGGL((ka_transport_face<2, 1>), grid_of(P.nx, P.ny + 1, 1), b, 0, s, P, a, T, v, wa, wT, ab, Tb, vb);
+    hipLaunchKernelGGL((ka_transport_cell<2>), grid_of(P.nx, P.ny, 1), b, 0, s, P, a, T, wa, wT, ab, Tb);
+  }
+}
+
+void adj_scale(hipStream_t s, long n, double f, const double* x, double* y) {
+  hipLaunchKernelGGL(ka_scale, dim3(nb1(n)), dim3(256), 0, s, n, f, x, y);
+}
+void adj_axpy(hipStream_t s, long n, double f, const double* x, double* y) {
+  hipLaunchKernelGGL(ka_axpy, dim3(nb1(n)), dim3(256), 0, s, n, f, x, y);
+}
+void adj_add_scalar(hipStream_t s, double* dst, const double* src) {
+  hipLaunchKernelGGL(ka_add_scalar, dim3(1), dim3(64), 0, s, dst, src);
+}
+
+}  // namespace tcf

@@ -122,6 +122,13 @@ struct tcf_grid {
   double* hscal;  // pinned host mirror
   int* hflag;
   size_t bytes;
+  // adjoint scratch (configs with TCF_WITH_ADJOINT; FP64 only)
+  struct Adj {
+    double *ab, *Tb, *usb, *vsb, *wsb, *ub, *vb, *wb, *pbar, *y, *skb, *Mxb, *Myb, *Mzb;
+    double *nbx, *nby, *nbz, *dsb, *wa, *wT, *sa, *sT;
+    long Ne;
+  } adj{};
+  bool has_adj = false;
   // optional event timing of one kernel family (measurement only)
   int prof_family = -1;
   std::vector<hipEvent_t> prof_ev;  // start/end pairs
@@ -262,6 +269,34 @@ size_t carve(const tcf_config* c, void* base, tcf_grid* g) {
     carve_fields<double>(cv, D, G->f64, c->mg_levels, true, G->u64, G->v64, G->w64, G->ax64, G->ay64, G->az64);
   const int nb = (int)std::max<long>((D.N + 255) / 256, (long)nblocks_cells(D.nx, D.ny, D.nz));
   G->nb = nb;
+  if (c->flags & TCF_WITH_ADJOINT) {
+    auto& A = G->adj;
+    const long N = D.N;
+    A.Ne = (long)(D.nx + 2) * (D.ny + 2) * (D.dim == 3 ? D.nz + 2 : 1);
+    A.ab = cv.take<double>(N);
+    A.Tb = cv.take<double>(N);
+    A.usb = cv.take<double>(D.Nu);
+    A.vsb = cv.take<double>(D.Nv);
+    A.wsb = D.dim == 3 ? cv.take<double>(D.Nw) : nullptr;
+    A.ub = cv.take<double>(D.Nu);
+    A.vb = cv.take<double>(D.Nv);
+    A.wb = D.dim == 3 ? cv.take<double>(D.Nw) : nullptr;
+    A.pbar = cv.take<double>(N);
+    A.y = cv.take<double>(N);
+    A.skb = cv.take<double>(N);
+    A.Mxb = cv.take<double>(N);
+    A.Myb = cv.take<double>(N);
+    A.Mzb = D.dim == 3 ? cv.take<double>(N) : nullptr;
+    A.nbx = cv.take<double>(A.Ne);
+    A.nby = cv.take<double>(A.Ne);
+    A.nbz = D.dim == 3 ? cv.take<double>(A.Ne) : nullptr;
+    A.dsb = cv.take<double>(A.Ne);
+    A.wa = cv.take<double>(N);
+    A.wT = cv.take<double>(N);
+    A.sa = cv.take<double>(N);
+    A.sT = cv.take<double>(N);
+    G->has_adj = true;
+  }
   double* pbase = cv.take<double>(6L * nb);  // contiguous: diagnostics write 6 strided arrays
   for (int k = 0; k < 6; ++k) G->part[k] = pbase ? pbase + (long)k * nb : nullptr;
   G->scal = cv.take<double>(S_NSLOT);
@@ -278,7 +313,8 @@ std::string validate(const tcf_config* c) {
   if ((double)c->nx * c->ny * (c->dim == 3 ? c->nz : 1) > 2.0e9) return "grid too large (more than 2e9 cells)";
   if (!(c->h > 0.0) || !std::isfinite(c->h)) return "h must be positive";
   if (c->precision != TCF_FP64 && c->precision != TCF_FP32_REFINE) return "unknown precision";
-  if (c->flags & ~TCF_TRANSPORT_ONLY) return "unknown flags";
+  if (c->flags & ~(TCF_TRANSPORT_ONLY | TCF_WITH_ADJOINT)) return "unknown flags";
+  if ((c->flags & TCF_WITH_ADJOINT) && c->precision != TCF_FP64) return "the adjoint needs precision TCF_FP64";
   if (!(c->rho1 > 0 && c->rho2 > 0)) return "densities must be positive";
   if (!(c->mu1 >= 0 && c->mu2 >= 0)) return "viscosities must be non-negative";
   if (!(c->rhocp1 > 0 && c->rhocp2 > 0)) return "rho*c_p must be positive";
@@ -692,6 +728,84 @@ tcf_status predictor_only(tcf_grid* g, double dt, double* us, double* vs, double
   return TCF_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Adjoint driver (FP64).
+
+// S1 forward, keeping the stage states in f64.a1/T1, a2/T2; state arrays end
+// at (alpha^{n+1}, T^{n+1}).
+void forward_transport_keep(tcf_grid* g, const KParams& P) {
+  Fields<double>& F = g->f64;
+  hipStream_t s = g->stream;
+  transport_stage<double>(P, s, F.a, F.T, F.a, F.T, F.u, F.v, F.w, F.a1, F.T1, 0.0, 1.0);
+  transport_stage<double>(P, s, F.a1, F.T1, F.a, F.T, F.u, F.v, F.w, F.a2, F.T2, 0.75, 0.25);
+  transport_stage<double>(P, s, F.a2, F.T2, F.a, F.T, F.u, F.v, F.w, F.a, F.T, 1.0 / 3.0, 2.0 / 3.0);
+}
+
+// Transposed SSP-RK3 (stages recomputed by the caller): given the adjoint
+// (va, vT) of (alpha^{n+1}, T^{n+1}), write (ab, Tb) = adjoint of (alpha^n,
+// T^n) and accumulate the face-velocity adjoints.
+void rk3_reverse(tcf_grid* g, const KParams& P, const double* a0, const double* T0, const double* va,
+                 const double* vT, double* ab, double* Tb) {
+  Fields<double>& F = g->f64;
+  auto& A = g->adj;
+  hipStream_t s = g->stream;
+  const long N = g->D.N;
+  // stage 3: out = 1/3 base + 2/3 G(a2, T2)
+  adj_scale(s, N, 2.0 / 3.0, va, A.wa);
+  adj_scale(s, N, 2.0 / 3.0, vT, A.wT);
+  fill_f64(s, N, A.sa, 0.0);
+  fill_f64(s, N, A.sT, 0.0);
+  adj_transport_stage(P, s, F.a2, F.T2, F.u, F.v, F.w, A.wa, A.wT, A.sa, A.sT, A.ub, A.vb, A.wb);
+  adj_scale(s, N, 1.0 / 3.0, va, ab);
+  adj_scale(s, N, 1.0 / 3.0, vT, Tb);
+  // stage 2: a2 = 3/4 base + 1/4 G(a1, T1)
+  adj_axpy(s, N, 0.75, A.sa, ab);
+  adj_axpy(s, N, 0.75, A.sT, Tb);
+  adj_scale(s, N, 0.25, A.sa, A.wa);
+  adj_scale(s, N, 0.25, A.sT, A.wT);
+  fill_f64(s, N, A.sa, 0.0);
+  fill_f64(s, N, A.sT, 0.0);
+  adj_transport_stage(P, s, F.a1, F.T1, F.u, F.v, F.w, A.wa, A.wT, A.sa, A.sT, A.ub, A.vb, A.wb);
+  // stage 1: a1 = G(a0, T0)
+  adj_transport_stage(P, s, a0, T0, F.u, F.v, F.w, A.sa, A.sT, ab, Tb, A.ub, A.vb, A.wb);
+}
+
+void zero_adj_faces(tcf_grid* g) {
+  auto& A = g->adj;
+  const Dims& D = g->D;
+  fill_f64(g->stream, D.Nu, A.ub, 0.0);
+  fill_f64(g->stream, D.Nv, A.vb, 0.0);
+  if (D.dim == 3) fill_f64(g->stream, D.Nw, A.wb, 0.0);
+}
+
+// (S2..S5)^T at the current fields (alpha', T', u^n) for a given ubar*;
+// accumulates into A.ab, A.Tb, A.ub.. and stores sbar in scal[S_SBAR].
+void predictor_reverse(tcf_grid* g, const KParams& P, const double* usb, const double* vsb, const double* wsb) {
+  Fields<double>& F = g->f64;
+  auto& A = g->adj;
+  hipStream_t s = g->stream;
+  const long N = g->D.N;
+  fill_f64(s, N, A.skb, 0.0);
+  fill_f64(s, N, A.Mxb, 0.0);
+  fill_f64(s, N, A.Myb, 0.0);
+  if (g->D.dim == 3) fill_f64(s, N, A.Mzb, 0.0);
+  fill_f64(s, A.Ne, A.nbx, 0.0);
+  fill_f64(s, A.Ne, A.nby, 0.0);
+  if (g->D.dim == 3) fill_f64(s, A.Ne, A.nbz, 0.0);
+  fill_f64(s, A.Ne, A.dsb, 0.0);
+  adj_predictor(P, s, F.a, F.sk, F.Mx, F.My, F.Mz, F.u, F.v, F.w, usb, vsb, wsb, A.ub, A.vb, A.wb, A.ab, A.skb,
+                A.Mxb, A.Myb, A.Mzb);
+  const int np = adj_geometry(P, s, F.a, F.T, A.skb, A.Mxb, A.Myb, A.Mzb, A.Tb, A.nbx, A.nby, A.nbz, A.dsb, A.ab,
+                              g->part[0]);
+  finalize(s, g->part[0], np, g->scal, g->iflag, F_STORE, S_SBAR, 0.0);
+}
+
+tcf_status adj_checks(tcf_grid* g) {
+  if (!g) return fail(TCF_E_INVALID, "grid is NULL");
+  if (!g->has_adj) return fail(TCF_E_INVALID, "grid was not initialised with TCF_WITH_ADJOINT");
+  return TCF_OK;
+}
+
 }  // namespace
 
 // =============================================================================
@@ -907,6 +1021,132 @@ tcf_status tcf_profile_read(tcf_grid* g, double* total_ms, long* launches) {
   HIPCHECK(prof_flush(g));
   *total_ms = g->prof_ms;
   *launches = g->prof_count;
+  return TCF_OK;
+}
+
+tcf_status tcf_step_backward(tcf_grid* g, double t_n, double dt, const double* const state_n[6],
+                             const double* const adj_np1[5], double* const adj_n[5], double* dL_dsigmaT) {
+  g_err.clear();
+  tcf_status st = adj_checks(g);
+  if (st != TCF_OK) return st;
+  const Dims& D = g->D;
+  if (!state_n || !adj_np1 || !adj_n || !dL_dsigmaT) return fail(TCF_E_INVALID, "NULL argument");
+  for (int k = 0; k < 5; ++k) {
+    const bool need = k < 4 || D.dim == 3;
+    if (need && (!state_n[k] || !adj_np1[k] || !adj_n[k])) return fail(TCF_E_INVALID, "NULL field pointer");
+  }
+  if (!(dt > 0) || !std::isfinite(dt) || !std::isfinite(t_n)) return fail(TCF_E_INVALID, "bad dt or t_n");
+  st = tcf_set_fields(g, t_n, state_n[0], state_n[1], state_n[2], state_n[3], D.dim == 3 ? state_n[4] : nullptr,
+                      state_n[5]);
+  if (st != TCF_OK) return st;
+  hipStream_t s = g->stream;
+  Fields<double>& F = g->f64;
+  auto& A = g->adj;
+  KParams P = g->P;
+  P.dt = dt;
+  P.t = t_n;
+  const long N = D.N;
+  // ---- forward S1..S7, keeping what the reverse sweep reads
+  forward_transport_keep(g, P);
+  geometry<double>(P, s, F.a, F.T, F.sk, F.Mx, F.My, F.Mz);
+  predictor<double>(P, s, F.a, F.sk, F.Mx, F.My, F.Mz, F.u, F.v, F.w, F.us, F.vs, F.ws);
+  const int nbc = nblocks_cells(D.nx, D.ny, D.nz);
+  divergence_rhs<double>(P, s, F.us, F.vs, F.ws, g->b64, g->part[0]);
+  finalize(s, g->part[0], nbc, g->scal, g->iflag, F_MEAN, S_MEAN, (double)N);
+  prepare_operator<double>(g);
+  st = solve(g, g->p64, nullptr);
+  if (st != TCF_OK && st != TCF_E_NOT_CONVERGED) return st;
+  // ---- S8^T
+  copy_f64(s, N, adj_np1[0], A.ab);
+  copy_f64(s, N, adj_np1[1], A.Tb);
+  adj_project(P, s, F.a, g->p64, adj_np1[2], adj_np1[3], D.dim == 3 ? adj_np1[4] : nullptr, A.pbar, A.ab);
+  // ---- S7^T: y = A^+ pbar with the same symmetric operator, then dA/dalpha
+  copy_f64(s, N, A.pbar, g->b64);
+  const int nbp = sum64_partials(s, N, g->b64, g->part[0]);
+  finalize(s, g->part[0], nbp, g->scal, g->iflag, F_MEAN, S_MEAN, (double)N);
+  fill_f64(s, N, A.y, 0.0);
+  st = solve(g, A.y, nullptr);
+  if (st != TCF_OK && st != TCF_E_NOT_CONVERGED) return st;
+  adj_poisson_alpha(P, s, F.a, g->p64, A.y, A.ab);
+  // ---- S6^T
+  adj_rhs(P, s, adj_np1[2], adj_np1[3], D.dim == 3 ? adj_np1[4] : nullptr, A.y, A.usb, A.vsb, A.wsb);
+  // ---- (S2..S5)^T
+  zero_adj_faces(g);
+  predictor_reverse(g, P, A.usb, A.vsb, A.wsb);
+  adj_add_scalar(s, dL_dsigmaT, g->scal + S_SBAR);
+  // ---- S1^T
+  rk3_reverse(g, P, state_n[0], state_n[1], A.ab, A.Tb, adj_n[0], adj_n[1]);
+  zero_walls<double>(P, s, A.ub, A.vb, A.wb);
+  copy_f64(s, D.Nu, A.ub, adj_n[2]);
+  copy_f64(s, D.Nv, A.vb, adj_n[3]);
+  if (D.dim == 3) copy_f64(s, D.Nw, A.wb, adj_n[4]);
+  HIPCHECK(hipGetLastError());
+  return st;
+}
+
+tcf_status tcf_adjoint_transport(tcf_grid* g, double dt, const double* ab_in, const double* Tb_in, double* ab_out,
+                                 double* Tb_out, double* ub, double* vb, double* wb) {
+  g_err.clear();
+  tcf_status st = adj_checks(g);
+  if (st != TCF_OK) return st;
+  const Dims& D = g->D;
+  if (!ab_in || !Tb_in || !ab_out || !Tb_out || !ub || !vb || (D.dim == 3 && !wb))
+    return fail(TCF_E_INVALID, "NULL argument");
+  if (ab_in == ab_out || Tb_in == Tb_out) return fail(TCF_E_INVALID, "input and output adjoints must not alias");
+  if (!g->has_fields) return fail(TCF_E_STATE, "fields not set");
+  if (!(dt > 0) || !std::isfinite(dt)) return fail(TCF_E_INVALID, "bad dt");
+  hipStream_t s = g->stream;
+  Fields<double>& F = g->f64;
+  auto& A = g->adj;
+  KParams P = g->P;
+  P.dt = dt;
+  P.t = g->t;
+  const long N = D.N;
+  // stages from the current state, without touching it: stage 3 is not needed
+  transport_stage<double>(P, s, F.a, F.T, F.a, F.T, F.u, F.v, F.w, F.a1, F.T1, 0.0, 1.0);
+  transport_stage<double>(P, s, F.a1, F.T1, F.a, F.T, F.u, F.v, F.w, F.a2, F.T2, 0.75, 0.25);
+  // the base state is read from copies (rk3_reverse reads a0/T0 after using sa/sT)
+  copy_f64(s, N, F.a, A.pbar);
+  copy_f64(s, N, F.T, A.y);
+  zero_adj_faces(g);
+  rk3_reverse(g, P, A.pbar, A.y, ab_in, Tb_in, ab_out, Tb_out);
+  zero_walls<double>(P, s, A.ub, A.vb, A.wb);
+  copy_f64(s, D.Nu, A.ub, ub);
+  copy_f64(s, D.Nv, A.vb, vb);
+  if (D.dim == 3) copy_f64(s, D.Nw, A.wb, wb);
+  HIPCHECK(hipGetLastError());
+  return TCF_OK;
+}
+
+tcf_status tcf_adjoint_predictor(tcf_grid* g, double dt, const double* usb, const double* vsb, const double* wsb,
+                                 double* ab, double* Tb, double* ub, double* vb, double* wb, double* sbar) {
+  g_err.clear();
+  tcf_status st = adj_checks(g);
+  if (st != TCF_OK) return st;
+  const Dims& D = g->D;
+  if (!usb || !vsb || !ab || !Tb || !ub || !vb || !sbar || (D.dim == 3 && (!wsb || !wb)))
+    return fail(TCF_E_INVALID, "NULL argument");
+  if (!g->has_fields) return fail(TCF_E_STATE, "fields not set");
+  if (!(dt > 0) || !std::isfinite(dt)) return fail(TCF_E_INVALID, "bad dt");
+  hipStream_t s = g->stream;
+  Fields<double>& F = g->f64;
+  auto& A = g->adj;
+  KParams P = g->P;
+  P.dt = dt;
+  P.t = g->t;
+  geometry<double>(P, s, F.a, F.T, F.sk, F.Mx, F.My, F.Mz);
+  fill_f64(s, D.N, A.ab, 0.0);
+  fill_f64(s, D.N, A.Tb, 0.0);
+  zero_adj_faces(g);
+  predictor_reverse(g, P, usb, vsb, wsb);
+  zero_walls<double>(P, s, A.ub, A.vb, A.wb);
+  copy_f64(s, D.N, A.ab, ab);
+  copy_f64(s, D.N, A.Tb, Tb);
+  copy_f64(s, D.Nu, A.ub, ub);
+  copy_f64(s, D.Nv, A.vb, vb);
+  if (D.dim == 3) copy_f64(s, D.Nw, A.wb, wb);
+  copy_f64(s, 1, g->scal + S_SBAR, sbar);
+  HIPCHECK(hipGetLastError());
   return TCF_OK;
 }
 

@@ -42,7 +42,7 @@ struct Fine {
 
 // Slots of the device scalar block (FP64).
 enum Slot { S_MEAN = 0, S_BB, S_RR, S_RZ, S_DQ, S_ALPHA, S_BETA, S_TOL2, S_SCALE,
-            S_SUMA, S_AMIN, S_AMAX, S_UMAX, S_DIV2, S_NONFIN, S_RR64, S_BB64, S_PMEAN, S_NSLOT = 24 };
+            S_SUMA, S_AMIN, S_AMAX, S_UMAX, S_DIV2, S_NONFIN, S_RR64, S_BB64, S_PMEAN, S_SBAR, S_NSLOT = 24 };
 // Integer flags: done, iteration count.
 enum IFlag { I_DONE = 0, I_ITERS = 1, I_NFLAG = 4 };
 enum FinOp { F_STORE = 0, F_MEAN, F_BB, F_ALPHA, F_RR, F_RZ_FIRST, F_RZ, F_MIN, F_MAX, F_SCALE };
@@ -143,6 +143,27 @@ void project(const KParams& P, hipStream_t s, const R* a, const double* p, const
 template <class R>
 void diagnostics(const KParams& P, hipStream_t s, const R* a, const double* u, const double* v,
                  const double* w, double* part, int stride);
+
+// adjoint (tcf_adjoint.hip), FP64
+void adj_project(const KParams& P, hipStream_t s, const double* a, const double* p, const double* ub,
+                 const double* vb, const double* wb, double* pbar, double* abar);
+void adj_poisson_alpha(const KParams& P, hipStream_t s, const double* a, const double* p, const double* y,
+                       double* abar);
+void adj_rhs(const KParams& P, hipStream_t s, const double* ubp, const double* vbp, const double* wbp,
+             const double* y, double* usb, double* vsb, double* wsb);
+void adj_predictor(const KParams& P, hipStream_t s, const double* a, const double* sk, const double* Mx,
+                   const double* My, const double* Mz, const double* u, const double* v, const double* w,
+                   const double* usb, const double* vsb, const double* wsb, double* ubar, double* vbar,
+                   double* wbar, double* abar, double* skbar, double* Mxb, double* Myb, double* Mzb);
+int adj_geometry(const KParams& P, hipStream_t s, const double* a, const double* T, const double* skb,
+                 const double* Mxb, const double* Myb, const double* Mzb, double* Tbar, double* nbx, double* nby,
+                 double* nbz, double* dsb, double* abar, double* spart);
+void adj_transport_stage(const KParams& P, hipStream_t s, const double* a, const double* T, const double* u,
+                         const double* v, const double* w, const double* wa, const double* wT, double* ab,
+                         double* Tb, double* ub, double* vb, double* wb);
+void adj_scale(hipStream_t s, long n, double f, const double* x, double* y);
+void adj_axpy(hipStream_t s, long n, double f, const double* x, double* y);
+void adj_add_scalar(hipStream_t s, double* dst, const double* src);
 
 // conversions
 void to_f32(hipStream_t s, long n, const double* x, float* y);

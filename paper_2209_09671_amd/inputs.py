@@ -242,12 +242,27 @@ def target_centroid(c):
     return rng.uniform(-0.02, 0.02, 3)
 
 
-def t_directions(c, k=16, seed=3):
-    """Seeded unit directions in the space of initial temperature fields."""
+def t_directions(c, k=16, seed=3, modes=4):
+    """Seeded smooth unit directions in the space of initial temperature
+    fields: random combinations of the cosine modes 0..modes-1 along each
+    axis (white noise would probe mostly grid-scale components to which a
+    loss of the droplet centroid is nearly blind)."""
     rng = np.random.default_rng(seed + 1000)
-    d = rng.standard_normal((k,) + shapes(c)["cell"])
-    d /= np.sqrt((d.reshape(k, -1) ** 2).sum(1)).reshape((k,) + (1,) * 3)
-    return d
+    nz, ny, nx = shapes(c)["cell"]
+    x = (np.arange(nx) + 0.5) / nx
+    y = (np.arange(ny) + 0.5) / ny
+    z = (np.arange(nz) + 0.5) / nz
+    out = np.zeros((k, nz, ny, nx))
+    mz = modes if c["dim"] == 3 else 1
+    for q in range(k):
+        for l in range(mz):
+            for m in range(modes):
+                for n in range(modes):
+                    out[q] += rng.standard_normal() * (np.cos(l * np.pi * z)[:, None, None] *
+                                                       np.cos(m * np.pi * y)[None, :, None] *
+                                                       np.cos(n * np.pi * x)[None, None, :])
+        out[q] /= np.linalg.norm(out[q])
+    return out
 
 
 def describe(c) -> str:

