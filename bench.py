@@ -124,6 +124,40 @@ def run_gpu(c, st, precision, steps, warmup, family=None):
                 relres=worst_res, div=worst_div, kernel_ms=kms, kernel_launches=kn, info=info)
 
 
+def adjoint_timing(c, st, steps, every):
+    """Seconds per adjoint step (FP64): gradient of the melt-pool kinetic
+    energy 1/2 h^3 sum_f rho_f u_f^2 after `steps` steps with respect to
+    dsigma/dT and the initial T, checkpoints every `every` steps; the time
+    includes the forward recomputation of each checkpoint segment."""
+    import torch
+    from paper_2209_09671_amd import tcf
+    dv = lambda x: None if x is None else torch.as_tensor(x, dtype=torch.float64, device="cuda")
+    a0, u0, v0, w0 = dv(st["alpha"]), dv(st["u"]), dv(st["v"]), dv(st["w"])
+    s = torch.tensor(c["dsigma_dT"], dtype=torch.float64, requires_grad=True)
+    T0 = dv(st["T"]).requires_grad_(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    a, T, u, v, w = tcf.TcfRollout.apply(s, T0, c, a0, u0, v0, w0, steps, every)
+    rho = c["rho1"] + a.clamp(0, 1) * (c["rho2"] - c["rho1"])
+    h3 = c["h"] ** 3
+    ke = 0.5 * h3 * ((0.5 * (rho[:, :, 1:] + rho[:, :, :-1]) * u[:, :, 1:-1] ** 2).sum()
+                     + (0.5 * (rho[:, 1:, :] + rho[:, :-1, :]) * v[:, 1:-1, :] ** 2).sum())
+    if w.numel():
+        ke = ke + 0.5 * h3 * (0.5 * (rho[1:] + rho[:-1]) * w[1:-1] ** 2).sum()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ke.backward()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    out = {"value": round((t2 - t1) / steps, 5), "unit": "s/step", "precision": "fp64",
+           "steps": steps, "checkpoint_every": every, "forward_s_per_step": round((t1 - t0) / steps, 5),
+           "loss": "1/2 h^3 sum_f rho_f u_f^2 (melt-pool kinetic energy)",
+           "dL_dsigmaT": float(s.grad), "grad_T0_norm": float(T0.grad.norm())}
+    del a, T, u, v, w, T0
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -132,8 +166,11 @@ def main():
     ap.add_argument("--workload", type=int, default=4)
     ap.add_argument("--kernel", default="smooth")
     ap.add_argument("--rtol", type=float, default=1e-8)
+    ap.add_argument("--inner-rtol", type=float, default=None)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--adjoint-steps", type=int, default=10)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this path runs on one GPU; multi-GPU runs are not part of this build "
@@ -145,6 +182,8 @@ def main():
 
     c = I.config(args.workload)
     c["p_rtol"] = args.rtol
+    if args.inner_rtol:
+        c["inner_rtol"] = args.inner_rtol
     st = I.initial_state(c)
     N = c["nx"] * c["ny"] * c["nz"]
     wl = c["name"]
@@ -170,6 +209,11 @@ def main():
                 "kernel": args.kernel, "avg_launch_ms": round(avg_ms, 5),
                 "launches": r32["kernel_launches"], "algorithmic_bytes_per_launch": ab}
 
+    adj = None
+    if not args.no_adjoint:
+        ca = dict(c, precision=0)
+        adj = adjoint_timing(ca, st, args.adjoint_steps, max(1, args.adjoint_steps // 2))
+
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(c, c["dt"], args.rtol)
@@ -194,6 +238,7 @@ def main():
                    "max_div_rel": r32["div"]},
         "fp64_same_accuracy": fp64,
         "wall_ms_per_step": round(r32["wall"] * 1e3 / args.steps, 4),
+        "adjoint": adj,
         "roofline": roof,
         "cpu_baseline": cpu,
     }

@@ -19,105 +19,6 @@ namespace {
 using namespace dev;
 
 // ---------------------------------------------------------------------------
-// S1: one SSP-RK3 stage for alpha and T.
-//   out = cb * base + ci * (in + dt * L(in))
-// L(alpha) = -div(u alpha), L(T) = -div(u T) + [div(lambda grad T) + Q delta_s]/(rho c_p)
-template <class R, int DIM>
-__global__ __launch_bounds__(256) void k_transport(KParams P, const R* __restrict__ a, const R* __restrict__ T,
-                                                   const R* ab, const R* Tb, const R* __restrict__ u,
-                                                   const R* __restrict__ v, const R* __restrict__ w, R* ao,
-                                                   R* To, R cb, R ci) {
-  const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
-  const int nx = P.nx, ny = P.ny, nz = P.nz;
-  if (i >= nx || j >= ny) return;
-  const R eps = R(P.weno_eps);
-  const long c = cidx(i, j, k, nx, ny);
-  R diva = R(0), divt = R(0);
-  // ---- x direction: faces i and i+1
-  {
-    R qa[7], qt[7];
-#pragma unroll
-    for (int m = 0; m < 7; ++m) {
-      qa[m] = A_at<DIM>(a, i - 3 + m, j, k, nx, ny, nz);
-      qt[m] = T_at<DIM>(T, i - 3 + m, j, k, P);
-    }
-    const R ulo = u[fidx<0>(i, j, k, nx, ny)], uhi = u[fidx<0>(i + 1, j, k, nx, ny)];
-    R Falo = R(0), Ftlo = R(0), Fahi = R(0), Fthi = R(0);
-    if (i > 0) { Falo = ulo * upwind(qa, ulo, eps); Ftlo = ulo * upwind(qt, ulo, eps); }
-    if (i < nx - 1) { Fahi = uhi * upwind(qa + 1, uhi, eps); Fthi = uhi * upwind(qt + 1, uhi, eps); }
-    diva += Fahi - Falo;
-    divt += Fthi - Ftlo;
-  }
-  // ---- y direction
-  {
-    R qa[7], qt[7];
-#pragma unroll
-    for (int m = 0; m < 7; ++m) {
-      qa[m] = A_at<DIM>(a, i, j - 3 + m, k, nx, ny, nz);
-      qt[m] = T_at<DIM>(T, i, j - 3 + m, k, P);
-    }
-    const R vlo = v[fidx<1>(i, j, k, nx, ny)], vhi = v[fidx<1>(i, j + 1, k, nx, ny)];
-    R Falo = R(0), Ftlo = R(0), Fahi = R(0), Fthi = R(0);
-    if (j > 0) { Falo = vlo * upwind(qa, vlo, eps); Ftlo = vlo * upwind(qt, vlo, eps); }
-    if (j < ny - 1) { Fahi = vhi * upwind(qa + 1, vhi, eps); Fthi = vhi * upwind(qt + 1, vhi, eps); }
-    diva += Fahi - Falo;
-    divt += Fthi - Ftlo;
-  }
-  if (DIM == 3) {
-    R qa[7], qt[7];
-#pragma unroll
-    for (int m = 0; m < 7; ++m) {
-      qa[m] = A_at<DIM>(a, i, j, k - 3 + m, nx, ny, nz);
-      qt[m] = T_at<DIM>(T, i, j, k - 3 + m, P);
-    }
-    const R wlo = w[fidx<2>(i, j, k, nx, ny)], whi = w[fidx<2>(i, j, k + 1, nx, ny)];
-    R Falo = R(0), Ftlo = R(0), Fahi = R(0), Fthi = R(0);
-    if (k > 0) { Falo = wlo * upwind(qa, wlo, eps); Ftlo = wlo * upwind(qt, wlo, eps); }
-    if (k < nz - 1) { Fahi = whi * upwind(qa + 1, whi, eps); Fthi = whi * upwind(qt + 1, whi, eps); }
-    diva += Fahi - Falo;
-    divt += Fthi - Ftlo;
-  }
-  const R ih = R(P.ih);
-  const R La = -diva * ih;
-  // conduction with arithmetic-mean face conductivity
-  const R ac = a[c], Tc = T[c];
-  const R lc = mixp(ac, P.lam1, P.lam2);
-  R cond = R(0);
-  {
-    const int di[6] = {-1, 1, 0, 0, 0, 0}, dj[6] = {0, 0, -1, 1, 0, 0}, dk[6] = {0, 0, 0, 0, -1, 1};
-#pragma unroll
-    for (int f = 0; f < 2 * DIM; ++f) {
-      const R an = A_at<DIM>(a, i + di[f], j + dj[f], k + dk[f], nx, ny, nz);
-      const R Tn = T_at<DIM>(T, i + di[f], j + dj[f], k + dk[f], P);
-      const R lf = R(0.5) * (lc + mixp(an, P.lam1, P.lam2));
-      cond += lf * (Tn - Tc);
-    }
-  }
-  cond *= ih * ih;
-  R src = R(0);
-  if (P.qP != 0.0) {
-    const R ih2 = R(0.5) * ih;
-    const R gx = (A_at<DIM>(a, i + 1, j, k, nx, ny, nz) - A_at<DIM>(a, i - 1, j, k, nx, ny, nz)) * ih2;
-    const R gy = (A_at<DIM>(a, i, j + 1, k, nx, ny, nz) - A_at<DIM>(a, i, j - 1, k, nx, ny, nz)) * ih2;
-    const R gz = DIM == 3 ? (A_at<DIM>(a, i, j, k + 1, nx, ny, nz) - A_at<DIM>(a, i, j, k - 1, nx, ny, nz)) * ih2 : R(0);
-    const R g2 = gx * gx + gy * gy + gz * gz;
-    const R ne = R(P.neps);
-    const R ds = g2 / (sqrt(g2 + ne * ne) + ne);
-    // Gaussian flux evaluated in FP64 (beam position and exponent)
-    const double xl = P.qx0 + P.qvx * P.t, yl = P.qy0 + P.qvy * P.t;
-    const double x = (i + 0.5) * P.h, y = (j + 0.5) * P.h;
-    const double r2 = (x - xl) * (x - xl) + (y - yl) * (y - yl);
-    const double R2 = P.qr * P.qr;
-    const double Q = 2.0 * P.qP / (M_PI * R2) * exp(-2.0 * r2 / R2);
-    src = R(Q) * ds;
-  }
-  const R LT = -divt * ih + (cond + src) / mixp(ac, P.rhocp1, P.rhocp2);
-  const R dt = R(P.dt);
-  ao[c] = cb * ab[c] + ci * (ac + dt * La);
-  To[c] = cb * Tb[c] + ci * (Tc + dt * LT);
-}
-
-// ---------------------------------------------------------------------------
 // S3: interface geometry per interior cell -> sigma*kappa, M.
 template <class R, int DIM>
 __device__ __forceinline__ void normal_at(const R* __restrict__ a, int i, int j, int k, int nx, int ny, int nz,
@@ -853,16 +754,6 @@ inline int nblk1(long n) { return (int)((n + 255) / 256); }
 // =============================================================================
 // Launchers
 template <class R>
-void transport_stage(const KParams& P, hipStream_t s, const R* a, const R* T, const R* ab, const R* Tb,
-                     const R* u, const R* v, const R* w, R* ao, R* To, double cb, double ci) {
-  dim3 g = grid_for(P.nx, P.ny, P.nz);
-  if (P.dim == 3)
-    hipLaunchKernelGGL((k_transport<R, 3>), g, blk(), 0, s, P, a, T, ab, Tb, u, v, w, ao, To, R(cb), R(ci));
-  else
-    hipLaunchKernelGGL((k_transport<R, 2>), g, blk(), 0, s, P, a, T, ab, Tb, u, v, w, ao, To, R(cb), R(ci));
-}
-
-template <class R>
 void geometry(const KParams& P, hipStream_t s, const R* a, const R* T, R* sk, R* Mx, R* My, R* Mz) {
   dim3 g = grid_for(P.nx, P.ny, P.nz);
   if (P.dim == 3) hipLaunchKernelGGL((k_geometry<R, 3>), g, blk(), 0, s, P, a, T, sk, Mx, My, Mz);
@@ -1085,8 +976,6 @@ void zero_walls(const KParams& P, hipStream_t s, R* u, R* v, R* w) {
 
 // explicit instantiations
 #define TCF_INST(R)                                                                                               \
-  template void transport_stage<R>(const KParams&, hipStream_t, const R*, const R*, const R*, const R*, const R*, \
-                                   const R*, const R*, R*, R*, double, double);                                   \
   template void geometry<R>(const KParams&, hipStream_t, const R*, const R*, R*, R*, R*, R*);                     \
   template void predictor<R>(const KParams&, hipStream_t, const R*, const R*, const R*, const R*, const R*,       \
                              const R*, const R*, const R*, R*, R*, R*);                                           \
