@@ -21,7 +21,13 @@ namespace {
 
 using namespace dev;
 
-constexpr int FX = 64, FY = 8;
+#ifndef TCF_FINE_FY
+#define TCF_FINE_FY 8
+#endif
+#ifndef TCF_FINE_BLOCKS
+#define TCF_FINE_BLOCKS 1024
+#endif
+constexpr int FX = 64, FY = TCF_FINE_FY;
 
 template <class R>
 struct Op0 {
@@ -76,8 +82,8 @@ __device__ __forceinline__ R wface(const Op0<R>& op, R rc, R an) {
 // ahead so that loads stay in flight across the barriers.  For each active
 // cell body(c, k, xc, Kx, dg) receives K0 x and the diagonal.  With POST, all
 // threads then pass a second barrier and post(k) runs (the restriction).
-template <class R, int DIM, bool HASX, bool POST, class XL, class BODY, class PST>
-__device__ __forceinline__ void march(const Op0<R>& op, const Tile& T, const XL& X, const BODY& body,
+template <class R, int DIM, bool HASX, bool POST, class XL, class PRE, class BODY, class PST>
+__device__ __forceinline__ void march(const Op0<R>& op, const Tile& T, const XL& X, const PRE& pre, const BODY& body,
                                       const PST& post) {
   __shared__ R sx[2][LY][LX];
   __shared__ R sa[2][LY][LX];
@@ -117,6 +123,9 @@ __device__ __forceinline__ void march(const Op0<R>& op, const Tile& T, const XL&
       }
     }
   };
+  // per-cell operands of the body (b, CG vectors), prefetched one plane ahead
+  using PV = decltype(pre(0L));
+  PV pv1 = T.act ? pre(col + pl * T.k0) : PV{};
   if (DIM == 3) load_centre(T.k0 - 1, x0, a0);
   load_centre(T.k0, x1, a1);
   load_halo(T.k0, hy1, hx1, gy1, gx1);
@@ -126,6 +135,7 @@ __device__ __forceinline__ void march(const Op0<R>& op, const Tile& T, const XL&
   }
   int buf = 0;
   for (int k = T.k0; k < T.k1; ++k) {
+    PV pv2 = (T.act && k + 1 < T.k1) ? pre(col + pl * (k + 1)) : PV{};
     if (DIM == 3) {
       load_centre(k + 2, x3, a3);
       load_halo(k + 2, hy3, hx3, gy3, gx3);
@@ -179,12 +189,13 @@ __device__ __forceinline__ void march(const Op0<R>& op, const Tile& T, const XL&
           d += w;
         }
       }
-      body(c, k, x1, s, d);
+      body(c, k, x1, s, d, pv1);
     }
     if (POST) {
       __syncthreads();
       post(k);
     }
+    pv1 = pv2;
     x0 = x1; x1 = x2; x2 = x3;
     a0 = a1; a1 = a2; a2 = a3;
     hy1 = hy2; hy2 = hy3; hx1 = hx2; hx2 = hx3;
@@ -192,6 +203,12 @@ __device__ __forceinline__ void march(const Op0<R>& op, const Tile& T, const XL&
     buf ^= 1;
   }
 }
+
+struct Empty {};
+template <class R>
+struct Vec4 {
+  R a, b, c, d;
+};
 
 struct NoPost {
   __device__ void operator()(int) const {}
@@ -205,7 +222,7 @@ __device__ __forceinline__ void write_partial(double acc, double* part) {
 
 // d' = z + beta d (d' = z on the first iteration); q = K0 d'; partial d'.q
 template <class R, int DIM>
-__global__ __launch_bounds__(512) void k0_spmv_upd(Op0<R> op, int kz, int ntx, int nty, const R* __restrict__ z,
+__global__ __launch_bounds__(FX * FY) void k0_spmv_upd(Op0<R> op, int kz, int ntx, int nty, const R* __restrict__ z,
                                                    const R* __restrict__ dold, R* __restrict__ dnew,
                                                    R* __restrict__ q, const double* __restrict__ scal, int first,
                                                    double* __restrict__ part, const int* __restrict__ iflag) {
@@ -214,19 +231,20 @@ __global__ __launch_bounds__(512) void k0_spmv_upd(Op0<R> op, int kz, int ntx, i
   const R beta = first ? R(0) : R(scal[S_BETA]);
   auto X = [&](long c, int, int, int) { return first ? z[c] : z[c] + beta * dold[c]; };
   double acc = 0.0;
-  auto body = [&](long c, int, R xc, R Kx, R) {
+  auto pre = [&](long) { return Empty{}; };
+  auto body = [&](long c, int, R xc, R Kx, R, const Empty&) {
     dnew[c] = xc;
     q[c] = Kx;
     acc += (double)xc * (double)Kx;
   };
-  march<R, DIM, true, false>(op, T, X, body, NoPost());
+  march<R, DIM, true, false>(op, T, X, pre, body, NoPost());
   write_partial(acc, part);
 }
 
 // x += alpha d; r -= alpha q (partial r.r); z1 = omega r / diag (first sweep
 // of the next V-cycle from a zero guess)
 template <class R, int DIM>
-__global__ __launch_bounds__(512) void k0_update_smooth(Op0<R> op, int kz, int ntx, int nty, R omega,
+__global__ __launch_bounds__(FX * FY) void k0_update_smooth(Op0<R> op, int kz, int ntx, int nty, R omega,
                                                         const double* __restrict__ scal, R* __restrict__ x,
                                                         R* __restrict__ r, const R* __restrict__ d,
                                                         const R* __restrict__ q, R* __restrict__ z1,
@@ -236,42 +254,44 @@ __global__ __launch_bounds__(512) void k0_update_smooth(Op0<R> op, int kz, int n
   const R al = R(scal[S_ALPHA]);
   double acc = 0.0;
   auto X = [&](long, int, int, int) { return R(0); };
-  auto body = [&](long c, int, R, R, R dg) {
-    x[c] += al * d[c];
-    const R rn = r[c] - al * q[c];
+  auto pre = [&](long c) { return Vec4<R>{x[c], r[c], d[c], q[c]}; };
+  auto body = [&](long c, int, R, R, R dg, const Vec4<R>& v) {
+    x[c] = v.a + al * v.c;
+    const R rn = v.b - al * v.d;
     r[c] = rn;
     acc += (double)rn * (double)rn;
     z1[c] = omega * recip(dg) * rn;
   };
-  march<R, DIM, false, false>(op, T, X, body, NoPost());
+  march<R, DIM, false, false>(op, T, X, pre, body, NoPost());
   write_partial(acc, part);
 }
 
 // z1 = omega b / diag
 template <class R, int DIM>
-__global__ __launch_bounds__(512) void k0_smooth_first(Op0<R> op, int kz, int ntx, int nty, R omega,
+__global__ __launch_bounds__(FX * FY) void k0_smooth_first(Op0<R> op, int kz, int ntx, int nty, R omega,
                                                        const R* __restrict__ b, R* __restrict__ z1,
                                                        const int* __restrict__ iflag) {
   if (iflag[I_DONE]) return;
   const Tile T = tile_of(op.nx, op.ny, op.nz, ntx, nty, kz);
   auto X = [&](long, int, int, int) { return R(0); };
-  auto body = [&](long c, int, R, R, R dg) { z1[c] = omega * recip(dg) * b[c]; };
-  march<R, DIM, false, false>(op, T, X, body, NoPost());
+  auto pre = [&](long c) { return b[c]; };
+  auto body = [&](long c, int, R, R, R dg, R bc) { z1[c] = omega * recip(dg) * bc; };
+  march<R, DIM, false, false>(op, T, X, pre, body, NoPost());
 }
 
 // damped Jacobi xo = x + omega (b - K0 x) / diag; optional partial b.xo.
 // PRO: the sweep acts on x' = x + omc * P e, the coarse correction applied on
 // the fly (e is the next-coarser level's solution).
 template <class R, int DIM, bool PRO>
-__global__ __launch_bounds__(512) void k0_smooth(Op0<R> op, int kz, int ntx, int nty, R omega,
+__global__ __launch_bounds__(FX * FY) void k0_smooth(Op0<R> op, int kz, int ntx, int nty, R omega,
                                                  const R* __restrict__ b, const R* __restrict__ x,
                                                  R* __restrict__ xo, const R* __restrict__ e, int cnx, int cny,
                                                  R omc, double* __restrict__ part, const int* __restrict__ iflag) {
   if (iflag[I_DONE]) return;
   const Tile T = tile_of(op.nx, op.ny, op.nz, ntx, nty, kz);
   double acc = 0.0;
-  auto body = [&](long c, int, R xc, R Kx, R dg) {
-    const R bc = b[c];
+  auto pre = [&](long c) { return b[c]; };
+  auto body = [&](long c, int, R xc, R Kx, R dg, R bc) {
     const R xn = xc + omega * recip(dg) * (bc - Kx);
     xo[c] = xn;
     acc += (double)bc * (double)xn;
@@ -280,7 +300,7 @@ __global__ __launch_bounds__(512) void k0_smooth(Op0<R> op, int kz, int ntx, int
     if (!PRO) return x[c];
     return x[c] + omc * e[(long)(ii >> 1) + (long)cnx * ((long)(jj >> 1) + (long)cny * (DIM == 3 ? (kk >> 1) : 0))];
   };
-  march<R, DIM, true, false>(op, T, X, body, NoPost());
+  march<R, DIM, true, false>(op, T, X, pre, body, NoPost());
   if (part) write_partial(acc, part);
 }
 
@@ -288,7 +308,7 @@ __global__ __launch_bounds__(512) void k0_smooth(Op0<R> op, int kz, int ntx, int
 // sum goes through LDS, the pair of planes is summed in a register, and the
 // thread at the even corner of each 2x2(x2) group writes the coarse value.
 template <class R, int DIM>
-__global__ __launch_bounds__(512) void k0_resid_restrict(Op0<R> op, int kz, int ntx, int nty, int cnx, int cny,
+__global__ __launch_bounds__(FX * FY) void k0_resid_restrict(Op0<R> op, int kz, int ntx, int nty, int cnx, int cny,
                                                          const R* __restrict__ b, const R* __restrict__ x,
                                                          R* __restrict__ bc, const int* __restrict__ iflag) {
   if (iflag[I_DONE]) return;
@@ -297,7 +317,8 @@ __global__ __launch_bounds__(512) void k0_resid_restrict(Op0<R> op, int kz, int 
   const int tx = threadIdx.x, ty = threadIdx.y;
   R zsum = R(0);
   auto X = [&](long c, int, int, int) { return x[c]; };
-  auto body = [&](long c, int, R, R Kx, R) { sres[ty][tx] = b[c] - Kx; };
+  auto pre = [&](long c) { return b[c]; };
+  auto body = [&](long, int, R, R Kx, R, R bc) { sres[ty][tx] = bc - Kx; };
   auto post = [&](int k) {
     if (T.act && !(tx & 1) && !(ty & 1)) {
       // the partner cells of an even corner lie inside the tile (nx, ny even)
@@ -309,7 +330,7 @@ __global__ __launch_bounds__(512) void k0_resid_restrict(Op0<R> op, int kz, int 
       }
     }
   };
-  march<R, DIM, true, true>(op, T, X, body, post);
+  march<R, DIM, true, true>(op, T, X, pre, body, post);
 }
 
 struct Launch {
@@ -321,8 +342,8 @@ Launch plan(int nx, int ny, int nz) {
   L.ntx = (nx + FX - 1) / FX;
   L.nty = (ny + FY - 1) / FY;
   const int cols = L.ntx * L.nty;
-  // aim for >= 1024 blocks (4 per CU) with chunks of at least 8 planes
-  int ntz = std::max(1, std::min(nz, (1024 + cols - 1) / cols));
+  // aim for >= TCF_FINE_BLOCKS blocks (4 per CU) with chunks of at least 8 planes
+  int ntz = std::max(1, std::min(nz, (TCF_FINE_BLOCKS + cols - 1) / cols));
   int kz = (nz + ntz - 1) / ntz;
   if (kz < 8 && nz >= 8) kz = 8;
   if (nz > 1 && (kz & 1)) kz += 1;  // plane pairs of the restriction stay in one chunk
