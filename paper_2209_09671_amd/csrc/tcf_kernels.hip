@@ -74,89 +74,6 @@ __global__ __launch_bounds__(256) void k_geometry(KParams P, const R* __restrict
 }
 
 // ---------------------------------------------------------------------------
-// S4-S5: predictor for velocity component D on its interior faces.
-template <class R, int DIM, int D>
-__global__ __launch_bounds__(256) void k_predictor(KParams P, const R* __restrict__ a, const R* __restrict__ sk,
-                                                   const R* __restrict__ M, const R* __restrict__ u,
-                                                   const R* __restrict__ v, const R* __restrict__ w,
-                                                   R* __restrict__ out) {
-  const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
-  const int nx = P.nx, ny = P.ny, nz = P.nz;
-  const int fnx = nx + (D == 0), fny = ny + (D == 1);
-  if (i >= fnx || j >= fny) return;
-  const long fo = fidx<D>(i, j, k, nx, ny);
-  const int id[3] = {i, j, k};
-  const int nD = D == 0 ? nx : (D == 1 ? ny : nz);
-  if (id[D] == 0 || id[D] == nD) { out[fo] = R(0); return; }
-  const R* vel[3] = {u, v, w};
-  const R* ud = vel[D];
-  const R eps = R(P.weno_eps), ih = R(P.ih);
-  int L[3] = {i, j, k};
-  L[D] -= 1;
-  const long cL = cidx(L[0], L[1], L[2], nx, ny), cR = cidx(i, j, k, nx, ny);
-  R conv = R(0), visc = R(0);
-#pragma unroll
-  for (int e = 0; e < DIM; ++e) {
-    // 7 samples of component D along e at offsets -3..3
-    R q[7];
-#pragma unroll
-    for (int m = 0; m < 7; ++m) {
-      int o[3] = {0, 0, 0};
-      o[e] = m - 3;
-      q[m] = V_at<D, DIM>(ud, i + o[0], j + o[1], k + o[2], nx, ny, nz);
-    }
-    if (e == D) {
-      const R Ulo = R(0.5) * (q[2] + q[3]), Uhi = R(0.5) * (q[3] + q[4]);
-      const R Flo = Ulo * upwind(q, Ulo, eps), Fhi = Uhi * upwind(q + 1, Uhi, eps);
-      const R mL = mixp(a[cL], P.mu1, P.mu2), mR = mixp(a[cR], P.mu1, P.mu2);
-      const R tlo = R(2) * mL * (q[3] - q[2]) * ih, thi = R(2) * mR * (q[4] - q[3]) * ih;
-      conv += (Fhi - Flo) * ih;
-      visc += (thi - tlo) * ih;
-    } else {
-      R F[2], tau[2];
-#pragma unroll
-      for (int side = 0; side < 2; ++side) {
-        const int ef = id[e] + side;
-        int pL[3] = {L[0], L[1], L[2]}, pR[3] = {i, j, k};
-        pL[e] = ef;
-        pR[e] = ef;
-        R veL, veR;
-        if (e == 0) {
-          veL = V_at<0, DIM>(u, pL[0], pL[1], pL[2], nx, ny, nz);
-          veR = V_at<0, DIM>(u, pR[0], pR[1], pR[2], nx, ny, nz);
-        } else if (e == 1) {
-          veL = V_at<1, DIM>(v, pL[0], pL[1], pL[2], nx, ny, nz);
-          veR = V_at<1, DIM>(v, pR[0], pR[1], pR[2], nx, ny, nz);
-        } else {
-          veL = V_at<2, DIM>(w, pL[0], pL[1], pL[2], nx, ny, nz);
-          veR = V_at<2, DIM>(w, pR[0], pR[1], pR[2], nx, ny, nz);
-        }
-        const R Vb = R(0.5) * (veL + veR);
-        F[side] = Vb * upwind(q + side, Vb, eps);
-        const R dud = (q[3 + side] - q[2 + side]) * ih;
-        const R dve = (veR - veL) * ih;
-        int c1[3] = {L[0], L[1], L[2]}, c2[3] = {i, j, k}, c3[3] = {L[0], L[1], L[2]}, c4[3] = {i, j, k};
-        c1[e] = ef - 1;
-        c2[e] = ef - 1;
-        c3[e] = ef;
-        c4[e] = ef;
-        const R me = R(0.25) * (mixp(A_at<DIM>(a, c1[0], c1[1], c1[2], nx, ny, nz), P.mu1, P.mu2) +
-                                mixp(A_at<DIM>(a, c2[0], c2[1], c2[2], nx, ny, nz), P.mu1, P.mu2) +
-                                mixp(A_at<DIM>(a, c3[0], c3[1], c3[2], nx, ny, nz), P.mu1, P.mu2) +
-                                mixp(A_at<DIM>(a, c4[0], c4[1], c4[2], nx, ny, nz), P.mu1, P.mu2));
-        tau[side] = me * (dud + dve);
-      }
-      conv += (F[1] - F[0]) * ih;
-      visc += (tau[1] - tau[0]) * ih;
-    }
-  }
-  const R aL = a[cL], aR = a[cR];
-  const R fst = R(0.5) * (sk[cL] + sk[cR]) * (aR - aL) * ih + R(0.5) * (M[cL] + M[cR]);
-  const R rhof = R(0.5) * (mixp(aL, P.rho1, P.rho2) + mixp(aR, P.rho1, P.rho2));
-  out[fo] = ud[fo] + R(P.dt) * (-conv + (visc + fst) / rhof);
-}
-
-// ---------------------------------------------------------------------------
 // S6: b = D u* / dt (FP64), block partial sums of b.
 template <class R, int DIM>
 __global__ __launch_bounds__(256) void k_divergence(KParams P, const R* __restrict__ us, const R* __restrict__ vs,
@@ -761,19 +678,6 @@ void geometry(const KParams& P, hipStream_t s, const R* a, const R* T, R* sk, R*
 }
 
 template <class R>
-void predictor(const KParams& P, hipStream_t s, const R* a, const R* sk, const R* Mx, const R* My, const R* Mz,
-               const R* u, const R* v, const R* w, R* us, R* vs, R* ws) {
-  if (P.dim == 3) {
-    hipLaunchKernelGGL((k_predictor<R, 3, 0>), grid_for(P.nx + 1, P.ny, P.nz), blk(), 0, s, P, a, sk, Mx, u, v, w, us);
-    hipLaunchKernelGGL((k_predictor<R, 3, 1>), grid_for(P.nx, P.ny + 1, P.nz), blk(), 0, s, P, a, sk, My, u, v, w, vs);
-    hipLaunchKernelGGL((k_predictor<R, 3, 2>), grid_for(P.nx, P.ny, P.nz + 1), blk(), 0, s, P, a, sk, Mz, u, v, w, ws);
-  } else {
-    hipLaunchKernelGGL((k_predictor<R, 2, 0>), grid_for(P.nx + 1, P.ny, 1), blk(), 0, s, P, a, sk, Mx, u, v, w, us);
-    hipLaunchKernelGGL((k_predictor<R, 2, 1>), grid_for(P.nx, P.ny + 1, 1), blk(), 0, s, P, a, sk, My, u, v, w, vs);
-  }
-}
-
-template <class R>
 void divergence_rhs(const KParams& P, hipStream_t s, const R* us, const R* vs, const R* ws, double* b,
                     double* part) {
   dim3 g = grid_for(P.nx, P.ny, P.nz);
@@ -977,8 +881,6 @@ void zero_walls(const KParams& P, hipStream_t s, R* u, R* v, R* w) {
 // explicit instantiations
 #define TCF_INST(R)                                                                                               \
   template void geometry<R>(const KParams&, hipStream_t, const R*, const R*, R*, R*, R*, R*);                     \
-  template void predictor<R>(const KParams&, hipStream_t, const R*, const R*, const R*, const R*, const R*,       \
-                             const R*, const R*, const R*, R*, R*, R*);                                           \
   template void divergence_rhs<R>(const KParams&, hipStream_t, const R*, const R*, const R*, double*, double*);                                                                          \
   template void face_weights<R>(const KParams&, hipStream_t, const R*, double*, double*, double*, float*, float*, \
                                 float*);                                                                          \
