@@ -70,10 +70,16 @@ __device__ __forceinline__ R V_at(const R* __restrict__ uc, int i, int j, int k,
   return sg * uc[fidx<C>(id[0], id[1], id[2], nx, ny)];
 }
 
+// Linear material mix p1 + clamp(a, 0, 1) (p2 - p1).
 template <class R>
 __device__ __forceinline__ R mixp(R a, double p1, double p2) {
   a = a < R(0) ? R(0) : (a > R(1) ? R(1) : a);
   return R(p1) + a * R(p2 - p1);
+}
+// FP32: the clamp is one median-of-three (identical for every finite a).
+template <>
+__device__ __forceinline__ float mixp<float>(float a, double p1, double p2) {
+  return float(p1) + __builtin_amdgcn_fmed3f(a, 0.0f, 1.0f) * float(p2 - p1);
 }
 
 // WENO5-JS value at the right edge of the centre sample c of (a,b,c,d,e).

@@ -19,6 +19,7 @@
 // along D, stress = mu_edge (du_D/dx_E + du_E/dx_D) with mu_edge the mean of
 // the four adjacent cell viscosities).
 #include <algorithm>
+#include <type_traits>
 
 #include "tcf_device.h"
 #include "tcf_internal.h"
@@ -27,6 +28,10 @@ namespace tcf {
 namespace {
 
 using namespace dev;
+
+#ifndef TCF_PRED_PF
+#define TCF_PRED_PF 1
+#endif
 
 constexpr int TX = 64, TY = 8, H = 3;
 constexpr int SX = TX + 2 * H, SY = TY + 2 * H;
@@ -87,75 +92,145 @@ struct PredArgs {
   R* out;
 };
 
-// Cell value with 1-deep even ghosts (a clamp).
-template <class R>
-__device__ __forceinline__ R cellv(const R* __restrict__ f, int i, int j, int k, int nx, int ny, int nz) {
-  return f[cidx(clampi(i, nx), clampi(j, ny), clampi(k, nz), nx, ny)];
+// In-plane offsets of one in-plane flux position (direction E = x or y) of
+// the D-face (px, py): cells L and R on either side along D (for D = z the
+// same column, in planes k-1 and k), the same cells shifted by -1 along E,
+// and u_E on face p_E in the columns of L and R.  Cell indices outside the
+// domain take the 1-deep even ghost (a clamp); face indices along E are in
+// range for every producer.
+struct SiteXY {
+  unsigned cL, cR, sL, sR, eL, eR;
+};
+
+template <int D, int E>
+__device__ __forceinline__ SiteXY site_xy(int px, int py, int nx, int ny) {
+  const int cxL = px - (D == 0), cyL = py - (D == 1), cxR = px, cyR = py;
+  auto coff = [&](int x, int y) { return (unsigned)(clampi(x, nx) + nx * clampi(y, ny)); };
+  SiteXY s;
+  s.cL = coff(cxL, cyL);
+  s.cR = coff(cxR, cyR);
+  s.sL = coff(cxL - (E == 0), cyL - (E == 1));
+  s.sR = coff(cxR - (E == 0), cyR - (E == 1));
+  if (E == 0) {  // u on x-face px, cell rows of L and R
+    s.eL = (unsigned)(px + (nx + 1) * clampi(cyL, ny));
+    s.eR = (unsigned)(px + (nx + 1) * clampi(cyR, ny));
+  } else {  // v on y-face py, cell columns of L and R
+    s.eL = (unsigned)(clampi(cxL, nx) + nx * py);
+    s.eR = (unsigned)(clampi(cxR, nx) + nx * py);
+  }
+  return s;
 }
 
-// Low-side flux pair of direction E for the D-face p (face index along D,
-// cell indices along the other axes; along E the face p sits between the
-// flux position and p + e_E).  q0..q5 = u_D(p - 3 e_E .. p + 2 e_E).
-template <class R, int DIM, int D, int E>
-__device__ __forceinline__ void flux_lo(const KParams& P, const R* __restrict__ a, const R* __restrict__ ue, int pi,
-                                        int pj, int pk, R q0, R q1, R q2, R q3, R q4, R q5, R eps, R ih, R& F,
-                                        R& tau) {
-  const int nx = P.nx, ny = P.ny, nz = P.nz;
-  int cl[3] = {pi, pj, pk};
-  cl[D] -= 1;
-  if (E == D) {
-    const R U = R(0.5) * (q2 + q3);
-    F = U * upw1(q0, q1, q2, q3, q4, q5, U, eps);
-    const R mu = mixp(cellv(a, cl[0], cl[1], cl[2], nx, ny, nz), P.mu1, P.mu2);
-    tau = R(2) * mu * (q3 - q2) * ih;
-  } else {
-    const int cr[3] = {pi, pj, pk};
-    // u_E on its face p[E], in the cells on either side along D
-    int eL[3] = {cl[0], cl[1], cl[2]}, eR[3] = {cr[0], cr[1], cr[2]};
-    const int nn[3] = {nx, ny, nz};
-    eL[D] = clampi(eL[D], nn[D]);
-    eR[D] = clampi(eR[D], nn[D]);
-    const R vL = ue[fidx<E>(eL[0], eL[1], DIM == 3 ? eL[2] : 0, nx, ny)];
-    const R vR = ue[fidx<E>(eR[0], eR[1], DIM == 3 ? eR[2] : 0, nx, ny)];
-    const R Vb = R(0.5) * (vL + vR);
-    F = Vb * upw1(q0, q1, q2, q3, q4, q5, Vb, eps);
-    // the four cells around the edge: (L, R along D) x (p_E - 1, p_E)
-    int lm[3] = {cl[0], cl[1], cl[2]}, rm[3] = {cr[0], cr[1], cr[2]};
-    lm[E] -= 1;
-    rm[E] -= 1;
-    const R me = R(0.25) * (mixp(cellv(a, lm[0], lm[1], lm[2], nx, ny, nz), P.mu1, P.mu2) +
-                            mixp(cellv(a, rm[0], rm[1], rm[2], nx, ny, nz), P.mu1, P.mu2) +
-                            mixp(cellv(a, cl[0], cl[1], cl[2], nx, ny, nz), P.mu1, P.mu2) +
-                            mixp(cellv(a, cr[0], cr[1], cr[2], nx, ny, nz), P.mu1, P.mu2));
-    tau = me * ((q3 - q2) + (vR - vL)) * ih;
+// Per-plane operands of one in-plane flux item: the cells L and R (c, cR),
+// the same shifted by -1 along E (s, sR) and u_E in the columns of L and R.
+// For E = D only c (the cell between the two D-faces) is used.
+template <class R>
+struct FluxOps {
+  R c, cR, s, sR, vL, vR;
+};
+
+template <class R, int D, int E>
+__device__ __forceinline__ void load_ops(FluxOps<R>& o, bool on, const SiteXY& s, const R* __restrict__ aL,
+                                         const R* __restrict__ aR, const R* __restrict__ eLp,
+                                         const R* __restrict__ eRp) {
+  if (!on) return;
+  o.c = aL[s.cL];
+  if (E != D) {
+    o.cR = aR[s.cR];
+    o.s = aL[s.sL];
+    o.sR = aR[s.sR];
+    o.vL = eLp[s.eL];
+    o.vR = eRp[s.eR];
   }
 }
 
-template <class R, int DIM, int D>
-__global__ __launch_bounds__(512) void k_pred2(PredArgs<R, DIM, D> A, int kz, int ntx, int nty) {
+// Low-side flux pair (convective flux, viscous stress times h) of the
+// in-plane direction E; q0..q5 = u_D(p - 3 e_E .. p + 2 e_E).
+template <class R, int D, int E>
+__device__ __forceinline__ void flux_pair(const KParams& P, const FluxOps<R>& o, R q0, R q1, R q2, R q3, R q4, R q5,
+                                          R eps, R& F, R& tau) {
+  if (E == D) {  // cell-centred: advecting velocity from u_D, stress 2 mu du_D/dx_D
+    const R U = R(0.5) * (q2 + q3);
+    F = U * upw1(q0, q1, q2, q3, q4, q5, U, eps);
+    tau = R(2) * mixp(o.c, P.mu1, P.mu2) * (q3 - q2);
+  } else {  // edge: u_E averaged over L and R, mu over the four cells
+    const R Vb = R(0.5) * (o.vL + o.vR);
+    F = Vb * upw1(q0, q1, q2, q3, q4, q5, Vb, eps);
+    const R me = R(0.25) * (mixp(o.s, P.mu1, P.mu2) + mixp(o.sR, P.mu1, P.mu2) + mixp(o.c, P.mu1, P.mu2) +
+                            mixp(o.cR, P.mu1, P.mu2));
+    tau = me * ((q3 - q2) + (o.vR - o.vL));
+  }
+}
+
+// Per-plane operands of the face itself: z-edge (D != z: u_z on the high
+// z-face in the columns of L and R, alpha of plane k+1) or cell-centre
+// (D = z: alpha of the cell above the face), and the force operands.
+template <class R>
+struct FaceOps {
+  R wL, wR, apL, apR;  // D != z: w(k+1) at L, R and alpha(k+1) at L, R; D = z: apR = alpha(k)
+  R skL, skR, mL, mR;  // sigma*kappa and M_D in the cells L and R
+};
+
+// PF: the per-plane operands of the first flux items and of the face are
+// loaded one plane ahead (FP32); otherwise at the top of their own plane.
+template <class R, int DIM, int D, bool PF>
+__device__ __forceinline__ void pred_body(const PredArgs<R, DIM, D>& A, int kz, int ntx, int nty) {
   __shared__ R sU[2][SY][SX];
-  __shared__ R fyF[TY][TX];
-  __shared__ R fyT[TY][TX];
+  __shared__ R fxF[TY][TX + 1];
+  __shared__ R fxT[TY][TX + 1];
+  __shared__ R fyF[TY + 1][TX];
+  __shared__ R fyT[TY + 1][TX];
   const KParams& P = A.P;
   const R* __restrict__ a = A.a;
   const R* __restrict__ ud = D == 0 ? A.u : (D == 1 ? A.v : A.w);
   const int nx = P.nx, ny = P.ny, nz = P.nz;
-  // face-index extents of component D
-  const int fn0 = nx + (D == 0), fn1 = ny + (D == 1), fn2 = DIM == 3 ? nz + (D == 2) : 1;
+  // face-index extents of u_D; the tiles and the march cover faces 0..n-1
+  // along D, the last wall face is written by its neighbour
+  const int fn0 = nx + (D == 0), fn1 = ny + (D == 1);
+  const int mz = DIM == 3 ? nz : 1;
+  const size_t plc = (size_t)nx * ny, plu = (size_t)(nx + 1) * ny, plv = (size_t)nx * (ny + 1);
   const int tx = threadIdx.x, ty = threadIdx.y, tid = tx + TX * ty;
   const int nb = gridDim.x, bl = blockIdx.x;
   const int t = (nb % 8 == 0) ? (bl % 8) * (nb / 8) + bl / 8 : bl;
   const int tile_x = t % ntx, rr = t / ntx, tile_y = rr % nty, tile_z = rr / nty;
   const int i0 = tile_x * TX, j0 = tile_y * TY;
   const int i = i0 + tx, j = j0 + ty;
-  const int k0 = tile_z * kz, k1 = min(k0 + kz, fn2);
+  const int k0 = tile_z * kz, k1 = min(k0 + kz, mz);
   const bool act = i < fn0 && j < fn1;
   const bool cval = i < fn0 + H && j < fn1 + H && !(i >= fn0 && j >= fn1);
-  // low-side flux producers: E = x for columns up to the last flux position
-  // (x = nx), E = y likewise; the face's own row/column must be a valid one
-  const bool xlo = j < fn1 && i <= nx && (D != 0 || i >= 1);
-  const bool ylo = i < fn0 && j <= ny && (D != 1 || j >= 1);
   const R eps = R(P.weno_eps), ih = R(P.ih), dt = R(P.dt);
+  // x-direction flux items: per row the 64 faces' low sides and the last
+  // face's high side (65 positions, 520 per tile); every thread takes one,
+  // threads 64..71 one more
+  const int nxi = (tid >= 64 && tid < 72) ? 2 : 1;
+  int xr[2], xm[2];
+  bool xon[2];
+#pragma unroll
+  for (int qq = 0; qq < 2; ++qq) {
+    const int wi = qq == 0 ? tid : 512 + (tid - 64);
+    xr[qq] = wi / (TX + 1);
+    xm[qq] = wi % (TX + 1);
+    const int px = i0 + xm[qq], py = j0 + xr[qq];
+    xon[qq] = qq < nxi && xr[qq] < TY && py < fn1 && px <= nx && (D != 0 || px >= 1);
+  }
+  // offsets of the first items are kept; those of the second items (72
+  // threads) are recomputed where they are used
+  const SiteXY xs0 = site_xy<D, 0>(i0 + xm[0], j0 + xr[0], nx, ny);
+  // y-direction flux items: 9 rows of 64; threads 0..63 also take row 8
+  const int nyi = tid < 64 ? 2 : 1;
+  int yr[2];
+  bool yon[2];
+#pragma unroll
+  for (int qq = 0; qq < 2; ++qq) {
+    yr[qq] = qq == 0 ? ty : TY;
+    const int px = i, py = j0 + yr[qq];
+    yon[qq] = qq < nyi && px < fn0 && py <= ny && (D != 1 || py >= 1);
+  }
+  const SiteXY ys0 = site_xy<D, 1>(i, j0 + yr[0], nx, ny);
+  // own face: in-plane offsets of its cells L and R (also the columns of w
+  // on the z-edges)
+  const unsigned oL = (unsigned)(clampi(i - (D == 0), nx) + nx * clampi(j - (D == 1), ny));
+  const unsigned oR = (unsigned)(clampi(i, nx) + nx * clampi(j, ny));
   int hox = 0, hoy = 0;
   const bool hrole = tid < NHALO;
   if (hrole) halo_pos(tid, hox, hoy);
@@ -163,94 +238,238 @@ __global__ __launch_bounds__(512) void k_pred2(PredArgs<R, DIM, D> A, int kz, in
   const bool hvalid = hrole && hi >= -H && hi < fn0 + H && hj >= -H && hj < fn1 + H &&
                       (hi >= 0 && hi < fn0 ? true : (hj >= 0 && hj < fn1)) &&
                       (hj >= 0 && hj < fn1 ? true : (hi >= 0 && hi < fn0));
-  auto ldU = [&](int ii, int jj, int kk) { return V_at<D, DIM>(ud, ii, jj, kk, nx, ny, nz); };
+  // u_D with its ghost rules: odd reflection about the walls (normal: about
+  // the wall face, tangential: about the wall); the in-plane part is fixed
+  // per thread, the plane part is uniform
+  const size_t plD = (size_t)fn0 * fn1;
+  auto refl = [](int id, int n, bool normal, R& sg) {
+    if (id < 0) {
+      id = normal ? -id : -1 - id;
+      sg = -sg;
+    } else if (id > n - (normal ? 0 : 1)) {
+      id = normal ? 2 * n - id : 2 * n - 1 - id;
+      sg = -sg;
+    }
+    return id;
+  };
+  auto inplane = [&](int ii, int jj, R& sg) {
+    sg = R(1);
+    const int ri = refl(ii, nx, D == 0, sg), rj = refl(jj, ny, D == 1, sg);
+    return (unsigned)(ri + fn0 * rj);
+  };
+  R qsg, hsg;
+  const unsigned qoff = inplane(i, j, qsg);
+  const unsigned hoff = inplane(hi, hj, hsg);
+  auto ldU = [&](unsigned off, R sgxy, int kk) {
+    R sz = R(1);
+    const R* pl = DIM == 2 ? ud : ud + (size_t)refl(kk, nz, D == 2, sz) * plD;
+    return (sgxy * sz) * pl[off];
+  };
+  // cell plane kk with the 1-deep even ghost along z
+  auto cpl = [&](const R* f, int kk) { return f + (size_t)min(max(kk, 0), nz - 1) * plc; };
+  // operand loads of plane kk: flux item qq (first or second) and the face
+  auto load_items = [&](int kk, int qq, FluxOps<R>& xn, FluxOps<R>& yn) {
+    const int kL = kk - (D == 2);
+    const R* aL = cpl(a, kL);
+    const R* aR = cpl(a, kk);
+    const R* uL = A.u + (size_t)min(max(kL, 0), nz - 1) * plu;
+    const R* uR = A.u + (size_t)min(kk, nz - 1) * plu;
+    const R* vL = A.v + (size_t)min(max(kL, 0), nz - 1) * plv;
+    const R* vR = A.v + (size_t)min(kk, nz - 1) * plv;
+    if (qq == 0) {
+      load_ops<R, D, 0>(xn, xon[0], xs0, aL, aR, uL, uR);
+      load_ops<R, D, 1>(yn, yon[0], ys0, aL, aR, vL, vR);
+    } else {
+      if (xon[1]) load_ops<R, D, 0>(xn, true, site_xy<D, 0>(i0 + xm[1], j0 + xr[1], nx, ny), aL, aR, uL, uR);
+      if (yon[1]) load_ops<R, D, 1>(yn, true, site_xy<D, 1>(i, j0 + TY, nx, ny), aL, aR, vL, vR);
+    }
+  };
+  auto load_face = [&](int kk, FaceOps<R>& fn) {
+    const int kL = kk - (D == 2);
+    const R* aR = cpl(a, kk);
+    if (act) {
+      if (DIM == 3 && D != 2) {
+        const R* wk = A.w + (size_t)(kk + 1) * plc;
+        const R* ap = cpl(a, kk + 1);
+        fn.wL = wk[oL];
+        fn.wR = wk[oR];
+        fn.apL = ap[oL];
+        fn.apR = ap[oR];
+      } else {
+        fn.apR = aR[oR];
+      }
+      fn.skL = cpl(A.sk, kL)[oL];
+      fn.skR = cpl(A.sk, kk)[oR];
+      fn.mL = cpl(A.M, kL)[oL];
+      fn.mR = cpl(A.M, kk)[oR];
+    }
+  };
+  FluxOps<R> xo{}, yo{};
+  FaceOps<R> fo{};
+  if (PF) {
+    load_items(k0, 0, xo, yo);
+    load_face(k0, fo);
+  }
+  // alpha of the cells L and R in plane k (D != z), or of the cell below
+  // the face (D = z): carried from plane to plane
+  R acL = R(0), acR = R(0);
+  if (act) {
+    if (D != 2) {
+      acL = a[(size_t)k0 * plc + oL];
+      acR = a[(size_t)k0 * plc + oR];
+    } else {
+      acL = cpl(a, k0 - 1)[oR];
+    }
+  }
   R q[7];
 #pragma unroll
   for (int m = 0; m < 7; ++m) q[m] = R(0);
   if (cval) {
     if (DIM == 3) {
 #pragma unroll
-      for (int m = 0; m < 6; ++m) q[m + 1] = ldU(i, j, k0 - 3 + m);
+      for (int m = 0; m < 6; ++m) q[m + 1] = ldU(qoff, qsg, k0 - 3 + m);
     } else {
-      q[3] = ldU(i, j, 0);
+      q[3] = ldU(qoff, qsg, 0);
     }
   }
-  R hu = hvalid ? ldU(hi, hj, k0) : R(0);
+  R hu = hvalid ? ldU(hoff, hsg, k0) : R(0);
   R fz_lo = R(0), tz_lo = R(0);
   bool have_lo = false;
   int buf = 0;
-  const R* ue_z = A.w;
   for (int k = k0; k < k1; ++k) {
+    // operands: first items and face one plane ahead (PF) or now; second
+    // items (waves 0 and 1 only) now
+    FluxOps<R> xn{}, yn{}, x2{}, y2{};
+    FaceOps<R> fn{};
+    if (PF) {
+      if (k + 1 < k1) {
+        load_items(k + 1, 0, xn, yn);
+        load_face(k + 1, fn);
+      }
+    } else {
+      load_items(k, 0, xo, yo);
+      load_face(k, fo);
+    }
+    if (nxi > 1 || nyi > 1) load_items(k, 1, x2, y2);
     if (DIM == 3) {
 #pragma unroll
       for (int m = 0; m < 6; ++m) q[m] = q[m + 1];
-      q[6] = cval ? ldU(i, j, k + 3) : R(0);
+      q[6] = cval ? ldU(qoff, qsg, k + 3) : R(0);
     }
-    const R nhu = (hvalid && k + 1 < k1) ? ldU(hi, hj, k + 1) : R(0);
+    const R nhu = (hvalid && k + 1 < k1) ? ldU(hoff, hsg, k + 1) : R(0);
     if (cval) sU[buf][ty + H][tx + H] = q[3];
     if (hvalid) sU[buf][hoy][hox] = hu;
     __syncthreads();
-    const int X = tx + H, Y = ty + H;
-    // x: low pair by every producer, high pair from the next lane
-    R fx = R(0), tx_ = R(0);
-    if (xlo)
-      flux_lo<R, DIM, D, 0>(P, a, A.u, i, j, k, sU[buf][Y][X - 3], sU[buf][Y][X - 2], sU[buf][Y][X - 1],
-                            sU[buf][Y][X], sU[buf][Y][X + 1], sU[buf][Y][X + 2], eps, ih, fx, tx_);
-    R fy = R(0), ty_ = R(0);
-    if (ylo)
-      flux_lo<R, DIM, D, 1>(P, a, A.v, i, j, k, sU[buf][Y - 3][X], sU[buf][Y - 2][X], sU[buf][Y - 1][X],
-                            sU[buf][Y][X], sU[buf][Y + 1][X], sU[buf][Y + 2][X], eps, ih, fy, ty_);
-    fyF[ty][tx] = fy;
-    fyT[ty][tx] = ty_;
-    R fxh = __shfl_down(fx, 1, 64), txh = __shfl_down(tx_, 1, 64);
-    const bool interior = act && (D == 0 ? (i >= 1 && i < nx) : (D == 1 ? (j >= 1 && j < ny) : (k >= 1 && k < nz)));
-    if (interior && tx == TX - 1)
-      flux_lo<R, DIM, D, 0>(P, a, A.u, i + 1, j, k, sU[buf][Y][X - 2], sU[buf][Y][X - 1], sU[buf][Y][X],
-                            sU[buf][Y][X + 1], sU[buf][Y][X + 2], sU[buf][Y][X + 3], eps, ih, fxh, txh);
-    __syncthreads();
-    R fyh = R(0), tyh = R(0);
-    if (interior) {
-      if (ty < TY - 1) {
-        fyh = fyF[ty + 1][tx];
-        tyh = fyT[ty + 1][tx];
-      } else {
-        flux_lo<R, DIM, D, 1>(P, a, A.v, i, j + 1, k, sU[buf][Y - 2][X], sU[buf][Y - 1][X], sU[buf][Y][X],
-                              sU[buf][Y + 1][X], sU[buf][Y + 2][X], sU[buf][Y + 3][X], eps, ih, fyh, tyh);
+#pragma unroll
+    for (int qq = 0; qq < 2; ++qq) {
+      if (qq < nxi) {
+        R F = R(0), T_ = R(0);
+        if (xon[qq]) {
+          const R* rw = &sU[buf][xr[qq] + H][xm[qq]];
+          flux_pair<R, D, 0>(P, qq == 0 ? xo : x2, rw[0], rw[1], rw[2], rw[3], rw[4], rw[5], eps, F, T_);
+        }
+        if (xr[qq] < TY) {
+          fxF[xr[qq]][xm[qq]] = F;
+          fxT[xr[qq]][xm[qq]] = T_;
+        }
       }
     }
-    R conv = (fxh - fx) + (fyh - fy);
-    R visc = (txh - tx_) + (tyh - ty_);
-    if (DIM == 3) {
+#pragma unroll
+    for (int qq = 0; qq < 2; ++qq) {
+      if (qq < nyi) {
+        R F = R(0), T_ = R(0);
+        if (yon[qq]) {
+          const int Y = yr[qq] + H, X = tx + H;
+          flux_pair<R, D, 1>(P, qq == 0 ? yo : y2, sU[buf][Y - 3][X], sU[buf][Y - 2][X], sU[buf][Y - 1][X], sU[buf][Y][X],
+                             sU[buf][Y + 1][X], sU[buf][Y + 2][X], eps, F, T_);
+        }
+        fyF[yr[qq]][tx] = F;
+        fyT[yr[qq]][tx] = T_;
+      }
+    }
+    __syncthreads();
+    const bool interior = act && (D == 0 ? (i >= 1 && i < nx) : (D == 1 ? (j >= 1 && j < ny) : (k >= 1)));
+    R conv = R(0), visc = R(0);
+    // alpha of the cells L and R of this face
+    const R alL = acL, alR = D == 2 ? fo.apR : acR;
+    if (DIM == 3 && act) {
       // z: the high pair of this plane is the low pair of the next one
-      const bool zprod = act && (D != 2 || k < nz);
-      if (!have_lo && act && (D != 2 || k >= 1))
-        flux_lo<R, DIM, D, 2>(P, a, ue_z, i, j, k, q[0], q[1], q[2], q[3], q[4], q[5], eps, ih, fz_lo, tz_lo);
-      R fzh = R(0), tzh = R(0);
-      if (zprod)
-        flux_lo<R, DIM, D, 2>(P, a, ue_z, i, j, k + 1, q[1], q[2], q[3], q[4], q[5], q[6], eps, ih, fzh, tzh);
-      conv += fzh - fz_lo;
-      visc += tzh - tz_lo;
-      fz_lo = fzh;
-      tz_lo = tzh;
+      if (D == 2) {
+        if (!have_lo && k >= 1) {
+          const R U = R(0.5) * (q[2] + q[3]);
+          fz_lo = U * upw1(q[0], q[1], q[2], q[3], q[4], q[5], U, eps);
+          tz_lo = R(2) * mixp(acL, P.mu1, P.mu2) * (q[3] - q[2]);
+        }
+        const R U = R(0.5) * (q[3] + q[4]);
+        const R fzh = U * upw1(q[1], q[2], q[3], q[4], q[5], q[6], U, eps);
+        const R tzh = R(2) * mixp(fo.apR, P.mu1, P.mu2) * (q[4] - q[3]);
+        conv = fzh - fz_lo;
+        visc = tzh - tz_lo;
+        fz_lo = fzh;
+        tz_lo = tzh;
+      } else {
+        if (!have_lo) {
+          const R* wk = A.w + (size_t)k * plc;
+          const R* am = cpl(a, k - 1);
+          const R wL = wk[oL], wR = wk[oR];
+          const R Vb = R(0.5) * (wL + wR);
+          fz_lo = Vb * upw1(q[0], q[1], q[2], q[3], q[4], q[5], Vb, eps);
+          const R me = R(0.25) * (mixp(am[oL], P.mu1, P.mu2) + mixp(am[oR], P.mu1, P.mu2) +
+                                  mixp(acL, P.mu1, P.mu2) + mixp(acR, P.mu1, P.mu2));
+          tz_lo = me * ((q[3] - q[2]) + (wR - wL));
+        }
+        const R Vb = R(0.5) * (fo.wL + fo.wR);
+        const R fzh = Vb * upw1(q[1], q[2], q[3], q[4], q[5], q[6], Vb, eps);
+        const R me = R(0.25) * (mixp(acL, P.mu1, P.mu2) + mixp(acR, P.mu1, P.mu2) + mixp(fo.apL, P.mu1, P.mu2) +
+                                mixp(fo.apR, P.mu1, P.mu2));
+        const R tzh = me * ((q[4] - q[3]) + (fo.wR - fo.wL));
+        conv = fzh - fz_lo;
+        visc = tzh - tz_lo;
+        fz_lo = fzh;
+        tz_lo = tzh;
+      }
       have_lo = true;
     }
+    if (interior) {
+      conv += (fxF[ty][tx + 1] - fxF[ty][tx]) + (fyF[ty + 1][tx] - fyF[ty][tx]);
+      visc += (fxT[ty][tx + 1] - fxT[ty][tx]) + (fyT[ty + 1][tx] - fyT[ty][tx]);
+      const R fst = R(0.5) * (fo.skL + fo.skR) * (alR - alL) * ih + R(0.5) * (fo.mL + fo.mR);
+      const R rhof = R(0.5) * (mixp(alL, P.rho1, P.rho2) + mixp(alR, P.rho1, P.rho2));
+      A.out[fidx<D>(i, j, k, nx, ny)] = q[3] + dt * (-conv * ih + (visc * ih * ih + fst) / rhof);
+    } else if (act) {
+      A.out[fidx<D>(i, j, k, nx, ny)] = R(0);
+    }
+    // the wall face at the far end along D
     if (act) {
-      const long fo = fidx<D>(i, j, k, nx, ny);
-      R val = R(0);
-      if (interior) {
-        int cl[3] = {i, j, k};
-        cl[D] -= 1;
-        const long cL = cidx(cl[0], cl[1], cl[2], nx, ny), cR = cidx(i, j, k, nx, ny);
-        const R aL = a[cL], aR = a[cR];
-        const R fst = R(0.5) * (A.sk[cL] + A.sk[cR]) * (aR - aL) * ih + R(0.5) * (A.M[cL] + A.M[cR]);
-        const R rhof = R(0.5) * (mixp(aL, P.rho1, P.rho2) + mixp(aR, P.rho1, P.rho2));
-        val = q[3] + dt * (-conv * ih + (visc * ih + fst) / rhof);
-      }
-      A.out[fo] = val;
+      if (D == 0 && i == nx - 1) A.out[fidx<0>(nx, j, k, nx, ny)] = R(0);
+      if (D == 1 && j == ny - 1) A.out[fidx<1>(i, ny, k, nx, ny)] = R(0);
+      if (D == 2 && k == nz - 1) A.out[fidx<2>(i, j, nz, nx, ny)] = R(0);
+    }
+    // carry alpha to the next plane and rotate the prefetched operands
+    if (D != 2) {
+      acL = fo.apL;
+      acR = fo.apR;
+    } else {
+      acL = fo.apR;
+    }
+    if (PF) {
+      xo = xn;
+      yo = yn;
+      fo = fn;
     }
     hu = nhu;
     buf ^= 1;
   }
+}
+
+// FP32 runs two 512-thread blocks per CU (at most 128 VGPRs); FP64 one.
+template <class R, int DIM, int D>
+__global__ __launch_bounds__(512, 4) void k_pred2_f(PredArgs<R, DIM, D> A, int kz, int ntx, int nty) {
+  pred_body<R, DIM, D, true>(A, kz, ntx, nty);
+}
+template <class R, int DIM, int D>
+__global__ __launch_bounds__(512) void k_pred2_d(PredArgs<R, DIM, D> A, int kz, int ntx, int nty) {
+  pred_body<R, DIM, D, false>(A, kz, ntx, nty);
 }
 
 int pred_plan(int fn0, int fn1, int fn2, int* kz, int* ntx, int* nty) {
@@ -268,11 +487,13 @@ int pred_plan(int fn0, int fn1, int fn2, int* kz, int* ntx, int* nty) {
 template <class R, int DIM, int D>
 void launch_pred(const KParams& P, hipStream_t s, const R* a, const R* sk, const R* M, const R* u, const R* v,
                  const R* w, R* out) {
-  const int fn0 = P.nx + (D == 0), fn1 = P.ny + (D == 1), fn2 = DIM == 3 ? P.nz + (D == 2) : 1;
   int kz, ntx, nty;
-  const int nb = pred_plan(fn0, fn1, fn2, &kz, &ntx, &nty);
+  const int nb = pred_plan(P.nx, P.ny, DIM == 3 ? P.nz : 1, &kz, &ntx, &nty);
   PredArgs<R, DIM, D> A{P, a, sk, M, u, v, w, out};
-  hipLaunchKernelGGL((k_pred2<R, DIM, D>), dim3(nb), dim3(TX, TY), 0, s, A, kz, ntx, nty);
+  if (std::is_same<R, float>::value && TCF_PRED_PF)
+    hipLaunchKernelGGL((k_pred2_f<R, DIM, D>), dim3(nb), dim3(TX, TY), 0, s, A, kz, ntx, nty);
+  else
+    hipLaunchKernelGGL((k_pred2_d<R, DIM, D>), dim3(nb), dim3(TX, TY), 0, s, A, kz, ntx, nty);
 }
 
 }  // namespace

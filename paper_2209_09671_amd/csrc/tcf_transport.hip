@@ -119,6 +119,15 @@ __global__ __launch_bounds__(512) void k_transport2(KParams P, int kz, int ntx, 
     ha = ld_a(hi, hj, k0);
     hT = ld_T(hi, hj, k0);
   }
+  // Gaussian surface heat flux of the column (x, y, t), FP64, once per column
+  R qcol = R(0);
+  if (P.qP != 0.0 && act) {
+    const double xl = P.qx0 + P.qvx * P.t, yl = P.qy0 + P.qvy * P.t;
+    const double x = (i + 0.5) * P.h, y = (j + 0.5) * P.h;
+    const double r2 = (x - xl) * (x - xl) + (y - yl) * (y - yl);
+    const double R2 = P.qr * P.qr;
+    qcol = R(2.0 * P.qP / (M_PI * R2) * exp(-2.0 * r2 / R2));
+  }
   R fza_lo = R(0), fzt_lo = R(0);  // low z-face flux carried between planes
   bool have_lo = false;
   int buf = 0;
@@ -248,11 +257,7 @@ __global__ __launch_bounds__(512) void k_transport2(KParams P, int kz, int ntx, 
         const R g2 = gx * gx + gy * gy + gz * gz;
         const R ne = R(P.neps);
         const R ds = g2 / (sqrt(g2 + ne * ne) + ne);
-        const double xl = P.qx0 + P.qvx * P.t, yl = P.qy0 + P.qvy * P.t;
-        const double x = (i + 0.5) * P.h, y = (j + 0.5) * P.h;
-        const double r2 = (x - xl) * (x - xl) + (y - yl) * (y - yl);
-        const double R2 = P.qr * P.qr;
-        src = R(2.0 * P.qP / (M_PI * R2) * exp(-2.0 * r2 / R2)) * ds;
+        src = qcol * ds;
       }
       const R LT = -divt * ih + (cond + src) / mixp(ac, P.rhocp1, P.rhocp2);
       ao[c] = cb * ab[c] + ci * (ac + dt * La);
