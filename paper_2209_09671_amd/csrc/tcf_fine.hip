@@ -41,6 +41,10 @@ __device__ __forceinline__ R rho0(const Op0<R>& op, R a) {
   a = a < R(0) ? R(0) : (a > R(1) ? R(1) : a);
   return R(op.rho1) + a * R(op.drho);
 }
+template <>
+__device__ __forceinline__ float rho0<float>(const Op0<float>& op, float a) {
+  return float(op.rho1) + __builtin_amdgcn_fmed3f(a, 0.0f, 1.0f) * float(op.drho);
+}
 __device__ __forceinline__ double coef(double c2, double s) { return c2 / s; }
 __device__ __forceinline__ float coef(float c2, float s) { return c2 * __builtin_amdgcn_rcpf(s); }
 __device__ __forceinline__ double recip(double s) { return 1.0 / s; }
@@ -71,20 +75,36 @@ constexpr int LX = FX + 2, LY = FY + 2;
 
 // face weight between cells with densities rc and rn
 template <class R>
-__device__ __forceinline__ R wface(const Op0<R>& op, R rc, R an) {
-  return coef(R(op.c2), rc + rho0(op, an));
+__device__ __forceinline__ R wface(const Op0<R>& op, R rc, R rn) {
+  return coef(R(op.c2), rc + rn);
 }
 
-// Plane march over a z-chunk with one streamed field x (loader X) and the
-// volume fraction.  Per plane: the tile and its one-cell halo go to a
+// Plane march over a z-chunk with one streamed field x and the volume
+// fraction.  Per plane: the tile and its one-cell halo go to a
 // double-buffered LDS plane (one barrier per plane), the z-neighbours stay
-// in registers, and the centre and halo values are prefetched two planes
-// ahead so that loads stay in flight across the barriers.  For each active
-// cell body(c, k, xc, Kx, dg) receives K0 x and the diagonal.  With POST, all
-// threads then pass a second barrier and post(k) runs (the restriction).
-template <class R, int DIM, bool HASX, bool POST, class XL, class PRE, class BODY, class PST>
-__device__ __forceinline__ void march(const Op0<R>& op, const Tile& T, const XL& X, const PRE& pre, const BODY& body,
-                                      const PST& post) {
+// in registers.  Loads run three planes ahead (per-cell operands pre(c) two
+// planes ahead) and are issued unconditionally, with the plane index clamped
+// to the chunk (a clamped load re-reads a cached plane and is not used), so
+// the number of loads in flight is the same on every path and the waits for
+// a plane's data do not drain the later prefetches.  The planes rotate
+// through five register slots by renaming (the loop is unrolled by five), so
+// no value is copied while its load is in flight; raw loads (xld) are
+// combined (xval) and alpha becomes a density only when the plane is used.
+// The weight of the face to the next plane is carried to it.  For each
+// active cell body(c, k, xc, Kx, dg, pv) receives K0 x, the diagonal and
+// pv = pre(c).  With POST, all threads then pass a second barrier and
+// post(k) runs (the restriction).
+template <class R, class XR, class PV>
+struct Slot {
+  XR xr, hyr, hxr;   // raw loads of x: centre and halo
+  R a, gy, gx;       // alpha: centre and halo
+  PV pv;             // per-cell operands
+  R xv, rho;         // x and density of the centre, once the plane is next
+};
+
+template <class R, int DIM, bool HASX, bool POST, class XLD, class XVAL, class PRE, class BODY, class PST>
+__device__ __forceinline__ void march(const Op0<R>& op, const Tile& T, const XLD& xld, const XVAL& xval,
+                                      const PRE& pre, const BODY& body, const PST& post) {
   __shared__ R sx[2][LY][LX];
   __shared__ R sa[2][LY][LX];
   const int tx = threadIdx.x, ty = threadIdx.y;
@@ -95,119 +115,144 @@ __device__ __forceinline__ void march(const Op0<R>& op, const Tile& T, const XL&
   const bool hasy = T.act && yr != 0 && T.j + yr >= 0 && T.j + yr < ny;
   const bool hasx = T.act && xr != 0 && T.i + xr >= 0 && T.i + xr < nx;
   const long col = T.act ? (long)T.i + (long)nx * T.j : 0;
-  const long oy = (long)yr * nx;
-  // plane slots: 0 = k-1, 1 = k, 2 = k+1, 3 = k+2 (centre); halo slots 1..3
-  R x0 = R(0), x1 = R(0), x2 = R(0), x3 = R(0), a0 = R(0), a1 = R(0), a2 = R(0), a3 = R(0);
-  R hy1 = R(0), hy2 = R(0), hy3 = R(0), hx1 = R(0), hx2 = R(0), hx3 = R(0);
-  R gy1 = R(0), gy2 = R(0), gy3 = R(0), gx1 = R(0), gx2 = R(0), gx3 = R(0);  // halo of alpha
-  auto load_centre = [&](int k, R& xv, R& av) {
-    if (T.act && k >= 0 && k < nz && (DIM == 3 || k == 0)) {
-      const long c = col + pl * k;
-      if (HASX) xv = X(c, T.i, T.j, k);
-      av = op.a[c];
-    } else {
-      xv = R(0);
-      av = R(0);
-    }
-  };
-  auto load_halo = [&](int k, R& hy, R& hx, R& gy, R& gx) {
-    if (k < T.k1) {
-      const long c = col + pl * k;
-      if (hasy) {
-        if (HASX) hy = X(c + oy, T.i, T.j + yr, k);
-        gy = op.a[c + oy];
-      }
-      if (hasx) {
-        if (HASX) hx = X(c + xr, T.i + xr, T.j, k);
-        gx = op.a[c + xr];
-      }
-    }
-  };
-  // per-cell operands of the body (b, CG vectors), prefetched one plane ahead
+  const long oyc = hasy ? (long)yr * nx : 0, oxc = hasx ? xr : 0;  // halo offset, own cell if none
+  const int hyj = hasy ? T.j + yr : T.j, hxi = hasx ? T.i + xr : T.i;
+  using XR = decltype(xld(0L, 0, 0, 0));
   using PV = decltype(pre(0L));
-  PV pv1 = T.act ? pre(col + pl * T.k0) : PV{};
-  if (DIM == 3) load_centre(T.k0 - 1, x0, a0);
-  load_centre(T.k0, x1, a1);
-  load_halo(T.k0, hy1, hx1, gy1, gx1);
-  if (DIM == 3) {
-    load_centre(T.k0 + 1, x2, a2);
-    load_halo(T.k0 + 1, hy2, hx2, gy2, gx2);
-  }
-  int buf = 0;
-  for (int k = T.k0; k < T.k1; ++k) {
-    PV pv2 = (T.act && k + 1 < T.k1) ? pre(col + pl * (k + 1)) : PV{};
-    if (DIM == 3) {
-      load_centre(k + 2, x3, a3);
-      load_halo(k + 2, hy3, hx3, gy3, gx3);
+  using S = Slot<R, XR, PV>;
+  // last plane whose centre is read (the z-neighbour of the chunk's last
+  // plane), last plane of the chunk
+  const int kc = DIM == 3 ? min(T.k1, nz - 1) : 0;
+  const int kh = max(T.k1 - 1, T.k0);
+  auto load_centre = [&](int k, S& s) {
+    const int kk = min(max(k, 0), kc);
+    const long c = col + pl * kk;
+    if (HASX) s.xr = xld(c, T.i, T.j, kk);
+    s.a = op.a[c];
+  };
+  auto load_halo = [&](int k, S& s) {
+    const int kk = min(k, kh);
+    const long c = col + pl * kk;
+    if (HASX) {
+      s.hyr = xld(c + oyc, T.i, hyj, kk);
+      s.hxr = xld(c + oxc, hxi, T.j, kk);
     }
+    s.gy = op.a[c + oyc];
+    s.gx = op.a[c + oxc];
+  };
+  auto load_pv = [&](int k, S& s) { s.pv = pre(col + pl * min(k, kh)); };
+  auto finish = [&](S& s) {  // the plane is about to be used
+    if (HASX) s.xv = xval(s.xr);
+    s.rho = rho0(op, s.a);
+  };
+  S A{}, B{}, C{}, D{}, E{};  // planes k0-1, k0, k0+1, k0+2; E receives k0+3
+  if (DIM == 3) load_centre(T.k0 - 1, A);
+  load_centre(T.k0, B);
+  load_halo(T.k0, B);
+  load_pv(T.k0, B);
+  if (DIM == 3) {
+    load_centre(T.k0 + 1, C);
+    load_halo(T.k0 + 1, C);
+    load_pv(T.k0 + 1, C);
+    load_centre(T.k0 + 2, D);
+    load_halo(T.k0 + 2, D);
+  }
+  if (DIM == 3) finish(A);
+  finish(B);
+  R wz = R(0);  // weight of the face between planes k-1 and k
+  if (DIM == 3 && T.act && T.k0 > 0) wz = wface(op, B.rho, A.rho);
+  // one plane; M = k-1, Cc = k, P1 = k+1, P2 = k+2, P3 receives k+3
+  auto step = [&](int k, S& M, S& Cc, S& P1, S& P2, S& P3) {
+    if (DIM == 3) {
+      load_centre(k + 3, P3);
+      load_halo(k + 3, P3);
+      load_pv(k + 2, P2);
+      finish(P1);
+    }
+    const int buf = k & 1;
+    const R rc = Cc.rho;
     if (T.act) {
-      if (HASX) sx[buf][ty + 1][tx + 1] = x1;
-      sa[buf][ty + 1][tx + 1] = a1;
+      if (HASX) sx[buf][ty + 1][tx + 1] = Cc.xv;
+      sa[buf][ty + 1][tx + 1] = rc;
       if (hasy) {
-        if (HASX) sx[buf][ty + 1 + yr][tx + 1] = hy1;
-        sa[buf][ty + 1 + yr][tx + 1] = gy1;
+        if (HASX) sx[buf][ty + 1 + yr][tx + 1] = xval(Cc.hyr);
+        sa[buf][ty + 1 + yr][tx + 1] = rho0(op, Cc.gy);
       }
       if (hasx) {
-        if (HASX) sx[buf][ty + 1][tx + 1 + xr] = hx1;
-        sa[buf][ty + 1][tx + 1 + xr] = gx1;
+        if (HASX) sx[buf][ty + 1][tx + 1 + xr] = xval(Cc.hxr);
+        sa[buf][ty + 1][tx + 1 + xr] = rho0(op, Cc.gx);
       }
     }
     __syncthreads();
     if (T.act) {
       const long c = col + pl * k;
-      const R rc = rho0(op, a1);
       R s = R(0), d = R(0);
       if (T.i > 0) {
         const R w = wface(op, rc, sa[buf][ty + 1][tx]);
-        if (HASX) s += w * (x1 - sx[buf][ty + 1][tx]);
+        if (HASX) s += w * (Cc.xv - sx[buf][ty + 1][tx]);
         d += w;
       }
       if (T.i < nx - 1) {
         const R w = wface(op, rc, sa[buf][ty + 1][tx + 2]);
-        if (HASX) s += w * (x1 - sx[buf][ty + 1][tx + 2]);
+        if (HASX) s += w * (Cc.xv - sx[buf][ty + 1][tx + 2]);
         d += w;
       }
       if (T.j > 0) {
         const R w = wface(op, rc, sa[buf][ty][tx + 1]);
-        if (HASX) s += w * (x1 - sx[buf][ty][tx + 1]);
+        if (HASX) s += w * (Cc.xv - sx[buf][ty][tx + 1]);
         d += w;
       }
       if (T.j < ny - 1) {
         const R w = wface(op, rc, sa[buf][ty + 2][tx + 1]);
-        if (HASX) s += w * (x1 - sx[buf][ty + 2][tx + 1]);
+        if (HASX) s += w * (Cc.xv - sx[buf][ty + 2][tx + 1]);
         d += w;
       }
       if (DIM == 3) {
         if (k > 0) {
-          const R w = wface(op, rc, a0);
-          if (HASX) s += w * (x1 - x0);
-          d += w;
+          if (HASX) s += wz * (Cc.xv - M.xv);
+          d += wz;
         }
+        wz = R(0);
         if (k < nz - 1) {
-          const R w = wface(op, rc, a2);
-          if (HASX) s += w * (x1 - x2);
-          d += w;
+          wz = wface(op, rc, P1.rho);
+          if (HASX) s += wz * (Cc.xv - P1.xv);
+          d += wz;
         }
       }
-      body(c, k, x1, s, d, pv1);
+      body(c, k, Cc.xv, s, d, Cc.pv);
     }
     if (POST) {
       __syncthreads();
       post(k);
     }
-    pv1 = pv2;
-    x0 = x1; x1 = x2; x2 = x3;
-    a0 = a1; a1 = a2; a2 = a3;
-    hy1 = hy2; hy2 = hy3; hx1 = hx2; hx2 = hx3;
-    gy1 = gy2; gy2 = gy3; gx1 = gx2; gx2 = gx3;
-    buf ^= 1;
+  };
+  int k = T.k0;
+  for (; k + 5 <= T.k1; k += 5) {
+    step(k, A, B, C, D, E);
+    step(k + 1, B, C, D, E, A);
+    step(k + 2, C, D, E, A, B);
+    step(k + 3, D, E, A, B, C);
+    step(k + 4, E, A, B, C, D);
   }
+  const int rem = T.k1 - k;
+  if (rem > 0) step(k, A, B, C, D, E);
+  if (rem > 1) step(k + 1, B, C, D, E, A);
+  if (rem > 2) step(k + 2, C, D, E, A, B);
+  if (rem > 3) step(k + 3, D, E, A, B, C);
 }
 
 struct Empty {};
 template <class R>
+struct Vec2 {
+  R a, b;
+};
+template <class R>
 struct Vec4 {
   R a, b, c, d;
+};
+template <class R>
+struct Ident {
+  __device__ R operator()(R v) const { return v; }
 };
 
 struct NoPost {
@@ -228,8 +273,11 @@ __global__ __launch_bounds__(FX * FY) void k0_spmv_upd(Op0<R> op, int kz, int nt
                                                    double* __restrict__ part, const int* __restrict__ iflag) {
   if (iflag[I_DONE]) return;
   const Tile T = tile_of(op.nx, op.ny, op.nz, ntx, nty, kz);
+  // on the first iteration d' = z + 0 z (the old direction is not read)
   const R beta = first ? R(0) : R(scal[S_BETA]);
-  auto X = [&](long c, int, int, int) { return first ? z[c] : z[c] + beta * dold[c]; };
+  const R* __restrict__ dsrc = first ? z : dold;
+  auto X = [&](long c, int, int, int) { return Vec2<R>{z[c], dsrc[c]}; };
+  auto XV = [&](const Vec2<R>& v) { return v.a + beta * v.b; };
   double acc = 0.0;
   auto pre = [&](long) { return Empty{}; };
   auto body = [&](long c, int, R xc, R Kx, R, const Empty&) {
@@ -237,7 +285,7 @@ __global__ __launch_bounds__(FX * FY) void k0_spmv_upd(Op0<R> op, int kz, int nt
     q[c] = Kx;
     acc += (double)xc * (double)Kx;
   };
-  march<R, DIM, true, false>(op, T, X, pre, body, NoPost());
+  march<R, DIM, true, false>(op, T, X, XV, pre, body, NoPost());
   write_partial(acc, part);
 }
 
@@ -255,6 +303,7 @@ __global__ __launch_bounds__(FX * FY) void k0_update_smooth(Op0<R> op, int kz, i
   double acc = 0.0;
   auto X = [&](long, int, int, int) { return R(0); };
   auto pre = [&](long c) { return Vec4<R>{x[c], r[c], d[c], q[c]}; };
+  const Ident<R> XV;
   auto body = [&](long c, int, R, R, R dg, const Vec4<R>& v) {
     x[c] = v.a + al * v.c;
     const R rn = v.b - al * v.d;
@@ -262,7 +311,7 @@ __global__ __launch_bounds__(FX * FY) void k0_update_smooth(Op0<R> op, int kz, i
     acc += (double)rn * (double)rn;
     z1[c] = omega * recip(dg) * rn;
   };
-  march<R, DIM, false, false>(op, T, X, pre, body, NoPost());
+  march<R, DIM, false, false>(op, T, X, XV, pre, body, NoPost());
   write_partial(acc, part);
 }
 
@@ -274,9 +323,10 @@ __global__ __launch_bounds__(FX * FY) void k0_smooth_first(Op0<R> op, int kz, in
   if (iflag[I_DONE]) return;
   const Tile T = tile_of(op.nx, op.ny, op.nz, ntx, nty, kz);
   auto X = [&](long, int, int, int) { return R(0); };
+  const Ident<R> XV;
   auto pre = [&](long c) { return b[c]; };
   auto body = [&](long c, int, R, R, R dg, R bc) { z1[c] = omega * recip(dg) * bc; };
-  march<R, DIM, false, false>(op, T, X, pre, body, NoPost());
+  march<R, DIM, false, false>(op, T, X, XV, pre, body, NoPost());
 }
 
 // damped Jacobi xo = x + omega (b - K0 x) / diag; optional partial b.xo.
@@ -297,10 +347,12 @@ __global__ __launch_bounds__(FX * FY) void k0_smooth(Op0<R> op, int kz, int ntx,
     acc += (double)bc * (double)xn;
   };
   auto X = [&](long c, int ii, int jj, int kk) {
-    if (!PRO) return x[c];
-    return x[c] + omc * e[(long)(ii >> 1) + (long)cnx * ((long)(jj >> 1) + (long)cny * (DIM == 3 ? (kk >> 1) : 0))];
+    if (!PRO) return Vec2<R>{x[c], R(0)};
+    return Vec2<R>{x[c],
+                   e[(long)(ii >> 1) + (long)cnx * ((long)(jj >> 1) + (long)cny * (DIM == 3 ? (kk >> 1) : 0))]};
   };
-  march<R, DIM, true, false>(op, T, X, pre, body, NoPost());
+  auto XV = [&](const Vec2<R>& v) { return PRO ? v.a + omc * v.b : v.a; };
+  march<R, DIM, true, false>(op, T, X, XV, pre, body, NoPost());
   if (part) write_partial(acc, part);
 }
 
@@ -317,6 +369,7 @@ __global__ __launch_bounds__(FX * FY) void k0_resid_restrict(Op0<R> op, int kz, 
   const int tx = threadIdx.x, ty = threadIdx.y;
   R zsum = R(0);
   auto X = [&](long c, int, int, int) { return x[c]; };
+  const Ident<R> XV;
   auto pre = [&](long c) { return b[c]; };
   auto body = [&](long, int, R, R Kx, R, R bc) { sres[ty][tx] = bc - Kx; };
   auto post = [&](int k) {
@@ -330,7 +383,7 @@ __global__ __launch_bounds__(FX * FY) void k0_resid_restrict(Op0<R> op, int kz, 
       }
     }
   };
-  march<R, DIM, true, true>(op, T, X, pre, body, post);
+  march<R, DIM, true, true>(op, T, X, XV, pre, body, post);
 }
 
 struct Launch {
