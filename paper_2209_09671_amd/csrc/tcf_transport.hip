@@ -64,6 +64,44 @@ __device__ __forceinline__ void halo_pos(int h, int& ox, int& oy) {
   }
 }
 
+// Ghost map of a column (ii, jj): in-plane offset of its mirror cell (even
+// reflection) and the affine map T = s raw + t of the Dirichlet walls it
+// lies beyond (each such wall maps v to 2 T_w - v).
+template <class R>
+struct ColMap {
+  unsigned off;
+  R s, t;
+};
+
+template <class R>
+__device__ __forceinline__ ColMap<R> col_map(const KParams& P, int ii, int jj, bool valid) {
+  ColMap<R> m{0u, R(1), R(0)};
+  if (!valid) return m;
+  auto flip = [&](int side) {
+    if (P.Tbc[side]) {
+      m.s = -m.s;
+      m.t = R(2) * R(P.Tw[side]) - m.t;
+    }
+  };
+  int ri = ii, rj = jj;
+  if (ii < 0) {
+    ri = -1 - ii;
+    flip(0);
+  } else if (ii >= P.nx) {
+    ri = 2 * P.nx - 1 - ii;
+    flip(1);
+  }
+  if (jj < 0) {
+    rj = -1 - jj;
+    flip(2);
+  } else if (jj >= P.ny) {
+    rj = 2 * P.ny - 1 - jj;
+    flip(3);
+  }
+  m.off = (unsigned)(ri + P.nx * rj);
+  return m;
+}
+
 template <class R, int DIM>
 __global__ __launch_bounds__(512) void k_transport2(KParams P, int kz, int ntx, int nty, const R* __restrict__ a,
                                                     const R* __restrict__ T, const R* ab, const R* Tb,
@@ -87,7 +125,7 @@ __global__ __launch_bounds__(512) void k_transport2(KParams P, int kz, int ntx, 
   // stencils of the last active cells read (corners are never read)
   const bool cval = i < nx + H && j < ny + H && !(i >= nx && j >= ny);
   const R eps = R(P.weno_eps), ih = R(P.ih), dt = R(P.dt);
-  const long pl = (long)nx * ny;
+  const size_t pl = (size_t)nx * ny, plu = (size_t)(nx + 1) * ny, plv = (size_t)nx * (ny + 1);
   // halo role of this thread
   int hox = 0, hoy = 0;
   const bool hrole = tid < NHALO;
@@ -95,30 +133,55 @@ __global__ __launch_bounds__(512) void k_transport2(KParams P, int kz, int ntx, 
   const int hi = i0 + hox - H, hj = j0 + hoy - H;
   const bool hvalid = hrole && hi >= -H && hi < nx + H && hj >= -H && hj < ny + H &&
                       (hi >= 0 && hi < nx ? true : (hj >= 0 && hj < ny)) && (hj >= 0 && hj < ny ? true : (hi >= 0 && hi < nx));
-  auto ld_a = [&](int ii, int jj, int kk) { return A_at<DIM>(a, ii, jj, kk, nx, ny, nz); };
-  auto ld_T = [&](int ii, int jj, int kk) { return T_at<DIM>(T, ii, jj, kk, P); };
+  // Every load below is issued unconditionally (positions a thread does not
+  // need map to a valid cell, planes are clamped or reflected), so the count
+  // of loads in flight is path independent and waiting for one plane's data
+  // does not drain the prefetches of the next.  Loaded values are consumed
+  // one plane after their load.
+  const ColMap<R> cm = col_map<R>(P, i, j, cval);
+  const ColMap<R> hm = col_map<R>(P, hi, hj, hvalid);
+  auto zrefl = [&](int kk) { return DIM == 3 ? (kk < 0 ? -1 - kk : (kk >= nz ? 2 * nz - 1 - kk : kk)) : 0; };
+  auto tval = [&](const ColMap<R>& m, R raw, int kk) {
+    R v0 = m.s * raw + m.t;
+    if (DIM == 3) {
+      if (kk < 0 && P.Tbc[4]) v0 = R(2) * R(P.Tw[4]) - v0;
+      if (kk >= nz && P.Tbc[5]) v0 = R(2) * R(P.Tw[5]) - v0;
+    }
+    return v0;
+  };
+  auto ldA = [&](unsigned off, int kk) { return a[off + (size_t)zrefl(kk) * pl]; };
+  auto ldT = [&](unsigned off, int kk) { return T[off + (size_t)zrefl(kk) * pl]; };
+  // in-plane offsets of the face velocities (low and high faces) and cells
+  const int ic = min(i, nx - 1), jc = min(j, ny - 1);
+  const unsigned uoL = (unsigned)(min(i, nx) + (nx + 1) * jc), uoH = (unsigned)(min(i + 1, nx) + (nx + 1) * jc);
+  const unsigned voL = (unsigned)(ic + nx * min(j, ny)), voH = (unsigned)(ic + nx * min(j + 1, ny));
+  const unsigned co = (unsigned)(ic + nx * jc);
   // column queues (k-3 .. k+3); in 2D only the centre is used
   R qa[7], qt[7];
   for (int m = 0; m < 7; ++m) {
     qa[m] = R(0);
     qt[m] = R(0);
   }
-  if (cval) {
-    if (DIM == 3) {
-      for (int m = 0; m < 6; ++m) {
-        qa[m + 1] = ld_a(i, j, k0 - 3 + m);
-        qt[m + 1] = ld_T(i, j, k0 - 3 + m);
-      }
-    } else {
-      qa[3] = ld_a(i, j, 0);
-      qt[3] = ld_T(i, j, 0);
+  const int kq = min(k1 + 2, nz + 2);  // last plane the queues need
+  R ia = R(0), iT = R(0);              // plane k+3 of the column, in flight
+  if (DIM == 3) {
+    for (int m = 0; m < 6; ++m) {
+      qa[m + 1] = ldA(cm.off, k0 - 3 + m);
+      qt[m + 1] = tval(cm, ldT(cm.off, k0 - 3 + m), k0 - 3 + m);
     }
+    ia = ldA(cm.off, min(k0 + 3, kq));
+    iT = ldT(cm.off, min(k0 + 3, kq));
+  } else {
+    qa[3] = ldA(cm.off, 0);
+    qt[3] = tval(cm, ldT(cm.off, 0), 0);
   }
-  R ha = R(0), hT = R(0);
-  if (hvalid) {
-    ha = ld_a(hi, hj, k0);
-    hT = ld_T(hi, hj, k0);
-  }
+  R ha = ldA(hm.off, k0), hT = ldT(hm.off, k0);  // halo of plane k (raw T)
+  // velocities and base state of plane k (loaded one plane ahead)
+  R uL = u[(size_t)k0 * plu + uoL], uH = u[(size_t)k0 * plu + uoH];
+  R vL = v[(size_t)k0 * plv + voL], vH = v[(size_t)k0 * plv + voH];
+  R wH = DIM == 3 ? w[(size_t)(k0 + 1) * pl + co] : R(0);
+  R bA = ab[(size_t)k0 * pl + co], bT = Tb[(size_t)k0 * pl + co];
+  const R wL0 = DIM == 3 ? w[(size_t)k0 * pl + co] : R(0);
   // Gaussian surface heat flux of the column (x, y, t), FP64, once per column
   R qcol = R(0);
   if (P.qP != 0.0 && act) {
@@ -132,37 +195,43 @@ __global__ __launch_bounds__(512) void k_transport2(KParams P, int kz, int ntx, 
   bool have_lo = false;
   int buf = 0;
   for (int k = k0; k < k1; ++k) {
-    // shift the queues and prefetch plane k+3 and the next plane's halo
+    // shift the queues, insert plane k+3 (loaded one plane ago), load k+4
     if (DIM == 3) {
       for (int m = 0; m < 6; ++m) {
         qa[m] = qa[m + 1];
         qt[m] = qt[m + 1];
       }
-      qa[6] = cval ? ld_a(i, j, k + 3) : R(0);
-      qt[6] = cval ? ld_T(i, j, k + 3) : R(0);
+      qa[6] = ia;
+      qt[6] = tval(cm, iT, k + 3);
+      ia = ldA(cm.off, min(k + 4, kq));
+      iT = ldT(cm.off, min(k + 4, kq));
     }
-    R nha = R(0), nhT = R(0);
-    if (hvalid && k + 1 < k1) {
-      nha = ld_a(hi, hj, k + 1);
-      nhT = ld_T(hi, hj, k + 1);
-    }
-    // publish the plane
+    // publish the plane, then load the next plane's halo
     if (cval) {
       sa[buf][ty + H][tx + H] = qa[3];
       sT[buf][ty + H][tx + H] = qt[3];
     }
     if (hvalid) {
       sa[buf][hoy][hox] = ha;
-      sT[buf][hoy][hox] = hT;
+      sT[buf][hoy][hox] = tval(hm, hT, k);
     }
+    const int kn = min(k + 1, k1 - 1);
+    ha = ldA(hm.off, kn);
+    hT = ldT(hm.off, kn);
+    // this plane's velocities and base state; prefetch the next plane's
+    const R ulo = uL, uhi = uH, vlo = vL, vhi = vH, whi = wH, abc = bA, Tbc = bT;
+    uL = u[(size_t)kn * plu + uoL];
+    uH = u[(size_t)kn * plu + uoH];
+    vL = v[(size_t)kn * plv + voL];
+    vH = v[(size_t)kn * plv + voH];
+    if (DIM == 3) wH = w[(size_t)min(kn + 1, nz) * pl + co];
+    bA = ab[(size_t)kn * pl + co];
+    bT = Tb[(size_t)kn * pl + co];
     __syncthreads();
     R Fxa_lo = R(0), Fxt_lo = R(0), Fya_lo = R(0), Fyt_lo = R(0);
-    const long c = (long)i + (long)nx * ((long)j + (long)ny * k);
-    R ulo = R(0), uhi = R(0), vlo = R(0), vhi = R(0);
+    const size_t c = (size_t)k * pl + co;
     if (act) {
       const int X = tx + H, Y = ty + H;
-      ulo = u[fidx<0>(i, j, k, nx, ny)];
-      vlo = v[fidx<1>(i, j, k, nx, ny)];
       if (i > 0) {
         Fxa_lo = ulo * upw(sa[buf][Y][X - 3], sa[buf][Y][X - 2], sa[buf][Y][X - 1], sa[buf][Y][X], sa[buf][Y][X + 1],
                            sa[buf][Y][X + 2], ulo, eps);
@@ -186,7 +255,6 @@ __global__ __launch_bounds__(512) void k_transport2(KParams P, int kz, int ntx, 
         Fxa_hi = R(0);
         Fxt_hi = R(0);
       } else if (tx == TX - 1) {
-        uhi = u[fidx<0>(i + 1, j, k, nx, ny)];
         Fxa_hi = uhi * upw(sa[buf][Y][X - 2], sa[buf][Y][X - 1], sa[buf][Y][X], sa[buf][Y][X + 1], sa[buf][Y][X + 2],
                            sa[buf][Y][X + 3], uhi, eps);
         Fxt_hi = uhi * upw(sT[buf][Y][X - 2], sT[buf][Y][X - 1], sT[buf][Y][X], sT[buf][Y][X + 1], sT[buf][Y][X + 2],
@@ -202,7 +270,6 @@ __global__ __launch_bounds__(512) void k_transport2(KParams P, int kz, int ntx, 
           Fya_hi = fya[ty + 1][tx];
           Fyt_hi = fyt[ty + 1][tx];
         } else {
-          vhi = v[fidx<1>(i, j + 1, k, nx, ny)];
           Fya_hi = vhi * upw(sa[buf][Y - 2][X], sa[buf][Y - 1][X], sa[buf][Y][X], sa[buf][Y + 1][X],
                              sa[buf][Y + 2][X], sa[buf][Y + 3][X], vhi, eps);
           Fyt_hi = vhi * upw(sT[buf][Y - 2][X], sT[buf][Y - 1][X], sT[buf][Y][X], sT[buf][Y + 1][X],
@@ -216,16 +283,14 @@ __global__ __launch_bounds__(512) void k_transport2(KParams P, int kz, int ntx, 
           fza_lo = R(0);
           fzt_lo = R(0);
           if (k > 0) {
-            const R wl = w[fidx<2>(i, j, k, nx, ny)];
-            fza_lo = wl * upw(qa[0], qa[1], qa[2], qa[3], qa[4], qa[5], wl, eps);
-            fzt_lo = wl * upw(qt[0], qt[1], qt[2], qt[3], qt[4], qt[5], wl, eps);
+            fza_lo = wL0 * upw(qa[0], qa[1], qa[2], qa[3], qa[4], qa[5], wL0, eps);
+            fzt_lo = wL0 * upw(qt[0], qt[1], qt[2], qt[3], qt[4], qt[5], wL0, eps);
           }
         }
         R fza_hi = R(0), fzt_hi = R(0);
         if (k + 1 < nz) {
-          const R wh = w[fidx<2>(i, j, k + 1, nx, ny)];
-          fza_hi = wh * upw(qa[1], qa[2], qa[3], qa[4], qa[5], qa[6], wh, eps);
-          fzt_hi = wh * upw(qt[1], qt[2], qt[3], qt[4], qt[5], qt[6], wh, eps);
+          fza_hi = whi * upw(qa[1], qa[2], qa[3], qa[4], qa[5], qa[6], whi, eps);
+          fzt_hi = whi * upw(qt[1], qt[2], qt[3], qt[4], qt[5], qt[6], whi, eps);
         }
         diva += fza_hi - fza_lo;
         divt += fzt_hi - fzt_lo;
@@ -260,11 +325,9 @@ __global__ __launch_bounds__(512) void k_transport2(KParams P, int kz, int ntx, 
         src = qcol * ds;
       }
       const R LT = -divt * ih + (cond + src) / mixp(ac, P.rhocp1, P.rhocp2);
-      ao[c] = cb * ab[c] + ci * (ac + dt * La);
-      To[c] = cb * Tb[c] + ci * (Tc + dt * LT);
+      ao[c] = cb * abc + ci * (ac + dt * La);
+      To[c] = cb * Tbc + ci * (Tc + dt * LT);
     }
-    ha = nha;
-    hT = nhT;
     buf ^= 1;
   }
 }
