@@ -130,10 +130,9 @@ struct FluxOps {
 };
 
 template <class R, int D, int E>
-__device__ __forceinline__ void load_ops(FluxOps<R>& o, bool on, const SiteXY& s, const R* __restrict__ aL,
+__device__ __forceinline__ void load_ops(FluxOps<R>& o, const SiteXY& s, const R* __restrict__ aL,
                                          const R* __restrict__ aR, const R* __restrict__ eLp,
                                          const R* __restrict__ eRp) {
-  if (!on) return;
   o.c = aL[s.cL];
   if (E != D) {
     o.cR = aR[s.cR];
@@ -260,14 +259,25 @@ __device__ __forceinline__ void pred_body(const PredArgs<R, DIM, D>& A, int kz, 
   R qsg, hsg;
   const unsigned qoff = inplane(i, j, qsg);
   const unsigned hoff = inplane(hi, hj, hsg);
-  auto ldU = [&](unsigned off, R sgxy, int kk) {
+  // raw load of plane kk and the sign of its z ghost rule (applied at use)
+  auto ldU = [&](unsigned off, int kk) {
     R sz = R(1);
     const R* pl = DIM == 2 ? ud : ud + (size_t)refl(kk, nz, D == 2, sz) * plD;
-    return (sgxy * sz) * pl[off];
+    return pl[off];
+  };
+  auto zsg = [&](int kk) {
+    R sz = R(1);
+    if (DIM == 3) refl(kk, nz, D == 2, sz);
+    return sz;
   };
   // cell plane kk with the 1-deep even ghost along z
   auto cpl = [&](const R* f, int kk) { return f + (size_t)min(max(kk, 0), nz - 1) * plc; };
-  // operand loads of plane kk: flux item qq (first or second) and the face
+  // Operand loads of plane kk: flux item qq (first or second) and the face.
+  // The first items (one plane ahead) and the face are loaded
+  // unconditionally (every offset is a valid cell), so the count of loads in
+  // flight is path independent and the waits for one plane's operands do
+  // not drain the next plane's; the second items (72 threads) are issued
+  // first.
   auto load_items = [&](int kk, int qq, FluxOps<R>& xn, FluxOps<R>& yn) {
     const int kL = kk - (D == 2);
     const R* aL = cpl(a, kL);
@@ -277,39 +287,33 @@ __device__ __forceinline__ void pred_body(const PredArgs<R, DIM, D>& A, int kz, 
     const R* vL = A.v + (size_t)min(max(kL, 0), nz - 1) * plv;
     const R* vR = A.v + (size_t)min(kk, nz - 1) * plv;
     if (qq == 0) {
-      load_ops<R, D, 0>(xn, xon[0], xs0, aL, aR, uL, uR);
-      load_ops<R, D, 1>(yn, yon[0], ys0, aL, aR, vL, vR);
+      load_ops<R, D, 0>(xn, xs0, aL, aR, uL, uR);
+      load_ops<R, D, 1>(yn, ys0, aL, aR, vL, vR);
     } else {
-      if (xon[1]) load_ops<R, D, 0>(xn, true, site_xy<D, 0>(i0 + xm[1], j0 + xr[1], nx, ny), aL, aR, uL, uR);
-      if (yon[1]) load_ops<R, D, 1>(yn, true, site_xy<D, 1>(i, j0 + TY, nx, ny), aL, aR, vL, vR);
+      if (xon[1]) load_ops<R, D, 0>(xn, site_xy<D, 0>(i0 + xm[1], j0 + xr[1], nx, ny), aL, aR, uL, uR);
+      if (yon[1]) load_ops<R, D, 1>(yn, site_xy<D, 1>(i, j0 + TY, nx, ny), aL, aR, vL, vR);
     }
   };
   auto load_face = [&](int kk, FaceOps<R>& fn) {
     const int kL = kk - (D == 2);
     const R* aR = cpl(a, kk);
-    if (act) {
-      if (DIM == 3 && D != 2) {
-        const R* wk = A.w + (size_t)(kk + 1) * plc;
-        const R* ap = cpl(a, kk + 1);
-        fn.wL = wk[oL];
-        fn.wR = wk[oR];
-        fn.apL = ap[oL];
-        fn.apR = ap[oR];
-      } else {
-        fn.apR = aR[oR];
-      }
-      fn.skL = cpl(A.sk, kL)[oL];
-      fn.skR = cpl(A.sk, kk)[oR];
-      fn.mL = cpl(A.M, kL)[oL];
-      fn.mR = cpl(A.M, kk)[oR];
+    if (DIM == 3 && D != 2) {
+      const R* wk = A.w + (size_t)min(kk + 1, nz) * plc;
+      const R* ap = cpl(a, kk + 1);
+      fn.wL = wk[oL];
+      fn.wR = wk[oR];
+      fn.apL = ap[oL];
+      fn.apR = ap[oR];
+    } else {
+      fn.apR = aR[oR];
     }
+    fn.skL = cpl(A.sk, kL)[oL];
+    fn.skR = cpl(A.sk, kk)[oR];
+    fn.mL = cpl(A.M, kL)[oL];
+    fn.mR = cpl(A.M, kk)[oR];
   };
   FluxOps<R> xo{}, yo{};
-  FaceOps<R> fo{};
-  if (PF) {
-    load_items(k0, 0, xo, yo);
-    load_face(k0, fo);
-  }
+  if (PF) load_items(k0, 0, xo, yo);
   // alpha of the cells L and R in plane k (D != z), or of the cell below
   // the face (D = z): carried from plane to plane
   R acL = R(0), acR = R(0);
@@ -321,44 +325,49 @@ __device__ __forceinline__ void pred_body(const PredArgs<R, DIM, D>& A, int kz, 
       acL = cpl(a, k0 - 1)[oR];
     }
   }
+  // u_D column queue (k-3 .. k+3); plane k+3 enters from qin, loaded one
+  // plane earlier.  Threads outside the ghost band load a valid cell and do
+  // not use it.
+  const unsigned qo = cval ? qoff : 0u, ho = hvalid ? hoff : 0u;
+  const int kq = k1 + 2;  // last plane the queue needs
   R q[7];
 #pragma unroll
   for (int m = 0; m < 7; ++m) q[m] = R(0);
-  if (cval) {
-    if (DIM == 3) {
+  R qin = R(0);
+  if (DIM == 3) {
 #pragma unroll
-      for (int m = 0; m < 6; ++m) q[m + 1] = ldU(qoff, qsg, k0 - 3 + m);
-    } else {
-      q[3] = ldU(qoff, qsg, 0);
-    }
+    for (int m = 0; m < 6; ++m) q[m + 1] = (qsg * zsg(k0 - 3 + m)) * ldU(qo, k0 - 3 + m);
+    qin = ldU(qo, min(k0 + 3, kq));
+  } else {
+    q[3] = qsg * ldU(qo, 0);
   }
-  R hu = hvalid ? ldU(hoff, hsg, k0) : R(0);
+  R hu = ldU(ho, k0);  // halo of plane k (raw)
   R fz_lo = R(0), tz_lo = R(0);
   bool have_lo = false;
   int buf = 0;
   for (int k = k0; k < k1; ++k) {
-    // operands: first items and face one plane ahead (PF) or now; second
-    // items (waves 0 and 1 only) now
+    // second items of this plane first, then the next plane's operands
+    // (PF) or this plane's
+    // (the face operands are used after the second barrier: loaded for this
+    // plane, after the second items and before the prefetches)
     FluxOps<R> xn{}, yn{}, x2{}, y2{};
-    FaceOps<R> fn{};
-    if (PF) {
-      if (k + 1 < k1) {
-        load_items(k + 1, 0, xn, yn);
-        load_face(k + 1, fn);
-      }
-    } else {
-      load_items(k, 0, xo, yo);
-      load_face(k, fo);
-    }
+    FaceOps<R> fo{};
     if (nxi > 1 || nyi > 1) load_items(k, 1, x2, y2);
+    load_face(k, fo);
+    if (PF)
+      load_items(min(k + 1, k1 - 1), 0, xn, yn);
+    else
+      load_items(k, 0, xo, yo);
     if (DIM == 3) {
 #pragma unroll
       for (int m = 0; m < 6; ++m) q[m] = q[m + 1];
-      q[6] = cval ? ldU(qoff, qsg, k + 3) : R(0);
+      q[6] = (qsg * zsg(k + 3)) * qin;
+      qin = ldU(qo, min(k + 4, kq));
     }
-    const R nhu = (hvalid && k + 1 < k1) ? ldU(hoff, hsg, k + 1) : R(0);
+    // publish the plane, then load the next plane's halo
     if (cval) sU[buf][ty + H][tx + H] = q[3];
-    if (hvalid) sU[buf][hoy][hox] = hu;
+    if (hvalid) sU[buf][hoy][hox] = hsg * hu;
+    hu = ldU(ho, min(k + 1, k1 - 1));
     __syncthreads();
 #pragma unroll
     for (int qq = 0; qq < 2; ++qq) {
@@ -455,9 +464,7 @@ __device__ __forceinline__ void pred_body(const PredArgs<R, DIM, D>& A, int kz, 
     if (PF) {
       xo = xn;
       yo = yn;
-      fo = fn;
     }
-    hu = nhu;
     buf ^= 1;
   }
 }
