@@ -85,17 +85,18 @@ void update_xr(hipStream_t s, long n, const double* scal, R* x, R* r, const R* d
 template <class R>
 void update_d(hipStream_t s, long n, const double* scal, const R* z, R* d, int first, const int* iflag);
 template <class R>
-void mg_smooth_first(hipStream_t s, const Level<R>& L, const R* b, R* x, const int* iflag);
+void mg_smooth_first(hipStream_t s, const Level<R>& L, const R* b, R* x, double om, const int* iflag);
 template <class R>
-void mg_smooth(hipStream_t s, int dim, const Level<R>& L, const R* b, const R* x, R* xo, double* part_rz, const int* iflag);
+void mg_smooth(hipStream_t s, int dim, const Level<R>& L, const R* b, const R* x, R* xo, double om, double* part_rz,
+               const int* iflag);
 template <class R>
 void mg_resid_restrict(hipStream_t s, int dim, const Level<R>& F, const R* b, const R* x, R* bc,
                        const int* iflag);
 template <class R>
 void mg_prolong_smooth(hipStream_t s, int dim, const Level<R>& F, const Level<R>& C, const R* b, const R* x,
-                       R* xo, double omega_c, double* part_rz, const int* iflag);
+                       R* xo, double omega_c, double om, double* part_rz, const int* iflag);
 template <class R>
-void mg_coarse_solve(hipStream_t s, int dim, const Level<R>& L, const R* b, R* x, int sweeps,
+void mg_coarse_solve(hipStream_t s, int dim, const Level<R>& L, const R* b, R* x, int sweeps, double om,
                      const int* iflag);
 
 // finest-level fused kernels (tcf_fine.hip); return the number of partials

@@ -244,16 +244,17 @@ __global__ __launch_bounds__(256) void k_update_d(long n, const double* __restri
 
 template <class R>
 __global__ __launch_bounds__(256) void k_smooth_first(long n, const R* __restrict__ wd, const R* __restrict__ b,
-                                                      R* __restrict__ x, const int* __restrict__ iflag) {
+                                                      R* __restrict__ x, R om, const int* __restrict__ iflag) {
   if (iflag[I_DONE]) return;
   const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c < n) x[c] = wd[c] * b[c];
+  if (c < n) x[c] = om * wd[c] * b[c];
 }
 
-// damped Jacobi: xo = x + wdiag (b - K x); optional partial of b.xo (= r.z on the finest level)
+// damped Jacobi: xo = x + om wdiag (b - K x) (wdiag = 1 / diag); optional
+// partial of b.xo (= r.z on the finest level)
 template <class R, int DIM>
 __global__ __launch_bounds__(256) void k_smooth(Level<R> L, const R* __restrict__ b, const R* __restrict__ x,
-                                                R* __restrict__ xo, double* __restrict__ part,
+                                                R* __restrict__ xo, R om, double* __restrict__ part,
                                                 const int* __restrict__ iflag) {
   if (iflag[I_DONE]) return;
   __shared__ double sh[8];
@@ -262,7 +263,7 @@ __global__ __launch_bounds__(256) void k_smooth(Level<R> L, const R* __restrict_
   if (i < L.nx && j < L.ny) {
     const long c = cidx(i, j, k, L.nx, L.ny);
     const R Kx = applyK<R, DIM>(x, L.ax, L.ay, L.az, i, j, k, L.nx, L.ny, L.nz);
-    const R xn = x[c] + L.wdiag[c] * (b[c] - Kx);
+    const R xn = x[c] + om * L.wdiag[c] * (b[c] - Kx);
     xo[c] = xn;
     val = (double)b[c] * (double)xn;
   }
@@ -292,11 +293,11 @@ __global__ __launch_bounds__(256) void k_resid_restrict(Level<R> F, int cnx, int
   bc[cidx(I, J, K, cnx, cny)] = s;
 }
 
-// x' = x + omega_c P e (on the fly), xo = x' + wdiag (b - K x')
+// x' = x + omega_c P e (on the fly), xo = x' + om wdiag (b - K x')
 template <class R, int DIM>
 __global__ __launch_bounds__(256) void k_prolong_smooth(Level<R> L, int cnx, int cny, const R* __restrict__ e,
                                                         const R* __restrict__ b, const R* __restrict__ x,
-                                                        R* __restrict__ xo, R omc, double* __restrict__ part,
+                                                        R* __restrict__ xo, R omc, R om, double* __restrict__ part,
                                                         const int* __restrict__ iflag) {
   if (iflag[I_DONE]) return;
   __shared__ double sh[8];
@@ -319,7 +320,7 @@ __global__ __launch_bounds__(256) void k_prolong_smooth(Level<R> L, int cnx, int
       if (k > 0) s += L.az[fidx<2>(i, j, k, nx, ny)] * (xc - xp(i, j, k - 1));
       if (k < nz - 1) s += L.az[fidx<2>(i, j, k + 1, nx, ny)] * (xc - xp(i, j, k + 1));
     }
-    const R xn = xc + L.wdiag[c] * (b[c] - s);
+    const R xn = xc + om * L.wdiag[c] * (b[c] - s);
     xo[c] = xn;
     val = (double)b[c] * (double)xn;
   }
@@ -333,7 +334,7 @@ __global__ __launch_bounds__(256) void k_prolong_smooth(Level<R> L, int cnx, int
 // (x and x2 are ping-pong buffers; the result ends in x).
 template <class R, int DIM>
 __global__ __launch_bounds__(1024) void k_coarse(Level<R> L, const R* __restrict__ b, R* __restrict__ x,
-                                                 R* __restrict__ x2, int sweeps, const int* __restrict__ iflag) {
+                                                 R* __restrict__ x2, int sweeps, R om, const int* __restrict__ iflag) {
   if (iflag[I_DONE]) return;
   const long n = L.n();
   for (long c = threadIdx.x; c < n; c += blockDim.x) x[c] = R(0);
@@ -344,7 +345,7 @@ __global__ __launch_bounds__(1024) void k_coarse(Level<R> L, const R* __restrict
     for (long c = threadIdx.x; c < n; c += blockDim.x) {
       const int i = (int)(c % L.nx), j = (int)((c / L.nx) % L.ny), k = (int)(c / ((long)L.nx * L.ny));
       const R Kx = applyK<R, DIM>(src, L.ax, L.ay, L.az, i, j, k, L.nx, L.ny, L.nz);
-      dst[c] = src[c] + L.wdiag[c] * (b[c] - Kx);
+      dst[c] = src[c] + om * L.wdiag[c] * (b[c] - Kx);
     }
     __syncthreads();
     R* t = src;
@@ -744,16 +745,16 @@ void update_d(hipStream_t s, long n, const double* scal, const R* z, R* d, int f
 }
 
 template <class R>
-void mg_smooth_first(hipStream_t s, const Level<R>& L, const R* b, R* x, const int* iflag) {
-  hipLaunchKernelGGL((k_smooth_first<R>), dim3(nblk1(L.n())), dim3(256), 0, s, L.n(), L.wdiag, b, x, iflag);
+void mg_smooth_first(hipStream_t s, const Level<R>& L, const R* b, R* x, double om, const int* iflag) {
+  hipLaunchKernelGGL((k_smooth_first<R>), dim3(nblk1(L.n())), dim3(256), 0, s, L.n(), L.wdiag, b, x, R(om), iflag);
 }
 
 template <class R>
-void mg_smooth(hipStream_t s, int dim, const Level<R>& L, const R* b, const R* x, R* xo, double* part,
+void mg_smooth(hipStream_t s, int dim, const Level<R>& L, const R* b, const R* x, R* xo, double om, double* part,
                const int* iflag) {
   dim3 g = grid_for(L.nx, L.ny, L.nz);
-  if (dim == 3) hipLaunchKernelGGL((k_smooth<R, 3>), g, blk(), 0, s, L, b, x, xo, part, iflag);
-  else hipLaunchKernelGGL((k_smooth<R, 2>), g, blk(), 0, s, L, b, x, xo, part, iflag);
+  if (dim == 3) hipLaunchKernelGGL((k_smooth<R, 3>), g, blk(), 0, s, L, b, x, xo, R(om), part, iflag);
+  else hipLaunchKernelGGL((k_smooth<R, 2>), g, blk(), 0, s, L, b, x, xo, R(om), part, iflag);
 }
 
 template <class R>
@@ -766,18 +767,21 @@ void mg_resid_restrict(hipStream_t s, int dim, const Level<R>& F, const R* b, co
 
 template <class R>
 void mg_prolong_smooth(hipStream_t s, int dim, const Level<R>& F, const Level<R>& C, const R* b, const R* x, R* xo,
-                       double omega_c, double* part, const int* iflag) {
+                       double omega_c, double om, double* part, const int* iflag) {
   dim3 g = grid_for(F.nx, F.ny, F.nz);
   if (dim == 3)
-    hipLaunchKernelGGL((k_prolong_smooth<R, 3>), g, blk(), 0, s, F, C.nx, C.ny, C.x, b, x, xo, R(omega_c), part, iflag);
+    hipLaunchKernelGGL((k_prolong_smooth<R, 3>), g, blk(), 0, s, F, C.nx, C.ny, C.x, b, x, xo, R(omega_c), R(om), part,
+                       iflag);
   else
-    hipLaunchKernelGGL((k_prolong_smooth<R, 2>), g, blk(), 0, s, F, C.nx, C.ny, C.x, b, x, xo, R(omega_c), part, iflag);
+    hipLaunchKernelGGL((k_prolong_smooth<R, 2>), g, blk(), 0, s, F, C.nx, C.ny, C.x, b, x, xo, R(omega_c), R(om), part,
+                       iflag);
 }
 
 template <class R>
-void mg_coarse_solve(hipStream_t s, int dim, const Level<R>& L, const R* b, R* x, int sweeps, const int* iflag) {
-  if (dim == 3) hipLaunchKernelGGL((k_coarse<R, 3>), dim3(1), dim3(1024), 0, s, L, b, x, L.x2, sweeps, iflag);
-  else hipLaunchKernelGGL((k_coarse<R, 2>), dim3(1), dim3(1024), 0, s, L, b, x, L.x2, sweeps, iflag);
+void mg_coarse_solve(hipStream_t s, int dim, const Level<R>& L, const R* b, R* x, int sweeps, double om,
+                     const int* iflag) {
+  if (dim == 3) hipLaunchKernelGGL((k_coarse<R, 3>), dim3(1), dim3(1024), 0, s, L, b, x, L.x2, sweeps, R(om), iflag);
+  else hipLaunchKernelGGL((k_coarse<R, 2>), dim3(1), dim3(1024), 0, s, L, b, x, L.x2, sweeps, R(om), iflag);
 }
 
 template <class R>
@@ -891,12 +895,12 @@ void zero_walls(const KParams& P, hipStream_t s, R* u, R* v, R* w) {
   template void spmv_dot<R>(hipStream_t, int, const Level<R>&, const R*, R*, double*, const int*);          \
   template void update_xr<R>(hipStream_t, long, const double*, R*, R*, const R*, const R*, double*, const int*);                                                                         \
   template void update_d<R>(hipStream_t, long, const double*, const R*, R*, int, const int*);                     \
-  template void mg_smooth_first<R>(hipStream_t, const Level<R>&, const R*, R*, const int*);                       \
-  template void mg_smooth<R>(hipStream_t, int, const Level<R>&, const R*, const R*, R*, double*, const int*);                                                                         \
+  template void mg_smooth_first<R>(hipStream_t, const Level<R>&, const R*, R*, double, const int*);                       \
+  template void mg_smooth<R>(hipStream_t, int, const Level<R>&, const R*, const R*, R*, double, double*, const int*);                                                                         \
   template void mg_resid_restrict<R>(hipStream_t, int, const Level<R>&, const R*, const R*, R*, const int*);      \
   template void mg_prolong_smooth<R>(hipStream_t, int, const Level<R>&, const Level<R>&, const R*, const R*, R*,  \
-                                     double, double*, const int*);                                          \
-  template void mg_coarse_solve<R>(hipStream_t, int, const Level<R>&, const R*, R*, int, const int*);             \
+                                     double, double, double*, const int*);                                  \
+  template void mg_coarse_solve<R>(hipStream_t, int, const Level<R>&, const R*, R*, int, double, const int*);             \
   template void project<R>(const KParams&, hipStream_t, const R*, const double*, const R*, const R*, const R*,    \
                            double*, double*, double*, R*, R*, R*);                                                \
   template void diagnostics<R>(const KParams&, hipStream_t, const R*, const double*, const double*,               \
