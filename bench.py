@@ -203,7 +203,7 @@ def main():
         avg_ms = r32["kernel_ms"] / r32["kernel_launches"]
         ab = algorithmic_bytes(args.kernel, c, 1)
         ach = ab / (avg_ms / 1e3) / 1e9
-        traffic = measured_traffic(args.kernel, wl.replace("^", ""))
+        traffic = measured_traffic(args.kernel, re.sub(r"\^\d", "", wl).replace("-", ""))
         roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": args.kernel, "avg_launch_ms": round(avg_ms, 5),
