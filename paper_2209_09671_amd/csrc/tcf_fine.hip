@@ -359,26 +359,37 @@ __global__ __launch_bounds__(FX * FY) void k0_smooth(Op0<R> op, int kz, int ntx,
 // bc = R (b - K0 x): fine cells marched like the sweeps; the 2x2 in-plane
 // sum goes through LDS, the pair of planes is summed in a register, and the
 // thread at the even corner of each 2x2(x2) group writes the coarse value.
+// With x1c it also writes the coarse level's first sweep from zero,
+// x1c = om0 bc / diag_c (wdc = 1 / diag_c).
 template <class R, int DIM>
 __global__ __launch_bounds__(FX * FY) void k0_resid_restrict(Op0<R> op, int kz, int ntx, int nty, int cnx, int cny,
                                                          const R* __restrict__ b, const R* __restrict__ x,
-                                                         R* __restrict__ bc, const int* __restrict__ iflag) {
+                                                         R* __restrict__ bc, const R* __restrict__ wdc,
+                                                         R* __restrict__ x1c, R om0, const int* __restrict__ iflag) {
   if (iflag[I_DONE]) return;
   __shared__ R sres[FY][FX];
   const Tile T = tile_of(op.nx, op.ny, op.nz, ntx, nty, kz);
   const int tx = threadIdx.x, ty = threadIdx.y;
-  R zsum = R(0);
+  R zsum = R(0), wdv = R(0);
   auto X = [&](long c, int, int, int) { return x[c]; };
   const Ident<R> XV;
   auto pre = [&](long c) { return b[c]; };
   auto body = [&](long, int, R, R Kx, R, R bc) { sres[ty][tx] = bc - Kx; };
+  // The four threads of a 2x2 group sum the same four residuals and store the
+  // same coarse value (no thread-dependent store); 1/diag of the coarse cell
+  // is loaded by every thread at the even plane and used at the odd one.
+  const long cbase = T.act ? (long)(T.i >> 1) + (long)cnx * (long)(T.j >> 1) : 0;
+  const long cplane = (long)cnx * cny;
+  const int bx = tx & ~1, by = ty & ~1;
   auto post = [&](int k) {
-    if (T.act && !(tx & 1) && !(ty & 1)) {
-      // the partner cells of an even corner lie inside the tile (nx, ny even)
-      zsum += (sres[ty][tx] + sres[ty][tx + 1]) + (sres[ty + 1][tx] + sres[ty + 1][tx + 1]);
+    const long ci = cbase + cplane * (DIM == 3 ? (k >> 1) : 0);
+    if (x1c && (DIM == 2 || !(k & 1))) wdv = wdc[ci];
+    if (T.act) {
+      // the partner cells lie inside the tile (nx, ny even)
+      zsum += (sres[by][bx] + sres[by][bx + 1]) + (sres[by + 1][bx] + sres[by + 1][bx + 1]);
       if (DIM == 2 || (k & 1)) {
-        const int K = DIM == 3 ? (k >> 1) : 0;
-        bc[(long)(T.i >> 1) + (long)cnx * ((long)(T.j >> 1) + (long)cny * K)] = zsum;
+        bc[ci] = zsum;
+        if (x1c) x1c[ci] = om0 * wdv * zsum;
         zsum = R(0);
       }
     }
@@ -487,16 +498,17 @@ int fine_smooth(hipStream_t s, int dim, const Fine<R>& F, double omega, const R*
 }
 
 template <class R>
-void fine_resid_restrict(hipStream_t s, int dim, const Fine<R>& F, const R* b, const R* x, R* bc, const int* iflag) {
+void fine_resid_restrict(hipStream_t s, int dim, const Fine<R>& F, const R* b, const R* x, R* bc, const R* wdc, R* x1c,
+                         double om0, const int* iflag) {
   const int cnx = F.nx / 2, cny = F.ny / 2;
   const Launch L = plan(F.nx, F.ny, F.nz);
   const Op0<R> op = op_of(F);
   if (dim == 3)
     hipLaunchKernelGGL((k0_resid_restrict<R, 3>), dim3(L.nblocks), dim3(FX, FY), 0, s, op, L.kz, L.ntx, L.nty, cnx, cny,
-                       b, x, bc, iflag);
+                       b, x, bc, wdc, x1c, R(om0), iflag);
   else
     hipLaunchKernelGGL((k0_resid_restrict<R, 2>), dim3(L.nblocks), dim3(FX, FY), 0, s, op, L.kz, L.ntx, L.nty, cnx, cny,
-                       b, x, bc, iflag);
+                       b, x, bc, wdc, x1c, R(om0), iflag);
 }
 
 #define TCF_FINE_INST(R)                                                                                          \
@@ -507,7 +519,8 @@ void fine_resid_restrict(hipStream_t s, int dim, const Fine<R>& F, const R* b, c
   template void fine_smooth_first<R>(hipStream_t, int, const Fine<R>&, double, const R*, R*, const int*);         \
   template int fine_smooth<R>(hipStream_t, int, const Fine<R>&, double, const R*, const R*, R*, const R*, int,    \
                               int, double, double*, const int*);                                                  \
-  template void fine_resid_restrict<R>(hipStream_t, int, const Fine<R>&, const R*, const R*, R*, const int*);
+  template void fine_resid_restrict<R>(hipStream_t, int, const Fine<R>&, const R*, const R*, R*, const R*, R*, double,  \
+                                        const int*);
 
 TCF_FINE_INST(double)
 TCF_FINE_INST(float)

@@ -376,13 +376,17 @@ hipError_t read_back(tcf_grid* g) {
   return hipStreamSynchronize(g->stream);
 }
 
-// Operator hierarchy from the fine face weights already in level 0.
+// Operator hierarchy.  Level 0 is applied matrix-free from alpha; its
+// stored weights exist only where something reads them: the FP64 path (its
+// initial residual and the coarsening) and single-level hierarchies (the
+// coarsest-level solve).  Otherwise level 1 is coarsened straight from alpha.
 template <class R>
-void build_levels(tcf_grid* g, Fields<R>& F) {
+void build_levels(tcf_grid* g, Fields<R>& F, bool level0_stored) {
   const int dim = g->D.dim;
-  make_wdiag<R>(g->stream, dim, F.lv[0], 1.0);
+  if (F.lv.size() == 1) make_wdiag<R>(g->stream, dim, F.lv[0], 1.0);
   for (size_t l = 1; l < F.lv.size(); ++l) {
-    coarsen_weights<R>(g->stream, dim, F.lv[l - 1], F.lv[l]);
+    if (l == 1 && !level0_stored) coarsen_from_alpha<R>(g->P, g->stream, F.a, F.lv[1]);
+    else coarsen_weights<R>(g->stream, dim, F.lv[l - 1], F.lv[l]);
     make_wdiag<R>(g->stream, dim, F.lv[l], 1.0);
   }
   if (F.cinv) coarse_factor<R>(g->stream, dim, F.lv.back(), F.cfac, F.cinv);
@@ -456,8 +460,10 @@ void vcycle(tcf_grid* g, Fields<R>& F, size_t l, const R* b, R* out, R* tmp, dou
       fine_smooth<R>(s, dim, Fd, wpre(k), b, bufs[(w - 1) & 1], bufs[w & 1], nullptr, 0, 0, 0.0, nullptr, g->iflag);
     }
     const R* cur = bufs[(w - 1) & 1];
-    fine_resid_restrict<R>(s, dim, Fd, b, cur, C.b, g->iflag);
-    vcycle<R>(g, F, 1, C.b, C.x, C.x2, nullptr, false, nullptr);
+    // a coarse level that smooths gets its first sweep from the restriction
+    const bool cfirst = l + 2 < F.lv.size();
+    fine_resid_restrict<R>(s, dim, Fd, b, cur, C.b, C.wdiag, cfirst ? C.x2 : nullptr, wpre(0), g->iflag);
+    vcycle<R>(g, F, 1, C.b, C.x, C.x2, nullptr, cfirst, nullptr);
     int n = fine_smooth<R>(s, dim, Fd, wpost(0), b, cur, bufs[w & 1], C.x, C.nx, C.ny, kOmegaC,
                            nu == 1 ? part : nullptr, g->iflag);
     ++w;
@@ -470,13 +476,14 @@ void vcycle(tcf_grid* g, Fields<R>& F, size_t l, const R* b, R* out, R* tmp, dou
     return;
   }
   int w = 0;  // next write goes to bufs[w & 1]
-  mg_smooth_first<R>(s, L, b, bufs[w & 1], wpre(0), g->iflag);
+  if (!first_done) mg_smooth_first<R>(s, L, b, bufs[w & 1], wpre(0), g->iflag);
   ++w;
   for (int k = 1; k < nu; ++k, ++w)
     mg_smooth<R>(s, dim, L, b, bufs[(w - 1) & 1], bufs[w & 1], wpre(k), nullptr, g->iflag);
   const R* cur = bufs[(w - 1) & 1];
-  mg_resid_restrict<R>(s, dim, L, b, cur, C.b, g->iflag);
-  vcycle<R>(g, F, l + 1, C.b, C.x, C.x2, nullptr, false, nullptr);
+  const bool cfirst = l + 2 < F.lv.size();
+  mg_resid_restrict<R>(s, dim, L, b, cur, C.b, C.wdiag, cfirst ? C.x2 : nullptr, wpre(0), g->iflag);
+  vcycle<R>(g, F, l + 1, C.b, C.x, C.x2, nullptr, cfirst, nullptr);
   mg_prolong_smooth<R>(s, dim, L, C, b, cur, bufs[w & 1], kOmegaC, wpost(0), nullptr, g->iflag);
   ++w;
   for (int k = 1; k < nu; ++k, ++w)
@@ -563,21 +570,20 @@ tcf_status solve_refined(tcf_grid* g, double* p, int* iters, int* nref, double* 
   Fields<float>& F = g->f32;
   const long N = g->D.N;
   const int dim = g->D.dim;
-  const int nbc = nblocks_cells(g->D.nx, g->D.ny, g->D.nz);
   const int nb1 = (int)((N + 255) / 256);
   const double rt = g->cfg.p_rtol, irt = g->cfg.inner_rtol;
   *iters = 0;
   *nref = 0;
   *converged = false;
   double bb = 0.0;
+  int nrp = 0;
   for (int ref = 0;; ++ref) {
     {
       Prof pr(g, FAM_RESID64);
-      resid64(s, dim, g->D.nx, g->D.ny, g->D.nz, g->ax64, g->ay64, g->az64, g->b64, g->scal, p, g->r64, g->part[0],
-              g->part[1]);
+      nrp = resid64a<float>(g->P, s, F.a, g->b64, g->scal, p, g->r64, g->part[0], g->part[1]);
     }
-    finalize(s, g->part[0], nbc, g->scal, g->iflag, F_STORE, S_BB64, 0.0);
-    finalize(s, g->part[1], nbc, g->scal, g->iflag, F_SCALE, 0, (double)N);
+    finalize(s, g->part[0], nrp, g->scal, g->iflag, F_STORE, S_BB64, 0.0);
+    finalize(s, g->part[1], nrp, g->scal, g->iflag, F_SCALE, 0, (double)N);
     HIPCHECK(read_back(g));
     bb = g->hscal[S_BB64];
     const double rr = g->hscal[S_RR64];
@@ -621,12 +627,15 @@ tcf_status solve_refined(tcf_grid* g, double* p, int* iters, int* nref, double* 
 template <class R>
 void prepare_operator(tcf_grid* g) {
   Fields<R>& F = fields<R>(g);
-  if (g->fp32)
+  bool stored = true;
+  if (!g->fp32)
+    face_weights<R>(g->P, g->stream, F.a, g->ax64, g->ay64, g->az64, nullptr, nullptr, nullptr);
+  else if (F.lv.size() == 1)
     face_weights<R>(g->P, g->stream, F.a, g->ax64, g->ay64, g->az64, g->f32.lv[0].ax, g->f32.lv[0].ay,
                     g->f32.lv[0].az);
   else
-    face_weights<R>(g->P, g->stream, F.a, g->ax64, g->ay64, g->az64, nullptr, nullptr, nullptr);
-  build_levels<R>(g, F);
+    stored = false;  // the FP64 refinement residual recomputes its weights from alpha
+  build_levels<R>(g, F, stored);
 }
 
 tcf_status solve(tcf_grid* g, double* p, tcf_step_info* inf) {
@@ -997,8 +1006,8 @@ tcf_status tcf_apply_A(tcf_grid* g, const double* x, double* y) {
   else prepare_operator<double>(g);
   // y = -(0 - 0) - K x = A x, with scal[S_MEAN] = 0 and a zero rhs
   fill_f64(s, 1, g->scal + S_MEAN, 0.0);
-  resid64(s, g->D.dim, g->D.nx, g->D.ny, g->D.nz, g->ax64, g->ay64, g->az64, g->zero64, g->scal, x, y, g->part[0],
-          g->part[1]);
+  if (g->fp32) resid64a<float>(g->P, s, g->f32.a, g->zero64, g->scal, x, y, g->part[0], g->part[1]);
+  else resid64a<double>(g->P, s, g->f64.a, g->zero64, g->scal, x, y, g->part[0], g->part[1]);
   HIPCHECK(hipGetLastError());
   return TCF_OK;
 }

@@ -72,6 +72,14 @@ template <class R>
 void make_wdiag(hipStream_t s, int dim, const Level<R>& L, double omega);
 template <class R>
 void coarsen_weights(hipStream_t s, int dim, const Level<R>& F, const Level<R>& C);
+// level-1 weights from alpha (the fine weights are not stored)
+template <class R>
+void coarsen_from_alpha(const KParams& P, hipStream_t s, const R* a, const Level<R>& C);
+// r = -(b - mean) - K p in FP64 with the fine weights recomputed from alpha;
+// block partials of ||rhs||^2 and ||r||^2; returns the number of partials
+template <class R>
+int resid64a(const KParams& P, hipStream_t s, const R* a, const double* b, const double* scal, const double* p,
+              double* r, double* pbb, double* prr);
 
 // PCG / multigrid building blocks on a level; all partial sums in FP64
 template <class R>
@@ -90,8 +98,8 @@ template <class R>
 void mg_smooth(hipStream_t s, int dim, const Level<R>& L, const R* b, const R* x, R* xo, double om, double* part_rz,
                const int* iflag);
 template <class R>
-void mg_resid_restrict(hipStream_t s, int dim, const Level<R>& F, const R* b, const R* x, R* bc,
-                       const int* iflag);
+void mg_resid_restrict(hipStream_t s, int dim, const Level<R>& F, const R* b, const R* x, R* bc, const R* wdc,
+                       R* x1c, double om0, const int* iflag);
 template <class R>
 void mg_prolong_smooth(hipStream_t s, int dim, const Level<R>& F, const Level<R>& C, const R* b, const R* x,
                        R* xo, double omega_c, double om, double* part_rz, const int* iflag);
@@ -113,7 +121,9 @@ template <class R>
 int fine_smooth(hipStream_t s, int dim, const Fine<R>& F, double omega, const R* b, const R* x, R* xo, const R* e,
                 int cnx, int cny, double omc, double* part, const int* iflag);
 template <class R>
-void fine_resid_restrict(hipStream_t s, int dim, const Fine<R>& F, const R* b, const R* x, R* bc, const int* iflag);
+// bc = R (b - K0 x); with x1c also x1c = om0 wdc bc (the coarse level's first sweep)
+void fine_resid_restrict(hipStream_t s, int dim, const Fine<R>& F, const R* b, const R* x, R* bc, const R* wdc, R* x1c,
+                         double om0, const int* iflag);
 
 // exact coarsest-level solve (levels with at most kCoarseDenseMax cells)
 template <class R>
@@ -126,9 +136,6 @@ void finalize(hipStream_t s, const double* part, int nparts, double* scal, int* 
 void init_flags(hipStream_t s, int* iflag);
 
 // FP64 refinement helpers (FP32 mode)
-void resid64(hipStream_t s, int dim, int nx, int ny, int nz, const double* ax, const double* ay,
-             const double* az, const double* b, const double* scal, const double* p, double* r,
-             double* part_bb, double* part_rr);
 void scale_to32(hipStream_t s, long n, const double* r, const double* scal, float* r32);
 void add_scaled(hipStream_t s, long n, const float* e, const double* scal, double* p);
 void subtract_mean(hipStream_t s, long n, const double* scal, int slot, double* p);

@@ -7,6 +7,7 @@
 // the arrays have exactly the ABI layout and need no padding or ghost-fill
 // pass.  Reductions are deterministic: wavefront shuffles, then LDS, then one
 // FP64 partial per block, summed in a fixed order by a one-block finalize.
+#include <algorithm>
 #include <cfloat>
 #include <cmath>
 
@@ -277,7 +278,8 @@ __global__ __launch_bounds__(256) void k_smooth(Level<R> L, const R* __restrict_
 template <class R, int DIM>
 __global__ __launch_bounds__(256) void k_resid_restrict(Level<R> F, int cnx, int cny, int cnz,
                                                         const R* __restrict__ b, const R* __restrict__ x,
-                                                        R* __restrict__ bc, const int* __restrict__ iflag) {
+                                                        R* __restrict__ bc, const R* __restrict__ wdc,
+                                                        R* __restrict__ x1c, R om0, const int* __restrict__ iflag) {
   if (iflag[I_DONE]) return;
   const int I = blockIdx.x * BX + threadIdx.x, J = blockIdx.y * BY + threadIdx.y, K = blockIdx.z;
   if (I >= cnx || J >= cny) return;
@@ -290,7 +292,9 @@ __global__ __launch_bounds__(256) void k_resid_restrict(Level<R> F, int cnx, int
         const long c = cidx(i, j, k, F.nx, F.ny);
         s += b[c] - applyK<R, DIM>(x, F.ax, F.ay, F.az, i, j, k, F.nx, F.ny, F.nz);
       }
-  bc[cidx(I, J, K, cnx, cny)] = s;
+  const long ci = cidx(I, J, K, cnx, cny);
+  bc[ci] = s;
+  if (x1c) x1c[ci] = om0 * wdc[ci] * s;  // the coarse level's first sweep from zero
 }
 
 // x' = x + omega_c P e (on the fly), xo = x' + om wdiag (b - K x')
@@ -492,22 +496,79 @@ __global__ void k_init_flags(int* iflag) {
 }
 
 // ---- FP64 refinement helpers -------------------------------------------------
-template <int DIM>
-__global__ __launch_bounds__(256) void k_resid64(int nx, int ny, int nz, const double* __restrict__ ax,
-                                                 const double* __restrict__ ay, const double* __restrict__ az,
-                                                 const double* __restrict__ b, const double* __restrict__ scal,
-                                                 const double* __restrict__ p, double* __restrict__ r,
-                                                 double* __restrict__ pbb, double* __restrict__ prr) {
+// FP64 residual r = -(b - mean b) - K p with the face weights recomputed from
+// alpha (a_f = (1/h^2) / (0.5 (rho_L + rho_R)) in FP64, the expression the
+// stored FP64 weights are made with): 28 bytes per cell instead of the 48 of
+// stored weights.  Block partials of ||rhs||^2 and ||r||^2.
+// FP64 reciprocal: hardware estimate refined by three Newton steps (each
+// doubles the correct bits; the result is within an ulp or two of 1/x, all
+// that the FP64 residual needs: the projection's own 1/rho_f agrees with it
+// to rounding).
+__device__ __forceinline__ double rcp64(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(r, fma(-x, r, 1.0), r);
+  r = fma(r, fma(-x, r, 1.0), r);
+  r = fma(r, fma(-x, r, 1.0), r);
+  return r;
+}
+
+template <class R, int DIM>
+__global__ __launch_bounds__(256) void k_resid64a(KParams P, int kz, const R* __restrict__ a,
+                                                  const double* __restrict__ b, const double* __restrict__ scal,
+                                                  const double* __restrict__ p, double* __restrict__ r,
+                                                  double* __restrict__ pbb, double* __restrict__ prr) {
+  // one column per thread, marching over a chunk of kz planes: the z
+  // neighbours of p and of the density roll through registers (loaded one
+  // plane ahead) and the weight of the face to the next plane is carried to
+  // it; the in-plane neighbours come through L1 from the block's own rows
   __shared__ double sh[8];
-  const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
+  const int nx = P.nx, ny = P.ny, nz = P.nz;
+  const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y;
+  const int k0 = blockIdx.z * kz, k1 = min(k0 + kz, nz);
+  const bool act = i < nx && j < ny;
+  const size_t pl = (size_t)nx * ny;
+  const size_t col = act ? (size_t)i + (size_t)nx * j : 0;
+  // in-plane neighbour offsets (own cell where there is none; its term is skipped)
+  const long oxm = i > 0 ? -1 : 0, oxp = i < nx - 1 ? 1 : 0;
+  const long oym = j > 0 ? -(long)nx : 0, oyp = j < ny - 1 ? (long)nx : 0;
+  const double c2 = 2.0 * P.ih * P.ih;  // a_f = c2 / (rho_L + rho_R)
+  auto rho = [&](R av) { return mixp((double)av, P.rho1, P.rho2); };
+  auto plane = [&](int kk) { return (size_t)min(max(kk, 0), nz - 1) * pl; };
   double vb = 0.0, vr = 0.0;
-  if (i < nx && j < ny) {
-    const long c = cidx(i, j, k, nx, ny);
-    const double rhs = -(b[c] - scal[S_MEAN]);
-    const double rr = rhs - applyK<double, DIM>(p, ax, ay, az, i, j, k, nx, ny, nz);
-    r[c] = rr;
-    vb = rhs * rhs;
-    vr = rr * rr;
+  double pm = p[col + plane(k0 - 1)], pc = p[col + plane(k0)], pp = p[col + plane(k0 + 1)];
+  R am = a[col + plane(k0 - 1)], ac = a[col + plane(k0)], ap = a[col + plane(k0 + 1)];
+  double wz = c2 * rcp64(rho(am) + rho(ac));  // face k-1 | k
+  for (int k = k0; k < k1; ++k) {
+    const double pn = p[col + plane(k + 2)];
+    const R an = a[col + plane(k + 2)];
+    const size_t c = col + (size_t)k * pl;
+    const double rc = rho(ac);
+    double sK = 0.0;
+    auto term = [&](double pnb, R anb) { return c2 * rcp64(rho(anb) + rc) * (pc - pnb); };
+    double wzn = 0.0;
+    if (act) {
+      if (oxm) sK += term(p[c + oxm], a[c + oxm]);
+      if (oxp) sK += term(p[c + oxp], a[c + oxp]);
+      if (oym) sK += term(p[c + oym], a[c + oym]);
+      if (oyp) sK += term(p[c + oyp], a[c + oyp]);
+      if (DIM == 3) {
+        if (k > 0) sK += wz * (pc - pm);
+        wzn = c2 * rcp64(rc + rho(ap));
+        if (k < nz - 1) sK += wzn * (pc - pp);
+      }
+      const double rhs = -(b[c] - scal[S_MEAN]);
+      const double rr = rhs - sK;
+      r[c] = rr;
+      vb += rhs * rhs;
+      vr += rr * rr;
+    }
+    wz = wzn;
+    pm = pc;
+    pc = pp;
+    pp = pn;
+    am = ac;
+    ac = ap;
+    ap = an;
   }
   const double sb = block_reduce<0>(vb, sh);
   const double sr = block_reduce<0>(vr, sh);
@@ -515,6 +576,43 @@ __global__ __launch_bounds__(256) void k_resid64(int nx, int ny, int nz, const d
     pbb[block_linear()] = sb;
     prr[block_linear()] = sr;
   }
+}
+
+// First coarse level's face weights straight from alpha: the sum of the
+// 2x2 fine face weights it covers, each (float)((1/h^2) / (0.5 (rho_L +
+// rho_R))) as the fine weights of the FP32 hierarchy are defined.
+template <class R, int DIM, int D>
+__global__ __launch_bounds__(256) void k_coarsen_a(KParams P, const R* __restrict__ a, int cnx, int cny, int cnz,
+                                                   R* __restrict__ cf) {
+  const int I = blockIdx.x * BX + threadIdx.x, J = blockIdx.y * BY + threadIdx.y, K = blockIdx.z;
+  const int cfx = cnx + (D == 0), cfy = cny + (D == 1);
+  if (I >= cfx || J >= cfy) return;
+  const int nx = P.nx, ny = P.ny, nz = P.nz;
+  const int kz = DIM == 3 ? 2 : 1;
+  const double ih2 = P.ih * P.ih;
+  // fine face (i, j, k) along D, between cells (i, j, k) - e_D and (i, j, k)
+  auto wf = [&](int i, int j, int k) -> R {
+    const int id[3] = {i, j, k};
+    const int nD = D == 0 ? nx : (D == 1 ? ny : nz);
+    if (id[D] <= 0 || id[D] >= nD) return R(0);
+    int L[3] = {i, j, k};
+    L[D] -= 1;
+    const double rL = mixp((double)a[cidx(L[0], L[1], L[2], nx, ny)], P.rho1, P.rho2);
+    const double rR = mixp((double)a[cidx(i, j, k, nx, ny)], P.rho1, P.rho2);
+    return R(ih2 / (0.5 * (rL + rR)));
+  };
+  R s = R(0);
+  if (D == 0) {
+    for (int dk = 0; dk < kz; ++dk)
+      for (int dj = 0; dj < 2; ++dj) s += wf(2 * I, 2 * J + dj, kz * K + dk);
+  } else if (D == 1) {
+    for (int dk = 0; dk < kz; ++dk)
+      for (int di = 0; di < 2; ++di) s += wf(2 * I + di, 2 * J, kz * K + dk);
+  } else {
+    for (int dj = 0; dj < 2; ++dj)
+      for (int di = 0; di < 2; ++di) s += wf(2 * I + di, 2 * J + dj, 2 * K);
+  }
+  cf[fidx<D>(I, J, K, cnx, cny)] = s;
 }
 
 __global__ __launch_bounds__(256) void k_scale_to32(long n, const double* __restrict__ r,
@@ -758,11 +856,14 @@ void mg_smooth(hipStream_t s, int dim, const Level<R>& L, const R* b, const R* x
 }
 
 template <class R>
-void mg_resid_restrict(hipStream_t s, int dim, const Level<R>& F, const R* b, const R* x, R* bc, const int* iflag) {
+void mg_resid_restrict(hipStream_t s, int dim, const Level<R>& F, const R* b, const R* x, R* bc, const R* wdc,
+                       R* x1c, double om0, const int* iflag) {
   const int cnx = F.nx / 2, cny = F.ny / 2, cnz = dim == 3 ? F.nz / 2 : 1;
   dim3 g = grid_for(cnx, cny, cnz);
-  if (dim == 3) hipLaunchKernelGGL((k_resid_restrict<R, 3>), g, blk(), 0, s, F, cnx, cny, cnz, b, x, bc, iflag);
-  else hipLaunchKernelGGL((k_resid_restrict<R, 2>), g, blk(), 0, s, F, cnx, cny, cnz, b, x, bc, iflag);
+  if (dim == 3)
+    hipLaunchKernelGGL((k_resid_restrict<R, 3>), g, blk(), 0, s, F, cnx, cny, cnz, b, x, bc, wdc, x1c, R(om0), iflag);
+  else
+    hipLaunchKernelGGL((k_resid_restrict<R, 2>), g, blk(), 0, s, F, cnx, cny, cnz, b, x, bc, wdc, x1c, R(om0), iflag);
 }
 
 template <class R>
@@ -806,11 +907,31 @@ void finalize(hipStream_t s, const double* part, int nparts, double* scal, int* 
 
 void init_flags(hipStream_t s, int* iflag) { hipLaunchKernelGGL(k_init_flags, dim3(1), dim3(64), 0, s, iflag); }
 
-void resid64(hipStream_t s, int dim, int nx, int ny, int nz, const double* ax, const double* ay, const double* az,
-             const double* b, const double* scal, const double* p, double* r, double* pbb, double* prr) {
-  dim3 g = grid_for(nx, ny, nz);
-  if (dim == 3) hipLaunchKernelGGL((k_resid64<3>), g, blk(), 0, s, nx, ny, nz, ax, ay, az, b, scal, p, r, pbb, prr);
-  else hipLaunchKernelGGL((k_resid64<2>), g, blk(), 0, s, nx, ny, nz, ax, ay, az, b, scal, p, r, pbb, prr);
+template <class R>
+int resid64a(const KParams& P, hipStream_t s, const R* a, const double* b, const double* scal, const double* p,
+             double* r, double* pbb, double* prr) {
+  // chunks of planes so that the grid has >= 2048 blocks of 256
+  const int ntx = (P.nx + BX - 1) / BX, nty = (P.ny + BY - 1) / BY;
+  const int nz = P.dim == 3 ? P.nz : 1;
+  int nch = std::max(1, std::min(nz, (2048 + ntx * nty - 1) / (ntx * nty)));
+  const int kz = (nz + nch - 1) / nch;
+  nch = (nz + kz - 1) / kz;
+  dim3 g(ntx, nty, nch);
+  if (P.dim == 3) hipLaunchKernelGGL((k_resid64a<R, 3>), g, blk(), 0, s, P, kz, a, b, scal, p, r, pbb, prr);
+  else hipLaunchKernelGGL((k_resid64a<R, 2>), g, blk(), 0, s, P, kz, a, b, scal, p, r, pbb, prr);
+  return ntx * nty * nch;
+}
+
+template <class R>
+void coarsen_from_alpha(const KParams& P, hipStream_t s, const R* a, const Level<R>& C) {
+  if (P.dim == 3) {
+    hipLaunchKernelGGL((k_coarsen_a<R, 3, 0>), grid_for(C.nx + 1, C.ny, C.nz), blk(), 0, s, P, a, C.nx, C.ny, C.nz, C.ax);
+    hipLaunchKernelGGL((k_coarsen_a<R, 3, 1>), grid_for(C.nx, C.ny + 1, C.nz), blk(), 0, s, P, a, C.nx, C.ny, C.nz, C.ay);
+    hipLaunchKernelGGL((k_coarsen_a<R, 3, 2>), grid_for(C.nx, C.ny, C.nz + 1), blk(), 0, s, P, a, C.nx, C.ny, C.nz, C.az);
+  } else {
+    hipLaunchKernelGGL((k_coarsen_a<R, 2, 0>), grid_for(C.nx + 1, C.ny, 1), blk(), 0, s, P, a, C.nx, C.ny, C.nz, C.ax);
+    hipLaunchKernelGGL((k_coarsen_a<R, 2, 1>), grid_for(C.nx, C.ny + 1, 1), blk(), 0, s, P, a, C.nx, C.ny, C.nz, C.ay);
+  }
 }
 
 void scale_to32(hipStream_t s, long n, const double* r, const double* scal, float* r32) {
@@ -890,6 +1011,9 @@ void zero_walls(const KParams& P, hipStream_t s, R* u, R* v, R* w) {
                                 float*);                                                                          \
   template void make_wdiag<R>(hipStream_t, int, const Level<R>&, double);                                         \
   template void coarsen_weights<R>(hipStream_t, int, const Level<R>&, const Level<R>&);                           \
+  template void coarsen_from_alpha<R>(const KParams&, hipStream_t, const R*, const Level<R>&);                    \
+  template int resid64a<R>(const KParams&, hipStream_t, const R*, const double*, const double*, const double*,    \
+                           double*, double*, double*);                                                          \
   template void rhs_resid<R>(hipStream_t, int, const Level<R>&, const double*, const double*, R*, R*, double*,    \
                              double*);                                                                      \
   template void spmv_dot<R>(hipStream_t, int, const Level<R>&, const R*, R*, double*, const int*);          \
@@ -897,7 +1021,8 @@ void zero_walls(const KParams& P, hipStream_t s, R* u, R* v, R* w) {
   template void update_d<R>(hipStream_t, long, const double*, const R*, R*, int, const int*);                     \
   template void mg_smooth_first<R>(hipStream_t, const Level<R>&, const R*, R*, double, const int*);                       \
   template void mg_smooth<R>(hipStream_t, int, const Level<R>&, const R*, const R*, R*, double, double*, const int*);                                                                         \
-  template void mg_resid_restrict<R>(hipStream_t, int, const Level<R>&, const R*, const R*, R*, const int*);      \
+  template void mg_resid_restrict<R>(hipStream_t, int, const Level<R>&, const R*, const R*, R*, const R*, R*,     \
+                                     double, const int*);                                                   \
   template void mg_prolong_smooth<R>(hipStream_t, int, const Level<R>&, const Level<R>&, const R*, const R*, R*,  \
                                      double, double, double*, const int*);                                  \
   template void mg_coarse_solve<R>(hipStream_t, int, const Level<R>&, const R*, R*, int, double, const int*);             \
