@@ -265,11 +265,12 @@ __device__ __forceinline__ void write_partial(double acc, double* part) {
   if (threadIdx.x == 0 && threadIdx.y == 0) part[blockIdx.x] = s;
 }
 
-// d' = z + beta d (d' = z on the first iteration); q = K0 d'; partial d'.q
+// d' = z + beta d (d' = z on the first iteration); partial d'.K0 d' (K0 d'
+// itself is not stored: the update pass recomputes it from d')
 template <class R, int DIM>
 __global__ __launch_bounds__(FX * FY) void k0_spmv_upd(Op0<R> op, int kz, int ntx, int nty, const R* __restrict__ z,
                                                    const R* __restrict__ dold, R* __restrict__ dnew,
-                                                   R* __restrict__ q, const double* __restrict__ scal, int first,
+                                                   const double* __restrict__ scal, int first,
                                                    double* __restrict__ part, const int* __restrict__ iflag) {
   if (iflag[I_DONE]) return;
   const Tile T = tile_of(op.nx, op.ny, op.nz, ntx, nty, kz);
@@ -282,36 +283,36 @@ __global__ __launch_bounds__(FX * FY) void k0_spmv_upd(Op0<R> op, int kz, int nt
   auto pre = [&](long) { return Empty{}; };
   auto body = [&](long c, int, R xc, R Kx, R, const Empty&) {
     dnew[c] = xc;
-    q[c] = Kx;
     acc += (double)xc * (double)Kx;
   };
   march<R, DIM, true, false>(op, T, X, XV, pre, body, NoPost());
   write_partial(acc, part);
 }
 
-// x += alpha d; r -= alpha q (partial r.r); z1 = omega r / diag (first sweep
-// of the next V-cycle from a zero guess)
+// x += alpha d; r -= alpha K0 d (K0 d recomputed from the streamed d, the
+// same arithmetic as the SpMV pass; partial r.r); z1 = omega r / diag (first
+// sweep of the next V-cycle from a zero guess)
 template <class R, int DIM>
 __global__ __launch_bounds__(FX * FY) void k0_update_smooth(Op0<R> op, int kz, int ntx, int nty, R omega,
                                                         const double* __restrict__ scal, R* __restrict__ x,
                                                         R* __restrict__ r, const R* __restrict__ d,
-                                                        const R* __restrict__ q, R* __restrict__ z1,
-                                                        double* __restrict__ part, const int* __restrict__ iflag) {
+                                                        R* __restrict__ z1, double* __restrict__ part,
+                                                        const int* __restrict__ iflag) {
   if (iflag[I_DONE]) return;
   const Tile T = tile_of(op.nx, op.ny, op.nz, ntx, nty, kz);
   const R al = R(scal[S_ALPHA]);
   double acc = 0.0;
-  auto X = [&](long, int, int, int) { return R(0); };
-  auto pre = [&](long c) { return Vec4<R>{x[c], r[c], d[c], q[c]}; };
+  auto X = [&](long c, int, int, int) { return d[c]; };
+  auto pre = [&](long c) { return Vec2<R>{x[c], r[c]}; };
   const Ident<R> XV;
-  auto body = [&](long c, int, R, R, R dg, const Vec4<R>& v) {
-    x[c] = v.a + al * v.c;
-    const R rn = v.b - al * v.d;
+  auto body = [&](long c, int, R dc, R Kd, R dg, const Vec2<R>& v) {
+    x[c] = v.a + al * dc;
+    const R rn = v.b - al * Kd;
     r[c] = rn;
     acc += (double)rn * (double)rn;
     z1[c] = omega * recip(dg) * rn;
   };
-  march<R, DIM, false, false>(op, T, X, XV, pre, body, NoPost());
+  march<R, DIM, true, false>(op, T, X, XV, pre, body, NoPost());
   write_partial(acc, part);
 }
 
@@ -435,30 +436,30 @@ Op0<R> op_of(const Fine<R>& F) {
 int fine_blocks(int nx, int ny, int nz) { return plan(nx, ny, nz).nblocks; }
 
 template <class R>
-int fine_spmv_upd(hipStream_t s, int dim, const Fine<R>& F, const R* z, const R* dold, R* dnew, R* q,
+int fine_spmv_upd(hipStream_t s, int dim, const Fine<R>& F, const R* z, const R* dold, R* dnew,
                   const double* scal, int first, double* part, const int* iflag) {
   const Launch L = plan(F.nx, F.ny, F.nz);
   const Op0<R> op = op_of(F);
   if (dim == 3)
     hipLaunchKernelGGL((k0_spmv_upd<R, 3>), dim3(L.nblocks), dim3(FX, FY), 0, s, op, L.kz, L.ntx, L.nty, z, dold, dnew,
-                       q, scal, first, part, iflag);
+                       scal, first, part, iflag);
   else
     hipLaunchKernelGGL((k0_spmv_upd<R, 2>), dim3(L.nblocks), dim3(FX, FY), 0, s, op, L.kz, L.ntx, L.nty, z, dold, dnew,
-                       q, scal, first, part, iflag);
+                       scal, first, part, iflag);
   return L.nblocks;
 }
 
 template <class R>
 int fine_update_smooth(hipStream_t s, int dim, const Fine<R>& F, double omega, const double* scal, R* x, R* r,
-                       const R* d, const R* q, R* z1, double* part, const int* iflag) {
+                       const R* d, R* z1, double* part, const int* iflag) {
   const Launch L = plan(F.nx, F.ny, F.nz);
   const Op0<R> op = op_of(F);
   if (dim == 3)
     hipLaunchKernelGGL((k0_update_smooth<R, 3>), dim3(L.nblocks), dim3(FX, FY), 0, s, op, L.kz, L.ntx, L.nty, R(omega),
-                       scal, x, r, d, q, z1, part, iflag);
+                       scal, x, r, d, z1, part, iflag);
   else
     hipLaunchKernelGGL((k0_update_smooth<R, 2>), dim3(L.nblocks), dim3(FX, FY), 0, s, op, L.kz, L.ntx, L.nty, R(omega),
-                       scal, x, r, d, q, z1, part, iflag);
+                       scal, x, r, d, z1, part, iflag);
   return L.nblocks;
 }
 
@@ -512,10 +513,10 @@ void fine_resid_restrict(hipStream_t s, int dim, const Fine<R>& F, const R* b, c
 }
 
 #define TCF_FINE_INST(R)                                                                                          \
-  template int fine_spmv_upd<R>(hipStream_t, int, const Fine<R>&, const R*, const R*, R*, R*, const double*, int, \
+  template int fine_spmv_upd<R>(hipStream_t, int, const Fine<R>&, const R*, const R*, R*, const double*, int,     \
                                 double*, const int*);                                                             \
   template int fine_update_smooth<R>(hipStream_t, int, const Fine<R>&, double, const double*, R*, R*, const R*,   \
-                                     const R*, R*, double*, const int*);                                          \
+                                     R*, double*, const int*);                                                    \
   template void fine_smooth_first<R>(hipStream_t, int, const Fine<R>&, double, const R*, R*, const int*);         \
   template int fine_smooth<R>(hipStream_t, int, const Fine<R>&, double, const R*, const R*, R*, const R*, int,    \
                               int, double, double*, const int*);                                                  \

@@ -59,7 +59,7 @@ struct Fields {
   R *sk, *Mx, *My, *Mz;                    // sigma*kappa, Marangoni vector
   R *us, *vs, *ws;                         // predictor
   std::vector<Level<R>> lv;                // Poisson levels (level 0 = fine)
-  R *r, *z, *z2, *d, *d2, *q;              // PCG vectors on the fine level (d ping-pong)
+  R *r, *z, *z2, *d, *d2;                  // PCG vectors on the fine level (d ping-pong)
   R* x;                                    // FP32 mode: inner correction e
   R* cinv = nullptr;                       // dense inverse of the coarsest level (if small)
   double* cfac = nullptr;                  // FP64 scratch of its factorisation
@@ -205,7 +205,6 @@ void carve_fields(Carver& cv, const Dims& D, Fields<R>& F, int mg_levels, bool a
   F.z2 = cv.take<R>(N);
   F.d = cv.take<R>(N);
   F.d2 = cv.take<R>(N);
-  F.q = cv.take<R>(N);
   F.x = alias_state ? nullptr : cv.take<R>(N);
   auto ld = level_dims(D, mg_levels);
   F.lv.clear();
@@ -515,11 +514,11 @@ tcf_status pcg_iterate(tcf_grid* g, Fields<R>& F, R* x, R* r, int maxit, int* it
   for (int it = 1; it <= maxit; ++it) {
     {
       Prof pr(g, FAM_SPMV);
-      np = fine_spmv_upd<R>(s, dim, Fd, F.z, dcur, dnext, F.q, g->scal, it == 1 ? 1 : 0, g->part[0], g->iflag);
+      np = fine_spmv_upd<R>(s, dim, Fd, F.z, dcur, dnext, g->scal, it == 1 ? 1 : 0, g->part[0], g->iflag);
     }
     finalize(s, g->part[0], np, g->scal, g->iflag, F_ALPHA, 0, 0.0);
     std::swap(dcur, dnext);
-    np = fine_update_smooth<R>(s, dim, Fd, wj, g->scal, x, r, dcur, F.q, F.z2, g->part[0], g->iflag);
+    np = fine_update_smooth<R>(s, dim, Fd, wj, g->scal, x, r, dcur, F.z2, g->part[0], g->iflag);
     finalize(s, g->part[0], np, g->scal, g->iflag, F_RR, 0, 1.0);
     vcycle<R>(g, F, 0, r, F.z, F.z2, g->part[0], true, &np);
     finalize(s, g->part[0], np, g->scal, g->iflag, F_RZ, 0, 0.0);

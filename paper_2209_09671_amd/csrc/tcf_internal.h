@@ -110,11 +110,11 @@ void mg_coarse_solve(hipStream_t s, int dim, const Level<R>& L, const R* b, R* x
 // finest-level fused kernels (tcf_fine.hip); return the number of partials
 int fine_blocks(int nx, int ny, int nz);
 template <class R>
-int fine_spmv_upd(hipStream_t s, int dim, const Fine<R>& F, const R* z, const R* dold, R* dnew, R* q,
+int fine_spmv_upd(hipStream_t s, int dim, const Fine<R>& F, const R* z, const R* dold, R* dnew,
                   const double* scal, int first, double* part, const int* iflag);
 template <class R>
 int fine_update_smooth(hipStream_t s, int dim, const Fine<R>& F, double omega, const double* scal, R* x, R* r,
-                       const R* d, const R* q, R* z1, double* part, const int* iflag);
+                       const R* d, R* z1, double* part, const int* iflag);
 template <class R>
 void fine_smooth_first(hipStream_t s, int dim, const Fine<R>& F, double omega, const R* b, R* z1, const int* iflag);
 template <class R>
