@@ -40,7 +40,8 @@ class OrcConfig(C.Structure):
                 ("weno_eps", C.c_double), ("normal_eps", C.c_double),
                 ("p_rtol", C.c_double), ("p_maxit", C.c_int), ("mg_nu", C.c_int),
                 ("mg_omega_c", C.c_double), ("mg_coarse_sweeps", C.c_int),
-                ("sigkap_const", C.c_double)]
+                ("sigkap_const", C.c_double),
+                ("species", C.c_int), ("dsigma_dc", C.c_double), ("c0", C.c_double)]
 
 
 class OrcInfo(C.Structure):
@@ -91,6 +92,8 @@ def make_config(c: dict, flags: int = 0, sigkap_const: float = 0.0) -> OrcConfig
     o.mg_omega_c = 1.9
     o.mg_coarse_sweeps = 30
     o.sigkap_const = sigkap_const
+    o.species = int(c.get("species", 0))
+    o.dsigma_dc, o.c0 = float(c.get("dsigma_dc", 0.0)), float(c.get("c0", 0.0))
     return o
 
 
@@ -127,33 +130,37 @@ def transport_rhs(c, t, alpha, T, u, v, w=None, flags=0):
     return La, LT
 
 
-def transport_step(c, t, dt, alpha, T, u, v, w=None, flags=0):
+def transport_step(c, t, dt, alpha, T, u, v, w=None, flags=0, cfield=None):
+    """One SSP-RK3 transport step; returns (alpha, T) or, with a species
+    field, (alpha, T, c)."""
     o = make_config(c, flags)
     a = _f64(alpha).copy()
     TT = _f64(T).copy()
+    cc = None if cfield is None else _f64(cfield).copy()
     u, v, w = map(_f64, (u, v, w))
-    lib().orc_transport_step(C.byref(o), C.c_double(t), C.c_double(dt), _p(a), _p(TT), _p(u), _p(v), _p(w))
-    return a, TT
+    lib().orc_transport_step(C.byref(o), C.c_double(t), C.c_double(dt), _p(a), _p(TT), _p(u), _p(v), _p(w),
+                             _p(cc))
+    return (a, TT) if cc is None else (a, TT, cc)
 
 
-def geometry(c, alpha, T, flags=0, sigkap_const=0.0):
+def geometry(c, alpha, T, flags=0, sigkap_const=0.0, cfield=None):
     o = make_config(c, flags, sigkap_const)
-    alpha, T = _f64(alpha), _f64(T)
+    alpha, T, cf = _f64(alpha), _f64(T), _f64(cfield)
     N = alpha.size
     n = np.empty((N, 3))
     kap, ds, sk = (np.empty_like(alpha) for _ in range(3))
     M = np.empty((N, 3))
-    lib().orc_geometry(C.byref(o), _p(alpha), _p(T), _p(n), _p(kap), _p(ds), _p(sk), _p(M))
+    lib().orc_geometry(C.byref(o), _p(alpha), _p(T), _p(n), _p(kap), _p(ds), _p(sk), _p(M), _p(cf))
     return dict(n=n, kappa=kap, delta_s=ds, sigkap=sk, M=M)
 
 
-def predictor(c, dt, alpha, T, u, v, w=None, flags=0, sigkap_const=0.0):
+def predictor(c, dt, alpha, T, u, v, w=None, flags=0, sigkap_const=0.0, cfield=None):
     o = make_config(c, flags, sigkap_const)
-    alpha, T, u, v, w = map(_f64, (alpha, T, u, v, w))
+    alpha, T, u, v, w, cf = map(_f64, (alpha, T, u, v, w, cfield))
     us, vs = np.empty_like(u), np.empty_like(v)
     ws = np.empty_like(w) if w is not None else None
     lib().orc_predictor(C.byref(o), C.c_double(dt), _p(alpha), _p(T), _p(u), _p(v), _p(w),
-                        _p(us), _p(vs), _p(ws))
+                        _p(us), _p(vs), _p(ws), _p(cf))
     return us, vs, ws
 
 
@@ -208,7 +215,8 @@ def project(c, dt, alpha, p, us, vs, ws=None):
 
 
 def step(c, state, t, dt, nsteps=1, flags=0, sigkap_const=0.0, rtol=None):
-    """Run nsteps full steps; returns (new_state, info dict, status)."""
+    """Run nsteps full steps; returns (new_state, info dict, status).  A
+    species field travels as state["c"] (used when the config has species)."""
     cc = dict(c)
     if rtol is not None:
         cc["oracle_rtol"] = rtol
@@ -217,5 +225,5 @@ def step(c, state, t, dt, nsteps=1, flags=0, sigkap_const=0.0, rtol=None):
     info = OrcInfo()
     st = lib().orc_step(C.byref(o), C.c_double(t), C.c_double(dt), C.c_int(nsteps),
                         _p(s["alpha"]), _p(s["T"]), _p(s["u"]), _p(s["v"]), _p(s["w"]), _p(s["p"]),
-                        C.byref(info))
+                        C.byref(info), _p(s.get("c")))
     return s, info.as_dict(), st

@@ -44,6 +44,10 @@ struct OrcConfig {
   double mg_omega_c;
   int mg_coarse_sweeps;
   double sigkap_const;
+  // solutal Marangoni (in-situ alloying, eq. 5): a species field c carried
+  // like alpha, sigma = sigma0 + dsigma_dT (T - T0) + dsigma_dc (c - c0)
+  int species;
+  double dsigma_dc, c0;
 };
 
 struct OrcInfo {
@@ -66,6 +70,7 @@ struct Grid {
   int nx, ny, nz, dim;
   double h;
   bool per;
+  const double* cf = nullptr;  // species field (read by the geometry when c.species)
   explicit Grid(const OrcConfig& cc)
       : c(cc), nx(cc.nx), ny(cc.ny), nz(cc.dim == 2 ? 1 : cc.nz), dim(cc.dim), h(cc.h),
         per((cc.flags & F_PERIODIC) != 0) {}
@@ -293,11 +298,58 @@ void transport_rhs(const Grid& g, double t, const double* a, const double* T, co
       }
 }
 
-// S1: SSP-RK3 (Shu-Osher) for alpha and T with the face velocity frozen.
+// Species right-hand side Lc = -div(u c): the same WENO5 upwind flux as alpha
+// (eq. 1 with c in place of alpha), with even ghosts (no flux through walls).
+// reading: the species is carried without diffusion.
+void advect_rhs(const Grid& g, const double* q, const double* u, const double* v, const double* w, double* Lq) {
+  const double h = g.h, eps = g.c.weno_eps;
+  const int nx = g.nx, ny = g.ny, nz = g.nz;
+  std::vector<double> F[3];
+  const double* vel[3] = {u, v, w};
+  for (int d = 0; d < g.dim; ++d) {
+    long nf = d == 0 ? g.Nu() : (d == 1 ? g.Nv() : g.Nw());
+    F[d].assign(nf, 0.0);
+    int fnx = nx + (d == 0), fny = ny + (d == 1), fnz = nz + (d == 2);
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int k = 0; k < fnz; ++k)
+      for (int j = 0; j < fny; ++j)
+        for (int i = 0; i < fnx; ++i) {
+          long fi = (long)i + (long)fnx * (j + (long)fny * k);
+          int m = d == 0 ? i : (d == 1 ? j : k);
+          if (m == 0 || m == g.n_of(d)) continue;  // wall: zero flux
+          double uf = vel[d][fi];
+          auto qq = [&](int mm) {
+            return d == 0 ? A(g, q, mm, j, k) : (d == 1 ? A(g, q, i, mm, k) : A(g, q, i, j, mm));
+          };
+          F[d][fi] = uf * upwind_weno(qq, m, uf, eps);
+        }
+  }
+#pragma omp parallel for collapse(2) schedule(static)
+  for (int k = 0; k < nz; ++k)
+    for (int j = 0; j < ny; ++j)
+      for (int i = 0; i < nx; ++i) {
+        double div = (F[0][g.fx(i + 1, j, k)] - F[0][g.fx(i, j, k)]) + (F[1][g.fy(i, j + 1, k)] - F[1][g.fy(i, j, k)]);
+        if (g.dim == 3) div += F[2][g.fz(i, j, k + 1)] - F[2][g.fz(i, j, k)];
+        Lq[g.cell(i, j, k)] = -div / h;
+      }
+}
+
+// S1: SSP-RK3 (Shu-Osher) for alpha and T (and the species c, when given)
+// with the face velocity frozen.
 // reading: the paper does not state its time integrator.
 void transport_rk3(const Grid& g, double t, double dt, std::vector<double>& a, std::vector<double>& T,
-                   const double* u, const double* v, const double* w) {
+                   const double* u, const double* v, const double* w, std::vector<double>* cs = nullptr) {
   long N = g.N();
+  if (cs) {  // the species: the same three stages with its own right-hand side
+    std::vector<double>& c = *cs;
+    std::vector<double> Lc(N), c1(N), c2(N);
+    advect_rhs(g, c.data(), u, v, w, Lc.data());
+    for (long q = 0; q < N; ++q) c1[q] = c[q] + dt * Lc[q];
+    advect_rhs(g, c1.data(), u, v, w, Lc.data());
+    for (long q = 0; q < N; ++q) c2[q] = 0.75 * c[q] + 0.25 * (c1[q] + dt * Lc[q]);
+    advect_rhs(g, c2.data(), u, v, w, Lc.data());
+    for (long q = 0; q < N; ++q) c[q] = c[q] / 3.0 + 2.0 / 3.0 * (c2[q] + dt * Lc[q]);
+  }
   std::vector<double> La(N), LT(N), a1(N), T1(N), a2(N), T2(N);
   transport_rhs(g, t, a.data(), T.data(), u, v, w, La.data(), LT.data());
   for (long c = 0; c < N; ++c) {
@@ -322,7 +374,9 @@ void transport_rk3(const Grid& g, double t, double dt, std::vector<double>& a, s
 // Outputs: n (3N), kappa, delta_s, sigma*kappa, Marangoni vector M (3N).
 // reading: kappa = -div(n) by central differences of cell-centre normals;
 // M = delta_s (grad sigma - n (n . grad sigma)), the tangential part of the
-// surface-tension gradient; sigma = sigma0 + dsigma_dT (T - T0).
+// surface-tension gradient; sigma = sigma0 + dsigma_dT (T - T0), plus
+// dsigma_dc (c - c0) with a species field, whose gradient enters grad sigma
+// by the chain rule of eq. 5 (central differences, even ghosts).
 void geometry(const Grid& g, const double* a, const double* T, double* nout, double* kap,
               double* ds, double* sk, double* M) {
   const OrcConfig& c = g.c;
@@ -359,6 +413,13 @@ void geometry(const Grid& g, const double* a, const double* T, double* nout, dou
         gs[0] = c.dsigma_dT * (Tg(g, T, i + 1, j, k) - Tg(g, T, i - 1, j, k)) * ih2;
         gs[1] = c.dsigma_dT * (Tg(g, T, i, j + 1, k) - Tg(g, T, i, j - 1, k)) * ih2;
         gs[2] = g.dim == 3 ? c.dsigma_dT * (Tg(g, T, i, j, k + 1) - Tg(g, T, i, j, k - 1)) * ih2 : 0.0;
+        if (c.species && g.cf) {
+          const double* q = g.cf;
+          sigma += c.dsigma_dc * (q[ci] - c.c0);
+          gs[0] += c.dsigma_dc * (A(g, q, i + 1, j, k) - A(g, q, i - 1, j, k)) * ih2;
+          gs[1] += c.dsigma_dc * (A(g, q, i, j + 1, k) - A(g, q, i, j - 1, k)) * ih2;
+          if (g.dim == 3) gs[2] += c.dsigma_dc * (A(g, q, i, j, k + 1) - A(g, q, i, j, k - 1)) * ih2;
+        }
         const double* n = &nn[3 * eidx(i, j, k)];
         double ndg = n[0] * gs[0] + n[1] * gs[1] + n[2] * gs[2];
         for (int d = 0; d < 3; ++d) {
@@ -794,15 +855,18 @@ void orc_transport_rhs(const OrcConfig* c, double t, const double* a, const doub
   transport_rhs(g, t, a, T, u, v, w, La, LT);
 }
 
+// cf: species field (NULL without one)
 void orc_geometry(const OrcConfig* c, const double* a, const double* T, double* n, double* kap,
-                  double* ds, double* sk, double* M) {
+                  double* ds, double* sk, double* M, const double* cf) {
   Grid g(*c);
+  g.cf = cf;
   geometry(g, a, T, n, kap, ds, sk, M);
 }
 
 void orc_predictor(const OrcConfig* c, double dt, const double* a, const double* T, const double* u,
-                   const double* v, const double* w, double* us, double* vs, double* ws) {
+                   const double* v, const double* w, double* us, double* vs, double* ws, const double* cf) {
   Grid g(*c);
+  g.cf = cf;
   predictor(g, dt, a, T, u, v, w, us, vs, ws);
 }
 
@@ -846,26 +910,33 @@ void orc_project(const OrcConfig* c, double dt, const double* a, const double* p
 }
 
 void orc_transport_step(const OrcConfig* c, double t, double dt, double* a, double* T, const double* u,
-                        const double* v, const double* w) {
+                        const double* v, const double* w, double* cf) {
   Grid g(*c);
   std::vector<double> av(a, a + g.N()), tv(T, T + g.N());
-  transport_rk3(g, t, dt, av, tv, u, v, w);
+  std::vector<double> cv;
+  if (cf) cv.assign(cf, cf + g.N());
+  transport_rk3(g, t, dt, av, tv, u, v, w, cf ? &cv : nullptr);
   std::memcpy(a, av.data(), sizeof(double) * g.N());
   std::memcpy(T, tv.data(), sizeof(double) * g.N());
+  if (cf) std::memcpy(cf, cv.data(), sizeof(double) * g.N());
 }
 
 // nsteps full steps S1..S8, state updated in place; t advances by dt per step.
+// cf: species field (NULL without one), advanced in place with the state.
 int orc_step(const OrcConfig* c, double t0, double dt, int nsteps, double* a, double* T, double* u,
-             double* v, double* w, double* p, OrcInfo* info) {
+             double* v, double* w, double* p, OrcInfo* info, double* cf) {
   Grid g(*c);
   long N = g.N();
   std::vector<double> av(a, a + N), tv(T, T + N);
+  std::vector<double> cv;
+  if (cf) cv.assign(cf, cf + N);
+  g.cf = cf ? cv.data() : nullptr;
   std::vector<double> us(g.Nu()), vs(g.Nv()), ws(g.Nw() ? g.Nw() : 1), b(N), dv(N);
   int status = 0;
   OrcInfo inf{};
   for (int s = 0; s < nsteps; ++s) {
     double t = t0 + s * dt;
-    transport_rk3(g, t, dt, av, tv, u, v, w);
+    transport_rk3(g, t, dt, av, tv, u, v, w, cf ? &cv : nullptr);
     if (!(c->flags & F_TRANSPORT_ONLY)) {
       predictor(g, dt, av.data(), tv.data(), u, v, w, us.data(), vs.data(), ws.data());
       divergence(g, us.data(), vs.data(), g.dim == 3 ? ws.data() : nullptr, b.data());
@@ -884,6 +955,7 @@ int orc_step(const OrcConfig* c, double t0, double dt, int nsteps, double* a, do
   }
   std::memcpy(a, av.data(), sizeof(double) * N);
   std::memcpy(T, tv.data(), sizeof(double) * N);
+  if (cf) std::memcpy(cf, cv.data(), sizeof(double) * N);
   inf.sum_alpha = sum(a, N);
   inf.alpha_min = *std::min_element(a, a + N);
   inf.alpha_max = *std::max_element(a, a + N);

@@ -206,6 +206,44 @@ def initial_state(c) -> dict:
     return st
 
 
+def with_species(c, dsigma_dc, kind="linear_x", c0=0.0, seed=5) -> dict:
+    """Config with a species field c (solutal Marangoni): sigma gains
+    dsigma_dc (c - c0).  The field itself comes from species_field(c)."""
+    out = dict(c)
+    out.update(species=1, dsigma_dc=float(dsigma_dc), c0=float(c0), species_kind=kind, species_seed=seed)
+    return out
+
+
+def species_field(c) -> np.ndarray:
+    """Initial species field of a config made by with_species, float64, cell
+    layout.  linear_x: c = x / L_x.  blob: a smooth seeded Gaussian bump of
+    amplitude 1 (centre and width from the seed).  alpha: a copy of the
+    initial volume fraction."""
+    s = shapes(c)
+    x, y, z = cell_centres(c)
+    kind = c.get("species_kind", "linear_x")
+    if kind == "alpha":
+        return initial_state(c)["alpha"].copy()
+    if c["dim"] == 2:
+        Y, X = np.meshgrid(y, x, indexing="ij")
+        X, Y, Z = X[None], Y[None], np.zeros_like(X[None])
+    else:
+        Z, Y, X = np.meshgrid(z, y, x, indexing="ij")
+    lx = c["nx"] * c["h"]
+    if kind == "linear_x":
+        f = X / lx
+    elif kind == "blob":
+        rng = np.random.default_rng(c.get("species_seed", 5))
+        ly, lz = c["ny"] * c["h"], c["nz"] * c["h"]
+        ctr = rng.uniform(0.3, 0.7, 3) * np.array([lx, ly, lz])
+        wid = rng.uniform(0.15, 0.25) * lx
+        r2 = (X - ctr[0]) ** 2 + (Y - ctr[1]) ** 2 + ((Z - ctr[2]) ** 2 if c["dim"] == 3 else 0.0)
+        f = np.exp(-r2 / (wid * wid))
+    else:
+        raise ValueError(f"unknown species kind {kind}")
+    return np.ascontiguousarray(np.broadcast_to(f, s["cell"]).reshape(s["cell"]), dtype=np.float64)
+
+
 def stream_velocity(c, amp=1.0):
     """Discretely divergence-free MAC velocity from face differences of the
     corner stream function psi = L sin^2(pi x/Lx) sin^2(pi y/Ly)/pi (L = Ly,
