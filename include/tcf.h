@@ -98,6 +98,14 @@ typedef struct tcf_config {
   int refine_maxit;        /* FP64 refinement sweeps limit (FP32 mode) */
   int mg_levels;           /* 0 = automatic */
   int mg_nu;               /* Jacobi sweeps before and after the coarse correction */
+  /* Solutal Marangoni (eq. 5: the surface-tension gradient is the chain rule
+   * over temperature and concentration; in-situ alloying).  species = 1
+   * carries a concentration field c (cell centres, set with tcf_set_species)
+   * with the same WENO5 / SSP-RK3 transport as alpha (no diffusion, no flux
+   * through walls) and adds dsigma_dc (c - c0) to sigma.  0 = no species
+   * (dsigma_dc, c0 ignored).  Not combined with TCF_WITH_ADJOINT. */
+  int species;
+  double dsigma_dc, c0;
 } tcf_config;
 
 typedef struct tcf_step_info {
@@ -128,6 +136,12 @@ tcf_status tcf_set_fields(tcf_grid* g, double t, const double* alpha, const doub
 /* Copy the state out (device FP64 pointers; any may be NULL to skip). */
 tcf_status tcf_get_fields(const tcf_grid* g, double* t, double* alpha, double* T, double* u, double* v,
                           double* w, double* p);
+
+/* Species field of a grid made with species = 1: copy in / out (device FP64,
+ * nx*ny*nz cells in the layout above).  TCF_E_STATE on a grid without a
+ * species; TCF_E_INVALID on a NULL pointer.  tcf_step needs it set once. */
+tcf_status tcf_set_species(tcf_grid* g, const double* c);
+tcf_status tcf_get_species(const tcf_grid* g, double* c);
 
 /* Advance nsteps steps of size dt (S1..S8 each).  info may be NULL; when set
  * it receives the diagnostics of the last step (forces a stream sync). */

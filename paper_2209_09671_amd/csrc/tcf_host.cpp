@@ -56,6 +56,7 @@ struct Fields {
   R *a = nullptr, *T = nullptr;            // state alpha, T (precision R)
   R *u = nullptr, *v = nullptr, *w = nullptr;  // velocity read by the stencils (alias of u64.. in FP64)
   R *a1, *T1, *a2, *T2;                    // RK3 stage values
+  R *c = nullptr, *c1 = nullptr, *c2 = nullptr;  // species field and its RK3 stages (species configs)
   R *sk, *Mx, *My, *Mz;                    // sigma*kappa, Marangoni vector
   R *us, *vs, *ws;                         // predictor
   std::vector<Level<R>> lv;                // Poisson levels (level 0 = fine)
@@ -109,6 +110,7 @@ struct tcf_grid {
   hipStream_t stream;
   bool fp32;
   bool has_fields = false;
+  bool has_species = false;  // species field set (configs with species = 1)
   double t = 0.0;
   // FP64 state and scratch (both modes)
   double *u64, *v64, *w64, *p64, *b64, *r64, *ax64, *ay64, *az64, *zero64;
@@ -175,11 +177,16 @@ struct Prof {
 };
 
 template <class R>
-void carve_fields(Carver& cv, const Dims& D, Fields<R>& F, int mg_levels, bool alias_state, double* u64,
-                  double* v64, double* w64, double* ax64, double* ay64, double* az64) {
+void carve_fields(Carver& cv, const Dims& D, Fields<R>& F, int mg_levels, bool alias_state, bool species,
+                  double* u64, double* v64, double* w64, double* ax64, double* ay64, double* az64) {
   const long N = D.N;
   F.a = cv.take<R>(N);
   F.T = cv.take<R>(N);
+  if (species) {
+    F.c = cv.take<R>(N);
+    F.c1 = cv.take<R>(N);
+    F.c2 = cv.take<R>(N);
+  }
   if (alias_state) {
     F.u = (R*)u64;
     F.v = (R*)v64;
@@ -263,9 +270,11 @@ size_t carve(const tcf_config* c, void* base, tcf_grid* g) {
   G->ay64 = cv.take<double>(D.Nv);
   G->az64 = D.dim == 3 ? cv.take<double>(D.Nw) : nullptr;
   if (c->precision == TCF_FP32_REFINE)
-    carve_fields<float>(cv, D, G->f32, c->mg_levels, false, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
+    carve_fields<float>(cv, D, G->f32, c->mg_levels, false, c->species != 0, nullptr, nullptr, nullptr, nullptr,
+                        nullptr, nullptr);
   else
-    carve_fields<double>(cv, D, G->f64, c->mg_levels, true, G->u64, G->v64, G->w64, G->ax64, G->ay64, G->az64);
+    carve_fields<double>(cv, D, G->f64, c->mg_levels, true, c->species != 0, G->u64, G->v64, G->w64, G->ax64,
+                         G->ay64, G->az64);
   const int nb = (int)std::max<long>((D.N + 255) / 256, (long)nblocks_cells(D.nx, D.ny, D.nz));
   G->nb = nb;
   if (c->flags & TCF_WITH_ADJOINT) {
@@ -314,6 +323,9 @@ std::string validate(const tcf_config* c) {
   if (c->precision != TCF_FP64 && c->precision != TCF_FP32_REFINE) return "unknown precision";
   if (c->flags & ~(TCF_TRANSPORT_ONLY | TCF_WITH_ADJOINT)) return "unknown flags";
   if ((c->flags & TCF_WITH_ADJOINT) && c->precision != TCF_FP64) return "the adjoint needs precision TCF_FP64";
+  if (c->species != 0 && c->species != 1) return "species must be 0 or 1";
+  if (c->species && (c->flags & TCF_WITH_ADJOINT)) return "the adjoint does not cover the species field";
+  if (c->species && (!std::isfinite(c->dsigma_dc) || !std::isfinite(c->c0))) return "dsigma_dc and c0 must be finite";
   if (!(c->rho1 > 0 && c->rho2 > 0)) return "densities must be positive";
   if (!(c->mu1 >= 0 && c->mu2 >= 0)) return "viscosities must be non-negative";
   if (!(c->rhocp1 > 0 && c->rhocp2 > 0)) return "rho*c_p must be positive";
@@ -352,6 +364,8 @@ KParams make_params(const tcf_config* c) {
   P.sigma0 = c->sigma0;
   P.s = c->dsigma_dT;
   P.T0 = c->T0;
+  P.sc = c->species ? c->dsigma_dc : 0.0;
+  P.c0 = c->species ? c->c0 : 0.0;
   for (int k = 0; k < 6; ++k) {
     P.Tbc[k] = c->T_bc[k];
     P.Tw[k] = c->T_wall[k];
@@ -680,12 +694,17 @@ tcf_status step_once(tcf_grid* g, double dt, tcf_step_info* inf, bool want_diag)
     Prof pr(g, FAM_TRANSPORT);
     transport_stage<R>(P, s, F.a2, F.T2, F.a, F.T, F.u, F.v, F.w, F.a, F.T, 1.0 / 3.0, 2.0 / 3.0);
   }
+  if (F.c) {  // the species: the same three stages
+    transport_scalar<R>(P, s, F.c, F.c, F.u, F.v, F.w, F.c1, 0.0, 1.0);
+    transport_scalar<R>(P, s, F.c1, F.c, F.u, F.v, F.w, F.c2, 0.75, 0.25);
+    transport_scalar<R>(P, s, F.c2, F.c, F.u, F.v, F.w, F.c, 1.0 / 3.0, 2.0 / 3.0);
+  }
   tcf_status st = TCF_OK;
   if (!(g->cfg.flags & TCF_TRANSPORT_ONLY)) {
     // S2-S5
     {
       Prof pr(g, FAM_GEOMETRY);
-      geometry<R>(P, s, F.a, F.T, F.sk, F.Mx, F.My, F.Mz);
+      geometry<R>(P, s, F.a, F.T, F.c, F.sk, F.Mx, F.My, F.Mz);
     }
     {
       Prof pr(g, FAM_PREDICTOR);
@@ -737,7 +756,7 @@ tcf_status predictor_only(tcf_grid* g, double dt, double* us, double* vs, double
   KParams P = g->P;
   P.dt = dt;
   P.t = g->t;
-  geometry<R>(P, s, F.a, F.T, F.sk, F.Mx, F.My, F.Mz);
+  geometry<R>(P, s, F.a, F.T, F.c, F.sk, F.Mx, F.My, F.Mz);
   predictor<R>(P, s, F.a, F.sk, F.Mx, F.My, F.Mz, F.u, F.v, F.w, F.us, F.vs, F.ws);
   const Dims& D = g->D;
   if (g->fp32) {
@@ -939,12 +958,38 @@ tcf_status tcf_get_fields(const tcf_grid* gc, double* t, double* alpha, double* 
   return TCF_OK;
 }
 
+tcf_status tcf_set_species(tcf_grid* g, const double* c) {
+  g_err.clear();
+  if (!g) return fail(TCF_E_INVALID, "grid is NULL");
+  if (!g->cfg.species) return fail(TCF_E_STATE, "the grid was created without a species (species = 0)");
+  if (!c) return fail(TCF_E_INVALID, "c must be non-NULL");
+  if (g->fp32) to_f32(g->stream, g->D.N, c, g->f32.c);
+  else copy_f64(g->stream, g->D.N, c, g->f64.c);
+  HIPCHECK(hipGetLastError());
+  g->has_species = true;
+  return TCF_OK;
+}
+
+tcf_status tcf_get_species(const tcf_grid* gc, double* c) {
+  g_err.clear();
+  if (!gc) return fail(TCF_E_INVALID, "grid is NULL");
+  tcf_grid* g = const_cast<tcf_grid*>(gc);
+  if (!g->cfg.species) return fail(TCF_E_STATE, "the grid was created without a species (species = 0)");
+  if (!g->has_species) return fail(TCF_E_STATE, "species field not set");
+  if (!c) return fail(TCF_E_INVALID, "c must be non-NULL");
+  if (g->fp32) to_f64(g->stream, g->D.N, g->f32.c, c);
+  else copy_f64(g->stream, g->D.N, g->f64.c, c);
+  HIPCHECK(hipGetLastError());
+  return TCF_OK;
+}
+
 tcf_status tcf_step(tcf_grid* g, double dt, int nsteps, tcf_step_info* info) {
   g_err.clear();
   if (!g) return fail(TCF_E_INVALID, "grid is NULL");
   if (!(dt > 0) || !std::isfinite(dt)) return fail(TCF_E_INVALID, "dt must be positive and finite");
   if (nsteps < 0) return fail(TCF_E_INVALID, "nsteps must be >= 0");
   if (!g->has_fields) return fail(TCF_E_STATE, "fields not set");
+  if (g->cfg.species && !g->has_species) return fail(TCF_E_STATE, "species field not set");
   if (info) std::memset(info, 0, sizeof(*info));
   tcf_status worst = TCF_OK;
   for (int k = 0; k < nsteps; ++k) {
@@ -992,6 +1037,7 @@ tcf_status tcf_predictor(tcf_grid* g, double dt, double* us, double* vs, double*
   if (!us || !vs || (g->D.dim == 3 && !ws)) return fail(TCF_E_INVALID, "output pointers must be non-NULL");
   if (!(dt > 0) || !std::isfinite(dt)) return fail(TCF_E_INVALID, "dt must be positive and finite");
   if (!g->has_fields) return fail(TCF_E_STATE, "fields not set");
+  if (g->cfg.species && !g->has_species) return fail(TCF_E_STATE, "species field not set");
   return g->fp32 ? predictor_only<float>(g, dt, us, vs, ws) : predictor_only<double>(g, dt, us, vs, ws);
 }
 
@@ -1073,7 +1119,7 @@ tcf_status tcf_step_backward(tcf_grid* g, double t_n, double dt, const double* c
   const long N = D.N;
   // ---- forward S1..S7, keeping what the reverse sweep reads
   forward_transport_keep(g, P);
-  geometry<double>(P, s, F.a, F.T, F.sk, F.Mx, F.My, F.Mz);
+  geometry<double>(P, s, F.a, F.T, nullptr, F.sk, F.Mx, F.My, F.Mz);
   predictor<double>(P, s, F.a, F.sk, F.Mx, F.My, F.Mz, F.u, F.v, F.w, F.us, F.vs, F.ws);
   const int nbc = nblocks_cells(D.nx, D.ny, D.nz);
   divergence_rhs<double>(P, s, F.us, F.vs, F.ws, g->b64, g->part[0]);
@@ -1159,7 +1205,7 @@ tcf_status tcf_adjoint_predictor(tcf_grid* g, double dt, const double* usb, cons
   KParams P = g->P;
   P.dt = dt;
   P.t = g->t;
-  geometry<double>(P, s, F.a, F.T, F.sk, F.Mx, F.My, F.Mz);
+  geometry<double>(P, s, F.a, F.T, nullptr, F.sk, F.Mx, F.My, F.Mz);
   fill_f64(s, D.N, A.ab, 0.0);
   fill_f64(s, D.N, A.Tb, 0.0);
   zero_adj_faces(g);

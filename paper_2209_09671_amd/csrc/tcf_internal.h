@@ -15,6 +15,7 @@ struct KParams {
   double h, ih, dt, t;
   double rho1, rho2, mu1, mu2, rhocp1, rhocp2, lam1, lam2;
   double sigma0, s, T0;
+  double sc, c0;  // species: sigma += sc (c - c0) (sc = 0 without a species)
   int Tbc[6];
   double Tw[6];
   double qP, qr, qx0, qy0, qvx, qvy;
@@ -55,8 +56,14 @@ inline int nblocks_cells(int nx, int ny, int nz) { return ((nx + 63) / 64) * ((n
 template <class R>
 void transport_stage(const KParams& P, hipStream_t s, const R* a, const R* T, const R* ab, const R* Tb,
                      const R* u, const R* v, const R* w, R* ao, R* To, double cb, double ci);
+// One SSP-RK3 stage of a passive cell field (the species) with alpha's
+// transport: qo = cb qb + ci (q + dt L(q)).
 template <class R>
-void geometry(const KParams& P, hipStream_t s, const R* a, const R* T, R* sk, R* Mx, R* My, R* Mz);
+void transport_scalar(const KParams& P, hipStream_t s, const R* q, const R* qb, const R* u, const R* v, const R* w,
+                      R* qo, double cb, double ci);
+template <class R>
+// c: species field or NULL (no solutal term)
+void geometry(const KParams& P, hipStream_t s, const R* a, const R* T, const R* c, R* sk, R* Mx, R* My, R* Mz);
 template <class R>
 void predictor(const KParams& P, hipStream_t s, const R* a, const R* sk, const R* Mx, const R* My,
                const R* Mz, const R* u, const R* v, const R* w, R* us, R* vs, R* ws);

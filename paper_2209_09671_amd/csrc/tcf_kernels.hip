@@ -35,8 +35,8 @@ __device__ __forceinline__ void normal_at(const R* __restrict__ a, int i, int j,
 
 template <class R, int DIM>
 __global__ __launch_bounds__(256) void k_geometry(KParams P, const R* __restrict__ a, const R* __restrict__ T,
-                                                  R* __restrict__ sk, R* __restrict__ Mx, R* __restrict__ My,
-                                                  R* __restrict__ Mz) {
+                                                  const R* __restrict__ cf, R* __restrict__ sk, R* __restrict__ Mx,
+                                                  R* __restrict__ My, R* __restrict__ Mz) {
   const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
   const int nx = P.nx, ny = P.ny, nz = P.nz;
   if (i >= nx || j >= ny) return;
@@ -63,10 +63,17 @@ __global__ __launch_bounds__(256) void k_geometry(KParams P, const R* __restrict
   const R n0 = gx / ge, n1 = gy / ge, n2 = gz / ge;
   const long c = cidx(i, j, k, nx, ny);
   const R s = R(P.s);
-  const R sigma = R(P.sigma0) + s * (T[c] - R(P.T0));
-  const R gs0 = s * (T_at<DIM>(T, i + 1, j, k, P) - T_at<DIM>(T, i - 1, j, k, P)) * ih2;
-  const R gs1 = s * (T_at<DIM>(T, i, j + 1, k, P) - T_at<DIM>(T, i, j - 1, k, P)) * ih2;
-  const R gs2 = DIM == 3 ? s * (T_at<DIM>(T, i, j, k + 1, P) - T_at<DIM>(T, i, j, k - 1, P)) * ih2 : R(0);
+  R sigma = R(P.sigma0) + s * (T[c] - R(P.T0));
+  R gs0 = s * (T_at<DIM>(T, i + 1, j, k, P) - T_at<DIM>(T, i - 1, j, k, P)) * ih2;
+  R gs1 = s * (T_at<DIM>(T, i, j + 1, k, P) - T_at<DIM>(T, i, j - 1, k, P)) * ih2;
+  R gs2 = DIM == 3 ? s * (T_at<DIM>(T, i, j, k + 1, P) - T_at<DIM>(T, i, j, k - 1, P)) * ih2 : R(0);
+  if (cf) {  // solutal part: sigma += s_c (c - c0), grad sigma += s_c grad c (even ghosts)
+    const R sc = R(P.sc);
+    sigma += sc * (cf[c] - R(P.c0));
+    gs0 += sc * (A_at<DIM>(cf, i + 1, j, k, nx, ny, nz) - A_at<DIM>(cf, i - 1, j, k, nx, ny, nz)) * ih2;
+    gs1 += sc * (A_at<DIM>(cf, i, j + 1, k, nx, ny, nz) - A_at<DIM>(cf, i, j - 1, k, nx, ny, nz)) * ih2;
+    if (DIM == 3) gs2 += sc * (A_at<DIM>(cf, i, j, k + 1, nx, ny, nz) - A_at<DIM>(cf, i, j, k - 1, nx, ny, nz)) * ih2;
+  }
   const R ndg = n0 * gs0 + n1 * gs1 + n2 * gs2;
   sk[c] = sigma * kappa;
   Mx[c] = ds * (gs0 - n0 * ndg);
@@ -770,10 +777,10 @@ inline int nblk1(long n) { return (int)((n + 255) / 256); }
 // =============================================================================
 // Launchers
 template <class R>
-void geometry(const KParams& P, hipStream_t s, const R* a, const R* T, R* sk, R* Mx, R* My, R* Mz) {
+void geometry(const KParams& P, hipStream_t s, const R* a, const R* T, const R* c, R* sk, R* Mx, R* My, R* Mz) {
   dim3 g = grid_for(P.nx, P.ny, P.nz);
-  if (P.dim == 3) hipLaunchKernelGGL((k_geometry<R, 3>), g, blk(), 0, s, P, a, T, sk, Mx, My, Mz);
-  else hipLaunchKernelGGL((k_geometry<R, 2>), g, blk(), 0, s, P, a, T, sk, Mx, My, Mz);
+  if (P.dim == 3) hipLaunchKernelGGL((k_geometry<R, 3>), g, blk(), 0, s, P, a, T, c, sk, Mx, My, Mz);
+  else hipLaunchKernelGGL((k_geometry<R, 2>), g, blk(), 0, s, P, a, T, c, sk, Mx, My, Mz);
 }
 
 template <class R>
@@ -1005,7 +1012,7 @@ void zero_walls(const KParams& P, hipStream_t s, R* u, R* v, R* w) {
 
 // explicit instantiations
 #define TCF_INST(R)                                                                                               \
-  template void geometry<R>(const KParams&, hipStream_t, const R*, const R*, R*, R*, R*, R*);                     \
+  template void geometry<R>(const KParams&, hipStream_t, const R*, const R*, const R*, R*, R*, R*, R*);          \
   template void divergence_rhs<R>(const KParams&, hipStream_t, const R*, const R*, const R*, double*, double*);                                                                          \
   template void face_weights<R>(const KParams&, hipStream_t, const R*, double*, double*, double*, float*, float*, \
                                 float*);                                                                          \

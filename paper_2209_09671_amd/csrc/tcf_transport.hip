@@ -102,15 +102,19 @@ __device__ __forceinline__ ColMap<R> col_map(const KParams& P, int ii, int jj, b
   return m;
 }
 
-template <class R, int DIM>
+// WT: alpha and T (the stage of S1); without WT the "alpha" slot carries any
+// passive cell field (the species) with exactly alpha's arithmetic, and
+// nothing of T is touched.
+template <class R, int DIM, bool WT>
 __global__ __launch_bounds__(512) void k_transport2(KParams P, int kz, int ntx, int nty, const R* __restrict__ a,
                                                     const R* __restrict__ T, const R* ab, const R* Tb,
                                                     const R* __restrict__ u, const R* __restrict__ v,
                                                     const R* __restrict__ w, R* ao, R* To, R cb, R ci) {
+  constexpr int NT = WT ? 2 : 1;
   __shared__ R sa[2][SY][SX];
-  __shared__ R sT[2][SY][SX];
+  __shared__ R sT[NT][WT ? SY : 1][WT ? SX : 1];
   __shared__ R fya[TY][TX];  // low y-face fluxes of the tile rows
-  __shared__ R fyt[TY][TX];
+  __shared__ R fyt[WT ? TY : 1][WT ? TX : 1];
   const int nx = P.nx, ny = P.ny, nz = P.nz;
   const int tx = threadIdx.x, ty = threadIdx.y, tid = tx + TX * ty;
   // XCD-grouped tile numbering (see the pressure kernels)
@@ -167,24 +171,24 @@ __global__ __launch_bounds__(512) void k_transport2(KParams P, int kz, int ntx, 
   if (DIM == 3) {
     for (int m = 0; m < 6; ++m) {
       qa[m + 1] = ldA(cm.off, k0 - 3 + m);
-      qt[m + 1] = tval(cm, ldT(cm.off, k0 - 3 + m), k0 - 3 + m);
+      if (WT) qt[m + 1] = tval(cm, ldT(cm.off, k0 - 3 + m), k0 - 3 + m);
     }
     ia = ldA(cm.off, min(k0 + 3, kq));
-    iT = ldT(cm.off, min(k0 + 3, kq));
+    if (WT) iT = ldT(cm.off, min(k0 + 3, kq));
   } else {
     qa[3] = ldA(cm.off, 0);
-    qt[3] = tval(cm, ldT(cm.off, 0), 0);
+    if (WT) qt[3] = tval(cm, ldT(cm.off, 0), 0);
   }
-  R ha = ldA(hm.off, k0), hT = ldT(hm.off, k0);  // halo of plane k (raw T)
+  R ha = ldA(hm.off, k0), hT = WT ? ldT(hm.off, k0) : R(0);  // halo of plane k (raw T)
   // velocities and base state of plane k (loaded one plane ahead)
   R uL = u[(size_t)k0 * plu + uoL], uH = u[(size_t)k0 * plu + uoH];
   R vL = v[(size_t)k0 * plv + voL], vH = v[(size_t)k0 * plv + voH];
   R wH = DIM == 3 ? w[(size_t)(k0 + 1) * pl + co] : R(0);
-  R bA = ab[(size_t)k0 * pl + co], bT = Tb[(size_t)k0 * pl + co];
+  R bA = ab[(size_t)k0 * pl + co], bT = WT ? Tb[(size_t)k0 * pl + co] : R(0);
   const R wL0 = DIM == 3 ? w[(size_t)k0 * pl + co] : R(0);
   // Gaussian surface heat flux of the column (x, y, t), FP64, once per column
   R qcol = R(0);
-  if (P.qP != 0.0 && act) {
+  if (WT && P.qP != 0.0 && act) {
     const double xl = P.qx0 + P.qvx * P.t, yl = P.qy0 + P.qvy * P.t;
     const double x = (i + 0.5) * P.h, y = (j + 0.5) * P.h;
     const double r2 = (x - xl) * (x - xl) + (y - yl) * (y - yl);
@@ -202,22 +206,24 @@ __global__ __launch_bounds__(512) void k_transport2(KParams P, int kz, int ntx, 
         qt[m] = qt[m + 1];
       }
       qa[6] = ia;
-      qt[6] = tval(cm, iT, k + 3);
       ia = ldA(cm.off, min(k + 4, kq));
-      iT = ldT(cm.off, min(k + 4, kq));
+      if (WT) {
+        qt[6] = tval(cm, iT, k + 3);
+        iT = ldT(cm.off, min(k + 4, kq));
+      }
     }
     // publish the plane, then load the next plane's halo
     if (cval) {
       sa[buf][ty + H][tx + H] = qa[3];
-      sT[buf][ty + H][tx + H] = qt[3];
+      if (WT) sT[buf][ty + H][tx + H] = qt[3];
     }
     if (hvalid) {
       sa[buf][hoy][hox] = ha;
-      sT[buf][hoy][hox] = tval(hm, hT, k);
+      if (WT) sT[buf][hoy][hox] = tval(hm, hT, k);
     }
     const int kn = min(k + 1, k1 - 1);
     ha = ldA(hm.off, kn);
-    hT = ldT(hm.off, kn);
+    if (WT) hT = ldT(hm.off, kn);
     // this plane's velocities and base state; prefetch the next plane's
     const R ulo = uL, uhi = uH, vlo = vL, vhi = vH, whi = wH, abc = bA, Tbc = bT;
     uL = u[(size_t)kn * plu + uoL];
@@ -226,7 +232,7 @@ __global__ __launch_bounds__(512) void k_transport2(KParams P, int kz, int ntx, 
     vH = v[(size_t)kn * plv + voH];
     if (DIM == 3) wH = w[(size_t)min(kn + 1, nz) * pl + co];
     bA = ab[(size_t)kn * pl + co];
-    bT = Tb[(size_t)kn * pl + co];
+    if (WT) bT = Tb[(size_t)kn * pl + co];
     __syncthreads();
     R Fxa_lo = R(0), Fxt_lo = R(0), Fya_lo = R(0), Fyt_lo = R(0);
     const size_t c = (size_t)k * pl + co;
@@ -235,20 +241,22 @@ __global__ __launch_bounds__(512) void k_transport2(KParams P, int kz, int ntx, 
       if (i > 0) {
         Fxa_lo = ulo * upw(sa[buf][Y][X - 3], sa[buf][Y][X - 2], sa[buf][Y][X - 1], sa[buf][Y][X], sa[buf][Y][X + 1],
                            sa[buf][Y][X + 2], ulo, eps);
-        Fxt_lo = ulo * upw(sT[buf][Y][X - 3], sT[buf][Y][X - 2], sT[buf][Y][X - 1], sT[buf][Y][X], sT[buf][Y][X + 1],
-                           sT[buf][Y][X + 2], ulo, eps);
+        if (WT)
+          Fxt_lo = ulo * upw(sT[buf][Y][X - 3], sT[buf][Y][X - 2], sT[buf][Y][X - 1], sT[buf][Y][X],
+                             sT[buf][Y][X + 1], sT[buf][Y][X + 2], ulo, eps);
       }
       if (j > 0) {
         Fya_lo = vlo * upw(sa[buf][Y - 3][X], sa[buf][Y - 2][X], sa[buf][Y - 1][X], sa[buf][Y][X], sa[buf][Y + 1][X],
                            sa[buf][Y + 2][X], vlo, eps);
-        Fyt_lo = vlo * upw(sT[buf][Y - 3][X], sT[buf][Y - 2][X], sT[buf][Y - 1][X], sT[buf][Y][X], sT[buf][Y + 1][X],
-                           sT[buf][Y + 2][X], vlo, eps);
+        if (WT)
+          Fyt_lo = vlo * upw(sT[buf][Y - 3][X], sT[buf][Y - 2][X], sT[buf][Y - 1][X], sT[buf][Y][X],
+                             sT[buf][Y + 1][X], sT[buf][Y + 2][X], vlo, eps);
       }
       fya[ty][tx] = Fya_lo;
-      fyt[ty][tx] = Fyt_lo;
+      if (WT) fyt[ty][tx] = Fyt_lo;
     }
     // high x-face: next lane's low face, computed here at the tile edge
-    R Fxa_hi = __shfl_down(Fxa_lo, 1, 64), Fxt_hi = __shfl_down(Fxt_lo, 1, 64);
+    R Fxa_hi = __shfl_down(Fxa_lo, 1, 64), Fxt_hi = WT ? __shfl_down(Fxt_lo, 1, 64) : R(0);
     if (act) {
       const int X = tx + H, Y = ty + H;
       if (i + 1 >= nx) {
@@ -257,8 +265,9 @@ __global__ __launch_bounds__(512) void k_transport2(KParams P, int kz, int ntx, 
       } else if (tx == TX - 1) {
         Fxa_hi = uhi * upw(sa[buf][Y][X - 2], sa[buf][Y][X - 1], sa[buf][Y][X], sa[buf][Y][X + 1], sa[buf][Y][X + 2],
                            sa[buf][Y][X + 3], uhi, eps);
-        Fxt_hi = uhi * upw(sT[buf][Y][X - 2], sT[buf][Y][X - 1], sT[buf][Y][X], sT[buf][Y][X + 1], sT[buf][Y][X + 2],
-                           sT[buf][Y][X + 3], uhi, eps);
+        if (WT)
+          Fxt_hi = uhi * upw(sT[buf][Y][X - 2], sT[buf][Y][X - 1], sT[buf][Y][X], sT[buf][Y][X + 1],
+                             sT[buf][Y][X + 2], sT[buf][Y][X + 3], uhi, eps);
       }
     }
     __syncthreads();
@@ -268,12 +277,13 @@ __global__ __launch_bounds__(512) void k_transport2(KParams P, int kz, int ntx, 
       if (j + 1 < ny) {
         if (ty < TY - 1) {
           Fya_hi = fya[ty + 1][tx];
-          Fyt_hi = fyt[ty + 1][tx];
+          if (WT) Fyt_hi = fyt[ty + 1][tx];
         } else {
           Fya_hi = vhi * upw(sa[buf][Y - 2][X], sa[buf][Y - 1][X], sa[buf][Y][X], sa[buf][Y + 1][X],
                              sa[buf][Y + 2][X], sa[buf][Y + 3][X], vhi, eps);
-          Fyt_hi = vhi * upw(sT[buf][Y - 2][X], sT[buf][Y - 1][X], sT[buf][Y][X], sT[buf][Y + 1][X],
-                             sT[buf][Y + 2][X], sT[buf][Y + 3][X], vhi, eps);
+          if (WT)
+            Fyt_hi = vhi * upw(sT[buf][Y - 2][X], sT[buf][Y - 1][X], sT[buf][Y][X], sT[buf][Y + 1][X],
+                               sT[buf][Y + 2][X], sT[buf][Y + 3][X], vhi, eps);
         }
       }
       R diva = (Fxa_hi - Fxa_lo) + (Fya_hi - Fya_lo);
@@ -284,13 +294,13 @@ __global__ __launch_bounds__(512) void k_transport2(KParams P, int kz, int ntx, 
           fzt_lo = R(0);
           if (k > 0) {
             fza_lo = wL0 * upw(qa[0], qa[1], qa[2], qa[3], qa[4], qa[5], wL0, eps);
-            fzt_lo = wL0 * upw(qt[0], qt[1], qt[2], qt[3], qt[4], qt[5], wL0, eps);
+            if (WT) fzt_lo = wL0 * upw(qt[0], qt[1], qt[2], qt[3], qt[4], qt[5], wL0, eps);
           }
         }
         R fza_hi = R(0), fzt_hi = R(0);
         if (k + 1 < nz) {
           fza_hi = whi * upw(qa[1], qa[2], qa[3], qa[4], qa[5], qa[6], whi, eps);
-          fzt_hi = whi * upw(qt[1], qt[2], qt[3], qt[4], qt[5], qt[6], whi, eps);
+          if (WT) fzt_hi = whi * upw(qt[1], qt[2], qt[3], qt[4], qt[5], qt[6], whi, eps);
         }
         diva += fza_hi - fza_lo;
         divt += fzt_hi - fzt_lo;
@@ -300,33 +310,35 @@ __global__ __launch_bounds__(512) void k_transport2(KParams P, int kz, int ntx, 
       }
       const R ac = qa[3], Tc = qt[3];
       const R La = -diva * ih;
-      // conduction: arithmetic-mean face conductivity, ghosts from the tile
-      const R lc = mixp(ac, P.lam1, P.lam2);
-      R cond = R(0);
-      {
-        const R an[4] = {sa[buf][Y][X - 1], sa[buf][Y][X + 1], sa[buf][Y - 1][X], sa[buf][Y + 1][X]};
-        const R tn[4] = {sT[buf][Y][X - 1], sT[buf][Y][X + 1], sT[buf][Y - 1][X], sT[buf][Y + 1][X]};
-        for (int f = 0; f < 4; ++f) cond += R(0.5) * (lc + mixp(an[f], P.lam1, P.lam2)) * (tn[f] - Tc);
-        if (DIM == 3) {
-          cond += R(0.5) * (lc + mixp(qa[2], P.lam1, P.lam2)) * (qt[2] - Tc);
-          cond += R(0.5) * (lc + mixp(qa[4], P.lam1, P.lam2)) * (qt[4] - Tc);
-        }
-      }
-      cond *= ih * ih;
-      R src = R(0);
-      if (P.qP != 0.0) {
-        const R h2 = R(0.5) * ih;
-        const R gx = (sa[buf][Y][X + 1] - sa[buf][Y][X - 1]) * h2;
-        const R gy = (sa[buf][Y + 1][X] - sa[buf][Y - 1][X]) * h2;
-        const R gz = DIM == 3 ? (qa[4] - qa[2]) * h2 : R(0);
-        const R g2 = gx * gx + gy * gy + gz * gz;
-        const R ne = R(P.neps);
-        const R ds = g2 / (sqrt(g2 + ne * ne) + ne);
-        src = qcol * ds;
-      }
-      const R LT = -divt * ih + (cond + src) / mixp(ac, P.rhocp1, P.rhocp2);
       ao[c] = cb * abc + ci * (ac + dt * La);
-      To[c] = cb * Tbc + ci * (Tc + dt * LT);
+      if (WT) {
+        // conduction: arithmetic-mean face conductivity, ghosts from the tile
+        const R lc = mixp(ac, P.lam1, P.lam2);
+        R cond = R(0);
+        {
+          const R an[4] = {sa[buf][Y][X - 1], sa[buf][Y][X + 1], sa[buf][Y - 1][X], sa[buf][Y + 1][X]};
+          const R tn[4] = {sT[buf][Y][X - 1], sT[buf][Y][X + 1], sT[buf][Y - 1][X], sT[buf][Y + 1][X]};
+          for (int f = 0; f < 4; ++f) cond += R(0.5) * (lc + mixp(an[f], P.lam1, P.lam2)) * (tn[f] - Tc);
+          if (DIM == 3) {
+            cond += R(0.5) * (lc + mixp(qa[2], P.lam1, P.lam2)) * (qt[2] - Tc);
+            cond += R(0.5) * (lc + mixp(qa[4], P.lam1, P.lam2)) * (qt[4] - Tc);
+          }
+        }
+        cond *= ih * ih;
+        R src = R(0);
+        if (P.qP != 0.0) {
+          const R h2 = R(0.5) * ih;
+          const R gx = (sa[buf][Y][X + 1] - sa[buf][Y][X - 1]) * h2;
+          const R gy = (sa[buf][Y + 1][X] - sa[buf][Y - 1][X]) * h2;
+          const R gz = DIM == 3 ? (qa[4] - qa[2]) * h2 : R(0);
+          const R g2 = gx * gx + gy * gy + gz * gz;
+          const R ne = R(P.neps);
+          const R ds = g2 / (sqrt(g2 + ne * ne) + ne);
+          src = qcol * ds;
+        }
+        const R LT = -divt * ih + (cond + src) / mixp(ac, P.rhocp1, P.rhocp2);
+        To[c] = cb * Tbc + ci * (Tc + dt * LT);
+      }
     }
     buf ^= 1;
   }
@@ -352,11 +364,24 @@ void transport_stage(const KParams& P, hipStream_t s, const R* a, const R* T, co
   int kz, ntx, nty;
   const int nb = transport_plan(P.nx, P.ny, P.nz, &kz, &ntx, &nty);
   if (P.dim == 3)
-    hipLaunchKernelGGL((k_transport2<R, 3>), dim3(nb), dim3(TX, TY), 0, s, P, kz, ntx, nty, a, T, ab, Tb, u, v, w, ao,
-                       To, R(cb), R(ci));
+    hipLaunchKernelGGL((k_transport2<R, 3, true>), dim3(nb), dim3(TX, TY), 0, s, P, kz, ntx, nty, a, T, ab, Tb, u, v,
+                       w, ao, To, R(cb), R(ci));
   else
-    hipLaunchKernelGGL((k_transport2<R, 2>), dim3(nb), dim3(TX, TY), 0, s, P, kz, ntx, nty, a, T, ab, Tb, u, v, w, ao,
-                       To, R(cb), R(ci));
+    hipLaunchKernelGGL((k_transport2<R, 2, true>), dim3(nb), dim3(TX, TY), 0, s, P, kz, ntx, nty, a, T, ab, Tb, u, v,
+                       w, ao, To, R(cb), R(ci));
+}
+
+template <class R>
+void transport_scalar(const KParams& P, hipStream_t s, const R* q, const R* qb, const R* u, const R* v, const R* w,
+                      R* qo, double cb, double ci) {
+  int kz, ntx, nty;
+  const int nb = transport_plan(P.nx, P.ny, P.nz, &kz, &ntx, &nty);
+  if (P.dim == 3)
+    hipLaunchKernelGGL((k_transport2<R, 3, false>), dim3(nb), dim3(TX, TY), 0, s, P, kz, ntx, nty, q, nullptr, qb,
+                       nullptr, u, v, w, qo, nullptr, R(cb), R(ci));
+  else
+    hipLaunchKernelGGL((k_transport2<R, 2, false>), dim3(nb), dim3(TX, TY), 0, s, P, kz, ntx, nty, q, nullptr, qb,
+                       nullptr, u, v, w, qo, nullptr, R(cb), R(ci));
 }
 
 template void transport_stage<double>(const KParams&, hipStream_t, const double*, const double*, const double*,
@@ -365,5 +390,9 @@ template void transport_stage<double>(const KParams&, hipStream_t, const double*
 template void transport_stage<float>(const KParams&, hipStream_t, const float*, const float*, const float*,
                                      const float*, const float*, const float*, const float*, float*, float*, double,
                                      double);
+template void transport_scalar<double>(const KParams&, hipStream_t, const double*, const double*, const double*,
+                                       const double*, const double*, double*, double, double);
+template void transport_scalar<float>(const KParams&, hipStream_t, const float*, const float*, const float*,
+                                      const float*, const float*, float*, double, double);
 
 }  // namespace tcf

@@ -40,7 +40,8 @@ class TcfConfig(C.Structure):
                 ("q_vx", C.c_double), ("q_vy", C.c_double),
                 ("weno_eps", C.c_double), ("normal_eps", C.c_double),
                 ("p_rtol", C.c_double), ("p_maxit", C.c_int), ("inner_rtol", C.c_double),
-                ("refine_maxit", C.c_int), ("mg_levels", C.c_int), ("mg_nu", C.c_int)]
+                ("refine_maxit", C.c_int), ("mg_levels", C.c_int), ("mg_nu", C.c_int),
+                ("species", C.c_int), ("dsigma_dc", C.c_double), ("c0", C.c_double)]
 
 
 class TcfStepInfo(C.Structure):
@@ -52,7 +53,8 @@ class TcfStepInfo(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
-EXPORTS = ["tcf_workspace_bytes", "tcf_init_grid", "tcf_set_fields", "tcf_get_fields", "tcf_step",
+EXPORTS = ["tcf_workspace_bytes", "tcf_init_grid", "tcf_set_fields", "tcf_get_fields", "tcf_set_species",
+           "tcf_get_species", "tcf_step",
            "tcf_solve_pressure", "tcf_predictor", "tcf_apply_A", "tcf_step_backward", "tcf_adjoint_transport",
            "tcf_adjoint_predictor", "tcf_profile", "tcf_profile_read", "tcf_destroy", "tcf_last_error"]
 
@@ -77,6 +79,10 @@ def load():
     lib.tcf_set_fields.argtypes = [vp, C.c_double, vp, vp, vp, vp, vp, vp]
     lib.tcf_get_fields.restype = st
     lib.tcf_get_fields.argtypes = [vp, C.POINTER(C.c_double), vp, vp, vp, vp, vp, vp]
+    lib.tcf_set_species.restype = st
+    lib.tcf_set_species.argtypes = [vp, vp]
+    lib.tcf_get_species.restype = st
+    lib.tcf_get_species.argtypes = [vp, vp]
     lib.tcf_step.restype = st
     lib.tcf_step.argtypes = [vp, C.c_double, C.c_int, C.POINTER(TcfStepInfo)]
     lib.tcf_solve_pressure.restype = st
@@ -123,6 +129,8 @@ def make_config(c: dict, precision=None, flags=None) -> TcfConfig:
     o.p_rtol, o.p_maxit = c["p_rtol"], c["p_maxit"]
     o.inner_rtol, o.refine_maxit = c["inner_rtol"], c["refine_maxit"]
     o.mg_levels, o.mg_nu = c["mg_levels"], c["mg_nu"]
+    o.species = int(c.get("species", 0))
+    o.dsigma_dc, o.c0 = float(c.get("dsigma_dc", 0.0)), float(c.get("c0", 0.0))
     return o
 
 
@@ -183,6 +191,18 @@ class Grid:
 
     def set_state(self, st: dict, t=0.0):
         self.set_fields(t, st["alpha"], st["T"], st["u"], st["v"], st.get("w"), st.get("p"))
+        if st.get("c") is not None:
+            self.set_species(st["c"])
+
+    def set_species(self, c):
+        ct = self._t(c)
+        self._keep_c = ct
+        _check(load().tcf_set_species(self.h, _ptr(ct)))
+
+    def get_species(self):
+        out = torch.empty(self.shapes["cell"], dtype=torch.float64, device=self.device)
+        _check(load().tcf_get_species(self.h, _ptr(out)))
+        return out
 
     def get_fields(self) -> dict:
         s = self.shapes

@@ -81,3 +81,23 @@ def test_binding_refuses_missing_library(monkeypatch, tmp_path):
     monkeypatch.setattr(tcf, "LIB_PATH", str(tmp_path / "nope.so"))
     with pytest.raises(RuntimeError, match="no CPU fallback"):
         tcf.load()
+
+
+def test_species_workspace_and_validation():
+    """A species adds its field and two RK3 stage arrays to the workspace;
+    species must be 0/1 and is not combined with the adjoint."""
+    c = I.config(3)
+    N = c["nx"] * c["ny"] * c["nz"]
+    cs = I.with_species(c, -0.2)
+    assert tcf.workspace_bytes(cs, precision=0) - tcf.workspace_bytes(c, precision=0) >= 3 * 8 * N
+    assert tcf.workspace_bytes(cs, precision=1) - tcf.workspace_bytes(c, precision=1) >= 3 * 4 * N
+    assert tcf.workspace_bytes(dict(cs, species=2)) == 0
+    assert tcf.workspace_bytes(dict(cs, dsigma_dc=float("nan"))) == 0
+    assert tcf.workspace_bytes(cs, precision=0, flags=tcf.TCF_WITH_ADJOINT) == 0
+    assert tcf.workspace_bytes(c, precision=0, flags=tcf.TCF_WITH_ADJOINT) > 0
+
+
+def test_species_entry_points_reject_null():
+    lib = tcf.load()
+    assert lib.tcf_set_species(None, None) == tcf.TCF_E_INVALID
+    assert lib.tcf_get_species(None, None) == tcf.TCF_E_INVALID
