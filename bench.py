@@ -10,7 +10,8 @@ iterative refinement at a divergence residual <= 1e-8; the plain FP64 path at
 the same accuracy is reported beside it.
 
 Prints ONE JSON line.  Options: --steps K --warmup W --gpus 1 --workload i
---kernel FAMILY (kernel family for the roofline entry) --no-cpu --no-fp64.
+--kernel FAMILY (kernel family for the roofline entry) --no-cpu --no-fp64
+--no-adjoint --no-species.
 """
 from __future__ import annotations
 
@@ -37,12 +38,21 @@ def algorithmic_bytes(family: str, c: dict, precision: int) -> float:
         # finest-level Jacobi sweep: x, b, alpha (face weights recomputed) read, x' written
         return N * w * (3 + 1)
     if family == "spmv":
-        # finest-level SpMV fused with d <- z + beta d: z, d, alpha read; d', q written
-        return N * w * (3 + 2)
+        # finest-level SpMV fused with d <- z + beta d: z, d, alpha read; d' written
+        # (K d' is not stored)
+        return N * w * (3 + 1)
+    if family == "update":
+        # x += alpha d, r -= alpha K d (K d recomputed), first Jacobi sweep:
+        # x, r, d, alpha read; x, r, z1 written
+        return N * w * (4 + 3)
     if family == "transport":
         # averaged over the three stages: alpha, T, one velocity per axis,
         # base alpha/T (stages 2, 3), outputs alpha, T
         return N * w * (2 + nfaces_per_cell + 2 * 2 / 3 + 2)
+    if family == "species":
+        # one species stage, averaged over the three: c, one velocity per
+        # axis, base c (stages 2, 3), output c
+        return N * w * (1 + nfaces_per_cell + 2 / 3 + 1)
     if family == "predictor":
         # per component launch: alpha, sigma*kappa, M_d, u, v, w, u*_d (write)
         return N * w * (3 + nfaces_per_cell + 1)
@@ -171,6 +181,7 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--adjoint-steps", type=int, default=10)
+    ap.add_argument("--no-species", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this path runs on one GPU; multi-GPU runs are not part of this build "
@@ -209,6 +220,23 @@ def main():
                 "kernel": args.kernel, "avg_launch_ms": round(avg_ms, 5),
                 "launches": r32["kernel_launches"], "algorithmic_bytes_per_launch": ab}
 
+    species = None
+    if not args.no_species:
+        # solutal Marangoni: the same workload carrying a species field (a
+        # seeded Gaussian bump of concentration) with sigma = sigma(T, c)
+        cs = I.with_species(c, -0.05, "blob")
+        rs = run_gpu(cs, dict(st, c=I.species_field(cs)), 1, args.steps, args.warmup, "species")
+        avg = rs["kernel_ms"] / max(rs["kernel_launches"], 1)
+        ab = algorithmic_bytes("species", c, 1)
+        species = {"value": round(N * args.steps / (rs["ev_ms"] / 1e3) / 1e6, 3), "unit": "Mcell-steps/s",
+                   "ms_per_step": round(rs["ev_ms"] / args.steps, 4),
+                   "added_ms_per_step": round((rs["ev_ms"] - r32["ev_ms"]) / args.steps, 4),
+                   "cg_iters_per_step": round(rs["iters"], 2), "max_div_rel": rs["div"],
+                   "dsigma_dc": cs["dsigma_dc"], "species_field": "blob",
+                   "species_stage": {"kernel": "k_transport2 (species only)", "avg_launch_ms": round(avg, 5),
+                                     "launches": rs["kernel_launches"], "algorithmic_bytes_per_launch": ab,
+                                     "achieved_GBs": round(ab / (avg / 1e3) / 1e9, 1)}}
+
     adj = None
     if not args.no_adjoint:
         ca = dict(c, precision=0)
@@ -239,6 +267,7 @@ def main():
         "fp64_same_accuracy": fp64,
         "wall_ms_per_step": round(r32["wall"] * 1e3 / args.steps, 4),
         "adjoint": adj,
+        "solutal_species": species,
         "roofline": roof,
         "cpu_baseline": cpu,
     }

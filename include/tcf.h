@@ -191,7 +191,9 @@ tcf_status tcf_adjoint_predictor(tcf_grid* g, double dt, const double* usb, cons
 
 /* Measurement: time every launch of one kernel family with HIP events on
  * the grid's stream ("transport", "geometry", "predictor", "smooth" = the
- * finest-level Jacobi sweeps, "spmv", "resid64", "project"; NULL or "" turns
+ * finest-level Jacobi sweeps, "spmv", "update" = the fused CG update and
+ * first sweep, "resid64", "project", "species" = the species transport
+ * stages; NULL or "" turns
  * timing off and clears the totals).  tcf_profile_read synchronises on the
  * last recorded event and returns the summed milliseconds and the number of
  * timed launches since tcf_profile was called. */

@@ -141,8 +141,10 @@ struct tcf_grid {
 
 namespace {
 
-enum Family { FAM_TRANSPORT = 0, FAM_GEOMETRY, FAM_PREDICTOR, FAM_SMOOTH0, FAM_SPMV, FAM_RESID64, FAM_PROJECT, FAM_N };
-const char* kFamilyNames[FAM_N] = {"transport", "geometry", "predictor", "smooth", "spmv", "resid64", "project"};
+enum Family { FAM_TRANSPORT = 0, FAM_GEOMETRY, FAM_PREDICTOR, FAM_SMOOTH0, FAM_SPMV, FAM_RESID64, FAM_PROJECT,
+              FAM_SPECIES, FAM_UPDATE, FAM_N };
+const char* kFamilyNames[FAM_N] = {"transport", "geometry", "predictor", "smooth", "spmv",
+                                   "resid64", "project", "species", "update"};
 constexpr size_t kProfPairs = 512;
 
 hipError_t prof_flush(tcf_grid* g) {
@@ -223,16 +225,21 @@ void carve_fields(Carver& cv, const Dims& D, Fields<R>& F, int mg_levels, bool a
     const long n = L.n();
     const long nu = (long)(L.nx + 1) * L.ny * L.nz, nv = (long)L.nx * (L.ny + 1) * L.nz,
                nw = D.dim == 3 ? (long)L.nx * L.ny * (L.nz + 1) : 0;
+    // level 0 of a multi-level hierarchy is applied matrix-free from alpha:
+    // only the FP64 path keeps its weights (aliased), and 1/diag is not kept
+    const bool matfree = l == 0 && ld.size() > 1;
     if (l == 0 && alias_state) {
       L.ax = (R*)ax64;
       L.ay = (R*)ay64;
       L.az = (R*)az64;
+    } else if (matfree) {
+      L.ax = L.ay = L.az = nullptr;
     } else {
       L.ax = cv.take<R>(nu);
       L.ay = cv.take<R>(nv);
       L.az = D.dim == 3 ? cv.take<R>(nw) : nullptr;
     }
-    L.wdiag = cv.take<R>(n);
+    L.wdiag = matfree ? nullptr : cv.take<R>(n);
     if (l > 0) {
       L.x = cv.take<R>(n);
       L.x2 = cv.take<R>(n);
@@ -266,9 +273,15 @@ size_t carve(const tcf_config* c, void* base, tcf_grid* g) {
   G->b64 = cv.take<double>(D.N);
   G->r64 = cv.take<double>(D.N);
   G->zero64 = cv.take<double>(D.N);
-  G->ax64 = cv.take<double>(D.Nu);
-  G->ay64 = cv.take<double>(D.Nv);
-  G->az64 = D.dim == 3 ? cv.take<double>(D.Nw) : nullptr;
+  // FP64 fine face weights: read by the FP64 path and by single-level
+  // hierarchies; the FP32 refinement recomputes them from alpha
+  if (c->precision != TCF_FP32_REFINE || level_dims(D, c->mg_levels).size() == 1) {
+    G->ax64 = cv.take<double>(D.Nu);
+    G->ay64 = cv.take<double>(D.Nv);
+    G->az64 = D.dim == 3 ? cv.take<double>(D.Nw) : nullptr;
+  } else {
+    G->ax64 = G->ay64 = G->az64 = nullptr;
+  }
   if (c->precision == TCF_FP32_REFINE)
     carve_fields<float>(cv, D, G->f32, c->mg_levels, false, c->species != 0, nullptr, nullptr, nullptr, nullptr,
                         nullptr, nullptr);
@@ -532,7 +545,10 @@ tcf_status pcg_iterate(tcf_grid* g, Fields<R>& F, R* x, R* r, int maxit, int* it
     }
     finalize(s, g->part[0], np, g->scal, g->iflag, F_ALPHA, 0, 0.0);
     std::swap(dcur, dnext);
-    np = fine_update_smooth<R>(s, dim, Fd, wj, g->scal, x, r, dcur, F.z2, g->part[0], g->iflag);
+    {
+      Prof pr(g, FAM_UPDATE);
+      np = fine_update_smooth<R>(s, dim, Fd, wj, g->scal, x, r, dcur, F.z2, g->part[0], g->iflag);
+    }
     finalize(s, g->part[0], np, g->scal, g->iflag, F_RR, 0, 1.0);
     vcycle<R>(g, F, 0, r, F.z, F.z2, g->part[0], true, &np);
     finalize(s, g->part[0], np, g->scal, g->iflag, F_RZ, 0, 0.0);
@@ -695,9 +711,18 @@ tcf_status step_once(tcf_grid* g, double dt, tcf_step_info* inf, bool want_diag)
     transport_stage<R>(P, s, F.a2, F.T2, F.a, F.T, F.u, F.v, F.w, F.a, F.T, 1.0 / 3.0, 2.0 / 3.0);
   }
   if (F.c) {  // the species: the same three stages
-    transport_scalar<R>(P, s, F.c, F.c, F.u, F.v, F.w, F.c1, 0.0, 1.0);
-    transport_scalar<R>(P, s, F.c1, F.c, F.u, F.v, F.w, F.c2, 0.75, 0.25);
-    transport_scalar<R>(P, s, F.c2, F.c, F.u, F.v, F.w, F.c, 1.0 / 3.0, 2.0 / 3.0);
+    {
+      Prof pr(g, FAM_SPECIES);
+      transport_scalar<R>(P, s, F.c, F.c, F.u, F.v, F.w, F.c1, 0.0, 1.0);
+    }
+    {
+      Prof pr(g, FAM_SPECIES);
+      transport_scalar<R>(P, s, F.c1, F.c, F.u, F.v, F.w, F.c2, 0.75, 0.25);
+    }
+    {
+      Prof pr(g, FAM_SPECIES);
+      transport_scalar<R>(P, s, F.c2, F.c, F.u, F.v, F.w, F.c, 1.0 / 3.0, 2.0 / 3.0);
+    }
   }
   tcf_status st = TCF_OK;
   if (!(g->cfg.flags & TCF_TRANSPORT_ONLY)) {
