@@ -137,6 +137,14 @@ __device__ __forceinline__ double block_reduce(double v, double* sh) {
 }
 
 __device__ __forceinline__ int block_linear() { return blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z); }
+// Tile number of a block of a 1-D grid, grouped by XCD: the dispatcher deals
+// blocks round-robin over the 8 XCDs (block b runs on XCD b % 8), so XCD x
+// receives the contiguous tile range [x nb/8, (x+1) nb/8) and neighbouring
+// tiles share that XCD's L2.
+__device__ __forceinline__ int xcd_tile() {
+  const int nb = gridDim.x, b = blockIdx.x;
+  return (nb % 8 == 0) ? (b % 8) * (nb / 8) + b / 8 : b;
+}
 
 
 }  // namespace dev

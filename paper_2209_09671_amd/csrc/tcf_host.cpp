@@ -750,14 +750,7 @@ tcf_status step_once(tcf_grid* g, double dt, tcf_step_info* inf, bool want_diag)
   }
   g->t += dt;
   if (want_diag) {
-    const int nbc = nblocks_cells(D.nx, D.ny, D.nz);
-    diagnostics<R>(P, s, F.a, g->u64, g->v64, g->w64, g->part[0], g->nb);
-    finalize(s, g->part[0], nbc, g->scal, g->iflag, F_STORE, S_SUMA, 0.0);
-    finalize(s, g->part[0] + g->nb, nbc, g->scal, g->iflag, F_MIN, S_AMIN, 0.0);
-    finalize(s, g->part[0] + 2 * g->nb, nbc, g->scal, g->iflag, F_MAX, S_AMAX, 0.0);
-    finalize(s, g->part[0] + 3 * g->nb, nbc, g->scal, g->iflag, F_STORE, S_DIV2, 0.0);
-    finalize(s, g->part[0] + 4 * g->nb, nbc, g->scal, g->iflag, F_MAX, S_UMAX, 0.0);
-    finalize(s, g->part[0] + 5 * g->nb, nbc, g->scal, g->iflag, F_MAX, S_NONFIN, 0.0);
+    diagnostics<R>(P, s, F.a, g->u64, g->v64, g->w64, g->part[0], g->nb, g->scal);
     HIPCHECK(read_back(g));
     const double* h = g->hscal;
     if (inf) {

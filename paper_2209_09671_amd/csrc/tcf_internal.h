@@ -155,9 +155,11 @@ void fill(hipStream_t s, long n, R* y, double v);
 template <class R>
 void project(const KParams& P, hipStream_t s, const R* a, const double* p, const R* us, const R* vs,
              const R* ws, double* u, double* v, double* w, R* ur, R* vr, R* wr);
+// per-block partials of the six diagnostics (stride apart, at most stride
+// blocks) reduced into scal[S_SUMA .. S_NONFIN]
 template <class R>
 void diagnostics(const KParams& P, hipStream_t s, const R* a, const double* u, const double* v,
-                 const double* w, double* part, int stride);
+                 const double* w, double* part, int stride, double* scal);
 
 // adjoint (tcf_adjoint.hip), FP64
 void adj_project(const KParams& P, hipStream_t s, const double* a, const double* p, const double* ub,

@@ -426,6 +426,65 @@ __global__ __launch_bounds__(1024) void k_coarse_factor(Level<R> L, double* __re
   }
 }
 
+// The same inverse for a coarsest level of at most kCoarseLdsMax cells, with
+// the matrix held in LDS (rows padded by one double against bank conflicts):
+// per pivot one barrier after the pivot row and column are copied out and
+// one after the elimination.
+constexpr int kCoarseLdsMax = 64;
+template <class R, int DIM>
+__global__ __launch_bounds__(1024) void k_coarse_factor_lds(Level<R> L, R* __restrict__ Minv) {
+  constexpr int LD = kCoarseLdsMax + 1;
+  __shared__ double A[kCoarseLdsMax * LD];
+  __shared__ double col[kCoarseLdsMax], prow[kCoarseLdsMax];
+  __shared__ double sh[16];
+  const int n = (int)L.n();
+  const int t = threadIdx.x, nt = blockDim.x;
+  for (int e = t; e < n * n; e += nt) A[(e / n) * LD + e % n] = 0.0;
+  __syncthreads();
+  double dsum = 0.0;
+  for (int c = t; c < n; c += nt) {
+    const int i = c % L.nx, j = (c / L.nx) % L.ny, k = c / (L.nx * L.ny);
+    double d = 0.0;
+    auto off = [&](int nb, double w) {
+      A[c * LD + nb] = -w;
+      d += w;
+    };
+    if (i > 0) off(c - 1, (double)L.ax[fidx<0>(i, j, k, L.nx, L.ny)]);
+    if (i < L.nx - 1) off(c + 1, (double)L.ax[fidx<0>(i + 1, j, k, L.nx, L.ny)]);
+    if (j > 0) off(c - L.nx, (double)L.ay[fidx<1>(i, j, k, L.nx, L.ny)]);
+    if (j < L.ny - 1) off(c + L.nx, (double)L.ay[fidx<1>(i, j + 1, k, L.nx, L.ny)]);
+    if (DIM == 3) {
+      const int pl = L.nx * L.ny;
+      if (k > 0) off(c - pl, (double)L.az[fidx<2>(i, j, k, L.nx, L.ny)]);
+      if (k < L.nz - 1) off(c + pl, (double)L.az[fidx<2>(i, j, k + 1, L.nx, L.ny)]);
+    }
+    A[c * LD + c] = d;
+    dsum += d;
+  }
+  const double gamma = block_reduce<0>(dsum, sh) / n;
+  __syncthreads();
+  for (int e = t; e < n * n; e += nt) A[(e / n) * LD + e % n] += gamma / n;
+  __syncthreads();
+  for (int p = 0; p < n; ++p) {
+    if (t < n) {
+      col[t] = A[t * LD + p];
+      prow[t] = A[p * LD + t];
+    }
+    __syncthreads();
+    const double piv = 1.0 / col[p];
+    for (int e = t; e < n * n; e += nt) {
+      const int i = e / n, j = e % n;
+      const double pj = (j == p ? 1.0 : prow[j]) * piv;  // the scaled pivot row
+      A[i * LD + j] = i == p ? pj : (j == p ? 0.0 : A[i * LD + j]) - col[i] * pj;
+    }
+    __syncthreads();
+  }
+  for (int e = t; e < n * n; e += nt) {
+    const int i = e / n, j = e % n;
+    Minv[e] = R(0.5 * (A[i * LD + j] + A[j * LD + i]));
+  }
+}
+
 // out = Minv b on the coarsest level (one block, one row per thread).
 template <class R>
 __global__ __launch_bounds__(1024) void k_coarse_apply(int n, const R* __restrict__ Minv, const R* __restrict__ b,
@@ -520,51 +579,60 @@ __device__ __forceinline__ double rcp64(double x) {
 }
 
 template <class R, int DIM>
-__global__ __launch_bounds__(256) void k_resid64a(KParams P, int kz, const R* __restrict__ a,
+__global__ __launch_bounds__(256) void k_resid64a(KParams P, int kz, int ntx, int nty, const R* __restrict__ a,
                                                   const double* __restrict__ b, const double* __restrict__ scal,
                                                   const double* __restrict__ p, double* __restrict__ r,
                                                   double* __restrict__ pbb, double* __restrict__ prr) {
   // one column per thread, marching over a chunk of kz planes: the z
   // neighbours of p and of the density roll through registers (loaded one
   // plane ahead) and the weight of the face to the next plane is carried to
-  // it; the in-plane neighbours come through L1 from the block's own rows
+  // it; the in-plane neighbours come through L1/L2 from the block's own rows
+  // and its neighbour tiles, which run on the same XCD.  Every load is
+  // unconditional: a missing neighbour (wall) reads the cell itself, whose
+  // term w (p_c - p_c) is exactly zero.
   __shared__ double sh[8];
   const int nx = P.nx, ny = P.ny, nz = P.nz;
-  const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y;
-  const int k0 = blockIdx.z * kz, k1 = min(k0 + kz, nz);
+  const int t = xcd_tile();
+  const int tx = t % ntx, ty = (t / ntx) % nty, tz = t / (ntx * nty);
+  const int i = tx * BX + threadIdx.x, j = ty * BY + threadIdx.y;
+  const int k0 = tz * kz, k1 = min(k0 + kz, nz);
   const bool act = i < nx && j < ny;
   const size_t pl = (size_t)nx * ny;
   const size_t col = act ? (size_t)i + (size_t)nx * j : 0;
-  // in-plane neighbour offsets (own cell where there is none; its term is skipped)
-  const long oxm = i > 0 ? -1 : 0, oxp = i < nx - 1 ? 1 : 0;
-  const long oym = j > 0 ? -(long)nx : 0, oyp = j < ny - 1 ? (long)nx : 0;
+  // (an inactive thread reads its column 0 only)
+  const long oxm = act && i > 0 ? -1 : 0, oxp = act && i < nx - 1 ? 1 : 0;
+  const long oym = act && j > 0 ? -(long)nx : 0, oyp = act && j < ny - 1 ? (long)nx : 0;
   const double c2 = 2.0 * P.ih * P.ih;  // a_f = c2 / (rho_L + rho_R)
   auto rho = [&](R av) { return mixp((double)av, P.rho1, P.rho2); };
   auto plane = [&](int kk) { return (size_t)min(max(kk, 0), nz - 1) * pl; };
+  const double mean = scal[S_MEAN];
   double vb = 0.0, vr = 0.0;
   double pm = p[col + plane(k0 - 1)], pc = p[col + plane(k0)], pp = p[col + plane(k0 + 1)];
   R am = a[col + plane(k0 - 1)], ac = a[col + plane(k0)], ap = a[col + plane(k0 + 1)];
   double wz = c2 * rcp64(rho(am) + rho(ac));  // face k-1 | k
   for (int k = k0; k < k1; ++k) {
-    const double pn = p[col + plane(k + 2)];
-    const R an = a[col + plane(k + 2)];
     const size_t c = col + (size_t)k * pl;
+    const size_t cn = col + plane(k + 2);
+    const double pn = p[cn];
+    const R an = a[cn];
+    const double p0 = p[c + oxm], p1 = p[c + oxp], p2 = p[c + oym], p3 = p[c + oyp];
+    const R a0 = a[c + oxm], a1 = a[c + oxp], a2 = a[c + oym], a3 = a[c + oyp];
+    const double bc = b[c];
     const double rc = rho(ac);
-    double sK = 0.0;
     auto term = [&](double pnb, R anb) { return c2 * rcp64(rho(anb) + rc) * (pc - pnb); };
+    double sK = term(p0, a0);
+    sK += term(p1, a1);
+    sK += term(p2, a2);
+    sK += term(p3, a3);
     double wzn = 0.0;
+    if (DIM == 3) {
+      sK += wz * (pc - pm);
+      wzn = c2 * rcp64(rc + rho(ap));
+      sK += wzn * (pc - pp);
+    }
+    const double rhs = -(bc - mean);
+    const double rr = rhs - sK;
     if (act) {
-      if (oxm) sK += term(p[c + oxm], a[c + oxm]);
-      if (oxp) sK += term(p[c + oxp], a[c + oxp]);
-      if (oym) sK += term(p[c + oym], a[c + oym]);
-      if (oyp) sK += term(p[c + oyp], a[c + oyp]);
-      if (DIM == 3) {
-        if (k > 0) sK += wz * (pc - pm);
-        wzn = c2 * rcp64(rc + rho(ap));
-        if (k < nz - 1) sK += wzn * (pc - pp);
-      }
-      const double rhs = -(b[c] - scal[S_MEAN]);
-      const double rr = rhs - sK;
       r[c] = rr;
       vb += rhs * rhs;
       vr += rr * rr;
@@ -580,8 +648,8 @@ __global__ __launch_bounds__(256) void k_resid64a(KParams P, int kz, const R* __
   const double sb = block_reduce<0>(vb, sh);
   const double sr = block_reduce<0>(vr, sh);
   if (threadIdx.x == 0 && threadIdx.y == 0) {
-    pbb[block_linear()] = sb;
-    prr[block_linear()] = sr;
+    pbb[blockIdx.x] = sb;
+    prr[blockIdx.x] = sr;
   }
 }
 
@@ -687,36 +755,50 @@ __global__ __launch_bounds__(256) void k_project(KParams P, const R* __restrict_
 }
 
 // Diagnostics per cell: alpha (sum/min/max), |D u|^2 and max |u_f| over the
-// cell's low faces (every interior face is some cell's low face).
+// cell's low faces (every interior face is some cell's low face), and a
+// non-finite flag.  Each thread marches its column over a chunk of kz planes
+// (the z face between two planes is loaded once and carried); the block then
+// reduces once.  Loads use indexes clamped into the grid, so every thread
+// issues the same loads; only active columns contribute.
 template <class R, int DIM>
-__global__ __launch_bounds__(256) void k_diag(KParams P, const R* __restrict__ a, const double* __restrict__ u,
-                                              const double* __restrict__ v, const double* __restrict__ w,
-                                              double* __restrict__ part, int stride) {
+__global__ __launch_bounds__(256) void k_diag(KParams P, int kz, int ntx, int nty, const R* __restrict__ a,
+                                              const double* __restrict__ u, const double* __restrict__ v,
+                                              const double* __restrict__ w, double* __restrict__ part, int stride) {
   __shared__ double sh[8];
-  const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
-  const int nx = P.nx, ny = P.ny;
+  const int nx = P.nx, ny = P.ny, nz = P.nz;
+  const int t = xcd_tile();
+  const int tx = t % ntx, ty = (t / ntx) % nty, tz = t / (ntx * nty);
+  const int i = tx * BX + threadIdx.x, j = ty * BY + threadIdx.y;
+  const int k0 = tz * kz, k1 = min(k0 + kz, nz);
+  const bool act = i < nx && j < ny;
+  const int ic = min(i, nx - 1), jc = min(j, ny - 1);
   double s = 0.0, mn = DBL_MAX, mx = -DBL_MAX, d2 = 0.0, um = 0.0, fin = 0.0;
-  if (i < nx && j < ny) {
-    const double av = (double)a[cidx(i, j, k, nx, ny)];
-    s = av;
-    mn = av;
-    mx = av;
-    const double u0 = u[fidx<0>(i, j, k, nx, ny)], u1 = u[fidx<0>(i + 1, j, k, nx, ny)];
-    const double v0 = v[fidx<1>(i, j, k, nx, ny)], v1 = v[fidx<1>(i, j + 1, k, nx, ny)];
+  double w0 = DIM == 3 ? w[fidx<2>(ic, jc, k0, nx, ny)] : 0.0;
+  for (int k = k0; k < k1; ++k) {
+    const double av = (double)a[cidx(ic, jc, k, nx, ny)];
+    const double u0 = u[fidx<0>(ic, jc, k, nx, ny)], u1 = u[fidx<0>(ic + 1, jc, k, nx, ny)];
+    const double v0 = v[fidx<1>(ic, jc, k, nx, ny)], v1 = v[fidx<1>(ic, jc + 1, k, nx, ny)];
+    const double w1 = DIM == 3 ? w[fidx<2>(ic, jc, k + 1, nx, ny)] : 0.0;
     double dv = (u1 - u0) + (v1 - v0);
-    um = fmax(fabs(u0), fabs(v0));
+    double m = fmax(fabs(u0), fabs(v0));
     double chk = av + u0 + v0;
     if (DIM == 3) {
-      const double w0 = w[fidx<2>(i, j, k, nx, ny)], w1 = w[fidx<2>(i, j, k + 1, nx, ny)];
       dv += w1 - w0;
-      um = fmax(um, fabs(w0));
+      m = fmax(m, fabs(w0));
       chk += w0;
     }
     dv *= P.ih;
-    d2 = dv * dv;
-    fin = isfinite(chk) ? 0.0 : 1.0;
+    if (act) {
+      s += av;
+      mn = fmin(mn, av);
+      mx = fmax(mx, av);
+      d2 += dv * dv;
+      um = fmax(um, m);
+      fin = isfinite(chk) ? fin : 1.0;
+    }
+    w0 = w1;
   }
-  const int bl = block_linear();
+  const int bl = blockIdx.x;
   double r;
   r = block_reduce<0>(s, sh);
   if (threadIdx.x == 0 && threadIdx.y == 0) part[bl] = r;
@@ -730,6 +812,40 @@ __global__ __launch_bounds__(256) void k_diag(KParams P, const R* __restrict__ a
   if (threadIdx.x == 0 && threadIdx.y == 0) part[4 * stride + bl] = r;
   r = block_reduce<1>(fin, sh);
   if (threadIdx.x == 0 && threadIdx.y == 0) part[5 * stride + bl] = r;
+}
+
+// The six diagnostics reductions of k_diag's partials in one launch, each in
+// the fixed order of k_finalize: sum alpha, min alpha, max alpha, |Du|^2,
+// max |u_f|, non-finite flag.
+__global__ __launch_bounds__(1024) void k_finalize_diag(const double* __restrict__ part, int n, int stride,
+                                                        double* __restrict__ scal) {
+  __shared__ double sh[16];
+  const int t = threadIdx.x, nt = blockDim.x;
+  const int slots[6] = {S_SUMA, S_AMIN, S_AMAX, S_DIV2, S_UMAX, S_NONFIN};
+  for (int q6 = 0; q6 < 6; ++q6) {
+    const double* pp = part + (long)q6 * stride;
+    const int kind = (q6 == 0 || q6 == 3) ? 0 : (q6 == 1 ? 2 : 1);  // 0 sum, 1 max, 2 min
+    double v;
+    if (kind == 0) {
+      double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+      int q = t;
+      for (; q + 3 * nt < n; q += 4 * nt) {
+        a0 += pp[q];
+        a1 += pp[q + nt];
+        a2 += pp[q + 2 * nt];
+        a3 += pp[q + 3 * nt];
+      }
+      for (; q < n; q += nt) a0 += pp[q];
+      v = block_reduce<0>((a0 + a1) + (a2 + a3), sh);
+    } else {
+      const double init = kind == 2 ? DBL_MAX : -DBL_MAX;
+      double a0 = init;
+      for (int q = t; q < n; q += nt) a0 = kind == 2 ? fmin(a0, pp[q]) : fmax(a0, pp[q]);
+      v = kind == 2 ? block_reduce<2>(a0, sh) : block_reduce<1>(a0, sh);
+    }
+    if (t == 0) scal[slots[q6]] = v;
+    __syncthreads();
+  }
 }
 
 __global__ __launch_bounds__(256) void k_to_f32(long n, const double* __restrict__ x, float* __restrict__ y) {
@@ -894,8 +1010,14 @@ void mg_coarse_solve(hipStream_t s, int dim, const Level<R>& L, const R* b, R* x
 
 template <class R>
 void coarse_factor(hipStream_t s, int dim, const Level<R>& L, double* A, R* Minv) {
-  if (dim == 3) hipLaunchKernelGGL((k_coarse_factor<R, 3>), dim3(1), dim3(1024), 0, s, L, A, Minv);
-  else hipLaunchKernelGGL((k_coarse_factor<R, 2>), dim3(1), dim3(1024), 0, s, L, A, Minv);
+  if (L.n() <= kCoarseLdsMax) {
+    if (dim == 3) hipLaunchKernelGGL((k_coarse_factor_lds<R, 3>), dim3(1), dim3(1024), 0, s, L, Minv);
+    else hipLaunchKernelGGL((k_coarse_factor_lds<R, 2>), dim3(1), dim3(1024), 0, s, L, Minv);
+  } else if (dim == 3) {
+    hipLaunchKernelGGL((k_coarse_factor<R, 3>), dim3(1), dim3(1024), 0, s, L, A, Minv);
+  } else {
+    hipLaunchKernelGGL((k_coarse_factor<R, 2>), dim3(1), dim3(1024), 0, s, L, A, Minv);
+  }
 }
 
 template <class R>
@@ -923,9 +1045,9 @@ int resid64a(const KParams& P, hipStream_t s, const R* a, const double* b, const
   int nch = std::max(1, std::min(nz, (2048 + ntx * nty - 1) / (ntx * nty)));
   const int kz = (nz + nch - 1) / nch;
   nch = (nz + kz - 1) / kz;
-  dim3 g(ntx, nty, nch);
-  if (P.dim == 3) hipLaunchKernelGGL((k_resid64a<R, 3>), g, blk(), 0, s, P, kz, a, b, scal, p, r, pbb, prr);
-  else hipLaunchKernelGGL((k_resid64a<R, 2>), g, blk(), 0, s, P, kz, a, b, scal, p, r, pbb, prr);
+  dim3 g(ntx * nty * nch);
+  if (P.dim == 3) hipLaunchKernelGGL((k_resid64a<R, 3>), g, blk(), 0, s, P, kz, ntx, nty, a, b, scal, p, r, pbb, prr);
+  else hipLaunchKernelGGL((k_resid64a<R, 2>), g, blk(), 0, s, P, kz, ntx, nty, a, b, scal, p, r, pbb, prr);
   return ntx * nty * nch;
 }
 
@@ -983,10 +1105,17 @@ void project(const KParams& P, hipStream_t s, const R* a, const double* p, const
 
 template <class R>
 void diagnostics(const KParams& P, hipStream_t s, const R* a, const double* u, const double* v, const double* w,
-                 double* part, int stride) {
-  dim3 g = grid_for(P.nx, P.ny, P.nz);
-  if (P.dim == 3) hipLaunchKernelGGL((k_diag<R, 3>), g, blk(), 0, s, P, a, u, v, w, part, stride);
-  else hipLaunchKernelGGL((k_diag<R, 2>), g, blk(), 0, s, P, a, u, v, w, part, stride);
+                 double* part, int stride, double* scal) {
+  // chunks of planes so that the grid has >= 2048 blocks of 256
+  const int ntx = (P.nx + BX - 1) / BX, nty = (P.ny + BY - 1) / BY;
+  const int nz = P.dim == 3 ? P.nz : 1;
+  int nch = std::max(1, std::min(nz, (2048 + ntx * nty - 1) / (ntx * nty)));
+  const int kz = (nz + nch - 1) / nch;
+  nch = (nz + kz - 1) / kz;
+  const int nb = ntx * nty * nch;
+  if (P.dim == 3) hipLaunchKernelGGL((k_diag<R, 3>), dim3(nb), blk(), 0, s, P, kz, ntx, nty, a, u, v, w, part, stride);
+  else hipLaunchKernelGGL((k_diag<R, 2>), dim3(nb), blk(), 0, s, P, kz, ntx, nty, a, u, v, w, part, stride);
+  hipLaunchKernelGGL(k_finalize_diag, dim3(1), dim3(1024), 0, s, part, nb, stride, scal);
 }
 
 void to_f32(hipStream_t s, long n, const double* x, float* y) {
@@ -1036,7 +1165,7 @@ void zero_walls(const KParams& P, hipStream_t s, R* u, R* v, R* w) {
   template void project<R>(const KParams&, hipStream_t, const R*, const double*, const R*, const R*, const R*,    \
                            double*, double*, double*, R*, R*, R*);                                                \
   template void diagnostics<R>(const KParams&, hipStream_t, const R*, const double*, const double*,               \
-                               const double*, double*, int);                                                \
+                               const double*, double*, int, double*);                                       \
   template void zero_walls<R>(const KParams&, hipStream_t, R*, R*, R*);
 
 TCF_INST(double)
