@@ -41,7 +41,8 @@ class OrcConfig(C.Structure):
                 ("p_rtol", C.c_double), ("p_maxit", C.c_int), ("mg_nu", C.c_int),
                 ("mg_omega_c", C.c_double), ("mg_coarse_sweeps", C.c_int),
                 ("sigkap_const", C.c_double),
-                ("species", C.c_int), ("dsigma_dc", C.c_double), ("c0", C.c_double)]
+                ("species", C.c_int), ("dsigma_dc", C.c_double), ("c0", C.c_double),
+                ("integrator", C.c_int)]
 
 
 class OrcInfo(C.Structure):
@@ -94,6 +95,7 @@ def make_config(c: dict, flags: int = 0, sigkap_const: float = 0.0) -> OrcConfig
     o.sigkap_const = sigkap_const
     o.species = int(c.get("species", 0))
     o.dsigma_dc, o.c0 = float(c.get("dsigma_dc", 0.0)), float(c.get("c0", 0.0))
+    o.integrator = int(c.get("integrator", 0))
     return o
 
 

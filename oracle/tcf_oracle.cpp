@@ -48,6 +48,10 @@ struct OrcConfig {
   // like alpha, sigma = sigma0 + dsigma_dT (T - T0) + dsigma_dc (c - c0)
   int species;
   double dsigma_dc, c0;
+  // time integrator: 0 = transport SSP-RK3 with frozen u^n, then one
+  // forward-Euler predictor and one projection; 1 = SSP-RK3 over the whole
+  // state with a projection in every stage
+  int integrator;
 };
 
 struct OrcInfo {
@@ -831,6 +835,75 @@ void project(const Grid& g, double dt, const double* a, const double* p, const d
   }
 }
 
+// Shu-Osher SSP-RK3 combination of stage s (0, 1, 2) from the base value q^n
+// and the forward-Euler update x = q^(s) + dt L(q^(s)), written exactly as in
+// transport_rk3 so that the two integrators agree where they must.
+inline double rk_stage(int s, double base, double x) {
+  return s == 0 ? x : (s == 1 ? 0.75 * base + 0.25 * x : base / 3.0 + 2.0 / 3.0 * x);
+}
+
+// One step of the per-stage projected SSP-RK3 (integrator 1).
+// reading: the paper does not state its time integrator.  This variant
+// applies the three Shu-Osher stages to the whole state (alpha, T, c, u):
+// every right-hand side of a stage (transport with the stage's own velocity,
+// the heat source at the stage time t, t + dt, t + dt/2, and the momentum
+// predictor with its geometry and CSF force) is taken at the stage state;
+// the stage's velocity is the same convex combination as the scalars and is
+// then projected with the density of the stage state, the alpha at which
+// the stage's momentum right-hand side was taken (so that the velocity moves
+// along P_alpha F of one state; projecting with the stage's new alpha instead
+// costs an O(dt^2) error per step wherever the density varies).  The
+// projection uses the stage's weight on dt (1, 1/4, 2/3) as its step (any
+// positive factor gives the same velocity; it only scales p).  Returns the
+// worst solver status; info gets the last stage's solve and divergence ratio.
+int step_rk3p(Grid& g, double t, double dt, std::vector<double>& av, std::vector<double>& tv,
+              std::vector<double>* cv, double* u, double* v, double* w, double* p, OrcInfo& inf) {
+  const OrcConfig& c = g.c;
+  const long N = g.N();
+  const bool mom = !(c.flags & F_TRANSPORT_ONLY);
+  double* vel[3] = {u, v, w};
+  const long nf[3] = {g.Nu(), g.Nv(), g.Nw()};
+  const std::vector<double> an(av), Tn(tv), cn = cv ? *cv : std::vector<double>();
+  std::vector<double> un[3];
+  for (int d = 0; d < g.dim; ++d) un[d].assign(vel[d], vel[d] + nf[d]);
+  std::vector<double> La(N), LT(N), Lc(cv ? N : 0), b(N), dv(N), as(N);
+  std::vector<double> us[3] = {std::vector<double>(g.Nu()), std::vector<double>(g.Nv()),
+                               std::vector<double>(g.Nw() ? g.Nw() : 1)};
+  const double tc[3] = {0.0, 1.0, 0.5}, wdt[3] = {1.0, 0.25, 2.0 / 3.0};
+  int status = 0;
+  for (int s = 0; s < 3; ++s) {
+    // right-hand sides at the stage state (av, tv, cv, u)
+    transport_rhs(g, t + tc[s] * dt, av.data(), tv.data(), u, v, w, La.data(), LT.data());
+    if (cv) advect_rhs(g, cv->data(), u, v, w, Lc.data());
+    if (mom) {
+      g.cf = cv ? cv->data() : nullptr;
+      predictor(g, dt, av.data(), tv.data(), u, v, w, us[0].data(), us[1].data(), us[2].data());
+    }
+    as = av;  // the stage state's alpha, for the projection
+    for (long q = 0; q < N; ++q) {
+      av[q] = rk_stage(s, an[q], av[q] + dt * La[q]);
+      tv[q] = rk_stage(s, Tn[q], tv[q] + dt * LT[q]);
+    }
+    if (cv)
+      for (long q = 0; q < N; ++q) (*cv)[q] = rk_stage(s, cn[q], (*cv)[q] + dt * Lc[q]);
+    if (!mom) continue;
+    for (int d = 0; d < g.dim; ++d)
+      for (long f = 0; f < nf[d]; ++f) us[d][f] = rk_stage(s, un[d][f], us[d][f]);
+    const double dts = wdt[s] * dt;
+    divergence(g, us[0].data(), us[1].data(), g.dim == 3 ? us[2].data() : nullptr, b.data());
+    const double nstar = std::sqrt(dot(b.data(), b.data(), N));
+    for (long q = 0; q < N; ++q) b[q] /= dts;
+    const int st = solve_pressure(g, as.data(), b.data(), p, &inf);
+    if (st) status = st;
+    project(g, dts, as.data(), p, us[0].data(), us[1].data(), us[2].data(), u, v, w);
+    divergence(g, u, v, g.dim == 3 ? w : nullptr, dv.data());
+    const double nnew = std::sqrt(dot(dv.data(), dv.data(), N));
+    inf.div_rel = nstar > 0.0 ? nnew / nstar : 0.0;
+  }
+  g.cf = cv ? cv->data() : nullptr;
+  return status;
+}
+
 bool finite_all(const double* x, long n) {
   for (long i = 0; i < n; ++i)
     if (!std::isfinite(x[i])) return false;
@@ -936,8 +1009,13 @@ int orc_step(const OrcConfig* c, double t0, double dt, int nsteps, double* a, do
   OrcInfo inf{};
   for (int s = 0; s < nsteps; ++s) {
     double t = t0 + s * dt;
-    transport_rk3(g, t, dt, av, tv, u, v, w, cf ? &cv : nullptr);
-    if (!(c->flags & F_TRANSPORT_ONLY)) {
+    if (c->integrator == 1) {
+      const int st = step_rk3p(g, t, dt, av, tv, cf ? &cv : nullptr, u, v, w, p, inf);
+      if (st) status = st;
+    } else {
+      transport_rk3(g, t, dt, av, tv, u, v, w, cf ? &cv : nullptr);
+    }
+    if (c->integrator != 1 && !(c->flags & F_TRANSPORT_ONLY)) {
       predictor(g, dt, av.data(), tv.data(), u, v, w, us.data(), vs.data(), ws.data());
       divergence(g, us.data(), vs.data(), g.dim == 3 ? ws.data() : nullptr, b.data());
       double nstar = std::sqrt(dot(b.data(), b.data(), N));
