@@ -11,7 +11,7 @@ the same accuracy is reported beside it.
 
 Prints ONE JSON line.  Options: --steps K --warmup W --gpus 1 --workload i
 --kernel FAMILY (kernel family for the roofline entry) --no-cpu --no-fp64
---no-adjoint --no-species.
+--no-adjoint --no-species --no-rk3p.
 """
 from __future__ import annotations
 
@@ -182,6 +182,7 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--adjoint-steps", type=int, default=10)
     ap.add_argument("--no-species", action="store_true")
+    ap.add_argument("--no-rk3p", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this path runs on one GPU; multi-GPU runs are not part of this build "
@@ -237,6 +238,16 @@ def main():
                                      "launches": rs["kernel_launches"], "algorithmic_bytes_per_launch": ab,
                                      "achieved_GBs": round(ab / (avg / 1e3) / 1e9, 1)}}
 
+    rk3p = None
+    if not args.no_rk3p:
+        # the time-accurate integrator: SSP-RK3 over the whole state with a
+        # projection in every stage (three pressure solves per step)
+        rr = run_gpu(dict(c, integrator=1), st, 1, args.steps, args.warmup)
+        rk3p = {"value": round(N * args.steps / (rr["ev_ms"] / 1e3) / 1e6, 3), "unit": "Mcell-steps/s",
+                "ms_per_step": round(rr["ev_ms"] / args.steps, 4), "cg_iters_per_step": round(rr["iters"], 2),
+                "refine_iters_per_step": round(rr["refs"], 2), "max_div_rel": rr["div"],
+                "max_p_relres": rr["relres"], "integrator": "SSP-RK3, projection in every stage"}
+
     adj = None
     if not args.no_adjoint:
         ca = dict(c, precision=0)
@@ -268,6 +279,7 @@ def main():
         "wall_ms_per_step": round(r32["wall"] * 1e3 / args.steps, 4),
         "adjoint": adj,
         "solutal_species": species,
+        "time_accurate_rk3": rk3p,
         "roofline": roof,
         "cpu_baseline": cpu,
     }

@@ -106,6 +106,17 @@ typedef struct tcf_config {
    * (dsigma_dc, c0 ignored).  Not combined with TCF_WITH_ADJOINT. */
   int species;
   double dsigma_dc, c0;
+  /* Time integrator.  0: SSP-RK3 transport of alpha, T (and c) with the
+   * velocity frozen at u^n, then one forward-Euler momentum predictor and
+   * one projection (first order in time overall).  1: time-accurate
+   * variant, SSP-RK3 (Shu-Osher) over the whole state (alpha, T, c, u) with
+   * a projection in every stage: each stage takes all right-hand sides
+   * (transport with the stage velocity, heat source at the stage time t,
+   * t + dt, t + dt/2, geometry, CSF force, predictor) at the stage state and
+   * projects the combined velocity with that state's density (three
+   * pressure solves per step, third order in time).  The paper does not
+   * state its integrator.  1 is not combined with TCF_WITH_ADJOINT. */
+  int integrator;
 } tcf_config;
 
 typedef struct tcf_step_info {

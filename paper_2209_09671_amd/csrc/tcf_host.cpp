@@ -114,6 +114,8 @@ struct tcf_grid {
   double t = 0.0;
   // FP64 state and scratch (both modes)
   double *u64, *v64, *w64, *p64, *b64, *r64, *ax64, *ay64, *az64, *zero64;
+  double *un64 = nullptr, *vn64 = nullptr, *wn64 = nullptr;  // base velocity u^n (integrator 1)
+  const void* a_op = nullptr;  // volume fraction of the pressure operator in use
   Fields<double> f64;
   Fields<float> f32;
   float *ax32, *ay32, *az32;
@@ -273,6 +275,11 @@ size_t carve(const tcf_config* c, void* base, tcf_grid* g) {
   G->b64 = cv.take<double>(D.N);
   G->r64 = cv.take<double>(D.N);
   G->zero64 = cv.take<double>(D.N);
+  if (c->integrator == 1) {
+    G->un64 = cv.take<double>(D.Nu);
+    G->vn64 = cv.take<double>(D.Nv);
+    G->wn64 = D.dim == 3 ? cv.take<double>(D.Nw) : nullptr;
+  }
   // FP64 fine face weights: read by the FP64 path and by single-level
   // hierarchies; the FP32 refinement recomputes them from alpha
   if (c->precision != TCF_FP32_REFINE || level_dims(D, c->mg_levels).size() == 1) {
@@ -339,6 +346,8 @@ std::string validate(const tcf_config* c) {
   if (c->species != 0 && c->species != 1) return "species must be 0 or 1";
   if (c->species && (c->flags & TCF_WITH_ADJOINT)) return "the adjoint does not cover the species field";
   if (c->species && (!std::isfinite(c->dsigma_dc) || !std::isfinite(c->c0))) return "dsigma_dc and c0 must be finite";
+  if (c->integrator != 0 && c->integrator != 1) return "integrator must be 0 or 1";
+  if (c->integrator == 1 && (c->flags & TCF_WITH_ADJOINT)) return "the adjoint covers integrator 0 only";
   if (!(c->rho1 > 0 && c->rho2 > 0)) return "densities must be positive";
   if (!(c->mu1 >= 0 && c->mu2 >= 0)) return "viscosities must be non-negative";
   if (!(c->rhocp1 > 0 && c->rhocp2 > 0)) return "rho*c_p must be positive";
@@ -407,11 +416,11 @@ hipError_t read_back(tcf_grid* g) {
 // initial residual and the coarsening) and single-level hierarchies (the
 // coarsest-level solve).  Otherwise level 1 is coarsened straight from alpha.
 template <class R>
-void build_levels(tcf_grid* g, Fields<R>& F, bool level0_stored) {
+void build_levels(tcf_grid* g, Fields<R>& F, const R* a, bool level0_stored) {
   const int dim = g->D.dim;
   if (F.lv.size() == 1) make_wdiag<R>(g->stream, dim, F.lv[0], 1.0);
   for (size_t l = 1; l < F.lv.size(); ++l) {
-    if (l == 1 && !level0_stored) coarsen_from_alpha<R>(g->P, g->stream, F.a, F.lv[1]);
+    if (l == 1 && !level0_stored) coarsen_from_alpha<R>(g->P, g->stream, a, F.lv[1]);
     else coarsen_weights<R>(g->stream, dim, F.lv[l - 1], F.lv[l]);
     make_wdiag<R>(g->stream, dim, F.lv[l], 1.0);
   }
@@ -428,7 +437,7 @@ Fields<float>& fields<float>(tcf_grid* g) { return g->f32; }
 template <class R>
 Fine<R> fine_desc(tcf_grid* g) {
   Fine<R> F;
-  F.a = fields<R>(g).a;
+  F.a = g->a_op ? (const R*)g->a_op : fields<R>(g).a;
   F.nx = g->D.nx;
   F.ny = g->D.ny;
   F.nz = g->D.nz;
@@ -609,7 +618,7 @@ tcf_status solve_refined(tcf_grid* g, double* p, int* iters, int* nref, double* 
   for (int ref = 0;; ++ref) {
     {
       Prof pr(g, FAM_RESID64);
-      nrp = resid64a<float>(g->P, s, F.a, g->b64, g->scal, p, g->r64, g->part[0], g->part[1]);
+      nrp = resid64a<float>(g->P, s, fine_desc<float>(g).a, g->b64, g->scal, p, g->r64, g->part[0], g->part[1]);
     }
     finalize(s, g->part[0], nrp, g->scal, g->iflag, F_STORE, S_BB64, 0.0);
     finalize(s, g->part[1], nrp, g->scal, g->iflag, F_SCALE, 0, (double)N);
@@ -652,19 +661,23 @@ tcf_status solve_refined(tcf_grid* g, double* p, int* iters, int* nref, double* 
   return TCF_OK;
 }
 
-// Fine face weights from the current alpha and the whole hierarchy.
+// Fine face weights from a volume fraction (the state's alpha unless one is
+// given) and the whole hierarchy; the finest-level kernels and the FP64
+// refinement residual recompute their weights from the same alpha.
 template <class R>
-void prepare_operator(tcf_grid* g) {
+void prepare_operator(tcf_grid* g, const R* a = nullptr) {
   Fields<R>& F = fields<R>(g);
+  if (!a) a = F.a;
+  g->a_op = a;
   bool stored = true;
   if (!g->fp32)
-    face_weights<R>(g->P, g->stream, F.a, g->ax64, g->ay64, g->az64, nullptr, nullptr, nullptr);
+    face_weights<R>(g->P, g->stream, a, g->ax64, g->ay64, g->az64, nullptr, nullptr, nullptr);
   else if (F.lv.size() == 1)
-    face_weights<R>(g->P, g->stream, F.a, g->ax64, g->ay64, g->az64, g->f32.lv[0].ax, g->f32.lv[0].ay,
+    face_weights<R>(g->P, g->stream, a, g->ax64, g->ay64, g->az64, g->f32.lv[0].ax, g->f32.lv[0].ay,
                     g->f32.lv[0].az);
   else
     stored = false;  // the FP64 refinement residual recomputes its weights from alpha
-  build_levels<R>(g, F, stored);
+  build_levels<R>(g, F, a, stored);
 }
 
 tcf_status solve(tcf_grid* g, double* p, tcf_step_info* inf) {
@@ -687,6 +700,9 @@ tcf_status solve(tcf_grid* g, double* p, tcf_step_info* inf) {
   if (!conv) return fail(TCF_E_NOT_CONVERGED, "pressure solve did not reach p_rtol (relres " + std::to_string(relres) + ")");
   return TCF_OK;
 }
+
+template <class R>
+tcf_status step_diag(tcf_grid* g, double dt, double dt_proj, tcf_step_info* inf);
 
 // One step S1..S8 in precision R.
 template <class R>
@@ -749,7 +765,19 @@ tcf_status step_once(tcf_grid* g, double dt, tcf_step_info* inf, bool want_diag)
                g->fp32 ? F.v : nullptr, g->fp32 ? F.w : nullptr);
   }
   g->t += dt;
-  if (want_diag) {
+  const tcf_status sd = want_diag ? step_diag<R>(g, dt, dt, inf) : TCF_OK;
+  return sd != TCF_OK ? sd : st;
+}
+
+// End-of-step diagnostics into inf (FP64 reductions).  dt_proj is the step
+// of the last projection: the divergence ratio is |D u| / |D u~| with
+// D u~ = dt_proj b.
+template <class R>
+tcf_status step_diag(tcf_grid* g, double dt, double dt_proj, tcf_step_info* inf) {
+  hipStream_t s = g->stream;
+  Fields<R>& F = fields<R>(g);
+  const KParams& P = g->P;
+  {
     diagnostics<R>(P, s, F.a, g->u64, g->v64, g->w64, g->part[0], g->nb, g->scal);
     HIPCHECK(read_back(g));
     const double* h = g->hscal;
@@ -759,12 +787,98 @@ tcf_status step_once(tcf_grid* g, double dt, tcf_step_info* inf, bool want_diag)
       inf->alpha_max = h[S_AMAX];
       inf->cfl_max = dt * h[S_UMAX] / g->cfg.h;
       const double bb = g->fp32 ? h[S_BB64] : h[S_BB];
-      inf->div_rel = (g->cfg.flags & TCF_TRANSPORT_ONLY) || bb == 0.0 ? 0.0 : std::sqrt(h[S_DIV2] / bb) / dt;
+      inf->div_rel = (g->cfg.flags & TCF_TRANSPORT_ONLY) || bb == 0.0 ? 0.0 : std::sqrt(h[S_DIV2] / bb) / dt_proj;
       inf->nonfinite = (h[S_NONFIN] > 0.0 || !std::isfinite(h[S_SUMA])) ? 1 : 0;
     }
     if (h[S_NONFIN] > 0.0 || !std::isfinite(h[S_SUMA])) return fail(TCF_E_NONFINITE, "non-finite fields after step");
   }
-  return st;
+  return TCF_OK;
+}
+
+// One step of the time-accurate integrator: SSP-RK3 (Shu-Osher) over the
+// whole state with a projection in every stage.  Stage k (0, 1, 2) takes all
+// right-hand sides at the stage state q_k = (alpha_k, T_k, c_k, u_k) and the
+// heat source at t + (0, 1, 1/2) dt:
+//   alpha_{k+1} = cb_k alpha^n + ci_k (alpha_k + dt L(q_k))   (T and c alike)
+//   u~          = cb_k u^n + ci_k (u_k + dt F(q_k))           (predictor, combine)
+//   u_{k+1}     = u~ - ci_k dt beta(alpha_k) G p,  D beta(alpha_k) G p = D u~ / (ci_k dt)
+// with (cb, ci) = (0, 1), (3/4, 1/4), (1/3, 2/3).  The projection takes the
+// density of the state the stage's momentum right-hand side was taken at.
+// Stage arrays: alpha_0 = F.a (also the base), alpha_1 = F.a1, alpha_2 =
+// F.a2; the last stage writes the base in place.  u^n is kept in FP64.
+template <class R>
+tcf_status step_rk3p(tcf_grid* g, double dt, tcf_step_info* inf, bool want_diag) {
+  hipStream_t s = g->stream;
+  Fields<R>& F = fields<R>(g);
+  const Dims& D = g->D;
+  const bool mom = !(g->cfg.flags & TCF_TRANSPORT_ONLY);
+  R* as[3] = {F.a, F.a1, F.a2};
+  R* ao[3] = {F.a1, F.a2, F.a};
+  R* Ts[3] = {F.T, F.T1, F.T2};
+  R* To[3] = {F.T1, F.T2, F.T};
+  R* cs[3] = {F.c, F.c1, F.c2};
+  R* co[3] = {F.c1, F.c2, F.c};
+  const double cb[3] = {0.0, 0.75, 1.0 / 3.0}, ci[3] = {1.0, 0.25, 2.0 / 3.0}, tc[3] = {0.0, 1.0, 0.5};
+  if (mom) {
+    copy_f64(s, D.Nu, g->u64, g->un64);
+    copy_f64(s, D.Nv, g->v64, g->vn64);
+    if (D.dim == 3) copy_f64(s, D.Nw, g->w64, g->wn64);
+  }
+  tcf_status worst = TCF_OK;
+  tcf_step_info acc{};
+  double dt_proj = dt;
+  for (int k = 0; k < 3; ++k) {
+    KParams P = g->P;
+    P.dt = dt;
+    P.t = g->t + tc[k] * dt;
+    if (mom) {
+      {
+        Prof pr(g, FAM_GEOMETRY);
+        geometry<R>(P, s, as[k], Ts[k], F.c ? cs[k] : nullptr, F.sk, F.Mx, F.My, F.Mz);
+      }
+      Prof pr(g, FAM_PREDICTOR);
+      predictor<R>(P, s, as[k], F.sk, F.Mx, F.My, F.Mz, F.u, F.v, F.w, F.us, F.vs, F.ws);
+    }
+    {
+      Prof pr(g, FAM_TRANSPORT);
+      transport_stage<R>(P, s, as[k], Ts[k], F.a, F.T, F.u, F.v, F.w, ao[k], To[k], cb[k], ci[k]);
+    }
+    if (F.c) {
+      Prof pr(g, FAM_SPECIES);
+      transport_scalar<R>(P, s, cs[k], F.c, F.u, F.v, F.w, co[k], cb[k], ci[k]);
+    }
+    if (!mom) continue;
+    if (k > 0) {
+      rk_combine<R>(s, D.Nu, k, g->un64, F.us);
+      rk_combine<R>(s, D.Nv, k, g->vn64, F.vs);
+      if (D.dim == 3) rk_combine<R>(s, D.Nw, k, g->wn64, F.ws);
+    }
+    KParams Pp = P;
+    Pp.dt = ci[k] * dt;  // the projection's step
+    const int nbc = nblocks_cells(D.nx, D.ny, D.nz);
+    divergence_rhs<R>(Pp, s, F.us, F.vs, F.ws, g->b64, g->part[0]);
+    finalize(s, g->part[0], nbc, g->scal, g->iflag, F_MEAN, S_MEAN, (double)D.N);
+    prepare_operator<R>(g, as[k]);
+    tcf_step_info si{};
+    const tcf_status st = solve(g, g->p64, &si);
+    if (st != TCF_OK && st != TCF_E_NOT_CONVERGED) return st;
+    if (st != TCF_OK) worst = st;
+    acc.cg_iters += si.cg_iters;
+    acc.refine_iters += si.refine_iters;
+    acc.p_relres = std::max(acc.p_relres, si.p_relres);
+    Prof pr(g, FAM_PROJECT);
+    project<R>(Pp, s, as[k], g->p64, F.us, F.vs, F.ws, g->u64, g->v64, g->w64, g->fp32 ? F.u : nullptr,
+               g->fp32 ? F.v : nullptr, g->fp32 ? F.w : nullptr);
+    dt_proj = Pp.dt;
+  }
+  g->t += dt;
+  if (inf) {
+    inf->cg_iters = acc.cg_iters;
+    inf->refine_iters = acc.refine_iters;
+    inf->p_relres = acc.p_relres;
+  }
+  const tcf_status sd = want_diag ? step_diag<R>(g, dt, dt_proj, inf) : TCF_OK;
+  return sd != TCF_OK ? sd : worst;
 }
 
 template <class R>
@@ -1012,8 +1126,11 @@ tcf_status tcf_step(tcf_grid* g, double dt, int nsteps, tcf_step_info* info) {
   tcf_status worst = TCF_OK;
   for (int k = 0; k < nsteps; ++k) {
     const bool last = k == nsteps - 1;
-    tcf_status st = g->fp32 ? step_once<float>(g, dt, last ? info : nullptr, last && info != nullptr)
-                            : step_once<double>(g, dt, last ? info : nullptr, last && info != nullptr);
+    tcf_step_info* inf = last ? info : nullptr;
+    const bool diag = last && info != nullptr;
+    tcf_status st = g->cfg.integrator == 1
+                        ? (g->fp32 ? step_rk3p<float>(g, dt, inf, diag) : step_rk3p<double>(g, dt, inf, diag))
+                        : (g->fp32 ? step_once<float>(g, dt, inf, diag) : step_once<double>(g, dt, inf, diag));
     if (st == TCF_E_NOT_CONVERGED) {
       worst = st;
       continue;

@@ -182,6 +182,11 @@ void adj_scale(hipStream_t s, long n, double f, const double* x, double* y);
 void adj_axpy(hipStream_t s, long n, double f, const double* x, double* y);
 void adj_add_scalar(hipStream_t s, double* dst, const double* src);
 
+// SSP-RK3 stage combination of a face velocity with the FP64 base velocity
+// (stage 1: 3/4 base + 1/4 x; stage 2: base/3 + 2/3 x), in place
+template <class R>
+void rk_combine(hipStream_t s, long n, int stage, const double* base, R* x);
+
 // conversions
 void to_f32(hipStream_t s, long n, const double* x, float* y);
 void to_f64(hipStream_t s, long n, const float* x, double* y);

@@ -465,17 +465,17 @@ __global__ __launch_bounds__(1024) void k_coarse_factor_lds(Level<R> L, R* __res
   __syncthreads();
   for (int e = t; e < n * n; e += nt) A[(e / n) * LD + e % n] += gamma / n;
   __syncthreads();
+  // thread t owns column j = t % 64 of rows t / 64 + 16 r (blockDim = 1024)
+  const int jj = t & (kCoarseLdsMax - 1), i0 = t >> 6;
   for (int p = 0; p < n; ++p) {
     if (t < n) {
       col[t] = A[t * LD + p];
       prow[t] = A[p * LD + t];
     }
     __syncthreads();
-    const double piv = 1.0 / col[p];
-    for (int e = t; e < n * n; e += nt) {
-      const int i = e / n, j = e % n;
-      const double pj = (j == p ? 1.0 : prow[j]) * piv;  // the scaled pivot row
-      A[i * LD + j] = i == p ? pj : (j == p ? 0.0 : A[i * LD + j]) - col[i] * pj;
+    if (jj < n) {
+      const double pj = (jj == p ? 1.0 : prow[jj]) / col[p];  // the scaled pivot row
+      for (int i = i0; i < n; i += 16) A[i * LD + jj] = i == p ? pj : (jj == p ? 0.0 : A[i * LD + jj]) - col[i] * pj;
     }
     __syncthreads();
   }
@@ -848,6 +848,17 @@ __global__ __launch_bounds__(1024) void k_finalize_diag(const double* __restrict
   }
 }
 
+// Shu-Osher SSP-RK3 combination of a face velocity with the step's base
+// velocity (FP64): stage 1 x <- 3/4 base + 1/4 x, stage 2 x <- base/3 + 2/3 x.
+template <class R>
+__global__ __launch_bounds__(256) void k_rk_combine(long n, int stage, const double* __restrict__ base,
+                                                    R* __restrict__ x) {
+  const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  const double b = base[c], v = (double)x[c];
+  x[c] = R(stage == 1 ? 0.75 * b + 0.25 * v : b / 3.0 + 2.0 / 3.0 * v);
+}
+
 __global__ __launch_bounds__(256) void k_to_f32(long n, const double* __restrict__ x, float* __restrict__ y) {
   const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (c < n) y[c] = (float)x[c];
@@ -1117,6 +1128,13 @@ void diagnostics(const KParams& P, hipStream_t s, const R* a, const double* u, c
   else hipLaunchKernelGGL((k_diag<R, 2>), dim3(nb), blk(), 0, s, P, kz, ntx, nty, a, u, v, w, part, stride);
   hipLaunchKernelGGL(k_finalize_diag, dim3(1), dim3(1024), 0, s, part, nb, stride, scal);
 }
+
+template <class R>
+void rk_combine(hipStream_t s, long n, int stage, const double* base, R* x) {
+  hipLaunchKernelGGL((k_rk_combine<R>), dim3(nblk1(n)), dim3(256), 0, s, n, stage, base, x);
+}
+template void rk_combine<double>(hipStream_t, long, int, const double*, double*);
+template void rk_combine<float>(hipStream_t, long, int, const double*, float*);
 
 void to_f32(hipStream_t s, long n, const double* x, float* y) {
   hipLaunchKernelGGL(k_to_f32, dim3(nblk1(n)), dim3(256), 0, s, n, x, y);

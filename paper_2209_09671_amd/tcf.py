@@ -41,7 +41,8 @@ class TcfConfig(C.Structure):
                 ("weno_eps", C.c_double), ("normal_eps", C.c_double),
                 ("p_rtol", C.c_double), ("p_maxit", C.c_int), ("inner_rtol", C.c_double),
                 ("refine_maxit", C.c_int), ("mg_levels", C.c_int), ("mg_nu", C.c_int),
-                ("species", C.c_int), ("dsigma_dc", C.c_double), ("c0", C.c_double)]
+                ("species", C.c_int), ("dsigma_dc", C.c_double), ("c0", C.c_double),
+                ("integrator", C.c_int)]
 
 
 class TcfStepInfo(C.Structure):
@@ -131,6 +132,7 @@ def make_config(c: dict, precision=None, flags=None) -> TcfConfig:
     o.mg_levels, o.mg_nu = c["mg_levels"], c["mg_nu"]
     o.species = int(c.get("species", 0))
     o.dsigma_dc, o.c0 = float(c.get("dsigma_dc", 0.0)), float(c.get("c0", 0.0))
+    o.integrator = int(c.get("integrator", 0))
     return o
 
 

@@ -97,6 +97,19 @@ def test_species_workspace_and_validation():
     assert tcf.workspace_bytes(c, precision=0, flags=tcf.TCF_WITH_ADJOINT) > 0
 
 
+def test_time_accurate_integrator_workspace_and_validation():
+    """Integrator 1 keeps the step's base velocity (three FP64 face arrays);
+    the integrator must be 0/1 and 1 is not combined with the adjoint."""
+    c = I.config(3)
+    nf = 3 * (c["nx"] + 1) * c["ny"] * c["nz"]
+    for prec in (0, 1):
+        extra = tcf.workspace_bytes(dict(c, integrator=1), precision=prec) - tcf.workspace_bytes(c, precision=prec)
+        assert nf * 8 <= extra < nf * 8 + 4096
+    assert tcf.workspace_bytes(dict(c, integrator=2)) == 0
+    assert tcf.workspace_bytes(dict(c, integrator=1), precision=0, flags=tcf.TCF_WITH_ADJOINT) == 0
+    assert tcf.workspace_bytes(dict(c, integrator=0), precision=0, flags=tcf.TCF_WITH_ADJOINT) > 0
+
+
 def test_species_entry_points_reject_null():
     lib = tcf.load()
     assert lib.tcf_set_species(None, None) == tcf.TCF_E_INVALID
