@@ -42,7 +42,10 @@ class OrcConfig(C.Structure):
                 ("mg_omega_c", C.c_double), ("mg_coarse_sweeps", C.c_int),
                 ("sigkap_const", C.c_double),
                 ("species", C.c_int), ("dsigma_dc", C.c_double), ("c0", C.c_double),
-                ("integrator", C.c_int)]
+                ("integrator", C.c_int),
+                ("nphases", C.c_int), ("rho34", C.c_double * 2), ("mu34", C.c_double * 2),
+                ("rhocp34", C.c_double * 2), ("lam34", C.c_double * 2),
+                ("sig0_pair", C.c_double * 6), ("dsig_pair", C.c_double * 6)]
 
 
 class OrcInfo(C.Structure):
@@ -96,6 +99,13 @@ def make_config(c: dict, flags: int = 0, sigkap_const: float = 0.0) -> OrcConfig
     o.species = int(c.get("species", 0))
     o.dsigma_dc, o.c0 = float(c.get("dsigma_dc", 0.0)), float(c.get("c0", 0.0))
     o.integrator = int(c.get("integrator", 0))
+    o.nphases = int(c.get("nphases", 0))
+    for q, ph in enumerate(c.get("phases", [])[:2]):  # phases 3 and 4
+        o.rho34[q], o.mu34[q] = ph["rho"], ph["mu"]
+        o.rhocp34[q], o.lam34[q] = ph["rhocp"], ph["lambda"]
+    for q in range(6):  # pairs (1,2), (1,3), (1,4), (2,3), (2,4), (3,4)
+        o.sig0_pair[q] = float(c.get("pair_sigma0", [0.0] * 6)[q])
+        o.dsig_pair[q] = float(c.get("pair_dsigma_dT", [0.0] * 6)[q])
     return o
 
 
@@ -132,16 +142,20 @@ def transport_rhs(c, t, alpha, T, u, v, w=None, flags=0):
     return La, LT
 
 
-def transport_step(c, t, dt, alpha, T, u, v, w=None, flags=0, cfield=None):
-    """One SSP-RK3 transport step; returns (alpha, T) or, with a species
-    field, (alpha, T, c)."""
+def transport_step(c, t, dt, alpha, T, u, v, w=None, flags=0, cfield=None, alpha3=None, alpha4=None):
+    """One SSP-RK3 transport step; returns (alpha, T), with a species field
+    (alpha, T, c), and for N phases (alpha, T, alpha3[, alpha4])."""
     o = make_config(c, flags)
     a = _f64(alpha).copy()
     TT = _f64(T).copy()
     cc = None if cfield is None else _f64(cfield).copy()
+    a3 = None if alpha3 is None else _f64(alpha3).copy()
+    a4 = None if alpha4 is None else _f64(alpha4).copy()
     u, v, w = map(_f64, (u, v, w))
     lib().orc_transport_step(C.byref(o), C.c_double(t), C.c_double(dt), _p(a), _p(TT), _p(u), _p(v), _p(w),
-                             _p(cc))
+                             _p(cc), _p(a3), _p(a4))
+    if a3 is not None:
+        return (a, TT, a3) if a4 is None else (a, TT, a3, a4)
     return (a, TT) if cc is None else (a, TT, cc)
 
 
@@ -156,14 +170,35 @@ def geometry(c, alpha, T, flags=0, sigkap_const=0.0, cfield=None):
     return dict(n=n, kappa=kap, delta_s=ds, sigkap=sk, M=M)
 
 
-def predictor(c, dt, alpha, T, u, v, w=None, flags=0, sigkap_const=0.0, cfield=None):
+def predictor(c, dt, alpha, T, u, v, w=None, flags=0, sigkap_const=0.0, cfield=None, alpha3=None, alpha4=None):
     o = make_config(c, flags, sigkap_const)
-    alpha, T, u, v, w, cf = map(_f64, (alpha, T, u, v, w, cfield))
+    alpha, T, u, v, w, cf, a3, a4 = map(_f64, (alpha, T, u, v, w, cfield, alpha3, alpha4))
     us, vs = np.empty_like(u), np.empty_like(v)
     ws = np.empty_like(w) if w is not None else None
     lib().orc_predictor(C.byref(o), C.c_double(dt), _p(alpha), _p(T), _p(u), _p(v), _p(w),
-                        _p(us), _p(vs), _p(ws), _p(cf))
+                        _p(us), _p(vs), _p(ws), _p(cf), _p(a3), _p(a4))
     return us, vs, ws
+
+
+def phase_pairs(nph):
+    """Pairs (i, j), i < j, of an N-phase config in the order of the pair tables."""
+    return [p for p in ((1, 2), (1, 3), (1, 4), (2, 3), (2, 4), (3, 4)) if p[1] <= nph]
+
+
+def geometry_n(c, alpha, alpha3, T, alpha4=None):
+    """N-phase geometry: dict of per-pair sigma_ij kappa_ij and delta_ij
+    (keys (i, j)) and the summed Marangoni vector M (N x 3)."""
+    o = make_config(c)
+    alpha, a3, a4, T = map(_f64, (alpha, alpha3, alpha4, T))
+    pairs = phase_pairs(o.nphases)
+    N = alpha.size
+    skp = np.zeros((len(pairs), N))
+    dsp = np.zeros((len(pairs), N))
+    M = np.empty((N, 3))
+    lib().orc_geometry_n(C.byref(o), _p(alpha), _p(a3), _p(a4), _p(T), _p(skp), _p(dsp), _p(M))
+    sh = alpha.shape
+    return dict(sigkap={p: skp[q].reshape(sh) for q, p in enumerate(pairs)},
+                delta={p: dsp[q].reshape(sh) for q, p in enumerate(pairs)}, M=M)
 
 
 def divergence(c, u, v, w=None):
@@ -195,30 +230,33 @@ def mg_levels(c):
     return lib().orc_mg_levels(C.byref(o))
 
 
-def solve_pressure(c, alpha, b, p0=None, rtol=None):
+def solve_pressure(c, alpha, b, p0=None, rtol=None, alpha3=None, alpha4=None):
     cc = dict(c)
     if rtol is not None:
         cc["oracle_rtol"] = rtol
     o = make_config(cc)
-    alpha, b = _f64(alpha), _f64(b)
+    alpha, b, a3, a4 = map(_f64, (alpha, b, alpha3, alpha4))
     p = np.zeros_like(b) if p0 is None else _f64(p0).copy()
     info = OrcInfo()
-    st = lib().orc_solve_pressure(C.byref(o), _p(alpha), _p(b), _p(p), C.byref(info))
+    st = lib().orc_solve_pressure(C.byref(o), _p(alpha), _p(b), _p(p), C.byref(info), _p(a3), _p(a4))
     return p, st, info.as_dict()
 
 
-def project(c, dt, alpha, p, us, vs, ws=None):
+def project(c, dt, alpha, p, us, vs, ws=None, alpha3=None, alpha4=None):
     o = make_config(c)
-    alpha, p, us, vs, ws = map(_f64, (alpha, p, us, vs, ws))
+    alpha, p, us, vs, ws, a3, a4 = map(_f64, (alpha, p, us, vs, ws, alpha3, alpha4))
     u, v = np.empty_like(us), np.empty_like(vs)
     w = np.empty_like(ws) if ws is not None else None
-    lib().orc_project(C.byref(o), C.c_double(dt), _p(alpha), _p(p), _p(us), _p(vs), _p(ws), _p(u), _p(v), _p(w))
+    lib().orc_project(C.byref(o), C.c_double(dt), _p(alpha), _p(p), _p(us), _p(vs), _p(ws), _p(u), _p(v), _p(w),
+                      _p(a3), _p(a4))
     return u, v, w
 
 
 def step(c, state, t, dt, nsteps=1, flags=0, sigkap_const=0.0, rtol=None):
     """Run nsteps full steps; returns (new_state, info dict, status).  A
-    species field travels as state["c"] (used when the config has species)."""
+    species field travels as state["c"] (used when the config has species),
+    the fractions of phases 3 and 4 of an N-phase config as state["alpha3"]
+    and state["alpha4"]."""
     cc = dict(c)
     if rtol is not None:
         cc["oracle_rtol"] = rtol
@@ -227,5 +265,5 @@ def step(c, state, t, dt, nsteps=1, flags=0, sigkap_const=0.0, rtol=None):
     info = OrcInfo()
     st = lib().orc_step(C.byref(o), C.c_double(t), C.c_double(dt), C.c_int(nsteps),
                         _p(s["alpha"]), _p(s["T"]), _p(s["u"]), _p(s["v"]), _p(s["w"]), _p(s["p"]),
-                        C.byref(info), _p(s.get("c")))
+                        C.byref(info), _p(s.get("c")), _p(s.get("alpha3")), _p(s.get("alpha4")))
     return s, info.as_dict(), st

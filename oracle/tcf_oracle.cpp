@@ -52,6 +52,14 @@ struct OrcConfig {
   // forward-Euler predictor and one projection; 1 = SSP-RK3 over the whole
   // state with a projection in every stage
   int integrator;
+  // N-phase VOF (eq. 1 for each phase j; several phases in one domain):
+  // nphases 0 or 2 = the two-phase model above; 3 or 4 add phases 3 and 4
+  // (fractions carried like alpha) with the material values below, and
+  // surface tension per pair of phases, pairs ordered (1,2), (1,3), (1,4),
+  // (2,3), (2,4), (3,4): sigma_ij = sig0_pair + dsig_pair (T - T0)
+  int nphases;
+  double rho34[2], mu34[2], rhocp34[2], lam34[2];
+  double sig0_pair[6], dsig_pair[6];
 };
 
 struct OrcInfo {
@@ -75,9 +83,12 @@ struct Grid {
   double h;
   bool per;
   const double* cf = nullptr;  // species field (read by the geometry when c.species)
+  int nph;                                  // number of phases (2: the two-phase model)
+  const double* ph3 = nullptr;              // fractions of phases 3 and 4 (N-phase model)
+  const double* ph4 = nullptr;
   explicit Grid(const OrcConfig& cc)
       : c(cc), nx(cc.nx), ny(cc.ny), nz(cc.dim == 2 ? 1 : cc.nz), dim(cc.dim), h(cc.h),
-        per((cc.flags & F_PERIODIC) != 0) {}
+        per((cc.flags & F_PERIODIC) != 0), nph(cc.nphases > 2 ? cc.nphases : 2) {}
   long N() const { return (long)nx * ny * nz; }
   long Nu() const { return (long)(nx + 1) * ny * nz; }
   long Nv() const { return (long)nx * (ny + 1) * nz; }
@@ -159,6 +170,46 @@ double Ucomp(const Grid& g, const double* u, int d, int i, int j, int k) {
 // reading: linear mixing in the clamped volume fraction.
 inline double clamp01(double a) { return a < 0.0 ? 0.0 : (a > 1.0 ? 1.0 : a); }
 inline double mix(double a, double p1, double p2) { return p1 + clamp01(a) * (p2 - p1); }
+
+// N-phase model (reading: eq. 1 holds for every phase; the paper gives no
+// mixture laws or pairwise surface tension for several phases).  Phase 1 is
+// the background, alpha_1 = 1 - sum_{j>=2} alpha_j; phase 2 is alpha, phases
+// 3 and 4 are carried like it.  A material law stays linear in each clamped
+// fraction relative to phase 1, P = P_1 + sum_{j>=2} clamp(alpha_j) (P_j -
+// P_1), which is mix() for two phases.
+enum MatKind { MAT_RHO = 0, MAT_MU, MAT_RHOCP, MAT_LAM };
+double A(const Grid& g, const double* a, int i, int j, int k);
+double matp(const Grid& g, const double* a, int i, int j, int k, int which) {
+  const OrcConfig& c = g.c;
+  const double p1[4] = {c.rho1, c.mu1, c.rhocp1, c.lam1}, p2[4] = {c.rho2, c.mu2, c.rhocp2, c.lam2};
+  const double* p34[4] = {c.rho34, c.mu34, c.rhocp34, c.lam34};
+  double v = p1[which] + clamp01(A(g, a, i, j, k)) * (p2[which] - p1[which]);
+  v += clamp01(A(g, g.ph3, i, j, k)) * (p34[which][0] - p1[which]);
+  if (g.nph == 4) v += clamp01(A(g, g.ph4, i, j, k)) * (p34[which][1] - p1[which]);
+  return v;
+}
+// fraction of phase q (1..4) at a cell, ghosts by even reflection
+double phase(const Grid& g, const double* a, int q, int i, int j, int k) {
+  if (q == 2) return A(g, a, i, j, k);
+  if (q == 3) return A(g, g.ph3, i, j, k);
+  if (q == 4) return A(g, g.ph4, i, j, k);
+  double s = A(g, a, i, j, k) + A(g, g.ph3, i, j, k);
+  if (g.nph == 4) s += A(g, g.ph4, i, j, k);
+  return 1.0 - s;
+}
+// pairs (i, j), i < j, of an N-phase grid and their slots in the pair tables
+int phase_pairs(int nph, int pi[6], int pj[6], int slot[6]) {
+  const int I[6] = {1, 1, 1, 2, 2, 3}, J[6] = {2, 3, 4, 3, 4, 4};
+  int n = 0;
+  for (int q = 0; q < 6; ++q)
+    if (J[q] <= nph) {
+      pi[n] = I[q];
+      pj[n] = J[q];
+      slot[n] = q;
+      ++n;
+    }
+  return n;
+}
 
 // ---------------------------------------------------------------------------
 // WENO5-JS (Jiang & Shu 1996): value at the right edge of cell c from cell
@@ -282,23 +333,34 @@ void transport_rhs(const Grid& g, double t, const double* a, const double* T, co
         // conduction: sum over the cell's faces of lambda_f (T_nb - T_c) / h^2,
         // lambda_f the arithmetic mean of the two cells' conductivities.
         double Tc = T[ci];
-        double lc = mix(a[ci], c.lam1, c.lam2);
+        const bool np = g.nph > 2;
+        double lc = np ? matp(g, a, i, j, k, MAT_LAM) : mix(a[ci], c.lam1, c.lam2);
         double cond = 0.0;
         const int off[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
         for (int d = 0; d < g.dim; ++d)
           for (int sgn = -1; sgn <= 1; sgn += 2) {
             int ii = i + sgn * off[d][0], jj = j + sgn * off[d][1], kk = k + sgn * off[d][2];
-            double lf = 0.5 * (lc + mix(A(g, a, ii, jj, kk), c.lam1, c.lam2));
+            double lf = 0.5 * (lc + (np ? matp(g, a, ii, jj, kk, MAT_LAM) : mix(A(g, a, ii, jj, kk), c.lam1, c.lam2)));
             cond += lf * (Tg(g, T, ii, jj, kk) - Tc);
           }
         cond /= h * h;
         double src = 0.0;
         if (c.q_power != 0.0) {
           double gr[3];
-          grad_alpha(g, a, i, j, k, gr);
+          if (np) {
+            // N phases: the flux heats the boundary of the condensed phases,
+            // the gradient of alpha_c = 1 - alpha_1 (alpha for two phases)
+            auto ac = [&](int ii, int jj, int kk) { return 1.0 - phase(g, a, 1, ii, jj, kk); };
+            const double ih2 = 1.0 / (2.0 * g.h);
+            gr[0] = (ac(i + 1, j, k) - ac(i - 1, j, k)) * ih2;
+            gr[1] = (ac(i, j + 1, k) - ac(i, j - 1, k)) * ih2;
+            gr[2] = g.dim == 3 ? (ac(i, j, k + 1) - ac(i, j, k - 1)) * ih2 : 0.0;
+          } else {
+            grad_alpha(g, a, i, j, k, gr);
+          }
           src = heat_flux(c, (i + 0.5) * h, (j + 0.5) * h, t) * delta_s_of(gr, c.normal_eps);
         }
-        LT[ci] = -divt / h + (cond + src) / mix(a[ci], c.rhocp1, c.rhocp2);
+        LT[ci] = -divt / h + (cond + src) / (np ? matp(g, a, i, j, k, MAT_RHOCP) : mix(a[ci], c.rhocp1, c.rhocp2));
       }
 }
 
@@ -341,6 +403,42 @@ void advect_rhs(const Grid& g, const double* q, const double* u, const double* v
 // S1: SSP-RK3 (Shu-Osher) for alpha and T (and the species c, when given)
 // with the face velocity frozen.
 // reading: the paper does not state its time integrator.
+// Shu-Osher SSP-RK3 combination of stage s (0, 1, 2) from the base value q^n
+// and the forward-Euler update x = q^(s) + dt L(q^(s)), written exactly as
+// the two-phase stages below so that the variants agree where they must.
+inline double rk_stage(int s, double base, double x) {
+  return s == 0 ? x : (s == 1 ? 0.75 * base + 0.25 * x : base / 3.0 + 2.0 / 3.0 * x);
+}
+
+// N-phase transport: the same three stages for alpha, T and the fractions of
+// phases 3 (and 4); each stage's T right-hand side takes its materials from
+// that stage's fractions.
+void transport_rk3_nphase(const Grid& g, double t, double dt, std::vector<double>& a, std::vector<double>& T,
+                          std::vector<double>& p3, std::vector<double>* p4, const double* u, const double* v,
+                          const double* w) {
+  const long N = g.N();
+  const std::vector<double> an(a), Tn(T), p3n(p3), p4n = p4 ? *p4 : std::vector<double>();
+  std::vector<double> as(a), Ts(T), q3(p3), q4 = p4n, La(N), LT(N), L3(N), L4(p4 ? N : 0);
+  Grid gs = g;
+  for (int s = 0; s < 3; ++s) {
+    gs.ph3 = q3.data();
+    gs.ph4 = p4 ? q4.data() : nullptr;
+    transport_rhs(gs, t, as.data(), Ts.data(), u, v, w, La.data(), LT.data());
+    advect_rhs(g, q3.data(), u, v, w, L3.data());
+    if (p4) advect_rhs(g, q4.data(), u, v, w, L4.data());
+    for (long q = 0; q < N; ++q) {
+      as[q] = rk_stage(s, an[q], as[q] + dt * La[q]);
+      Ts[q] = rk_stage(s, Tn[q], Ts[q] + dt * LT[q]);
+      q3[q] = rk_stage(s, p3n[q], q3[q] + dt * L3[q]);
+      if (p4) q4[q] = rk_stage(s, p4n[q], q4[q] + dt * L4[q]);
+    }
+  }
+  a = as;
+  T = Ts;
+  p3 = q3;
+  if (p4) *p4 = q4;
+}
+
 void transport_rk3(const Grid& g, double t, double dt, std::vector<double>& a, std::vector<double>& T,
                    const double* u, const double* v, const double* w, std::vector<double>* cs = nullptr) {
   long N = g.N();
@@ -436,6 +534,97 @@ void geometry(const Grid& g, const double* a, const double* T, double* nout, dou
       }
 }
 
+// N-phase interface geometry (reading; eqs. 4-7 applied to each pair of
+// phases).  For a pair i < j the pair gradient g_ij = alpha_i grad alpha_j -
+// alpha_j grad alpha_i points into phase j (for two phases g_12 = grad
+// alpha); n_ij = g_ij / |g_ij|_eps, delta_ij and kappa_ij = -div n_ij as in
+// geometry(); sigma_ij = sig0_pair + dsig_pair (T - T0) and M_ij = delta_ij
+// (grad sigma_ij - n_ij (n_ij . grad sigma_ij)).  Outputs per pair p (in the
+// order of phase_pairs): sigma_ij kappa_ij (skp[p N + c]) and delta_ij
+// (dsp[p N + c]), and the Marangoni vector summed over the pairs (M, 3N).
+void geometry_n(const Grid& g, const double* a, const double* T, double* skp, double* dsp, double* M) {
+  const OrcConfig& c = g.c;
+  const int nx = g.nx, ny = g.ny, nz = g.nz;
+  const long N = g.N();
+  const int ex = nx + 2, ey = ny + 2, ez = g.dim == 3 ? nz + 2 : 1;
+  const int oz = g.dim == 3 ? 1 : 0;
+  const double ih2 = 1.0 / (2.0 * g.h);
+  int pi[6], pj[6], slot[6];
+  const int np = phase_pairs(g.nph, pi, pj, slot);
+  auto eidx = [&](int i, int j, int k) { return (long)(i + 1) + (long)ex * ((j + 1) + (long)ey * (k + oz)); };
+  for (long q = 0; q < 3 * N; ++q) M[q] = 0.0;
+  std::vector<double> nn(3L * ex * ey * ez);
+  for (int p = 0; p < np; ++p) {
+    const int I = pi[p], J = pj[p];
+    auto pg = [&](int i, int j, int k, double gr[3]) {  // g_IJ at a cell of the ghost ring or inside
+      const double ai = phase(g, a, I, i, j, k), aj = phase(g, a, J, i, j, k);
+      auto d = [&](int q, int di, int dj, int dk) {
+        return (phase(g, a, q, i + di, j + dj, k + dk) - phase(g, a, q, i - di, j - dj, k - dk)) * ih2;
+      };
+      gr[0] = ai * d(J, 1, 0, 0) - aj * d(I, 1, 0, 0);
+      gr[1] = ai * d(J, 0, 1, 0) - aj * d(I, 0, 1, 0);
+      gr[2] = g.dim == 3 ? ai * d(J, 0, 0, 1) - aj * d(I, 0, 0, 1) : 0.0;
+    };
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int k = -oz; k < nz + oz; ++k)
+      for (int j = -1; j < ny + 1; ++j)
+        for (int i = -1; i < nx + 1; ++i) {
+          double gr[3];
+          pg(i, j, k, gr);
+          double ge = std::sqrt(gr[0] * gr[0] + gr[1] * gr[1] + gr[2] * gr[2] + c.normal_eps * c.normal_eps);
+          long e = eidx(i, j, k);
+          for (int d = 0; d < 3; ++d) nn[3 * e + d] = gr[d] / ge;
+        }
+    const double s0 = c.sig0_pair[slot[p]], sT = c.dsig_pair[slot[p]];
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int k = 0; k < nz; ++k)
+      for (int j = 0; j < ny; ++j)
+        for (int i = 0; i < nx; ++i) {
+          long ci = g.cell(i, j, k);
+          double divn = (nn[3 * eidx(i + 1, j, k) + 0] - nn[3 * eidx(i - 1, j, k) + 0]) * ih2 +
+                        (nn[3 * eidx(i, j + 1, k) + 1] - nn[3 * eidx(i, j - 1, k) + 1]) * ih2;
+          if (g.dim == 3) divn += (nn[3 * eidx(i, j, k + 1) + 2] - nn[3 * eidx(i, j, k - 1) + 2]) * ih2;
+          double gr[3];
+          pg(i, j, k, gr);
+          double dls = delta_s_of(gr, c.normal_eps);
+          double sigma = s0 + sT * (T[ci] - c.T0);
+          double gs[3];
+          gs[0] = sT * (Tg(g, T, i + 1, j, k) - Tg(g, T, i - 1, j, k)) * ih2;
+          gs[1] = sT * (Tg(g, T, i, j + 1, k) - Tg(g, T, i, j - 1, k)) * ih2;
+          gs[2] = g.dim == 3 ? sT * (Tg(g, T, i, j, k + 1) - Tg(g, T, i, j, k - 1)) * ih2 : 0.0;
+          const double* n = &nn[3 * eidx(i, j, k)];
+          double ndg = n[0] * gs[0] + n[1] * gs[1] + n[2] * gs[2];
+          for (int d = 0; d < 3; ++d) M[3 * ci + d] += dls * (gs[d] - n[d] * ndg);
+          skp[p * N + ci] = sigma * -divn;
+          if (dsp) dsp[p * N + ci] = dls;
+        }
+  }
+}
+
+// N-phase face force along d between cells L and R (reading): the pair
+// forces sigma_ij kappa_ij g_ij with the face form of the pair gradient,
+// G_ij = avg(alpha_i) (alpha_j,R - alpha_j,L)/h - avg(alpha_j) (alpha_i,R -
+// alpha_i,L)/h (which is (alpha_R - alpha_L)/h for two phases, the
+// balanced-force face gradient), plus the face average of the Marangoni
+// vector.
+double face_force_n(const Grid& g, const double* a, const double* skp, const double* M, int d, int i, int j,
+                    int k) {
+  int L[3] = {i, j, k};
+  L[d] -= 1;
+  const long cL = g.cell(L[0], L[1], L[2]), cR = g.cell(i, j, k);
+  const long N = g.N();
+  int pi[6], pj[6], slot[6];
+  const int np = phase_pairs(g.nph, pi, pj, slot);
+  double f = 0.5 * (M[3 * cL + d] + M[3 * cR + d]);
+  for (int p = 0; p < np; ++p) {
+    const double iL = phase(g, a, pi[p], L[0], L[1], L[2]), iR = phase(g, a, pi[p], i, j, k);
+    const double jL = phase(g, a, pj[p], L[0], L[1], L[2]), jR = phase(g, a, pj[p], i, j, k);
+    const double G = (0.5 * (iL + iR) * (jR - jL) - 0.5 * (jL + jR) * (iR - iL)) / g.h;
+    f += 0.5 * (skp[p * N + cL] + skp[p * N + cR]) * G;
+  }
+  return f;
+}
+
 // ---------------------------------------------------------------------------
 // S4-S5: momentum predictor on interior faces.
 //   u* = u + dt [ -C(u) + (V(u) + f_st) / rho_f ]
@@ -451,12 +640,22 @@ void predictor(const Grid& g, double dt, const double* a, const double* T, const
   const int nx = g.nx, ny = g.ny, nz = g.nz, dim = g.dim;
   const double h = g.h, eps = c.weno_eps;
   long N = g.N();
-  std::vector<double> kap(N), ds(N), sk(N), M(3 * N);
-  geometry(g, a, T, nullptr, kap.data(), ds.data(), sk.data(), M.data());
+  const bool nphase = g.nph > 2;
+  std::vector<double> kap(N), ds(N), sk(N), M(3 * N), skp;
+  if (nphase) {
+    skp.assign(6 * N, 0.0);
+    geometry_n(g, a, T, skp.data(), nullptr, M.data());
+  } else {
+    geometry(g, a, T, nullptr, kap.data(), ds.data(), sk.data(), M.data());
+  }
   const double* vel[3] = {u, v, w};
   double* out[3] = {us, vs, ws};
-  auto mu = [&](int i, int j, int k) { return mix(A(g, a, i, j, k), c.mu1, c.mu2); };
-  auto rho = [&](int i, int j, int k) { return mix(a[g.cell(i, j, k)], c.rho1, c.rho2); };
+  auto mu = [&](int i, int j, int k) {
+    return nphase ? matp(g, a, i, j, k, MAT_MU) : mix(A(g, a, i, j, k), c.mu1, c.mu2);
+  };
+  auto rho = [&](int i, int j, int k) {
+    return nphase ? matp(g, a, i, j, k, MAT_RHO) : mix(a[g.cell(i, j, k)], c.rho1, c.rho2);
+  };
   for (int d = 0; d < dim; ++d) {
     int fnx = nx + (d == 0), fny = ny + (d == 1), fnz = nz + (d == 2);
 #pragma omp parallel for collapse(2) schedule(static)
@@ -543,7 +742,8 @@ void predictor(const Grid& g, double dt, const double* a, const double* T, const
               visc += (Thi - Tlo) / h;
             }
           }
-          double fst = 0.5 * (sk[cL] + sk[cR]) * (a[cR] - a[cL]) / h + 0.5 * (M[3 * cL + d] + M[3 * cR + d]);
+          double fst = nphase ? face_force_n(g, a, skp.data(), M.data(), d, i, j, k)
+                              : 0.5 * (sk[cL] + sk[cR]) * (a[cR] - a[cL]) / h + 0.5 * (M[3 * cL + d] + M[3 * cR + d]);
           double rhof = 0.5 * (rho(L[0], L[1], L[2]) + rho(i, j, k));
           out[d][fi] = vel[d][fi] + dt * (-conv + (visc + fst) / rhof);
         }
@@ -653,11 +853,13 @@ Level finest_level(const Grid& g, const double* a) {
   for (int k = 0; k < g.nz; ++k)
     for (int j = 0; j < g.ny; ++j)
       for (int i = 0; i < g.nx; ++i) {
-        double rc = mix(a[g.cell(i, j, k)], c.rho1, c.rho2);
-        if (i > 0) L.ax[g.fx(i, j, k)] = ih2 / (0.5 * (mix(a[g.cell(i - 1, j, k)], c.rho1, c.rho2) + rc));
-        if (j > 0) L.ay[g.fy(i, j, k)] = ih2 / (0.5 * (mix(a[g.cell(i, j - 1, k)], c.rho1, c.rho2) + rc));
-        if (g.dim == 3 && k > 0)
-          L.az[g.fz(i, j, k)] = ih2 / (0.5 * (mix(a[g.cell(i, j, k - 1)], c.rho1, c.rho2) + rc));
+        auto rho = [&](int ii, int jj, int kk) {
+          return g.nph > 2 ? matp(g, a, ii, jj, kk, MAT_RHO) : mix(a[g.cell(ii, jj, kk)], c.rho1, c.rho2);
+        };
+        double rc = rho(i, j, k);
+        if (i > 0) L.ax[g.fx(i, j, k)] = ih2 / (0.5 * (rho(i - 1, j, k) + rc));
+        if (j > 0) L.ay[g.fy(i, j, k)] = ih2 / (0.5 * (rho(i, j - 1, k) + rc));
+        if (g.dim == 3 && k > 0) L.az[g.fz(i, j, k)] = ih2 / (0.5 * (rho(i, j, k - 1) + rc));
       }
   make_diag(L);
   return L;
@@ -829,17 +1031,11 @@ void project(const Grid& g, double dt, const double* a, const double* p, const d
           int L[3] = {i, j, k};
           L[d] -= 1;
           long cL = g.cell(L[0], L[1], L[2]), cR = g.cell(i, j, k);
-          double rhof = 0.5 * (mix(a[cL], c.rho1, c.rho2) + mix(a[cR], c.rho1, c.rho2));
+          double rhof = g.nph > 2 ? 0.5 * (matp(g, a, L[0], L[1], L[2], MAT_RHO) + matp(g, a, i, j, k, MAT_RHO))
+                                  : 0.5 * (mix(a[cL], c.rho1, c.rho2) + mix(a[cR], c.rho1, c.rho2));
           dst[d][fi] = src[d][fi] - dt * (1.0 / rhof) * (p[cR] - p[cL]) / g.h;
         }
   }
-}
-
-// Shu-Osher SSP-RK3 combination of stage s (0, 1, 2) from the base value q^n
-// and the forward-Euler update x = q^(s) + dt L(q^(s)), written exactly as in
-// transport_rk3 so that the two integrators agree where they must.
-inline double rk_stage(int s, double base, double x) {
-  return s == 0 ? x : (s == 1 ? 0.75 * base + 0.25 * x : base / 3.0 + 2.0 / 3.0 * x);
 }
 
 // One step of the per-stage projected SSP-RK3 (integrator 1).
@@ -936,11 +1132,26 @@ void orc_geometry(const OrcConfig* c, const double* a, const double* T, double* 
   geometry(g, a, T, n, kap, ds, sk, M);
 }
 
+// a3, a4: fractions of phases 3 and 4 (N-phase configs; NULL otherwise)
 void orc_predictor(const OrcConfig* c, double dt, const double* a, const double* T, const double* u,
-                   const double* v, const double* w, double* us, double* vs, double* ws, const double* cf) {
+                   const double* v, const double* w, double* us, double* vs, double* ws, const double* cf,
+                   const double* a3, const double* a4) {
   Grid g(*c);
   g.cf = cf;
+  g.ph3 = a3;
+  g.ph4 = a4;
   predictor(g, dt, a, T, u, v, w, us, vs, ws);
+}
+
+// N-phase geometry: per pair sigma_ij kappa_ij and delta_ij (npairs x N, in
+// the order (1,2), (1,3), (1,4), (2,3), (2,4), (3,4) restricted to the
+// phases present) and the summed Marangoni vector (3N).
+void orc_geometry_n(const OrcConfig* c, const double* a, const double* a3, const double* a4, const double* T,
+                    double* skp, double* dsp, double* M) {
+  Grid g(*c);
+  g.ph3 = a3;
+  g.ph4 = a4;
+  geometry_n(g, a, T, skp, dsp, M);
 }
 
 void orc_divergence(const OrcConfig* c, const double* u, const double* v, const double* w, double* out) {
@@ -971,20 +1182,37 @@ int orc_mg_levels(const OrcConfig* c) {
   return (int)hierarchy(g, a.data()).size();
 }
 
-int orc_solve_pressure(const OrcConfig* c, const double* a, const double* b, double* p, OrcInfo* info) {
+int orc_solve_pressure(const OrcConfig* c, const double* a, const double* b, double* p, OrcInfo* info,
+                       const double* a3, const double* a4) {
   Grid g(*c);
+  g.ph3 = a3;
+  g.ph4 = a4;
   return solve_pressure(g, a, b, p, info);
 }
 
 void orc_project(const OrcConfig* c, double dt, const double* a, const double* p, const double* us,
-                 const double* vs, const double* ws, double* u, double* v, double* w) {
+                 const double* vs, const double* ws, double* u, double* v, double* w, const double* a3,
+                 const double* a4) {
   Grid g(*c);
+  g.ph3 = a3;
+  g.ph4 = a4;
   project(g, dt, a, p, us, vs, ws, u, v, w);
 }
 
 void orc_transport_step(const OrcConfig* c, double t, double dt, double* a, double* T, const double* u,
-                        const double* v, const double* w, double* cf) {
+                        const double* v, const double* w, double* cf, double* a3, double* a4) {
   Grid g(*c);
+  if (g.nph > 2) {  // N phases: alpha, T and the fractions of phases 3 (and 4)
+    const long N = g.N();
+    std::vector<double> av(a, a + N), tv(T, T + N), p3(a3, a3 + N), p4;
+    if (g.nph == 4) p4.assign(a4, a4 + N);
+    transport_rk3_nphase(g, t, dt, av, tv, p3, g.nph == 4 ? &p4 : nullptr, u, v, w);
+    std::memcpy(a, av.data(), sizeof(double) * N);
+    std::memcpy(T, tv.data(), sizeof(double) * N);
+    std::memcpy(a3, p3.data(), sizeof(double) * N);
+    if (g.nph == 4) std::memcpy(a4, p4.data(), sizeof(double) * N);
+    return;
+  }
   std::vector<double> av(a, a + g.N()), tv(T, T + g.N());
   std::vector<double> cv;
   if (cf) cv.assign(cf, cf + g.N());
@@ -996,14 +1224,24 @@ void orc_transport_step(const OrcConfig* c, double t, double dt, double* a, doub
 
 // nsteps full steps S1..S8, state updated in place; t advances by dt per step.
 // cf: species field (NULL without one), advanced in place with the state.
+// a3, a4: fractions of phases 3 and 4 of an N-phase config (advanced in
+// place; NULL otherwise).  Returns 5 for a combination the oracle does not
+// define (N phases with a species or with integrator 1, missing fractions).
 int orc_step(const OrcConfig* c, double t0, double dt, int nsteps, double* a, double* T, double* u,
-             double* v, double* w, double* p, OrcInfo* info, double* cf) {
+             double* v, double* w, double* p, OrcInfo* info, double* cf, double* a3, double* a4) {
   Grid g(*c);
   long N = g.N();
+  if (g.nph > 2 && (!a3 || (g.nph == 4 && !a4) || c->species || c->integrator == 1 || g.nph > 4)) return 5;
   std::vector<double> av(a, a + N), tv(T, T + N);
-  std::vector<double> cv;
+  std::vector<double> cv, p3, p4;
   if (cf) cv.assign(cf, cf + N);
   g.cf = cf ? cv.data() : nullptr;
+  if (g.nph > 2) {
+    p3.assign(a3, a3 + N);
+    if (g.nph == 4) p4.assign(a4, a4 + N);
+    g.ph3 = p3.data();
+    g.ph4 = g.nph == 4 ? p4.data() : nullptr;
+  }
   std::vector<double> us(g.Nu()), vs(g.Nv()), ws(g.Nw() ? g.Nw() : 1), b(N), dv(N);
   int status = 0;
   OrcInfo inf{};
@@ -1012,6 +1250,10 @@ int orc_step(const OrcConfig* c, double t0, double dt, int nsteps, double* a, do
     if (c->integrator == 1) {
       const int st = step_rk3p(g, t, dt, av, tv, cf ? &cv : nullptr, u, v, w, p, inf);
       if (st) status = st;
+    } else if (g.nph > 2) {
+      transport_rk3_nphase(g, t, dt, av, tv, p3, g.nph == 4 ? &p4 : nullptr, u, v, w);
+      g.ph3 = p3.data();
+      g.ph4 = g.nph == 4 ? p4.data() : nullptr;
     } else {
       transport_rk3(g, t, dt, av, tv, u, v, w, cf ? &cv : nullptr);
     }
@@ -1034,6 +1276,8 @@ int orc_step(const OrcConfig* c, double t0, double dt, int nsteps, double* a, do
   std::memcpy(a, av.data(), sizeof(double) * N);
   std::memcpy(T, tv.data(), sizeof(double) * N);
   if (cf) std::memcpy(cf, cv.data(), sizeof(double) * N);
+  if (g.nph > 2) std::memcpy(a3, p3.data(), sizeof(double) * N);
+  if (g.nph == 4) std::memcpy(a4, p4.data(), sizeof(double) * N);
   inf.sum_alpha = sum(a, N);
   inf.alpha_min = *std::min_element(a, a + N);
   inf.alpha_max = *std::max_element(a, a + N);

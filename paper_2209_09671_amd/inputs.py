@@ -244,6 +244,101 @@ def species_field(c) -> np.ndarray:
     return np.ascontiguousarray(np.broadcast_to(f, s["cell"]).reshape(s["cell"]), dtype=np.float64)
 
 
+# ----------------------------------------------------------------------------
+# N-phase VOF (eq. 1 for every phase; phase 1 is the background with
+# alpha_1 = 1 - sum of the others)
+PAIRS = ((1, 2), (1, 3), (1, 4), (2, 3), (2, 4), (3, 4))
+
+
+def with_phases(c, layout, phases, pair_sigma0, pair_dsigma_dT) -> dict:
+    """N-phase config: ``phases`` lists the material values of phases 3 (and
+    4) as dicts with rho, mu, rhocp, lambda; ``pair_sigma0`` and
+    ``pair_dsigma_dT`` map a pair (i, j) of phases to sigma_ij = sigma0 +
+    dsigma_dT (T - T0) (missing pairs carry no tension).  ``layout`` names
+    the initial fractions built by phase_fields."""
+    out = dict(c)
+    out.update(nphases=2 + len(phases), phases=[dict(p) for p in phases], phase_layout=layout,
+               pair_sigma0=[float(pair_sigma0.get(p, 0.0)) for p in PAIRS],
+               pair_dsigma_dT=[float(pair_dsigma_dT.get(p, 0.0)) for p in PAIRS])
+    return out
+
+
+def droplet_phases(c, layout):
+    """The 2D droplet sheet with a third phase (denser, more viscous) and
+    distinct surface tensions for the three pairs."""
+    ph3 = dict(rho=3.0, mu=0.03, rhocp=2.0, **{"lambda": 1.5e-3})
+    return with_phases(c, layout, [ph3], {(1, 2): 1.0, (1, 3): 0.8, (2, 3): 0.5},
+                       {(1, 2): -0.1, (1, 3): -0.05, (2, 3): -0.02})
+
+
+def meltpool_phases(c):
+    """The melt-pool sheet with three phases: gas (1), liquid metal (2) in a
+    pool under the beam's start, and solid metal (3) around and below it.
+    Without a phase-change model the solid is a fluid 1000 times more viscous
+    than the melt with a higher conductivity; gas-liquid keeps the thermal
+    Marangoni law, gas-solid a constant tension, liquid-solid none."""
+    ph3 = dict(rho=c["rho2"], mu=1000.0 * c["mu2"], rhocp=c["rhocp2"], **{"lambda": 20.0})
+    return with_phases(c, "meltpool3", [ph3], {(1, 2): c["sigma0"], (1, 3): c["sigma0"]},
+                       {(1, 2): c["dsigma_dT"]})
+
+
+def phase_fields(c) -> dict:
+    """Initial fractions of an N-phase config: dict(alpha=alpha_2,
+    alpha3=..., [alpha4=...]) as float64 cell arrays (tanh edges of length
+    1.5 h).  Layouts: absent (phase 2 as in initial_state, phase 3 zero),
+    two_drops (2D: drops of phases 2 and 3 of radius 0.1 L at 0.25 L and
+    0.75 L), layers (phase 3 below
+    0.3 L, phase 2 up to 0.6 L, background above, along the vertical), lens
+    (2D: a phase-3 drop on a phase-2 layer), meltpool3 (the melt-pool surface
+    with a liquid half-ellipsoid under the beam's start, solid elsewhere)."""
+    s = shapes(c)
+    h = c["h"]
+    w = 1.5 * h
+    x, y, z = cell_centres(c)
+    if c["dim"] == 2:
+        Y, X = np.meshgrid(y, x, indexing="ij")
+        X, Y, Z = X[None], Y[None], None
+    else:
+        Z, Y, X = np.meshgrid(z, y, x, indexing="ij")
+    vert = Y if c["dim"] == 2 else Z
+    lv = (c["ny"] if c["dim"] == 2 else c["nz"]) * h
+    lay = c["phase_layout"]
+    if lay == "absent":
+        a2 = initial_state(c)["alpha"]
+        a3 = np.zeros_like(a2)
+    elif lay == "two_drops":
+        lx, ly = c["nx"] * h, c["ny"] * h
+        r2 = np.hypot(X - 0.25 * lx, Y - 0.5 * ly)
+        r3 = np.hypot(X - 0.75 * lx, Y - 0.5 * ly)
+        a2 = _smooth_step(0.1 * lx - r2, w)
+        a3 = _smooth_step(0.1 * lx - r3, w)
+    elif lay == "layers":
+        a3 = _smooth_step(0.3 * lv - vert, w)
+        a2 = _smooth_step(0.6 * lv - vert, w) - a3
+    elif lay == "lens":
+        a3 = _smooth_step(0.15 - np.hypot(X - 0.5, Y - 0.45), w)
+        a2 = _smooth_step(0.45 - Y, w) * (1.0 - a3)
+    elif lay == "meltpool3":
+        ac = initial_state(c)["alpha"]
+        lx, ly, lz = c["nx"] * h, c["ny"] * h, c["nz"] * h
+        e = np.sqrt(((X - c["q_x0"]) / (0.25 * lx)) ** 2 + ((Y - c["q_y0"]) / (0.25 * ly)) ** 2
+                    + ((Z - 0.5 * lz) / (0.2 * lz)) ** 2)
+        pool = _smooth_step(0.25 * lx * (1.0 - e), w)
+        a2 = ac * pool
+        a3 = ac * (1.0 - pool)
+    else:
+        raise ValueError(f"unknown phase layout {lay}")
+    f = lambda q: np.ascontiguousarray(np.broadcast_to(q, s["cell"]).reshape(s["cell"]), dtype=np.float64)
+    return dict(alpha=f(a2), alpha3=f(a3))
+
+
+def phase_state(c) -> dict:
+    """initial_state(c) with the fractions of phase_fields(c)."""
+    st = initial_state(c)
+    st.update(phase_fields(c))
+    return st
+
+
 def stream_velocity(c, amp=1.0):
     """Discretely divergence-free MAC velocity from face differences of the
     corner stream function psi = L sin^2(pi x/Lx) sin^2(pi y/Ly)/pi (L = Ly,
