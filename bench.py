@@ -11,7 +11,7 @@ the same accuracy is reported beside it.
 
 Prints ONE JSON line.  Options: --steps K --warmup W --gpus 1 --workload i
 --kernel FAMILY (kernel family for the roofline entry) --no-cpu --no-fp64
---no-adjoint --no-species --no-rk3p.
+--no-adjoint --no-species --no-rk3p --no-nphase.
 """
 from __future__ import annotations
 
@@ -183,6 +183,7 @@ def main():
     ap.add_argument("--adjoint-steps", type=int, default=10)
     ap.add_argument("--no-species", action="store_true")
     ap.add_argument("--no-rk3p", action="store_true")
+    ap.add_argument("--no-nphase", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this path runs on one GPU; multi-GPU runs are not part of this build "
@@ -248,6 +249,16 @@ def main():
                 "refine_iters_per_step": round(rr["refs"], 2), "max_div_rel": rr["div"],
                 "max_p_relres": rr["relres"], "integrator": "SSP-RK3, projection in every stage"}
 
+    nphase = None
+    if not args.no_nphase:
+        # N-phase VOF: gas, a liquid pool and solid metal (three phases,
+        # per-pair surface tension) on the same grid and beam
+        cn = I.meltpool_phases(c)
+        rn = run_gpu(cn, I.phase_state(cn), 1, args.steps, args.warmup)
+        nphase = {"value": round(N * args.steps / (rn["ev_ms"] / 1e3) / 1e6, 3), "unit": "Mcell-steps/s",
+                  "ms_per_step": round(rn["ev_ms"] / args.steps, 4), "cg_iters_per_step": round(rn["iters"], 2),
+                  "max_div_rel": rn["div"], "phases": "gas, liquid metal, solid metal"}
+
     adj = None
     if not args.no_adjoint:
         ca = dict(c, precision=0)
@@ -280,6 +291,7 @@ def main():
         "adjoint": adj,
         "solutal_species": species,
         "time_accurate_rk3": rk3p,
+        "nphase_3": nphase,
         "roofline": roof,
         "cpu_baseline": cpu,
     }

@@ -117,6 +117,23 @@ typedef struct tcf_config {
    * pressure solves per step, third order in time).  The paper does not
    * state its integrator.  1 is not combined with TCF_WITH_ADJOINT. */
   int integrator;
+  /* N-phase VOF (eq. 1 for every phase of several in one domain).  0 or 2:
+   * the two-phase model (alpha = phase 2, phase 1 the rest).  3 or 4: the
+   * fractions of phases 3 and 4 (set with tcf_set_phases) are carried by
+   * the same WENO5 / SSP-RK3 transport as alpha; phase 1 is the background
+   * with alpha_1 = 1 - the others.  Material laws are linear in each clamped
+   * fraction relative to phase 1 (P = P_1 + sum_j clamp(alpha_j)(P_j - P_1),
+   * phases 1 and 2 from rho1, rho2, ... above, phases 3 and 4 from the
+   * arrays below).  Every pair of phases i < j has its own surface tension
+   * sigma_ij = pair_sigma0 + pair_dsigma_dT (T - T0), acting through the
+   * pair gradient alpha_i grad alpha_j - alpha_j grad alpha_i with the
+   * curvature and Marangoni terms of eqs. 4-7; pairs are ordered (1,2),
+   * (1,3), (1,4), (2,3), (2,4), (3,4) (sigma0, dsigma_dT are not used).  The
+   * heat source acts at the boundary of the condensed fraction 1 - alpha_1.
+   * Not combined with species, integrator 1 or TCF_WITH_ADJOINT. */
+  int nphases;
+  double rho34[2], mu34[2], rhocp34[2], lambda34[2];
+  double pair_sigma0[6], pair_dsigma_dT[6];
 } tcf_config;
 
 typedef struct tcf_step_info {
@@ -152,6 +169,13 @@ tcf_status tcf_get_fields(const tcf_grid* g, double* t, double* alpha, double* T
  * nx*ny*nz cells in the layout above).  TCF_E_STATE on a grid without a
  * species; TCF_E_INVALID on a NULL pointer.  tcf_step needs it set once. */
 tcf_status tcf_set_species(tcf_grid* g, const double* c);
+
+/* Fractions of phases 3 and 4 of a grid made with nphases = 3 or 4: copy in
+ * / out (device FP64, cell layout like alpha; a4 is ignored and may be NULL
+ * when nphases = 3).  TCF_E_STATE on a two-phase grid or (get) before they
+ * are set; TCF_E_INVALID on a missing pointer.  tcf_step needs them set. */
+tcf_status tcf_set_phases(tcf_grid* g, const double* a3, const double* a4);
+tcf_status tcf_get_phases(const tcf_grid* g, double* a3, double* a4);
 tcf_status tcf_get_species(const tcf_grid* g, double* c);
 
 /* Advance nsteps steps of size dt (S1..S8 each).  info may be NULL; when set

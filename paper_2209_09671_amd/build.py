@@ -9,7 +9,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtcf.so")
-SOURCES = ["tcf_kernels.hip", "tcf_transport.hip", "tcf_predictor.hip", "tcf_fine.hip", "tcf_adjoint.hip", "tcf_host.cpp"]
+SOURCES = ["tcf_kernels.hip", "tcf_transport.hip", "tcf_predictor.hip", "tcf_fine.hip", "tcf_adjoint.hip",
+           "tcf_nphase.hip", "tcf_host.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          # keep the compiler from emitting packed FP32 instructions

@@ -57,6 +57,14 @@ struct Fields {
   R *u = nullptr, *v = nullptr, *w = nullptr;  // velocity read by the stencils (alias of u64.. in FP64)
   R *a1, *T1, *a2, *T2;                    // RK3 stage values
   R *c = nullptr, *c1 = nullptr, *c2 = nullptr;  // species field and its RK3 stages (species configs)
+  // N-phase configs: fractions of phases 3, 4 and their RK3 stages; the
+  // mixture (rho, mu, rho c_p, lambda, the density as a fraction of the
+  // operator's range, the condensed fraction 1 - alpha_1); per-pair
+  // sigma*kappa; the face CSF force
+  R *p3 = nullptr, *p31 = nullptr, *p32 = nullptr, *p4 = nullptr, *p41 = nullptr, *p42 = nullptr;
+  R *mrho = nullptr, *mmu = nullptr, *mrcp = nullptr, *mlam = nullptr, *marho = nullptr, *mac = nullptr;
+  R* skp = nullptr;
+  R *fx = nullptr, *fy = nullptr, *fz = nullptr;
   R *sk, *Mx, *My, *Mz;                    // sigma*kappa, Marangoni vector
   R *us, *vs, *ws;                         // predictor
   std::vector<Level<R>> lv;                // Poisson levels (level 0 = fine)
@@ -111,6 +119,9 @@ struct tcf_grid {
   bool fp32;
   bool has_fields = false;
   bool has_species = false;  // species field set (configs with species = 1)
+  bool has_phases = false;   // fractions of phases 3 (and 4) set (N-phase configs)
+  int nph = 2;               // number of phases
+  double op_rho1 = 0.0, op_rho2 = 0.0;  // density range of the pressure operator's linear mix
   double t = 0.0;
   // FP64 state and scratch (both modes)
   double *u64, *v64, *w64, *p64, *b64, *r64, *ax64, *ay64, *az64, *zero64;
@@ -181,7 +192,7 @@ struct Prof {
 };
 
 template <class R>
-void carve_fields(Carver& cv, const Dims& D, Fields<R>& F, int mg_levels, bool alias_state, bool species,
+void carve_fields(Carver& cv, const Dims& D, Fields<R>& F, int mg_levels, bool alias_state, bool species, int nph,
                   double* u64, double* v64, double* w64, double* ax64, double* ay64, double* az64) {
   const long N = D.N;
   F.a = cv.take<R>(N);
@@ -190,6 +201,26 @@ void carve_fields(Carver& cv, const Dims& D, Fields<R>& F, int mg_levels, bool a
     F.c = cv.take<R>(N);
     F.c1 = cv.take<R>(N);
     F.c2 = cv.take<R>(N);
+  }
+  if (nph > 2) {
+    F.p3 = cv.take<R>(N);
+    F.p31 = cv.take<R>(N);
+    F.p32 = cv.take<R>(N);
+    if (nph == 4) {
+      F.p4 = cv.take<R>(N);
+      F.p41 = cv.take<R>(N);
+      F.p42 = cv.take<R>(N);
+    }
+    F.mrho = cv.take<R>(N);
+    F.mmu = cv.take<R>(N);
+    F.mrcp = cv.take<R>(N);
+    F.mlam = cv.take<R>(N);
+    F.marho = cv.take<R>(N);
+    F.mac = cv.take<R>(N);
+    F.skp = cv.take<R>((nph == 4 ? 6 : 3) * N);
+    F.fx = cv.take<R>(D.Nu);
+    F.fy = cv.take<R>(D.Nv);
+    F.fz = D.dim == 3 ? cv.take<R>(D.Nw) : nullptr;
   }
   if (alias_state) {
     F.u = (R*)u64;
@@ -290,11 +321,11 @@ size_t carve(const tcf_config* c, void* base, tcf_grid* g) {
     G->ax64 = G->ay64 = G->az64 = nullptr;
   }
   if (c->precision == TCF_FP32_REFINE)
-    carve_fields<float>(cv, D, G->f32, c->mg_levels, false, c->species != 0, nullptr, nullptr, nullptr, nullptr,
-                        nullptr, nullptr);
+    carve_fields<float>(cv, D, G->f32, c->mg_levels, false, c->species != 0, c->nphases, nullptr, nullptr, nullptr,
+                        nullptr, nullptr, nullptr);
   else
-    carve_fields<double>(cv, D, G->f64, c->mg_levels, true, c->species != 0, G->u64, G->v64, G->w64, G->ax64,
-                         G->ay64, G->az64);
+    carve_fields<double>(cv, D, G->f64, c->mg_levels, true, c->species != 0, c->nphases, G->u64, G->v64, G->w64,
+                         G->ax64, G->ay64, G->az64);
   const int nb = (int)std::max<long>((D.N + 255) / 256, (long)nblocks_cells(D.nx, D.ny, D.nz));
   G->nb = nb;
   if (c->flags & TCF_WITH_ADJOINT) {
@@ -348,6 +379,18 @@ std::string validate(const tcf_config* c) {
   if (c->species && (!std::isfinite(c->dsigma_dc) || !std::isfinite(c->c0))) return "dsigma_dc and c0 must be finite";
   if (c->integrator != 0 && c->integrator != 1) return "integrator must be 0 or 1";
   if (c->integrator == 1 && (c->flags & TCF_WITH_ADJOINT)) return "the adjoint covers integrator 0 only";
+  if (c->nphases != 0 && (c->nphases < 2 || c->nphases > 4)) return "nphases must be 0, 2, 3 or 4";
+  if (c->nphases > 2) {
+    if (c->species) return "the N-phase model is not combined with a species";
+    if (c->integrator == 1) return "the N-phase model uses integrator 0";
+    if (c->flags & TCF_WITH_ADJOINT) return "the adjoint covers the two-phase model only";
+    for (int q = 0; q < c->nphases - 2; ++q)
+      if (!(c->rho34[q] > 0 && c->rhocp34[q] > 0 && c->mu34[q] >= 0 && c->lambda34[q] >= 0))
+        return "phase 3/4 materials: densities and rho*c_p positive, mu and lambda non-negative";
+    for (int q = 0; q < 6; ++q)
+      if (!std::isfinite(c->pair_sigma0[q]) || !std::isfinite(c->pair_dsigma_dT[q]))
+        return "pair surface tensions must be finite";
+  }
   if (!(c->rho1 > 0 && c->rho2 > 0)) return "densities must be positive";
   if (!(c->mu1 >= 0 && c->mu2 >= 0)) return "viscosities must be non-negative";
   if (!(c->rhocp1 > 0 && c->rhocp2 > 0)) return "rho*c_p must be positive";
@@ -388,6 +431,17 @@ KParams make_params(const tcf_config* c) {
   P.T0 = c->T0;
   P.sc = c->species ? c->dsigma_dc : 0.0;
   P.c0 = c->species ? c->c0 : 0.0;
+  P.nph = c->nphases > 2 ? c->nphases : 2;
+  for (int q = 0; q < 2; ++q) {
+    P.mat34[0][q] = c->rho34[q];
+    P.mat34[1][q] = c->mu34[q];
+    P.mat34[2][q] = c->rhocp34[q];
+    P.mat34[3][q] = c->lambda34[q];
+  }
+  for (int q = 0; q < 6; ++q) {
+    P.sig0p[q] = c->pair_sigma0[q];
+    P.dsigp[q] = c->pair_dsigma_dT[q];
+  }
   for (int k = 0; k < 6; ++k) {
     P.Tbc[k] = c->T_bc[k];
     P.Tw[k] = c->T_wall[k];
@@ -411,6 +465,15 @@ hipError_t read_back(tcf_grid* g) {
   return hipStreamSynchronize(g->stream);
 }
 
+// Launch constants of the pressure operator: the grid's, with the density
+// range of the operator's linear mix (no step size: for the solver only).
+KParams op_params(const tcf_grid* g) {
+  KParams P = g->P;
+  P.rho1 = g->op_rho1;
+  P.rho2 = g->op_rho2;
+  return P;
+}
+
 // Operator hierarchy.  Level 0 is applied matrix-free from alpha; its
 // stored weights exist only where something reads them: the FP64 path (its
 // initial residual and the coarsening) and single-level hierarchies (the
@@ -420,7 +483,7 @@ void build_levels(tcf_grid* g, Fields<R>& F, const R* a, bool level0_stored) {
   const int dim = g->D.dim;
   if (F.lv.size() == 1) make_wdiag<R>(g->stream, dim, F.lv[0], 1.0);
   for (size_t l = 1; l < F.lv.size(); ++l) {
-    if (l == 1 && !level0_stored) coarsen_from_alpha<R>(g->P, g->stream, a, F.lv[1]);
+    if (l == 1 && !level0_stored) coarsen_from_alpha<R>(op_params(g), g->stream, a, F.lv[1]);
     else coarsen_weights<R>(g->stream, dim, F.lv[l - 1], F.lv[l]);
     make_wdiag<R>(g->stream, dim, F.lv[l], 1.0);
   }
@@ -441,8 +504,8 @@ Fine<R> fine_desc(tcf_grid* g) {
   F.nx = g->D.nx;
   F.ny = g->D.ny;
   F.nz = g->D.nz;
-  F.rho1 = g->cfg.rho1;
-  F.drho = g->cfg.rho2 - g->cfg.rho1;
+  F.rho1 = g->op_rho1;
+  F.drho = g->op_rho2 - g->op_rho1;
   F.c2 = 2.0 / (g->cfg.h * g->cfg.h);
   return F;
 }
@@ -618,7 +681,8 @@ tcf_status solve_refined(tcf_grid* g, double* p, int* iters, int* nref, double* 
   for (int ref = 0;; ++ref) {
     {
       Prof pr(g, FAM_RESID64);
-      nrp = resid64a<float>(g->P, s, fine_desc<float>(g).a, g->b64, g->scal, p, g->r64, g->part[0], g->part[1]);
+      nrp = resid64a<float>(op_params(g), s, fine_desc<float>(g).a, g->b64, g->scal, p, g->r64, g->part[0],
+                            g->part[1]);
     }
     finalize(s, g->part[0], nrp, g->scal, g->iflag, F_STORE, S_BB64, 0.0);
     finalize(s, g->part[1], nrp, g->scal, g->iflag, F_SCALE, 0, (double)N);
@@ -664,16 +728,27 @@ tcf_status solve_refined(tcf_grid* g, double* p, int* iters, int* nref, double* 
 // Fine face weights from a volume fraction (the state's alpha unless one is
 // given) and the whole hierarchy; the finest-level kernels and the FP64
 // refinement residual recompute their weights from the same alpha.
+// The density of the operator is rho_op1 + clamp(a) (rho_op2 - rho_op1):
+// the two-phase mix of alpha (the state's unless a stage's is given) by
+// default; the N-phase step passes its mixture density as a fraction of a
+// range that holds every mixture.
 template <class R>
-void prepare_operator(tcf_grid* g, const R* a = nullptr) {
+void prepare_operator(tcf_grid* g, const R* a = nullptr, double rho_op1 = NAN, double rho_op2 = NAN) {
   Fields<R>& F = fields<R>(g);
   if (!a) a = F.a;
+  if (std::isnan(rho_op1) || std::isnan(rho_op2)) {
+    rho_op1 = g->cfg.rho1;
+    rho_op2 = g->cfg.rho2;
+  }
   g->a_op = a;
+  g->op_rho1 = rho_op1;
+  g->op_rho2 = rho_op2;
+  const KParams P = op_params(g);
   bool stored = true;
   if (!g->fp32)
-    face_weights<R>(g->P, g->stream, a, g->ax64, g->ay64, g->az64, nullptr, nullptr, nullptr);
+    face_weights<R>(P, g->stream, a, g->ax64, g->ay64, g->az64, nullptr, nullptr, nullptr);
   else if (F.lv.size() == 1)
-    face_weights<R>(g->P, g->stream, a, g->ax64, g->ay64, g->az64, g->f32.lv[0].ax, g->f32.lv[0].ay,
+    face_weights<R>(P, g->stream, a, g->ax64, g->ay64, g->az64, g->f32.lv[0].ax, g->f32.lv[0].ay,
                     g->f32.lv[0].az);
   else
     stored = false;  // the FP64 refinement residual recomputes its weights from alpha
@@ -703,6 +778,113 @@ tcf_status solve(tcf_grid* g, double* p, tcf_step_info* inf) {
 
 template <class R>
 tcf_status step_diag(tcf_grid* g, double dt, double dt_proj, tcf_step_info* inf);
+
+// N-phase model: a density range that holds every mixture rho_1 + sum_j
+// clamp(alpha_j)(rho_j - rho_1), so that the pressure operator's linear mix
+// of the density fraction never clamps.
+void np_rho_range(const tcf_grid* g, double* lo, double* hi) {
+  const KParams& P = g->P;
+  double l = P.rho1 + std::min(0.0, P.rho2 - P.rho1), h = P.rho1 + std::max(0.0, P.rho2 - P.rho1);
+  for (int q = 0; q < g->nph - 2; ++q) {
+    l += std::min(0.0, P.mat34[0][q] - P.rho1);
+    h += std::max(0.0, P.mat34[0][q] - P.rho1);
+  }
+  *lo = l;
+  *hi = h > l ? h : l + 1.0;  // equal densities: every fraction is 0
+}
+
+// Mixture of the given fractions (N-phase fields of F).
+template <class R>
+void np_mix(tcf_grid* g, const R* a2, const R* a3, const R* a4) {
+  Fields<R>& F = fields<R>(g);
+  double lo, hi;
+  np_rho_range(g, &lo, &hi);
+  np_mixture<R>(g->P, g->stream, a2, a3, a4, F.mrho, F.mmu, F.mrcp, F.mlam, F.marho, F.mac, lo, hi);
+}
+
+// S2-S5 of the N-phase model at the state fractions: mixture, per-pair
+// geometry, face CSF force, predictor into F.us, F.vs, F.ws.
+template <class R>
+void np_momentum_rhs(tcf_grid* g, const KParams& P) {
+  Fields<R>& F = fields<R>(g);
+  hipStream_t s = g->stream;
+  np_mix<R>(g, F.a, F.p3, F.p4);
+  {
+    Prof pr(g, FAM_GEOMETRY);
+    np_geometry<R>(P, s, F.a, F.p3, F.p4, F.T, F.skp, F.Mx, F.My, F.Mz);
+    np_face_force<R>(P, s, F.a, F.p3, F.p4, F.skp, F.Mx, F.My, F.Mz, F.fx, F.fy, F.fz);
+  }
+  Prof pr(g, FAM_PREDICTOR);
+  np_predictor<R>(P, s, F.mrho, F.mmu, F.fx, F.fy, F.fz, F.u, F.v, F.w, F.us, F.vs, F.ws);
+}
+
+// The pressure operator of the current state: the two-phase mix of alpha,
+// or the N-phase mixture density as a fraction of its range.
+template <class R>
+void prepare_state_operator(tcf_grid* g) {
+  if (g->nph > 2) {
+    Fields<R>& F = fields<R>(g);
+    np_mix<R>(g, F.a, F.p3, F.p4);
+    double lo, hi;
+    np_rho_range(g, &lo, &hi);
+    prepare_operator<R>(g, F.marho, lo, hi);
+  } else {
+    prepare_operator<R>(g);
+  }
+}
+
+// One step of the N-phase model (integrator 0): SSP-RK3 transport of alpha,
+// T and the fractions of phases 3 (and 4) with u^n frozen, each stage's T
+// right-hand side with the mixture of that stage's fractions; then the
+// mixture, geometry, face force and predictor at the new fractions, the
+// pressure solve with the mixture density, and the projection.
+template <class R>
+tcf_status step_np(tcf_grid* g, double dt, tcf_step_info* inf, bool want_diag) {
+  hipStream_t s = g->stream;
+  Fields<R>& F = fields<R>(g);
+  const Dims& D = g->D;
+  KParams P = g->P;
+  P.dt = dt;
+  P.t = g->t;
+  R* as[3] = {F.a, F.a1, F.a2};
+  R* ao[3] = {F.a1, F.a2, F.a};
+  R* Ts[3] = {F.T, F.T1, F.T2};
+  R* To[3] = {F.T1, F.T2, F.T};
+  R* p3s[3] = {F.p3, F.p31, F.p32};
+  R* p3o[3] = {F.p31, F.p32, F.p3};
+  R* p4s[3] = {F.p4, F.p41, F.p42};
+  R* p4o[3] = {F.p41, F.p42, F.p4};
+  const double cb[3] = {0.0, 0.75, 1.0 / 3.0}, ci[3] = {1.0, 0.25, 2.0 / 3.0};
+  for (int k = 0; k < 3; ++k) {
+    np_mix<R>(g, as[k], p3s[k], g->nph == 4 ? p4s[k] : nullptr);
+    Prof pr(g, FAM_TRANSPORT);
+    np_tstage<R>(P, s, Ts[k], F.T, F.u, F.v, F.w, F.mlam, F.mrcp, F.mac, To[k], cb[k], ci[k]);
+    transport_scalar<R>(P, s, as[k], F.a, F.u, F.v, F.w, ao[k], cb[k], ci[k]);
+    transport_scalar<R>(P, s, p3s[k], F.p3, F.u, F.v, F.w, p3o[k], cb[k], ci[k]);
+    if (g->nph == 4) transport_scalar<R>(P, s, p4s[k], F.p4, F.u, F.v, F.w, p4o[k], cb[k], ci[k]);
+  }
+  tcf_status st = TCF_OK;
+  if (!(g->cfg.flags & TCF_TRANSPORT_ONLY)) {
+    np_momentum_rhs<R>(g, P);
+    const int nbc = nblocks_cells(D.nx, D.ny, D.nz);
+    divergence_rhs<R>(P, s, F.us, F.vs, F.ws, g->b64, g->part[0]);
+    finalize(s, g->part[0], nbc, g->scal, g->iflag, F_MEAN, S_MEAN, (double)D.N);
+    double lo, hi;
+    np_rho_range(g, &lo, &hi);
+    prepare_operator<R>(g, F.marho, lo, hi);  // F.marho: the mixture of the new fractions
+    st = solve(g, g->p64, inf);
+    if (st != TCF_OK && st != TCF_E_NOT_CONVERGED) return st;
+    KParams Pp = P;  // this step's constants with the operator's density range
+    Pp.rho1 = lo;
+    Pp.rho2 = hi;
+    Prof pr(g, FAM_PROJECT);
+    project<R>(Pp, s, F.marho, g->p64, F.us, F.vs, F.ws, g->u64, g->v64, g->w64, g->fp32 ? F.u : nullptr,
+               g->fp32 ? F.v : nullptr, g->fp32 ? F.w : nullptr);
+  }
+  g->t += dt;
+  const tcf_status sd = want_diag ? step_diag<R>(g, dt, dt, inf) : TCF_OK;
+  return sd != TCF_OK ? sd : st;
+}
 
 // One step S1..S8 in precision R.
 template <class R>
@@ -888,8 +1070,12 @@ tcf_status predictor_only(tcf_grid* g, double dt, double* us, double* vs, double
   KParams P = g->P;
   P.dt = dt;
   P.t = g->t;
-  geometry<R>(P, s, F.a, F.T, F.c, F.sk, F.Mx, F.My, F.Mz);
-  predictor<R>(P, s, F.a, F.sk, F.Mx, F.My, F.Mz, F.u, F.v, F.w, F.us, F.vs, F.ws);
+  if (g->nph > 2) {
+    np_momentum_rhs<R>(g, P);
+  } else {
+    geometry<R>(P, s, F.a, F.T, F.c, F.sk, F.Mx, F.My, F.Mz);
+    predictor<R>(P, s, F.a, F.sk, F.Mx, F.My, F.Mz, F.u, F.v, F.w, F.us, F.vs, F.ws);
+  }
   const Dims& D = g->D;
   if (g->fp32) {
     to_f64(s, D.Nu, (const float*)F.us, us);
@@ -1009,6 +1195,9 @@ tcf_status tcf_init_grid(const tcf_config* cfg, void* workspace, size_t bytes, v
   if (g->cfg.dim == 2) g->cfg.nz = 1;
   g->D = dims_of(&g->cfg);
   g->P = make_params(&g->cfg);
+  g->nph = g->P.nph;
+  g->op_rho1 = g->cfg.rho1;
+  g->op_rho2 = g->cfg.rho2;
   g->stream = (hipStream_t)hip_stream;
   g->fp32 = cfg->precision == TCF_FP32_REFINE;
   g->bytes = bytes;
@@ -1102,6 +1291,43 @@ tcf_status tcf_set_species(tcf_grid* g, const double* c) {
   return TCF_OK;
 }
 
+tcf_status tcf_set_phases(tcf_grid* g, const double* a3, const double* a4) {
+  g_err.clear();
+  if (!g) return fail(TCF_E_INVALID, "grid is NULL");
+  if (g->nph <= 2) return fail(TCF_E_STATE, "the grid has two phases (nphases < 3)");
+  if (!a3 || (g->nph == 4 && !a4)) return fail(TCF_E_INVALID, "a3 (and a4 with four phases) must be non-NULL");
+  const long N = g->D.N;
+  if (g->fp32) {
+    to_f32(g->stream, N, a3, g->f32.p3);
+    if (g->nph == 4) to_f32(g->stream, N, a4, g->f32.p4);
+  } else {
+    copy_f64(g->stream, N, a3, g->f64.p3);
+    if (g->nph == 4) copy_f64(g->stream, N, a4, g->f64.p4);
+  }
+  HIPCHECK(hipGetLastError());
+  g->has_phases = true;
+  return TCF_OK;
+}
+
+tcf_status tcf_get_phases(const tcf_grid* gc, double* a3, double* a4) {
+  g_err.clear();
+  if (!gc) return fail(TCF_E_INVALID, "grid is NULL");
+  tcf_grid* g = const_cast<tcf_grid*>(gc);
+  if (g->nph <= 2) return fail(TCF_E_STATE, "the grid has two phases (nphases < 3)");
+  if (!g->has_phases) return fail(TCF_E_STATE, "phase fractions not set");
+  if (!a3 || (g->nph == 4 && !a4)) return fail(TCF_E_INVALID, "a3 (and a4 with four phases) must be non-NULL");
+  const long N = g->D.N;
+  if (g->fp32) {
+    to_f64(g->stream, N, g->f32.p3, a3);
+    if (g->nph == 4) to_f64(g->stream, N, g->f32.p4, a4);
+  } else {
+    copy_f64(g->stream, N, g->f64.p3, a3);
+    if (g->nph == 4) copy_f64(g->stream, N, g->f64.p4, a4);
+  }
+  HIPCHECK(hipGetLastError());
+  return TCF_OK;
+}
+
 tcf_status tcf_get_species(const tcf_grid* gc, double* c) {
   g_err.clear();
   if (!gc) return fail(TCF_E_INVALID, "grid is NULL");
@@ -1122,13 +1348,15 @@ tcf_status tcf_step(tcf_grid* g, double dt, int nsteps, tcf_step_info* info) {
   if (nsteps < 0) return fail(TCF_E_INVALID, "nsteps must be >= 0");
   if (!g->has_fields) return fail(TCF_E_STATE, "fields not set");
   if (g->cfg.species && !g->has_species) return fail(TCF_E_STATE, "species field not set");
+  if (g->nph > 2 && !g->has_phases) return fail(TCF_E_STATE, "phase fractions not set");
   if (info) std::memset(info, 0, sizeof(*info));
   tcf_status worst = TCF_OK;
   for (int k = 0; k < nsteps; ++k) {
     const bool last = k == nsteps - 1;
     tcf_step_info* inf = last ? info : nullptr;
     const bool diag = last && info != nullptr;
-    tcf_status st = g->cfg.integrator == 1
+    tcf_status st = g->nph > 2 ? (g->fp32 ? step_np<float>(g, dt, inf, diag) : step_np<double>(g, dt, inf, diag))
+                    : g->cfg.integrator == 1
                         ? (g->fp32 ? step_rk3p<float>(g, dt, inf, diag) : step_rk3p<double>(g, dt, inf, diag))
                         : (g->fp32 ? step_once<float>(g, dt, inf, diag) : step_once<double>(g, dt, inf, diag));
     if (st == TCF_E_NOT_CONVERGED) {
@@ -1158,8 +1386,8 @@ tcf_status tcf_solve_pressure(tcf_grid* g, const double* rhs, double* p, tcf_ste
   copy_f64(s, N, rhs, g->b64);
   const int nbp = sum64_partials(s, N, g->b64, g->part[0]);
   finalize(s, g->part[0], nbp, g->scal, g->iflag, F_MEAN, S_MEAN, (double)N);
-  if (g->fp32) prepare_operator<float>(g);
-  else prepare_operator<double>(g);
+  if (g->fp32) prepare_state_operator<float>(g);
+  else prepare_state_operator<double>(g);
   tcf_status st = solve(g, p, info);
   hipError_t e = hipStreamSynchronize(s);
   if (e != hipSuccess) return fail(TCF_E_DEVICE, std::string("solve: ") + hipGetErrorString(e));
@@ -1173,6 +1401,7 @@ tcf_status tcf_predictor(tcf_grid* g, double dt, double* us, double* vs, double*
   if (!(dt > 0) || !std::isfinite(dt)) return fail(TCF_E_INVALID, "dt must be positive and finite");
   if (!g->has_fields) return fail(TCF_E_STATE, "fields not set");
   if (g->cfg.species && !g->has_species) return fail(TCF_E_STATE, "species field not set");
+  if (g->nph > 2 && !g->has_phases) return fail(TCF_E_STATE, "phase fractions not set");
   return g->fp32 ? predictor_only<float>(g, dt, us, vs, ws) : predictor_only<double>(g, dt, us, vs, ws);
 }
 
@@ -1181,13 +1410,15 @@ tcf_status tcf_apply_A(tcf_grid* g, const double* x, double* y) {
   if (!g) return fail(TCF_E_INVALID, "grid is NULL");
   if (!x || !y) return fail(TCF_E_INVALID, "x and y must be non-NULL");
   if (!g->has_fields) return fail(TCF_E_STATE, "fields not set");
+  if (g->nph > 2 && !g->has_phases) return fail(TCF_E_STATE, "phase fractions not set");
   hipStream_t s = g->stream;
-  if (g->fp32) prepare_operator<float>(g);
-  else prepare_operator<double>(g);
+  if (g->fp32) prepare_state_operator<float>(g);
+  else prepare_state_operator<double>(g);
   // y = -(0 - 0) - K x = A x, with scal[S_MEAN] = 0 and a zero rhs
   fill_f64(s, 1, g->scal + S_MEAN, 0.0);
-  if (g->fp32) resid64a<float>(g->P, s, g->f32.a, g->zero64, g->scal, x, y, g->part[0], g->part[1]);
-  else resid64a<double>(g->P, s, g->f64.a, g->zero64, g->scal, x, y, g->part[0], g->part[1]);
+  const KParams Pop = op_params(g);
+  if (g->fp32) resid64a<float>(Pop, s, fine_desc<float>(g).a, g->zero64, g->scal, x, y, g->part[0], g->part[1]);
+  else resid64a<double>(Pop, s, fine_desc<double>(g).a, g->zero64, g->scal, x, y, g->part[0], g->part[1]);
   HIPCHECK(hipGetLastError());
   return TCF_OK;
 }

@@ -16,6 +16,12 @@ struct KParams {
   double rho1, rho2, mu1, mu2, rhocp1, rhocp2, lam1, lam2;
   double sigma0, s, T0;
   double sc, c0;  // species: sigma += sc (c - c0) (sc = 0 without a species)
+  // N-phase model (nph 3 or 4; 2 otherwise): material values of phases 3
+  // and 4 (rho, mu, rho c_p, lambda) and per-pair sigma0 / dsigma/dT in the
+  // order (1,2), (1,3), (1,4), (2,3), (2,4), (3,4)
+  int nph;
+  double mat34[4][2];
+  double sig0p[6], dsigp[6];
   int Tbc[6];
   double Tw[6];
   double qP, qr, qx0, qy0, qvx, qvy;
@@ -181,6 +187,28 @@ void adj_transport_stage(const KParams& P, hipStream_t s, const double* a, const
 void adj_scale(hipStream_t s, long n, double f, const double* x, double* y);
 void adj_axpy(hipStream_t s, long n, double f, const double* x, double* y);
 void adj_add_scalar(hipStream_t s, double* dst, const double* src);
+
+// N-phase model (tcf_nphase.hip).  Mixture per cell from the fractions of
+// phases 2..N (rho, mu, rho c_p, lambda; the density as the fraction of
+// [rlo, rhi]; the condensed fraction 1 - alpha_1); per-pair sigma*kappa
+// (pair-major) and the summed Marangoni vector; the face CSF force; the
+// momentum predictor from the mixture; one temperature RK3 stage with the
+// mixture's conductivity and heat capacity.  a4 = NULL with three phases.
+template <class R>
+void np_mixture(const KParams& P, hipStream_t s, const R* a2, const R* a3, const R* a4, R* rho, R* mu, R* rcp,
+                R* lam, R* arho, R* ac, double rlo, double rhi);
+template <class R>
+void np_geometry(const KParams& P, hipStream_t s, const R* a2, const R* a3, const R* a4, const R* T, R* skp, R* Mx,
+                 R* My, R* Mz);
+template <class R>
+void np_face_force(const KParams& P, hipStream_t s, const R* a2, const R* a3, const R* a4, const R* skp, const R* Mx,
+                   const R* My, const R* Mz, R* fx, R* fy, R* fz);
+template <class R>
+void np_predictor(const KParams& P, hipStream_t s, const R* rho, const R* mu, const R* fx, const R* fy, const R* fz,
+                  const R* u, const R* v, const R* w, R* us, R* vs, R* ws);
+template <class R>
+void np_tstage(const KParams& P, hipStream_t s, const R* T, const R* Tb, const R* u, const R* v, const R* w,
+               const R* lam, const R* rcp, const R* ac, R* To, double cb, double ci);
 
 // SSP-RK3 stage combination of a face velocity with the FP64 base velocity
 // (stage 1: 3/4 base + 1/4 x; stage 2: base/3 + 2/3 x), in place

@@ -1,0 +1,442 @@
+// N-phase VOF kernels (eq. 1 for every phase of several in one domain).
+//
+// Phase 1 is the background with alpha_1 = 1 - (alpha_2 + alpha_3 [+
+// alpha_4]); phases 2..N are carried by the scalar WENO5 / SSP-RK3 transport
+// of the two-phase path.  These kernels produce what the two-phase kernels
+// take from alpha alone: the mixture (material laws linear in each clamped
+// fraction relative to phase 1), the per-pair interface geometry and CSF
+// force, the momentum predictor from the mixture, and the temperature stage
+// with the mixture's conductivity and heat capacity.  Each surface-tension
+// pair i < j acts through its pair gradient g_ij = alpha_i grad alpha_j -
+// alpha_j grad alpha_i (grad alpha for two phases) with the curvature and
+// Marangoni terms of eqs. 4-7.  One thread per cell or face on 64 x 4
+// blocks; ghost values by reflected indexing as in the two-phase kernels.
+#include <cfloat>
+#include <cmath>
+
+#include "tcf_device.h"
+#include "tcf_internal.h"
+
+namespace tcf {
+namespace {
+
+using namespace dev;
+
+inline dim3 grid_np(int fnx, int fny, int fnz) { return dim3((fnx + BX - 1) / BX, (fny + BY - 1) / BY, fnz); }
+inline dim3 blk_np() { return dim3(BX, BY, 1); }
+
+// Pairs (i, j) of an N-phase grid in the order of the pair tables; slot =
+// position in the six-pair table (1,2), (1,3), (1,4), (2,3), (2,4), (3,4).
+template <int NPH>
+struct PairList;
+template <>
+struct PairList<3> {
+  static constexpr int n = 3;
+  __device__ static int I(int p) { return p == 2 ? 2 : 1; }
+  __device__ static int J(int p) { return p == 0 ? 2 : 3; }
+  __device__ static int slot(int p) { return p == 2 ? 3 : p; }
+};
+template <>
+struct PairList<4> {
+  static constexpr int n = 6;
+  __device__ static int I(int p) { return p < 3 ? 1 : (p < 5 ? 2 : 3); }
+  __device__ static int J(int p) { return p < 3 ? p + 2 : (p < 5 ? p - 0 : 4); }
+  __device__ static int slot(int p) { return p; }
+};
+
+template <class R>
+struct Phases {
+  const R* a2;
+  const R* a3;
+  const R* a4;
+};
+
+// fraction of phase q (1..4) at a cell, ghosts by even reflection
+template <int DIM, int NPH, class R>
+__device__ __forceinline__ R ph_at(const Phases<R>& F, int q, int i, int j, int k, int nx, int ny, int nz) {
+  if (q == 2) return A_at<DIM>(F.a2, i, j, k, nx, ny, nz);
+  if (q == 3) return A_at<DIM>(F.a3, i, j, k, nx, ny, nz);
+  if (NPH == 4 && q == 4) return A_at<DIM>(F.a4, i, j, k, nx, ny, nz);
+  R s = A_at<DIM>(F.a2, i, j, k, nx, ny, nz) + A_at<DIM>(F.a3, i, j, k, nx, ny, nz);
+  if (NPH == 4) s += A_at<DIM>(F.a4, i, j, k, nx, ny, nz);
+  return R(1) - s;
+}
+
+// ---------------------------------------------------------------------------
+// Mixture per cell: rho, mu, rho c_p, lambda = P_1 + sum_j clamp(alpha_j)
+// (P_j - P_1) (FP64, then stored in R); the density as the fraction
+// (rho - rlo) / (rhi - rlo) of a range that holds every mixture, which the
+// pressure kernels' linear mix turns back into rho; the condensed fraction
+// 1 - alpha_1.
+template <class R, int NPH>
+__global__ __launch_bounds__(256) void k_np_mixture(KParams P, long n, Phases<R> F, R* __restrict__ rho,
+                                                    R* __restrict__ mu, R* __restrict__ rcp, R* __restrict__ lam,
+                                                    R* __restrict__ arho, R* __restrict__ ac, double rlo,
+                                                    double rhi) {
+  const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  auto cl = [](double v) { return v < 0.0 ? 0.0 : (v > 1.0 ? 1.0 : v); };
+  const double a2 = (double)F.a2[c], a3 = (double)F.a3[c], a4 = NPH == 4 ? (double)F.a4[c] : 0.0;
+  const double p1[4] = {P.rho1, P.mu1, P.rhocp1, P.lam1}, p2[4] = {P.rho2, P.mu2, P.rhocp2, P.lam2};
+  double m[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    double v = p1[q] + cl(a2) * (p2[q] - p1[q]);
+    v += cl(a3) * (P.mat34[q][0] - p1[q]);
+    if (NPH == 4) v += cl(a4) * (P.mat34[q][1] - p1[q]);
+    m[q] = v;
+  }
+  rho[c] = R(m[0]);
+  mu[c] = R(m[1]);
+  rcp[c] = R(m[2]);
+  lam[c] = R(m[3]);
+  arho[c] = R((m[0] - rlo) / (rhi - rlo));
+  double s = a2 + a3;
+  if (NPH == 4) s += a4;
+  ac[c] = R(1.0 - (1.0 - s));
+}
+
+// ---------------------------------------------------------------------------
+// Geometry per interior cell: for each pair, sigma_ij kappa_ij into skp
+// (pair-major) and the Marangoni vector summed over the pairs into M.
+template <class R, int DIM, int NPH>
+__device__ __forceinline__ void pair_grad(const Phases<R>& F, int I, int J, int i, int j, int k, int nx, int ny,
+                                          int nz, R ih2, R g[3]) {
+  const R ai = ph_at<DIM, NPH>(F, I, i, j, k, nx, ny, nz), aj = ph_at<DIM, NPH>(F, J, i, j, k, nx, ny, nz);
+  auto d = [&](int q, int di, int dj, int dk) {
+    return (ph_at<DIM, NPH>(F, q, i + di, j + dj, k + dk, nx, ny, nz) -
+            ph_at<DIM, NPH>(F, q, i - di, j - dj, k - dk, nx, ny, nz)) * ih2;
+  };
+  g[0] = ai * d(J, 1, 0, 0) - aj * d(I, 1, 0, 0);
+  g[1] = ai * d(J, 0, 1, 0) - aj * d(I, 0, 1, 0);
+  g[2] = DIM == 3 ? ai * d(J, 0, 0, 1) - aj * d(I, 0, 0, 1) : R(0);
+}
+
+template <class R, int DIM, int NPH>
+__global__ __launch_bounds__(256) void k_np_geometry(KParams P, Phases<R> F, const R* __restrict__ T,
+                                                     R* __restrict__ skp, R* __restrict__ Mx, R* __restrict__ My,
+                                                     R* __restrict__ Mz) {
+  const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
+  const int nx = P.nx, ny = P.ny, nz = P.nz;
+  if (i >= nx || j >= ny) return;
+  const R ih2 = R(0.5 * P.ih), ne = R(P.neps);
+  const long c = cidx(i, j, k, nx, ny);
+  const long N = (long)nx * ny * nz;
+  const R Tc = T[c];
+  const R dT0 = (T_at<DIM>(T, i + 1, j, k, P) - T_at<DIM>(T, i - 1, j, k, P)) * ih2;
+  const R dT1 = (T_at<DIM>(T, i, j + 1, k, P) - T_at<DIM>(T, i, j - 1, k, P)) * ih2;
+  const R dT2 = DIM == 3 ? (T_at<DIM>(T, i, j, k + 1, P) - T_at<DIM>(T, i, j, k - 1, P)) * ih2 : R(0);
+  R M0 = R(0), M1 = R(0), M2 = R(0);
+  for (int p = 0; p < PairList<NPH>::n; ++p) {
+    const int I = PairList<NPH>::I(p), J = PairList<NPH>::J(p), sl = PairList<NPH>::slot(p);
+    auto normal = [&](int ii, int jj, int kk, R n[3]) {
+      R g[3];
+      pair_grad<R, DIM, NPH>(F, I, J, ii, jj, kk, nx, ny, nz, ih2, g);
+      const R ge = sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2] + ne * ne);
+      n[0] = g[0] / ge;
+      n[1] = g[1] / ge;
+      n[2] = g[2] / ge;
+    };
+    R np[3], nm[3];
+    normal(i + 1, j, k, np);
+    normal(i - 1, j, k, nm);
+    R divn = (np[0] - nm[0]) * ih2;
+    normal(i, j + 1, k, np);
+    normal(i, j - 1, k, nm);
+    divn += (np[1] - nm[1]) * ih2;
+    if (DIM == 3) {
+      normal(i, j, k + 1, np);
+      normal(i, j, k - 1, nm);
+      divn += (np[2] - nm[2]) * ih2;
+    }
+    R g[3];
+    pair_grad<R, DIM, NPH>(F, I, J, i, j, k, nx, ny, nz, ih2, g);
+    const R g2 = g[0] * g[0] + g[1] * g[1] + g[2] * g[2];
+    const R ge = sqrt(g2 + ne * ne);
+    const R ds = g2 / (ge + ne);
+    const R n0 = g[0] / ge, n1 = g[1] / ge, n2 = g[2] / ge;
+    const R sT = R(P.dsigp[sl]);
+    const R sigma = R(P.sig0p[sl]) + sT * (Tc - R(P.T0));
+    const R gs0 = sT * dT0, gs1 = sT * dT1, gs2 = sT * dT2;
+    const R ndg = n0 * gs0 + n1 * gs1 + n2 * gs2;
+    M0 += ds * (gs0 - n0 * ndg);
+    M1 += ds * (gs1 - n1 * ndg);
+    M2 += ds * (gs2 - n2 * ndg);
+    skp[p * N + c] = sigma * -divn;
+  }
+  Mx[c] = M0;
+  My[c] = M1;
+  if (DIM == 3) Mz[c] = M2;
+}
+
+// ---------------------------------------------------------------------------
+// Face CSF force of direction D: 1/2 (M_L + M_R)_D plus, per pair,
+// 1/2 (skp_L + skp_R) times the face pair gradient avg(alpha_i)(alpha_j,R -
+// alpha_j,L)/h - avg(alpha_j)(alpha_i,R - alpha_i,L)/h; wall faces 0.
+template <class R, int DIM, int D, int NPH>
+__global__ __launch_bounds__(256) void k_np_face_force(KParams P, Phases<R> F, const R* __restrict__ skp,
+                                                       const R* __restrict__ Md, R* __restrict__ f) {
+  const int nx = P.nx, ny = P.ny, nz = P.nz;
+  const int fnx = nx + (D == 0), fny = ny + (D == 1);
+  const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
+  if (i >= fnx || j >= fny) return;
+  const long fi = (long)i + (long)fnx * ((long)j + (long)fny * k);
+  const int m = D == 0 ? i : (D == 1 ? j : k), nd = D == 0 ? nx : (D == 1 ? ny : nz);
+  if (m == 0 || m == nd) {
+    f[fi] = R(0);
+    return;
+  }
+  const int iL = i - (D == 0), jL = j - (D == 1), kL = k - (D == 2);
+  const long cL = cidx(iL, jL, kL, nx, ny), cR = cidx(i, j, k, nx, ny);
+  const long N = (long)nx * ny * nz;
+  const R ih = R(P.ih);
+  R fo = R(0.5) * (Md[cL] + Md[cR]);
+  for (int p = 0; p < PairList<NPH>::n; ++p) {
+    const int I = PairList<NPH>::I(p), J = PairList<NPH>::J(p);
+    const R aiL = ph_at<DIM, NPH>(F, I, iL, jL, kL, nx, ny, nz), aiR = ph_at<DIM, NPH>(F, I, i, j, k, nx, ny, nz);
+    const R ajL = ph_at<DIM, NPH>(F, J, iL, jL, kL, nx, ny, nz), ajR = ph_at<DIM, NPH>(F, J, i, j, k, nx, ny, nz);
+    const R G = (R(0.5) * (aiL + aiR) * (ajR - ajL) - R(0.5) * (ajL + ajR) * (aiR - aiL)) * ih;
+    fo += R(0.5) * (skp[p * N + cL] + skp[p * N + cR]) * G;
+  }
+  f[fi] = fo;
+}
+
+// ---------------------------------------------------------------------------
+// Momentum predictor of component D from the mixture: u* = u + dt (-C(u) +
+// (V(u) + f) / rho_f) with the conservative WENO5 convection and the
+// variable-mu stress of the two-phase predictor (mu on edges the mean of
+// four cells, rho_f the mean of two), f the face force above.
+template <class R, int DIM, int D>
+__global__ __launch_bounds__(256) void k_np_predictor(KParams P, const R* __restrict__ rho, const R* __restrict__ mu,
+                                                      const R* __restrict__ f, const R* __restrict__ u,
+                                                      const R* __restrict__ v, const R* __restrict__ w,
+                                                      R* __restrict__ us) {
+  const int nx = P.nx, ny = P.ny, nz = P.nz;
+  const int fnx = nx + (D == 0), fny = ny + (D == 1);
+  const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
+  if (i >= fnx || j >= fny) return;
+  const long fi = (long)i + (long)fnx * ((long)j + (long)fny * k);
+  const int id[3] = {i, j, k};
+  const int nd = D == 0 ? nx : (D == 1 ? ny : nz);
+  if (id[D] == 0 || id[D] == nd) {
+    us[fi] = R(0);
+    return;
+  }
+  const R* vel[3] = {u, v, w};
+  const R h = R(P.h), eps = R(P.weno_eps);
+  auto comp = [&](int C, int ii, int jj, int kk) -> R {
+    if (C == 0) return V_at<0, DIM>(u, ii, jj, kk, nx, ny, nz);
+    if (C == 1) return V_at<1, DIM>(v, ii, jj, kk, nx, ny, nz);
+    return V_at<2, DIM>(w, ii, jj, kk, nx, ny, nz);
+  };
+  auto ud = [&](int oi, int oj, int ok) { return comp(D, i + oi, j + oj, k + ok); };
+  auto mu_at = [&](int ii, int jj, int kk) { return A_at<DIM>(mu, ii, jj, kk, nx, ny, nz); };
+  int L[3] = {i, j, k};
+  L[D] -= 1;
+  R conv = R(0), visc = R(0);
+  for (int e = 0; e < DIM; ++e) {
+    int oe[3] = {0, 0, 0};
+    oe[e] = 1;
+    R Fs[2], Ts[2];
+    if (e == D) {
+      for (int side = 0; side < 2; ++side) {
+        const int s0 = side - 1;
+        const R Ub = R(0.5) * (ud(s0 * oe[0], s0 * oe[1], s0 * oe[2]) +
+                               ud((s0 + 1) * oe[0], (s0 + 1) * oe[1], (s0 + 1) * oe[2]));
+        R q[6];
+        for (int t = 0; t < 6; ++t) {
+          const int mm = s0 + 1 - 3 + t;
+          q[t] = ud(mm * oe[0], mm * oe[1], mm * oe[2]);
+        }
+        const R Uh = upwind(q, Ub, eps);
+        int cc[3] = {i, j, k};
+        cc[D] += s0;
+        const R tau = R(2) * mu_at(cc[0], cc[1], cc[2]) *
+                      (ud((s0 + 1) * oe[0], (s0 + 1) * oe[1], (s0 + 1) * oe[2]) - ud(s0 * oe[0], s0 * oe[1], s0 * oe[2])) / h;
+        Fs[side] = Ub * Uh;
+        Ts[side] = tau;
+      }
+    } else {
+      for (int side = 0; side < 2; ++side) {
+        const int ef = id[e] + side;
+        int pL[3] = {L[0], L[1], L[2]}, pR[3] = {i, j, k};
+        pL[e] = ef;
+        pR[e] = ef;
+        const R VL = comp(e, pL[0], pL[1], pL[2]), VR = comp(e, pR[0], pR[1], pR[2]);
+        const R Vb = R(0.5) * (VL + VR);
+        R q[6];
+        for (int t = 0; t < 6; ++t) {
+          int o[3] = {0, 0, 0};
+          o[e] = ef - 3 + t - id[e];
+          q[t] = ud(o[0], o[1], o[2]);
+        }
+        const R Uh = upwind(q, Vb, eps);
+        int o0[3] = {0, 0, 0}, o1[3] = {0, 0, 0};
+        o0[e] = ef - 1 - id[e];
+        o1[e] = ef - id[e];
+        const R dud = (ud(o1[0], o1[1], o1[2]) - ud(o0[0], o0[1], o0[2])) / h;
+        const R dve = (VR - VL) / h;
+        int c1[3] = {L[0], L[1], L[2]}, c2[3] = {i, j, k}, c3[3] = {L[0], L[1], L[2]}, c4[3] = {i, j, k};
+        c1[e] = ef - 1;
+        c2[e] = ef - 1;
+        c3[e] = ef;
+        c4[e] = ef;
+        const R me = R(0.25) * (mu_at(c1[0], c1[1], c1[2]) + mu_at(c2[0], c2[1], c2[2]) + mu_at(c3[0], c3[1], c3[2]) +
+                                mu_at(c4[0], c4[1], c4[2]));
+        Fs[side] = Vb * Uh;
+        Ts[side] = me * (dud + dve);
+      }
+    }
+    conv += (Fs[1] - Fs[0]) / h;
+    visc += (Ts[1] - Ts[0]) / h;
+  }
+  const R rhof = R(0.5) * (rho[cidx(L[0], L[1], L[2], nx, ny)] + rho[cidx(i, j, k, nx, ny)]);
+  us[fi] = vel[D][fi] + R(P.dt) * (-conv + (visc + f[fi]) / rhof);
+}
+
+// ---------------------------------------------------------------------------
+// Temperature stage with the mixture: LT = -div(u T) + [div(lambda grad T) +
+// Q delta_c] / (rho c_p), delta_c the regularised gradient norm of the
+// condensed fraction; To = cb Tb + ci (T + dt LT).
+template <class R, int DIM>
+__global__ __launch_bounds__(256) void k_np_tstage(KParams P, const R* __restrict__ T, const R* __restrict__ Tb,
+                                                   const R* __restrict__ u, const R* __restrict__ v,
+                                                   const R* __restrict__ w, const R* __restrict__ lam,
+                                                   const R* __restrict__ rcp, const R* __restrict__ ac,
+                                                   R* __restrict__ To, double cb, double ci) {
+  const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
+  const int nx = P.nx, ny = P.ny, nz = P.nz;
+  if (i >= nx || j >= ny) return;
+  const long c = cidx(i, j, k, nx, ny);
+  const R eps = R(P.weno_eps), h = R(P.h);
+  // WENO5 upwind flux through the d-face with index m along d (walls: 0)
+  auto flux = [&](int d, int m) -> R {
+    const int nd = d == 0 ? nx : (d == 1 ? ny : nz);
+    if (m == 0 || m == nd) return R(0);
+    R uf;
+    if (d == 0) uf = u[fidx<0>(m, j, k, nx, ny)];
+    else if (d == 1) uf = v[fidx<1>(i, m, k, nx, ny)];
+    else uf = w[fidx<2>(i, j, m, nx, ny)];
+    R q[6];
+    for (int t = 0; t < 6; ++t) {
+      const int mm = m - 3 + t;
+      q[t] = d == 0 ? T_at<DIM>(T, mm, j, k, P) : (d == 1 ? T_at<DIM>(T, i, mm, k, P) : T_at<DIM>(T, i, j, mm, P));
+    }
+    return uf * upwind(q, uf, eps);
+  };
+  R divt = (flux(0, i + 1) - flux(0, i)) + (flux(1, j + 1) - flux(1, j));
+  if (DIM == 3) divt += flux(2, k + 1) - flux(2, k);
+  const R Tc = T[c], lc = lam[c];
+  R cond = R(0);
+  const int off[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
+  for (int d = 0; d < DIM; ++d)
+    for (int sg = -1; sg <= 1; sg += 2) {
+      const int ii = i + sg * off[d][0], jj = j + sg * off[d][1], kk = k + sg * off[d][2];
+      const R lf = R(0.5) * (lc + A_at<DIM>(lam, ii, jj, kk, nx, ny, nz));
+      cond += lf * (T_at<DIM>(T, ii, jj, kk, P) - Tc);
+    }
+  cond /= h * h;
+  R src = R(0);
+  if (P.qP != 0.0) {
+    const R ih2 = R(0.5 * P.ih), ne = R(P.neps);
+    const R g0 = (A_at<DIM>(ac, i + 1, j, k, nx, ny, nz) - A_at<DIM>(ac, i - 1, j, k, nx, ny, nz)) * ih2;
+    const R g1 = (A_at<DIM>(ac, i, j + 1, k, nx, ny, nz) - A_at<DIM>(ac, i, j - 1, k, nx, ny, nz)) * ih2;
+    const R g2 = DIM == 3 ? (A_at<DIM>(ac, i, j, k + 1, nx, ny, nz) - A_at<DIM>(ac, i, j, k - 1, nx, ny, nz)) * ih2 : R(0);
+    const R gg = g0 * g0 + g1 * g1 + g2 * g2;
+    const R ds = gg / (sqrt(gg + ne * ne) + ne);
+    const double xl = P.qx0 + P.qvx * P.t, yl = P.qy0 + P.qvy * P.t;
+    const double x = (i + 0.5) * P.h, y = (j + 0.5) * P.h;
+    const double r2 = (x - xl) * (x - xl) + (y - yl) * (y - yl);
+    const double R2 = P.qr * P.qr;
+    src = R(2.0 * P.qP / (M_PI * R2) * exp(-2.0 * r2 / R2)) * ds;
+  }
+  const R LT = -divt / h + (cond + src) / rcp[c];
+  To[c] = R(cb) * Tb[c] + R(ci) * (Tc + R(P.dt) * LT);
+}
+
+}  // namespace
+
+// ---- launchers ---------------------------------------------------------------
+template <class R>
+void np_mixture(const KParams& P, hipStream_t s, const R* a2, const R* a3, const R* a4, R* rho, R* mu, R* rcp,
+                R* lam, R* arho, R* ac, double rlo, double rhi) {
+  const long n = (long)P.nx * P.ny * P.nz;
+  const Phases<R> F{a2, a3, a4};
+  const dim3 g((unsigned)((n + 255) / 256));
+  if (P.nph == 4) hipLaunchKernelGGL((k_np_mixture<R, 4>), g, dim3(256), 0, s, P, n, F, rho, mu, rcp, lam, arho, ac, rlo, rhi);
+  else hipLaunchKernelGGL((k_np_mixture<R, 3>), g, dim3(256), 0, s, P, n, F, rho, mu, rcp, lam, arho, ac, rlo, rhi);
+}
+
+template <class R>
+void np_geometry(const KParams& P, hipStream_t s, const R* a2, const R* a3, const R* a4, const R* T, R* skp, R* Mx,
+                 R* My, R* Mz) {
+  const Phases<R> F{a2, a3, a4};
+  const dim3 g = grid_np(P.nx, P.ny, P.nz);
+  if (P.dim == 3) {
+    if (P.nph == 4) hipLaunchKernelGGL((k_np_geometry<R, 3, 4>), g, blk_np(), 0, s, P, F, T, skp, Mx, My, Mz);
+    else hipLaunchKernelGGL((k_np_geometry<R, 3, 3>), g, blk_np(), 0, s, P, F, T, skp, Mx, My, Mz);
+  } else {
+    if (P.nph == 4) hipLaunchKernelGGL((k_np_geometry<R, 2, 4>), g, blk_np(), 0, s, P, F, T, skp, Mx, My, Mz);
+    else hipLaunchKernelGGL((k_np_geometry<R, 2, 3>), g, blk_np(), 0, s, P, F, T, skp, Mx, My, Mz);
+  }
+}
+
+template <class R, int DIM, int NPH>
+static void face_force_dim(const KParams& P, hipStream_t s, const Phases<R>& F, const R* skp, const R* Mx, const R* My,
+                           const R* Mz, R* fx, R* fy, R* fz) {
+  hipLaunchKernelGGL((k_np_face_force<R, DIM, 0, NPH>), grid_np(P.nx + 1, P.ny, P.nz), blk_np(), 0, s, P, F, skp, Mx, fx);
+  hipLaunchKernelGGL((k_np_face_force<R, DIM, 1, NPH>), grid_np(P.nx, P.ny + 1, P.nz), blk_np(), 0, s, P, F, skp, My, fy);
+  if (DIM == 3)
+    hipLaunchKernelGGL((k_np_face_force<R, DIM, 2, NPH>), grid_np(P.nx, P.ny, P.nz + 1), blk_np(), 0, s, P, F, skp, Mz, fz);
+}
+
+template <class R>
+void np_face_force(const KParams& P, hipStream_t s, const R* a2, const R* a3, const R* a4, const R* skp, const R* Mx,
+                   const R* My, const R* Mz, R* fx, R* fy, R* fz) {
+  const Phases<R> F{a2, a3, a4};
+  if (P.dim == 3) {
+    if (P.nph == 4) face_force_dim<R, 3, 4>(P, s, F, skp, Mx, My, Mz, fx, fy, fz);
+    else face_force_dim<R, 3, 3>(P, s, F, skp, Mx, My, Mz, fx, fy, fz);
+  } else {
+    if (P.nph == 4) face_force_dim<R, 2, 4>(P, s, F, skp, Mx, My, Mz, fx, fy, fz);
+    else face_force_dim<R, 2, 3>(P, s, F, skp, Mx, My, Mz, fx, fy, fz);
+  }
+}
+
+template <class R>
+void np_predictor(const KParams& P, hipStream_t s, const R* rho, const R* mu, const R* fx, const R* fy, const R* fz,
+                  const R* u, const R* v, const R* w, R* us, R* vs, R* ws) {
+  if (P.dim == 3) {
+    hipLaunchKernelGGL((k_np_predictor<R, 3, 0>), grid_np(P.nx + 1, P.ny, P.nz), blk_np(), 0, s, P, rho, mu, fx, u, v, w, us);
+    hipLaunchKernelGGL((k_np_predictor<R, 3, 1>), grid_np(P.nx, P.ny + 1, P.nz), blk_np(), 0, s, P, rho, mu, fy, u, v, w, vs);
+    hipLaunchKernelGGL((k_np_predictor<R, 3, 2>), grid_np(P.nx, P.ny, P.nz + 1), blk_np(), 0, s, P, rho, mu, fz, u, v, w, ws);
+  } else {
+    hipLaunchKernelGGL((k_np_predictor<R, 2, 0>), grid_np(P.nx + 1, P.ny, 1), blk_np(), 0, s, P, rho, mu, fx, u, v, w, us);
+    hipLaunchKernelGGL((k_np_predictor<R, 2, 1>), grid_np(P.nx, P.ny + 1, 1), blk_np(), 0, s, P, rho, mu, fy, u, v, w, vs);
+  }
+}
+
+template <class R>
+void np_tstage(const KParams& P, hipStream_t s, const R* T, const R* Tb, const R* u, const R* v, const R* w,
+               const R* lam, const R* rcp, const R* ac, R* To, double cb, double ci) {
+  const dim3 g = grid_np(P.nx, P.ny, P.dim == 3 ? P.nz : 1);
+  if (P.dim == 3) hipLaunchKernelGGL((k_np_tstage<R, 3>), g, blk_np(), 0, s, P, T, Tb, u, v, w, lam, rcp, ac, To, cb, ci);
+  else hipLaunchKernelGGL((k_np_tstage<R, 2>), g, blk_np(), 0, s, P, T, Tb, u, v, w, lam, rcp, ac, To, cb, ci);
+}
+
+#define TCF_NP_INST(R)                                                                                              \
+  template void np_mixture<R>(const KParams&, hipStream_t, const R*, const R*, const R*, R*, R*, R*, R*, R*, R*,  \
+                              double, double);                                                                     \
+  template void np_geometry<R>(const KParams&, hipStream_t, const R*, const R*, const R*, const R*, R*, R*, R*,   \
+                               R*);                                                                                \
+  template void np_face_force<R>(const KParams&, hipStream_t, const R*, const R*, const R*, const R*, const R*,    \
+                                 const R*, const R*, R*, R*, R*);                                                  \
+  template void np_predictor<R>(const KParams&, hipStream_t, const R*, const R*, const R*, const R*, const R*,     \
+                                const R*, const R*, const R*, R*, R*, R*);                                         \
+  template void np_tstage<R>(const KParams&, hipStream_t, const R*, const R*, const R*, const R*, const R*,        \
+                             const R*, const R*, const R*, R*, double, double);
+
+TCF_NP_INST(double)
+TCF_NP_INST(float)
+
+}  // namespace tcf

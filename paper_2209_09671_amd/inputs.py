@@ -271,15 +271,30 @@ def droplet_phases(c, layout):
                        {(1, 2): -0.1, (1, 3): -0.05, (2, 3): -0.02})
 
 
+def droplet_phases4(c, layout):
+    """droplet_phases with a fourth phase (lighter, less viscous) and tensions
+    for all six pairs."""
+    ph3 = dict(rho=3.0, mu=0.03, rhocp=2.0, **{"lambda": 1.5e-3})
+    ph4 = dict(rho=1.5, mu=0.005, rhocp=3.0, **{"lambda": 0.8e-3})
+    return with_phases(c, layout, [ph3, ph4],
+                       {(1, 2): 1.0, (1, 3): 0.8, (1, 4): 0.6, (2, 3): 0.5, (2, 4): 0.4, (3, 4): 0.3},
+                       {(1, 2): -0.1, (1, 3): -0.05, (1, 4): -0.08, (2, 3): -0.02, (2, 4): -0.03, (3, 4): -0.01})
+
+
 def meltpool_phases(c):
     """The melt-pool sheet with three phases: gas (1), liquid metal (2) in a
     pool under the beam's start, and solid metal (3) around and below it.
-    Without a phase-change model the solid is a fluid 1000 times more viscous
-    than the melt with a higher conductivity; gas-liquid keeps the thermal
-    Marangoni law, gas-solid a constant tension, liquid-solid none."""
-    ph3 = dict(rho=c["rho2"], mu=1000.0 * c["mu2"], rhocp=c["rhocp2"], **{"lambda": 20.0})
-    return with_phases(c, "meltpool3", [ph3], {(1, 2): c["sigma0"], (1, 3): c["sigma0"]},
-                       {(1, 2): c["dsigma_dT"]})
+    Without a phase-change model the solid is a more viscous fluid with a
+    higher conductivity; gas-liquid keeps the thermal
+    Marangoni law, gas-solid a constant tension, liquid-solid none.  The
+    solid's viscosity (50 times the melt's) keeps the explicit viscous number
+    dt mu / (rho h^2) at 0.05 on the 2.5 um grid with dt = 1e-8 s."""
+    ph3 = dict(rho=c["rho2"], mu=50.0 * c["mu2"], rhocp=c["rhocp2"], **{"lambda": 20.0})
+    out = with_phases(c, "meltpool3", [ph3], {(1, 2): c["sigma0"], (1, 3): c["sigma0"]},
+                      {(1, 2): c["dsigma_dT"]})
+    # the beam starts at (L_x / 4, L_y / 2) of this box, above the pool
+    out.update(q_x0=c["nx"] * c["h"] / 4.0, q_y0=c["ny"] * c["h"] / 2.0)
+    return out
 
 
 def phase_fields(c) -> dict:
@@ -287,7 +302,9 @@ def phase_fields(c) -> dict:
     alpha3=..., [alpha4=...]) as float64 cell arrays (tanh edges of length
     1.5 h).  Layouts: absent (phase 2 as in initial_state, phase 3 zero),
     two_drops (2D: drops of phases 2 and 3 of radius 0.1 L at 0.25 L and
-    0.75 L), layers (phase 3 below
+    0.75 L), layers4 (phases 4 | 3 | 2 | 1 upward, edges at 0.25, 0.45,
+    0.65 L), absent4 (the lens with a fourth phase of zero fraction), layers
+    (phase 3 below
     0.3 L, phase 2 up to 0.6 L, background above, along the vertical), lens
     (2D: a phase-3 drop on a phase-2 layer), meltpool3 (the melt-pool surface
     with a liquid half-ellipsoid under the beam's start, solid elsewhere)."""
@@ -315,13 +332,19 @@ def phase_fields(c) -> dict:
     elif lay == "layers":
         a3 = _smooth_step(0.3 * lv - vert, w)
         a2 = _smooth_step(0.6 * lv - vert, w) - a3
+    elif lay == "layers4":
+        a4 = _smooth_step(0.25 * lv - vert, w)
+        a3 = _smooth_step(0.45 * lv - vert, w) - a4
+        a2 = _smooth_step(0.65 * lv - vert, w) - a3 - a4
+    elif lay == "absent4":
+        a2, a3 = None, None
     elif lay == "lens":
         a3 = _smooth_step(0.15 - np.hypot(X - 0.5, Y - 0.45), w)
         a2 = _smooth_step(0.45 - Y, w) * (1.0 - a3)
     elif lay == "meltpool3":
         ac = initial_state(c)["alpha"]
         lx, ly, lz = c["nx"] * h, c["ny"] * h, c["nz"] * h
-        e = np.sqrt(((X - c["q_x0"]) / (0.25 * lx)) ** 2 + ((Y - c["q_y0"]) / (0.25 * ly)) ** 2
+        e = np.sqrt(((X - 0.25 * lx) / (0.25 * lx)) ** 2 + ((Y - 0.5 * ly) / (0.25 * ly)) ** 2
                     + ((Z - 0.5 * lz) / (0.2 * lz)) ** 2)
         pool = _smooth_step(0.25 * lx * (1.0 - e), w)
         a2 = ac * pool
@@ -329,7 +352,14 @@ def phase_fields(c) -> dict:
     else:
         raise ValueError(f"unknown phase layout {lay}")
     f = lambda q: np.ascontiguousarray(np.broadcast_to(q, s["cell"]).reshape(s["cell"]), dtype=np.float64)
-    return dict(alpha=f(a2), alpha3=f(a3))
+    if lay == "absent4":  # the lens of three phases with a fourth of zero fraction
+        out = phase_fields(dict(c, phase_layout="lens"))
+        out["alpha4"] = np.zeros_like(out["alpha"])
+        return out
+    out = dict(alpha=f(a2), alpha3=f(a3))
+    if lay == "layers4":
+        out["alpha4"] = f(a4)
+    return out
 
 
 def phase_state(c) -> dict:

@@ -42,7 +42,10 @@ class TcfConfig(C.Structure):
                 ("p_rtol", C.c_double), ("p_maxit", C.c_int), ("inner_rtol", C.c_double),
                 ("refine_maxit", C.c_int), ("mg_levels", C.c_int), ("mg_nu", C.c_int),
                 ("species", C.c_int), ("dsigma_dc", C.c_double), ("c0", C.c_double),
-                ("integrator", C.c_int)]
+                ("integrator", C.c_int),
+                ("nphases", C.c_int), ("rho34", C.c_double * 2), ("mu34", C.c_double * 2),
+                ("rhocp34", C.c_double * 2), ("lambda34", C.c_double * 2),
+                ("pair_sigma0", C.c_double * 6), ("pair_dsigma_dT", C.c_double * 6)]
 
 
 class TcfStepInfo(C.Structure):
@@ -55,7 +58,7 @@ class TcfStepInfo(C.Structure):
 
 
 EXPORTS = ["tcf_workspace_bytes", "tcf_init_grid", "tcf_set_fields", "tcf_get_fields", "tcf_set_species",
-           "tcf_get_species", "tcf_step",
+           "tcf_get_species", "tcf_set_phases", "tcf_get_phases", "tcf_step",
            "tcf_solve_pressure", "tcf_predictor", "tcf_apply_A", "tcf_step_backward", "tcf_adjoint_transport",
            "tcf_adjoint_predictor", "tcf_profile", "tcf_profile_read", "tcf_destroy", "tcf_last_error"]
 
@@ -84,6 +87,10 @@ def load():
     lib.tcf_set_species.argtypes = [vp, vp]
     lib.tcf_get_species.restype = st
     lib.tcf_get_species.argtypes = [vp, vp]
+    lib.tcf_set_phases.restype = C.c_int
+    lib.tcf_set_phases.argtypes = [vp, vp, vp]
+    lib.tcf_get_phases.restype = C.c_int
+    lib.tcf_get_phases.argtypes = [vp, vp, vp]
     lib.tcf_step.restype = st
     lib.tcf_step.argtypes = [vp, C.c_double, C.c_int, C.POINTER(TcfStepInfo)]
     lib.tcf_solve_pressure.restype = st
@@ -133,6 +140,13 @@ def make_config(c: dict, precision=None, flags=None) -> TcfConfig:
     o.species = int(c.get("species", 0))
     o.dsigma_dc, o.c0 = float(c.get("dsigma_dc", 0.0)), float(c.get("c0", 0.0))
     o.integrator = int(c.get("integrator", 0))
+    o.nphases = int(c.get("nphases", 0))
+    for q, ph in enumerate(c.get("phases", [])[:2]):  # phases 3 and 4
+        o.rho34[q], o.mu34[q] = ph["rho"], ph["mu"]
+        o.rhocp34[q], o.lambda34[q] = ph["rhocp"], ph["lambda"]
+    for q in range(6):  # pairs (1,2), (1,3), (1,4), (2,3), (2,4), (3,4)
+        o.pair_sigma0[q] = float(c.get("pair_sigma0", [0.0] * 6)[q])
+        o.pair_dsigma_dT[q] = float(c.get("pair_dsigma_dT", [0.0] * 6)[q])
     return o
 
 
@@ -195,6 +209,23 @@ class Grid:
         self.set_fields(t, st["alpha"], st["T"], st["u"], st["v"], st.get("w"), st.get("p"))
         if st.get("c") is not None:
             self.set_species(st["c"])
+        if st.get("alpha3") is not None:
+            self.set_phases(st["alpha3"], st.get("alpha4"))
+
+    def set_phases(self, a3, a4=None):
+        """Fractions of phases 3 (and 4) of an N-phase grid."""
+        t3 = self._t(a3)
+        t4 = None if a4 is None else self._t(a4)
+        self._keep_ph = (t3, t4)
+        _check(load().tcf_set_phases(self.h, _ptr(t3), _ptr(t4)))
+
+    def get_phases(self):
+        """(alpha3, alpha4 or None) of an N-phase grid."""
+        shp = self.shapes["cell"]
+        a3 = torch.empty(shp, dtype=torch.float64, device=self.device)
+        a4 = torch.empty(shp, dtype=torch.float64, device=self.device) if self.c.get("nphases", 0) == 4 else None
+        _check(load().tcf_get_phases(self.h, _ptr(a3), _ptr(a4)))
+        return a3, a4
 
     def set_species(self, c):
         ct = self._t(c)

@@ -110,6 +110,39 @@ def test_time_accurate_integrator_workspace_and_validation():
     assert tcf.workspace_bytes(dict(c, integrator=0), precision=0, flags=tcf.TCF_WITH_ADJOINT) > 0
 
 
+def test_nphase_workspace_and_validation():
+    """N phases add the extra fractions with their RK3 stages, the mixture,
+    per-pair sigma*kappa and the face force; nphases must be 0, 2, 3 or 4,
+    phase materials physical, and N phases exclude species, integrator 1 and
+    the adjoint."""
+    c = I.config(3)
+    N = c["nx"] * c["ny"] * c["nz"]
+    c3 = I.droplet_phases(c, "lens")
+    c4 = I.droplet_phases4(c, "layers4")
+    b2 = tcf.workspace_bytes(c, precision=0)
+    b3 = tcf.workspace_bytes(c3, precision=0)
+    b4 = tcf.workspace_bytes(c4, precision=0)
+    assert b3 - b2 >= (3 + 6 + 3 + 3) * 8 * N
+    assert b4 - b3 >= (3 + 3) * 8 * N
+    assert tcf.workspace_bytes(c3, precision=1) - tcf.workspace_bytes(c, precision=1) >= (3 + 6 + 3 + 3) * 4 * N
+    assert tcf.workspace_bytes(dict(c3, nphases=5)) == 0
+    assert tcf.workspace_bytes(dict(c3, nphases=1)) == 0
+    bad = dict(c3, phases=[dict(c3["phases"][0], rho=-1.0)])
+    assert tcf.workspace_bytes(bad) == 0
+    nan_pair = dict(c3, pair_sigma0=[float("nan")] + c3["pair_sigma0"][1:])
+    assert tcf.workspace_bytes(nan_pair) == 0
+    assert tcf.workspace_bytes(dict(c3, integrator=1)) == 0
+    assert tcf.workspace_bytes(I.with_species(c3, -0.1)) == 0
+    assert tcf.workspace_bytes(c3, precision=0, flags=tcf.TCF_WITH_ADJOINT) == 0
+    assert tcf.workspace_bytes(dict(c, nphases=2)) == b2
+
+
+def test_phase_entry_points_reject_null():
+    lib = tcf.load()
+    assert lib.tcf_set_phases(None, None, None) == tcf.TCF_E_INVALID
+    assert lib.tcf_get_phases(None, None, None) == tcf.TCF_E_INVALID
+
+
 def test_species_entry_points_reject_null():
     lib = tcf.load()
     assert lib.tcf_set_species(None, None) == tcf.TCF_E_INVALID

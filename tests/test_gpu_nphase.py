@@ -1,0 +1,178 @@
+"""The N-phase model (three or four phases: fractions carried by eq. 1,
+mixture material laws, per-pair surface tension) on the HIP path, through the
+C ABI, against the FP64 oracle on the same seeded inputs.
+
+Bars as for the two-phase step: single operators (the predictor with its
+geometry and face force) <= 1e-12 per-field relative L2; FP64 full steps <=
+1e-10 after one step and <= 1e-8 after many (p mean-free); the melt pool in
+FP64 <= 1e-9; FP32 + FP64 refinement keeps the divergence residual <= 1e-8
+with every fraction and T within 1e-6 of the FP64 oracle.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import pyoracle as O
+from paper_2209_09671_amd import inputs as I
+from paper_2209_09671_amd import tcf
+
+pytestmark = pytest.mark.gpu
+
+KEYS = ("alpha", "alpha3", "alpha4", "T", "u", "v", "w", "p")
+
+
+def rel(a, b):
+    a, b = np.ravel(a), np.ravel(b)
+    nb = np.linalg.norm(b)
+    return float(np.linalg.norm(a - b) / nb) if nb > 0 else float(np.linalg.norm(a - b))
+
+
+def errors(g, o, keys=KEYS):
+    e = {}
+    for k in keys:
+        if g.get(k) is None or o.get(k) is None:
+            continue
+        x, y = g[k], o[k]
+        if k == "p":
+            x, y = x - x.mean(), y - y.mean()
+        e[k] = rel(x, y)
+    return e
+
+
+def host(d):
+    torch.cuda.synchronize()
+    return {k: (v.cpu().numpy() if torch.is_tensor(v) else v) for k, v in d.items()}
+
+
+def gpu_run(c, st, dt, nsteps, precision=0, flags=0):
+    print(f"[gpu] nphase {c.get('phase_layout')} N={c.get('nphases')} {c['nx']}x{c['ny']}x{c['nz']} "
+          f"prec={precision} steps={nsteps}", flush=True)
+    g = tcf.Grid(c, precision=precision, flags=flags)
+    g.set_state(st)
+    info = g.step(dt, nsteps, check=False)
+    out = g.get_fields()
+    if c.get("nphases", 0) > 2:
+        out["alpha3"], out["alpha4"] = g.get_phases()
+    out = host(out)
+    g.close()
+    return out, info
+
+
+def lens_2d():
+    return I.droplet_phases(I.config(0), "lens")
+
+
+def layers4_3d():
+    c = I.droplet_phases4(I.custom(I.config(3), nx=32, ny=28, nz=36), "layers4")
+    c["T_bc"] = [0] * 6
+    return c
+
+
+def x_ramp(c):
+    """T = x: a temperature gradient along the layers (Marangoni flow)."""
+    x = (np.arange(c["nx"]) + 0.5) * c["h"]
+    return np.ascontiguousarray(np.broadcast_to(x, (c["nz"], c["ny"], c["nx"])), dtype=np.float64)
+
+
+@pytest.mark.parametrize("make", [lens_2d, layers4_3d])
+def test_nphase_predictor_matches_oracle(make):
+    c = make()
+    st = I.phase_state(c)
+    st["T"] = x_ramp(c)
+    st["u"], st["v"], st["w"] = I.stream_velocity(c, 0.2)
+    print(f"[gpu] nphase predictor {c['phase_layout']}", flush=True)
+    g = tcf.Grid(c)
+    g.set_state(st)
+    us, vs, ws = g.predictor(c["dt"])
+    got = host(dict(u=us, v=vs, w=ws))
+    g.close()
+    ref = O.predictor(c, c["dt"], st["alpha"], st["T"], st["u"], st["v"], st["w"], alpha3=st["alpha3"],
+                      alpha4=st.get("alpha4"))
+    for k, r in zip(("u", "v", "w"), ref):
+        if r is not None:
+            assert rel(got[k], r) <= 1e-12, (k, rel(got[k], r))
+
+
+@pytest.mark.parametrize("nsteps,tol", [(1, 1e-10), (20, 1e-8)])
+def test_nphase_lens_2d_matches_oracle(nsteps, tol):
+    c = lens_2d()
+    st = I.phase_state(c)
+    g, info = gpu_run(c, st, c["dt"], nsteps)
+    o, _, status = O.step(c, st, 0.0, c["dt"], nsteps)
+    assert info["status"] == 0 and status == 0, info
+    e = errors(g, o)
+    assert max(e.values()) <= tol, e
+    assert abs(g["alpha3"].sum() - st["alpha3"].sum()) <= 1e-12 * st["alpha3"].sum()
+
+
+def test_four_phases_3d_matches_oracle():
+    """Four flat layers in 3D driven by T = x: the flow lies in the x-z
+    plane, so v vanishes in exact arithmetic (only solver residue is left in
+    it); the velocity is compared as one field."""
+    c = layers4_3d()
+    st = I.phase_state(c)
+    st["T"] = x_ramp(c)
+    g, info = gpu_run(c, st, c["dt"], 2)
+    o, _, status = O.step(c, st, 0.0, c["dt"], 2)
+    assert info["status"] == 0 and status == 0, info
+    e = errors(g, o, ("alpha", "alpha3", "alpha4", "T", "p"))
+    vel = lambda d: np.concatenate([d["u"].ravel(), d["v"].ravel(), d["w"].ravel()])
+    e["velocity"] = rel(vel(g), vel(o))
+    assert max(e.values()) <= 1e-10, e
+    assert np.abs(g["u"]).max() > 1e-6  # the layers move
+
+
+def test_absent_third_phase_matches_two_phase_gpu():
+    c = I.config(0)
+    st = I.initial_state(c)
+    g2, _ = gpu_run(c, st, c["dt"], 5)
+    cn = I.droplet_phases(c, "absent")
+    gn, _ = gpu_run(cn, I.phase_state(cn), c["dt"], 5)
+    for k in ("alpha", "T", "u", "v", "p"):
+        x, y = (gn[k] - gn[k].mean(), g2[k] - g2[k].mean()) if k == "p" else (gn[k], g2[k])
+        assert rel(x, y) <= 1e-10, k
+    assert np.array_equal(gn["alpha3"], np.zeros_like(gn["alpha3"]))
+
+
+def test_meltpool_three_phases_fp64_matches_oracle():
+    """Gas, a liquid pool and solid metal at 7500:1 with the moving heat
+    source (at the condensed-phase boundary) and thermal Marangoni on the
+    gas-liquid pair."""
+    c = I.meltpool_phases(I.custom(I.config(2), nx=48, ny=24, nz=24))
+    st = I.phase_state(c)
+    g, info = gpu_run(c, st, 1e-8, 2)
+    o, _, status = O.step(c, st, 0.0, 1e-8, 2)
+    assert info["status"] == 0 and status == 0, info
+    e = errors(g, o)
+    assert max(e.values()) <= 1e-9, e
+
+
+def test_meltpool_three_phases_fp32_refined():
+    c = I.meltpool_phases(I.custom(I.config(2), nx=64, ny=32, nz=32))
+    c["p_rtol"] = 1e-8
+    st = I.phase_state(c)
+    g, info = gpu_run(c, st, 1e-8, 2, precision=1)
+    o, _, _ = O.step(c, st, 0.0, 1e-8, 2, rtol=1e-12)
+    assert info["status"] == 0, info
+    assert info["div_rel"] <= 1e-8
+    e = errors(g, o, ("alpha", "alpha3", "T"))
+    assert max(e.values()) <= 1e-6, e
+
+
+def test_nphase_state_errors():
+    c = lens_2d()
+    g = tcf.Grid(c, precision=0)
+    g.set_state(I.initial_state(c))  # no phase fractions yet
+    with pytest.raises(tcf.TcfError) as ei:
+        g.step(c["dt"], 1)
+    assert ei.value.status == tcf.TCF_E_STATE
+    with pytest.raises(tcf.TcfError) as ei:
+        g.get_phases()
+    assert ei.value.status == tcf.TCF_E_STATE
+    g.close()
+    g = tcf.Grid(I.config(0), precision=0)
+    z = torch.zeros((1, 64, 64), dtype=torch.float64, device="cuda")
+    with pytest.raises(tcf.TcfError) as ei:
+        g.set_phases(z)
+    assert ei.value.status == tcf.TCF_E_STATE
+    g.close()

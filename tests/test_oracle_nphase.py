@@ -145,6 +145,39 @@ def test_every_phase_is_conserved():
     assert not np.array_equal(out["alpha3"], st["alpha3"])
 
 
+def test_absent_fourth_phase_changes_nothing():
+    """Four phases with phase 4 of zero fraction: the three-phase step."""
+    c = I.config(0)
+    c3 = I.droplet_phases(c, "lens")
+    c4 = I.droplet_phases4(c, "absent4")
+    for q in ((1, 2), (1, 3), (2, 3)):  # same tensions for the three pairs that act
+        k = I.PAIRS.index(q)
+        c4["pair_sigma0"][k], c4["pair_dsigma_dT"][k] = c3["pair_sigma0"][k], c3["pair_dsigma_dT"][k]
+    s3 = I.phase_state(c3)
+    s4 = I.phase_state(c4)
+    ref, _, st3 = O.step(c3, s3, 0.0, c["dt"], 5)
+    out, _, st4 = O.step(c4, s4, 0.0, c["dt"], 5)
+    assert st3 == st4 == 0
+    for k in FIELDS + ("alpha3",):
+        assert rel(out[k], ref[k]) <= 1e-12, k
+    assert np.array_equal(out["alpha4"], np.zeros_like(out["alpha4"]))
+
+
+def test_four_flat_layers_at_uniform_temperature_stay_at_rest():
+    c = I.custom(I.config(0), nx=48, ny=48)
+    c["T_bc"] = [0] * 6
+    cn = I.droplet_phases4(c, "layers4")
+    st = I.phase_state(cn)
+    st["T"] = np.full_like(st["T"], 0.3)
+    _, vs, _ = O.predictor(cn, c["dt"], st["alpha"], st["T"], st["u"], st["v"], alpha3=st["alpha3"],
+                           alpha4=st["alpha4"])
+    out, info, status = O.step(cn, st, 0.0, c["dt"], 1, rtol=1e-12)
+    assert status == 0
+    assert np.abs(vs).max() > 0
+    assert np.abs(out["u"]).max() <= 1e-10 * np.abs(vs).max()
+    assert np.abs(out["v"]).max() <= 1e-10 * np.abs(vs).max()
+
+
 def test_undefined_combinations_are_refused():
     c = I.droplet_phases(I.config(0), "lens")
     st = I.phase_state(c)
