@@ -358,8 +358,8 @@ size_t carve(const tcf_config* c, void* base, tcf_grid* g) {
   }
   double* pbase = cv.take<double>(6L * nb);  // contiguous: diagnostics write 6 strided arrays
   for (int k = 0; k < 6; ++k) G->part[k] = pbase ? pbase + (long)k * nb : nullptr;
-  G->scal = cv.take<double>(S_NSLOT);
-  G->iflag = cv.take<int>(I_NFLAG);
+  G->scal = cv.take<double>(S_NSLOT + (I_NFLAG * sizeof(int) + sizeof(double) - 1) / sizeof(double));
+  G->iflag = G->scal ? (int*)(G->scal + S_NSLOT) : nullptr;  // flags follow the scalars (one read-back)
   return cv.off + kAlign;
 }
 
@@ -457,10 +457,12 @@ KParams make_params(const tcf_config* c) {
   return P;
 }
 
+// The scalar block and the flags are one device block (flags after the
+// S_NSLOT doubles) mirrored by one pinned host block: one copy per read.
+constexpr size_t kScalBlockBytes = sizeof(double) * S_NSLOT + sizeof(int) * I_NFLAG;
+
 hipError_t read_back(tcf_grid* g) {
-  hipError_t e = hipMemcpyAsync(g->hscal, g->scal, sizeof(double) * S_NSLOT, hipMemcpyDeviceToHost, g->stream);
-  if (e != hipSuccess) return e;
-  e = hipMemcpyAsync(g->hflag, g->iflag, sizeof(int) * I_NFLAG, hipMemcpyDeviceToHost, g->stream);
+  hipError_t e = hipMemcpyAsync(g->hscal, g->scal, kScalBlockBytes, hipMemcpyDeviceToHost, g->stream);
   if (e != hipSuccess) return e;
   return hipStreamSynchronize(g->stream);
 }
@@ -706,13 +708,12 @@ tcf_status solve_refined(tcf_grid* g, double* p, int* iters, int* nref, double* 
     }
     if (ref >= g->cfg.refine_maxit) break;
     // inner solve of K e = r64 / scale in FP32 from e = 0
-    scale_to32(s, N, g->r64, g->scal, F.r);
+    scale_to32(s, N, g->r64, g->scal, F.r, g->part[0]);  // with the partials of |r32|^2
     fill<float>(s, N, F.x, 0.0);
     init_flags(s, g->iflag);
     // reduce the scaled residual only as far as this sweep needs to reach
     // the FP64 target (never below inner_rtol)
     const double tau = std::min(0.5, std::max(irt, 0.5 * rt * std::sqrt(bb / rr)));
-    dot_partials<float>(s, N, F.r, F.r, g->part[0]);
     finalize(s, g->part[0], nb1, g->scal, g->iflag, F_BB, 0, tau * tau);
     int it = 0;
     bool conv = false;
@@ -1202,11 +1203,11 @@ tcf_status tcf_init_grid(const tcf_config* cfg, void* workspace, size_t bytes, v
   g->fp32 = cfg->precision == TCF_FP32_REFINE;
   g->bytes = bytes;
   carve(&g->cfg, workspace, g);
-  if (hipHostMalloc((void**)&g->hscal, sizeof(double) * S_NSLOT, hipHostMallocDefault) != hipSuccess ||
-      hipHostMalloc((void**)&g->hflag, sizeof(int) * I_NFLAG, hipHostMallocDefault) != hipSuccess) {
+  if (hipHostMalloc((void**)&g->hscal, kScalBlockBytes, hipHostMallocDefault) != hipSuccess) {
     delete g;
     return fail(TCF_E_DEVICE, "pinned host buffer allocation failed");
   }
+  g->hflag = (int*)(g->hscal + S_NSLOT);
   // zero scalars and flags, the zero vector, and the pressure
   fill_f64(g->stream, S_NSLOT, g->scal, 0.0);
   init_flags(g->stream, g->iflag);
@@ -1215,7 +1216,6 @@ tcf_status tcf_init_grid(const tcf_config* cfg, void* workspace, size_t bytes, v
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) {
     hipHostFree(g->hscal);
-    hipHostFree(g->hflag);
     delete g;
     return fail(TCF_E_DEVICE, std::string("init kernels: ") + hipGetErrorString(e));
   }
@@ -1428,7 +1428,6 @@ void tcf_destroy(tcf_grid* g) {
   hipStreamSynchronize(g->stream);
   for (hipEvent_t e : g->prof_ev) hipEventDestroy(e);
   hipHostFree(g->hscal);
-  hipHostFree(g->hflag);
   delete g;
 }
 

@@ -149,7 +149,8 @@ void finalize(hipStream_t s, const double* part, int nparts, double* scal, int* 
 void init_flags(hipStream_t s, int* iflag);
 
 // FP64 refinement helpers (FP32 mode)
-void scale_to32(hipStream_t s, long n, const double* r, const double* scal, float* r32);
+// r32 = r / scal[S_SCALE]; part: nblocks(256) partials of |r32|^2
+void scale_to32(hipStream_t s, long n, const double* r, const double* scal, float* r32, double* part);
 void add_scaled(hipStream_t s, long n, const float* e, const double* scal, double* p);
 void subtract_mean(hipStream_t s, long n, const double* scal, int slot, double* p);
 int sum64_partials(hipStream_t s, long n, const double* x, double* part);

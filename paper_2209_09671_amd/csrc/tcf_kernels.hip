@@ -690,10 +690,20 @@ __global__ __launch_bounds__(256) void k_coarsen_a(KParams P, const R* __restric
   cf[fidx<D>(I, J, K, cnx, cny)] = s;
 }
 
+// r32 = r / scale in FP32, and per-block partials of |r32|^2 (FP64)
 __global__ __launch_bounds__(256) void k_scale_to32(long n, const double* __restrict__ r,
-                                                    const double* __restrict__ scal, float* __restrict__ r32) {
+                                                    const double* __restrict__ scal, float* __restrict__ r32,
+                                                    double* __restrict__ part) {
+  __shared__ double sh[8];
   const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c < n) r32[c] = (float)(r[c] / scal[S_SCALE]);
+  double v = 0.0;
+  if (c < n) {
+    const float q = (float)(r[c] / scal[S_SCALE]);
+    r32[c] = q;
+    v = (double)q * (double)q;
+  }
+  const double sm = block_reduce<0>(v, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = sm;
 }
 __global__ __launch_bounds__(256) void k_add_scaled(long n, const float* __restrict__ e,
                                                     const double* __restrict__ scal, double* __restrict__ p) {
@@ -1074,8 +1084,8 @@ void coarsen_from_alpha(const KParams& P, hipStream_t s, const R* a, const Level
   }
 }
 
-void scale_to32(hipStream_t s, long n, const double* r, const double* scal, float* r32) {
-  hipLaunchKernelGGL(k_scale_to32, dim3(nblk1(n)), dim3(256), 0, s, n, r, scal, r32);
+void scale_to32(hipStream_t s, long n, const double* r, const double* scal, float* r32, double* part) {
+  hipLaunchKernelGGL(k_scale_to32, dim3(nblk1(n)), dim3(256), 0, s, n, r, scal, r32, part);
 }
 void add_scaled(hipStream_t s, long n, const float* e, const double* scal, double* p) {
   hipLaunchKernelGGL(k_add_scaled, dim3(nblk1(n)), dim3(256), 0, s, n, e, scal, p);
