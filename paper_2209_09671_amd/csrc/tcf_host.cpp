@@ -62,8 +62,9 @@ struct Fields {
   // operator's range, the condensed fraction 1 - alpha_1); per-pair
   // sigma*kappa; the face CSF force
   R *p3 = nullptr, *p31 = nullptr, *p32 = nullptr, *p4 = nullptr, *p41 = nullptr, *p42 = nullptr;
-  R *mrho = nullptr, *mmu = nullptr, *mrcp = nullptr, *mlam = nullptr, *marho = nullptr, *mac = nullptr;
-  R* skp = nullptr;
+  R *mrho = nullptr, *mmu = nullptr, *mrcp = nullptr, *mlam = nullptr, *marho = nullptr, *mamu = nullptr;
+  R* mac = nullptr;
+  R *skp = nullptr, *nrm = nullptr, *dsp = nullptr;  // per pair: sigma*kappa; normals and delta (scratch)
   R *fx = nullptr, *fy = nullptr, *fz = nullptr;
   R *sk, *Mx, *My, *Mz;                    // sigma*kappa, Marangoni vector
   R *us, *vs, *ws;                         // predictor
@@ -216,8 +217,12 @@ void carve_fields(Carver& cv, const Dims& D, Fields<R>& F, int mg_levels, bool a
     F.mrcp = cv.take<R>(N);
     F.mlam = cv.take<R>(N);
     F.marho = cv.take<R>(N);
+    F.mamu = cv.take<R>(N);
     F.mac = cv.take<R>(N);
-    F.skp = cv.take<R>((nph == 4 ? 6 : 3) * N);
+    const int npair = nph == 4 ? 6 : 3;
+    F.skp = cv.take<R>(npair * N);
+    F.nrm = cv.take<R>(3L * npair * N);
+    F.dsp = cv.take<R>(npair * N);
     F.fx = cv.take<R>(D.Nu);
     F.fy = cv.take<R>(D.Nv);
     F.fz = D.dim == 3 ? cv.take<R>(D.Nw) : nullptr;
@@ -780,27 +785,31 @@ tcf_status solve(tcf_grid* g, double* p, tcf_step_info* inf) {
 template <class R>
 tcf_status step_diag(tcf_grid* g, double dt, double dt_proj, tcf_step_info* inf);
 
-// N-phase model: a density range that holds every mixture rho_1 + sum_j
-// clamp(alpha_j)(rho_j - rho_1), so that the pressure operator's linear mix
-// of the density fraction never clamps.
-void np_rho_range(const tcf_grid* g, double* lo, double* hi) {
+// N-phase model: a range of material `which` (0 density, 1 viscosity) that
+// holds every mixture P_1 + sum_j clamp(alpha_j)(P_j - P_1), so that the
+// linear mix of its fraction in the pressure kernels and the predictor
+// never clamps.
+void np_range(const tcf_grid* g, int which, double* lo, double* hi) {
   const KParams& P = g->P;
-  double l = P.rho1 + std::min(0.0, P.rho2 - P.rho1), h = P.rho1 + std::max(0.0, P.rho2 - P.rho1);
+  const double p1 = which == 0 ? P.rho1 : P.mu1, p2 = which == 0 ? P.rho2 : P.mu2;
+  double l = p1 + std::min(0.0, p2 - p1), h = p1 + std::max(0.0, p2 - p1);
   for (int q = 0; q < g->nph - 2; ++q) {
-    l += std::min(0.0, P.mat34[0][q] - P.rho1);
-    h += std::max(0.0, P.mat34[0][q] - P.rho1);
+    l += std::min(0.0, P.mat34[which][q] - p1);
+    h += std::max(0.0, P.mat34[which][q] - p1);
   }
   *lo = l;
-  *hi = h > l ? h : l + 1.0;  // equal densities: every fraction is 0
+  *hi = h > l ? h : l + 1.0;  // equal values: every fraction is 0
 }
+void np_rho_range(const tcf_grid* g, double* lo, double* hi) { np_range(g, 0, lo, hi); }
 
 // Mixture of the given fractions (N-phase fields of F).
 template <class R>
 void np_mix(tcf_grid* g, const R* a2, const R* a3, const R* a4) {
   Fields<R>& F = fields<R>(g);
-  double lo, hi;
-  np_rho_range(g, &lo, &hi);
-  np_mixture<R>(g->P, g->stream, a2, a3, a4, F.mrho, F.mmu, F.mrcp, F.mlam, F.marho, F.mac, lo, hi);
+  double lo, hi, mlo, mhi;
+  np_range(g, 0, &lo, &hi);
+  np_range(g, 1, &mlo, &mhi);
+  np_mixture<R>(g->P, g->stream, a2, a3, a4, F.mrho, F.mmu, F.mrcp, F.mlam, F.marho, F.mamu, F.mac, lo, hi, mlo, mhi);
 }
 
 // S2-S5 of the N-phase model at the state fractions: mixture, per-pair
@@ -812,11 +821,16 @@ void np_momentum_rhs(tcf_grid* g, const KParams& P) {
   np_mix<R>(g, F.a, F.p3, F.p4);
   {
     Prof pr(g, FAM_GEOMETRY);
-    np_geometry<R>(P, s, F.a, F.p3, F.p4, F.T, F.skp, F.Mx, F.My, F.Mz);
+    np_geometry<R>(P, s, F.a, F.p3, F.p4, F.T, F.nrm, F.dsp, F.skp, F.Mx, F.My, F.Mz);
     np_face_force<R>(P, s, F.a, F.p3, F.p4, F.skp, F.Mx, F.My, F.Mz, F.fx, F.fy, F.fz);
   }
+  // the predictor in its material form: viscosity and density fractions
+  // of their ranges, and the face force
+  KParams Pm = P;
+  np_range(g, 0, &Pm.rho1, &Pm.rho2);
+  np_range(g, 1, &Pm.mu1, &Pm.mu2);
   Prof pr(g, FAM_PREDICTOR);
-  np_predictor<R>(P, s, F.mrho, F.mmu, F.fx, F.fy, F.fz, F.u, F.v, F.w, F.us, F.vs, F.ws);
+  predictor_mat<R>(Pm, s, F.mamu, F.marho, F.fx, F.fy, F.fz, F.u, F.v, F.w, F.us, F.vs, F.ws);
 }
 
 // The pressure operator of the current state: the two-phase mix of alpha,

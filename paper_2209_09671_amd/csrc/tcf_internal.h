@@ -190,23 +190,27 @@ void adj_axpy(hipStream_t s, long n, double f, const double* x, double* y);
 void adj_add_scalar(hipStream_t s, double* dst, const double* src);
 
 // N-phase model (tcf_nphase.hip).  Mixture per cell from the fractions of
-// phases 2..N (rho, mu, rho c_p, lambda; the density as the fraction of
-// [rlo, rhi]; the condensed fraction 1 - alpha_1); per-pair sigma*kappa
-// (pair-major) and the summed Marangoni vector; the face CSF force; the
-// momentum predictor from the mixture; one temperature RK3 stage with the
-// mixture's conductivity and heat capacity.  a4 = NULL with three phases.
+// phases 2..N (rho, mu, rho c_p, lambda; the density and the viscosity as
+// fractions of [rlo, rhi] and [mlo, mhi]; the condensed fraction
+// 1 - alpha_1); per-pair sigma*kappa (pair-major) and the summed Marangoni
+// vector; the face CSF force; one temperature RK3 stage with the mixture's
+// conductivity and heat capacity.  a4 = NULL with three phases.
 template <class R>
 void np_mixture(const KParams& P, hipStream_t s, const R* a2, const R* a3, const R* a4, R* rho, R* mu, R* rcp,
-                R* lam, R* arho, R* ac, double rlo, double rhi);
+                R* lam, R* arho, R* amu, R* ac, double rlo, double rhi, double mlo, double mhi);
+// (nrm: 3 N per pair, dsp: N per pair; scratch of the two geometry passes)
 template <class R>
-void np_geometry(const KParams& P, hipStream_t s, const R* a2, const R* a3, const R* a4, const R* T, R* skp, R* Mx,
-                 R* My, R* Mz);
+void np_geometry(const KParams& P, hipStream_t s, const R* a2, const R* a3, const R* a4, const R* T, R* nrm, R* dsp,
+                 R* skp, R* Mx, R* My, R* Mz);
 template <class R>
 void np_face_force(const KParams& P, hipStream_t s, const R* a2, const R* a3, const R* a4, const R* skp, const R* Mx,
                    const R* My, const R* Mz, R* fx, R* fy, R* fz);
+// the predictor in its material form: amu the viscosity as a fraction of
+// [P.mu1, P.mu2], arho the density as a fraction of [P.rho1, P.rho2], and
+// the face CSF force fx, fy, fz on the faces
 template <class R>
-void np_predictor(const KParams& P, hipStream_t s, const R* rho, const R* mu, const R* fx, const R* fy, const R* fz,
-                  const R* u, const R* v, const R* w, R* us, R* vs, R* ws);
+void predictor_mat(const KParams& P, hipStream_t s, const R* amu, const R* arho, const R* fx, const R* fy,
+                   const R* fz, const R* u, const R* v, const R* w, R* us, R* vs, R* ws);
 template <class R>
 void np_tstage(const KParams& P, hipStream_t s, const R* T, const R* Tb, const R* u, const R* v, const R* w,
                const R* lam, const R* rcp, const R* ac, R* To, double cb, double ci);

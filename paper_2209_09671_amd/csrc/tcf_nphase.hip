@@ -5,9 +5,10 @@
 // of the two-phase path.  These kernels produce what the two-phase kernels
 // take from alpha alone: the mixture (material laws linear in each clamped
 // fraction relative to phase 1), the per-pair interface geometry and CSF
-// force, the momentum predictor from the mixture, and the temperature stage
-// with the mixture's conductivity and heat capacity.  Each surface-tension
-// pair i < j acts through its pair gradient g_ij = alpha_i grad alpha_j -
+// force, and the temperature stage with the mixture's conductivity and heat
+// capacity (the momentum predictor is the two-phase kernel in its material
+// form, fed the mixture's viscosity and density and this face force).  Each
+// surface-tension pair i < j acts through its pair gradient g_ij = alpha_i grad alpha_j -
 // alpha_j grad alpha_i (grad alpha for two phases) with the curvature and
 // Marangoni terms of eqs. 4-7.  One thread per cell or face on 64 x 4
 // blocks; ghost values by reflected indexing as in the two-phase kernels.
@@ -64,15 +65,15 @@ __device__ __forceinline__ R ph_at(const Phases<R>& F, int q, int i, int j, int 
 
 // ---------------------------------------------------------------------------
 // Mixture per cell: rho, mu, rho c_p, lambda = P_1 + sum_j clamp(alpha_j)
-// (P_j - P_1) (FP64, then stored in R); the density as the fraction
-// (rho - rlo) / (rhi - rlo) of a range that holds every mixture, which the
-// pressure kernels' linear mix turns back into rho; the condensed fraction
-// 1 - alpha_1.
+// (P_j - P_1) (FP64, then stored in R); the density and the viscosity as
+// fractions (P - lo) / (hi - lo) of ranges that hold every mixture, which
+// the linear mixes of the pressure kernels and the predictor turn back
+// into rho and mu; the condensed fraction 1 - alpha_1.
 template <class R, int NPH>
 __global__ __launch_bounds__(256) void k_np_mixture(KParams P, long n, Phases<R> F, R* __restrict__ rho,
                                                     R* __restrict__ mu, R* __restrict__ rcp, R* __restrict__ lam,
-                                                    R* __restrict__ arho, R* __restrict__ ac, double rlo,
-                                                    double rhi) {
+                                                    R* __restrict__ arho, R* __restrict__ amu, R* __restrict__ ac,
+                                                    double rlo, double rhi, double mlo, double mhi) {
   const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= n) return;
   auto cl = [](double v) { return v < 0.0 ? 0.0 : (v > 1.0 ? 1.0 : v); };
@@ -91,14 +92,18 @@ __global__ __launch_bounds__(256) void k_np_mixture(KParams P, long n, Phases<R>
   rcp[c] = R(m[2]);
   lam[c] = R(m[3]);
   arho[c] = R((m[0] - rlo) / (rhi - rlo));
+  amu[c] = R((m[1] - mlo) / (mhi - mlo));
   double s = a2 + a3;
   if (NPH == 4) s += a4;
   ac[c] = R(1.0 - (1.0 - s));
 }
 
 // ---------------------------------------------------------------------------
-// Geometry per interior cell: for each pair, sigma_ij kappa_ij into skp
-// (pair-major) and the Marangoni vector summed over the pairs into M.
+// Geometry per interior cell in two passes: for each pair, the pair
+// gradient g = alpha_i grad alpha_j - alpha_j grad alpha_i (central
+// differences of the phases, even ghosts) and from it the normal and delta;
+// then sigma_ij kappa_ij (pair-major) and the Marangoni vector summed over
+// the pairs.
 template <class R, int DIM, int NPH>
 __device__ __forceinline__ void pair_grad(const Phases<R>& F, int I, int J, int i, int j, int k, int nx, int ny,
                                           int nz, R ih2, R g[3]) {
@@ -112,49 +117,59 @@ __device__ __forceinline__ void pair_grad(const Phases<R>& F, int I, int J, int 
   g[2] = DIM == 3 ? ai * d(J, 0, 0, 1) - aj * d(I, 0, 0, 1) : R(0);
 }
 
+// Pass A: per interior cell and pair, the unit normal n = g / |g|_eps
+// (pair-major, three components) and delta = |g|^2 / (|g|_eps + eps).
 template <class R, int DIM, int NPH>
-__global__ __launch_bounds__(256) void k_np_geometry(KParams P, Phases<R> F, const R* __restrict__ T,
-                                                     R* __restrict__ skp, R* __restrict__ Mx, R* __restrict__ My,
-                                                     R* __restrict__ Mz) {
+__global__ __launch_bounds__(256) void k_np_normals(KParams P, Phases<R> F, R* __restrict__ nrm,
+                                                    R* __restrict__ dsp) {
   const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
   const int nx = P.nx, ny = P.ny, nz = P.nz;
   if (i >= nx || j >= ny) return;
   const R ih2 = R(0.5 * P.ih), ne = R(P.neps);
   const long c = cidx(i, j, k, nx, ny);
   const long N = (long)nx * ny * nz;
+  for (int p = 0; p < PairList<NPH>::n; ++p) {
+    R g[3];
+    pair_grad<R, DIM, NPH>(F, PairList<NPH>::I(p), PairList<NPH>::J(p), i, j, k, nx, ny, nz, ih2, g);
+    const R g2 = g[0] * g[0] + g[1] * g[1] + g[2] * g[2];
+    const R ge = sqrt(g2 + ne * ne);
+    nrm[(3 * p + 0) * N + c] = g[0] / ge;
+    nrm[(3 * p + 1) * N + c] = g[1] / ge;
+    nrm[(3 * p + 2) * N + c] = g[2] / ge;
+    dsp[p * N + c] = g2 / (ge + ne);
+  }
+}
+
+// Pass B: per interior cell and pair, kappa = -div n by central differences
+// of the stored normals.  Across a wall the neighbour's normal is the
+// cell's own with the wall-normal component negated: the even reflection of
+// the phases makes the pair gradient of a ghost cell exactly that.  Then
+// sigma_ij kappa_ij into skp and the Marangoni vector summed over the pairs.
+template <class R, int DIM, int NPH>
+__global__ __launch_bounds__(256) void k_np_geometry(KParams P, const R* __restrict__ nrm, const R* __restrict__ dsp,
+                                                     const R* __restrict__ T, R* __restrict__ skp,
+                                                     R* __restrict__ Mx, R* __restrict__ My, R* __restrict__ Mz) {
+  const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
+  const int nx = P.nx, ny = P.ny, nz = P.nz;
+  if (i >= nx || j >= ny) return;
+  const R ih2 = R(0.5 * P.ih);
+  const long c = cidx(i, j, k, nx, ny);
+  const long N = (long)nx * ny * nz, pl = (long)nx * ny;
   const R Tc = T[c];
   const R dT0 = (T_at<DIM>(T, i + 1, j, k, P) - T_at<DIM>(T, i - 1, j, k, P)) * ih2;
   const R dT1 = (T_at<DIM>(T, i, j + 1, k, P) - T_at<DIM>(T, i, j - 1, k, P)) * ih2;
   const R dT2 = DIM == 3 ? (T_at<DIM>(T, i, j, k + 1, P) - T_at<DIM>(T, i, j, k - 1, P)) * ih2 : R(0);
   R M0 = R(0), M1 = R(0), M2 = R(0);
   for (int p = 0; p < PairList<NPH>::n; ++p) {
-    const int I = PairList<NPH>::I(p), J = PairList<NPH>::J(p), sl = PairList<NPH>::slot(p);
-    auto normal = [&](int ii, int jj, int kk, R n[3]) {
-      R g[3];
-      pair_grad<R, DIM, NPH>(F, I, J, ii, jj, kk, nx, ny, nz, ih2, g);
-      const R ge = sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2] + ne * ne);
-      n[0] = g[0] / ge;
-      n[1] = g[1] / ge;
-      n[2] = g[2] / ge;
-    };
-    R np[3], nm[3];
-    normal(i + 1, j, k, np);
-    normal(i - 1, j, k, nm);
-    R divn = (np[0] - nm[0]) * ih2;
-    normal(i, j + 1, k, np);
-    normal(i, j - 1, k, nm);
-    divn += (np[1] - nm[1]) * ih2;
-    if (DIM == 3) {
-      normal(i, j, k + 1, np);
-      normal(i, j, k - 1, nm);
-      divn += (np[2] - nm[2]) * ih2;
-    }
-    R g[3];
-    pair_grad<R, DIM, NPH>(F, I, J, i, j, k, nx, ny, nz, ih2, g);
-    const R g2 = g[0] * g[0] + g[1] * g[1] + g[2] * g[2];
-    const R ge = sqrt(g2 + ne * ne);
-    const R ds = g2 / (ge + ne);
-    const R n0 = g[0] / ge, n1 = g[1] / ge, n2 = g[2] / ge;
+    const int sl = PairList<NPH>::slot(p);
+    const R* nxp = nrm + (3 * p + 0) * N;
+    const R* nyp = nrm + (3 * p + 1) * N;
+    const R* nzp = nrm + (3 * p + 2) * N;
+    const R n0 = nxp[c], n1 = nyp[c], n2 = DIM == 3 ? nzp[c] : R(0);
+    R divn = ((i + 1 < nx ? nxp[c + 1] : -n0) - (i > 0 ? nxp[c - 1] : -n0)) * ih2;
+    divn += ((j + 1 < ny ? nyp[c + nx] : -n1) - (j > 0 ? nyp[c - nx] : -n1)) * ih2;
+    if (DIM == 3) divn += ((k + 1 < nz ? nzp[c + pl] : -n2) - (k > 0 ? nzp[c - pl] : -n2)) * ih2;
+    const R ds = dsp[p * N + c];
     const R sT = R(P.dsigp[sl]);
     const R sigma = R(P.sig0p[sl]) + sT * (Tc - R(P.T0));
     const R gs0 = sT * dT0, gs1 = sT * dT1, gs2 = sT * dT2;
@@ -199,99 +214,6 @@ __global__ __launch_bounds__(256) void k_np_face_force(KParams P, Phases<R> F, c
     fo += R(0.5) * (skp[p * N + cL] + skp[p * N + cR]) * G;
   }
   f[fi] = fo;
-}
-
-// ---------------------------------------------------------------------------
-// Momentum predictor of component D from the mixture: u* = u + dt (-C(u) +
-// (V(u) + f) / rho_f) with the conservative WENO5 convection and the
-// variable-mu stress of the two-phase predictor (mu on edges the mean of
-// four cells, rho_f the mean of two), f the face force above.
-template <class R, int DIM, int D>
-__global__ __launch_bounds__(256) void k_np_predictor(KParams P, const R* __restrict__ rho, const R* __restrict__ mu,
-                                                      const R* __restrict__ f, const R* __restrict__ u,
-                                                      const R* __restrict__ v, const R* __restrict__ w,
-                                                      R* __restrict__ us) {
-  const int nx = P.nx, ny = P.ny, nz = P.nz;
-  const int fnx = nx + (D == 0), fny = ny + (D == 1);
-  const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
-  if (i >= fnx || j >= fny) return;
-  const long fi = (long)i + (long)fnx * ((long)j + (long)fny * k);
-  const int id[3] = {i, j, k};
-  const int nd = D == 0 ? nx : (D == 1 ? ny : nz);
-  if (id[D] == 0 || id[D] == nd) {
-    us[fi] = R(0);
-    return;
-  }
-  const R* vel[3] = {u, v, w};
-  const R h = R(P.h), eps = R(P.weno_eps);
-  auto comp = [&](int C, int ii, int jj, int kk) -> R {
-    if (C == 0) return V_at<0, DIM>(u, ii, jj, kk, nx, ny, nz);
-    if (C == 1) return V_at<1, DIM>(v, ii, jj, kk, nx, ny, nz);
-    return V_at<2, DIM>(w, ii, jj, kk, nx, ny, nz);
-  };
-  auto ud = [&](int oi, int oj, int ok) { return comp(D, i + oi, j + oj, k + ok); };
-  auto mu_at = [&](int ii, int jj, int kk) { return A_at<DIM>(mu, ii, jj, kk, nx, ny, nz); };
-  int L[3] = {i, j, k};
-  L[D] -= 1;
-  R conv = R(0), visc = R(0);
-  for (int e = 0; e < DIM; ++e) {
-    int oe[3] = {0, 0, 0};
-    oe[e] = 1;
-    R Fs[2], Ts[2];
-    if (e == D) {
-      for (int side = 0; side < 2; ++side) {
-        const int s0 = side - 1;
-        const R Ub = R(0.5) * (ud(s0 * oe[0], s0 * oe[1], s0 * oe[2]) +
-                               ud((s0 + 1) * oe[0], (s0 + 1) * oe[1], (s0 + 1) * oe[2]));
-        R q[6];
-        for (int t = 0; t < 6; ++t) {
-          const int mm = s0 + 1 - 3 + t;
-          q[t] = ud(mm * oe[0], mm * oe[1], mm * oe[2]);
-        }
-        const R Uh = upwind(q, Ub, eps);
-        int cc[3] = {i, j, k};
-        cc[D] += s0;
-        const R tau = R(2) * mu_at(cc[0], cc[1], cc[2]) *
-                      (ud((s0 + 1) * oe[0], (s0 + 1) * oe[1], (s0 + 1) * oe[2]) - ud(s0 * oe[0], s0 * oe[1], s0 * oe[2])) / h;
-        Fs[side] = Ub * Uh;
-        Ts[side] = tau;
-      }
-    } else {
-      for (int side = 0; side < 2; ++side) {
-        const int ef = id[e] + side;
-        int pL[3] = {L[0], L[1], L[2]}, pR[3] = {i, j, k};
-        pL[e] = ef;
-        pR[e] = ef;
-        const R VL = comp(e, pL[0], pL[1], pL[2]), VR = comp(e, pR[0], pR[1], pR[2]);
-        const R Vb = R(0.5) * (VL + VR);
-        R q[6];
-        for (int t = 0; t < 6; ++t) {
-          int o[3] = {0, 0, 0};
-          o[e] = ef - 3 + t - id[e];
-          q[t] = ud(o[0], o[1], o[2]);
-        }
-        const R Uh = upwind(q, Vb, eps);
-        int o0[3] = {0, 0, 0}, o1[3] = {0, 0, 0};
-        o0[e] = ef - 1 - id[e];
-        o1[e] = ef - id[e];
-        const R dud = (ud(o1[0], o1[1], o1[2]) - ud(o0[0], o0[1], o0[2])) / h;
-        const R dve = (VR - VL) / h;
-        int c1[3] = {L[0], L[1], L[2]}, c2[3] = {i, j, k}, c3[3] = {L[0], L[1], L[2]}, c4[3] = {i, j, k};
-        c1[e] = ef - 1;
-        c2[e] = ef - 1;
-        c3[e] = ef;
-        c4[e] = ef;
-        const R me = R(0.25) * (mu_at(c1[0], c1[1], c1[2]) + mu_at(c2[0], c2[1], c2[2]) + mu_at(c3[0], c3[1], c3[2]) +
-                                mu_at(c4[0], c4[1], c4[2]));
-        Fs[side] = Vb * Uh;
-        Ts[side] = me * (dud + dve);
-      }
-    }
-    conv += (Fs[1] - Fs[0]) / h;
-    visc += (Ts[1] - Ts[0]) / h;
-  }
-  const R rhof = R(0.5) * (rho[cidx(L[0], L[1], L[2], nx, ny)] + rho[cidx(i, j, k, nx, ny)]);
-  us[fi] = vel[D][fi] + R(P.dt) * (-conv + (visc + f[fi]) / rhof);
 }
 
 // ---------------------------------------------------------------------------
@@ -359,25 +281,36 @@ __global__ __launch_bounds__(256) void k_np_tstage(KParams P, const R* __restric
 // ---- launchers ---------------------------------------------------------------
 template <class R>
 void np_mixture(const KParams& P, hipStream_t s, const R* a2, const R* a3, const R* a4, R* rho, R* mu, R* rcp,
-                R* lam, R* arho, R* ac, double rlo, double rhi) {
+                R* lam, R* arho, R* amu, R* ac, double rlo, double rhi, double mlo, double mhi) {
   const long n = (long)P.nx * P.ny * P.nz;
   const Phases<R> F{a2, a3, a4};
   const dim3 g((unsigned)((n + 255) / 256));
-  if (P.nph == 4) hipLaunchKernelGGL((k_np_mixture<R, 4>), g, dim3(256), 0, s, P, n, F, rho, mu, rcp, lam, arho, ac, rlo, rhi);
-  else hipLaunchKernelGGL((k_np_mixture<R, 3>), g, dim3(256), 0, s, P, n, F, rho, mu, rcp, lam, arho, ac, rlo, rhi);
+  if (P.nph == 4)
+    hipLaunchKernelGGL((k_np_mixture<R, 4>), g, dim3(256), 0, s, P, n, F, rho, mu, rcp, lam, arho, amu, ac, rlo, rhi,
+                       mlo, mhi);
+  else
+    hipLaunchKernelGGL((k_np_mixture<R, 3>), g, dim3(256), 0, s, P, n, F, rho, mu, rcp, lam, arho, amu, ac, rlo, rhi,
+                       mlo, mhi);
+}
+
+template <class R, int DIM, int NPH>
+static void geometry_dim(const KParams& P, hipStream_t s, const Phases<R>& F, const R* T, R* nrm, R* dsp, R* skp,
+                         R* Mx, R* My, R* Mz) {
+  const dim3 g = grid_np(P.nx, P.ny, DIM == 3 ? P.nz : 1);
+  hipLaunchKernelGGL((k_np_normals<R, DIM, NPH>), g, blk_np(), 0, s, P, F, nrm, dsp);
+  hipLaunchKernelGGL((k_np_geometry<R, DIM, NPH>), g, blk_np(), 0, s, P, nrm, dsp, T, skp, Mx, My, Mz);
 }
 
 template <class R>
-void np_geometry(const KParams& P, hipStream_t s, const R* a2, const R* a3, const R* a4, const R* T, R* skp, R* Mx,
-                 R* My, R* Mz) {
+void np_geometry(const KParams& P, hipStream_t s, const R* a2, const R* a3, const R* a4, const R* T, R* nrm, R* dsp,
+                 R* skp, R* Mx, R* My, R* Mz) {
   const Phases<R> F{a2, a3, a4};
-  const dim3 g = grid_np(P.nx, P.ny, P.nz);
   if (P.dim == 3) {
-    if (P.nph == 4) hipLaunchKernelGGL((k_np_geometry<R, 3, 4>), g, blk_np(), 0, s, P, F, T, skp, Mx, My, Mz);
-    else hipLaunchKernelGGL((k_np_geometry<R, 3, 3>), g, blk_np(), 0, s, P, F, T, skp, Mx, My, Mz);
+    if (P.nph == 4) geometry_dim<R, 3, 4>(P, s, F, T, nrm, dsp, skp, Mx, My, Mz);
+    else geometry_dim<R, 3, 3>(P, s, F, T, nrm, dsp, skp, Mx, My, Mz);
   } else {
-    if (P.nph == 4) hipLaunchKernelGGL((k_np_geometry<R, 2, 4>), g, blk_np(), 0, s, P, F, T, skp, Mx, My, Mz);
-    else hipLaunchKernelGGL((k_np_geometry<R, 2, 3>), g, blk_np(), 0, s, P, F, T, skp, Mx, My, Mz);
+    if (P.nph == 4) geometry_dim<R, 2, 4>(P, s, F, T, nrm, dsp, skp, Mx, My, Mz);
+    else geometry_dim<R, 2, 3>(P, s, F, T, nrm, dsp, skp, Mx, My, Mz);
   }
 }
 
@@ -404,19 +337,6 @@ void np_face_force(const KParams& P, hipStream_t s, const R* a2, const R* a3, co
 }
 
 template <class R>
-void np_predictor(const KParams& P, hipStream_t s, const R* rho, const R* mu, const R* fx, const R* fy, const R* fz,
-                  const R* u, const R* v, const R* w, R* us, R* vs, R* ws) {
-  if (P.dim == 3) {
-    hipLaunchKernelGGL((k_np_predictor<R, 3, 0>), grid_np(P.nx + 1, P.ny, P.nz), blk_np(), 0, s, P, rho, mu, fx, u, v, w, us);
-    hipLaunchKernelGGL((k_np_predictor<R, 3, 1>), grid_np(P.nx, P.ny + 1, P.nz), blk_np(), 0, s, P, rho, mu, fy, u, v, w, vs);
-    hipLaunchKernelGGL((k_np_predictor<R, 3, 2>), grid_np(P.nx, P.ny, P.nz + 1), blk_np(), 0, s, P, rho, mu, fz, u, v, w, ws);
-  } else {
-    hipLaunchKernelGGL((k_np_predictor<R, 2, 0>), grid_np(P.nx + 1, P.ny, 1), blk_np(), 0, s, P, rho, mu, fx, u, v, w, us);
-    hipLaunchKernelGGL((k_np_predictor<R, 2, 1>), grid_np(P.nx, P.ny + 1, 1), blk_np(), 0, s, P, rho, mu, fy, u, v, w, vs);
-  }
-}
-
-template <class R>
 void np_tstage(const KParams& P, hipStream_t s, const R* T, const R* Tb, const R* u, const R* v, const R* w,
                const R* lam, const R* rcp, const R* ac, R* To, double cb, double ci) {
   const dim3 g = grid_np(P.nx, P.ny, P.dim == 3 ? P.nz : 1);
@@ -426,13 +346,11 @@ void np_tstage(const KParams& P, hipStream_t s, const R* T, const R* Tb, const R
 
 #define TCF_NP_INST(R)                                                                                              \
   template void np_mixture<R>(const KParams&, hipStream_t, const R*, const R*, const R*, R*, R*, R*, R*, R*, R*,  \
-                              double, double);                                                                     \
+                              R*, double, double, double, double);                                                 \
   template void np_geometry<R>(const KParams&, hipStream_t, const R*, const R*, const R*, const R*, R*, R*, R*,   \
-                               R*);                                                                                \
+                               R*, R*, R*);                                                                        \
   template void np_face_force<R>(const KParams&, hipStream_t, const R*, const R*, const R*, const R*, const R*,    \
                                  const R*, const R*, R*, R*, R*);                                                  \
-  template void np_predictor<R>(const KParams&, hipStream_t, const R*, const R*, const R*, const R*, const R*,     \
-                                const R*, const R*, const R*, R*, R*, R*);                                         \
   template void np_tstage<R>(const KParams&, hipStream_t, const R*, const R*, const R*, const R*, const R*,        \
                              const R*, const R*, const R*, R*, double, double);
 

@@ -90,6 +90,7 @@ struct PredArgs {
   const R* v;
   const R* w;
   R* out;
+  const R* ff;  // the material form: the face CSF force on the D-faces
 };
 
 // In-plane offsets of one in-plane flux position (direction E = x or y) of
@@ -172,7 +173,11 @@ struct FaceOps {
 
 // PF: the per-plane operands of the first flux items and of the face are
 // loaded one plane ahead (FP32); otherwise at the top of their own plane.
-template <class R, int DIM, int D, bool PF>
+// MAT: the material form of the N-phase model.  a is then the viscosity
+// as a fraction of [mu1, mu2], sk the density as a fraction of [rho1, rho2],
+// and the face force comes precomputed (ff) instead of from sigma*kappa, M
+// and the jump of alpha; every other operand and step is the same.
+template <class R, int DIM, int D, bool PF, bool MAT>
 __device__ __forceinline__ void pred_body(const PredArgs<R, DIM, D>& A, int kz, int ntx, int nty) {
   __shared__ R sU[2][SY][SX];
   __shared__ R fxF[TY][TX + 1];
@@ -230,6 +235,8 @@ __device__ __forceinline__ void pred_body(const PredArgs<R, DIM, D>& A, int kz, 
   // on the z-edges)
   const unsigned oL = (unsigned)(clampi(i - (D == 0), nx) + nx * clampi(j - (D == 1), ny));
   const unsigned oR = (unsigned)(clampi(i, nx) + nx * clampi(j, ny));
+  // MAT: in-plane offset and plane stride of this thread's D-face (clamped)
+  const size_t ffo = (size_t)clampi(i, fn0) + (size_t)fn0 * clampi(j, fn1), ffp = (size_t)fn0 * fn1;
   int hox = 0, hoy = 0;
   const bool hrole = tid < NHALO;
   if (hrole) halo_pos(tid, hox, hoy);
@@ -309,8 +316,12 @@ __device__ __forceinline__ void pred_body(const PredArgs<R, DIM, D>& A, int kz, 
     }
     fn.skL = cpl(A.sk, kL)[oL];
     fn.skR = cpl(A.sk, kk)[oR];
-    fn.mL = cpl(A.M, kL)[oL];
-    fn.mR = cpl(A.M, kk)[oR];
+    if (MAT) {
+      fn.mL = A.ff[ffo + (size_t)kk * ffp];
+    } else {
+      fn.mL = cpl(A.M, kL)[oL];
+      fn.mR = cpl(A.M, kk)[oR];
+    }
   };
   FluxOps<R> xo{}, yo{};
   if (PF) load_items(k0, 0, xo, yo);
@@ -442,8 +453,9 @@ __device__ __forceinline__ void pred_body(const PredArgs<R, DIM, D>& A, int kz, 
     if (interior) {
       conv += (fxF[ty][tx + 1] - fxF[ty][tx]) + (fyF[ty + 1][tx] - fyF[ty][tx]);
       visc += (fxT[ty][tx + 1] - fxT[ty][tx]) + (fyT[ty + 1][tx] - fyT[ty][tx]);
-      const R fst = R(0.5) * (fo.skL + fo.skR) * (alR - alL) * ih + R(0.5) * (fo.mL + fo.mR);
-      const R rhof = R(0.5) * (mixp(alL, P.rho1, P.rho2) + mixp(alR, P.rho1, P.rho2));
+      const R fst = MAT ? fo.mL : R(0.5) * (fo.skL + fo.skR) * (alR - alL) * ih + R(0.5) * (fo.mL + fo.mR);
+      const R rhof = MAT ? R(0.5) * (mixp(fo.skL, P.rho1, P.rho2) + mixp(fo.skR, P.rho1, P.rho2))
+                         : R(0.5) * (mixp(alL, P.rho1, P.rho2) + mixp(alR, P.rho1, P.rho2));
       A.out[fidx<D>(i, j, k, nx, ny)] = q[3] + dt * (-conv * ih + (visc * ih * ih + fst) / rhof);
     } else if (act) {
       A.out[fidx<D>(i, j, k, nx, ny)] = R(0);
@@ -470,13 +482,13 @@ __device__ __forceinline__ void pred_body(const PredArgs<R, DIM, D>& A, int kz, 
 }
 
 // FP32 runs two 512-thread blocks per CU (at most 128 VGPRs); FP64 one.
-template <class R, int DIM, int D>
+template <class R, int DIM, int D, bool MAT>
 __global__ __launch_bounds__(512, 4) void k_pred2_f(PredArgs<R, DIM, D> A, int kz, int ntx, int nty) {
-  pred_body<R, DIM, D, true>(A, kz, ntx, nty);
+  pred_body<R, DIM, D, true, MAT>(A, kz, ntx, nty);
 }
-template <class R, int DIM, int D>
+template <class R, int DIM, int D, bool MAT>
 __global__ __launch_bounds__(512) void k_pred2_d(PredArgs<R, DIM, D> A, int kz, int ntx, int nty) {
-  pred_body<R, DIM, D, false>(A, kz, ntx, nty);
+  pred_body<R, DIM, D, false, MAT>(A, kz, ntx, nty);
 }
 
 int pred_plan(int fn0, int fn1, int fn2, int* kz, int* ntx, int* nty) {
@@ -491,16 +503,16 @@ int pred_plan(int fn0, int fn1, int fn2, int* kz, int* ntx, int* nty) {
   return cols * ntz;
 }
 
-template <class R, int DIM, int D>
+template <class R, int DIM, int D, bool MAT>
 void launch_pred(const KParams& P, hipStream_t s, const R* a, const R* sk, const R* M, const R* u, const R* v,
-                 const R* w, R* out) {
+                 const R* w, R* out, const R* ff) {
   int kz, ntx, nty;
   const int nb = pred_plan(P.nx, P.ny, DIM == 3 ? P.nz : 1, &kz, &ntx, &nty);
-  PredArgs<R, DIM, D> A{P, a, sk, M, u, v, w, out};
+  PredArgs<R, DIM, D> A{P, a, sk, M, u, v, w, out, ff};
   if (std::is_same<R, float>::value && TCF_PRED_PF)
-    hipLaunchKernelGGL((k_pred2_f<R, DIM, D>), dim3(nb), dim3(TX, TY), 0, s, A, kz, ntx, nty);
+    hipLaunchKernelGGL((k_pred2_f<R, DIM, D, MAT>), dim3(nb), dim3(TX, TY), 0, s, A, kz, ntx, nty);
   else
-    hipLaunchKernelGGL((k_pred2_d<R, DIM, D>), dim3(nb), dim3(TX, TY), 0, s, A, kz, ntx, nty);
+    hipLaunchKernelGGL((k_pred2_d<R, DIM, D, MAT>), dim3(nb), dim3(TX, TY), 0, s, A, kz, ntx, nty);
 }
 
 }  // namespace
@@ -509,14 +521,33 @@ template <class R>
 void predictor(const KParams& P, hipStream_t s, const R* a, const R* sk, const R* Mx, const R* My, const R* Mz,
                const R* u, const R* v, const R* w, R* us, R* vs, R* ws) {
   if (P.dim == 3) {
-    launch_pred<R, 3, 0>(P, s, a, sk, Mx, u, v, w, us);
-    launch_pred<R, 3, 1>(P, s, a, sk, My, u, v, w, vs);
-    launch_pred<R, 3, 2>(P, s, a, sk, Mz, u, v, w, ws);
+    launch_pred<R, 3, 0, false>(P, s, a, sk, Mx, u, v, w, us, nullptr);
+    launch_pred<R, 3, 1, false>(P, s, a, sk, My, u, v, w, vs, nullptr);
+    launch_pred<R, 3, 2, false>(P, s, a, sk, Mz, u, v, w, ws, nullptr);
   } else {
-    launch_pred<R, 2, 0>(P, s, a, sk, Mx, u, v, w, us);
-    launch_pred<R, 2, 1>(P, s, a, sk, My, u, v, w, vs);
+    launch_pred<R, 2, 0, false>(P, s, a, sk, Mx, u, v, w, us, nullptr);
+    launch_pred<R, 2, 1, false>(P, s, a, sk, My, u, v, w, vs, nullptr);
   }
 }
+
+template <class R>
+void predictor_mat(const KParams& P, hipStream_t s, const R* amu, const R* arho, const R* fx, const R* fy,
+                   const R* fz, const R* u, const R* v, const R* w, R* us, R* vs, R* ws) {
+  if (P.dim == 3) {
+    launch_pred<R, 3, 0, true>(P, s, amu, arho, nullptr, u, v, w, us, fx);
+    launch_pred<R, 3, 1, true>(P, s, amu, arho, nullptr, u, v, w, vs, fy);
+    launch_pred<R, 3, 2, true>(P, s, amu, arho, nullptr, u, v, w, ws, fz);
+  } else {
+    launch_pred<R, 2, 0, true>(P, s, amu, arho, nullptr, u, v, w, us, fx);
+    launch_pred<R, 2, 1, true>(P, s, amu, arho, nullptr, u, v, w, vs, fy);
+  }
+}
+template void predictor_mat<double>(const KParams&, hipStream_t, const double*, const double*, const double*,
+                                    const double*, const double*, const double*, const double*, const double*,
+                                    double*, double*, double*);
+template void predictor_mat<float>(const KParams&, hipStream_t, const float*, const float*, const float*,
+                                   const float*, const float*, const float*, const float*, const float*, float*,
+                                   float*, float*);
 
 template void predictor<double>(const KParams&, hipStream_t, const double*, const double*, const double*,
                                 const double*, const double*, const double*, const double*, const double*, double*,
