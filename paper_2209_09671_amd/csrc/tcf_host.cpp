@@ -62,8 +62,8 @@ struct Fields {
   // operator's range, the condensed fraction 1 - alpha_1); per-pair
   // sigma*kappa; the face CSF force
   R *p3 = nullptr, *p31 = nullptr, *p32 = nullptr, *p4 = nullptr, *p41 = nullptr, *p42 = nullptr;
-  R *mrho = nullptr, *mmu = nullptr, *mrcp = nullptr, *mlam = nullptr, *marho = nullptr, *mamu = nullptr;
-  R* mac = nullptr;
+  R *mrcp = nullptr, *mlam = nullptr, *mdq = nullptr;  // N-phase mixture: rho c_p, lambda, heat-source delta
+  R *marho = nullptr, *mamu = nullptr;                 // density and viscosity as fractions of their ranges
   R *skp = nullptr, *nrm = nullptr, *dsp = nullptr;  // per pair: sigma*kappa; normals and delta (scratch)
   R *fx = nullptr, *fy = nullptr, *fz = nullptr;
   R *sk, *Mx, *My, *Mz;                    // sigma*kappa, Marangoni vector
@@ -212,13 +212,11 @@ void carve_fields(Carver& cv, const Dims& D, Fields<R>& F, int mg_levels, bool a
       F.p41 = cv.take<R>(N);
       F.p42 = cv.take<R>(N);
     }
-    F.mrho = cv.take<R>(N);
-    F.mmu = cv.take<R>(N);
     F.mrcp = cv.take<R>(N);
     F.mlam = cv.take<R>(N);
+    F.mdq = cv.take<R>(N);
     F.marho = cv.take<R>(N);
     F.mamu = cv.take<R>(N);
-    F.mac = cv.take<R>(N);
     const int npair = nph == 4 ? 6 : 3;
     F.skp = cv.take<R>(npair * N);
     F.nrm = cv.take<R>(3L * npair * N);
@@ -802,14 +800,15 @@ void np_range(const tcf_grid* g, int which, double* lo, double* hi) {
 }
 void np_rho_range(const tcf_grid* g, double* lo, double* hi) { np_range(g, 0, lo, hi); }
 
-// Mixture of the given fractions (N-phase fields of F).
+// Density and viscosity of the mixture of the given fractions, as fractions
+// of their ranges (N-phase fields of F).
 template <class R>
 void np_mix(tcf_grid* g, const R* a2, const R* a3, const R* a4) {
   Fields<R>& F = fields<R>(g);
   double lo, hi, mlo, mhi;
   np_range(g, 0, &lo, &hi);
   np_range(g, 1, &mlo, &mhi);
-  np_mixture<R>(g->P, g->stream, a2, a3, a4, F.mrho, F.mmu, F.mrcp, F.mlam, F.marho, F.mamu, F.mac, lo, hi, mlo, mhi);
+  np_mixture<R>(g->P, g->stream, a2, a3, a4, F.marho, F.mamu, lo, hi, mlo, mhi);
 }
 
 // S2-S5 of the N-phase model at the state fractions: mixture, per-pair
@@ -871,9 +870,9 @@ tcf_status step_np(tcf_grid* g, double dt, tcf_step_info* inf, bool want_diag) {
   R* p4o[3] = {F.p41, F.p42, F.p4};
   const double cb[3] = {0.0, 0.75, 1.0 / 3.0}, ci[3] = {1.0, 0.25, 2.0 / 3.0};
   for (int k = 0; k < 3; ++k) {
-    np_mix<R>(g, as[k], p3s[k], g->nph == 4 ? p4s[k] : nullptr);
     Prof pr(g, FAM_TRANSPORT);
-    np_tstage<R>(P, s, Ts[k], F.T, F.u, F.v, F.w, F.mlam, F.mrcp, F.mac, To[k], cb[k], ci[k]);
+    np_mixture_thermal<R>(P, s, as[k], p3s[k], g->nph == 4 ? p4s[k] : nullptr, F.mrcp, F.mlam, F.mdq);
+    transport_temperature<R>(P, s, F.mlam, F.mrcp, F.mdq, Ts[k], F.T, F.u, F.v, F.w, To[k], cb[k], ci[k]);
     transport_scalar<R>(P, s, as[k], F.a, F.u, F.v, F.w, ao[k], cb[k], ci[k]);
     transport_scalar<R>(P, s, p3s[k], F.p3, F.u, F.v, F.w, p3o[k], cb[k], ci[k]);
     if (g->nph == 4) transport_scalar<R>(P, s, p4s[k], F.p4, F.u, F.v, F.w, p4o[k], cb[k], ci[k]);

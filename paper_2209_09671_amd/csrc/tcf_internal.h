@@ -67,6 +67,12 @@ void transport_stage(const KParams& P, hipStream_t s, const R* a, const R* T, co
 template <class R>
 void transport_scalar(const KParams& P, hipStream_t s, const R* q, const R* qb, const R* u, const R* v, const R* w,
                       R* qo, double cb, double ci);
+// One SSP-RK3 stage of T alone with cell materials (the N-phase mixture):
+// lam the conductivity, rcp the heat capacity rho c_p, dq the interface
+// delta of the heat source (read only with P.qP != 0).
+template <class R>
+void transport_temperature(const KParams& P, hipStream_t s, const R* lam, const R* rcp, const R* dq, const R* T,
+                           const R* Tb, const R* u, const R* v, const R* w, R* To, double cb, double ci);
 template <class R>
 // c: species field or NULL (no solutal term)
 void geometry(const KParams& P, hipStream_t s, const R* a, const R* T, const R* c, R* sk, R* Mx, R* My, R* Mz);
@@ -190,14 +196,17 @@ void adj_axpy(hipStream_t s, long n, double f, const double* x, double* y);
 void adj_add_scalar(hipStream_t s, double* dst, const double* src);
 
 // N-phase model (tcf_nphase.hip).  Mixture per cell from the fractions of
-// phases 2..N (rho, mu, rho c_p, lambda; the density and the viscosity as
-// fractions of [rlo, rhi] and [mlo, mhi]; the condensed fraction
-// 1 - alpha_1); per-pair sigma*kappa (pair-major) and the summed Marangoni
-// vector; the face CSF force; one temperature RK3 stage with the mixture's
-// conductivity and heat capacity.  a4 = NULL with three phases.
+// phases 2..N: the density and the viscosity as fractions of [rlo, rhi]
+// and [mlo, mhi]; or (thermal) rho c_p, lambda and, with a heat source, the
+// interface delta of the condensed fraction 1 - alpha_1.  Per-pair
+// sigma*kappa (pair-major) and the summed Marangoni vector; the face CSF
+// force.  a4 = NULL with three phases.
 template <class R>
-void np_mixture(const KParams& P, hipStream_t s, const R* a2, const R* a3, const R* a4, R* rho, R* mu, R* rcp,
-                R* lam, R* arho, R* amu, R* ac, double rlo, double rhi, double mlo, double mhi);
+void np_mixture(const KParams& P, hipStream_t s, const R* a2, const R* a3, const R* a4, R* arho, R* amu, double rlo,
+                double rhi, double mlo, double mhi);
+template <class R>
+void np_mixture_thermal(const KParams& P, hipStream_t s, const R* a2, const R* a3, const R* a4, R* rcp, R* lam,
+                        R* dq);
 // (nrm: 3 N per pair, dsp: N per pair; scratch of the two geometry passes)
 template <class R>
 void np_geometry(const KParams& P, hipStream_t s, const R* a2, const R* a3, const R* a4, const R* T, R* nrm, R* dsp,
@@ -211,9 +220,6 @@ void np_face_force(const KParams& P, hipStream_t s, const R* a2, const R* a3, co
 template <class R>
 void predictor_mat(const KParams& P, hipStream_t s, const R* amu, const R* arho, const R* fx, const R* fy,
                    const R* fz, const R* u, const R* v, const R* w, R* us, R* vs, R* ws);
-template <class R>
-void np_tstage(const KParams& P, hipStream_t s, const R* T, const R* Tb, const R* u, const R* v, const R* w,
-               const R* lam, const R* rcp, const R* ac, R* To, double cb, double ci);
 
 // SSP-RK3 stage combination of a face velocity with the FP64 base velocity
 // (stage 1: 3/4 base + 1/4 x; stage 2: base/3 + 2/3 x), in place

@@ -4,13 +4,14 @@
 // alpha_4]); phases 2..N are carried by the scalar WENO5 / SSP-RK3 transport
 // of the two-phase path.  These kernels produce what the two-phase kernels
 // take from alpha alone: the mixture (material laws linear in each clamped
-// fraction relative to phase 1), the per-pair interface geometry and CSF
-// force, and the temperature stage with the mixture's conductivity and heat
-// capacity (the momentum predictor is the two-phase kernel in its material
-// form, fed the mixture's viscosity and density and this face force).  Each
-// surface-tension pair i < j acts through its pair gradient g_ij = alpha_i grad alpha_j -
-// alpha_j grad alpha_i (grad alpha for two phases) with the curvature and
-// Marangoni terms of eqs. 4-7.  One thread per cell or face on 64 x 4
+// fraction relative to phase 1) and the per-pair interface geometry and CSF
+// force.  The temperature stage and the momentum predictor are the
+// two-phase kernels in their material forms, fed the mixture's
+// conductivity, heat capacity and heat-source delta, and its viscosity,
+// density and this face force.  Each surface-tension pair i < j acts
+// through its pair gradient g_ij = alpha_i grad alpha_j - alpha_j grad
+// alpha_i (grad alpha for two phases) with the curvature and Marangoni
+// terms of eqs. 4-7.  One thread per cell or face on 64 x 4
 // blocks; ghost values by reflected indexing as in the two-phase kernels.
 #include <cfloat>
 #include <cmath>
@@ -64,38 +65,54 @@ __device__ __forceinline__ R ph_at(const Phases<R>& F, int q, int i, int j, int 
 }
 
 // ---------------------------------------------------------------------------
-// Mixture per cell: rho, mu, rho c_p, lambda = P_1 + sum_j clamp(alpha_j)
-// (P_j - P_1) (FP64, then stored in R); the density and the viscosity as
-// fractions (P - lo) / (hi - lo) of ranges that hold every mixture, which
-// the linear mixes of the pressure kernels and the predictor turn back
-// into rho and mu; the condensed fraction 1 - alpha_1.
-template <class R, int NPH>
-__global__ __launch_bounds__(256) void k_np_mixture(KParams P, long n, Phases<R> F, R* __restrict__ rho,
-                                                    R* __restrict__ mu, R* __restrict__ rcp, R* __restrict__ lam,
-                                                    R* __restrict__ arho, R* __restrict__ amu, R* __restrict__ ac,
-                                                    double rlo, double rhi, double mlo, double mhi) {
-  const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= n) return;
+// Mixture per cell of rho, mu, rho c_p, lambda = P_1 + sum_j clamp(alpha_j)
+// (P_j - P_1) (FP64, then stored in R).  THERMAL: o0 = rho c_p, o1 =
+// lambda, and with a heat source o2 = the delta |grad a_c|^2 / (|grad
+// a_c|_eps + eps) of the condensed fraction a_c = 1 - alpha_1 (central
+// differences, even ghosts).  Otherwise o0, o1 = the density and the
+// viscosity as fractions (P - lo) / (hi - lo) of ranges that hold every
+// mixture, which the linear mixes of the pressure kernels and the predictor
+// turn back into rho and mu.
+template <class R, int DIM, int NPH, bool THERMAL>
+__global__ __launch_bounds__(256) void k_np_mixture(KParams P, Phases<R> F, R* __restrict__ o0, R* __restrict__ o1,
+                                                    R* __restrict__ o2, double lo0, double hi0, double lo1,
+                                                    double hi1) {
+  const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
+  const int nx = P.nx, ny = P.ny, nz = P.nz;
+  if (i >= nx || j >= ny) return;
+  const long c = cidx(i, j, k, nx, ny);
   auto cl = [](double v) { return v < 0.0 ? 0.0 : (v > 1.0 ? 1.0 : v); };
   const double a2 = (double)F.a2[c], a3 = (double)F.a3[c], a4 = NPH == 4 ? (double)F.a4[c] : 0.0;
   const double p1[4] = {P.rho1, P.mu1, P.rhocp1, P.lam1}, p2[4] = {P.rho2, P.mu2, P.rhocp2, P.lam2};
-  double m[4];
+  double m[2];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
+  for (int r = 0; r < 2; ++r) {
+    const int q = THERMAL ? 2 + r : r;
     double v = p1[q] + cl(a2) * (p2[q] - p1[q]);
     v += cl(a3) * (P.mat34[q][0] - p1[q]);
     if (NPH == 4) v += cl(a4) * (P.mat34[q][1] - p1[q]);
-    m[q] = v;
+    m[r] = v;
   }
-  rho[c] = R(m[0]);
-  mu[c] = R(m[1]);
-  rcp[c] = R(m[2]);
-  lam[c] = R(m[3]);
-  arho[c] = R((m[0] - rlo) / (rhi - rlo));
-  amu[c] = R((m[1] - mlo) / (mhi - mlo));
-  double s = a2 + a3;
-  if (NPH == 4) s += a4;
-  ac[c] = R(1.0 - (1.0 - s));
+  if (THERMAL) {
+    o0[c] = R(m[0]);
+    o1[c] = R(m[1]);
+    if (P.qP != 0.0) {
+      auto acond = [&](int ii, int jj, int kk) {
+        double sm = (double)A_at<DIM>(F.a2, ii, jj, kk, nx, ny, nz) + (double)A_at<DIM>(F.a3, ii, jj, kk, nx, ny, nz);
+        if (NPH == 4) sm += (double)A_at<DIM>(F.a4, ii, jj, kk, nx, ny, nz);
+        return R(1.0 - (1.0 - sm));
+      };
+      const R ih2 = R(0.5 * P.ih), ne = R(P.neps);
+      const R g0 = (acond(i + 1, j, k) - acond(i - 1, j, k)) * ih2;
+      const R g1 = (acond(i, j + 1, k) - acond(i, j - 1, k)) * ih2;
+      const R g2 = DIM == 3 ? (acond(i, j, k + 1) - acond(i, j, k - 1)) * ih2 : R(0);
+      const R gg = g0 * g0 + g1 * g1 + g2 * g2;
+      o2[c] = gg / (sqrt(gg + ne * ne) + ne);
+    }
+  } else {
+    o0[c] = R((m[0] - lo0) / (hi0 - lo0));
+    o1[c] = R((m[1] - lo1) / (hi1 - lo1));
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -216,81 +233,36 @@ __global__ __launch_bounds__(256) void k_np_face_force(KParams P, Phases<R> F, c
   f[fi] = fo;
 }
 
-// ---------------------------------------------------------------------------
-// Temperature stage with the mixture: LT = -div(u T) + [div(lambda grad T) +
-// Q delta_c] / (rho c_p), delta_c the regularised gradient norm of the
-// condensed fraction; To = cb Tb + ci (T + dt LT).
-template <class R, int DIM>
-__global__ __launch_bounds__(256) void k_np_tstage(KParams P, const R* __restrict__ T, const R* __restrict__ Tb,
-                                                   const R* __restrict__ u, const R* __restrict__ v,
-                                                   const R* __restrict__ w, const R* __restrict__ lam,
-                                                   const R* __restrict__ rcp, const R* __restrict__ ac,
-                                                   R* __restrict__ To, double cb, double ci) {
-  const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
-  const int nx = P.nx, ny = P.ny, nz = P.nz;
-  if (i >= nx || j >= ny) return;
-  const long c = cidx(i, j, k, nx, ny);
-  const R eps = R(P.weno_eps), h = R(P.h);
-  // WENO5 upwind flux through the d-face with index m along d (walls: 0)
-  auto flux = [&](int d, int m) -> R {
-    const int nd = d == 0 ? nx : (d == 1 ? ny : nz);
-    if (m == 0 || m == nd) return R(0);
-    R uf;
-    if (d == 0) uf = u[fidx<0>(m, j, k, nx, ny)];
-    else if (d == 1) uf = v[fidx<1>(i, m, k, nx, ny)];
-    else uf = w[fidx<2>(i, j, m, nx, ny)];
-    R q[6];
-    for (int t = 0; t < 6; ++t) {
-      const int mm = m - 3 + t;
-      q[t] = d == 0 ? T_at<DIM>(T, mm, j, k, P) : (d == 1 ? T_at<DIM>(T, i, mm, k, P) : T_at<DIM>(T, i, j, mm, P));
-    }
-    return uf * upwind(q, uf, eps);
-  };
-  R divt = (flux(0, i + 1) - flux(0, i)) + (flux(1, j + 1) - flux(1, j));
-  if (DIM == 3) divt += flux(2, k + 1) - flux(2, k);
-  const R Tc = T[c], lc = lam[c];
-  R cond = R(0);
-  const int off[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
-  for (int d = 0; d < DIM; ++d)
-    for (int sg = -1; sg <= 1; sg += 2) {
-      const int ii = i + sg * off[d][0], jj = j + sg * off[d][1], kk = k + sg * off[d][2];
-      const R lf = R(0.5) * (lc + A_at<DIM>(lam, ii, jj, kk, nx, ny, nz));
-      cond += lf * (T_at<DIM>(T, ii, jj, kk, P) - Tc);
-    }
-  cond /= h * h;
-  R src = R(0);
-  if (P.qP != 0.0) {
-    const R ih2 = R(0.5 * P.ih), ne = R(P.neps);
-    const R g0 = (A_at<DIM>(ac, i + 1, j, k, nx, ny, nz) - A_at<DIM>(ac, i - 1, j, k, nx, ny, nz)) * ih2;
-    const R g1 = (A_at<DIM>(ac, i, j + 1, k, nx, ny, nz) - A_at<DIM>(ac, i, j - 1, k, nx, ny, nz)) * ih2;
-    const R g2 = DIM == 3 ? (A_at<DIM>(ac, i, j, k + 1, nx, ny, nz) - A_at<DIM>(ac, i, j, k - 1, nx, ny, nz)) * ih2 : R(0);
-    const R gg = g0 * g0 + g1 * g1 + g2 * g2;
-    const R ds = gg / (sqrt(gg + ne * ne) + ne);
-    const double xl = P.qx0 + P.qvx * P.t, yl = P.qy0 + P.qvy * P.t;
-    const double x = (i + 0.5) * P.h, y = (j + 0.5) * P.h;
-    const double r2 = (x - xl) * (x - xl) + (y - yl) * (y - yl);
-    const double R2 = P.qr * P.qr;
-    src = R(2.0 * P.qP / (M_PI * R2) * exp(-2.0 * r2 / R2)) * ds;
-  }
-  const R LT = -divt / h + (cond + src) / rcp[c];
-  To[c] = R(cb) * Tb[c] + R(ci) * (Tc + R(P.dt) * LT);
-}
-
 }  // namespace
 
 // ---- launchers ---------------------------------------------------------------
+template <class R, bool THERMAL>
+static void mixture(const KParams& P, hipStream_t s, const Phases<R>& F, R* o0, R* o1, R* o2, double lo0,
+                    double hi0, double lo1, double hi1) {
+  const dim3 g = grid_np(P.nx, P.ny, P.dim == 3 ? P.nz : 1);
+  if (P.dim == 3) {
+    if (P.nph == 4)
+      hipLaunchKernelGGL((k_np_mixture<R, 3, 4, THERMAL>), g, blk_np(), 0, s, P, F, o0, o1, o2, lo0, hi0, lo1, hi1);
+    else
+      hipLaunchKernelGGL((k_np_mixture<R, 3, 3, THERMAL>), g, blk_np(), 0, s, P, F, o0, o1, o2, lo0, hi0, lo1, hi1);
+  } else {
+    if (P.nph == 4)
+      hipLaunchKernelGGL((k_np_mixture<R, 2, 4, THERMAL>), g, blk_np(), 0, s, P, F, o0, o1, o2, lo0, hi0, lo1, hi1);
+    else
+      hipLaunchKernelGGL((k_np_mixture<R, 2, 3, THERMAL>), g, blk_np(), 0, s, P, F, o0, o1, o2, lo0, hi0, lo1, hi1);
+  }
+}
+
 template <class R>
-void np_mixture(const KParams& P, hipStream_t s, const R* a2, const R* a3, const R* a4, R* rho, R* mu, R* rcp,
-                R* lam, R* arho, R* amu, R* ac, double rlo, double rhi, double mlo, double mhi) {
-  const long n = (long)P.nx * P.ny * P.nz;
-  const Phases<R> F{a2, a3, a4};
-  const dim3 g((unsigned)((n + 255) / 256));
-  if (P.nph == 4)
-    hipLaunchKernelGGL((k_np_mixture<R, 4>), g, dim3(256), 0, s, P, n, F, rho, mu, rcp, lam, arho, amu, ac, rlo, rhi,
-                       mlo, mhi);
-  else
-    hipLaunchKernelGGL((k_np_mixture<R, 3>), g, dim3(256), 0, s, P, n, F, rho, mu, rcp, lam, arho, amu, ac, rlo, rhi,
-                       mlo, mhi);
+void np_mixture_thermal(const KParams& P, hipStream_t s, const R* a2, const R* a3, const R* a4, R* rcp, R* lam,
+                        R* dq) {
+  mixture<R, true>(P, s, Phases<R>{a2, a3, a4}, rcp, lam, dq, 0.0, 1.0, 0.0, 1.0);
+}
+
+template <class R>
+void np_mixture(const KParams& P, hipStream_t s, const R* a2, const R* a3, const R* a4, R* arho, R* amu, double rlo,
+                double rhi, double mlo, double mhi) {
+  mixture<R, false>(P, s, Phases<R>{a2, a3, a4}, arho, amu, nullptr, rlo, rhi, mlo, mhi);
 }
 
 template <class R, int DIM, int NPH>
@@ -336,23 +308,14 @@ void np_face_force(const KParams& P, hipStream_t s, const R* a2, const R* a3, co
   }
 }
 
-template <class R>
-void np_tstage(const KParams& P, hipStream_t s, const R* T, const R* Tb, const R* u, const R* v, const R* w,
-               const R* lam, const R* rcp, const R* ac, R* To, double cb, double ci) {
-  const dim3 g = grid_np(P.nx, P.ny, P.dim == 3 ? P.nz : 1);
-  if (P.dim == 3) hipLaunchKernelGGL((k_np_tstage<R, 3>), g, blk_np(), 0, s, P, T, Tb, u, v, w, lam, rcp, ac, To, cb, ci);
-  else hipLaunchKernelGGL((k_np_tstage<R, 2>), g, blk_np(), 0, s, P, T, Tb, u, v, w, lam, rcp, ac, To, cb, ci);
-}
-
 #define TCF_NP_INST(R)                                                                                              \
-  template void np_mixture<R>(const KParams&, hipStream_t, const R*, const R*, const R*, R*, R*, R*, R*, R*, R*,  \
-                              R*, double, double, double, double);                                                 \
+  template void np_mixture<R>(const KParams&, hipStream_t, const R*, const R*, const R*, R*, R*, double, double,   \
+                              double, double);                                                                     \
+  template void np_mixture_thermal<R>(const KParams&, hipStream_t, const R*, const R*, const R*, R*, R*, R*);      \
   template void np_geometry<R>(const KParams&, hipStream_t, const R*, const R*, const R*, const R*, R*, R*, R*,   \
                                R*, R*, R*);                                                                        \
   template void np_face_force<R>(const KParams&, hipStream_t, const R*, const R*, const R*, const R*, const R*,    \
-                                 const R*, const R*, R*, R*, R*);                                                  \
-  template void np_tstage<R>(const KParams&, hipStream_t, const R*, const R*, const R*, const R*, const R*,        \
-                             const R*, const R*, const R*, R*, double, double);
+                                 const R*, const R*, R*, R*, R*);
 
 TCF_NP_INST(double)
 TCF_NP_INST(float)

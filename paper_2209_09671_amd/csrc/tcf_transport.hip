@@ -102,14 +102,21 @@ __device__ __forceinline__ ColMap<R> col_map(const KParams& P, int ii, int jj, b
   return m;
 }
 
-// WT: alpha and T (the stage of S1); without WT the "alpha" slot carries any
-// passive cell field (the species) with exactly alpha's arithmetic, and
-// nothing of T is touched.
-template <class R, int DIM, bool WT>
+// MODE 1: alpha and T (the stage of S1).
+// MODE 0: the "alpha" slot carries any passive cell field (the species, the
+// fraction of a further phase) with exactly alpha's arithmetic; nothing of T
+// is touched.
+// MODE 2: T alone with cell materials: the "alpha" slot carries the
+// conductivity lambda (read with its halo for the face means, not
+// transported, ab and ao unused), rc the heat capacity rho c_p and dq the
+// interface delta that the heat flux is spread over.
+template <class R, int DIM, int MODE>
 __global__ __launch_bounds__(512) void k_transport2(KParams P, int kz, int ntx, int nty, const R* __restrict__ a,
                                                     const R* __restrict__ T, const R* ab, const R* Tb,
                                                     const R* __restrict__ u, const R* __restrict__ v,
-                                                    const R* __restrict__ w, R* ao, R* To, R cb, R ci) {
+                                                    const R* __restrict__ w, R* ao, R* To, R cb, R ci,
+                                                    const R* __restrict__ rc, const R* __restrict__ dq) {
+  constexpr bool WT = MODE != 0, WA = MODE != 2;
   constexpr int NT = WT ? 2 : 1;
   __shared__ R sa[2][SY][SX];
   __shared__ R sT[NT][WT ? SY : 1][WT ? SX : 1];
@@ -184,7 +191,9 @@ __global__ __launch_bounds__(512) void k_transport2(KParams P, int kz, int ntx, 
   R uL = u[(size_t)k0 * plu + uoL], uH = u[(size_t)k0 * plu + uoH];
   R vL = v[(size_t)k0 * plv + voL], vH = v[(size_t)k0 * plv + voH];
   R wH = DIM == 3 ? w[(size_t)(k0 + 1) * pl + co] : R(0);
-  R bA = ab[(size_t)k0 * pl + co], bT = WT ? Tb[(size_t)k0 * pl + co] : R(0);
+  R bA = WA ? ab[(size_t)k0 * pl + co] : R(0), bT = WT ? Tb[(size_t)k0 * pl + co] : R(0);
+  const bool wq = MODE == 2 && P.qP != 0.0;
+  R bR = MODE == 2 ? rc[(size_t)k0 * pl + co] : R(0), bQ = wq ? dq[(size_t)k0 * pl + co] : R(0);
   const R wL0 = DIM == 3 ? w[(size_t)k0 * pl + co] : R(0);
   // Gaussian surface heat flux of the column (x, y, t), FP64, once per column
   R qcol = R(0);
@@ -225,34 +234,38 @@ __global__ __launch_bounds__(512) void k_transport2(KParams P, int kz, int ntx, 
     ha = ldA(hm.off, kn);
     if (WT) hT = ldT(hm.off, kn);
     // this plane's velocities and base state; prefetch the next plane's
-    const R ulo = uL, uhi = uH, vlo = vL, vhi = vH, whi = wH, abc = bA, Tbc = bT;
+    const R ulo = uL, uhi = uH, vlo = vL, vhi = vH, whi = wH, abc = bA, Tbc = bT, rcc = bR, dqc = bQ;
     uL = u[(size_t)kn * plu + uoL];
     uH = u[(size_t)kn * plu + uoH];
     vL = v[(size_t)kn * plv + voL];
     vH = v[(size_t)kn * plv + voH];
     if (DIM == 3) wH = w[(size_t)min(kn + 1, nz) * pl + co];
-    bA = ab[(size_t)kn * pl + co];
+    if (WA) bA = ab[(size_t)kn * pl + co];
     if (WT) bT = Tb[(size_t)kn * pl + co];
+    if (MODE == 2) bR = rc[(size_t)kn * pl + co];
+    if (wq) bQ = dq[(size_t)kn * pl + co];
     __syncthreads();
     R Fxa_lo = R(0), Fxt_lo = R(0), Fya_lo = R(0), Fyt_lo = R(0);
     const size_t c = (size_t)k * pl + co;
     if (act) {
       const int X = tx + H, Y = ty + H;
       if (i > 0) {
-        Fxa_lo = ulo * upw(sa[buf][Y][X - 3], sa[buf][Y][X - 2], sa[buf][Y][X - 1], sa[buf][Y][X], sa[buf][Y][X + 1],
+        if (WA)
+          Fxa_lo = ulo * upw(sa[buf][Y][X - 3], sa[buf][Y][X - 2], sa[buf][Y][X - 1], sa[buf][Y][X], sa[buf][Y][X + 1],
                            sa[buf][Y][X + 2], ulo, eps);
         if (WT)
           Fxt_lo = ulo * upw(sT[buf][Y][X - 3], sT[buf][Y][X - 2], sT[buf][Y][X - 1], sT[buf][Y][X],
                              sT[buf][Y][X + 1], sT[buf][Y][X + 2], ulo, eps);
       }
       if (j > 0) {
-        Fya_lo = vlo * upw(sa[buf][Y - 3][X], sa[buf][Y - 2][X], sa[buf][Y - 1][X], sa[buf][Y][X], sa[buf][Y + 1][X],
+        if (WA)
+          Fya_lo = vlo * upw(sa[buf][Y - 3][X], sa[buf][Y - 2][X], sa[buf][Y - 1][X], sa[buf][Y][X], sa[buf][Y + 1][X],
                            sa[buf][Y + 2][X], vlo, eps);
         if (WT)
           Fyt_lo = vlo * upw(sT[buf][Y - 3][X], sT[buf][Y - 2][X], sT[buf][Y - 1][X], sT[buf][Y][X],
                              sT[buf][Y + 1][X], sT[buf][Y + 2][X], vlo, eps);
       }
-      fya[ty][tx] = Fya_lo;
+      if (WA) fya[ty][tx] = Fya_lo;
       if (WT) fyt[ty][tx] = Fyt_lo;
     }
     // high x-face: next lane's low face, computed here at the tile edge
@@ -263,7 +276,8 @@ __global__ __launch_bounds__(512) void k_transport2(KParams P, int kz, int ntx, 
         Fxa_hi = R(0);
         Fxt_hi = R(0);
       } else if (tx == TX - 1) {
-        Fxa_hi = uhi * upw(sa[buf][Y][X - 2], sa[buf][Y][X - 1], sa[buf][Y][X], sa[buf][Y][X + 1], sa[buf][Y][X + 2],
+        if (WA)
+          Fxa_hi = uhi * upw(sa[buf][Y][X - 2], sa[buf][Y][X - 1], sa[buf][Y][X], sa[buf][Y][X + 1], sa[buf][Y][X + 2],
                            sa[buf][Y][X + 3], uhi, eps);
         if (WT)
           Fxt_hi = uhi * upw(sT[buf][Y][X - 2], sT[buf][Y][X - 1], sT[buf][Y][X], sT[buf][Y][X + 1],
@@ -276,10 +290,11 @@ __global__ __launch_bounds__(512) void k_transport2(KParams P, int kz, int ntx, 
       R Fya_hi = R(0), Fyt_hi = R(0);
       if (j + 1 < ny) {
         if (ty < TY - 1) {
-          Fya_hi = fya[ty + 1][tx];
+          if (WA) Fya_hi = fya[ty + 1][tx];
           if (WT) Fyt_hi = fyt[ty + 1][tx];
         } else {
-          Fya_hi = vhi * upw(sa[buf][Y - 2][X], sa[buf][Y - 1][X], sa[buf][Y][X], sa[buf][Y + 1][X],
+          if (WA)
+            Fya_hi = vhi * upw(sa[buf][Y - 2][X], sa[buf][Y - 1][X], sa[buf][Y][X], sa[buf][Y + 1][X],
                              sa[buf][Y + 2][X], sa[buf][Y + 3][X], vhi, eps);
           if (WT)
             Fyt_hi = vhi * upw(sT[buf][Y - 2][X], sT[buf][Y - 1][X], sT[buf][Y][X], sT[buf][Y + 1][X],
@@ -293,13 +308,13 @@ __global__ __launch_bounds__(512) void k_transport2(KParams P, int kz, int ntx, 
           fza_lo = R(0);
           fzt_lo = R(0);
           if (k > 0) {
-            fza_lo = wL0 * upw(qa[0], qa[1], qa[2], qa[3], qa[4], qa[5], wL0, eps);
+            if (WA) fza_lo = wL0 * upw(qa[0], qa[1], qa[2], qa[3], qa[4], qa[5], wL0, eps);
             if (WT) fzt_lo = wL0 * upw(qt[0], qt[1], qt[2], qt[3], qt[4], qt[5], wL0, eps);
           }
         }
         R fza_hi = R(0), fzt_hi = R(0);
         if (k + 1 < nz) {
-          fza_hi = whi * upw(qa[1], qa[2], qa[3], qa[4], qa[5], qa[6], whi, eps);
+          if (WA) fza_hi = whi * upw(qa[1], qa[2], qa[3], qa[4], qa[5], qa[6], whi, eps);
           if (WT) fzt_hi = whi * upw(qt[1], qt[2], qt[3], qt[4], qt[5], qt[6], whi, eps);
         }
         diva += fza_hi - fza_lo;
@@ -310,23 +325,26 @@ __global__ __launch_bounds__(512) void k_transport2(KParams P, int kz, int ntx, 
       }
       const R ac = qa[3], Tc = qt[3];
       const R La = -diva * ih;
-      ao[c] = cb * abc + ci * (ac + dt * La);
+      if (WA) ao[c] = cb * abc + ci * (ac + dt * La);
       if (WT) {
         // conduction: arithmetic-mean face conductivity, ghosts from the tile
-        const R lc = mixp(ac, P.lam1, P.lam2);
+        auto lam = [&](R x) { return MODE == 2 ? x : mixp(x, P.lam1, P.lam2); };
+        const R lc = lam(ac);
         R cond = R(0);
         {
           const R an[4] = {sa[buf][Y][X - 1], sa[buf][Y][X + 1], sa[buf][Y - 1][X], sa[buf][Y + 1][X]};
           const R tn[4] = {sT[buf][Y][X - 1], sT[buf][Y][X + 1], sT[buf][Y - 1][X], sT[buf][Y + 1][X]};
-          for (int f = 0; f < 4; ++f) cond += R(0.5) * (lc + mixp(an[f], P.lam1, P.lam2)) * (tn[f] - Tc);
+          for (int f = 0; f < 4; ++f) cond += R(0.5) * (lc + lam(an[f])) * (tn[f] - Tc);
           if (DIM == 3) {
-            cond += R(0.5) * (lc + mixp(qa[2], P.lam1, P.lam2)) * (qt[2] - Tc);
-            cond += R(0.5) * (lc + mixp(qa[4], P.lam1, P.lam2)) * (qt[4] - Tc);
+            cond += R(0.5) * (lc + lam(qa[2])) * (qt[2] - Tc);
+            cond += R(0.5) * (lc + lam(qa[4])) * (qt[4] - Tc);
           }
         }
         cond *= ih * ih;
         R src = R(0);
-        if (P.qP != 0.0) {
+        if (MODE == 2) {
+          src = qcol * dqc;
+        } else if (P.qP != 0.0) {
           const R h2 = R(0.5) * ih;
           const R gx = (sa[buf][Y][X + 1] - sa[buf][Y][X - 1]) * h2;
           const R gy = (sa[buf][Y + 1][X] - sa[buf][Y - 1][X]) * h2;
@@ -336,7 +354,7 @@ __global__ __launch_bounds__(512) void k_transport2(KParams P, int kz, int ntx, 
           const R ds = g2 / (sqrt(g2 + ne * ne) + ne);
           src = qcol * ds;
         }
-        const R LT = -divt * ih + (cond + src) / mixp(ac, P.rhocp1, P.rhocp2);
+        const R LT = -divt * ih + (cond + src) / (MODE == 2 ? rcc : mixp(ac, P.rhocp1, P.rhocp2));
         To[c] = cb * Tbc + ci * (Tc + dt * LT);
       }
     }
@@ -364,11 +382,24 @@ void transport_stage(const KParams& P, hipStream_t s, const R* a, const R* T, co
   int kz, ntx, nty;
   const int nb = transport_plan(P.nx, P.ny, P.nz, &kz, &ntx, &nty);
   if (P.dim == 3)
-    hipLaunchKernelGGL((k_transport2<R, 3, true>), dim3(nb), dim3(TX, TY), 0, s, P, kz, ntx, nty, a, T, ab, Tb, u, v,
-                       w, ao, To, R(cb), R(ci));
+    hipLaunchKernelGGL((k_transport2<R, 3, 1>), dim3(nb), dim3(TX, TY), 0, s, P, kz, ntx, nty, a, T, ab, Tb, u, v, w,
+                       ao, To, R(cb), R(ci), nullptr, nullptr);
   else
-    hipLaunchKernelGGL((k_transport2<R, 2, true>), dim3(nb), dim3(TX, TY), 0, s, P, kz, ntx, nty, a, T, ab, Tb, u, v,
-                       w, ao, To, R(cb), R(ci));
+    hipLaunchKernelGGL((k_transport2<R, 2, 1>), dim3(nb), dim3(TX, TY), 0, s, P, kz, ntx, nty, a, T, ab, Tb, u, v, w,
+                       ao, To, R(cb), R(ci), nullptr, nullptr);
+}
+
+template <class R>
+void transport_temperature(const KParams& P, hipStream_t s, const R* lam, const R* rcp, const R* dq, const R* T,
+                           const R* Tb, const R* u, const R* v, const R* w, R* To, double cb, double ci) {
+  int kz, ntx, nty;
+  const int nb = transport_plan(P.nx, P.ny, P.nz, &kz, &ntx, &nty);
+  if (P.dim == 3)
+    hipLaunchKernelGGL((k_transport2<R, 3, 2>), dim3(nb), dim3(TX, TY), 0, s, P, kz, ntx, nty, lam, T, nullptr, Tb, u,
+                       v, w, nullptr, To, R(cb), R(ci), rcp, dq);
+  else
+    hipLaunchKernelGGL((k_transport2<R, 2, 2>), dim3(nb), dim3(TX, TY), 0, s, P, kz, ntx, nty, lam, T, nullptr, Tb, u,
+                       v, w, nullptr, To, R(cb), R(ci), rcp, dq);
 }
 
 template <class R>
@@ -377,11 +408,11 @@ void transport_scalar(const KParams& P, hipStream_t s, const R* q, const R* qb, 
   int kz, ntx, nty;
   const int nb = transport_plan(P.nx, P.ny, P.nz, &kz, &ntx, &nty);
   if (P.dim == 3)
-    hipLaunchKernelGGL((k_transport2<R, 3, false>), dim3(nb), dim3(TX, TY), 0, s, P, kz, ntx, nty, q, nullptr, qb,
-                       nullptr, u, v, w, qo, nullptr, R(cb), R(ci));
+    hipLaunchKernelGGL((k_transport2<R, 3, 0>), dim3(nb), dim3(TX, TY), 0, s, P, kz, ntx, nty, q, nullptr, qb, nullptr,
+                       u, v, w, qo, nullptr, R(cb), R(ci), nullptr, nullptr);
   else
-    hipLaunchKernelGGL((k_transport2<R, 2, false>), dim3(nb), dim3(TX, TY), 0, s, P, kz, ntx, nty, q, nullptr, qb,
-                       nullptr, u, v, w, qo, nullptr, R(cb), R(ci));
+    hipLaunchKernelGGL((k_transport2<R, 2, 0>), dim3(nb), dim3(TX, TY), 0, s, P, kz, ntx, nty, q, nullptr, qb, nullptr,
+                       u, v, w, qo, nullptr, R(cb), R(ci), nullptr, nullptr);
 }
 
 template void transport_stage<double>(const KParams&, hipStream_t, const double*, const double*, const double*,
@@ -394,5 +425,11 @@ template void transport_scalar<double>(const KParams&, hipStream_t, const double
                                        const double*, const double*, double*, double, double);
 template void transport_scalar<float>(const KParams&, hipStream_t, const float*, const float*, const float*,
                                       const float*, const float*, float*, double, double);
+template void transport_temperature<double>(const KParams&, hipStream_t, const double*, const double*, const double*,
+                                            const double*, const double*, const double*, const double*, const double*,
+                                            double*, double, double);
+template void transport_temperature<float>(const KParams&, hipStream_t, const float*, const float*, const float*,
+                                           const float*, const float*, const float*, const float*, const float*,
+                                           float*, double, double);
 
 }  // namespace tcf
