@@ -82,28 +82,6 @@ __device__ __forceinline__ float mixp<float>(float a, double p1, double p2) {
   return float(p1) + __builtin_amdgcn_fmed3f(a, 0.0f, 1.0f) * float(p2 - p1);
 }
 
-// WENO5-JS value at the right edge of the centre sample c of (a,b,c,d,e).
-template <class R>
-__device__ __forceinline__ R weno5(R a, R b, R c, R d, R e, R eps) {
-  const R q0 = (R(2) * a - R(7) * b + R(11) * c) * R(1.0 / 6.0);
-  const R q1 = (-b + R(5) * c + R(2) * d) * R(1.0 / 6.0);
-  const R q2 = (R(2) * c + R(5) * d - e) * R(1.0 / 6.0);
-  const R t0 = a - R(2) * b + c, u0 = a - R(4) * b + R(3) * c;
-  const R t1 = b - R(2) * c + d, u1 = b - d;
-  const R t2 = c - R(2) * d + e, u2 = R(3) * c - R(4) * d + e;
-  const R e0 = eps + (R(13.0 / 12.0) * t0 * t0 + R(0.25) * u0 * u0);
-  const R e1 = eps + (R(13.0 / 12.0) * t1 * t1 + R(0.25) * u1 * u1);
-  const R e2 = eps + (R(13.0 / 12.0) * t2 * t2 + R(0.25) * u2 * u2);
-  const R a0 = R(0.1) / (e0 * e0), a1 = R(0.6) / (e1 * e1), a2 = R(0.3) / (e2 * e2);
-  return (a0 * q0 + a1 * q1 + a2 * q2) / (a0 + a1 + a2);
-}
-
-// q[k] = Q(f-3+k), k = 0..5; value at face f (between Q(f-1) and Q(f)).
-template <class R>
-__device__ __forceinline__ R upwind(const R* q, R vel, R eps) {
-  return vel >= R(0) ? weno5(q[0], q[1], q[2], q[3], q[4], eps) : weno5(q[5], q[4], q[3], q[2], q[1], eps);
-}
-
 // ---------------------------------------------------------------------------
 // Deterministic block reduction (256 threads = 4 wavefronts of 64).
 __device__ __forceinline__ double wave_sum(double v) {

@@ -44,10 +44,12 @@ __device__ __forceinline__ R weno5x(R a, R b, R c, R d, R e, R eps) {
   return (a0 * q0 + a1 * q1 + a2 * q2) * rcpx(R(6) * (a0 + a1 + a2));
 }
 
-// q[m] = Q(f-3+m); value at face f, upwind by the sign of vel
+// q[m] = Q(f-3+m); value at face f, upwind by the sign of vel.  The stencil
+// is picked before the one WENO5 evaluation, so lanes of both signs share it.
 template <class R>
 __device__ __forceinline__ R upw(R q0, R q1, R q2, R q3, R q4, R q5, R vel, R eps) {
-  return vel >= R(0) ? weno5x(q0, q1, q2, q3, q4, eps) : weno5x(q5, q4, q3, q2, q1, eps);
+  const bool pos = vel >= R(0);
+  return weno5x(pos ? q0 : q5, pos ? q1 : q4, pos ? q2 : q3, pos ? q3 : q2, pos ? q4 : q1, eps);
 }
 
 // halo slot -> (ox, oy) offset in the LDS tile (0..SX-1, 0..SY-1)
