@@ -35,6 +35,13 @@ tcf_status fail(tcf_status st, const std::string& msg) {
 constexpr size_t kAlign = 256;
 constexpr double kOmegaC = 1.9;  // over-correction of the piecewise-constant coarse correction
 constexpr int kCoarseSweeps = 30;
+// levels of at most this many cells (and everything below them) run as one
+// block (the coarse tail of the V-cycle)
+#ifndef TCF_MG_TAIL_CELLS
+#define TCF_MG_TAIL_CELLS kTailCells
+#endif
+constexpr long kMgTailCells = TCF_MG_TAIL_CELLS;
+static_assert(kMgTailCells <= kTailCells, "the tail stages a level's residuals in LDS of kTailCells values");
 
 // Bump allocator over the caller's workspace; with base == nullptr it only
 // counts bytes, so sizing and carving share one code path.
@@ -576,6 +583,26 @@ void vcycle(tcf_grid* g, Fields<R>& F, size_t l, const R* b, R* out, R* tmp, dou
                          k == nu - 1 ? part : nullptr, g->iflag);
     }
     if (np) *np = n;
+    return;
+  }
+  long tail_lds = 0;
+  for (size_t q = l; q < F.lv.size(); ++q) tail_lds += 3 * F.lv[q].n();
+  if (L.n() <= kMgTailCells && F.lv.size() - l <= (size_t)kTailLevels && nu <= kTailNu && tail_lds <= kTailLds) {
+    // the rest of the cycle in one block (b, out, tmp are this level's b, x, x2)
+    MgTail<R> T{};
+    T.nl = (int)(F.lv.size() - l);
+    for (int q = 0; q < T.nl; ++q) T.lv[q] = F.lv[l + q];
+    T.nu = nu;
+    T.first_done = first_done ? 1 : 0;
+    T.cinv = F.cinv;
+    T.csweeps = kCoarseSweeps;
+    T.cj = jacobi_omega(dim);
+    T.omc = kOmegaC;
+    for (int k = 0; k < nu; ++k) {
+      T.wpre[k] = wpre(k);
+      T.wpost[k] = wpost(k);
+    }
+    mg_tail<R>(s, dim, T, g->iflag);
     return;
   }
   int w = 0;  // next write goes to bufs[w & 1]

@@ -38,6 +38,24 @@ struct Level {
   __host__ __device__ long n() const { return (long)nx * ny * nz; }
 };
 
+// The coarse end of a V-cycle run by one block (levels of at most
+// kTailCells cells): lv[0] the tail's first level, lv[nl - 1] the coarsest,
+// solved by cinv (dense inverse) or csweeps damped-Jacobi sweeps of weight
+// cj; pre- and post-smoothing weights, the coarse-correction weight omc;
+// first_done: lv[0].x2 already holds the first pre-smoothing sweep.
+constexpr int kTailLevels = 8, kTailCells = 1024, kTailNu = 8;
+// LDS values of the tail: three vectors per level; a level holds at most a
+// quarter of its parent's cells, so all levels below the first at most a third
+constexpr int kTailLds = 3 * (kTailCells + kTailCells / 3 + 1);
+template <class R>
+struct MgTail {
+  Level<R> lv[kTailLevels];
+  int nl, nu, csweeps, first_done;
+  const R* cinv;
+  double wpre[kTailNu], wpost[kTailNu];
+  double omc, cj;
+};
+
 // Finest level of the pressure operator: face weights recomputed from alpha,
 // a_f = c2 / (rho_L + rho_R) with rho = rho1 + clamp(alpha, 0, 1) drho.
 template <class R>
@@ -149,6 +167,8 @@ template <class R>
 void coarse_factor(hipStream_t s, int dim, const Level<R>& L, double* A, R* Minv);
 template <class R>
 void coarse_apply(hipStream_t s, int n, const R* Minv, const R* b, R* out, const int* iflag);
+template <class R>
+void mg_tail(hipStream_t s, int dim, const MgTail<R>& T, const int* iflag);
 
 void finalize(hipStream_t s, const double* part, int nparts, double* scal, int* iflag, int op, int slot,
               double arg);

@@ -258,6 +258,48 @@ __global__ __launch_bounds__(256) void k_smooth_first(long n, const R* __restric
   if (c < n) x[c] = om * wd[c] * b[c];
 }
 
+// Per-cell bodies of the multigrid level kernels, shared by the one-kernel
+// coarse tail below so that both produce the same values.
+// damped Jacobi sweep of cell c = (i, j, k): x + om wdiag (b - K x)
+template <class R, int DIM>
+__device__ __forceinline__ R smooth_cell(const Level<R>& L, const R* __restrict__ b, const R* __restrict__ x, R om,
+                                         int i, int j, int k, long c) {
+  const R Kx = applyK<R, DIM>(x, L.ax, L.ay, L.az, i, j, k, L.nx, L.ny, L.nz);
+  return x[c] + om * L.wdiag[c] * (b[c] - Kx);
+}
+
+// residual b - K x of cell (i, j, k)
+template <class R, int DIM>
+__device__ __forceinline__ R resid_cell(const Level<R>& F, const R* __restrict__ b, const R* __restrict__ x, int i,
+                                        int j, int k) {
+  return b[cidx(i, j, k, F.nx, F.ny)] - applyK<R, DIM>(x, F.ax, F.ay, F.az, i, j, k, F.nx, F.ny, F.nz);
+}
+
+// x' = x + omc P e (piecewise-constant prolongation on the fly), then one
+// sweep: x' + om wdiag (b - K x') at cell (i, j, k)
+template <class R, int DIM>
+__device__ __forceinline__ R prolong_smooth_cell(const Level<R>& L, int cnx, int cny, const R* __restrict__ e,
+                                                 const R* __restrict__ b, const R* __restrict__ x, R omc, R om, int i,
+                                                 int j, int k) {
+  const int kz = DIM == 3 ? 2 : 1;
+  const int nx = L.nx, ny = L.ny, nz = L.nz;
+  auto xp = [&](int ii, int jj, int kk) {
+    return x[cidx(ii, jj, kk, nx, ny)] + omc * e[cidx(ii >> 1, jj >> 1, kk / kz, cnx, cny)];
+  };
+  const long c = cidx(i, j, k, nx, ny);
+  const R xc = xp(i, j, k);
+  R s = R(0);
+  if (i > 0) s += L.ax[fidx<0>(i, j, k, nx, ny)] * (xc - xp(i - 1, j, k));
+  if (i < nx - 1) s += L.ax[fidx<0>(i + 1, j, k, nx, ny)] * (xc - xp(i + 1, j, k));
+  if (j > 0) s += L.ay[fidx<1>(i, j, k, nx, ny)] * (xc - xp(i, j - 1, k));
+  if (j < ny - 1) s += L.ay[fidx<1>(i, j + 1, k, nx, ny)] * (xc - xp(i, j + 1, k));
+  if (DIM == 3) {
+    if (k > 0) s += L.az[fidx<2>(i, j, k, nx, ny)] * (xc - xp(i, j, k - 1));
+    if (k < nz - 1) s += L.az[fidx<2>(i, j, k + 1, nx, ny)] * (xc - xp(i, j, k + 1));
+  }
+  return xc + om * L.wdiag[c] * (b[c] - s);
+}
+
 // damped Jacobi: xo = x + om wdiag (b - K x) (wdiag = 1 / diag); optional
 // partial of b.xo (= r.z on the finest level)
 template <class R, int DIM>
@@ -270,8 +312,7 @@ __global__ __launch_bounds__(256) void k_smooth(Level<R> L, const R* __restrict_
   double val = 0.0;
   if (i < L.nx && j < L.ny) {
     const long c = cidx(i, j, k, L.nx, L.ny);
-    const R Kx = applyK<R, DIM>(x, L.ax, L.ay, L.az, i, j, k, L.nx, L.ny, L.nz);
-    const R xn = x[c] + om * L.wdiag[c] * (b[c] - Kx);
+    const R xn = smooth_cell<R, DIM>(L, b, x, om, i, j, k, c);
     xo[c] = xn;
     val = (double)b[c] * (double)xn;
   }
@@ -295,9 +336,7 @@ __global__ __launch_bounds__(256) void k_resid_restrict(Level<R> F, int cnx, int
   for (int dk = 0; dk < kz; ++dk)
     for (int dj = 0; dj < 2; ++dj)
       for (int di = 0; di < 2; ++di) {
-        const int i = 2 * I + di, j = 2 * J + dj, k = kz * K + dk;
-        const long c = cidx(i, j, k, F.nx, F.ny);
-        s += b[c] - applyK<R, DIM>(x, F.ax, F.ay, F.az, i, j, k, F.nx, F.ny, F.nz);
+        s += resid_cell<R, DIM>(F, b, x, 2 * I + di, 2 * J + dj, kz * K + dk);
       }
   const long ci = cidx(I, J, K, cnx, cny);
   bc[ci] = s;
@@ -313,25 +352,10 @@ __global__ __launch_bounds__(256) void k_prolong_smooth(Level<R> L, int cnx, int
   if (iflag[I_DONE]) return;
   __shared__ double sh[8];
   const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
-  const int kz = DIM == 3 ? 2 : 1;
   double val = 0.0;
   if (i < L.nx && j < L.ny) {
-    const int nx = L.nx, ny = L.ny, nz = L.nz;
-    auto xp = [&](int ii, int jj, int kk) {
-      return x[cidx(ii, jj, kk, nx, ny)] + omc * e[cidx(ii >> 1, jj >> 1, kk / kz, cnx, cny)];
-    };
-    const long c = cidx(i, j, k, nx, ny);
-    const R xc = xp(i, j, k);
-    R s = R(0);
-    if (i > 0) s += L.ax[fidx<0>(i, j, k, nx, ny)] * (xc - xp(i - 1, j, k));
-    if (i < nx - 1) s += L.ax[fidx<0>(i + 1, j, k, nx, ny)] * (xc - xp(i + 1, j, k));
-    if (j > 0) s += L.ay[fidx<1>(i, j, k, nx, ny)] * (xc - xp(i, j - 1, k));
-    if (j < ny - 1) s += L.ay[fidx<1>(i, j + 1, k, nx, ny)] * (xc - xp(i, j + 1, k));
-    if (DIM == 3) {
-      if (k > 0) s += L.az[fidx<2>(i, j, k, nx, ny)] * (xc - xp(i, j, k - 1));
-      if (k < nz - 1) s += L.az[fidx<2>(i, j, k + 1, nx, ny)] * (xc - xp(i, j, k + 1));
-    }
-    const R xn = xc + om * L.wdiag[c] * (b[c] - s);
+    const long c = cidx(i, j, k, L.nx, L.ny);
+    const R xn = prolong_smooth_cell<R, DIM>(L, cnx, cny, e, b, x, omc, om, i, j, k);
     xo[c] = xn;
     val = (double)b[c] * (double)xn;
   }
@@ -503,6 +527,174 @@ __global__ __launch_bounds__(1024) void k_coarse_apply(int n, const R* __restric
     }
     if (j < n) s0 += row[j] * sb[j];
     out[i] = s0 + s1;
+  }
+}
+
+// The coarse end of the symmetric V-cycle in one block: from the tail's
+// first level (its right-hand side, and unless first_done is clear its
+// first pre-smoothing sweep, in b and x2) down to the coarsest level and
+// back up, with the same sweeps, restrictions, coarsest solve and
+// prolongations, and the same per-cell arithmetic, as the per-level kernels.
+// Every level's iterates and right-hand side live in LDS for the whole
+// tail (three vectors per level), the face weights are read from memory,
+// a block barrier separates the phases, and only the result reaches memory
+// (the first level's x).  A thread owns up to kTailPer cells of a level and
+// issues all their loads before its first store.  A restriction stages the
+// fine residuals in the level's free iterate buffer, then sums each coarse
+// cell's children in the per-level kernel's order.
+constexpr int kTailThreads = 1024, kTailPer = kTailCells / kTailThreads;
+static_assert(kTailPer * kTailThreads == kTailCells, "tail cells per thread");
+
+template <class R, int DIM>
+__global__ __launch_bounds__(kTailThreads) void k_mg_tail(MgTail<R> T, const int* __restrict__ iflag) {
+  if (iflag[I_DONE]) return;
+  __shared__ R sm[kTailLds];
+  const int t = threadIdx.x;
+  const int kz = DIM == 3 ? 2 : 1;
+  // (32-bit index arithmetic: a tail level holds at most kTailCells cells)
+  auto ijk = [](int c, int nx, int ny, int& i, int& j, int& k) {
+    const int q = c / nx;
+    i = c - q * nx;
+    j = q % ny;
+    k = q / ny;
+  };
+  // out[c] = fn(c) for the level's n cells, then a block barrier
+  auto phase = [&](int n, R* out, auto fn) {
+    R v[kTailPer];
+#pragma unroll
+    for (int u = 0; u < kTailPer; ++u) {
+      const int c = t + u * kTailThreads;
+      if (c < n) v[u] = fn(c);
+    }
+#pragma unroll
+    for (int u = 0; u < kTailPer; ++u) {
+      const int c = t + u * kTailThreads;
+      if (c < n) out[c] = v[u];
+    }
+    __syncthreads();
+  };
+  // LDS vectors of level l: X0 (the role of x2), X1 (of x), B (of b)
+  auto base = [&](int l) {
+    int off = 0;
+    for (int q = 0; q < l; ++q) off += 3 * (int)T.lv[q].n();
+    return sm + off;
+  };
+  auto X0 = [&](int l) { return base(l); };
+  auto X1 = [&](int l) { return base(l) + (int)T.lv[l].n(); };
+  auto Bv = [&](int l) { return base(l) + 2 * (int)T.lv[l].n(); };
+  {
+    const Level<R>& L = T.lv[0];
+    const int n = (int)L.n();
+    R* b0 = Bv(0);
+    R* x0 = X0(0);
+    phase(n, b0, [&](int c) { return L.b[c]; });
+    if (T.first_done) phase(n, x0, [&](int c) { return L.x2[c]; });
+    else phase(n, x0, [&](int c) { return R(T.wpre[0]) * L.wdiag[c] * b0[c]; });
+  }
+  // after the pre-smoothing of a level its iterate is in buffer (nu - 1) & 1
+  // of {X0, X1}, and buffer nu & 1 is free until the post-smoothing
+  for (int l = 0; l + 1 < T.nl; ++l) {
+    const Level<R>& L = T.lv[l];
+    const int n = (int)L.n();
+    auto buf = [&](int w) { return (w & 1) ? X1(l) : X0(l); };
+    const R* b = Bv(l);
+    int w = 1;
+    for (int q = 1; q < T.nu; ++q, ++w) {
+      const R* xi = buf(w - 1);
+      phase(n, buf(w), [&](int c) {
+        int i, j, k;
+        ijk(c, L.nx, L.ny, i, j, k);
+        return smooth_cell<R, DIM>(L, b, xi, R(T.wpre[q]), i, j, k, c);
+      });
+    }
+    const R* cur = buf(w - 1);
+    R* rs = buf(w);
+    // restriction into level l + 1 (and its first sweep unless it is the coarsest)
+    phase(n, rs, [&](int c) {
+      int i, j, k;
+      ijk(c, L.nx, L.ny, i, j, k);
+      return resid_cell<R, DIM>(L, b, cur, i, j, k);
+    });
+    const Level<R>& C = T.lv[l + 1];
+    const int nc = (int)C.n();
+    R* bc = Bv(l + 1);
+    phase(nc, bc, [&](int ci) {
+      int I, J, K;
+      ijk(ci, C.nx, C.ny, I, J, K);
+      R s = R(0);
+      for (int dk = 0; dk < kz; ++dk)
+        for (int dj = 0; dj < 2; ++dj)
+          for (int di = 0; di < 2; ++di) s += rs[cidx(2 * I + di, 2 * J + dj, kz * K + dk, L.nx, L.ny)];
+      return s;
+    });
+    if (l + 2 < T.nl) phase(nc, X0(l + 1), [&](int ci) { return R(T.wpre[0]) * C.wdiag[ci] * bc[ci]; });
+  }
+  // coarsest level: x = Minv b (dense inverse), else damped-Jacobi sweeps from zero
+  {
+    const int lc = T.nl - 1;
+    const Level<R>& L = T.lv[lc];
+    const int n = (int)L.n();
+    const R* b = Bv(lc);
+    R* x = X1(lc);
+    if (T.cinv) {
+      phase(n, x, [&](int i) {
+        const R* row = T.cinv + (long)i * n;
+        R s0 = R(0), s1 = R(0);
+        int j = 0;
+        for (; j + 1 < n; j += 2) {
+          s0 += row[j] * b[j];
+          s1 += row[j + 1] * b[j + 1];
+        }
+        if (j < n) s0 += row[j] * b[j];
+        return s0 + s1;
+      });
+    } else {
+      phase(n, x, [&](int) { return R(0); });
+      R* src = x;
+      R* dst = X0(lc);
+      for (int q = 0; q < T.csweeps; ++q) {
+        const R* xi = src;
+        phase(n, dst, [&](int c) {
+          int i, j, k;
+          ijk(c, L.nx, L.ny, i, j, k);
+          const R Kx = applyK<R, DIM>(xi, L.ax, L.ay, L.az, i, j, k, L.nx, L.ny, L.nz);
+          return xi[c] + R(T.cj) * L.wdiag[c] * (b[c] - Kx);
+        });
+        R* tmp = src;
+        src = dst;
+        dst = tmp;
+      }
+      if (src != x) {
+        const R* xi = src;
+        phase(n, x, [&](int c) { return xi[c]; });
+      }
+    }
+  }
+  for (int l = T.nl - 2; l >= 0; --l) {
+    const Level<R>& L = T.lv[l];
+    const Level<R>& C = T.lv[l + 1];
+    const int n = (int)L.n();
+    auto buf = [&](int w) { return (w & 1) ? X1(l) : X0(l); };
+    const R* b = Bv(l);
+    const R* e = X1(l + 1);
+    const R* cur = buf(T.nu - 1);
+    // the level's last write (buffer 1, the role of x) of level 0 goes to memory
+    auto dest = [&](int w) { return (l == 0 && w == 2 * T.nu - 1) ? L.x : buf(w); };
+    int w = T.nu;
+    phase(n, dest(w), [&](int c) {
+      int i, j, k;
+      ijk(c, L.nx, L.ny, i, j, k);
+      return prolong_smooth_cell<R, DIM>(L, C.nx, C.ny, e, b, cur, R(T.omc), R(T.wpost[0]), i, j, k);
+    });
+    ++w;
+    for (int q = 1; q < T.nu; ++q, ++w) {
+      const R* xi = buf(w - 1);
+      phase(n, dest(w), [&](int c) {
+        int i, j, k;
+        ijk(c, L.nx, L.ny, i, j, k);
+        return smooth_cell<R, DIM>(L, b, xi, R(T.wpost[q]), i, j, k, c);
+      });
+    }
   }
 }
 
@@ -1045,6 +1237,14 @@ template <class R>
 void coarse_apply(hipStream_t s, int n, const R* Minv, const R* b, R* out, const int* iflag) {
   hipLaunchKernelGGL((k_coarse_apply<R>), dim3(1), dim3(1024), 0, s, n, Minv, b, out, iflag);
 }
+
+template <class R>
+void mg_tail(hipStream_t s, int dim, const MgTail<R>& T, const int* iflag) {
+  if (dim == 3) hipLaunchKernelGGL((k_mg_tail<R, 3>), dim3(1), dim3(kTailThreads), 0, s, T, iflag);
+  else hipLaunchKernelGGL((k_mg_tail<R, 2>), dim3(1), dim3(kTailThreads), 0, s, T, iflag);
+}
+template void mg_tail<double>(hipStream_t, int, const MgTail<double>&, const int*);
+template void mg_tail<float>(hipStream_t, int, const MgTail<float>&, const int*);
 template void coarse_factor<double>(hipStream_t, int, const Level<double>&, double*, double*);
 template void coarse_factor<float>(hipStream_t, int, const Level<float>&, double*, float*);
 template void coarse_apply<double>(hipStream_t, int, const double*, const double*, double*, const int*);
