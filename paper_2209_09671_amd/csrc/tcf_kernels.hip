@@ -323,21 +323,32 @@ __global__ __launch_bounds__(256) void k_smooth(Level<R> L, const R* __restrict_
 }
 
 // bc = R (b - K x): each coarse cell sums the residuals of its children.
+// A 64 x 4 block owns a 64 x 4 x kz tile of fine cells (kz = 2 planes in
+// 3D): each thread computes the residuals of its column's kz cells into
+// LDS, then one thread per coarse cell of the tile (32 x 2) sums its
+// children in (dk, dj, di) order.
 template <class R, int DIM>
 __global__ __launch_bounds__(256) void k_resid_restrict(Level<R> F, int cnx, int cny, int cnz,
                                                         const R* __restrict__ b, const R* __restrict__ x,
                                                         R* __restrict__ bc, const R* __restrict__ wdc,
                                                         R* __restrict__ x1c, R om0, const int* __restrict__ iflag) {
   if (iflag[I_DONE]) return;
-  const int I = blockIdx.x * BX + threadIdx.x, J = blockIdx.y * BY + threadIdx.y, K = blockIdx.z;
+  constexpr int kz = DIM == 3 ? 2 : 1;
+  __shared__ R rs[kz][BY][BX];
+  const int tx = threadIdx.x, ty = threadIdx.y;
+  const int i = blockIdx.x * BX + tx, j = blockIdx.y * BY + ty, K = blockIdx.z;
+  if (i < F.nx && j < F.ny)
+    for (int dk = 0; dk < kz; ++dk) rs[dk][ty][tx] = resid_cell<R, DIM>(F, b, x, i, j, kz * K + dk);
+  __syncthreads();
+  const int t = tx + BX * ty;
+  if (t >= (BX / 2) * (BY / 2)) return;
+  const int ti = t % (BX / 2), tj = t / (BX / 2);
+  const int I = blockIdx.x * (BX / 2) + ti, J = blockIdx.y * (BY / 2) + tj;
   if (I >= cnx || J >= cny) return;
-  const int kz = DIM == 3 ? 2 : 1;
   R s = R(0);
   for (int dk = 0; dk < kz; ++dk)
     for (int dj = 0; dj < 2; ++dj)
-      for (int di = 0; di < 2; ++di) {
-        s += resid_cell<R, DIM>(F, b, x, 2 * I + di, 2 * J + dj, kz * K + dk);
-      }
+      for (int di = 0; di < 2; ++di) s += rs[dk][2 * tj + dj][2 * ti + di];
   const long ci = cidx(I, J, K, cnx, cny);
   bc[ci] = s;
   if (x1c) x1c[ci] = om0 * wdc[ci] * s;  // the coarse level's first sweep from zero
@@ -1195,7 +1206,7 @@ template <class R>
 void mg_resid_restrict(hipStream_t s, int dim, const Level<R>& F, const R* b, const R* x, R* bc, const R* wdc,
                        R* x1c, double om0, const int* iflag) {
   const int cnx = F.nx / 2, cny = F.ny / 2, cnz = dim == 3 ? F.nz / 2 : 1;
-  dim3 g = grid_for(cnx, cny, cnz);
+  dim3 g = grid_for(F.nx, F.ny, cnz);  // blocks of fine tiles, one coarse plane each
   if (dim == 3)
     hipLaunchKernelGGL((k_resid_restrict<R, 3>), g, blk(), 0, s, F, cnx, cny, cnz, b, x, bc, wdc, x1c, R(om0), iflag);
   else
