@@ -37,17 +37,29 @@ template <class R, int DIM>
 __global__ __launch_bounds__(256) void k_geometry(KParams P, const R* __restrict__ a, const R* __restrict__ T,
                                                   const R* __restrict__ cf, R* __restrict__ sk, R* __restrict__ Mx,
                                                   R* __restrict__ My, R* __restrict__ Mz) {
-  const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
+  // the in-plane normals of the block's tile and its one-cell ring (ghost
+  // cells included) are computed once into LDS; the two z neighbours' by
+  // each thread
+  __shared__ R sn[2][BY + 2][BX + 2];
+  const int tx = threadIdx.x, ty = threadIdx.y;
+  const int i = blockIdx.x * BX + tx, j = blockIdx.y * BY + ty, k = blockIdx.z;
   const int nx = P.nx, ny = P.ny, nz = P.nz;
-  if (i >= nx || j >= ny) return;
   const R ih2 = R(0.5 * P.ih), ne = R(P.neps);
+  for (int q = tx + BX * ty; q < (BX + 2) * (BY + 2); q += BX * BY) {
+    const int qx = q % (BX + 2), qy = q / (BX + 2);
+    const int ii = blockIdx.x * BX - 1 + qx, jj = blockIdx.y * BY - 1 + qy;
+    if (ii <= nx && jj <= ny) {
+      R nq[3];
+      normal_at<R, DIM>(a, ii, jj, k, nx, ny, nz, ih2, ne, nq);
+      sn[0][qy][qx] = nq[0];
+      sn[1][qy][qx] = nq[1];
+    }
+  }
+  __syncthreads();
+  if (i >= nx || j >= ny) return;
   R nn[3], np[3];
-  normal_at<R, DIM>(a, i + 1, j, k, nx, ny, nz, ih2, ne, np);
-  normal_at<R, DIM>(a, i - 1, j, k, nx, ny, nz, ih2, ne, nn);
-  R divn = (np[0] - nn[0]) * ih2;
-  normal_at<R, DIM>(a, i, j + 1, k, nx, ny, nz, ih2, ne, np);
-  normal_at<R, DIM>(a, i, j - 1, k, nx, ny, nz, ih2, ne, nn);
-  divn += (np[1] - nn[1]) * ih2;
+  R divn = (sn[0][ty + 1][tx + 2] - sn[0][ty + 1][tx]) * ih2;
+  divn += (sn[1][ty + 2][tx + 1] - sn[1][ty][tx + 1]) * ih2;
   if (DIM == 3) {
     normal_at<R, DIM>(a, i, j, k + 1, nx, ny, nz, ih2, ne, np);
     normal_at<R, DIM>(a, i, j, k - 1, nx, ny, nz, ih2, ne, nn);
