@@ -144,6 +144,7 @@ struct tcf_grid {
   int* iflag;
   double* hscal;  // pinned host mirror
   int* hflag;
+  hipEvent_t rb_ev = nullptr;  // completion of the last copy into hscal
   size_t bytes;
   // adjoint scratch (configs with TCF_WITH_ADJOINT; FP64 only)
   struct Adj {
@@ -477,6 +478,15 @@ hipError_t read_back(tcf_grid* g) {
   return hipStreamSynchronize(g->stream);
 }
 
+// The copy of read_back queued without waiting; wait_back blocks until it
+// has landed, while the stream may already run the work queued after it.
+hipError_t read_back_async(tcf_grid* g) {
+  hipError_t e = hipMemcpyAsync(g->hscal, g->scal, kScalBlockBytes, hipMemcpyDeviceToHost, g->stream);
+  if (e != hipSuccess) return e;
+  return hipEventRecord(g->rb_ev, g->stream);
+}
+hipError_t wait_back(tcf_grid* g) { return hipEventSynchronize(g->rb_ev); }
+
 // Launch constants of the pressure operator: the grid's, with the density
 // range of the operator's linear mix (no step size: for the solver only).
 KParams op_params(const tcf_grid* g) {
@@ -623,7 +633,13 @@ void vcycle(tcf_grid* g, Fields<R>& F, size_t l, const R* b, R* out, R* tmp, dou
 // PCG iterations on K x = rhs with r holding the initial residual and the
 // done flag / tolerance already set.  The search direction ping-pongs
 // between d and d2; the first Jacobi sweep of each preconditioner
-// application is fused into the x/r update.
+// application is fused into the x/r update.  The convergence flag of an
+// iteration is set with its residual norm, before its preconditioner: it is
+// copied to the host there, and the host waits for that copy (not for the
+// stream) while the preconditioner runs, then queues the next iteration.
+// Every kernel of the solve returns at once when the flag is set, so an
+// initial residual already below the tolerance ends after the first
+// iteration with no work done.
 template <class R>
 tcf_status pcg_iterate(tcf_grid* g, Fields<R>& F, R* x, R* r, int maxit, int* iters, bool* converged) {
   hipStream_t s = g->stream;
@@ -631,12 +647,6 @@ tcf_status pcg_iterate(tcf_grid* g, Fields<R>& F, R* x, R* r, int maxit, int* it
   const Fine<R> Fd = fine_desc<R>(g);
   const double wj = sweep_omega(dim, g->cfg.mg_nu, 0);  // first pre-smoothing sweep, fused into the update
   *converged = false;
-  HIPCHECK(read_back(g));
-  if (g->hflag[I_DONE]) {
-    *iters = 0;
-    *converged = true;
-    return TCF_OK;
-  }
   int np = 0;
   vcycle<R>(g, F, 0, r, F.z, F.z2, g->part[0], false, &np);
   finalize(s, g->part[0], np, g->scal, g->iflag, F_RZ_FIRST, 0, 0.0);
@@ -654,9 +664,10 @@ tcf_status pcg_iterate(tcf_grid* g, Fields<R>& F, R* x, R* r, int maxit, int* it
       np = fine_update_smooth<R>(s, dim, Fd, wj, g->scal, x, r, dcur, F.z2, g->part[0], g->iflag);
     }
     finalize(s, g->part[0], np, g->scal, g->iflag, F_RR, 0, 1.0);
+    HIPCHECK(read_back_async(g));
     vcycle<R>(g, F, 0, r, F.z, F.z2, g->part[0], true, &np);
     finalize(s, g->part[0], np, g->scal, g->iflag, F_RZ, 0, 0.0);
-    HIPCHECK(read_back(g));
+    HIPCHECK(wait_back(g));
     if (g->hflag[I_DONE]) break;
   }
   *iters = g->hflag[I_ITERS];
@@ -1248,6 +1259,11 @@ tcf_status tcf_init_grid(const tcf_config* cfg, void* workspace, size_t bytes, v
     return fail(TCF_E_DEVICE, "pinned host buffer allocation failed");
   }
   g->hflag = (int*)(g->hscal + S_NSLOT);
+  if (hipEventCreateWithFlags(&g->rb_ev, hipEventDisableTiming) != hipSuccess) {
+    hipHostFree(g->hscal);
+    delete g;
+    return fail(TCF_E_DEVICE, "event creation failed");
+  }
   // zero scalars and flags, the zero vector, and the pressure
   fill_f64(g->stream, S_NSLOT, g->scal, 0.0);
   init_flags(g->stream, g->iflag);
@@ -1255,6 +1271,7 @@ tcf_status tcf_init_grid(const tcf_config* cfg, void* workspace, size_t bytes, v
   fill_f64(g->stream, g->D.N, g->p64, 0.0);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) {
+    hipEventDestroy(g->rb_ev);
     hipHostFree(g->hscal);
     delete g;
     return fail(TCF_E_DEVICE, std::string("init kernels: ") + hipGetErrorString(e));
@@ -1467,6 +1484,7 @@ void tcf_destroy(tcf_grid* g) {
   if (!g) return;
   hipStreamSynchronize(g->stream);
   for (hipEvent_t e : g->prof_ev) hipEventDestroy(e);
+  if (g->rb_ev) hipEventDestroy(g->rb_ev);
   hipHostFree(g->hscal);
   delete g;
 }
