@@ -93,6 +93,130 @@ __global__ __launch_bounds__(256) void k_geometry(KParams P, const R* __restrict
   if (DIM == 3) Mz[c] = ds * (gs2 - n2 * ndg);
 }
 
+// The 3-D geometry marching along z: a 64 x 4 tile per block over a chunk
+// of planes.  alpha of planes k-1 .. k+2 with a two-cell ring (ghosts by
+// even reflection on load) sits in a five-slot LDS ring, so every plane of
+// alpha is read from memory once per tile; the in-plane normals of plane k
+// (tile and one-cell ring) are computed once into LDS and the own column's
+// z normal of plane k+1 is carried to the next two planes.  Every normal
+// and gradient is the same expression as in k_geometry, on the same values.
+constexpr int GX = BX + 4, GY = BY + 4, GR = 5;  // alpha tile with its ring, ring slots
+constexpr int GN = ((GX * GY) + BX * BY - 1) / (BX * BY);  // alpha loads per thread and plane
+
+template <class R>
+__global__ __launch_bounds__(256) void k_geometry_z(KParams P, int kz, int ntx, int nty, const R* __restrict__ a,
+                                                    const R* __restrict__ T, const R* __restrict__ cf,
+                                                    R* __restrict__ sk, R* __restrict__ Mx, R* __restrict__ My,
+                                                    R* __restrict__ Mz) {
+  __shared__ R sa[GR][GY][GX];
+  __shared__ R snx[BY + 2][BX + 2], sny[BY + 2][BX + 2];
+  const int nx = P.nx, ny = P.ny, nz = P.nz;
+  const int t = xcd_tile();
+  const int tx = threadIdx.x, ty = threadIdx.y, tid = tx + BX * ty;
+  const int i0 = (t % ntx) * BX, j0 = ((t / ntx) % nty) * BY, tz = t / (ntx * nty);
+  const int k0 = tz * kz, k1 = min(k0 + kz, nz);
+  const int i = i0 + tx, j = j0 + ty;
+  const bool act = i < nx && j < ny;
+  const R ih2 = R(0.5 * P.ih), ne = R(P.neps);
+  const size_t pl = (size_t)nx * ny;
+  // in-plane source offsets of this thread's ring-tile positions (positions
+  // past the ring map to a valid cell and are never read)
+  unsigned off[GN];
+  for (int q = 0; q < GN; ++q) {
+    const int e = tid + q * BX * BY;
+    const int ex = e % GX, ey = e / GX;
+    const int ri = min(max(refl(i0 - 2 + ex, nx), 0), nx - 1), rj = min(max(refl(j0 - 2 + ey, ny), 0), ny - 1);
+    off[q] = e < GX * GY ? (unsigned)(ri + nx * rj) : 0u;
+  }
+  auto plane = [&](int kk) { return (size_t)min(max(refl(kk, nz), 0), nz - 1) * pl; };
+  R v[GN];
+  auto load = [&](int kk) {
+    const size_t po = plane(kk);
+    for (int q = 0; q < GN; ++q) v[q] = a[po + off[q]];
+  };
+  auto store = [&](int kk) {
+    const int sl = ((kk % GR) + GR) % GR;
+    for (int q = 0; q < GN; ++q) {
+      const int e = tid + q * BX * BY;
+      if (e < GX * GY) sa[sl][e / GX][e % GX] = v[q];
+    }
+  };
+  auto slot = [&](int kk) { return ((kk % GR) + GR) % GR; };
+  for (int kk = k0 - 1; kk <= k0 + 2; ++kk) {
+    load(kk);
+    store(kk);
+  }
+  load(k0 + 3);
+  // z normals of the own column at planes k0 - 1 and k0
+  const int ic = min(i, nx - 1), jc = min(j, ny - 1);
+  R nq[3];
+  normal_at<R, 3>(a, ic, jc, k0 - 1, nx, ny, nz, ih2, ne, nq);
+  R nzm = nq[2];
+  normal_at<R, 3>(a, ic, jc, k0, nx, ny, nz, ih2, ne, nq);
+  R nzc = nq[2];
+  const int X = tx + 2, Y = ty + 2;  // own cell in the alpha tile
+  for (int k = k0; k < k1; ++k) {
+    __syncthreads();  // planes k-1 .. k+2 are in LDS; the previous plane's reads are done
+    const int sm = slot(k - 1), sc = slot(k), sp = slot(k + 1), sq = slot(k + 2);
+    // in-plane normals of plane k on the tile and its ring
+    for (int e = tid; e < (BX + 2) * (BY + 2); e += BX * BY) {
+      const int px = e % (BX + 2) + 1, py = e / (BX + 2) + 1;  // position in the alpha tile
+      const R gx = (sa[sc][py][px + 1] - sa[sc][py][px - 1]) * ih2;
+      const R gy = (sa[sc][py + 1][px] - sa[sc][py - 1][px]) * ih2;
+      const R gz = (sa[sp][py][px] - sa[sm][py][px]) * ih2;
+      const R inv = R(1) / sqrt(gx * gx + gy * gy + gz * gz + ne * ne);
+      snx[py - 1][px - 1] = gx * inv;
+      sny[py - 1][px - 1] = gy * inv;
+    }
+    // the own column's z normal of plane k + 1
+    R nzp;
+    {
+      const R gx = (sa[sp][Y][X + 1] - sa[sp][Y][X - 1]) * ih2;
+      const R gy = (sa[sp][Y + 1][X] - sa[sp][Y - 1][X]) * ih2;
+      const R gz = (sa[sq][Y][X] - sa[sc][Y][X]) * ih2;
+      const R inv = R(1) / sqrt(gx * gx + gy * gy + gz * gz + ne * ne);
+      nzp = gz * inv;
+    }
+    // plane k + 3 into the slot of plane k - 2 (no longer read), then prefetch k + 4
+    store(k + 3);
+    load(min(k + 4, nz + 2));
+    __syncthreads();
+    if (act) {
+      R divn = (snx[ty + 1][tx + 2] - snx[ty + 1][tx]) * ih2;
+      divn += (sny[ty + 2][tx + 1] - sny[ty][tx + 1]) * ih2;
+      divn += (nzp - nzm) * ih2;
+      const R kappa = -divn;
+      const R gx = (sa[sc][Y][X + 1] - sa[sc][Y][X - 1]) * ih2;
+      const R gy = (sa[sc][Y + 1][X] - sa[sc][Y - 1][X]) * ih2;
+      const R gz = (sa[sp][Y][X] - sa[sm][Y][X]) * ih2;
+      const R g2 = gx * gx + gy * gy + gz * gz;
+      const R ge = sqrt(g2 + ne * ne);
+      const R ds = g2 / (ge + ne);
+      const R n0 = gx / ge, n1 = gy / ge, n2 = gz / ge;
+      const long c = cidx(i, j, k, nx, ny);
+      const R s = R(P.s);
+      R sigma = R(P.sigma0) + s * (T[c] - R(P.T0));
+      R gs0 = s * (T_at<3>(T, i + 1, j, k, P) - T_at<3>(T, i - 1, j, k, P)) * ih2;
+      R gs1 = s * (T_at<3>(T, i, j + 1, k, P) - T_at<3>(T, i, j - 1, k, P)) * ih2;
+      R gs2 = s * (T_at<3>(T, i, j, k + 1, P) - T_at<3>(T, i, j, k - 1, P)) * ih2;
+      if (cf) {
+        const R sc_ = R(P.sc);
+        sigma += sc_ * (cf[c] - R(P.c0));
+        gs0 += sc_ * (A_at<3>(cf, i + 1, j, k, nx, ny, nz) - A_at<3>(cf, i - 1, j, k, nx, ny, nz)) * ih2;
+        gs1 += sc_ * (A_at<3>(cf, i, j + 1, k, nx, ny, nz) - A_at<3>(cf, i, j - 1, k, nx, ny, nz)) * ih2;
+        gs2 += sc_ * (A_at<3>(cf, i, j, k + 1, nx, ny, nz) - A_at<3>(cf, i, j, k - 1, nx, ny, nz)) * ih2;
+      }
+      const R ndg = n0 * gs0 + n1 * gs1 + n2 * gs2;
+      sk[c] = sigma * kappa;
+      Mx[c] = ds * (gs0 - n0 * ndg);
+      My[c] = ds * (gs1 - n1 * ndg);
+      Mz[c] = ds * (gs2 - n2 * ndg);
+    }
+    nzm = nzc;
+    nzc = nzp;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // S6: b = D u* / dt (FP64), block partial sums of b.
 template <class R, int DIM>
@@ -1130,9 +1254,17 @@ inline int nblk1(long n) { return (int)((n + 255) / 256); }
 // Launchers
 template <class R>
 void geometry(const KParams& P, hipStream_t s, const R* a, const R* T, const R* c, R* sk, R* Mx, R* My, R* Mz) {
-  dim3 g = grid_for(P.nx, P.ny, P.nz);
-  if (P.dim == 3) hipLaunchKernelGGL((k_geometry<R, 3>), g, blk(), 0, s, P, a, T, c, sk, Mx, My, Mz);
-  else hipLaunchKernelGGL((k_geometry<R, 2>), g, blk(), 0, s, P, a, T, c, sk, Mx, My, Mz);
+  if (P.dim == 3) {
+    // chunks of planes so that the grid has >= 2048 blocks of 256
+    const int ntx = (P.nx + BX - 1) / BX, nty = (P.ny + BY - 1) / BY;
+    int nch = std::max(1, std::min(P.nz, (2048 + ntx * nty - 1) / (ntx * nty)));
+    const int kz = (P.nz + nch - 1) / nch;
+    nch = (P.nz + kz - 1) / kz;
+    hipLaunchKernelGGL((k_geometry_z<R>), dim3(ntx * nty * nch), blk(), 0, s, P, kz, ntx, nty, a, T, c, sk, Mx, My,
+                       Mz);
+  } else {
+    hipLaunchKernelGGL((k_geometry<R, 2>), grid_for(P.nx, P.ny, 1), blk(), 0, s, P, a, T, c, sk, Mx, My, Mz);
+  }
 }
 
 template <class R>
