@@ -10,7 +10,10 @@
 // x-face fluxes: each lane computes its low face, the high face arrives from
 // the next lane by a wavefront shuffle (a wavefront is one 64-wide row).
 // y-face fluxes: each row computes its low face; the high face is read from
-// the next row through LDS.  WENO5 weights use one reciprocal per face.
+// the next row through LDS.  A WENO5 evaluation takes one reciprocal per
+// nonlinear weight and one for their normalisation, on the stencil picked
+// by the velocity's sign.  The kernel also runs in two other modes (below):
+// one passive cell field, or T alone with cell materials.
 #include <algorithm>
 
 #include "tcf_device.h"
