@@ -13,6 +13,7 @@
 // alpha_i (grad alpha for two phases) with the curvature and Marangoni
 // terms of eqs. 4-7.  One thread per cell or face on 64 x 4
 // blocks; ghost values by reflected indexing as in the two-phase kernels.
+#include <algorithm>
 #include <cfloat>
 #include <cmath>
 
@@ -201,6 +202,156 @@ __global__ __launch_bounds__(256) void k_np_geometry(KParams P, const R* __restr
   if (DIM == 3) Mz[c] = M2;
 }
 
+// 3-D pair geometry marching along z (one kernel): a 64 x 4 tile per block
+// over a chunk of planes.  The fractions of phases 2..N of planes k-1 ..
+// k+2 with a two-cell ring (ghosts by even reflection on load) sit in a
+// five-slot LDS ring per phase; for each pair the in-plane normals of plane
+// k (tile and one-cell ring) are computed once into LDS and the own
+// column's z normal of plane k+1 is carried.  The pair gradients, normals,
+// deltas and the rest are the expressions of the two-pass kernels above,
+// whose stored normals at ghost cells are the same values.
+constexpr int NGX = BX + 4, NGY = BY + 4, NGR = 5;
+constexpr int NGN = (NGX * NGY + BX * BY - 1) / (BX * BY);
+
+template <class R, int NPH>
+__global__ __launch_bounds__(256) void k_np_geometry_z(KParams P, int kz, int ntx, int nty, Phases<R> F,
+                                                       const R* __restrict__ T, R* __restrict__ skp,
+                                                       R* __restrict__ Mx, R* __restrict__ My, R* __restrict__ Mz) {
+  constexpr int NF = NPH - 1, NP = PairList<NPH>::n;
+  __shared__ R sa[NF][NGR][NGY][NGX];
+  __shared__ R snx[NP][BY + 2][BX + 2], sny[NP][BY + 2][BX + 2];
+  const int nx = P.nx, ny = P.ny, nz = P.nz;
+  const int t = xcd_tile();
+  const int tx = threadIdx.x, ty = threadIdx.y, tid = tx + BX * ty;
+  const int i0 = (t % ntx) * BX, j0 = ((t / ntx) % nty) * BY, tz = t / (ntx * nty);
+  const int k0 = tz * kz, k1 = min(k0 + kz, nz);
+  const int i = i0 + tx, j = j0 + ty;
+  const bool act = i < nx && j < ny;
+  const R ih2 = R(0.5 * P.ih), ne = R(P.neps);
+  const size_t pl = (size_t)nx * ny;
+  const long N = (long)nx * ny * nz;
+  const R* src[3] = {F.a2, F.a3, F.a4};
+  unsigned off[NGN];
+  for (int q = 0; q < NGN; ++q) {
+    const int e = tid + q * BX * BY;
+    const int ex = e % NGX, ey = e / NGX;
+    const int ri = min(max(refl(i0 - 2 + ex, nx), 0), nx - 1), rj = min(max(refl(j0 - 2 + ey, ny), 0), ny - 1);
+    off[q] = e < NGX * NGY ? (unsigned)(ri + nx * rj) : 0u;
+  }
+  auto plane = [&](int kk) { return (size_t)min(max(refl(kk, nz), 0), nz - 1) * pl; };
+  auto slot = [](int kk) { return ((kk % NGR) + NGR) % NGR; };
+  R v[NF][NGN];
+  auto load = [&](int kk) {
+    const size_t po = plane(kk);
+    for (int f = 0; f < NF; ++f)
+      for (int q = 0; q < NGN; ++q) v[f][q] = src[f][po + off[q]];
+  };
+  auto store = [&](int kk) {
+    const int sl = slot(kk);
+    for (int q = 0; q < NGN; ++q) {
+      const int e = tid + q * BX * BY;
+      if (e < NGX * NGY)
+        for (int f = 0; f < NF; ++f) sa[f][sl][e / NGX][e % NGX] = v[f][q];
+    }
+  };
+  // fraction of phase q (1..NPH) at tile position (x, y) of a slot
+  auto ph = [&](int q, int sl, int y, int x) {
+    if (q >= 2) return sa[q - 2][sl][y][x];
+    R sm = sa[0][sl][y][x] + sa[1][sl][y][x];
+    if (NPH == 4) sm += sa[NF - 1][sl][y][x];
+    return R(1) - sm;
+  };
+  // pair gradient of pair p at tile position (x, y) of plane slot sc (z
+  // neighbours in slots sm, sp)
+  auto grad = [&](int p, int sm, int sc, int sp, int y, int x, R g[3]) {
+    const int I = PairList<NPH>::I(p), J = PairList<NPH>::J(p);
+    const R ai = ph(I, sc, y, x), aj = ph(J, sc, y, x);
+    auto dx = [&](int q) { return (ph(q, sc, y, x + 1) - ph(q, sc, y, x - 1)) * ih2; };
+    auto dy = [&](int q) { return (ph(q, sc, y + 1, x) - ph(q, sc, y - 1, x)) * ih2; };
+    auto dz = [&](int q) { return (ph(q, sp, y, x) - ph(q, sm, y, x)) * ih2; };
+    g[0] = ai * dx(J) - aj * dx(I);
+    g[1] = ai * dy(J) - aj * dy(I);
+    g[2] = ai * dz(J) - aj * dz(I);
+  };
+  for (int kk = k0 - 1; kk <= k0 + 2; ++kk) {
+    load(kk);
+    store(kk);
+  }
+  load(k0 + 3);
+  const int ic = min(i, nx - 1), jc = min(j, ny - 1);
+  R nzm[NP], nzc[NP];
+  for (int p = 0; p < NP; ++p) {
+    R g[3];
+    pair_grad<R, 3, NPH>(F, PairList<NPH>::I(p), PairList<NPH>::J(p), ic, jc, k0 - 1, nx, ny, nz, ih2, g);
+    R g2 = g[0] * g[0] + g[1] * g[1] + g[2] * g[2];
+    nzm[p] = g[2] / sqrt(g2 + ne * ne);
+    pair_grad<R, 3, NPH>(F, PairList<NPH>::I(p), PairList<NPH>::J(p), ic, jc, k0, nx, ny, nz, ih2, g);
+    g2 = g[0] * g[0] + g[1] * g[1] + g[2] * g[2];
+    nzc[p] = g[2] / sqrt(g2 + ne * ne);
+  }
+  const int X = tx + 2, Y = ty + 2;
+  for (int k = k0; k < k1; ++k) {
+    __syncthreads();
+    const int sm = slot(k - 1), sc = slot(k), sp = slot(k + 1), sq = slot(k + 2);
+    for (int e = tid; e < (BX + 2) * (BY + 2); e += BX * BY) {
+      const int px = e % (BX + 2) + 1, py = e / (BX + 2) + 1;
+      for (int p = 0; p < NP; ++p) {
+        R g[3];
+        grad(p, sm, sc, sp, py, px, g);
+        const R g2 = g[0] * g[0] + g[1] * g[1] + g[2] * g[2];
+        const R ge = sqrt(g2 + ne * ne);
+        snx[p][py - 1][px - 1] = g[0] / ge;
+        sny[p][py - 1][px - 1] = g[1] / ge;
+      }
+    }
+    R nzp[NP];
+    for (int p = 0; p < NP; ++p) {
+      R g[3];
+      grad(p, sc, sp, sq, Y, X, g);
+      const R g2 = g[0] * g[0] + g[1] * g[1] + g[2] * g[2];
+      nzp[p] = g[2] / sqrt(g2 + ne * ne);
+    }
+    store(k + 3);
+    load(min(k + 4, nz + 2));
+    __syncthreads();
+    if (act) {
+      const long c = cidx(i, j, k, nx, ny);
+      const R Tc = T[c];
+      const R dT0 = (T_at<3>(T, i + 1, j, k, P) - T_at<3>(T, i - 1, j, k, P)) * ih2;
+      const R dT1 = (T_at<3>(T, i, j + 1, k, P) - T_at<3>(T, i, j - 1, k, P)) * ih2;
+      const R dT2 = (T_at<3>(T, i, j, k + 1, P) - T_at<3>(T, i, j, k - 1, P)) * ih2;
+      R M0 = R(0), M1 = R(0), M2 = R(0);
+      for (int p = 0; p < NP; ++p) {
+        const int sl = PairList<NPH>::slot(p);
+        R g[3];
+        grad(p, sm, sc, sp, Y, X, g);
+        const R g2 = g[0] * g[0] + g[1] * g[1] + g[2] * g[2];
+        const R ge = sqrt(g2 + ne * ne);
+        const R n0 = g[0] / ge, n1 = g[1] / ge, n2 = g[2] / ge;
+        const R ds = g2 / (ge + ne);
+        R divn = (snx[p][ty + 1][tx + 2] - snx[p][ty + 1][tx]) * ih2;
+        divn += (sny[p][ty + 2][tx + 1] - sny[p][ty][tx + 1]) * ih2;
+        divn += (nzp[p] - nzm[p]) * ih2;
+        const R sT = R(P.dsigp[sl]);
+        const R sigma = R(P.sig0p[sl]) + sT * (Tc - R(P.T0));
+        const R gs0 = sT * dT0, gs1 = sT * dT1, gs2 = sT * dT2;
+        const R ndg = n0 * gs0 + n1 * gs1 + n2 * gs2;
+        M0 += ds * (gs0 - n0 * ndg);
+        M1 += ds * (gs1 - n1 * ndg);
+        M2 += ds * (gs2 - n2 * ndg);
+        skp[p * N + c] = sigma * -divn;
+      }
+      Mx[c] = M0;
+      My[c] = M1;
+      Mz[c] = M2;
+    }
+    for (int p = 0; p < NP; ++p) {
+      nzm[p] = nzc[p];
+      nzc[p] = nzp[p];
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Face CSF force of direction D: 1/2 (M_L + M_R)_D plus, per pair,
 // 1/2 (skp_L + skp_R) times the face pair gradient avg(alpha_i)(alpha_j,R -
@@ -268,7 +419,17 @@ void np_mixture(const KParams& P, hipStream_t s, const R* a2, const R* a3, const
 template <class R, int DIM, int NPH>
 static void geometry_dim(const KParams& P, hipStream_t s, const Phases<R>& F, const R* T, R* nrm, R* dsp, R* skp,
                          R* Mx, R* My, R* Mz) {
-  const dim3 g = grid_np(P.nx, P.ny, DIM == 3 ? P.nz : 1);
+  if (DIM == 3) {
+    // chunks of planes so that the grid has >= 2048 blocks of 256
+    const int ntx = (P.nx + BX - 1) / BX, nty = (P.ny + BY - 1) / BY;
+    int nch = std::max(1, std::min(P.nz, (2048 + ntx * nty - 1) / (ntx * nty)));
+    const int kz = (P.nz + nch - 1) / nch;
+    nch = (P.nz + kz - 1) / kz;
+    hipLaunchKernelGGL((k_np_geometry_z<R, NPH>), dim3(ntx * nty * nch), blk_np(), 0, s, P, kz, ntx, nty, F, T, skp,
+                       Mx, My, Mz);
+    return;
+  }
+  const dim3 g = grid_np(P.nx, P.ny, 1);
   hipLaunchKernelGGL((k_np_normals<R, DIM, NPH>), g, blk_np(), 0, s, P, F, nrm, dsp);
   hipLaunchKernelGGL((k_np_geometry<R, DIM, NPH>), g, blk_np(), 0, s, P, nrm, dsp, T, skp, Mx, My, Mz);
 }
