@@ -176,3 +176,18 @@ def test_nphase_state_errors():
         g.set_phases(z)
     assert ei.value.status == tcf.TCF_E_STATE
     g.close()
+
+
+def test_meltpool_three_phases_full_size_properties():
+    """256^3 gas / liquid / solid melt pool in the benchmark's launch
+    configuration (FP32 + refinement): two steps, finite fields, converged
+    solves, FP64 divergence residual <= 1e-8, the volume of every phase
+    conserved."""
+    c = I.meltpool_phases(dict(I.config(4), p_rtol=1e-8))
+    st = I.phase_state(c)
+    g, info = gpu_run(c, st, c["dt"], 2, precision=1)
+    assert info["status"] == 0 and info["nonfinite"] == 0, info
+    assert info["div_rel"] <= 1e-8, info
+    for k in ("alpha", "alpha3"):
+        s0 = float(st[k].sum())
+        assert abs(float(g[k].sum()) - s0) <= 1e-6 * s0, k

@@ -135,3 +135,17 @@ def test_rk3p_rejected_with_adjoint_and_bad_value():
     with pytest.raises(tcf.TcfError) as ei:
         tcf.Grid(dict(I.config(0), integrator=3), precision=0)
     assert ei.value.status == tcf.TCF_E_INVALID
+
+
+def test_rk3p_full_size_meltpool_256_properties():
+    """256^3 melt pool in the benchmark's launch configuration for the
+    time-accurate integrator (FP32 + refinement): two steps, finite fields,
+    every stage's solve converged (status 0), FP64 divergence residual of
+    the last projection <= 1e-8, alpha conserved."""
+    c = dict(I.config(4), integrator=1, p_rtol=1e-8)
+    st = I.initial_state(c)
+    g, info = gpu_run(c, st, c["dt"], 2, precision=1)
+    assert info["status"] == 0 and info["nonfinite"] == 0, info
+    assert info["div_rel"] <= 1e-8, info
+    s0 = st["alpha"].sum()
+    assert abs(float(g["alpha"].sum()) - s0) <= 1e-6 * s0
