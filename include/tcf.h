@@ -98,6 +98,13 @@ typedef struct tcf_config {
   int refine_maxit;        /* FP64 refinement sweeps limit (FP32 mode) */
   int mg_levels;           /* 0 = automatic */
   int mg_nu;               /* Jacobi sweeps before and after the coarse correction */
+  /* Initial guess of each step's pressure solve.  0: the last pressure.
+   * 1: the linear extrapolation in time 2 p^n - p^(n-1), once the grid holds
+   * the previous pressure (from its second step on, or after
+   * tcf_set_pressure_history).  Only the iteration count changes: the solve
+   * still runs to p_rtol.  No effect with integrator 1 or
+   * TCF_WITH_ADJOINT. */
+  int p_extrapolate;
   /* Solutal Marangoni (eq. 5: the surface-tension gradient is the chain rule
    * over temperature and concentration; in-situ alloying).  species = 1
    * carries a concentration field c (cell centres, set with tcf_set_species)
@@ -164,6 +171,16 @@ tcf_status tcf_set_fields(tcf_grid* g, double t, const double* alpha, const doub
 /* Copy the state out (device FP64 pointers; any may be NULL to skip). */
 tcf_status tcf_get_fields(const tcf_grid* g, double* t, double* alpha, double* T, double* u, double* v,
                           double* w, double* p);
+
+/* Previous pressure p^(n-1) of the extrapolated initial guess
+ * (p_extrapolate = 1): copy out / in (device FP64, cell layout like p), so
+ * that a run restarted from tcf_get_fields plus this field repeats the
+ * uninterrupted run bitwise.  tcf_set_fields clears it; set with NULL
+ * clears it too.  TCF_E_STATE on a grid that does not extrapolate or (get)
+ * holds no previous pressure; TCF_E_INVALID on a NULL grid or (get) a NULL
+ * pointer. */
+tcf_status tcf_get_pressure_history(const tcf_grid* g, double* p_prev);
+tcf_status tcf_set_pressure_history(tcf_grid* g, const double* p_prev);
 
 /* Species field of a grid made with species = 1: copy in / out (device FP64,
  * nx*ny*nz cells in the layout above).  TCF_E_STATE on a grid without a

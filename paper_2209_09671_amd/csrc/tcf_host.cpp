@@ -127,6 +127,8 @@ struct tcf_grid {
   bool fp32;
   bool has_fields = false;
   bool has_species = false;  // species field set (configs with species = 1)
+  double* pprev = nullptr;   // previous pressure of the extrapolated guess (p_extrapolate = 1)
+  bool has_pprev = false;
   bool has_phases = false;   // fractions of phases 3 (and 4) set (N-phase configs)
   int nph = 2;               // number of phases
   double op_rho1 = 0.0, op_rho2 = 0.0;  // density range of the pressure operator's linear mix
@@ -305,6 +307,12 @@ void carve_fields(Carver& cv, const Dims& D, Fields<R>& F, int mg_levels, bool a
   }
 }
 
+// The extrapolated initial guess is used by the one-solve integrators of
+// the forward step only.
+bool extrapolates(const tcf_config* c) {
+  return c->p_extrapolate == 1 && c->integrator == 0 && !(c->flags & TCF_WITH_ADJOINT);
+}
+
 size_t carve(const tcf_config* c, void* base, tcf_grid* g) {
   Dims D = dims_of(c);
   Carver cv(base);
@@ -317,6 +325,7 @@ size_t carve(const tcf_config* c, void* base, tcf_grid* g) {
   G->b64 = cv.take<double>(D.N);
   G->r64 = cv.take<double>(D.N);
   G->zero64 = cv.take<double>(D.N);
+  if (extrapolates(c)) G->pprev = cv.take<double>(D.N);
   if (c->integrator == 1) {
     G->un64 = cv.take<double>(D.Nu);
     G->vn64 = cv.take<double>(D.Nv);
@@ -415,6 +424,7 @@ std::string validate(const tcf_config* c) {
   if (c->p_maxit < 1) return "p_maxit must be >= 1";
   if (c->mg_nu < 1 || c->mg_nu > 8) return "mg_nu must be in 1..8";
   if (c->mg_levels < 0) return "mg_levels must be >= 0";
+  if (c->p_extrapolate != 0 && c->p_extrapolate != 1) return "p_extrapolate must be 0 or 1";
   if (c->precision == TCF_FP32_REFINE && (!(c->inner_rtol > 0 && c->inner_rtol < 1) || c->refine_maxit < 1))
     return "FP32 mode needs 0 < inner_rtol < 1 and refine_maxit >= 1";
   return "";
@@ -885,6 +895,19 @@ void prepare_state_operator(tcf_grid* g) {
   }
 }
 
+// Initial guess of the step's pressure solve (p_extrapolate = 1): p <- 2 p -
+// p_prev with p_prev <- p, once the previous pressure is held; before that
+// the last pressure, which becomes p_prev.
+void pressure_guess(tcf_grid* g) {
+  if (!g->pprev) return;
+  if (g->has_pprev) {
+    extrapolate_f64(g->stream, g->D.N, g->p64, g->pprev);
+  } else {
+    copy_f64(g->stream, g->D.N, g->p64, g->pprev);
+    g->has_pprev = true;
+  }
+}
+
 // One step of the N-phase model (integrator 0): SSP-RK3 transport of alpha,
 // T and the fractions of phases 3 (and 4) with u^n frozen, each stage's T
 // right-hand side with the mixture of that stage's fractions; then the
@@ -924,6 +947,7 @@ tcf_status step_np(tcf_grid* g, double dt, tcf_step_info* inf, bool want_diag) {
     double lo, hi;
     np_rho_range(g, &lo, &hi);
     prepare_operator<R>(g, F.marho, lo, hi);  // F.marho: the mixture of the new fractions
+    pressure_guess(g);
     st = solve(g, g->p64, inf);
     if (st != TCF_OK && st != TCF_E_NOT_CONVERGED) return st;
     KParams Pp = P;  // this step's constants with the operator's density range
@@ -991,6 +1015,7 @@ tcf_status step_once(tcf_grid* g, double dt, tcf_step_info* inf, bool want_diag)
     finalize(s, g->part[0], nbc, g->scal, g->iflag, F_MEAN, S_MEAN, (double)D.N);
     // S7
     prepare_operator<R>(g);
+    pressure_guess(g);
     st = solve(g, g->p64, inf);
     if (st != TCF_OK && st != TCF_E_NOT_CONVERGED) return st;
     // S8
@@ -1309,6 +1334,7 @@ tcf_status tcf_set_fields(tcf_grid* g, double t, const double* alpha, const doub
   HIPCHECK(hipGetLastError());
   g->t = t;
   g->has_fields = true;
+  g->has_pprev = false;
   return TCF_OK;
 }
 
@@ -1333,6 +1359,32 @@ tcf_status tcf_get_fields(const tcf_grid* gc, double* t, double* alpha, double* 
   if (w && D.dim == 3) copy_f64(s, D.Nw, g->w64, w);
   if (p) copy_f64(s, D.N, g->p64, p);
   HIPCHECK(hipGetLastError());
+  return TCF_OK;
+}
+
+tcf_status tcf_get_pressure_history(const tcf_grid* gc, double* p_prev) {
+  g_err.clear();
+  if (!gc) return fail(TCF_E_INVALID, "grid is NULL");
+  tcf_grid* g = const_cast<tcf_grid*>(gc);
+  if (!g->pprev) return fail(TCF_E_STATE, "the grid does not extrapolate the pressure");
+  if (!g->has_pprev) return fail(TCF_E_STATE, "no previous pressure held");
+  if (!p_prev) return fail(TCF_E_INVALID, "p_prev must be non-NULL");
+  copy_f64(g->stream, g->D.N, g->pprev, p_prev);
+  HIPCHECK(hipGetLastError());
+  return TCF_OK;
+}
+
+tcf_status tcf_set_pressure_history(tcf_grid* g, const double* p_prev) {
+  g_err.clear();
+  if (!g) return fail(TCF_E_INVALID, "grid is NULL");
+  if (!g->pprev) return fail(TCF_E_STATE, "the grid does not extrapolate the pressure");
+  if (!p_prev) {
+    g->has_pprev = false;
+    return TCF_OK;
+  }
+  copy_f64(g->stream, g->D.N, p_prev, g->pprev);
+  HIPCHECK(hipGetLastError());
+  g->has_pprev = true;
   return TCF_OK;
 }
 

@@ -250,6 +250,8 @@ void rk_combine(hipStream_t s, long n, int stage, const double* base, R* x);
 void to_f32(hipStream_t s, long n, const double* x, float* y);
 void to_f64(hipStream_t s, long n, const float* x, double* y);
 void copy_f64(hipStream_t s, long n, const double* x, double* y);
+// p <- 2 p - pp and pp <- the old p (linear extrapolation in time)
+void extrapolate_f64(hipStream_t s, long n, double* p, double* pp);
 void fill_f64(hipStream_t s, long n, double* y, double v);
 template <class R>
 void zero_walls(const KParams& P, hipStream_t s, R* u, R* v, R* w);

@@ -1216,6 +1216,14 @@ __global__ __launch_bounds__(256) void k_to_f64(long n, const float* __restrict_
   const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (c < n) y[c] = (double)x[c];
 }
+__global__ __launch_bounds__(256) void k_extrapolate64(long n, double* __restrict__ p, double* __restrict__ pp) {
+  const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  const double pc = p[c];
+  p[c] = 2.0 * pc - pp[c];
+  pp[c] = pc;
+}
+
 __global__ __launch_bounds__(256) void k_copy64(long n, const double* __restrict__ x, double* __restrict__ y) {
   const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (c < n) y[c] = x[c];
@@ -1507,6 +1515,10 @@ void to_f32(hipStream_t s, long n, const double* x, float* y) {
 void to_f64(hipStream_t s, long n, const float* x, double* y) {
   hipLaunchKernelGGL(k_to_f64, dim3(nblk1(n)), dim3(256), 0, s, n, x, y);
 }
+void extrapolate_f64(hipStream_t s, long n, double* p, double* pp) {
+  hipLaunchKernelGGL(k_extrapolate64, dim3(nblk1(n)), dim3(256), 0, s, n, p, pp);
+}
+
 void copy_f64(hipStream_t s, long n, const double* x, double* y) {
   hipLaunchKernelGGL(k_copy64, dim3(nblk1(n)), dim3(256), 0, s, n, x, y);
 }

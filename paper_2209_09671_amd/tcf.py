@@ -40,7 +40,7 @@ class TcfConfig(C.Structure):
                 ("q_vx", C.c_double), ("q_vy", C.c_double),
                 ("weno_eps", C.c_double), ("normal_eps", C.c_double),
                 ("p_rtol", C.c_double), ("p_maxit", C.c_int), ("inner_rtol", C.c_double),
-                ("refine_maxit", C.c_int), ("mg_levels", C.c_int), ("mg_nu", C.c_int),
+                ("refine_maxit", C.c_int), ("mg_levels", C.c_int), ("mg_nu", C.c_int), ("p_extrapolate", C.c_int),
                 ("species", C.c_int), ("dsigma_dc", C.c_double), ("c0", C.c_double),
                 ("integrator", C.c_int),
                 ("nphases", C.c_int), ("rho34", C.c_double * 2), ("mu34", C.c_double * 2),
@@ -57,7 +57,8 @@ class TcfStepInfo(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
-EXPORTS = ["tcf_workspace_bytes", "tcf_init_grid", "tcf_set_fields", "tcf_get_fields", "tcf_set_species",
+EXPORTS = ["tcf_workspace_bytes", "tcf_init_grid", "tcf_set_fields", "tcf_get_fields",
+           "tcf_get_pressure_history", "tcf_set_pressure_history", "tcf_set_species",
            "tcf_get_species", "tcf_set_phases", "tcf_get_phases", "tcf_step",
            "tcf_solve_pressure", "tcf_predictor", "tcf_apply_A", "tcf_step_backward", "tcf_adjoint_transport",
            "tcf_adjoint_predictor", "tcf_profile", "tcf_profile_read", "tcf_destroy", "tcf_last_error"]
@@ -83,6 +84,10 @@ def load():
     lib.tcf_set_fields.argtypes = [vp, C.c_double, vp, vp, vp, vp, vp, vp]
     lib.tcf_get_fields.restype = st
     lib.tcf_get_fields.argtypes = [vp, C.POINTER(C.c_double), vp, vp, vp, vp, vp, vp]
+    lib.tcf_get_pressure_history.restype = st
+    lib.tcf_get_pressure_history.argtypes = [vp, vp]
+    lib.tcf_set_pressure_history.restype = st
+    lib.tcf_set_pressure_history.argtypes = [vp, vp]
     lib.tcf_set_species.restype = st
     lib.tcf_set_species.argtypes = [vp, vp]
     lib.tcf_get_species.restype = st
@@ -137,6 +142,7 @@ def make_config(c: dict, precision=None, flags=None) -> TcfConfig:
     o.p_rtol, o.p_maxit = c["p_rtol"], c["p_maxit"]
     o.inner_rtol, o.refine_maxit = c["inner_rtol"], c["refine_maxit"]
     o.mg_levels, o.mg_nu = c["mg_levels"], c["mg_nu"]
+    o.p_extrapolate = int(c.get("p_extrapolate", 1))
     o.species = int(c.get("species", 0))
     o.dsigma_dc, o.c0 = float(c.get("dsigma_dc", 0.0)), float(c.get("c0", 0.0))
     o.integrator = int(c.get("integrator", 0))
@@ -206,7 +212,13 @@ class Grid:
         _check(load().tcf_set_fields(self.h, C.c_double(t), *[_ptr(x) for x in ts]))
 
     def set_state(self, st: dict, t=0.0):
+        """Fields (and, when given, the species, the phases and the previous
+        pressure of the extrapolated guess, as get_fields returns them)."""
         self.set_fields(t, st["alpha"], st["T"], st["u"], st["v"], st.get("w"), st.get("p"))
+        if st.get("p_prev") is not None:
+            pp = self._t(st["p_prev"])
+            self._keep_pp = pp
+            _check(load().tcf_set_pressure_history(self.h, _ptr(pp)))
         if st.get("c") is not None:
             self.set_species(st["c"])
         if st.get("alpha3") is not None:
@@ -246,6 +258,12 @@ class Grid:
         _check(load().tcf_get_fields(self.h, C.byref(t), _ptr(out["alpha"]), _ptr(out["T"]), _ptr(out["u"]),
                                      _ptr(out["v"]), _ptr(out["w"]), _ptr(out["p"])))
         out["t"] = t.value
+        # the previous pressure of the extrapolated initial guess, if held
+        pp = torch.empty(s["cell"], dtype=torch.float64, device=self.device)
+        st = load().tcf_get_pressure_history(self.h, _ptr(pp))
+        if st not in (TCF_OK, TCF_E_STATE):
+            raise TcfError(st, load().tcf_last_error().decode())
+        out["p_prev"] = pp if st == TCF_OK else None
         return out
 
     def step(self, dt, nsteps=1, info=True, check=True):

@@ -100,7 +100,7 @@ def test_species_workspace_and_validation():
 def test_time_accurate_integrator_workspace_and_validation():
     """Integrator 1 keeps the step's base velocity (three FP64 face arrays);
     the integrator must be 0/1 and 1 is not combined with the adjoint."""
-    c = I.config(3)
+    c = dict(I.config(3), p_extrapolate=0)
     nf = 3 * (c["nx"] + 1) * c["ny"] * c["nz"]
     for prec in (0, 1):
         extra = tcf.workspace_bytes(dict(c, integrator=1), precision=prec) - tcf.workspace_bytes(c, precision=prec)
@@ -147,3 +147,25 @@ def test_species_entry_points_reject_null():
     lib = tcf.load()
     assert lib.tcf_set_species(None, None) == tcf.TCF_E_INVALID
     assert lib.tcf_get_species(None, None) == tcf.TCF_E_INVALID
+
+
+def test_pressure_extrapolation_workspace_and_validation():
+    """p_extrapolate = 1 keeps the previous pressure (one FP64 cell array) on
+    grids whose integrator solves once per step; it must be 0/1, and has no
+    effect (no storage) with integrator 1 or the adjoint."""
+    c = I.config(3)
+    N = c["nx"] * c["ny"] * c["nz"]
+    on, off = dict(c, p_extrapolate=1), dict(c, p_extrapolate=0)
+    for prec in (0, 1):
+        d = tcf.workspace_bytes(on, precision=prec) - tcf.workspace_bytes(off, precision=prec)
+        assert 8 * N <= d < 8 * N + 4096
+    assert tcf.workspace_bytes(dict(c, p_extrapolate=2)) == 0
+    assert tcf.workspace_bytes(dict(on, integrator=1)) == tcf.workspace_bytes(dict(off, integrator=1))
+    assert (tcf.workspace_bytes(on, precision=0, flags=tcf.TCF_WITH_ADJOINT)
+            == tcf.workspace_bytes(off, precision=0, flags=tcf.TCF_WITH_ADJOINT))
+
+
+def test_pressure_history_entry_points_reject_null():
+    lib = tcf.load()
+    assert lib.tcf_get_pressure_history(None, None) == tcf.TCF_E_INVALID
+    assert lib.tcf_set_pressure_history(None, None) == tcf.TCF_E_INVALID

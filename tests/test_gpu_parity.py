@@ -279,3 +279,28 @@ def test_full_size_meltpool_256_matches_oracle():
         assert e[k] <= 1e-4, e
     assert e["p"] <= 2e-5, e
     assert info["div_rel"] <= 1e-8, info
+
+
+def test_extrapolated_pressure_guess_agrees_and_saves_iterations():
+    """The extrapolated initial guess 2 p^n - p^(n-1) changes only the
+    iteration count: over 10 FP64 steps of the 2D droplet and of a 64 x 32 x
+    32 melt pool the fields agree with the last-pressure guess to the solve
+    tolerance, and the CG iterations do not increase."""
+    for c0, dt in ((I.config(0), None), (I.custom(I.config(2), nx=64, ny=32, nz=32), 1e-8)):
+        c0 = dict(c0, p_rtol=1e-11)
+        dt = dt or c0["dt"]
+        st = I.initial_state(c0)
+        res = {}
+        for ex in (0, 1):
+            c = dict(c0, p_extrapolate=ex)
+            print(f"[gpu] extrapolate={ex} {c['nx']}x{c['ny']}x{c['nz']}", flush=True)
+            g = tcf.Grid(c, precision=0)
+            g.set_state(st)
+            iters = 0
+            for _ in range(10):
+                iters += g.step(dt, 1)["cg_iters"]
+            res[ex] = (host(g.get_fields()), iters)
+            g.close()
+        e = field_errors(res[1][0], res[0][0])
+        assert max(e.values()) <= 1e-8, e
+        assert res[1][1] <= res[0][1], (res[0][1], res[1][1])
