@@ -98,9 +98,11 @@ typedef struct tcf_config {
   int refine_maxit;        /* FP64 refinement sweeps limit (FP32 mode) */
   int mg_levels;           /* 0 = automatic */
   int mg_nu;               /* Jacobi sweeps before and after the coarse correction */
-  /* Initial guess of each step's pressure solve.  0: the last pressure.
-   * 1: the linear extrapolation in time 2 p^n - p^(n-1), once the grid holds
-   * the previous pressure (from its second step on, or after
+  /* Initial guess of each step's pressure solve: the polynomial
+   * extrapolation in time of order p_extrapolate (0, 1 or 2) through the
+   * last pressures, 0: p^n; 1: 2 p^n - p^(n-1); 2: 3 p^n - 3 p^(n-1) +
+   * p^(n-2).  The order is limited by the previous pressures the grid holds
+   * (none after tcf_set_fields; one more after each step, or as given to
    * tcf_set_pressure_history).  Only the iteration count changes: the solve
    * still runs to p_rtol.  No effect with integrator 1 or
    * TCF_WITH_ADJOINT. */
@@ -172,15 +174,16 @@ tcf_status tcf_set_fields(tcf_grid* g, double t, const double* alpha, const doub
 tcf_status tcf_get_fields(const tcf_grid* g, double* t, double* alpha, double* T, double* u, double* v,
                           double* w, double* p);
 
-/* Previous pressure p^(n-1) of the extrapolated initial guess
- * (p_extrapolate = 1): copy out / in (device FP64, cell layout like p), so
- * that a run restarted from tcf_get_fields plus this field repeats the
- * uninterrupted run bitwise.  tcf_set_fields clears it; set with NULL
- * clears it too.  TCF_E_STATE on a grid that does not extrapolate or (get)
- * holds no previous pressure; TCF_E_INVALID on a NULL grid or (get) a NULL
- * pointer. */
-tcf_status tcf_get_pressure_history(const tcf_grid* g, double* p_prev);
-tcf_status tcf_set_pressure_history(tcf_grid* g, const double* p_prev);
+/* Previous pressures of the extrapolated initial guess (p_extrapolate > 0):
+ * held = how many are held (0 .. p_extrapolate), p1 = p^(n-1), p2 =
+ * p^(n-2) (device FP64, cell layout like p; p1 is read / written when held
+ * >= 1, p2 when held = 2, otherwise they may be NULL).  A run restarted
+ * from tcf_get_fields plus this history repeats the uninterrupted run
+ * bitwise.  tcf_set_fields clears the history.  TCF_E_STATE on a grid that
+ * does not extrapolate; TCF_E_INVALID on a NULL grid or held pointer, held
+ * out of range, or a NULL pointer that held requires. */
+tcf_status tcf_get_pressure_history(const tcf_grid* g, double* p1, double* p2, int* held);
+tcf_status tcf_set_pressure_history(tcf_grid* g, const double* p1, const double* p2, int held);
 
 /* Species field of a grid made with species = 1: copy in / out (device FP64,
  * nx*ny*nz cells in the layout above).  TCF_E_STATE on a grid without a

@@ -127,8 +127,8 @@ struct tcf_grid {
   bool fp32;
   bool has_fields = false;
   bool has_species = false;  // species field set (configs with species = 1)
-  double* pprev = nullptr;   // previous pressure of the extrapolated guess (p_extrapolate = 1)
-  bool has_pprev = false;
+  double* phist[2] = {nullptr, nullptr};  // p^(n-1), p^(n-2) of the extrapolated guess
+  int nhist = 0;                           // how many of them are held
   bool has_phases = false;   // fractions of phases 3 (and 4) set (N-phase configs)
   int nph = 2;               // number of phases
   double op_rho1 = 0.0, op_rho2 = 0.0;  // density range of the pressure operator's linear mix
@@ -310,7 +310,7 @@ void carve_fields(Carver& cv, const Dims& D, Fields<R>& F, int mg_levels, bool a
 // The extrapolated initial guess is used by the one-solve integrators of
 // the forward step only.
 bool extrapolates(const tcf_config* c) {
-  return c->p_extrapolate == 1 && c->integrator == 0 && !(c->flags & TCF_WITH_ADJOINT);
+  return c->p_extrapolate > 0 && c->integrator == 0 && !(c->flags & TCF_WITH_ADJOINT);
 }
 
 size_t carve(const tcf_config* c, void* base, tcf_grid* g) {
@@ -325,7 +325,8 @@ size_t carve(const tcf_config* c, void* base, tcf_grid* g) {
   G->b64 = cv.take<double>(D.N);
   G->r64 = cv.take<double>(D.N);
   G->zero64 = cv.take<double>(D.N);
-  if (extrapolates(c)) G->pprev = cv.take<double>(D.N);
+  if (extrapolates(c))
+    for (int q = 0; q < c->p_extrapolate; ++q) G->phist[q] = cv.take<double>(D.N);
   if (c->integrator == 1) {
     G->un64 = cv.take<double>(D.Nu);
     G->vn64 = cv.take<double>(D.Nv);
@@ -424,7 +425,7 @@ std::string validate(const tcf_config* c) {
   if (c->p_maxit < 1) return "p_maxit must be >= 1";
   if (c->mg_nu < 1 || c->mg_nu > 8) return "mg_nu must be in 1..8";
   if (c->mg_levels < 0) return "mg_levels must be >= 0";
-  if (c->p_extrapolate != 0 && c->p_extrapolate != 1) return "p_extrapolate must be 0 or 1";
+  if (c->p_extrapolate < 0 || c->p_extrapolate > 2) return "p_extrapolate must be 0, 1 or 2";
   if (c->precision == TCF_FP32_REFINE && (!(c->inner_rtol > 0 && c->inner_rtol < 1) || c->refine_maxit < 1))
     return "FP32 mode needs 0 < inner_rtol < 1 and refine_maxit >= 1";
   return "";
@@ -895,17 +896,15 @@ void prepare_state_operator(tcf_grid* g) {
   }
 }
 
-// Initial guess of the step's pressure solve (p_extrapolate = 1): p <- 2 p -
-// p_prev with p_prev <- p, once the previous pressure is held; before that
-// the last pressure, which becomes p_prev.
+// Initial guess of the step's pressure solve (p_extrapolate > 0): the
+// extrapolation through p and the previous pressures held, of the order
+// configured or as far as they go, while the history shifts by one.
 void pressure_guess(tcf_grid* g) {
-  if (!g->pprev) return;
-  if (g->has_pprev) {
-    extrapolate_f64(g->stream, g->D.N, g->p64, g->pprev);
-  } else {
-    copy_f64(g->stream, g->D.N, g->p64, g->pprev);
-    g->has_pprev = true;
-  }
+  const int K = g->cfg.p_extrapolate;
+  if (!g->phist[0]) return;
+  const int m = std::min(g->nhist, K);
+  extrapolate_f64(g->stream, g->D.N, m, K, g->p64, g->phist[0], g->phist[1]);
+  g->nhist = std::min(g->nhist + 1, K);
 }
 
 // One step of the N-phase model (integrator 0): SSP-RK3 transport of alpha,
@@ -1334,7 +1333,7 @@ tcf_status tcf_set_fields(tcf_grid* g, double t, const double* alpha, const doub
   HIPCHECK(hipGetLastError());
   g->t = t;
   g->has_fields = true;
-  g->has_pprev = false;
+  g->nhist = 0;
   return TCF_OK;
 }
 
@@ -1362,29 +1361,31 @@ tcf_status tcf_get_fields(const tcf_grid* gc, double* t, double* alpha, double* 
   return TCF_OK;
 }
 
-tcf_status tcf_get_pressure_history(const tcf_grid* gc, double* p_prev) {
+tcf_status tcf_get_pressure_history(const tcf_grid* gc, double* p1, double* p2, int* held) {
   g_err.clear();
-  if (!gc) return fail(TCF_E_INVALID, "grid is NULL");
+  if (!gc || !held) return fail(TCF_E_INVALID, "grid and held must be non-NULL");
   tcf_grid* g = const_cast<tcf_grid*>(gc);
-  if (!g->pprev) return fail(TCF_E_STATE, "the grid does not extrapolate the pressure");
-  if (!g->has_pprev) return fail(TCF_E_STATE, "no previous pressure held");
-  if (!p_prev) return fail(TCF_E_INVALID, "p_prev must be non-NULL");
-  copy_f64(g->stream, g->D.N, g->pprev, p_prev);
+  if (!g->phist[0]) return fail(TCF_E_STATE, "the grid does not extrapolate the pressure");
+  if ((g->nhist >= 1 && !p1) || (g->nhist >= 2 && !p2))
+    return fail(TCF_E_INVALID, "p1 (and p2 with two pressures held) must be non-NULL");
+  *held = g->nhist;
+  if (g->nhist >= 1) copy_f64(g->stream, g->D.N, g->phist[0], p1);
+  if (g->nhist >= 2) copy_f64(g->stream, g->D.N, g->phist[1], p2);
   HIPCHECK(hipGetLastError());
   return TCF_OK;
 }
 
-tcf_status tcf_set_pressure_history(tcf_grid* g, const double* p_prev) {
+tcf_status tcf_set_pressure_history(tcf_grid* g, const double* p1, const double* p2, int held) {
   g_err.clear();
   if (!g) return fail(TCF_E_INVALID, "grid is NULL");
-  if (!g->pprev) return fail(TCF_E_STATE, "the grid does not extrapolate the pressure");
-  if (!p_prev) {
-    g->has_pprev = false;
-    return TCF_OK;
-  }
-  copy_f64(g->stream, g->D.N, p_prev, g->pprev);
+  if (!g->phist[0]) return fail(TCF_E_STATE, "the grid does not extrapolate the pressure");
+  if (held < 0 || held > g->cfg.p_extrapolate) return fail(TCF_E_INVALID, "held must be in 0..p_extrapolate");
+  if ((held >= 1 && !p1) || (held >= 2 && !p2))
+    return fail(TCF_E_INVALID, "p1 (and p2 with held = 2) must be non-NULL");
+  if (held >= 1) copy_f64(g->stream, g->D.N, p1, g->phist[0]);
+  if (held >= 2) copy_f64(g->stream, g->D.N, p2, g->phist[1]);
   HIPCHECK(hipGetLastError());
-  g->has_pprev = true;
+  g->nhist = held;
   return TCF_OK;
 }
 

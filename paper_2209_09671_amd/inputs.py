@@ -36,7 +36,7 @@ _DEFAULTS = dict(
     refine_maxit=30,
     mg_levels=0,          # 0 = as many as the grid allows
     mg_nu=2,
-    p_extrapolate=1,      # pressure guess 2 p^n - p^(n-1) from the second step on
+    p_extrapolate=2,      # pressure guess 3 p^n - 3 p^(n-1) + p^(n-2) (lower orders until held)
     q_power=0.0, q_radius=1.0, q_x0=0.0, q_y0=0.0, q_vx=0.0, q_vy=0.0,
 )
 

@@ -85,9 +85,9 @@ def load():
     lib.tcf_get_fields.restype = st
     lib.tcf_get_fields.argtypes = [vp, C.POINTER(C.c_double), vp, vp, vp, vp, vp, vp]
     lib.tcf_get_pressure_history.restype = st
-    lib.tcf_get_pressure_history.argtypes = [vp, vp]
+    lib.tcf_get_pressure_history.argtypes = [vp, vp, vp, C.POINTER(C.c_int)]
     lib.tcf_set_pressure_history.restype = st
-    lib.tcf_set_pressure_history.argtypes = [vp, vp]
+    lib.tcf_set_pressure_history.argtypes = [vp, vp, vp, C.c_int]
     lib.tcf_set_species.restype = st
     lib.tcf_set_species.argtypes = [vp, vp]
     lib.tcf_get_species.restype = st
@@ -142,7 +142,7 @@ def make_config(c: dict, precision=None, flags=None) -> TcfConfig:
     o.p_rtol, o.p_maxit = c["p_rtol"], c["p_maxit"]
     o.inner_rtol, o.refine_maxit = c["inner_rtol"], c["refine_maxit"]
     o.mg_levels, o.mg_nu = c["mg_levels"], c["mg_nu"]
-    o.p_extrapolate = int(c.get("p_extrapolate", 1))
+    o.p_extrapolate = int(c.get("p_extrapolate", 2))
     o.species = int(c.get("species", 0))
     o.dsigma_dc, o.c0 = float(c.get("dsigma_dc", 0.0)), float(c.get("c0", 0.0))
     o.integrator = int(c.get("integrator", 0))
@@ -215,10 +215,10 @@ class Grid:
         """Fields (and, when given, the species, the phases and the previous
         pressure of the extrapolated guess, as get_fields returns them)."""
         self.set_fields(t, st["alpha"], st["T"], st["u"], st["v"], st.get("w"), st.get("p"))
-        if st.get("p_prev") is not None:
-            pp = self._t(st["p_prev"])
-            self._keep_pp = pp
-            _check(load().tcf_set_pressure_history(self.h, _ptr(pp)))
+        if st.get("p_held"):
+            p1, p2 = self._t(st.get("p_prev")), self._t(st.get("p_prev2"))
+            self._keep_pp = (p1, p2)
+            _check(load().tcf_set_pressure_history(self.h, _ptr(p1), _ptr(p2), C.c_int(st["p_held"])))
         if st.get("c") is not None:
             self.set_species(st["c"])
         if st.get("alpha3") is not None:
@@ -258,12 +258,17 @@ class Grid:
         _check(load().tcf_get_fields(self.h, C.byref(t), _ptr(out["alpha"]), _ptr(out["T"]), _ptr(out["u"]),
                                      _ptr(out["v"]), _ptr(out["w"]), _ptr(out["p"])))
         out["t"] = t.value
-        # the previous pressure of the extrapolated initial guess, if held
-        pp = torch.empty(s["cell"], dtype=torch.float64, device=self.device)
-        st = load().tcf_get_pressure_history(self.h, _ptr(pp))
+        # the previous pressures of the extrapolated initial guess, if held
+        p1 = torch.empty(s["cell"], dtype=torch.float64, device=self.device)
+        p2 = torch.empty(s["cell"], dtype=torch.float64, device=self.device)
+        held = C.c_int(0)
+        st = load().tcf_get_pressure_history(self.h, _ptr(p1), _ptr(p2), C.byref(held))
         if st not in (TCF_OK, TCF_E_STATE):
             raise TcfError(st, load().tcf_last_error().decode())
-        out["p_prev"] = pp if st == TCF_OK else None
+        n = held.value if st == TCF_OK else 0
+        out["p_held"] = n
+        out["p_prev"] = p1 if n >= 1 else None
+        out["p_prev2"] = p2 if n >= 2 else None
         return out
 
     def step(self, dt, nsteps=1, info=True, check=True):

@@ -150,22 +150,25 @@ def test_species_entry_points_reject_null():
 
 
 def test_pressure_extrapolation_workspace_and_validation():
-    """p_extrapolate = 1 keeps the previous pressure (one FP64 cell array) on
-    grids whose integrator solves once per step; it must be 0/1, and has no
-    effect (no storage) with integrator 1 or the adjoint."""
+    """p_extrapolate = K keeps the K previous pressures (FP64 cell arrays) on
+    grids whose integrator solves once per step; it must be 0, 1 or 2, and
+    has no effect (no storage) with integrator 1 or the adjoint."""
     c = I.config(3)
     N = c["nx"] * c["ny"] * c["nz"]
-    on, off = dict(c, p_extrapolate=1), dict(c, p_extrapolate=0)
-    for prec in (0, 1):
-        d = tcf.workspace_bytes(on, precision=prec) - tcf.workspace_bytes(off, precision=prec)
-        assert 8 * N <= d < 8 * N + 4096
-    assert tcf.workspace_bytes(dict(c, p_extrapolate=2)) == 0
-    assert tcf.workspace_bytes(dict(on, integrator=1)) == tcf.workspace_bytes(dict(off, integrator=1))
-    assert (tcf.workspace_bytes(on, precision=0, flags=tcf.TCF_WITH_ADJOINT)
-            == tcf.workspace_bytes(off, precision=0, flags=tcf.TCF_WITH_ADJOINT))
+    off = dict(c, p_extrapolate=0)
+    for K in (1, 2):
+        on = dict(c, p_extrapolate=K)
+        for prec in (0, 1):
+            d = tcf.workspace_bytes(on, precision=prec) - tcf.workspace_bytes(off, precision=prec)
+            assert 8 * K * N <= d < 8 * K * N + 4096
+        assert tcf.workspace_bytes(dict(on, integrator=1)) == tcf.workspace_bytes(dict(off, integrator=1))
+        assert (tcf.workspace_bytes(on, precision=0, flags=tcf.TCF_WITH_ADJOINT)
+                == tcf.workspace_bytes(off, precision=0, flags=tcf.TCF_WITH_ADJOINT))
+    assert tcf.workspace_bytes(dict(c, p_extrapolate=3)) == 0
+    assert tcf.workspace_bytes(dict(c, p_extrapolate=-1)) == 0
 
 
 def test_pressure_history_entry_points_reject_null():
     lib = tcf.load()
-    assert lib.tcf_get_pressure_history(None, None) == tcf.TCF_E_INVALID
-    assert lib.tcf_set_pressure_history(None, None) == tcf.TCF_E_INVALID
+    assert lib.tcf_get_pressure_history(None, None, None, None) == tcf.TCF_E_INVALID
+    assert lib.tcf_set_pressure_history(None, None, None, 0) == tcf.TCF_E_INVALID
