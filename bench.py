@@ -291,6 +291,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl, "cells": N, "grid": [c["nx"], c["ny"], c["nz"]], "h_m": c["h"],
                    "dt_s": c["dt"], "precision": "fp32 stencils/inner solve, fp64 refinement",
+                   "pressure_guess": f"extrapolated in time, order {c.get('p_extrapolate', 2)}",
                    "p_rtol": args.rtol, "cg_iters_per_step": round(r32["iters"], 2),
                    "refine_iters_per_step": round(r32["refs"], 2), "max_p_relres": r32["relres"],
                    "max_div_rel": r32["div"]},
