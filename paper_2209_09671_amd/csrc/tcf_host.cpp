@@ -898,12 +898,26 @@ void prepare_state_operator(tcf_grid* g) {
 
 // Initial guess of the step's pressure solve (p_extrapolate > 0): the
 // extrapolation through p and the previous pressures held, of the order
-// configured or as far as they go, while the history shifts by one.
+// configured or as far as they go, while the history shifts by one.  The
+// guess is written into the buffer of the oldest pressure, and the three
+// buffers change roles (no copies).
 void pressure_guess(tcf_grid* g) {
   const int K = g->cfg.p_extrapolate;
   if (!g->phist[0]) return;
   const int m = std::min(g->nhist, K);
-  extrapolate_f64(g->stream, g->D.N, m, K, g->p64, g->phist[0], g->phist[1]);
+  double* p = g->p64;
+  double* h1 = g->phist[0];
+  double* h2 = g->phist[1];
+  if (m == 0) {  // no guess: p stays, the history shifts
+    if (K == 2) std::swap(g->phist[0], g->phist[1]);
+    copy_f64(g->stream, g->D.N, p, g->phist[0]);
+  } else {
+    double* out = K == 2 ? h2 : h1;  // the oldest pressure's buffer
+    extrapolate_f64(g->stream, g->D.N, m, p, h1, h2, out);
+    g->p64 = out;
+    if (K == 2) g->phist[1] = h1;
+    g->phist[0] = p;
+  }
   g->nhist = std::min(g->nhist + 1, K);
 }
 

@@ -250,10 +250,10 @@ void rk_combine(hipStream_t s, long n, int stage, const double* base, R* x);
 void to_f32(hipStream_t s, long n, const double* x, float* y);
 void to_f64(hipStream_t s, long n, const float* x, double* y);
 void copy_f64(hipStream_t s, long n, const double* x, double* y);
-// Extrapolation in time of order m (0, 1 or 2) through p and the previous
-// pressures h1 = p^(n-1), h2 = p^(n-2), then the history shifts by one
-// (h2 <- h1 when K = 2, h1 <- the old p); h2 may be NULL when K = 1.
-void extrapolate_f64(hipStream_t s, long n, int m, int K, double* p, double* h1, double* h2);
+// out = the extrapolation in time of order m (1 or 2) through p and the
+// previous pressures h1 = p^(n-1), h2 = p^(n-2): 2 p - h1, or 3 p - 3 h1 +
+// h2 (out may be h1 or h2; h2 is not read for m = 1)
+void extrapolate_f64(hipStream_t s, long n, int m, const double* p, const double* h1, const double* h2, double* out);
 void fill_f64(hipStream_t s, long n, double* y, double v);
 template <class R>
 void zero_walls(const KParams& P, hipStream_t s, R* u, R* v, R* w);

@@ -1216,17 +1216,12 @@ __global__ __launch_bounds__(256) void k_to_f64(long n, const float* __restrict_
   const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (c < n) y[c] = (double)x[c];
 }
-template <int M, int K>
-__global__ __launch_bounds__(256) void k_extrapolate64(long n, double* __restrict__ p, double* __restrict__ h1,
-                                                       double* __restrict__ h2) {
+template <int M>
+__global__ __launch_bounds__(256) void k_extrapolate64(long n, const double* __restrict__ p, const double* h1,
+                                                       const double* h2, double* out) {
   const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= n) return;
-  const double pc = p[c];
-  const double a = M >= 1 || K == 2 ? h1[c] : 0.0;
-  if (M == 1) p[c] = 2.0 * pc - a;
-  if (M == 2) p[c] = 3.0 * pc - 3.0 * a + h2[c];
-  if (K == 2) h2[c] = a;
-  h1[c] = pc;
+  out[c] = M == 1 ? 2.0 * p[c] - h1[c] : 3.0 * p[c] - 3.0 * h1[c] + h2[c];
 }
 
 __global__ __launch_bounds__(256) void k_copy64(long n, const double* __restrict__ x, double* __restrict__ y) {
@@ -1520,16 +1515,11 @@ void to_f32(hipStream_t s, long n, const double* x, float* y) {
 void to_f64(hipStream_t s, long n, const float* x, double* y) {
   hipLaunchKernelGGL(k_to_f64, dim3(nblk1(n)), dim3(256), 0, s, n, x, y);
 }
-void extrapolate_f64(hipStream_t s, long n, int m, int K, double* p, double* h1, double* h2) {
+void extrapolate_f64(hipStream_t s, long n, int m, const double* p, const double* h1, const double* h2,
+                     double* out) {
   const dim3 g(nblk1(n)), b(256);
-  if (K == 1) {
-    if (m == 0) hipLaunchKernelGGL((k_extrapolate64<0, 1>), g, b, 0, s, n, p, h1, h2);
-    else hipLaunchKernelGGL((k_extrapolate64<1, 1>), g, b, 0, s, n, p, h1, h2);
-  } else {
-    if (m == 0) hipLaunchKernelGGL((k_extrapolate64<0, 2>), g, b, 0, s, n, p, h1, h2);
-    else if (m == 1) hipLaunchKernelGGL((k_extrapolate64<1, 2>), g, b, 0, s, n, p, h1, h2);
-    else hipLaunchKernelGGL((k_extrapolate64<2, 2>), g, b, 0, s, n, p, h1, h2);
-  }
+  if (m == 1) hipLaunchKernelGGL((k_extrapolate64<1>), g, b, 0, s, n, p, h1, h2, out);
+  else hipLaunchKernelGGL((k_extrapolate64<2>), g, b, 0, s, n, p, h1, h2, out);
 }
 
 void copy_f64(hipStream_t s, long n, const double* x, double* y) {
