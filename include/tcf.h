@@ -104,8 +104,9 @@ typedef struct tcf_config {
    * p^(n-2).  The order is limited by the previous pressures the grid holds
    * (none after tcf_set_fields; one more after each step, or as given to
    * tcf_set_pressure_history).  Only the iteration count changes: the solve
-   * still runs to p_rtol.  No effect with integrator 1 or
-   * TCF_WITH_ADJOINT. */
+   * still runs to p_rtol.  No effect with integrator 1.  (tcf_step_backward
+   * sets the state without history: its recomputed forward step starts
+   * from the pressure of the state it was given for the step after.) */
   int p_extrapolate;
   /* Solutal Marangoni (eq. 5: the surface-tension gradient is the chain rule
    * over temperature and concentration; in-situ alloying).  species = 1

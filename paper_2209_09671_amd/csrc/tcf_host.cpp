@@ -313,11 +313,8 @@ void carve_fields(Carver& cv, const Dims& D, Fields<R>& F, int mg_levels, bool a
   }
 }
 
-// The extrapolated initial guess is used by the one-solve integrators of
-// the forward step only.
-bool extrapolates(const tcf_config* c) {
-  return c->p_extrapolate > 0 && c->integrator == 0 && !(c->flags & TCF_WITH_ADJOINT);
-}
+// The extrapolated initial guess is used by the one-solve integrator.
+bool extrapolates(const tcf_config* c) { return c->p_extrapolate > 0 && c->integrator == 0; }
 
 size_t carve(const tcf_config* c, void* base, tcf_grid* g) {
   Dims D = dims_of(c);

@@ -409,7 +409,7 @@ class TcfRollout(torch.autograd.Function):
             n0, st0 = ctx.ckpt[seg]
             n1 = bounds[seg + 1]
             # replay the segment, keeping every state
-            g.set_fields(st0["t"], st0["alpha"], st0["T"], st0["u"], st0["v"], st0["w"], st0["p"])
+            g.set_state(st0, st0["t"])  # with the pressure history, so the replay repeats the forward
             states = []
             for n in range(n0, n1):
                 f = g.get_fields()
