@@ -320,3 +320,38 @@ def test_restart_with_second_order_history_bitwise():
     h2, _ = gpu_run(c, h1, c["dt"], 2, t=3 * c["dt"])
     for k in ("alpha", "T", "u", "v", "p"):
         assert np.array_equal(a[k], h2[k]), k
+
+
+def test_pressure_history_entry_points():
+    """The history of the extrapolated guess round-trips through the C ABI,
+    tcf_set_fields clears it, and held outside 0..p_extrapolate or a missing
+    pointer is refused."""
+    import ctypes as C
+    c = dict(I.config(0), p_extrapolate=2)
+    st = I.initial_state(c)
+    g = tcf.Grid(c, precision=0)
+    g.set_state(st)
+    assert g.get_fields()["p_held"] == 0
+    g.step(c["dt"], 3)
+    f = g.get_fields()
+    assert f["p_held"] == 2
+    lib = tcf.load()
+    p1 = torch.rand(g.shapes["cell"], dtype=torch.float64, device="cuda")
+    p2 = torch.rand(g.shapes["cell"], dtype=torch.float64, device="cuda")
+    assert lib.tcf_set_pressure_history(g.h, C.c_void_p(p1.data_ptr()), C.c_void_p(p2.data_ptr()), 2) == tcf.TCF_OK
+    h = g.get_fields()
+    torch.cuda.synchronize()
+    assert h["p_held"] == 2 and torch.equal(h["p_prev"], p1) and torch.equal(h["p_prev2"], p2)
+    assert lib.tcf_set_pressure_history(g.h, C.c_void_p(p1.data_ptr()), None, 2) == tcf.TCF_E_INVALID
+    assert lib.tcf_set_pressure_history(g.h, None, None, 3) == tcf.TCF_E_INVALID
+    assert lib.tcf_set_pressure_history(g.h, None, None, 0) == tcf.TCF_OK
+    assert g.get_fields()["p_held"] == 0
+    g.step(c["dt"], 1)
+    assert g.get_fields()["p_held"] == 1
+    g.set_state(st)
+    assert g.get_fields()["p_held"] == 0
+    g.close()
+    g = tcf.Grid(dict(c, p_extrapolate=0), precision=0)
+    held = C.c_int(-1)
+    assert lib.tcf_get_pressure_history(g.h, None, None, C.byref(held)) == tcf.TCF_E_STATE
+    g.close()
