@@ -103,10 +103,13 @@ typedef struct tcf_config {
    * last pressures, 0: p^n; 1: 2 p^n - p^(n-1); 2: 3 p^n - 3 p^(n-1) +
    * p^(n-2).  The order is limited by the previous pressures the grid holds
    * (none after tcf_set_fields; one more after each step, or as given to
-   * tcf_set_pressure_history).  Only the iteration count changes: the solve
-   * still runs to p_rtol.  No effect with integrator 1.  (tcf_step_backward
-   * sets the state without history: its recomputed forward step starts
-   * from the pressure of the state it was given for the step after.) */
+   * tcf_set_pressure_history).  With integrator 1 each of the three stage
+   * solves extrapolates that stage's pressures of the last steps (kept
+   * inside the grid, cleared by tcf_set_fields, not exposed).  Only the
+   * iteration count changes: every solve still runs to p_rtol.
+   * (tcf_step_backward sets the state without history: its recomputed
+   * forward step starts from the pressure of the state it was given for
+   * the step after.) */
   int p_extrapolate;
   /* Solutal Marangoni (eq. 5: the surface-tension gradient is the chain rule
    * over temperature and concentration; in-situ alloying).  species = 1
@@ -181,7 +184,8 @@ tcf_status tcf_get_fields(const tcf_grid* g, double* t, double* alpha, double* T
  * >= 1, p2 when held = 2, otherwise they may be NULL).  A run restarted
  * from tcf_get_fields plus this history repeats the uninterrupted run
  * bitwise.  tcf_set_fields clears the history.  TCF_E_STATE on a grid that
- * does not extrapolate; TCF_E_INVALID on a NULL grid or held pointer, held
+ * keeps no such history (p_extrapolate = 0, or integrator 1, whose
+ * per-stage histories stay internal); TCF_E_INVALID on a NULL grid or held pointer, held
  * out of range, or a NULL pointer that held requires. */
 tcf_status tcf_get_pressure_history(const tcf_grid* g, double* p1, double* p2, int* held);
 tcf_status tcf_set_pressure_history(tcf_grid* g, const double* p1, const double* p2, int held);

@@ -129,6 +129,10 @@ struct tcf_grid {
   bool has_species = false;  // species field set (configs with species = 1)
   double* phist[2] = {nullptr, nullptr};  // p^(n-1), p^(n-2) of the extrapolated guess
   int nhist = 0;                           // how many of them are held
+  // integrator 1: per stage the stage pressures of the last steps (newest
+  // first), and how many steps they hold
+  double* shist[3][3] = {};
+  int snhist = 0;
   bool has_phases = false;   // fractions of phases 3 (and 4) set (N-phase configs)
   int nph = 2;               // number of phases
   double op_rho1 = 0.0, op_rho2 = 0.0;  // density range of the pressure operator's linear mix
@@ -330,6 +334,9 @@ size_t carve(const tcf_config* c, void* base, tcf_grid* g) {
   G->zero64 = cv.take<double>(D.N);
   if (extrapolates(c))
     for (int q = 0; q < c->p_extrapolate; ++q) G->phist[q] = cv.take<double>(D.N);
+  if (c->p_extrapolate > 0 && c->integrator == 1)
+    for (int k = 0; k < 3; ++k)
+      for (int q = 0; q <= c->p_extrapolate; ++q) G->shist[k][q] = cv.take<double>(D.N);
   if (c->integrator == 1) {
     G->un64 = cv.take<double>(D.Nu);
     G->vn64 = cv.take<double>(D.Nv);
@@ -1135,8 +1142,23 @@ tcf_status step_rk3p(tcf_grid* g, double dt, tcf_step_info* inf, bool want_diag)
     divergence_rhs<R>(Pp, s, F.us, F.vs, F.ws, g->b64, g->part[0]);
     finalize(s, g->part[0], nbc, g->scal, g->iflag, F_MEAN, S_MEAN, (double)D.N);
     prepare_operator<R>(g, as[k]);
+    // initial guess: this stage's pressures of the last steps extrapolated
+    // in time (else the previous stage's pressure)
+    double** H = g->shist[k];
+    const int K = g->cfg.p_extrapolate;
+    if (H[0] && g->snhist > 0) {
+      const int m = std::min(g->snhist - 1, K);
+      if (m == 0) copy_f64(s, D.N, H[0], g->p64);
+      else extrapolate_f64(s, D.N, m, H[0], H[1], H[2], g->p64);
+    }
     tcf_step_info si{};
     const tcf_status st = solve(g, g->p64, &si);
+    if (H[0]) {  // the stage's history shifts: the oldest buffer takes this pressure
+      double* old = H[K];
+      for (int q = K; q > 0; --q) H[q] = H[q - 1];
+      H[0] = old;
+      copy_f64(s, D.N, g->p64, H[0]);
+    }
     if (st != TCF_OK && st != TCF_E_NOT_CONVERGED) return st;
     if (st != TCF_OK) worst = st;
     acc.cg_iters += si.cg_iters;
@@ -1147,6 +1169,7 @@ tcf_status step_rk3p(tcf_grid* g, double dt, tcf_step_info* inf, bool want_diag)
                g->fp32 ? F.v : nullptr, g->fp32 ? F.w : nullptr);
     dt_proj = Pp.dt;
   }
+  if (mom) g->snhist = std::min(g->snhist + 1, g->cfg.p_extrapolate + 1);
   g->t += dt;
   if (inf) {
     inf->cg_iters = acc.cg_iters;
@@ -1352,6 +1375,7 @@ tcf_status tcf_set_fields(tcf_grid* g, double t, const double* alpha, const doub
   g->t = t;
   g->has_fields = true;
   g->nhist = 0;
+  g->snhist = 0;
   return TCF_OK;
 }
 
