@@ -156,13 +156,15 @@ struct tcf_grid {
   struct Adj {
     double *ab, *Tb, *usb, *vsb, *wsb, *ub, *vb, *wb, *pbar, *y, *skb, *Mxb, *Myb, *Mzb;
     double *nbx, *nby, *nbz, *dsb, *wa, *wT, *sa, *sT;
-    double* pnext;  // the pressure of the state given to the last backward step
+    double* pnext;   // the pressure of the state given to the last backward step
+    double* yh[2];   // the adjoint pressures of the two calls before the last (newest first)
     long Ne;
     // time and step of the last backward step: when the next call is the
     // step before it, its forward solve starts from pnext (the solution it
     // recomputes) and its adjoint solve from the last y
     double t_last = 0.0, dt_last = 0.0;
     bool chain = false;
+    int nchain = 0;  // consecutive chained calls whose adjoint pressures are held (A.y, then yh)
   } adj{};
   bool has_adj = false;
   // optional event timing of one kernel family (measurement only)
@@ -373,6 +375,8 @@ size_t carve(const tcf_config* c, void* base, tcf_grid* g) {
     A.wb = D.dim == 3 ? cv.take<double>(D.Nw) : nullptr;
     A.pbar = cv.take<double>(N);
     A.pnext = cv.take<double>(N);
+    A.yh[0] = cv.take<double>(N);
+    A.yh[1] = cv.take<double>(N);
     A.y = cv.take<double>(N);
     A.skb = cv.take<double>(N);
     A.Mxb = cv.take<double>(N);
@@ -1658,7 +1662,23 @@ tcf_status tcf_step_backward(tcf_grid* g, double t_n, double dt, const double* c
   copy_f64(s, N, A.pbar, g->b64);
   const int nbp = sum64_partials(s, N, g->b64, g->part[0]);
   finalize(s, g->part[0], nbp, g->scal, g->iflag, F_MEAN, S_MEAN, (double)N);
-  if (!chain) fill_f64(s, N, A.y, 0.0);
+  // the adjoint pressure: zero, or the last one extrapolated through the
+  // earlier ones held (quadratic in the step index once three are held)
+  if (!chain) {
+    fill_f64(s, N, A.y, 0.0);
+    A.nchain = 0;
+  } else if (A.nchain >= 2) {
+    const int m = std::min(A.nchain - 1, 2);
+    // the guess goes into the buffer of the oldest (yh[1]: read in place
+    // when m = 2, free when m = 1); then the roles shift by one
+    double* out = A.yh[1];
+    extrapolate_f64(s, N, m, A.y, A.yh[0], A.yh[1], out);
+    A.yh[1] = A.yh[0];
+    A.yh[0] = A.y;
+    A.y = out;
+  } else {
+    copy_f64(s, N, A.y, A.yh[0]);  // keep the last one as history
+  }
   st = solve(g, A.y, nullptr);
   if (st != TCF_OK && st != TCF_E_NOT_CONVERGED) return st;
   adj_poisson_alpha(P, s, F.a, g->p64, A.y, A.ab);
@@ -1679,6 +1699,7 @@ tcf_status tcf_step_backward(tcf_grid* g, double t_n, double dt, const double* c
   A.t_last = t_n;
   A.dt_last = dt;
   A.chain = true;
+  A.nchain = std::min(A.nchain + 1, 3);
   HIPCHECK(hipGetLastError());
   return st;
 }
