@@ -194,8 +194,8 @@ def main():
     ap.add_argument("--no-nphase", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this path runs on one GPU; multi-GPU runs are not part of this build "
-              "(see the sharding notes in DESIGN.md)", file=sys.stderr)
+        print("bench.py: this path runs on one GPU; runs on several GPUs are not supported "
+              "(the step is measured on one GPU's share of the grid)", file=sys.stderr)
         sys.exit(2)
 
     import torch
