@@ -258,14 +258,16 @@ class Grid:
         _check(load().tcf_get_fields(self.h, C.byref(t), _ptr(out["alpha"]), _ptr(out["T"]), _ptr(out["u"]),
                                      _ptr(out["v"]), _ptr(out["w"]), _ptr(out["p"])))
         out["t"] = t.value
-        # the previous pressures of the extrapolated initial guess, if held
-        p1 = torch.empty(s["cell"], dtype=torch.float64, device=self.device)
-        p2 = torch.empty(s["cell"], dtype=torch.float64, device=self.device)
-        held = C.c_int(0)
-        st = load().tcf_get_pressure_history(self.h, _ptr(p1), _ptr(p2), C.byref(held))
-        if st not in (TCF_OK, TCF_E_STATE):
-            raise TcfError(st, load().tcf_last_error().decode())
-        n = held.value if st == TCF_OK else 0
+        # the previous pressures of the extrapolated initial guess, if the
+        # grid keeps them (one-solve integrator) and holds any
+        n = 0
+        p1 = p2 = None
+        if self.cfg.p_extrapolate > 0 and self.cfg.integrator == 0:
+            p1 = torch.empty(s["cell"], dtype=torch.float64, device=self.device)
+            p2 = torch.empty(s["cell"], dtype=torch.float64, device=self.device)
+            held = C.c_int(0)
+            _check(load().tcf_get_pressure_history(self.h, _ptr(p1), _ptr(p2), C.byref(held)))
+            n = held.value
         out["p_held"] = n
         out["p_prev"] = p1 if n >= 1 else None
         out["p_prev2"] = p2 if n >= 2 else None
