@@ -10,7 +10,11 @@
 // x-face fluxes: each lane computes its low face, the high face arrives from
 // the next lane by a wavefront shuffle (a wavefront is one 64-wide row).
 // y-face fluxes: each row computes its low face; the high face is read from
-// the next row through LDS.  A WENO5 evaluation takes one reciprocal per
+// the next row through LDS.  The faces past the tile's high edges (the high
+// x-face of each row, the high y-face of each column: 72 per plane and field)
+// are computed one per lane by the first wavefronts and passed through LDS, so
+// no wavefront issues a WENO5 evaluation for a single lane.  A WENO5
+// evaluation takes one reciprocal per
 // nonlinear weight and one for their normalisation, on the stencil picked
 // by the velocity's sign.  The kernel also runs in two other modes (below):
 // one passive cell field, or T alone with cell materials.
@@ -27,6 +31,7 @@ using namespace dev;
 constexpr int TX = 64, TY = 8, H = 3;
 constexpr int SX = TX + 2 * H, SY = TY + 2 * H;
 constexpr int NHALO = 2 * H * TY + 2 * H * TX;  // x strips + y strips (corners unused)
+constexpr int NE = TY + TX;                     // tile-edge faces of a plane: x (one per row), y (one per column)
 
 // WENO5-JS with the normalisation folded into one reciprocal.
 __device__ __forceinline__ float rcpx(float x) { return __builtin_amdgcn_rcpf(x); }
@@ -122,11 +127,14 @@ __global__ __launch_bounds__(512) void k_transport2(KParams P, int kz, int ntx, 
                                                     const R* __restrict__ w, R* ao, R* To, R cb, R ci,
                                                     const R* __restrict__ rc, const R* __restrict__ dq) {
   constexpr bool WT = MODE != 0, WA = MODE != 2;
-  constexpr int NT = WT ? 2 : 1;
-  __shared__ R sa[2][SY][SX];
-  __shared__ R sT[NT][WT ? SY : 1][WT ? SX : 1];
+  constexpr int NF = WT ? 2 : 1;                   // LDS fields: the alpha slot, T
+  constexpr int NEF = (WA ? 1 : 0) + (WT ? 1 : 0);  // transported fields
+  __shared__ R sq[NF][2][SY][SX];                  // [field][buffer][row][column]
+  R(*sa)[SY][SX] = sq[0];
+  R(*sT)[SY][SX] = sq[NF - 1];
   __shared__ R fya[TY][TX];  // low y-face fluxes of the tile rows
   __shared__ R fyt[WT ? TY : 1][WT ? TX : 1];
+  __shared__ R sedge[2][NE];  // tile-edge face fluxes [alpha slot, T][x edges, then y edges]
   const int nx = P.nx, ny = P.ny, nz = P.nz;
   const int tx = threadIdx.x, ty = threadIdx.y, tid = tx + TX * ty;
   // XCD-grouped tile numbering (see the pressure kernels)
@@ -169,8 +177,8 @@ __global__ __launch_bounds__(512) void k_transport2(KParams P, int kz, int ntx, 
   auto ldT = [&](unsigned off, int kk) { return T[off + (size_t)zrefl(kk) * pl]; };
   // in-plane offsets of the face velocities (low and high faces) and cells
   const int ic = min(i, nx - 1), jc = min(j, ny - 1);
-  const unsigned uoL = (unsigned)(min(i, nx) + (nx + 1) * jc), uoH = (unsigned)(min(i + 1, nx) + (nx + 1) * jc);
-  const unsigned voL = (unsigned)(ic + nx * min(j, ny)), voH = (unsigned)(ic + nx * min(j + 1, ny));
+  const unsigned uoL = (unsigned)(min(i, nx) + (nx + 1) * jc);
+  const unsigned voL = (unsigned)(ic + nx * min(j, ny));
   const unsigned co = (unsigned)(ic + nx * jc);
   // column queues (k-3 .. k+3); in 2D only the centre is used
   R qa[7], qt[7];
@@ -193,13 +201,26 @@ __global__ __launch_bounds__(512) void k_transport2(KParams P, int kz, int ntx, 
   }
   R ha = ldA(hm.off, k0), hT = WT ? ldT(hm.off, k0) : R(0);  // halo of plane k (raw T)
   // velocities and base state of plane k (loaded one plane ahead)
-  R uL = u[(size_t)k0 * plu + uoL], uH = u[(size_t)k0 * plu + uoH];
-  R vL = v[(size_t)k0 * plv + voL], vH = v[(size_t)k0 * plv + voH];
+  R uL = u[(size_t)k0 * plu + uoL];
+  R vL = v[(size_t)k0 * plv + voL];
   R wH = DIM == 3 ? w[(size_t)(k0 + 1) * pl + co] : R(0);
   R bA = WA ? ab[(size_t)k0 * pl + co] : R(0), bT = WT ? Tb[(size_t)k0 * pl + co] : R(0);
   const bool wq = MODE == 2 && P.qP != 0.0;
   R bR = MODE == 2 ? rc[(size_t)k0 * pl + co] : R(0), bQ = wq ? dq[(size_t)k0 * pl + co] : R(0);
   const R wL0 = DIM == 3 ? w[(size_t)k0 * pl + co] : R(0);
+  // Tile-edge role: lane tid < NEF * NE computes field ef at edge face ee,
+  // the high x-face of row ee (ee < TY) or the high y-face of column ee - TY.
+  // Its 6-cell stencil starts at LDS offset est with stride 1 (x) or SX (y);
+  // the face velocity offset is clamped so that every lane's load is valid.
+  const bool erole = tid < NEF * NE;
+  const int ee = tid % NE, ef = (WA && WT) ? min(tid / NE, 1) : (WA ? 0 : 1);
+  const bool ex = ee < TY;
+  const int est = ex ? (ee + H) * SX + TX : TY * SX + (ee - TY) + H, es = ex ? 1 : SX;
+  const R* __restrict__ ev = ex ? u : v;
+  const size_t epl = ex ? plu : plv;
+  const unsigned eoff = ex ? (unsigned)(min(i0 + TX, nx) + (nx + 1) * min(j0 + ee, ny - 1))
+                           : (unsigned)(min(i0 + ee - TY, nx - 1) + nx * min(j0 + TY, ny));
+  R eV = ev[(size_t)k0 * epl + eoff];
   // Gaussian surface heat flux of the column (x, y, t), FP64, once per column
   R qcol = R(0);
   if (WT && P.qP != 0.0 && act) {
@@ -239,11 +260,10 @@ __global__ __launch_bounds__(512) void k_transport2(KParams P, int kz, int ntx, 
     ha = ldA(hm.off, kn);
     if (WT) hT = ldT(hm.off, kn);
     // this plane's velocities and base state; prefetch the next plane's
-    const R ulo = uL, uhi = uH, vlo = vL, vhi = vH, whi = wH, abc = bA, Tbc = bT, rcc = bR, dqc = bQ;
+    const R ulo = uL, vlo = vL, whi = wH, abc = bA, Tbc = bT, rcc = bR, dqc = bQ, evel = eV;
     uL = u[(size_t)kn * plu + uoL];
-    uH = u[(size_t)kn * plu + uoH];
     vL = v[(size_t)kn * plv + voL];
-    vH = v[(size_t)kn * plv + voH];
+    eV = ev[(size_t)kn * epl + eoff];
     if (DIM == 3) wH = w[(size_t)min(kn + 1, nz) * pl + co];
     if (WA) bA = ab[(size_t)kn * pl + co];
     if (WT) bT = Tb[(size_t)kn * pl + co];
@@ -273,37 +293,32 @@ __global__ __launch_bounds__(512) void k_transport2(KParams P, int kz, int ntx, 
       if (WA) fya[ty][tx] = Fya_lo;
       if (WT) fyt[ty][tx] = Fyt_lo;
     }
-    // high x-face: next lane's low face, computed here at the tile edge
+    // tile-edge faces (their values are read only where the face is inside
+    // the domain; elsewhere the stencil holds stale LDS and is unused)
+    if (erole) {
+      const R* sb = &sq[ef][buf][0][0] + est;
+      sedge[ef][ee] = evel * upw(sb[0], sb[es], sb[2 * es], sb[3 * es], sb[4 * es], sb[5 * es], evel, eps);
+    }
+    // high x-face: next lane's low face
     R Fxa_hi = __shfl_down(Fxa_lo, 1, 64), Fxt_hi = WT ? __shfl_down(Fxt_lo, 1, 64) : R(0);
+    __syncthreads();
     if (act) {
       const int X = tx + H, Y = ty + H;
       if (i + 1 >= nx) {
         Fxa_hi = R(0);
         Fxt_hi = R(0);
       } else if (tx == TX - 1) {
-        if (WA)
-          Fxa_hi = uhi * upw(sa[buf][Y][X - 2], sa[buf][Y][X - 1], sa[buf][Y][X], sa[buf][Y][X + 1], sa[buf][Y][X + 2],
-                           sa[buf][Y][X + 3], uhi, eps);
-        if (WT)
-          Fxt_hi = uhi * upw(sT[buf][Y][X - 2], sT[buf][Y][X - 1], sT[buf][Y][X], sT[buf][Y][X + 1],
-                             sT[buf][Y][X + 2], sT[buf][Y][X + 3], uhi, eps);
+        if (WA) Fxa_hi = sedge[0][ty];
+        if (WT) Fxt_hi = sedge[1][ty];
       }
-    }
-    __syncthreads();
-    if (act) {
-      const int X = tx + H, Y = ty + H;
       R Fya_hi = R(0), Fyt_hi = R(0);
       if (j + 1 < ny) {
         if (ty < TY - 1) {
           if (WA) Fya_hi = fya[ty + 1][tx];
           if (WT) Fyt_hi = fyt[ty + 1][tx];
         } else {
-          if (WA)
-            Fya_hi = vhi * upw(sa[buf][Y - 2][X], sa[buf][Y - 1][X], sa[buf][Y][X], sa[buf][Y + 1][X],
-                             sa[buf][Y + 2][X], sa[buf][Y + 3][X], vhi, eps);
-          if (WT)
-            Fyt_hi = vhi * upw(sT[buf][Y - 2][X], sT[buf][Y - 1][X], sT[buf][Y][X], sT[buf][Y + 1][X],
-                               sT[buf][Y + 2][X], sT[buf][Y + 3][X], vhi, eps);
+          if (WA) Fya_hi = sedge[0][TY + tx];
+          if (WT) Fyt_hi = sedge[1][TY + tx];
         }
       }
       R diva = (Fxa_hi - Fxa_lo) + (Fya_hi - Fya_lo);
