@@ -11,7 +11,10 @@
 // slab, which keeps the y-halo rows in that XCD's L2.  The CG vector updates
 // are fused into the stencil passes: d <- z + beta d into the SpMV, and
 // x += alpha d, r -= alpha q plus the first Jacobi sweep into one pass.
+// The FP64 residual of the refinement marches the same way with FP64
+// densities, weights and pressure.
 #include <algorithm>
+#include <type_traits>
 
 #include "tcf_device.h"
 #include "tcf_internal.h"
@@ -50,6 +53,35 @@ __device__ __forceinline__ float coef(float c2, float s) { return c2 * __builtin
 __device__ __forceinline__ double recip(double s) { return 1.0 / s; }
 __device__ __forceinline__ float recip(float s) { return __builtin_amdgcn_rcpf(s); }
 
+// The FP64 operator on a volume fraction of type A (the refinement
+// residual): densities and face weights a_f = c2 / (rho_L + rho_R) in FP64,
+// with c2 = 2/h^2 formed as 2 (1/h)^2.
+template <class A>
+struct Op64 {
+  const A* a;
+  int nx, ny, nz;
+  double rho1, drho, c2;
+};
+
+template <class A>
+__device__ __forceinline__ double rho0(const Op64<A>& op, A a) {
+  double x = (double)a;
+  x = x < 0.0 ? 0.0 : (x > 1.0 ? 1.0 : x);
+  return op.rho1 + x * op.drho;
+}
+
+// FP64 reciprocal: hardware estimate refined by three Newton steps (each
+// doubles the correct bits; the result is within an ulp or two of 1/x, all
+// that the FP64 residual needs: the projection's own 1/rho_f agrees with it
+// to rounding).
+__device__ __forceinline__ double rcp64(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(r, fma(-x, r, 1.0), r);
+  r = fma(r, fma(-x, r, 1.0), r);
+  r = fma(r, fma(-x, r, 1.0), r);
+  return r;
+}
+
 struct Tile {
   int i, j, k0, k1;
   bool act;
@@ -78,6 +110,10 @@ template <class R>
 __device__ __forceinline__ R wface(const Op0<R>& op, R rc, R rn) {
   return coef(R(op.c2), rc + rn);
 }
+template <class A>
+__device__ __forceinline__ double wface(const Op64<A>& op, double rc, double rn) {
+  return op.c2 * rcp64(rc + rn);
+}
 
 // Plane march over a z-chunk with one streamed field x and the volume
 // fraction.  Per plane: the tile and its one-cell halo go to a
@@ -94,16 +130,16 @@ __device__ __forceinline__ R wface(const Op0<R>& op, R rc, R rn) {
 // active cell body(c, k, xc, Kx, dg, pv) receives K0 x, the diagonal and
 // pv = pre(c).  With POST, all threads then pass a second barrier and
 // post(k) runs (the restriction).
-template <class R, class XR, class PV>
+template <class R, class AR, class XR, class PV>
 struct Slot {
   XR xr, hyr, hxr;   // raw loads of x: centre and halo
-  R a, gy, gx;       // alpha: centre and halo
+  AR a, gy, gx;      // alpha (as stored): centre and halo
   PV pv;             // per-cell operands
   R xv, rho;         // x and density of the centre, once the plane is next
 };
 
-template <class R, int DIM, bool HASX, bool POST, class XLD, class XVAL, class PRE, class BODY, class PST>
-__device__ __forceinline__ void march(const Op0<R>& op, const Tile& T, const XLD& xld, const XVAL& xval,
+template <class R, int DIM, bool HASX, bool POST, class OP, class XLD, class XVAL, class PRE, class BODY, class PST>
+__device__ __forceinline__ void march(const OP& op, const Tile& T, const XLD& xld, const XVAL& xval,
                                       const PRE& pre, const BODY& body, const PST& post) {
   __shared__ R sx[2][LY][LX];
   __shared__ R sa[2][LY][LX];
@@ -119,7 +155,8 @@ __device__ __forceinline__ void march(const Op0<R>& op, const Tile& T, const XLD
   const int hyj = hasy ? T.j + yr : T.j, hxi = hasx ? T.i + xr : T.i;
   using XR = decltype(xld(0L, 0, 0, 0));
   using PV = decltype(pre(0L));
-  using S = Slot<R, XR, PV>;
+  using AR = std::remove_cv_t<std::remove_reference_t<decltype(op.a[0])>>;
+  using S = Slot<R, AR, XR, PV>;
   // last plane whose centre is read (the z-neighbour of the chunk's last
   // plane), last plane of the chunk
   const int kc = DIM == 3 ? min(T.k1, nz - 1) : 0;
@@ -398,6 +435,32 @@ __global__ __launch_bounds__(FX * FY) void k0_resid_restrict(Op0<R> op, int kz, 
   march<R, DIM, true, true>(op, T, X, XV, pre, body, post);
 }
 
+// FP64 residual of the refinement, r = -(b - mean b) - K p, with block
+// partials of ||b - mean b||^2 and ||r||^2.  28 bytes per cell (alpha as
+// stored, b and p read, r written) instead of the 48 of stored FP64 weights.
+template <class A, int DIM>
+__global__ __launch_bounds__(FX * FY) void k0_resid64(Op64<A> op, int kz, int ntx, int nty,
+                                                  const double* __restrict__ b, const double* __restrict__ scal,
+                                                  const double* __restrict__ p, double* __restrict__ r,
+                                                  double* __restrict__ pbb, double* __restrict__ prr) {
+  const Tile T = tile_of(op.nx, op.ny, op.nz, ntx, nty, kz);
+  const double mean = scal[S_MEAN];
+  double vb = 0.0, vr = 0.0;
+  auto X = [&](long c, int, int, int) { return p[c]; };
+  const Ident<double> XV;
+  auto pre = [&](long c) { return b[c]; };
+  auto body = [&](long c, int, double, double Kp, double, double bc) {
+    const double rhs = -(bc - mean);
+    const double rr = rhs - Kp;
+    r[c] = rr;
+    vb += rhs * rhs;
+    vr += rr * rr;
+  };
+  march<double, DIM, true, false>(op, T, X, XV, pre, body, NoPost());
+  write_partial(vb, pbb);
+  write_partial(vr, prr);
+}
+
 struct Launch {
   int ntx, nty, kz, nblocks;
 };
@@ -512,6 +575,21 @@ void fine_resid_restrict(hipStream_t s, int dim, const Fine<R>& F, const R* b, c
                        b, x, bc, wdc, x1c, R(om0), iflag);
 }
 
+template <class R>
+int resid64a(const KParams& P, hipStream_t s, const R* a, const double* b, const double* scal, const double* p,
+             double* r, double* pbb, double* prr) {
+  const int nz = P.dim == 3 ? P.nz : 1;
+  const Launch L = plan(P.nx, P.ny, nz);
+  const Op64<R> op{a, P.nx, P.ny, nz, P.rho1, P.rho2 - P.rho1, 2.0 * P.ih * P.ih};
+  if (P.dim == 3)
+    hipLaunchKernelGGL((k0_resid64<R, 3>), dim3(L.nblocks), dim3(FX, FY), 0, s, op, L.kz, L.ntx, L.nty, b, scal, p, r,
+                       pbb, prr);
+  else
+    hipLaunchKernelGGL((k0_resid64<R, 2>), dim3(L.nblocks), dim3(FX, FY), 0, s, op, L.kz, L.ntx, L.nty, b, scal, p, r,
+                       pbb, prr);
+  return L.nblocks;
+}
+
 #define TCF_FINE_INST(R)                                                                                          \
   template int fine_spmv_upd<R>(hipStream_t, int, const Fine<R>&, const R*, const R*, R*, const double*, int,     \
                                 double*, const int*);                                                             \
@@ -521,7 +599,9 @@ void fine_resid_restrict(hipStream_t s, int dim, const Fine<R>& F, const R* b, c
   template int fine_smooth<R>(hipStream_t, int, const Fine<R>&, double, const R*, const R*, R*, const R*, int,    \
                               int, double, double*, const int*);                                                  \
   template void fine_resid_restrict<R>(hipStream_t, int, const Fine<R>&, const R*, const R*, R*, const R*, R*, double,  \
-                                        const int*);
+                                        const int*);                                                              \
+  template int resid64a<R>(const KParams&, hipStream_t, const R*, const double*, const double*, const double*,    \
+                           double*, double*, double*);
 
 TCF_FINE_INST(double)
 TCF_FINE_INST(float)

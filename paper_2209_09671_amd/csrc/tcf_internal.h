@@ -112,11 +112,6 @@ void coarsen_weights(hipStream_t s, int dim, const Level<R>& F, const Level<R>& 
 // level-1 weights from alpha (the fine weights are not stored)
 template <class R>
 void coarsen_from_alpha(const KParams& P, hipStream_t s, const R* a, const Level<R>& C);
-// r = -(b - mean) - K p in FP64 with the fine weights recomputed from alpha;
-// block partials of ||rhs||^2 and ||r||^2; returns the number of partials
-template <class R>
-int resid64a(const KParams& P, hipStream_t s, const R* a, const double* b, const double* scal, const double* p,
-              double* r, double* pbb, double* prr);
 
 // PCG / multigrid building blocks on a level; all partial sums in FP64
 template <class R>
@@ -146,6 +141,12 @@ void mg_coarse_solve(hipStream_t s, int dim, const Level<R>& L, const R* b, R* x
 
 // finest-level fused kernels (tcf_fine.hip); return the number of partials
 int fine_blocks(int nx, int ny, int nz);
+// r = -(b - mean) - K p in FP64 with the fine weights recomputed from alpha
+// (densities rho1 + clamp(alpha)(rho2 - rho1) of P); block partials of
+// ||rhs||^2 and ||r||^2
+template <class R>
+int resid64a(const KParams& P, hipStream_t s, const R* a, const double* b, const double* scal, const double* p,
+             double* r, double* pbb, double* prr);
 template <class R>
 int fine_spmv_upd(hipStream_t s, int dim, const Fine<R>& F, const R* z, const R* dold, R* dnew,
                   const double* scal, int first, double* part, const int* iflag);

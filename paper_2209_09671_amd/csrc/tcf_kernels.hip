@@ -900,98 +900,6 @@ __global__ void k_init_flags(int* iflag) {
   if (threadIdx.x < I_NFLAG) iflag[threadIdx.x] = 0;
 }
 
-// ---- FP64 refinement helpers -------------------------------------------------
-// FP64 residual r = -(b - mean b) - K p with the face weights recomputed from
-// alpha (a_f = (1/h^2) / (0.5 (rho_L + rho_R)) in FP64, the expression the
-// stored FP64 weights are made with): 28 bytes per cell instead of the 48 of
-// stored weights.  Block partials of ||rhs||^2 and ||r||^2.
-// FP64 reciprocal: hardware estimate refined by three Newton steps (each
-// doubles the correct bits; the result is within an ulp or two of 1/x, all
-// that the FP64 residual needs: the projection's own 1/rho_f agrees with it
-// to rounding).
-__device__ __forceinline__ double rcp64(double x) {
-  double r = __builtin_amdgcn_rcp(x);
-  r = fma(r, fma(-x, r, 1.0), r);
-  r = fma(r, fma(-x, r, 1.0), r);
-  r = fma(r, fma(-x, r, 1.0), r);
-  return r;
-}
-
-template <class R, int DIM>
-__global__ __launch_bounds__(256) void k_resid64a(KParams P, int kz, int ntx, int nty, const R* __restrict__ a,
-                                                  const double* __restrict__ b, const double* __restrict__ scal,
-                                                  const double* __restrict__ p, double* __restrict__ r,
-                                                  double* __restrict__ pbb, double* __restrict__ prr) {
-  // one column per thread, marching over a chunk of kz planes: the z
-  // neighbours of p and of the density roll through registers (loaded one
-  // plane ahead) and the weight of the face to the next plane is carried to
-  // it; the in-plane neighbours come through L1/L2 from the block's own rows
-  // and its neighbour tiles, which run on the same XCD.  Every load is
-  // unconditional: a missing neighbour (wall) reads the cell itself, whose
-  // term w (p_c - p_c) is exactly zero.
-  __shared__ double sh[8];
-  const int nx = P.nx, ny = P.ny, nz = P.nz;
-  const int t = xcd_tile();
-  const int tx = t % ntx, ty = (t / ntx) % nty, tz = t / (ntx * nty);
-  const int i = tx * BX + threadIdx.x, j = ty * BY + threadIdx.y;
-  const int k0 = tz * kz, k1 = min(k0 + kz, nz);
-  const bool act = i < nx && j < ny;
-  const size_t pl = (size_t)nx * ny;
-  const size_t col = act ? (size_t)i + (size_t)nx * j : 0;
-  // (an inactive thread reads its column 0 only)
-  const long oxm = act && i > 0 ? -1 : 0, oxp = act && i < nx - 1 ? 1 : 0;
-  const long oym = act && j > 0 ? -(long)nx : 0, oyp = act && j < ny - 1 ? (long)nx : 0;
-  const double c2 = 2.0 * P.ih * P.ih;  // a_f = c2 / (rho_L + rho_R)
-  auto rho = [&](R av) { return mixp((double)av, P.rho1, P.rho2); };
-  auto plane = [&](int kk) { return (size_t)min(max(kk, 0), nz - 1) * pl; };
-  const double mean = scal[S_MEAN];
-  double vb = 0.0, vr = 0.0;
-  double pm = p[col + plane(k0 - 1)], pc = p[col + plane(k0)], pp = p[col + plane(k0 + 1)];
-  R am = a[col + plane(k0 - 1)], ac = a[col + plane(k0)], ap = a[col + plane(k0 + 1)];
-  double wz = c2 * rcp64(rho(am) + rho(ac));  // face k-1 | k
-  for (int k = k0; k < k1; ++k) {
-    const size_t c = col + (size_t)k * pl;
-    const size_t cn = col + plane(k + 2);
-    const double pn = p[cn];
-    const R an = a[cn];
-    const double p0 = p[c + oxm], p1 = p[c + oxp], p2 = p[c + oym], p3 = p[c + oyp];
-    const R a0 = a[c + oxm], a1 = a[c + oxp], a2 = a[c + oym], a3 = a[c + oyp];
-    const double bc = b[c];
-    const double rc = rho(ac);
-    auto term = [&](double pnb, R anb) { return c2 * rcp64(rho(anb) + rc) * (pc - pnb); };
-    double sK = term(p0, a0);
-    sK += term(p1, a1);
-    sK += term(p2, a2);
-    sK += term(p3, a3);
-    double wzn = 0.0;
-    if (DIM == 3) {
-      sK += wz * (pc - pm);
-      wzn = c2 * rcp64(rc + rho(ap));
-      sK += wzn * (pc - pp);
-    }
-    const double rhs = -(bc - mean);
-    const double rr = rhs - sK;
-    if (act) {
-      r[c] = rr;
-      vb += rhs * rhs;
-      vr += rr * rr;
-    }
-    wz = wzn;
-    pm = pc;
-    pc = pp;
-    pp = pn;
-    am = ac;
-    ac = ap;
-    ap = an;
-  }
-  const double sb = block_reduce<0>(vb, sh);
-  const double sr = block_reduce<0>(vr, sh);
-  if (threadIdx.x == 0 && threadIdx.y == 0) {
-    pbb[blockIdx.x] = sb;
-    prr[blockIdx.x] = sr;
-  }
-}
-
 // First coarse level's face weights straight from alpha: the sum of the
 // 2x2 fine face weights it covers, each (float)((1/h^2) / (0.5 (rho_L +
 // rho_R))) as the fine weights of the FP32 hierarchy are defined.
@@ -1421,21 +1329,6 @@ void finalize(hipStream_t s, const double* part, int nparts, double* scal, int* 
 void init_flags(hipStream_t s, int* iflag) { hipLaunchKernelGGL(k_init_flags, dim3(1), dim3(64), 0, s, iflag); }
 
 template <class R>
-int resid64a(const KParams& P, hipStream_t s, const R* a, const double* b, const double* scal, const double* p,
-             double* r, double* pbb, double* prr) {
-  // chunks of planes so that the grid has >= 2048 blocks of 256
-  const int ntx = (P.nx + BX - 1) / BX, nty = (P.ny + BY - 1) / BY;
-  const int nz = P.dim == 3 ? P.nz : 1;
-  int nch = std::max(1, std::min(nz, (2048 + ntx * nty - 1) / (ntx * nty)));
-  const int kz = (nz + nch - 1) / nch;
-  nch = (nz + kz - 1) / kz;
-  dim3 g(ntx * nty * nch);
-  if (P.dim == 3) hipLaunchKernelGGL((k_resid64a<R, 3>), g, blk(), 0, s, P, kz, ntx, nty, a, b, scal, p, r, pbb, prr);
-  else hipLaunchKernelGGL((k_resid64a<R, 2>), g, blk(), 0, s, P, kz, ntx, nty, a, b, scal, p, r, pbb, prr);
-  return ntx * nty * nch;
-}
-
-template <class R>
 void coarsen_from_alpha(const KParams& P, hipStream_t s, const R* a, const Level<R>& C) {
   if (P.dim == 3) {
     hipLaunchKernelGGL((k_coarsen_a<R, 3, 0>), grid_for(C.nx + 1, C.ny, C.nz), blk(), 0, s, P, a, C.nx, C.ny, C.nz, C.ax);
@@ -1546,8 +1439,6 @@ void zero_walls(const KParams& P, hipStream_t s, R* u, R* v, R* w) {
   template void make_wdiag<R>(hipStream_t, int, const Level<R>&, double);                                         \
   template void coarsen_weights<R>(hipStream_t, int, const Level<R>&, const Level<R>&);                           \
   template void coarsen_from_alpha<R>(const KParams&, hipStream_t, const R*, const Level<R>&);                    \
-  template int resid64a<R>(const KParams&, hipStream_t, const R*, const double*, const double*, const double*,    \
-                           double*, double*, double*);                                                          \
   template void rhs_resid<R>(hipStream_t, int, const Level<R>&, const double*, const double*, R*, R*, double*,    \
                              double*);                                                                      \
   template void spmv_dot<R>(hipStream_t, int, const Level<R>&, const R*, R*, double*, const int*);          \
