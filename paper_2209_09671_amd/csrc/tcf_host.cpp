@@ -151,6 +151,9 @@ struct tcf_grid {
   double* hscal;  // pinned host mirror
   int* hflag;
   hipEvent_t rb_ev = nullptr;  // completion of the last copy into hscal
+  // CG iterations the last solve of each kind took (0: none yet): the
+  // state's pressure or another right-hand side, first or later refinement
+  int pcg_expect[4] = {0, 0, 0, 0};
   size_t bytes;
   // adjoint scratch (configs with TCF_WITH_ADJOINT; FP64 only)
   struct Adj {
@@ -665,9 +668,12 @@ void vcycle(tcf_grid* g, Fields<R>& F, size_t l, const R* b, R* out, R* tmp, dou
 // stream) while the preconditioner runs, then queues the next iteration.
 // Every kernel of the solve returns at once when the flag is set, so an
 // initial residual already below the tolerance ends after the first
-// iteration with no work done.
+// iteration with no work done.  From the iteration count at which the last
+// solve of the same kind converged on, the host waits for the flag before
+// queuing the preconditioner instead: a solve that has converged then ends
+// without queuing a preconditioner whose kernels would all return at once.
 template <class R>
-tcf_status pcg_iterate(tcf_grid* g, Fields<R>& F, R* x, R* r, int maxit, int* iters, bool* converged) {
+tcf_status pcg_iterate(tcf_grid* g, Fields<R>& F, R* x, R* r, int maxit, int kind, int* iters, bool* converged) {
   hipStream_t s = g->stream;
   const int dim = g->D.dim;
   const Fine<R> Fd = fine_desc<R>(g);
@@ -678,7 +684,10 @@ tcf_status pcg_iterate(tcf_grid* g, Fields<R>& F, R* x, R* r, int maxit, int* it
   finalize(s, g->part[0], np, g->scal, g->iflag, F_RZ_FIRST, 0, 0.0);
   R* dcur = F.d;
   R* dnext = F.d2;
+  const int expect = g->pcg_expect[kind];
+  int last = 0;
   for (int it = 1; it <= maxit; ++it) {
+    last = it;
     {
       Prof pr(g, FAM_SPMV);
       np = fine_spmv_upd<R>(s, dim, Fd, F.z, dcur, dnext, g->scal, it == 1 ? 1 : 0, g->part[0], g->iflag);
@@ -691,6 +700,10 @@ tcf_status pcg_iterate(tcf_grid* g, Fields<R>& F, R* x, R* r, int maxit, int* it
     }
     finalize(s, g->part[0], np, g->scal, g->iflag, F_RR, 0, 1.0);
     HIPCHECK(read_back_async(g));
+    if (expect > 0 && it >= expect) {
+      HIPCHECK(wait_back(g));
+      if (g->hflag[I_DONE]) break;
+    }
     vcycle<R>(g, F, 0, r, F.z, F.z2, g->part[0], true, &np);
     finalize(s, g->part[0], np, g->scal, g->iflag, F_RZ, 0, 0.0);
     HIPCHECK(wait_back(g));
@@ -698,11 +711,12 @@ tcf_status pcg_iterate(tcf_grid* g, Fields<R>& F, R* x, R* r, int maxit, int* it
   }
   *iters = g->hflag[I_ITERS];
   *converged = g->hflag[I_DONE] != 0 && std::isfinite(g->hscal[S_RR]);
+  g->pcg_expect[kind] = *converged ? last : 0;
   return TCF_OK;
 }
 
 // FP64 solve of A p = b (b in b64, its mean in scal[S_MEAN]); p warm start.
-tcf_status solve_fp64(tcf_grid* g, double* p, int* iters, double* relres, bool* converged) {
+tcf_status solve_fp64(tcf_grid* g, double* p, int kind, int* iters, double* relres, bool* converged) {
   hipStream_t s = g->stream;
   Fields<double>& F = g->f64;
   const Level<double>& L0 = F.lv[0];
@@ -727,7 +741,7 @@ tcf_status solve_fp64(tcf_grid* g, double* p, int* iters, double* relres, bool* 
     *converged = true;
     return TCF_OK;
   }
-  tcf_status st = pcg_iterate<double>(g, F, p, F.r, g->cfg.p_maxit, iters, converged);
+  tcf_status st = pcg_iterate<double>(g, F, p, F.r, g->cfg.p_maxit, kind, iters, converged);
   if (st != TCF_OK) return st;
   *relres = std::sqrt(g->hscal[S_RR] / bb);
   if (!std::isfinite(g->hscal[S_RR])) return TCF_E_NONFINITE;
@@ -735,7 +749,7 @@ tcf_status solve_fp64(tcf_grid* g, double* p, int* iters, double* relres, bool* 
 }
 
 // FP32 inner MG-PCG inside FP64 iterative refinement.
-tcf_status solve_refined(tcf_grid* g, double* p, int* iters, int* nref, double* relres, bool* converged) {
+tcf_status solve_refined(tcf_grid* g, double* p, int kind, int* iters, int* nref, double* relres, bool* converged) {
   hipStream_t s = g->stream;
   Fields<float>& F = g->f32;
   const long N = g->D.N;
@@ -784,7 +798,7 @@ tcf_status solve_refined(tcf_grid* g, double* p, int* iters, int* nref, double* 
     finalize(s, g->part[0], nb1, g->scal, g->iflag, F_BB, 0, tau * tau);
     int it = 0;
     bool conv = false;
-    tcf_status st = pcg_iterate<float>(g, F, F.x, F.r, g->cfg.p_maxit, &it, &conv);
+    tcf_status st = pcg_iterate<float>(g, F, F.x, F.r, g->cfg.p_maxit, kind + (ref > 0 ? 1 : 0), &it, &conv);
     if (st != TCF_OK) return st;
     *iters += it;
     add_scaled(s, N, F.x, g->scal, p);
@@ -828,8 +842,9 @@ tcf_status solve(tcf_grid* g, double* p, tcf_step_info* inf) {
   double relres = 0.0;
   bool conv = false;
   tcf_status st;
-  if (g->fp32) st = solve_refined(g, p, &iters, &nref, &relres, &conv);
-  else st = solve_fp64(g, p, &iters, &relres, &conv);
+  const int kind = p == g->p64 ? 0 : 2;
+  if (g->fp32) st = solve_refined(g, p, kind, &iters, &nref, &relres, &conv);
+  else st = solve_fp64(g, p, kind, &iters, &relres, &conv);
   if (st != TCF_OK) return st;
   // gauge: mean(p) = 0
   const int nbp = sum64_partials(g->stream, g->D.N, p, g->part[2]);
