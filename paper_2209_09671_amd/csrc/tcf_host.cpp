@@ -860,7 +860,7 @@ tcf_status solve(tcf_grid* g, double* p, tcf_step_info* inf) {
 }
 
 template <class R>
-tcf_status step_diag(tcf_grid* g, double dt, double dt_proj, tcf_step_info* inf);
+tcf_status step_diag(tcf_grid* g, double dt, double dt_proj, tcf_step_info* inf, bool launched = false);
 
 // N-phase model: a range of material `which` (0 density, 1 viscosity) that
 // holds every mixture P_1 + sum_j clamp(alpha_j)(P_j - P_1), so that the
@@ -997,11 +997,16 @@ tcf_status step_np(tcf_grid* g, double dt, tcf_step_info* inf, bool want_diag) {
     Pp.rho1 = lo;
     Pp.rho2 = hi;
     Prof pr(g, FAM_PROJECT);
-    project<R>(Pp, s, F.marho, g->p64, F.us, F.vs, F.ws, g->u64, g->v64, g->w64, g->fp32 ? F.u : nullptr,
-               g->fp32 ? F.v : nullptr, g->fp32 ? F.w : nullptr);
+    if (want_diag)  // with the end-of-step diagnostics in the same pass
+      project_diag<R>(Pp, s, F.marho, F.a, g->p64, F.us, F.vs, F.ws, g->u64, g->v64, g->w64, g->fp32 ? F.u : nullptr,
+                      g->fp32 ? F.v : nullptr, g->fp32 ? F.w : nullptr, g->part[0], g->nb, g->scal);
+    else
+      project<R>(Pp, s, F.marho, g->p64, F.us, F.vs, F.ws, g->u64, g->v64, g->w64, g->fp32 ? F.u : nullptr,
+                 g->fp32 ? F.v : nullptr, g->fp32 ? F.w : nullptr);
   }
   g->t += dt;
-  const tcf_status sd = want_diag ? step_diag<R>(g, dt, dt, inf) : TCF_OK;
+  const bool fused = want_diag && !(g->cfg.flags & TCF_TRANSPORT_ONLY);
+  const tcf_status sd = want_diag ? step_diag<R>(g, dt, dt, inf, fused) : TCF_OK;
   return sd != TCF_OK ? sd : st;
 }
 
@@ -1063,11 +1068,16 @@ tcf_status step_once(tcf_grid* g, double dt, tcf_step_info* inf, bool want_diag)
     if (st != TCF_OK && st != TCF_E_NOT_CONVERGED) return st;
     // S8
     Prof pr(g, FAM_PROJECT);
-    project<R>(P, s, F.a, g->p64, F.us, F.vs, F.ws, g->u64, g->v64, g->w64, g->fp32 ? F.u : nullptr,
-               g->fp32 ? F.v : nullptr, g->fp32 ? F.w : nullptr);
+    if (want_diag)  // with the end-of-step diagnostics in the same pass
+      project_diag<R>(P, s, F.a, F.a, g->p64, F.us, F.vs, F.ws, g->u64, g->v64, g->w64, g->fp32 ? F.u : nullptr,
+                      g->fp32 ? F.v : nullptr, g->fp32 ? F.w : nullptr, g->part[0], g->nb, g->scal);
+    else
+      project<R>(P, s, F.a, g->p64, F.us, F.vs, F.ws, g->u64, g->v64, g->w64, g->fp32 ? F.u : nullptr,
+                 g->fp32 ? F.v : nullptr, g->fp32 ? F.w : nullptr);
   }
   g->t += dt;
-  const tcf_status sd = want_diag ? step_diag<R>(g, dt, dt, inf) : TCF_OK;
+  const bool fused = want_diag && !(g->cfg.flags & TCF_TRANSPORT_ONLY);
+  const tcf_status sd = want_diag ? step_diag<R>(g, dt, dt, inf, fused) : TCF_OK;
   return sd != TCF_OK ? sd : st;
 }
 
@@ -1075,12 +1085,12 @@ tcf_status step_once(tcf_grid* g, double dt, tcf_step_info* inf, bool want_diag)
 // of the last projection: the divergence ratio is |D u| / |D u~| with
 // D u~ = dt_proj b.
 template <class R>
-tcf_status step_diag(tcf_grid* g, double dt, double dt_proj, tcf_step_info* inf) {
+tcf_status step_diag(tcf_grid* g, double dt, double dt_proj, tcf_step_info* inf, bool launched) {
   hipStream_t s = g->stream;
   Fields<R>& F = fields<R>(g);
   const KParams& P = g->P;
   {
-    diagnostics<R>(P, s, F.a, g->u64, g->v64, g->w64, g->part[0], g->nb, g->scal);
+    if (!launched) diagnostics<R>(P, s, F.a, g->u64, g->v64, g->w64, g->part[0], g->nb, g->scal);
     HIPCHECK(read_back(g));
     const double* h = g->hscal;
     if (inf) {
@@ -1184,8 +1194,13 @@ tcf_status step_rk3p(tcf_grid* g, double dt, tcf_step_info* inf, bool want_diag)
     acc.refine_iters += si.refine_iters;
     acc.p_relres = std::max(acc.p_relres, si.p_relres);
     Prof pr(g, FAM_PROJECT);
-    project<R>(Pp, s, as[k], g->p64, F.us, F.vs, F.ws, g->u64, g->v64, g->w64, g->fp32 ? F.u : nullptr,
-               g->fp32 ? F.v : nullptr, g->fp32 ? F.w : nullptr);
+    if (want_diag && k == 2)  // the last projection with the end-of-step diagnostics
+      project_diag<R>(Pp, s, as[k], F.a, g->p64, F.us, F.vs, F.ws, g->u64, g->v64, g->w64,
+                      g->fp32 ? F.u : nullptr, g->fp32 ? F.v : nullptr, g->fp32 ? F.w : nullptr, g->part[0], g->nb,
+                      g->scal);
+    else
+      project<R>(Pp, s, as[k], g->p64, F.us, F.vs, F.ws, g->u64, g->v64, g->w64, g->fp32 ? F.u : nullptr,
+                 g->fp32 ? F.v : nullptr, g->fp32 ? F.w : nullptr);
     dt_proj = Pp.dt;
   }
   if (mom) g->snhist = std::min(g->snhist + 1, g->cfg.p_extrapolate + 1);
@@ -1195,7 +1210,7 @@ tcf_status step_rk3p(tcf_grid* g, double dt, tcf_step_info* inf, bool want_diag)
     inf->refine_iters = acc.refine_iters;
     inf->p_relres = acc.p_relres;
   }
-  const tcf_status sd = want_diag ? step_diag<R>(g, dt, dt_proj, inf) : TCF_OK;
+  const tcf_status sd = want_diag ? step_diag<R>(g, dt, dt_proj, inf, mom) : TCF_OK;
   return sd != TCF_OK ? sd : worst;
 }
 

@@ -189,6 +189,13 @@ void fill(hipStream_t s, long n, R* y, double v);
 template <class R>
 void project(const KParams& P, hipStream_t s, const R* a, const double* p, const R* us, const R* vs,
              const R* ws, double* u, double* v, double* w, R* ur, R* vr, R* wr);
+// S8 and the diagnostics in one pass: the projection on the density fraction
+// arho (mixed over [P.rho1, P.rho2]), the diagnostics of the volume fraction
+// a on the projected velocity, as diagnostics() computes them
+template <class R>
+void project_diag(const KParams& P, hipStream_t s, const R* arho, const R* a, const double* p, const R* us,
+                  const R* vs, const R* ws, double* u, double* v, double* w, R* ur, R* vr, R* wr, double* part,
+                  int stride, double* scal);
 // per-block partials of the six diagnostics (stride apart, at most stride
 // blocks) reduced into scal[S_SUMA .. S_NONFIN]
 template <class R>

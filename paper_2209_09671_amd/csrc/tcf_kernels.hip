@@ -988,6 +988,13 @@ __global__ __launch_bounds__(256) void k_fill(long n, R* __restrict__ y, R v) {
 
 // ---------------------------------------------------------------------------
 // S8: projection; in FP32 mode also refresh the FP32 mirror of the velocity.
+// One interior face between the cells L and R.
+template <class R>
+__device__ __forceinline__ double proj_face(const KParams& P, R usv, R aL, R aR, double pL, double pR) {
+  const double rhof = 0.5 * (mixp((double)aL, P.rho1, P.rho2) + mixp((double)aR, P.rho1, P.rho2));
+  return (double)usv - P.dt * (1.0 / rhof) * (pR - pL) * P.ih;
+}
+
 template <class R, int DIM, int D>
 __global__ __launch_bounds__(256) void k_project(KParams P, const R* __restrict__ a, const double* __restrict__ p,
                                                  const R* __restrict__ us, double* __restrict__ u,
@@ -1004,11 +1011,30 @@ __global__ __launch_bounds__(256) void k_project(KParams P, const R* __restrict_
     int L[3] = {i, j, k};
     L[D] -= 1;
     const long cL = cidx(L[0], L[1], L[2], nx, ny), cR = cidx(i, j, k, nx, ny);
-    const double rhof = 0.5 * (mixp((double)a[cL], P.rho1, P.rho2) + mixp((double)a[cR], P.rho1, P.rho2));
-    val = (double)us[fo] - P.dt * (1.0 / rhof) * (p[cR] - p[cL]) * P.ih;
+    val = proj_face(P, us[fo], a[cL], a[cR], p[cL], p[cR]);
   }
   u[fo] = val;
   if (ur) ur[fo] = (R)val;
+}
+
+// Block partials of the six diagnostics, stride apart: sum alpha, min alpha,
+// max alpha, |Du|^2, max |u_f|, non-finite flag.
+__device__ __forceinline__ void diag_partials(double s, double mn, double mx, double d2, double um, double fin,
+                                              double* part, int stride, double* sh) {
+  const int bl = blockIdx.x;
+  double r;
+  r = block_reduce<0>(s, sh);
+  if (threadIdx.x == 0 && threadIdx.y == 0) part[bl] = r;
+  r = block_reduce<2>(mn, sh);
+  if (threadIdx.x == 0 && threadIdx.y == 0) part[stride + bl] = r;
+  r = block_reduce<1>(mx, sh);
+  if (threadIdx.x == 0 && threadIdx.y == 0) part[2 * stride + bl] = r;
+  r = block_reduce<0>(d2, sh);
+  if (threadIdx.x == 0 && threadIdx.y == 0) part[3 * stride + bl] = r;
+  r = block_reduce<1>(um, sh);
+  if (threadIdx.x == 0 && threadIdx.y == 0) part[4 * stride + bl] = r;
+  r = block_reduce<1>(fin, sh);
+  if (threadIdx.x == 0 && threadIdx.y == 0) part[5 * stride + bl] = r;
 }
 
 // Diagnostics per cell: alpha (sum/min/max), |D u|^2 and max |u_f| over the
@@ -1055,20 +1081,111 @@ __global__ __launch_bounds__(256) void k_diag(KParams P, int kz, int ntx, int nt
     }
     w0 = w1;
   }
-  const int bl = blockIdx.x;
-  double r;
-  r = block_reduce<0>(s, sh);
-  if (threadIdx.x == 0 && threadIdx.y == 0) part[bl] = r;
-  r = block_reduce<2>(mn, sh);
-  if (threadIdx.x == 0 && threadIdx.y == 0) part[stride + bl] = r;
-  r = block_reduce<1>(mx, sh);
-  if (threadIdx.x == 0 && threadIdx.y == 0) part[2 * stride + bl] = r;
-  r = block_reduce<0>(d2, sh);
-  if (threadIdx.x == 0 && threadIdx.y == 0) part[3 * stride + bl] = r;
-  r = block_reduce<1>(um, sh);
-  if (threadIdx.x == 0 && threadIdx.y == 0) part[4 * stride + bl] = r;
-  r = block_reduce<1>(fin, sh);
-  if (threadIdx.x == 0 && threadIdx.y == 0) part[5 * stride + bl] = r;
+  diag_partials(s, mn, mx, d2, um, fin, part, stride, sh);
+}
+
+// S8 fused with the diagnostics of k_diag: one pass instead of one per
+// velocity component plus k_diag.  Each thread marches the column of
+// k_diag's plan and writes the projected low faces of its cells (and the wall
+// faces at the high ends).  It recomputes its in-plane high faces from the
+// same operands with the same arithmetic (bitwise the values their own cells
+// write) and carries the z face between planes, so the diagnostics see
+// exactly the stored velocities and follow k_diag's order.  arho is the
+// density fraction of the projection (mixed over [P.rho1, P.rho2]), a the
+// volume fraction the diagnostics sum.  The column's centre values of p and
+// arho roll through registers, loaded one plane ahead; in-plane neighbours
+// are clamped into the grid (a wall face reads none of them).
+template <class R, int DIM>
+__global__ __launch_bounds__(256) void k_project_diag(KParams P, int kz, int ntx, int nty, const R* __restrict__ arho,
+                                                      const R* __restrict__ a, const double* __restrict__ p,
+                                                      const R* __restrict__ us, const R* __restrict__ vs,
+                                                      const R* __restrict__ ws, double* __restrict__ u,
+                                                      double* __restrict__ v, double* __restrict__ w,
+                                                      R* __restrict__ ur, R* __restrict__ vr, R* __restrict__ wr,
+                                                      double* __restrict__ part, int stride) {
+  __shared__ double sh[8];
+  const int nx = P.nx, ny = P.ny, nz = DIM == 3 ? P.nz : 1;
+  const int t = xcd_tile();
+  const int tx = t % ntx, ty = (t / ntx) % nty, tz = t / (ntx * nty);
+  const int i = tx * BX + threadIdx.x, j = ty * BY + threadIdx.y;
+  const int k0 = tz * kz, k1 = min(k0 + kz, nz);
+  const bool act = i < nx && j < ny;
+  const int ic = min(i, nx - 1), jc = min(j, ny - 1);
+  const long pl = (long)nx * ny, col = (long)ic + (long)nx * jc;
+  const bool xlo = ic > 0, xhi = ic < nx - 1, ylo = jc > 0, yhi = jc < ny - 1;
+  const long oxm = xlo ? -1 : 0, oxp = xhi ? 1 : 0, oym = ylo ? -(long)nx : 0, oyp = yhi ? (long)nx : 0;
+  auto plane = [&](int kk) { return (long)min(max(kk, 0), nz - 1) * pl; };
+  double s = 0.0, mn = DBL_MAX, mx = -DBL_MAX, d2 = 0.0, um = 0.0, fin = 0.0;
+  double pm = p[col + plane(k0 - 1)], pc = p[col + plane(k0)], pp = p[col + plane(k0 + 1)];
+  R am = arho[col + plane(k0 - 1)], ac = arho[col + plane(k0)], ap = arho[col + plane(k0 + 1)];
+  double wlo = 0.0;  // projected z face below the plane
+  if (DIM == 3 && k0 > 0) wlo = proj_face(P, ws[col + (long)k0 * pl], am, ac, pm, pc);
+  for (int k = k0; k < k1; ++k) {
+    const long c = col + (long)k * pl;
+    const long cn = col + plane(k + 2);
+    const double pn = p[cn];
+    const R an = arho[cn];
+    const double px0 = p[c + oxm], px1 = p[c + oxp], py0 = p[c + oym], py1 = p[c + oyp];
+    const R ax0 = arho[c + oxm], ax1 = arho[c + oxp], ay0 = arho[c + oym], ay1 = arho[c + oyp];
+    const long fx = fidx<0>(ic, jc, k, nx, ny), fy = fidx<1>(ic, jc, k, nx, ny);
+    const R usl = us[fx], ush = us[fx + 1], vsl = vs[fy], vsh = vs[fy + nx];
+    const R wsh = DIM == 3 ? ws[c + pl] : R(0);
+    const double av = (double)a[c];
+    const double u0 = xlo ? proj_face(P, usl, ax0, ac, px0, pc) : 0.0;
+    const double u1 = xhi ? proj_face(P, ush, ac, ax1, pc, px1) : 0.0;
+    const double v0 = ylo ? proj_face(P, vsl, ay0, ac, py0, pc) : 0.0;
+    const double v1 = yhi ? proj_face(P, vsh, ac, ay1, pc, py1) : 0.0;
+    const double w0 = wlo;
+    const double w1 = DIM == 3 && k + 1 < nz ? proj_face(P, wsh, ac, ap, pc, pp) : 0.0;
+    if (act) {
+      u[fx] = u0;
+      v[fy] = v0;
+      if (ur) ur[fx] = (R)u0;
+      if (vr) vr[fy] = (R)v0;
+      if (i == nx - 1) {
+        u[fx + 1] = 0.0;
+        if (ur) ur[fx + 1] = R(0);
+      }
+      if (j == ny - 1) {
+        v[fy + nx] = 0.0;
+        if (vr) vr[fy + nx] = R(0);
+      }
+      if (DIM == 3) {
+        w[c] = w0;
+        if (wr) wr[c] = (R)w0;
+        if (k == nz - 1) {
+          w[c + pl] = 0.0;
+          if (wr) wr[c + pl] = R(0);
+        }
+      }
+    }
+    // the diagnostics of k_diag on the projected faces
+    double dv = (u1 - u0) + (v1 - v0);
+    double m = fmax(fabs(u0), fabs(v0));
+    double chk = av + u0 + v0;
+    if (DIM == 3) {
+      dv += w1 - w0;
+      m = fmax(m, fabs(w0));
+      chk += w0;
+    }
+    dv *= P.ih;
+    if (act) {
+      s += av;
+      mn = fmin(mn, av);
+      mx = fmax(mx, av);
+      d2 += dv * dv;
+      um = fmax(um, m);
+      fin = isfinite(chk) ? fin : 1.0;
+    }
+    wlo = w1;
+    pm = pc;
+    pc = pp;
+    pp = pn;
+    am = ac;
+    ac = ap;
+    ap = an;
+  }
+  diag_partials(s, mn, mx, d2, um, fin, part, stride, sh);
 }
 
 // The six diagnostics reductions of k_diag's partials in one launch, each in
@@ -1380,16 +1497,39 @@ void project(const KParams& P, hipStream_t s, const R* a, const double* p, const
   }
 }
 
+// Column plan of the diagnostics: chunks of planes so that the grid has
+// >= 2048 blocks of 256; returns the number of blocks.
+static int diag_plan(const KParams& P, int* kz, int* ntx, int* nty) {
+  *ntx = (P.nx + BX - 1) / BX;
+  *nty = (P.ny + BY - 1) / BY;
+  const int nz = P.dim == 3 ? P.nz : 1;
+  const int cols = *ntx * *nty;
+  int nch = std::max(1, std::min(nz, (2048 + cols - 1) / cols));
+  *kz = (nz + nch - 1) / nch;
+  nch = (nz + *kz - 1) / *kz;
+  return cols * nch;
+}
+
+template <class R>
+void project_diag(const KParams& P, hipStream_t s, const R* arho, const R* a, const double* p, const R* us,
+                  const R* vs, const R* ws, double* u, double* v, double* w, R* ur, R* vr, R* wr, double* part,
+                  int stride, double* scal) {
+  int kz, ntx, nty;
+  const int nb = diag_plan(P, &kz, &ntx, &nty);
+  if (P.dim == 3)
+    hipLaunchKernelGGL((k_project_diag<R, 3>), dim3(nb), blk(), 0, s, P, kz, ntx, nty, arho, a, p, us, vs, ws, u, v, w,
+                       ur, vr, wr, part, stride);
+  else
+    hipLaunchKernelGGL((k_project_diag<R, 2>), dim3(nb), blk(), 0, s, P, kz, ntx, nty, arho, a, p, us, vs, ws, u, v, w,
+                       ur, vr, wr, part, stride);
+  hipLaunchKernelGGL(k_finalize_diag, dim3(1), dim3(1024), 0, s, part, nb, stride, scal);
+}
+
 template <class R>
 void diagnostics(const KParams& P, hipStream_t s, const R* a, const double* u, const double* v, const double* w,
                  double* part, int stride, double* scal) {
-  // chunks of planes so that the grid has >= 2048 blocks of 256
-  const int ntx = (P.nx + BX - 1) / BX, nty = (P.ny + BY - 1) / BY;
-  const int nz = P.dim == 3 ? P.nz : 1;
-  int nch = std::max(1, std::min(nz, (2048 + ntx * nty - 1) / (ntx * nty)));
-  const int kz = (nz + nch - 1) / nch;
-  nch = (nz + kz - 1) / kz;
-  const int nb = ntx * nty * nch;
+  int kz, ntx, nty;
+  const int nb = diag_plan(P, &kz, &ntx, &nty);
   if (P.dim == 3) hipLaunchKernelGGL((k_diag<R, 3>), dim3(nb), blk(), 0, s, P, kz, ntx, nty, a, u, v, w, part, stride);
   else hipLaunchKernelGGL((k_diag<R, 2>), dim3(nb), blk(), 0, s, P, kz, ntx, nty, a, u, v, w, part, stride);
   hipLaunchKernelGGL(k_finalize_diag, dim3(1), dim3(1024), 0, s, part, nb, stride, scal);
@@ -1455,6 +1595,9 @@ void zero_walls(const KParams& P, hipStream_t s, R* u, R* v, R* w) {
                            double*, double*, double*, R*, R*, R*);                                                \
   template void diagnostics<R>(const KParams&, hipStream_t, const R*, const double*, const double*,               \
                                const double*, double*, int, double*);                                       \
+  template void project_diag<R>(const KParams&, hipStream_t, const R*, const R*, const double*, const R*,        \
+                                const R*, const R*, double*, double*, double*, R*, R*, R*, double*, int,       \
+                                double*);                                                                   \
   template void zero_walls<R>(const KParams&, hipStream_t, R*, R*, R*);
 
 TCF_INST(double)
