@@ -328,10 +328,11 @@ __global__ __launch_bounds__(FX * FY) void k0_spmv_upd(Op0<R> op, int kz, int nt
 
 // x += alpha d; r -= alpha K0 d (K0 d recomputed from the streamed d, the
 // same arithmetic as the SpMV pass; partial r.r); z1 = omega r / diag (first
-// sweep of the next V-cycle from a zero guess)
+// sweep of the next V-cycle from a zero guess).  With xzero, x starts from
+// zero and is not read (x = alpha d).
 template <class R, int DIM>
 __global__ __launch_bounds__(FX * FY) void k0_update_smooth(Op0<R> op, int kz, int ntx, int nty, R omega,
-                                                        const double* __restrict__ scal, R* __restrict__ x,
+                                                        const double* __restrict__ scal, int xzero, R* __restrict__ x,
                                                         R* __restrict__ r, const R* __restrict__ d,
                                                         R* __restrict__ z1, double* __restrict__ part,
                                                         const int* __restrict__ iflag) {
@@ -340,10 +341,11 @@ __global__ __launch_bounds__(FX * FY) void k0_update_smooth(Op0<R> op, int kz, i
   const R al = R(scal[S_ALPHA]);
   double acc = 0.0;
   auto X = [&](long c, int, int, int) { return d[c]; };
-  auto pre = [&](long c) { return Vec2<R>{x[c], r[c]}; };
+  const R* __restrict__ xs = xzero ? r : x;  // from zero: a load of r, which is read anyway
+  auto pre = [&](long c) { return Vec2<R>{xs[c], r[c]}; };
   const Ident<R> XV;
   auto body = [&](long c, int, R dc, R Kd, R dg, const Vec2<R>& v) {
-    x[c] = v.a + al * dc;
+    x[c] = (xzero ? R(0) : v.a) + al * dc;
     const R rn = v.b - al * Kd;
     r[c] = rn;
     acc += (double)rn * (double)rn;
@@ -513,16 +515,16 @@ int fine_spmv_upd(hipStream_t s, int dim, const Fine<R>& F, const R* z, const R*
 }
 
 template <class R>
-int fine_update_smooth(hipStream_t s, int dim, const Fine<R>& F, double omega, const double* scal, R* x, R* r,
-                       const R* d, R* z1, double* part, const int* iflag) {
+int fine_update_smooth(hipStream_t s, int dim, const Fine<R>& F, double omega, const double* scal, int xzero, R* x,
+                       R* r, const R* d, R* z1, double* part, const int* iflag) {
   const Launch L = plan(F.nx, F.ny, F.nz);
   const Op0<R> op = op_of(F);
   if (dim == 3)
     hipLaunchKernelGGL((k0_update_smooth<R, 3>), dim3(L.nblocks), dim3(FX, FY), 0, s, op, L.kz, L.ntx, L.nty, R(omega),
-                       scal, x, r, d, z1, part, iflag);
+                       scal, xzero, x, r, d, z1, part, iflag);
   else
     hipLaunchKernelGGL((k0_update_smooth<R, 2>), dim3(L.nblocks), dim3(FX, FY), 0, s, op, L.kz, L.ntx, L.nty, R(omega),
-                       scal, x, r, d, z1, part, iflag);
+                       scal, xzero, x, r, d, z1, part, iflag);
   return L.nblocks;
 }
 
@@ -593,7 +595,7 @@ int resid64a(const KParams& P, hipStream_t s, const R* a, const double* b, const
 #define TCF_FINE_INST(R)                                                                                          \
   template int fine_spmv_upd<R>(hipStream_t, int, const Fine<R>&, const R*, const R*, R*, const double*, int,     \
                                 double*, const int*);                                                             \
-  template int fine_update_smooth<R>(hipStream_t, int, const Fine<R>&, double, const double*, R*, R*, const R*,   \
+  template int fine_update_smooth<R>(hipStream_t, int, const Fine<R>&, double, const double*, int, R*, R*, const R*, \
                                      R*, double*, const int*);                                                    \
   template void fine_smooth_first<R>(hipStream_t, int, const Fine<R>&, double, const R*, R*, const int*);         \
   template int fine_smooth<R>(hipStream_t, int, const Fine<R>&, double, const R*, const R*, R*, const R*, int,    \

@@ -672,8 +672,12 @@ void vcycle(tcf_grid* g, Fields<R>& F, size_t l, const R* b, R* out, R* tmp, dou
 // solve of the same kind converged on, the host waits for the flag before
 // queuing the preconditioner instead: a solve that has converged then ends
 // without queuing a preconditioner whose kernels would all return at once.
+// With x_zero, x starts from zero without being cleared: the first update
+// writes x = alpha d (the first update always runs, the flag being set only
+// by the residual norm after it).
 template <class R>
-tcf_status pcg_iterate(tcf_grid* g, Fields<R>& F, R* x, R* r, int maxit, int kind, int* iters, bool* converged) {
+tcf_status pcg_iterate(tcf_grid* g, Fields<R>& F, R* x, R* r, int maxit, int kind, bool x_zero, int* iters,
+                       bool* converged) {
   hipStream_t s = g->stream;
   const int dim = g->D.dim;
   const Fine<R> Fd = fine_desc<R>(g);
@@ -696,7 +700,8 @@ tcf_status pcg_iterate(tcf_grid* g, Fields<R>& F, R* x, R* r, int maxit, int kin
     std::swap(dcur, dnext);
     {
       Prof pr(g, FAM_UPDATE);
-      np = fine_update_smooth<R>(s, dim, Fd, wj, g->scal, x, r, dcur, F.z2, g->part[0], g->iflag);
+      np = fine_update_smooth<R>(s, dim, Fd, wj, g->scal, x_zero && it == 1 ? 1 : 0, x, r, dcur, F.z2, g->part[0],
+                                 g->iflag);
     }
     finalize(s, g->part[0], np, g->scal, g->iflag, F_RR, 0, 1.0);
     HIPCHECK(read_back_async(g));
@@ -741,7 +746,7 @@ tcf_status solve_fp64(tcf_grid* g, double* p, int kind, int* iters, double* relr
     *converged = true;
     return TCF_OK;
   }
-  tcf_status st = pcg_iterate<double>(g, F, p, F.r, g->cfg.p_maxit, kind, iters, converged);
+  tcf_status st = pcg_iterate<double>(g, F, p, F.r, g->cfg.p_maxit, kind, false, iters, converged);
   if (st != TCF_OK) return st;
   *relres = std::sqrt(g->hscal[S_RR] / bb);
   if (!std::isfinite(g->hscal[S_RR])) return TCF_E_NONFINITE;
@@ -749,7 +754,10 @@ tcf_status solve_fp64(tcf_grid* g, double* p, int kind, int* iters, double* relr
 }
 
 // FP32 inner MG-PCG inside FP64 iterative refinement.
-tcf_status solve_refined(tcf_grid* g, double* p, int kind, int* iters, int* nref, double* relres, bool* converged) {
+// psum: the number of partials of sum(p) left in part[2] by the last
+// correction (0: none, the caller sums p itself).
+tcf_status solve_refined(tcf_grid* g, double* p, int kind, int* iters, int* nref, double* relres, bool* converged,
+                         int* psum) {
   hipStream_t s = g->stream;
   Fields<float>& F = g->f32;
   const long N = g->D.N;
@@ -759,6 +767,7 @@ tcf_status solve_refined(tcf_grid* g, double* p, int kind, int* iters, int* nref
   *iters = 0;
   *nref = 0;
   *converged = false;
+  *psum = 0;
   double bb = 0.0;
   int nrp = 0;
   for (int ref = 0;; ++ref) {
@@ -790,7 +799,6 @@ tcf_status solve_refined(tcf_grid* g, double* p, int kind, int* iters, int* nref
     if (ref >= g->cfg.refine_maxit) break;
     // inner solve of K e = r64 / scale in FP32 from e = 0
     scale_to32(s, N, g->r64, g->scal, F.r, g->part[0]);  // with the partials of |r32|^2
-    fill<float>(s, N, F.x, 0.0);
     init_flags(s, g->iflag);
     // reduce the scaled residual only as far as this sweep needs to reach
     // the FP64 target (never below inner_rtol)
@@ -798,10 +806,10 @@ tcf_status solve_refined(tcf_grid* g, double* p, int kind, int* iters, int* nref
     finalize(s, g->part[0], nb1, g->scal, g->iflag, F_BB, 0, tau * tau);
     int it = 0;
     bool conv = false;
-    tcf_status st = pcg_iterate<float>(g, F, F.x, F.r, g->cfg.p_maxit, kind + (ref > 0 ? 1 : 0), &it, &conv);
+    tcf_status st = pcg_iterate<float>(g, F, F.x, F.r, g->cfg.p_maxit, kind + (ref > 0 ? 1 : 0), true, &it, &conv);
     if (st != TCF_OK) return st;
     *iters += it;
-    add_scaled(s, N, F.x, g->scal, p);
+    *psum = add_scaled(s, N, F.x, g->scal, p, g->part[2]);
     *nref = ref + 1;
   }
   return TCF_OK;
@@ -843,11 +851,12 @@ tcf_status solve(tcf_grid* g, double* p, tcf_step_info* inf) {
   bool conv = false;
   tcf_status st;
   const int kind = p == g->p64 ? 0 : 2;
-  if (g->fp32) st = solve_refined(g, p, kind, &iters, &nref, &relres, &conv);
+  int nbp = 0;  // partials of sum(p) in part[2], if the solve left them
+  if (g->fp32) st = solve_refined(g, p, kind, &iters, &nref, &relres, &conv, &nbp);
   else st = solve_fp64(g, p, kind, &iters, &relres, &conv);
   if (st != TCF_OK) return st;
   // gauge: mean(p) = 0
-  const int nbp = sum64_partials(g->stream, g->D.N, p, g->part[2]);
+  if (nbp == 0) nbp = sum64_partials(g->stream, g->D.N, p, g->part[2]);
   finalize(g->stream, g->part[2], nbp, g->scal, g->iflag, F_MEAN, S_PMEAN, (double)g->D.N);
   subtract_mean(g->stream, g->D.N, g->scal, S_PMEAN, p);
   if (inf) {

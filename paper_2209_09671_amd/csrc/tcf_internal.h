@@ -151,7 +151,7 @@ template <class R>
 int fine_spmv_upd(hipStream_t s, int dim, const Fine<R>& F, const R* z, const R* dold, R* dnew,
                   const double* scal, int first, double* part, const int* iflag);
 template <class R>
-int fine_update_smooth(hipStream_t s, int dim, const Fine<R>& F, double omega, const double* scal, R* x, R* r,
+int fine_update_smooth(hipStream_t s, int dim, const Fine<R>& F, double omega, const double* scal, int xzero, R* x, R* r,
                        const R* d, R* z1, double* part, const int* iflag);
 template <class R>
 void fine_smooth_first(hipStream_t s, int dim, const Fine<R>& F, double omega, const R* b, R* z1, const int* iflag);
@@ -178,7 +178,9 @@ void init_flags(hipStream_t s, int* iflag);
 // FP64 refinement helpers (FP32 mode)
 // r32 = r / scal[S_SCALE]; part: nblocks(256) partials of |r32|^2
 void scale_to32(hipStream_t s, long n, const double* r, const double* scal, float* r32, double* part);
-void add_scaled(hipStream_t s, long n, const float* e, const double* scal, double* p);
+// p += scal[S_SCALE] e; part: nblocks(256) partials of the new p, as
+// sum64_partials(p) gives them; returns their number
+int add_scaled(hipStream_t s, long n, const float* e, const double* scal, double* p, double* part);
 void subtract_mean(hipStream_t s, long n, const double* scal, int slot, double* p);
 int sum64_partials(hipStream_t s, long n, const double* x, double* part);
 template <class R>

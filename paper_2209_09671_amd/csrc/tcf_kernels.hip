@@ -952,10 +952,20 @@ __global__ __launch_bounds__(256) void k_scale_to32(long n, const double* __rest
   const double sm = block_reduce<0>(v, sh);
   if (threadIdx.x == 0) part[blockIdx.x] = sm;
 }
+// p += scale e, with per-block partial sums of the new p (the blocks and the
+// order of k_sum64, so the mean is the one k_sum64 would give)
 __global__ __launch_bounds__(256) void k_add_scaled(long n, const float* __restrict__ e,
-                                                    const double* __restrict__ scal, double* __restrict__ p) {
+                                                    const double* __restrict__ scal, double* __restrict__ p,
+                                                    double* __restrict__ part) {
+  __shared__ double sh[8];
   const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c < n) p[c] += scal[S_SCALE] * (double)e[c];
+  double v = 0.0;
+  if (c < n) {
+    v = p[c] + scal[S_SCALE] * (double)e[c];
+    p[c] = v;
+  }
+  const double s = block_reduce<0>(v, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 __global__ __launch_bounds__(256) void k_sub_mean(long n, const double* __restrict__ scal, int slot,
                                                   double* __restrict__ p) {
@@ -1460,8 +1470,9 @@ void coarsen_from_alpha(const KParams& P, hipStream_t s, const R* a, const Level
 void scale_to32(hipStream_t s, long n, const double* r, const double* scal, float* r32, double* part) {
   hipLaunchKernelGGL(k_scale_to32, dim3(nblk1(n)), dim3(256), 0, s, n, r, scal, r32, part);
 }
-void add_scaled(hipStream_t s, long n, const float* e, const double* scal, double* p) {
-  hipLaunchKernelGGL(k_add_scaled, dim3(nblk1(n)), dim3(256), 0, s, n, e, scal, p);
+int add_scaled(hipStream_t s, long n, const float* e, const double* scal, double* p, double* part) {
+  hipLaunchKernelGGL(k_add_scaled, dim3(nblk1(n)), dim3(256), 0, s, n, e, scal, p, part);
+  return nblk1(n);
 }
 void subtract_mean(hipStream_t s, long n, const double* scal, int slot, double* p) {
   hipLaunchKernelGGL(k_sub_mean, dim3(nblk1(n)), dim3(256), 0, s, n, scal, slot, p);
