@@ -41,18 +41,23 @@ __device__ __forceinline__ float rcpx(float x) { return __builtin_amdgcn_rcpf(x)
 __device__ __forceinline__ double rcpx(double x) { return 1.0 / x; }
 
 // WENO5-JS reconstruction at the right edge of c, with one reciprocal for
-// the normalisation of each smoothness weight and one for the blend.
+// the normalisation of each smoothness weight and one for the blend.  The
+// smoothness indicators beta_k = (13/12) t_k^2 + (1/4) u_k^2 and epsilon are
+// both taken times 12/13 (eps_w = (12/13) eps), which leaves the normalised
+// weights d_k / (eps + beta_k)^2 unchanged: one multiply and two FMAs per
+// indicator.
 template <class R>
-__device__ __forceinline__ R weno5r(R a, R b, R c, R d, R e, R eps) {
+__device__ __forceinline__ R weno5r(R a, R b, R c, R d, R e, R epsw) {
   const R q0 = (R(2) * a - R(7) * b + R(11) * c);
   const R q1 = (-b + R(5) * c + R(2) * d);
   const R q2 = (R(2) * c + R(5) * d - e);
   const R t0 = a - R(2) * b + c, u0 = a - R(4) * b + R(3) * c;
   const R t1 = b - R(2) * c + d, u1 = b - d;
   const R t2 = c - R(2) * d + e, u2 = R(3) * c - R(4) * d + e;
-  const R i0 = rcpx(eps + (R(13.0 / 12.0) * t0 * t0 + R(0.25) * u0 * u0));
-  const R i1 = rcpx(eps + (R(13.0 / 12.0) * t1 * t1 + R(0.25) * u1 * u1));
-  const R i2 = rcpx(eps + (R(13.0 / 12.0) * t2 * t2 + R(0.25) * u2 * u2));
+  const R cu = R(3.0 / 13.0);
+  const R i0 = rcpx(fma(cu * u0, u0, fma(t0, t0, epsw)));
+  const R i1 = rcpx(fma(cu * u1, u1, fma(t1, t1, epsw)));
+  const R i2 = rcpx(fma(cu * u2, u2, fma(t2, t2, epsw)));
   const R a0 = R(0.1) * i0 * i0, a1 = R(0.6) * i1 * i1, a2 = R(0.3) * i2 * i2;
   return (a0 * q0 + a1 * q1 + a2 * q2) * rcpx(R(6) * (a0 + a1 + a2));
 }
@@ -202,7 +207,7 @@ __device__ __forceinline__ void pred_body(const PredArgs<R, DIM, D>& A, int kz, 
   const int k0 = tile_z * kz, k1 = min(k0 + kz, mz);
   const bool act = i < fn0 && j < fn1;
   const bool cval = i < fn0 + H && j < fn1 + H && !(i >= fn0 && j >= fn1);
-  const R eps = R(P.weno_eps), ih = R(P.ih), dt = R(P.dt);
+  const R eps = R(P.weno_eps * (12.0 / 13.0)), ih = R(P.ih), dt = R(P.dt);  // eps_w of weno5r
   // x-direction flux items: per row the 64 faces' low sides and the last
   // face's high side (65 positions, 520 per tile); every thread takes one,
   // threads 64..71 one more
