@@ -534,9 +534,9 @@ void build_levels(tcf_grid* g, Fields<R>& F, const R* a, bool level0_stored) {
   const int dim = g->D.dim;
   if (F.lv.size() == 1) make_wdiag<R>(g->stream, dim, F.lv[0], 1.0);
   for (size_t l = 1; l < F.lv.size(); ++l) {
+    // the level's weights and 1/diag in one pass
     if (l == 1 && !level0_stored) coarsen_from_alpha<R>(op_params(g), g->stream, a, F.lv[1]);
     else coarsen_weights<R>(g->stream, dim, F.lv[l - 1], F.lv[l]);
-    make_wdiag<R>(g->stream, dim, F.lv[l], 1.0);
   }
   if (F.cinv) coarse_factor<R>(g->stream, dim, F.lv.back(), F.cfac, F.cinv);
 }

@@ -107,9 +107,11 @@ void face_weights(const KParams& P, hipStream_t s, const R* a, double* ax, doubl
                   float* fx, float* fy, float* fz);
 template <class R>
 void make_wdiag(hipStream_t s, int dim, const Level<R>& L, double omega);
+// Galerkin weights of the coarse level C from the level F below it, and
+// C's 1/diag, in one pass
 template <class R>
 void coarsen_weights(hipStream_t s, int dim, const Level<R>& F, const Level<R>& C);
-// level-1 weights from alpha (the fine weights are not stored)
+// the same for level 1 straight from alpha (the fine weights are not stored)
 template <class R>
 void coarsen_from_alpha(const KParams& P, hipStream_t s, const R* a, const Level<R>& C);
 

@@ -274,26 +274,73 @@ __global__ __launch_bounds__(256) void k_wdiag(int nx, int ny, int nz, const R* 
   wd[cidx(i, j, k, nx, ny)] = d > R(0) ? omega / d : R(0);
 }
 
-// Galerkin coarse face weights for piecewise-constant P and R = P^T.
-template <class R, int DIM, int D>
-__global__ __launch_bounds__(256) void k_coarsen(int fnx_, int fny_, int fnz_, const R* __restrict__ ff,
-                                                 int cnx, int cny, int cnz, R* __restrict__ cf) {
-  const int I = blockIdx.x * BX + threadIdx.x, J = blockIdx.y * BY + threadIdx.y, K = blockIdx.z;
-  const int cfx = cnx + (D == 0), cfy = cny + (D == 1);
-  if (I >= cfx || J >= cfy) return;
+// One coarse level of the Galerkin hierarchy in one pass.  A fine face
+// weight along D: stored (ff), or with FROMA computed from alpha as the
+// finest weights are defined, (R)((1/h^2) / (0.5 (rho_L + rho_R))), 0 on the
+// walls (the first coarse level when the finest weights are not stored).
+template <class R, int D, bool FROMA>
+__device__ __forceinline__ R fine_w(const KParams& P, const R* __restrict__ a, const R* __restrict__ ff, int fnx,
+                                    int fny, int fnz, int i, int j, int k) {
+  if (!FROMA) return ff[fidx<D>(i, j, k, fnx, fny)];
+  const int id[3] = {i, j, k};
+  const int nD = D == 0 ? fnx : (D == 1 ? fny : fnz);
+  if (id[D] <= 0 || id[D] >= nD) return R(0);
+  int L[3] = {i, j, k};
+  L[D] -= 1;
+  const double ih2 = P.ih * P.ih;
+  const double rL = mixp((double)a[cidx(L[0], L[1], L[2], fnx, fny)], P.rho1, P.rho2);
+  const double rR = mixp((double)a[cidx(i, j, k, fnx, fny)], P.rho1, P.rho2);
+  return R(ih2 / (0.5 * (rL + rR)));
+}
+
+// Coarse face (I, J, K) along D: the sum of the 2x2 fine faces it covers
+// (piecewise-constant P, R = P^T), in a fixed order.
+template <class R, int DIM, int D, bool FROMA>
+__device__ __forceinline__ R coarse_face(const KParams& P, const R* __restrict__ a, const R* __restrict__ ff,
+                                         int fnx, int fny, int fnz, int I, int J, int K) {
   const int kz = DIM == 3 ? 2 : 1;
   R s = R(0);
   if (D == 0) {
     for (int dk = 0; dk < kz; ++dk)
-      for (int dj = 0; dj < 2; ++dj) s += ff[fidx<0>(2 * I, 2 * J + dj, kz * K + dk, fnx_, fny_)];
+      for (int dj = 0; dj < 2; ++dj) s += fine_w<R, 0, FROMA>(P, a, ff, fnx, fny, fnz, 2 * I, 2 * J + dj, kz * K + dk);
   } else if (D == 1) {
     for (int dk = 0; dk < kz; ++dk)
-      for (int di = 0; di < 2; ++di) s += ff[fidx<1>(2 * I + di, 2 * J, kz * K + dk, fnx_, fny_)];
+      for (int di = 0; di < 2; ++di) s += fine_w<R, 1, FROMA>(P, a, ff, fnx, fny, fnz, 2 * I + di, 2 * J, kz * K + dk);
   } else {
     for (int dj = 0; dj < 2; ++dj)
-      for (int di = 0; di < 2; ++di) s += ff[fidx<2>(2 * I + di, 2 * J + dj, 2 * K, fnx_, fny_)];
+      for (int di = 0; di < 2; ++di) s += fine_w<R, 2, FROMA>(P, a, ff, fnx, fny, fnz, 2 * I + di, 2 * J + dj, 2 * K);
   }
-  cf[fidx<D>(I, J, K, cnx, cny)] = s;
+  return s;
+}
+
+// One thread per coarse cell: its low face weights along x, y, z (and the
+// wall faces at the high ends) and omega / diag of the cell, whose high faces
+// (written by the neighbours) are recomputed with the same sums.
+template <class R, int DIM, bool FROMA>
+__global__ __launch_bounds__(256) void k_coarsen_level(KParams P, const R* __restrict__ a, const R* __restrict__ fx,
+                                                       const R* __restrict__ fy, const R* __restrict__ fz, int fnx,
+                                                       int fny, int fnz, int cnx, int cny, int cnz,
+                                                       R* __restrict__ cx, R* __restrict__ cy, R* __restrict__ cz,
+                                                       R* __restrict__ wd, R omega) {
+  const int I = blockIdx.x * BX + threadIdx.x, J = blockIdx.y * BY + threadIdx.y, K = blockIdx.z;
+  if (I >= cnx || J >= cny) return;
+  const R x0 = coarse_face<R, DIM, 0, FROMA>(P, a, fx, fnx, fny, fnz, I, J, K);
+  const R x1 = coarse_face<R, DIM, 0, FROMA>(P, a, fx, fnx, fny, fnz, I + 1, J, K);
+  const R y0 = coarse_face<R, DIM, 1, FROMA>(P, a, fy, fnx, fny, fnz, I, J, K);
+  const R y1 = coarse_face<R, DIM, 1, FROMA>(P, a, fy, fnx, fny, fnz, I, J + 1, K);
+  cx[fidx<0>(I, J, K, cnx, cny)] = x0;
+  if (I == cnx - 1) cx[fidx<0>(cnx, J, K, cnx, cny)] = x1;
+  cy[fidx<1>(I, J, K, cnx, cny)] = y0;
+  if (J == cny - 1) cy[fidx<1>(I, cny, K, cnx, cny)] = y1;
+  R d = x0 + x1 + y0 + y1;
+  if (DIM == 3) {
+    const R z0 = coarse_face<R, DIM, 2, FROMA>(P, a, fz, fnx, fny, fnz, I, J, K);
+    const R z1 = coarse_face<R, DIM, 2, FROMA>(P, a, fz, fnx, fny, fnz, I, J, K + 1);
+    cz[fidx<2>(I, J, K, cnx, cny)] = z0;
+    if (K == cnz - 1) cz[fidx<2>(I, J, cnz, cnx, cny)] = z1;
+    d += z0 + z1;
+  }
+  wd[cidx(I, J, K, cnx, cny)] = d > R(0) ? omega / d : R(0);
 }
 
 // (K x)_c = sum_f a_f (x_c - x_nb) on a level (walls carry a_f = 0).
@@ -900,43 +947,6 @@ __global__ void k_init_flags(int* iflag) {
   if (threadIdx.x < I_NFLAG) iflag[threadIdx.x] = 0;
 }
 
-// First coarse level's face weights straight from alpha: the sum of the
-// 2x2 fine face weights it covers, each (float)((1/h^2) / (0.5 (rho_L +
-// rho_R))) as the fine weights of the FP32 hierarchy are defined.
-template <class R, int DIM, int D>
-__global__ __launch_bounds__(256) void k_coarsen_a(KParams P, const R* __restrict__ a, int cnx, int cny, int cnz,
-                                                   R* __restrict__ cf) {
-  const int I = blockIdx.x * BX + threadIdx.x, J = blockIdx.y * BY + threadIdx.y, K = blockIdx.z;
-  const int cfx = cnx + (D == 0), cfy = cny + (D == 1);
-  if (I >= cfx || J >= cfy) return;
-  const int nx = P.nx, ny = P.ny, nz = P.nz;
-  const int kz = DIM == 3 ? 2 : 1;
-  const double ih2 = P.ih * P.ih;
-  // fine face (i, j, k) along D, between cells (i, j, k) - e_D and (i, j, k)
-  auto wf = [&](int i, int j, int k) -> R {
-    const int id[3] = {i, j, k};
-    const int nD = D == 0 ? nx : (D == 1 ? ny : nz);
-    if (id[D] <= 0 || id[D] >= nD) return R(0);
-    int L[3] = {i, j, k};
-    L[D] -= 1;
-    const double rL = mixp((double)a[cidx(L[0], L[1], L[2], nx, ny)], P.rho1, P.rho2);
-    const double rR = mixp((double)a[cidx(i, j, k, nx, ny)], P.rho1, P.rho2);
-    return R(ih2 / (0.5 * (rL + rR)));
-  };
-  R s = R(0);
-  if (D == 0) {
-    for (int dk = 0; dk < kz; ++dk)
-      for (int dj = 0; dj < 2; ++dj) s += wf(2 * I, 2 * J + dj, kz * K + dk);
-  } else if (D == 1) {
-    for (int dk = 0; dk < kz; ++dk)
-      for (int di = 0; di < 2; ++di) s += wf(2 * I + di, 2 * J, kz * K + dk);
-  } else {
-    for (int dj = 0; dj < 2; ++dj)
-      for (int di = 0; di < 2; ++di) s += wf(2 * I + di, 2 * J + dj, 2 * K);
-  }
-  cf[fidx<D>(I, J, K, cnx, cny)] = s;
-}
-
 // r32 = r / scale in FP32, and per-block partials of |r32|^2 (FP64)
 __global__ __launch_bounds__(256) void k_scale_to32(long n, const double* __restrict__ r,
                                                     const double* __restrict__ scal, float* __restrict__ r32,
@@ -1340,14 +1350,13 @@ void make_wdiag(hipStream_t s, int dim, const Level<R>& L, double omega) {
 
 template <class R>
 void coarsen_weights(hipStream_t s, int dim, const Level<R>& F, const Level<R>& C) {
-  if (dim == 3) {
-    hipLaunchKernelGGL((k_coarsen<R, 3, 0>), grid_for(C.nx + 1, C.ny, C.nz), blk(), 0, s, F.nx, F.ny, F.nz, F.ax, C.nx, C.ny, C.nz, C.ax);
-    hipLaunchKernelGGL((k_coarsen<R, 3, 1>), grid_for(C.nx, C.ny + 1, C.nz), blk(), 0, s, F.nx, F.ny, F.nz, F.ay, C.nx, C.ny, C.nz, C.ay);
-    hipLaunchKernelGGL((k_coarsen<R, 3, 2>), grid_for(C.nx, C.ny, C.nz + 1), blk(), 0, s, F.nx, F.ny, F.nz, F.az, C.nx, C.ny, C.nz, C.az);
-  } else {
-    hipLaunchKernelGGL((k_coarsen<R, 2, 0>), grid_for(C.nx + 1, C.ny, 1), blk(), 0, s, F.nx, F.ny, F.nz, F.ax, C.nx, C.ny, C.nz, C.ax);
-    hipLaunchKernelGGL((k_coarsen<R, 2, 1>), grid_for(C.nx, C.ny + 1, 1), blk(), 0, s, F.nx, F.ny, F.nz, F.ay, C.nx, C.ny, C.nz, C.ay);
-  }
+  const KParams P{};
+  if (dim == 3)
+    hipLaunchKernelGGL((k_coarsen_level<R, 3, false>), grid_for(C.nx, C.ny, C.nz), blk(), 0, s, P, nullptr, F.ax, F.ay,
+                       F.az, F.nx, F.ny, F.nz, C.nx, C.ny, C.nz, C.ax, C.ay, C.az, C.wdiag, R(1.0));
+  else
+    hipLaunchKernelGGL((k_coarsen_level<R, 2, false>), grid_for(C.nx, C.ny, 1), blk(), 0, s, P, nullptr, F.ax, F.ay,
+                       nullptr, F.nx, F.ny, F.nz, C.nx, C.ny, C.nz, C.ax, C.ay, nullptr, C.wdiag, R(1.0));
 }
 
 template <class R>
@@ -1457,14 +1466,12 @@ void init_flags(hipStream_t s, int* iflag) { hipLaunchKernelGGL(k_init_flags, di
 
 template <class R>
 void coarsen_from_alpha(const KParams& P, hipStream_t s, const R* a, const Level<R>& C) {
-  if (P.dim == 3) {
-    hipLaunchKernelGGL((k_coarsen_a<R, 3, 0>), grid_for(C.nx + 1, C.ny, C.nz), blk(), 0, s, P, a, C.nx, C.ny, C.nz, C.ax);
-    hipLaunchKernelGGL((k_coarsen_a<R, 3, 1>), grid_for(C.nx, C.ny + 1, C.nz), blk(), 0, s, P, a, C.nx, C.ny, C.nz, C.ay);
-    hipLaunchKernelGGL((k_coarsen_a<R, 3, 2>), grid_for(C.nx, C.ny, C.nz + 1), blk(), 0, s, P, a, C.nx, C.ny, C.nz, C.az);
-  } else {
-    hipLaunchKernelGGL((k_coarsen_a<R, 2, 0>), grid_for(C.nx + 1, C.ny, 1), blk(), 0, s, P, a, C.nx, C.ny, C.nz, C.ax);
-    hipLaunchKernelGGL((k_coarsen_a<R, 2, 1>), grid_for(C.nx, C.ny + 1, 1), blk(), 0, s, P, a, C.nx, C.ny, C.nz, C.ay);
-  }
+  if (P.dim == 3)
+    hipLaunchKernelGGL((k_coarsen_level<R, 3, true>), grid_for(C.nx, C.ny, C.nz), blk(), 0, s, P, a, nullptr, nullptr,
+                       nullptr, P.nx, P.ny, P.nz, C.nx, C.ny, C.nz, C.ax, C.ay, C.az, C.wdiag, R(1.0));
+  else
+    hipLaunchKernelGGL((k_coarsen_level<R, 2, true>), grid_for(C.nx, C.ny, 1), blk(), 0, s, P, a, nullptr, nullptr,
+                       nullptr, P.nx, P.ny, 1, C.nx, C.ny, C.nz, C.ax, C.ay, nullptr, C.wdiag, R(1.0));
 }
 
 void scale_to32(hipStream_t s, long n, const double* r, const double* scal, float* r32, double* part) {
