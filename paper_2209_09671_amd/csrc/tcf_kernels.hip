@@ -314,9 +314,9 @@ __device__ __forceinline__ R coarse_face(const KParams& P, const R* __restrict__
 }
 
 // One thread per coarse cell: its low face weights along x, y, z (and the
-// wall faces at the high ends) and omega / diag of the cell, whose high faces
-// (written by the neighbours) are recomputed with the same sums.
-template <class R, int DIM, bool FROMA>
+// wall faces at the high ends) and, with WD, omega / diag of the cell, whose
+// high faces (written by the neighbours) are recomputed with the same sums.
+template <class R, int DIM, bool FROMA, bool WD>
 __global__ __launch_bounds__(256) void k_coarsen_level(KParams P, const R* __restrict__ a, const R* __restrict__ fx,
                                                        const R* __restrict__ fy, const R* __restrict__ fz, int fnx,
                                                        int fny, int fnz, int cnx, int cny, int cnz,
@@ -325,9 +325,9 @@ __global__ __launch_bounds__(256) void k_coarsen_level(KParams P, const R* __res
   const int I = blockIdx.x * BX + threadIdx.x, J = blockIdx.y * BY + threadIdx.y, K = blockIdx.z;
   if (I >= cnx || J >= cny) return;
   const R x0 = coarse_face<R, DIM, 0, FROMA>(P, a, fx, fnx, fny, fnz, I, J, K);
-  const R x1 = coarse_face<R, DIM, 0, FROMA>(P, a, fx, fnx, fny, fnz, I + 1, J, K);
+  const R x1 = WD || I == cnx - 1 ? coarse_face<R, DIM, 0, FROMA>(P, a, fx, fnx, fny, fnz, I + 1, J, K) : R(0);
   const R y0 = coarse_face<R, DIM, 1, FROMA>(P, a, fy, fnx, fny, fnz, I, J, K);
-  const R y1 = coarse_face<R, DIM, 1, FROMA>(P, a, fy, fnx, fny, fnz, I, J + 1, K);
+  const R y1 = WD || J == cny - 1 ? coarse_face<R, DIM, 1, FROMA>(P, a, fy, fnx, fny, fnz, I, J + 1, K) : R(0);
   cx[fidx<0>(I, J, K, cnx, cny)] = x0;
   if (I == cnx - 1) cx[fidx<0>(cnx, J, K, cnx, cny)] = x1;
   cy[fidx<1>(I, J, K, cnx, cny)] = y0;
@@ -335,12 +335,12 @@ __global__ __launch_bounds__(256) void k_coarsen_level(KParams P, const R* __res
   R d = x0 + x1 + y0 + y1;
   if (DIM == 3) {
     const R z0 = coarse_face<R, DIM, 2, FROMA>(P, a, fz, fnx, fny, fnz, I, J, K);
-    const R z1 = coarse_face<R, DIM, 2, FROMA>(P, a, fz, fnx, fny, fnz, I, J, K + 1);
+    const R z1 = WD || K == cnz - 1 ? coarse_face<R, DIM, 2, FROMA>(P, a, fz, fnx, fny, fnz, I, J, K + 1) : R(0);
     cz[fidx<2>(I, J, K, cnx, cny)] = z0;
     if (K == cnz - 1) cz[fidx<2>(I, J, cnz, cnx, cny)] = z1;
     d += z0 + z1;
   }
-  wd[cidx(I, J, K, cnx, cny)] = d > R(0) ? omega / d : R(0);
+  if (WD) wd[cidx(I, J, K, cnx, cny)] = d > R(0) ? omega / d : R(0);
 }
 
 // (K x)_c = sum_f a_f (x_c - x_nb) on a level (walls carry a_f = 0).
@@ -644,9 +644,10 @@ __global__ __launch_bounds__(1024) void k_coarse_factor(Level<R> L, double* __re
   }
 }
 
-// The same inverse for a coarsest level of at most kCoarseLdsMax cells, with
-// the matrix held in LDS (rows padded by one double against bank conflicts):
-// per pivot one barrier after the pivot row and column are copied out and
+// The same inverse for a coarsest level of at most kCoarseLdsMax cells: the
+// matrix is assembled in LDS (rows padded by one double against bank
+// conflicts) and eliminated in registers, four entries per thread; per pivot
+// one barrier after the pivot row and column are published through LDS and
 // one after the elimination.
 constexpr int kCoarseLdsMax = 64;
 template <class R, int DIM>
@@ -683,20 +684,41 @@ __global__ __launch_bounds__(1024) void k_coarse_factor_lds(Level<R> L, R* __res
   __syncthreads();
   for (int e = t; e < n * n; e += nt) A[(e / n) * LD + e % n] += gamma / n;
   __syncthreads();
-  // thread t owns column j = t % 64 of rows t / 64 + 16 r (blockDim = 1024)
+  // Thread t owns column j = t % 64 of rows t / 64 + 16 r, r = 0..3
+  // (blockDim = 1024), held in registers during the elimination; only the
+  // pivot column and row of each step pass through LDS.
   const int jj = t & (kCoarseLdsMax - 1), i0 = t >> 6;
+  double m[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int i = i0 + 16 * r;
+    m[r] = i < n && jj < n ? A[i * LD + jj] : 0.0;
+  }
   for (int p = 0; p < n; ++p) {
-    if (t < n) {
-      col[t] = A[t * LD + p];
-      prow[t] = A[p * LD + t];
+    const int rp = p >> 4;
+    if (jj == p) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        if (i0 + 16 * r < n) col[i0 + 16 * r] = m[r];
     }
+    if ((p & 15) == i0 && jj < n) prow[jj] = rp == 0 ? m[0] : (rp == 1 ? m[1] : (rp == 2 ? m[2] : m[3]));
     __syncthreads();
     if (jj < n) {
       const double pj = (jj == p ? 1.0 : prow[jj]) / col[p];  // the scaled pivot row
-      for (int i = i0; i < n; i += 16) A[i * LD + jj] = i == p ? pj : (jj == p ? 0.0 : A[i * LD + jj]) - col[i] * pj;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = i0 + 16 * r;
+        if (i < n) m[r] = i == p ? pj : (jj == p ? 0.0 : m[r]) - col[i] * pj;
+      }
     }
     __syncthreads();
   }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int i = i0 + 16 * r;
+    if (i < n && jj < n) A[i * LD + jj] = m[r];
+  }
+  __syncthreads();
   for (int e = t; e < n * n; e += nt) {
     const int i = e / n, j = e % n;
     Minv[e] = R(0.5 * (A[i * LD + j] + A[j * LD + i]));
@@ -1352,10 +1374,10 @@ template <class R>
 void coarsen_weights(hipStream_t s, int dim, const Level<R>& F, const Level<R>& C) {
   const KParams P{};
   if (dim == 3)
-    hipLaunchKernelGGL((k_coarsen_level<R, 3, false>), grid_for(C.nx, C.ny, C.nz), blk(), 0, s, P, nullptr, F.ax, F.ay,
+    hipLaunchKernelGGL((k_coarsen_level<R, 3, false, true>), grid_for(C.nx, C.ny, C.nz), blk(), 0, s, P, nullptr, F.ax, F.ay,
                        F.az, F.nx, F.ny, F.nz, C.nx, C.ny, C.nz, C.ax, C.ay, C.az, C.wdiag, R(1.0));
   else
-    hipLaunchKernelGGL((k_coarsen_level<R, 2, false>), grid_for(C.nx, C.ny, 1), blk(), 0, s, P, nullptr, F.ax, F.ay,
+    hipLaunchKernelGGL((k_coarsen_level<R, 2, false, true>), grid_for(C.nx, C.ny, 1), blk(), 0, s, P, nullptr, F.ax, F.ay,
                        nullptr, F.nx, F.ny, F.nz, C.nx, C.ny, C.nz, C.ax, C.ay, nullptr, C.wdiag, R(1.0));
 }
 
@@ -1466,12 +1488,15 @@ void init_flags(hipStream_t s, int* iflag) { hipLaunchKernelGGL(k_init_flags, di
 
 template <class R>
 void coarsen_from_alpha(const KParams& P, hipStream_t s, const R* a, const Level<R>& C) {
+  // each fine weight takes an FP64 division here: the faces are computed once
+  // and 1/diag in a pass of its own instead of recomputing the high faces
   if (P.dim == 3)
-    hipLaunchKernelGGL((k_coarsen_level<R, 3, true>), grid_for(C.nx, C.ny, C.nz), blk(), 0, s, P, a, nullptr, nullptr,
-                       nullptr, P.nx, P.ny, P.nz, C.nx, C.ny, C.nz, C.ax, C.ay, C.az, C.wdiag, R(1.0));
+    hipLaunchKernelGGL((k_coarsen_level<R, 3, true, false>), grid_for(C.nx, C.ny, C.nz), blk(), 0, s, P, a, nullptr,
+                       nullptr, nullptr, P.nx, P.ny, P.nz, C.nx, C.ny, C.nz, C.ax, C.ay, C.az, C.wdiag, R(1.0));
   else
-    hipLaunchKernelGGL((k_coarsen_level<R, 2, true>), grid_for(C.nx, C.ny, 1), blk(), 0, s, P, a, nullptr, nullptr,
-                       nullptr, P.nx, P.ny, 1, C.nx, C.ny, C.nz, C.ax, C.ay, nullptr, C.wdiag, R(1.0));
+    hipLaunchKernelGGL((k_coarsen_level<R, 2, true, false>), grid_for(C.nx, C.ny, 1), blk(), 0, s, P, a, nullptr,
+                       nullptr, nullptr, P.nx, P.ny, 1, C.nx, C.ny, C.nz, C.ax, C.ay, nullptr, C.wdiag, R(1.0));
+  make_wdiag<R>(s, P.dim, C, 1.0);
 }
 
 void scale_to32(hipStream_t s, long n, const double* r, const double* scal, float* r32, double* part) {
