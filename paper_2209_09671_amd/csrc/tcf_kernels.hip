@@ -1135,8 +1135,10 @@ __global__ __launch_bounds__(256) void k_diag(KParams P, int kz, int ntx, int nt
 // exactly the stored velocities and follow k_diag's order.  arho is the
 // density fraction of the projection (mixed over [P.rho1, P.rho2]), a the
 // volume fraction the diagnostics sum.  The column's centre values of p and
-// arho roll through registers, loaded one plane ahead; in-plane neighbours
-// are clamped into the grid (a wall face reads none of them).
+// arho roll through registers; every operand of a plane is loaded one plane
+// ahead (the last prefetch of a chunk re-reads its last plane and is not
+// used); in-plane neighbours are clamped into the grid (a wall face reads
+// none of them).
 template <class R, int DIM>
 __global__ __launch_bounds__(256) void k_project_diag(KParams P, int kz, int ntx, int nty, const R* __restrict__ arho,
                                                       const R* __restrict__ a, const double* __restrict__ p,
@@ -1162,17 +1164,42 @@ __global__ __launch_bounds__(256) void k_project_diag(KParams P, int kz, int ntx
   R am = arho[col + plane(k0 - 1)], ac = arho[col + plane(k0)], ap = arho[col + plane(k0 + 1)];
   double wlo = 0.0;  // projected z face below the plane
   if (DIM == 3 && k0 > 0) wlo = proj_face(P, ws[col + (long)k0 * pl], am, ac, pm, pc);
+  // the operands of plane k: p and arho of the column two planes up, the
+  // in-plane neighbours, the predicted faces and alpha of the cell
+  struct Ops {
+    double pn, px0, px1, py0, py1;
+    R an, ax0, ax1, ay0, ay1, usl, ush, vsl, vsh, wsh, av;
+  };
+  auto load = [&](int kk, Ops& o) {
+    const long c = col + (long)kk * pl, cn = col + plane(kk + 2);
+    const long fx = fidx<0>(ic, jc, kk, nx, ny), fy = fidx<1>(ic, jc, kk, nx, ny);
+    o.pn = p[cn];
+    o.an = arho[cn];
+    o.px0 = p[c + oxm];
+    o.px1 = p[c + oxp];
+    o.py0 = p[c + oym];
+    o.py1 = p[c + oyp];
+    o.ax0 = arho[c + oxm];
+    o.ax1 = arho[c + oxp];
+    o.ay0 = arho[c + oym];
+    o.ay1 = arho[c + oyp];
+    o.usl = us[fx];
+    o.ush = us[fx + 1];
+    o.vsl = vs[fy];
+    o.vsh = vs[fy + nx];
+    o.wsh = DIM == 3 ? ws[c + pl] : R(0);
+    o.av = a[c];
+  };
+  Ops cur, nxt;
+  load(k0, cur);
   for (int k = k0; k < k1; ++k) {
+    load(min(k + 1, k1 - 1), nxt);
     const long c = col + (long)k * pl;
-    const long cn = col + plane(k + 2);
-    const double pn = p[cn];
-    const R an = arho[cn];
-    const double px0 = p[c + oxm], px1 = p[c + oxp], py0 = p[c + oym], py1 = p[c + oyp];
-    const R ax0 = arho[c + oxm], ax1 = arho[c + oxp], ay0 = arho[c + oym], ay1 = arho[c + oyp];
     const long fx = fidx<0>(ic, jc, k, nx, ny), fy = fidx<1>(ic, jc, k, nx, ny);
-    const R usl = us[fx], ush = us[fx + 1], vsl = vs[fy], vsh = vs[fy + nx];
-    const R wsh = DIM == 3 ? ws[c + pl] : R(0);
-    const double av = (double)a[c];
+    const double pn = cur.pn, px0 = cur.px0, px1 = cur.px1, py0 = cur.py0, py1 = cur.py1;
+    const R an = cur.an, ax0 = cur.ax0, ax1 = cur.ax1, ay0 = cur.ay0, ay1 = cur.ay1;
+    const R usl = cur.usl, ush = cur.ush, vsl = cur.vsl, vsh = cur.vsh, wsh = cur.wsh;
+    const double av = (double)cur.av;
     const double u0 = xlo ? proj_face(P, usl, ax0, ac, px0, pc) : 0.0;
     const double u1 = xhi ? proj_face(P, ush, ac, ax1, pc, px1) : 0.0;
     const double v0 = ylo ? proj_face(P, vsl, ay0, ac, py0, pc) : 0.0;
@@ -1226,6 +1253,7 @@ __global__ __launch_bounds__(256) void k_project_diag(KParams P, int kz, int ntx
     am = ac;
     ac = ap;
     ap = an;
+    cur = nxt;
   }
   diag_partials(s, mn, mx, d2, um, fin, part, stride, sh);
 }
