@@ -467,13 +467,15 @@ struct Launch {
   int ntx, nty, kz, nblocks;
 };
 
-Launch plan(int nx, int ny, int nz) {
+Launch plan(int nx, int ny, int nz, int target = TCF_FINE_BLOCKS) {
   Launch L;
   L.ntx = (nx + FX - 1) / FX;
   L.nty = (ny + FY - 1) / FY;
   const int cols = L.ntx * L.nty;
-  // aim for >= TCF_FINE_BLOCKS blocks (4 per CU) with chunks of at least 8 planes
-  int ntz = std::max(1, std::min(nz, (TCF_FINE_BLOCKS + cols - 1) / cols));
+  // aim for >= target blocks (TCF_FINE_BLOCKS: two full rounds of the two
+  // blocks per CU that most of these kernels' register counts allow) with
+  // chunks of at least 8 planes
+  int ntz = std::max(1, std::min(nz, (target + cols - 1) / cols));
   int kz = (nz + ntz - 1) / ntz;
   if (kz < 8 && nz >= 8) kz = 8;
   if (nz > 1 && (kz & 1)) kz += 1;  // plane pairs of the restriction stay in one chunk
@@ -540,10 +542,34 @@ void fine_smooth_first(hipStream_t s, int dim, const Fine<R>& F, double omega, c
                        b, z1, iflag);
 }
 
+// Blocks the GPU holds at once for kernel k (512 threads), over all CUs; 0
+// if the runtime cannot tell.
+int resident_blocks(const void* k) {
+  int dev = 0, ncu = 0, per = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k, FX * FY, 0) != hipSuccess)
+    return 0;
+  return per * ncu;
+}
+
+// The plain sweep holds more blocks per CU than the other finest-level
+// kernels (fewer registers): it is launched as one full round of them, so
+// that no partial round trails.
+template <class R, int DIM>
+int sweep_blocks() {
+  static const int n = [] {
+    const int r = resident_blocks((const void*)k0_smooth<R, DIM, false>);
+    return r >= 256 ? r : TCF_FINE_BLOCKS;
+  }();
+  return n;
+}
+
 template <class R>
 int fine_smooth(hipStream_t s, int dim, const Fine<R>& F, double omega, const R* b, const R* x, R* xo, const R* e,
                 int cnx, int cny, double omc, double* part, const int* iflag) {
-  const Launch L = plan(F.nx, F.ny, F.nz);
+  const int target = e ? TCF_FINE_BLOCKS : (dim == 3 ? sweep_blocks<R, 3>() : sweep_blocks<R, 2>());
+  const Launch L = plan(F.nx, F.ny, F.nz, target);
   const Op0<R> op = op_of(F);
   if (dim == 3) {
     if (e)
