@@ -369,6 +369,31 @@ __global__ __launch_bounds__(FX * FY) void k0_smooth_first(Op0<R> op, int kz, in
   march<R, DIM, false, false>(op, T, X, XV, pre, body, NoPost());
 }
 
+// The inner FP32 solve's first sweep straight from the FP64 refinement
+// residual: r32 = (float)(r64 / scale) is written as the inner right-hand
+// side, z1 = omega r32 / diag, and block partials of |r32|^2 (one pass
+// instead of a scaling pass and a sweep).
+template <int DIM>
+__global__ __launch_bounds__(FX * FY) void k0_smooth_first64(Op0<float> op, int kz, int ntx, int nty, float omega,
+                                                         const double* __restrict__ r64,
+                                                         const double* __restrict__ scal, float* __restrict__ r32,
+                                                         float* __restrict__ z1, double* __restrict__ part) {
+  const Tile T = tile_of(op.nx, op.ny, op.nz, ntx, nty, kz);
+  const double scale = scal[S_SCALE];
+  double acc = 0.0;
+  auto X = [&](long, int, int, int) { return 0.0f; };
+  const Ident<float> XV;
+  auto pre = [&](long c) { return r64[c]; };
+  auto body = [&](long c, int, float, float, float dg, double rv) {
+    const float q = (float)(rv / scale);
+    r32[c] = q;
+    z1[c] = omega * recip(dg) * q;
+    acc += (double)q * (double)q;
+  };
+  march<float, DIM, false, false>(op, T, X, XV, pre, body, NoPost());
+  write_partial(acc, part);
+}
+
 // damped Jacobi xo = x + omega (b - K0 x) / diag; optional partial b.xo.
 // PRO: the sweep acts on x' = x + omc * P e, the coarse correction applied on
 // the fly (e is the next-coarser level's solution).
@@ -563,6 +588,19 @@ int sweep_blocks() {
     return r >= 256 ? r : TCF_FINE_BLOCKS;
   }();
   return n;
+}
+
+int fine_smooth_first64(hipStream_t s, int dim, const Fine<float>& F, double omega, const double* r64,
+                        const double* scal, float* r32, float* z1, double* part) {
+  const Launch L = plan(F.nx, F.ny, F.nz);
+  const Op0<float> op = op_of(F);
+  if (dim == 3)
+    hipLaunchKernelGGL((k0_smooth_first64<3>), dim3(L.nblocks), dim3(FX, FY), 0, s, op, L.kz, L.ntx, L.nty,
+                       float(omega), r64, scal, r32, z1, part);
+  else
+    hipLaunchKernelGGL((k0_smooth_first64<2>), dim3(L.nblocks), dim3(FX, FY), 0, s, op, L.kz, L.ntx, L.nty,
+                       float(omega), r64, scal, r32, z1, part);
+  return L.nblocks;
 }
 
 template <class R>

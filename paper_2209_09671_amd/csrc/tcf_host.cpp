@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/tcf.h"
@@ -582,8 +583,21 @@ inline double sweep_omega(int dim, int nu, int k) {
 // 0 only) receives the partials of b.out and *np their count.  Buffers
 // alternate so that the last write lands in out.  With first_done the first
 // Jacobi sweep (omega_0 b / diag) is already in tmp.
+// The inner FP32 solve's right-hand side taken straight from the FP64
+// refinement residual: the first sweep of the first V-cycle scales r64 into
+// the solve's r (see fine_smooth_first64); part receives the partials of
+// |r|^2 (np of them), reduced with tolerance factor tau2 once that cycle is
+// queued.
+struct FromR64 {
+  const double* r64;
+  double* part;
+  double tau2;
+  int np;
+};
+
 template <class R>
-void vcycle(tcf_grid* g, Fields<R>& F, size_t l, const R* b, R* out, R* tmp, double* part, bool first_done, int* np) {
+void vcycle(tcf_grid* g, Fields<R>& F, size_t l, const R* b, R* out, R* tmp, double* part, bool first_done, int* np,
+            FromR64* f64 = nullptr) {
   hipStream_t s = g->stream;
   const int dim = g->D.dim;
   const int nu = g->cfg.mg_nu;
@@ -603,7 +617,17 @@ void vcycle(tcf_grid* g, Fields<R>& F, size_t l, const R* b, R* out, R* tmp, dou
   if (l == 0) {
     const Fine<R> Fd = fine_desc<R>(g);
     int w = 1;
-    if (!first_done) fine_smooth_first<R>(s, dim, Fd, wpre(0), b, bufs[0], g->iflag);
+    if (!first_done) {
+      if constexpr (std::is_same<R, float>::value) {
+        if (f64)  // b is the solve's r, written here
+          f64->np = fine_smooth_first64(s, dim, Fd, wpre(0), f64->r64, g->scal, const_cast<float*>(b), bufs[0],
+                                        f64->part);
+        else
+          fine_smooth_first<R>(s, dim, Fd, wpre(0), b, bufs[0], g->iflag);
+      } else {
+        fine_smooth_first<R>(s, dim, Fd, wpre(0), b, bufs[0], g->iflag);
+      }
+    }
     for (int k = 1; k < nu; ++k, ++w) {
       Prof pr(g, FAM_SMOOTH0);
       fine_smooth<R>(s, dim, Fd, wpre(k), b, bufs[(w - 1) & 1], bufs[w & 1], nullptr, 0, 0, 0.0, nullptr, g->iflag);
@@ -675,16 +699,19 @@ void vcycle(tcf_grid* g, Fields<R>& F, size_t l, const R* b, R* out, R* tmp, dou
 // With x_zero, x starts from zero without being cleared: the first update
 // writes x = alpha d (the first update always runs, the flag being set only
 // by the residual norm after it).
+// With f64, r is filled from the FP64 residual by the first preconditioner
+// application (multigrid hierarchies of two or more levels only).
 template <class R>
 tcf_status pcg_iterate(tcf_grid* g, Fields<R>& F, R* x, R* r, int maxit, int kind, bool x_zero, int* iters,
-                       bool* converged) {
+                       bool* converged, FromR64* f64 = nullptr) {
   hipStream_t s = g->stream;
   const int dim = g->D.dim;
   const Fine<R> Fd = fine_desc<R>(g);
   const double wj = sweep_omega(dim, g->cfg.mg_nu, 0);  // first pre-smoothing sweep, fused into the update
   *converged = false;
   int np = 0;
-  vcycle<R>(g, F, 0, r, F.z, F.z2, g->part[0], false, &np);
+  vcycle<R>(g, F, 0, r, F.z, F.z2, g->part[0], false, &np, f64);
+  if (f64) finalize(s, f64->part, f64->np, g->scal, g->iflag, F_BB, 0, f64->tau2);
   finalize(s, g->part[0], np, g->scal, g->iflag, F_RZ_FIRST, 0, 0.0);
   R* dcur = F.d;
   R* dnext = F.d2;
@@ -798,15 +825,22 @@ tcf_status solve_refined(tcf_grid* g, double* p, int kind, int* iters, int* nref
     }
     if (ref >= g->cfg.refine_maxit) break;
     // inner solve of K e = r64 / scale in FP32 from e = 0
-    scale_to32(s, N, g->r64, g->scal, F.r, g->part[0]);  // with the partials of |r32|^2
-    init_flags(s, g->iflag);
     // reduce the scaled residual only as far as this sweep needs to reach
     // the FP64 target (never below inner_rtol)
     const double tau = std::min(0.5, std::max(irt, 0.5 * rt * std::sqrt(bb / rr)));
-    finalize(s, g->part[0], nb1, g->scal, g->iflag, F_BB, 0, tau * tau);
+    // the scaled residual r32 = r64 / scale with the partials of |r32|^2:
+    // from the first sweep of a multigrid hierarchy, else in a pass of its own
+    FromR64 f64{g->r64, g->part[1], tau * tau, 0};
+    const bool fused = F.lv.size() > 1;
+    init_flags(s, g->iflag);
+    if (!fused) {
+      scale_to32(s, N, g->r64, g->scal, F.r, g->part[0]);
+      finalize(s, g->part[0], nb1, g->scal, g->iflag, F_BB, 0, tau * tau);
+    }
     int it = 0;
     bool conv = false;
-    tcf_status st = pcg_iterate<float>(g, F, F.x, F.r, g->cfg.p_maxit, kind + (ref > 0 ? 1 : 0), true, &it, &conv);
+    tcf_status st = pcg_iterate<float>(g, F, F.x, F.r, g->cfg.p_maxit, kind + (ref > 0 ? 1 : 0), true, &it, &conv,
+                                       fused ? &f64 : nullptr);
     if (st != TCF_OK) return st;
     *iters += it;
     *psum = add_scaled(s, N, F.x, g->scal, p, g->part[2]);

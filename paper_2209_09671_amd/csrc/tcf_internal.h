@@ -143,6 +143,10 @@ void mg_coarse_solve(hipStream_t s, int dim, const Level<R>& L, const R* b, R* x
 
 // finest-level fused kernels (tcf_fine.hip); return the number of partials
 int fine_blocks(int nx, int ny, int nz);
+// the inner solve's first sweep from the FP64 residual: r32 = r64 / scale
+// (scal[S_SCALE]) written, z1 = omega r32 / diag, partials of |r32|^2
+int fine_smooth_first64(hipStream_t s, int dim, const Fine<float>& F, double omega, const double* r64,
+                        const double* scal, float* r32, float* z1, double* part);
 // r = -(b - mean) - K p in FP64 with the fine weights recomputed from alpha
 // (densities rho1 + clamp(alpha)(rho2 - rho1) of P); block partials of
 // ||rhs||^2 and ||r||^2
