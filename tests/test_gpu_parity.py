@@ -197,6 +197,25 @@ def test_full_step_meltpool_fp32_refined():
     assert max(e.values()) <= 1e-4, e
 
 
+def test_full_step_fp32_refined_single_level():
+    """FP32 refinement on grids whose hierarchy has one level (an odd
+    extent): the inner right-hand side is then scaled in a pass of its own
+    instead of by the first multigrid sweep.  One step of each against the
+    FP64 oracle, to the bar of the multigrid case."""
+    for c in (I.custom(I.config(2), nx=18, ny=13, nz=10), I.custom(I.config(0), nx=33, ny=20)):
+        c["p_rtol"] = 1e-10
+        c["p_maxit"] = 1000
+        st = I.initial_state(c)
+        g, info = gpu_run(c, st, c["dt"], 1, precision=1)
+        o, _, _ = O.step(c, st, 0.0, c["dt"], 1, rtol=1e-13)
+        assert info["status"] == 0, info
+        assert info["p_relres"] <= 1e-10 and info["div_rel"] <= 1e-8, info
+        e = field_errors(g, o)
+        print("fp32-refined single-level rel. L2 vs FP64 oracle:", e, flush=True)
+        assert e["alpha"] <= 1e-6 and e["T"] <= 1e-6, e
+        assert max(e.values()) <= 1e-4, e
+
+
 def test_deterministic_and_restart_bitwise():
     c = I.config(0)
     st = I.initial_state(c)
