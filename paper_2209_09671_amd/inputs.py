@@ -391,6 +391,30 @@ def stream_velocity(c, amp=1.0):
     return (np.ascontiguousarray(u), np.ascontiguousarray(v), w)
 
 
+def stream_velocity_3d(c, amp=1.0):
+    """A 3-D discretely divergence-free MAC velocity with all three
+    components nonzero: the x-y flow of stream_velocity (modulated along z)
+    plus an x-z flow from the edge stream function
+    L sin^2(pi x/Lx) sin^2(pi z/Lz)/pi, modulated along y by
+    1/2 + cos(pi y/Ly)/3.  Each part is a face difference of an edge
+    potential times a factor constant on the faces it differences, so the
+    discrete divergence vanishes; normal velocities vanish on the walls."""
+    assert c["dim"] == 3
+    nx, ny, nz, h = c["nx"], c["ny"], c["nz"], c["h"]
+    lx, ly, lz = nx * h, ny * h, nz * h
+    u, v, w = stream_velocity(c, amp)
+    xn = np.arange(nx + 1) * h
+    zn = np.arange(nz + 1) * h
+    yc = (np.arange(ny) + 0.5) * h
+    psi = lz * (np.sin(np.pi * xn / lx)[None, :] ** 2 * np.sin(np.pi * zn / lz)[:, None] ** 2) / np.pi
+    f = (0.5 + np.cos(np.pi * yc / ly) / 3.0)[None, :, None]
+    u = u + amp * f * ((psi[1:, :] - psi[:-1, :]) / h)[:, None, :]            # (nz, ny, nx+1)
+    w = -amp * f * ((psi[:, 1:] - psi[:, :-1]) / h)[:, None, :]               # (nz+1, ny, nx)
+    u[:, :, 0] = u[:, :, -1] = 0.0
+    w[0] = w[-1] = 0.0
+    return (np.ascontiguousarray(u), v, np.ascontiguousarray(w))
+
+
 def random_fields(c, seed, scale=1.0):
     """Smooth-ish random fields for operator checks (not physical)."""
     rng = np.random.default_rng(seed)
