@@ -2,7 +2,9 @@
 
 For a random linear functional f(x) = <W, S(x)> and a random direction d,
 <S^T W, d> from the adjoint kernels must equal (f(x + eps d) - f(x - eps d)) /
-(2 eps).  Directions on alpha avoid cells where clamp(alpha, 0, 1) has its
+(2 eps).  The forward S of the differences is taken on both sides: the
+HIP path itself, and the FP64 CPU oracle (so the adjoint is pinned to the
+method's definition, not only to the kernels it transposes).  Directions on alpha avoid cells where clamp(alpha, 0, 1) has its
 kink; velocities carry a small random part so that no advecting velocity sits
 at the upwind switch.  Tolerances: 1e-6 relative for single sub-steps, 1e-5
 for the full step and the multi-step rollout (the bar the method's workload
@@ -12,6 +14,7 @@ import numpy as np
 import pytest
 import torch
 
+from oracle import pyoracle as O
 from paper_2209_09671_amd import inputs as I
 from paper_2209_09671_amd import tcf
 
@@ -184,6 +187,105 @@ def test_full_step_adjoint_matches_fd(make):
     assert abs(float(sbar) - fds) <= 1e-5 * abs(fds), (float(sbar), fds)
 
 
+@pytest.mark.parametrize("make", [lambda: I.custom(I.config(0), nx=40, ny=32),
+                                  lambda: I.custom(I.config(3), nx=20, ny=16, nz=18), meltpool_small])
+def test_full_step_adjoint_matches_oracle_fd(make):
+    """tcf_step_backward against central differences of the ORACLE's step
+    (FP64 CPU, its own pressure solve to 1e-13): the adjoint of the HIP
+    path is the derivative of the method as the oracle defines it, along
+    a random state direction and along dsigma/dT, to 1e-5 relative."""
+    c = make()
+    c["p_rtol"] = 1e-13
+    melt = c["T0"] != 0
+    st = perturbed_state(c, 15, amp=3.0 if melt else 0.3)
+    dt = c["dt"]
+    g = tcf.Grid(c, precision=0, flags=tcf.TCF_WITH_ADJOINT)
+    rng = np.random.default_rng(19)
+    W = {k: (rng.standard_normal(st[k].shape) if st.get(k) is not None else None)
+         for k in ("alpha", "T", "u", "v", "w")}
+    _zero_walls(c, W)
+    sbar = torch.zeros((), dtype=torch.float64, device="cuda")
+    adj = g.step_backward(0.0, dt, {k: dev(v) for k, v in st.items()}, {k: dev(v) for k, v in W.items()}, sbar)
+    adj = {k: host(v) for k, v in adj.items()}
+    g.close()
+    d = direction(c, st, 16)
+    keys = ("alpha", "T", "u", "v", "w")
+    lhs = dot(adj, d, keys)
+
+    def f(state, cc=c):
+        o, _, status = O.step(cc, state, 0.0, dt, 1, rtol=1e-13)
+        assert status == 0
+        return dot(o, W, keys)
+
+    eps = 1e-7 if melt else 1e-5
+    fd = (f(shifted(st, d, eps)) - f(shifted(st, d, -eps))) / (2 * eps)
+    print(f"[adjoint vs oracle FD] state: {lhs:.12e} {fd:.12e} rel {abs(lhs - fd) / abs(fd):.2e}", flush=True)
+    assert abs(lhs - fd) <= 1e-5 * abs(fd), (lhs, fd)
+    es = 0.1 * abs(c["dsigma_dT"])
+    fds = (f(st, dict(c, dsigma_dT=c["dsigma_dT"] + es)) - f(st, dict(c, dsigma_dT=c["dsigma_dT"] - es))) / (2 * es)
+    print(f"[adjoint vs oracle FD] dsigma_dT: {float(sbar):.12e} {fds:.12e}", flush=True)
+    assert abs(float(sbar) - fds) <= 1e-5 * abs(fds), (float(sbar), fds)
+
+
+@pytest.mark.parametrize("make", [lambda: I.custom(I.config(0), nx=40, ny=32),
+                                  lambda: I.custom(I.config(3), nx=20, ny=16, nz=18), meltpool_small])
+def test_predictor_adjoint_matches_oracle_fd(make):
+    """tcf_adjoint_predictor against central differences of the oracle's
+    predictor (S2-S5), to 1e-6 relative."""
+    c = make()
+    st = perturbed_state(c, 11, amp=3.0 if c["T0"] != 0 else 0.3)
+    dt = c["dt"]
+    g = tcf.Grid(c, precision=0, flags=tcf.TCF_WITH_ADJOINT)
+    rng = np.random.default_rng(17)
+    W = {k: rng.standard_normal(st[k].shape) for k in ("u", "v", "w") if st.get(k) is not None}
+    _zero_walls(c, dict(W, w=W.get("w")))
+    g.set_state(st)
+    adj = g.adjoint_predictor(dt, dev(W["u"]), dev(W["v"]), dev(W.get("w")))
+    adj = {k: host(v) for k, v in adj.items()}
+    g.close()
+    d = direction(c, st, 13)
+    lhs = dot(adj, d, ("alpha", "T", "u", "v", "w"))
+
+    def f(state, cc=c):
+        us, vs, ws = O.predictor(cc, dt, state["alpha"], state["T"], state["u"], state["v"], state.get("w"))
+        return dot(dict(u=us, v=vs, w=ws), W, ("u", "v", "w"))
+
+    eps = 1e-8 if c["rho2"] > 100 else 1e-6
+    fd = (f(shifted(st, d, eps)) - f(shifted(st, d, -eps))) / (2 * eps)
+    assert abs(lhs - fd) <= 1e-6 * max(abs(fd), 1e-30), (lhs, fd)
+    # u* is linear in dsigma/dT (sigma is), so a large step has no truncation
+    # error and keeps the difference far above the rounding of u*
+    es = 0.1 * abs(c["dsigma_dT"])
+    fds = (f(st, dict(c, dsigma_dT=c["dsigma_dT"] + es)) - f(st, dict(c, dsigma_dT=c["dsigma_dT"] - es))) / (2 * es)
+    assert abs(float(adj["dsigma_dT"]) - fds) <= 1e-6 * abs(fds), (float(adj["dsigma_dT"]), fds)
+
+
+@pytest.mark.parametrize("make", [lambda: I.custom(I.config(0), nx=40, ny=32), meltpool_small])
+def test_transport_adjoint_matches_oracle_fd(make):
+    """tcf_adjoint_transport against central differences of the oracle's
+    SSP-RK3 transport step (S1), to 1e-6 relative."""
+    c = make()
+    st = perturbed_state(c, 12, amp=0.3 if c["T0"] == 0 else 3.0)
+    dt = c["dt"] if c["T0"] == 0 else 1e-8
+    g = tcf.Grid(c, precision=0, flags=tcf.TCF_WITH_ADJOINT | tcf.TCF_TRANSPORT_ONLY)
+    rng = np.random.default_rng(18)
+    Wa, WT = rng.standard_normal(st["alpha"].shape), rng.standard_normal(st["T"].shape)
+    g.set_state(st)
+    adj = g.adjoint_transport(dt, dev(Wa), dev(WT))
+    adj = {k: host(v) for k, v in adj.items()}
+    g.close()
+    d = direction(c, st, 14)
+    lhs = dot(adj, d, ("alpha", "T", "u", "v", "w"))
+
+    def f(state):
+        a, T = O.transport_step(c, 0.0, dt, state["alpha"], state["T"], state["u"], state["v"], state.get("w"))
+        return float(np.vdot(a, Wa) + np.vdot(T, WT))
+
+    eps = 1e-6
+    fd = (f(shifted(st, d, eps)) - f(shifted(st, d, -eps))) / (2 * eps)
+    assert abs(lhs - fd) <= 1e-6 * abs(fd), (lhs, fd)
+
+
 def centroid_loss(c, alpha, u, v, w, target):
     h = c["h"]
     x = (torch.arange(c["nx"], dtype=torch.float64, device=alpha.device) + 0.5) * h
@@ -254,3 +356,51 @@ def test_rollout_gradient_matches_fd(dim):
         tol = 1e-5 if dim == 2 else 1e-4
         scale = max(abs(fd), 1e-3 * np.linalg.norm(gT) * np.linalg.norm(dT))
         assert abs(ad - fd) <= tol * scale, (ad, fd, np.linalg.norm(gT))
+
+
+def test_rollout_gradient_3d_flowing_state_matches_fd():
+    """3-D rollout (20^3 droplet, 10 steps, checkpoints every 4) from a
+    flowing initial state, the droplet loss's gradients with respect to
+    dsigma/dT and two smooth T0 directions against central differences, to
+    1e-5 relative to |g_FD| alone.  Started from rest, the advecting
+    velocities of many faces sit at zero, where the upwind choice makes the
+    loss only piecewise smooth and the differences resolve the small T0
+    derivative to a few 1e-5 (the test above keeps that case, with the
+    scale floor of the workload's pass criterion); a flowing state keeps
+    every face away from the switch."""
+    c = I.custom(I.config(3), nx=20, ny=20, nz=20)
+    c["p_rtol"] = 1e-13
+    nsteps, k = 10, 4
+    st = perturbed_state(c, 21, amp=0.3)
+    tgt = torch.tensor(np.array([0.5, 0.45, 0.45]) + I.target_centroid(c), device="cuda")
+    a0, u0, v0, w0 = dev(st["alpha"]), dev(st["u"]), dev(st["v"]), dev(st["w"])
+    s = torch.tensor(c["dsigma_dT"], dtype=torch.float64, requires_grad=True)
+    T0 = dev(st["T"]).requires_grad_(True)
+    out = tcf.TcfRollout.apply(s, T0, c, a0, u0, v0, w0, nsteps, k)
+    loss = centroid_loss(c, out[0], out[2], out[3], out[4], tgt)
+    loss.backward()
+    gs, gT = float(s.grad), host(T0.grad)
+
+    def L(sv, T):
+        with torch.no_grad():
+            o = tcf.TcfRollout.apply(torch.tensor(sv, dtype=torch.float64), T, c, a0, u0, v0, w0, nsteps, k)
+            return float(centroid_loss(c, o[0], o[2], o[3], o[4], tgt))
+
+    def richardson(fun, eps):
+        d1 = (fun(eps) - fun(-eps)) / (2 * eps)
+        d2 = (fun(eps / 2) - fun(-eps / 2)) / eps
+        return (4 * d2 - d1) / 3
+
+    s0 = c["dsigma_dT"]
+    fds = richardson(lambda e: L(s0 + e, T0.detach()), 1e-3 * abs(s0))
+    print(f"[rollout 3d flowing] s: {gs:.12e} {fds:.12e} rel {abs(gs - fds) / abs(fds):.2e}", flush=True)
+    assert abs(gs - fds) <= 1e-5 * abs(fds), (gs, fds)
+    # of six seeded smooth directions, the two along which the loss changes
+    # most (a direction nearly orthogonal to the gradient leaves a derivative
+    # the differences resolve only to the loss's own noise)
+    dirs = sorted(I.t_directions(c, k=6), key=lambda d: -abs(float(np.vdot(gT, d))))[:2]
+    for dT in dirs:
+        fd = richardson(lambda e: L(s0, T0.detach() + e * dev(dT)), 4e-2)
+        ad = float(np.vdot(gT, dT))
+        print(f"[rollout 3d flowing] T0: {ad:.12e} {fd:.12e} rel {abs(ad - fd) / abs(fd):.2e}", flush=True)
+        assert abs(ad - fd) <= 1e-5 * abs(fd), (ad, fd)
