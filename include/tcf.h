@@ -169,6 +169,32 @@ size_t tcf_workspace_bytes(const tcf_config* cfg);
 tcf_status tcf_init_grid(const tcf_config* cfg, void* workspace, size_t bytes, void* hip_stream,
                          tcf_grid** out);
 
+/* For callers that cannot allocate memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid allocation): tcf_init_grid with
+ * the workspace taken from a fixed device array inside the library instead
+ * of a caller allocation.  Each GPU holds one such array of
+ * TCF_STATIC_WORKSPACE_BYTES (128 MiB) from its first use until the process
+ * ends; the grid lives on the device current at the call.  The call
+ * allocates nothing: no device or pinned host memory (the handle and its
+ * host mirror of the solver scalars are slots inside the library, one per
+ * GPU) and, after the first call on a device, no event either.  Every other
+ * entry point works on the handle as on any grid, and tcf_destroy releases
+ * the slot.
+ *   TCF_E_WORKSPACE : tcf_workspace_bytes(cfg) exceeds the fixed array
+ *                     (e.g. 2D up to 512^2, 3D up to 128 x 64 x 64 fit);
+ *   TCF_E_STATE     : a grid on this GPU's fixed workspace is still open
+ *                     (one at a time per GPU; destroy it first);
+ *   TCF_E_INVALID   : as tcf_init_grid.
+ * Successive grids on one GPU share the array and find the last grid's
+ * contents in it: the call clears what must start at zero, and everything
+ * else is written before it is read.  The handle's calls are ordered on its
+ * stream; calls on it from several host threads at once race, as on any
+ * grid.  Its solver scalars are read back through pageable host memory, with
+ * a stream synchronisation per read (no overlap of that read with queued
+ * work). */
+#define TCF_STATIC_WORKSPACE_BYTES ((size_t)128 << 20)
+tcf_status tcf_init_grid_static(const tcf_config* cfg, void* hip_stream, tcf_grid** out);
+
 /* Copy the state in (device FP64 pointers, layout above).  w must be NULL in
  * 2D; p may be NULL (zero pressure).  Wall-face velocities are forced to 0. */
 tcf_status tcf_set_fields(tcf_grid* g, double t, const double* alpha, const double* T, const double* u,

@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <type_traits>
 #include <vector>
@@ -149,9 +150,10 @@ struct tcf_grid {
   int nb;  // capacity of each partial array
   double* scal;
   int* iflag;
-  double* hscal;  // pinned host mirror
+  double* hscal;  // pinned host mirror (pageable, inside the slot, on a fixed-workspace grid)
   int* hflag;
   hipEvent_t rb_ev = nullptr;  // completion of the last copy into hscal
+  int static_dev = -1;         // device whose fixed workspace this grid uses (-1: caller's workspace)
   // CG iterations the last solve of each kind took (0: none yet): the
   // state's pressure or another right-hand side, first or later refinement
   int pcg_expect[4] = {0, 0, 0, 0};
@@ -510,9 +512,13 @@ hipError_t read_back(tcf_grid* g) {
 
 // The copy of read_back queued without waiting; wait_back blocks until it
 // has landed, while the stream may already run the work queued after it.
+// On a fixed-workspace grid the mirror is pageable host memory, which a
+// queued copy may fill after the event completes: the copy is waited for
+// on the stream there.
 hipError_t read_back_async(tcf_grid* g) {
   hipError_t e = hipMemcpyAsync(g->hscal, g->scal, kScalBlockBytes, hipMemcpyDeviceToHost, g->stream);
   if (e != hipSuccess) return e;
+  if (g->static_dev >= 0 && (e = hipStreamSynchronize(g->stream)) != hipSuccess) return e;
   return hipEventRecord(g->rb_ev, g->stream);
 }
 hipError_t wait_back(tcf_grid* g) { return hipEventSynchronize(g->rb_ev); }
@@ -1362,6 +1368,53 @@ tcf_status adj_checks(tcf_grid* g) {
   return TCF_OK;
 }
 
+// Carve the workspace and clear what must start at zero (scalars, flags,
+// the zero vector, the pressure); the rest of the workspace is written
+// before it is read, so a reused workspace needs no clearing.
+void init_handle(tcf_grid* g, const tcf_config* cfg, void* workspace, size_t bytes, void* hip_stream) {
+  g->cfg = *cfg;
+  if (g->cfg.dim == 2) g->cfg.nz = 1;
+  g->D = dims_of(&g->cfg);
+  g->P = make_params(&g->cfg);
+  g->nph = g->P.nph;
+  g->op_rho1 = g->cfg.rho1;
+  g->op_rho2 = g->cfg.rho2;
+  g->stream = (hipStream_t)hip_stream;
+  g->fp32 = cfg->precision == TCF_FP32_REFINE;
+  g->bytes = bytes;
+  carve(&g->cfg, workspace, g);
+}
+
+void clear_start(tcf_grid* g) {
+  g->hflag = (int*)(g->hscal + S_NSLOT);
+  fill_f64(g->stream, S_NSLOT, g->scal, 0.0);
+  init_flags(g->stream, g->iflag);
+  fill_f64(g->stream, g->D.N, g->zero64, 0.0);
+  fill_f64(g->stream, g->D.N, g->p64, 0.0);
+}
+
+}  // namespace
+
+// -----------------------------------------------------------------------------
+// Fixed workspace of tcf_init_grid_static: one array per GPU, held until the
+// process ends.  In host code its name is only a stand-in: its device
+// address on each GPU comes from hipGetSymbolAddress (once per device, with
+// that device current) and only that address is passed on.
+static __device__ __align__(256) unsigned char scratch[TCF_STATIC_WORKSPACE_BYTES];
+
+namespace {
+
+constexpr int kMaxStaticDevices = 64;
+struct StaticSlot {
+  void* ptr = nullptr;      // device address of scratch on this GPU (nullptr: not looked up yet)
+  hipEvent_t ev = nullptr;  // read-back event of the slot's grids, kept for the process
+  bool in_use = false;      // a grid on this GPU's fixed workspace is open
+  tcf_grid grid;            // the handle, reset by each tcf_init_grid_static
+  alignas(64) unsigned char mirror[kScalBlockBytes];  // host mirror of the scalar block
+};
+StaticSlot g_static[kMaxStaticDevices];
+std::mutex g_static_mu;
+
 }  // namespace
 
 // =============================================================================
@@ -1385,32 +1438,17 @@ tcf_status tcf_init_grid(const tcf_config* cfg, void* workspace, size_t bytes, v
   if (bytes < need) return fail(TCF_E_WORKSPACE, "workspace too small: need " + std::to_string(need) + " bytes");
   tcf_grid* g = new (std::nothrow) tcf_grid();
   if (!g) return fail(TCF_E_INVALID, "host allocation failed");
-  g->cfg = *cfg;
-  if (g->cfg.dim == 2) g->cfg.nz = 1;
-  g->D = dims_of(&g->cfg);
-  g->P = make_params(&g->cfg);
-  g->nph = g->P.nph;
-  g->op_rho1 = g->cfg.rho1;
-  g->op_rho2 = g->cfg.rho2;
-  g->stream = (hipStream_t)hip_stream;
-  g->fp32 = cfg->precision == TCF_FP32_REFINE;
-  g->bytes = bytes;
-  carve(&g->cfg, workspace, g);
+  init_handle(g, cfg, workspace, bytes, hip_stream);
   if (hipHostMalloc((void**)&g->hscal, kScalBlockBytes, hipHostMallocDefault) != hipSuccess) {
     delete g;
     return fail(TCF_E_DEVICE, "pinned host buffer allocation failed");
   }
-  g->hflag = (int*)(g->hscal + S_NSLOT);
   if (hipEventCreateWithFlags(&g->rb_ev, hipEventDisableTiming) != hipSuccess) {
     hipHostFree(g->hscal);
     delete g;
     return fail(TCF_E_DEVICE, "event creation failed");
   }
-  // zero scalars and flags, the zero vector, and the pressure
-  fill_f64(g->stream, S_NSLOT, g->scal, 0.0);
-  init_flags(g->stream, g->iflag);
-  fill_f64(g->stream, g->D.N, g->zero64, 0.0);
-  fill_f64(g->stream, g->D.N, g->p64, 0.0);
+  clear_start(g);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) {
     hipEventDestroy(g->rb_ev);
@@ -1418,6 +1456,51 @@ tcf_status tcf_init_grid(const tcf_config* cfg, void* workspace, size_t bytes, v
     delete g;
     return fail(TCF_E_DEVICE, std::string("init kernels: ") + hipGetErrorString(e));
   }
+  *out = g;
+  return TCF_OK;
+}
+
+tcf_status tcf_init_grid_static(const tcf_config* cfg, void* hip_stream, tcf_grid** out) {
+  g_err.clear();
+  if (!out) return fail(TCF_E_INVALID, "out is NULL");
+  *out = nullptr;
+  std::string why = validate(cfg);
+  if (!why.empty()) return fail(TCF_E_INVALID, why);
+  const size_t need = carve(cfg, nullptr, nullptr);
+  if (need > TCF_STATIC_WORKSPACE_BYTES)
+    return fail(TCF_E_WORKSPACE, "configuration needs " + std::to_string(need) +
+                                     " bytes of workspace; the fixed workspace holds " +
+                                     std::to_string((size_t)TCF_STATIC_WORKSPACE_BYTES));
+  int dev = -1;
+  HIPCHECK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxStaticDevices) return fail(TCF_E_DEVICE, "device index out of range");
+  std::lock_guard<std::mutex> lock(g_static_mu);
+  StaticSlot& sl = g_static[dev];
+  if (sl.in_use)
+    return fail(TCF_E_STATE, "the fixed workspace of this GPU is in use by an open grid (tcf_destroy it first)");
+  if (!sl.ptr) {
+    // once per device, with that device current
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return fail(TCF_E_DEVICE, std::string("hipGetSymbolAddress: ") + hipGetErrorString(e));
+    if (!p || (uintptr_t)p % kAlign) return fail(TCF_E_DEVICE, "fixed workspace address is not 256-byte aligned");
+    hipEvent_t ev = nullptr;
+    e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (e != hipSuccess) return fail(TCF_E_DEVICE, std::string("event creation: ") + hipGetErrorString(e));
+    sl.ptr = p;
+    sl.ev = ev;
+  }
+  tcf_grid* g = &sl.grid;
+  g->prof_ev.clear();
+  *g = tcf_grid();
+  init_handle(g, cfg, sl.ptr, TCF_STATIC_WORKSPACE_BYTES, hip_stream);
+  g->hscal = (double*)sl.mirror;
+  g->rb_ev = sl.ev;
+  g->static_dev = dev;
+  clear_start(g);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(TCF_E_DEVICE, std::string("init kernels: ") + hipGetErrorString(e));
+  sl.in_use = true;
   *out = g;
   return TCF_OK;
 }
@@ -1656,6 +1739,12 @@ void tcf_destroy(tcf_grid* g) {
   if (!g) return;
   hipStreamSynchronize(g->stream);
   for (hipEvent_t e : g->prof_ev) hipEventDestroy(e);
+  if (g->static_dev >= 0) {  // the handle, its event and mirror belong to the device's slot
+    g->prof_ev.clear();
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    g_static[g->static_dev].in_use = false;
+    return;
+  }
   if (g->rb_ev) hipEventDestroy(g->rb_ev);
   hipHostFree(g->hscal);
   delete g;

@@ -57,7 +57,7 @@ class TcfStepInfo(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
-EXPORTS = ["tcf_workspace_bytes", "tcf_init_grid", "tcf_set_fields", "tcf_get_fields",
+EXPORTS = ["tcf_workspace_bytes", "tcf_init_grid", "tcf_init_grid_static", "tcf_set_fields", "tcf_get_fields",
            "tcf_get_pressure_history", "tcf_set_pressure_history", "tcf_set_species",
            "tcf_get_species", "tcf_set_phases", "tcf_get_phases", "tcf_step",
            "tcf_solve_pressure", "tcf_predictor", "tcf_apply_A", "tcf_step_backward", "tcf_adjoint_transport",
@@ -80,6 +80,8 @@ def load():
     lib.tcf_workspace_bytes.argtypes = [cfgp]
     lib.tcf_init_grid.restype = st
     lib.tcf_init_grid.argtypes = [cfgp, vp, C.c_size_t, vp, C.POINTER(vp)]
+    lib.tcf_init_grid_static.restype = st
+    lib.tcf_init_grid_static.argtypes = [cfgp, vp, C.POINTER(vp)]
     lib.tcf_set_fields.restype = st
     lib.tcf_set_fields.argtypes = [vp, C.c_double, vp, vp, vp, vp, vp, vp]
     lib.tcf_get_fields.restype = st
@@ -177,7 +179,9 @@ def workspace_bytes(c: dict, precision=None, flags=None) -> int:
 class Grid:
     """One simulation state on one GPU (device memory owned by torch)."""
 
-    def __init__(self, c: dict, precision=None, flags=None, device="cuda"):
+    def __init__(self, c: dict, precision=None, flags=None, device="cuda", static=False):
+        """static=True: the workspace is the library's fixed per-GPU array
+        (tcf_init_grid_static), nothing is allocated for it."""
         lib = load()
         self.c = dict(c)
         self.cfg = make_config(c, precision, flags)
@@ -185,15 +189,21 @@ class Grid:
         if nbytes == 0:
             raise TcfError(TCF_E_INVALID, "invalid configuration")
         self.device = torch.device(device)
-        raw = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
-        off = (-raw.data_ptr()) % 256
-        self._ws_raw = raw
-        self.ws_ptr = raw.data_ptr() + off
-        self.ws_bytes = nbytes
         self.stream = torch.cuda.current_stream(self.device)
         h = C.c_void_p()
-        _check(lib.tcf_init_grid(C.byref(self.cfg), C.c_void_p(self.ws_ptr), C.c_size_t(nbytes),
-                                 C.c_void_p(self.stream.cuda_stream), C.byref(h)))
+        if static:
+            self._ws_raw, self.ws_ptr, self.ws_bytes = None, None, nbytes
+            with torch.cuda.device(self.device):
+                _check(lib.tcf_init_grid_static(C.byref(self.cfg), C.c_void_p(self.stream.cuda_stream),
+                                                C.byref(h)))
+        else:
+            raw = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+            off = (-raw.data_ptr()) % 256
+            self._ws_raw = raw
+            self.ws_ptr = raw.data_ptr() + off
+            self.ws_bytes = nbytes
+            _check(lib.tcf_init_grid(C.byref(self.cfg), C.c_void_p(self.ws_ptr), C.c_size_t(nbytes),
+                                     C.c_void_p(self.stream.cuda_stream), C.byref(h)))
         self.h = h
         nx, ny, nz = self.cfg.nx, self.cfg.ny, self.cfg.nz
         self.shapes = dict(cell=(nz, ny, nx), u=(nz, ny, nx + 1), v=(nz, ny + 1, nx),
