@@ -9,9 +9,18 @@ inputs resident in HBM.  The primary line is the FP32-stencil path with FP64
 iterative refinement at a divergence residual <= 1e-8; the plain FP64 path at
 the same accuracy is reported beside it.
 
-Prints ONE JSON line.  Options: --steps K --warmup W --gpus 1 --workload i
---kernel FAMILY (kernel family for the roofline entry) --no-cpu --no-fp64
---no-adjoint --no-species --no-rk3p --no-nphase.
+The timed steps follow a spin-up (--spinup, default 200 steps from rest):
+the beam has then heated the melt surface and driven a Marangoni flow (CFL
+~0.12 at step 200), and the pressure solve needs the iterations of the
+developed flow (7 CG iterations and 2 refinements per step instead of 4 and
+1 from rest).  With no phase change the surface temperature keeps rising and
+the flow passes the explicit CFL limit near step 330, so the window stays
+below that.  Then --warmup W untimed and --steps K timed steps.
+
+Prints ONE JSON line.  Options: --steps K --warmup W --gpus 1 --spinup S
+--cpu-steps C --no-cpu --no-fp64 --no-kernels --no-adjoint --no-species
+--no-rk3p --no-nphase.  `--trace-summary CSV` prints the per-kernel table of
+the last --trace-steps steps of a rocprofv3 kernel trace instead.
 """
 from __future__ import annotations
 
@@ -19,6 +28,7 @@ import argparse
 import hashlib
 import json
 import os
+import platform
 import re
 import sys
 import time
@@ -27,38 +37,61 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+# kernel families timed with HIP events (tcf_profile), in the order tried
+FAMILIES = ("transport", "smooth", "update", "spmv", "predictor", "resid64", "project", "geometry")
+KERNEL_NAMES = {"transport": "k_transport2<float,3,1>", "smooth": "k0_smooth<float,3,*>",
+                "update": "k0_update_smooth<float,3>", "spmv": "k0_spmv_upd<float,3>",
+                "predictor": "k_pred2_f<float,3,*>", "resid64": "k0_resid64<float,3>",
+                "project": "k_project_diag<float,3>", "geometry": "k_geometry_z<float>",
+                "species": "k_transport2<float,3,0>"}
 
 
-def algorithmic_bytes(family: str, c: dict, precision: int) -> float:
-    """Bytes one launch of a kernel family must move (each value once)."""
+def algorithmic_bytes(family: str, c: dict) -> float:
+    """Bytes one launch of a kernel family of the FP32 path must move (each
+    value read or written once; face arrays counted as N values)."""
     N = c["nx"] * c["ny"] * c["nz"]
-    w = 4 if precision == 1 else 8
-    nfaces_per_cell = 3 if c["dim"] == 3 else 2
+    w = 4
+    nf = 3 if c["dim"] == 3 else 2
     if family == "smooth":
         # finest-level Jacobi sweep: x, b, alpha (face weights recomputed) read, x' written
         return N * w * (3 + 1)
     if family == "spmv":
-        # finest-level SpMV fused with d <- z + beta d: z, d, alpha read; d' written
-        # (K d' is not stored)
+        # d <- z + beta d with d'.K d': z, d, alpha read; d' written (K d' not stored)
         return N * w * (3 + 1)
     if family == "update":
-        # x += alpha d, r -= alpha K d (K d recomputed), first Jacobi sweep:
-        # x, r, d, alpha read; x, r, z1 written
+        # x += alpha d, r -= alpha K d (K d recomputed), first sweep: x, r, d, alpha / x, r, z1
         return N * w * (4 + 3)
     if family == "transport":
-        # averaged over the three stages: alpha, T, one velocity per axis,
-        # base alpha/T (stages 2, 3), outputs alpha, T
-        return N * w * (2 + nfaces_per_cell + 2 * 2 / 3 + 2)
+        # per stage, averaged over the three: alpha, T, one velocity per axis,
+        # base alpha and T (stages 2, 3) read; alpha, T written
+        return N * w * (2 + nf + 2 * 2 / 3 + 2)
     if family == "species":
-        # one species stage, averaged over the three: c, one velocity per
-        # axis, base c (stages 2, 3), output c
-        return N * w * (1 + nfaces_per_cell + 2 / 3 + 1)
+        return N * w * (1 + nf + 2 / 3 + 1)
     if family == "predictor":
-        # per component launch: alpha, sigma*kappa, M_d, u, v, w, u*_d (write)
-        return N * w * (3 + nfaces_per_cell + 1)
+        # per component: alpha, sigma*kappa, M_d and the nf velocities read; u*_d written
+        return N * w * (3 + nf + 1)
     if family == "resid64":
-        return N * 8 * (3 + nfaces_per_cell + 1)
+        # FP64 refinement residual: b, p (FP64), alpha read; r (FP64) written
+        return N * (8 + 8 + w + 8)
+    if family == "project":
+        # alpha, p (FP64), u*, v*, w* read; u, v, w written in FP64 and FP32
+        return N * (w + 8 + nf * w) + N * nf * (8 + w)
+    if family == "geometry":
+        # alpha, T read; sigma*kappa and the nf components of M written
+        return N * w * (2 + 1 + nf)
     raise ValueError(family)
+
+
+def step_bytes_per_cell(n_it: float, n_ref: float, precision: int) -> float:
+    """The path's algorithmic HBM bytes per cell-step: 42 + 26 n_it values
+    (transport stages 25, predictor with the divergence 9, projection 8, and
+    per CG iteration the SpMV, the vector updates and one V(2,2) cycle's
+    finest-level sweeps with the coarse levels' share) of w bytes, plus in
+    the FP32 path the FP64 words of u, v, w, p and the right-hand side, and
+    per refinement the FP64 residual pass."""
+    if precision == 1:
+        return (42 + 26 * n_it) * 4 + (8 + 28 * n_ref)
+    return (42 + 26 * n_it) * 8
 
 
 def kernel_source_hash() -> str:
@@ -74,7 +107,7 @@ def kernel_source_hash() -> str:
 
 def measured_traffic(family: str, workload: str):
     """HBM bytes per launch from committed rocprofv3 counter summaries, if
-    they were taken on the current kernel source (else None)."""
+    they were taken on the current kernel sources (else None)."""
     path = os.path.join(ROOT, "profiles", f"counters_{family}_{workload}.md")
     if not os.path.exists(path):
         return None
@@ -86,36 +119,59 @@ def measured_traffic(family: str, workload: str):
     return float(b.group(1))
 
 
-def cpu_baseline(c: dict, dt: float, rtol: float):
-    """One step of the same workload on the host cores with the FP64 oracle."""
+def host_cpu():
+    model = platform.processor() or ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return model, os.cpu_count()
+
+
+def cpu_baseline(c: dict, rtol: float, steps: int):
+    """The FP64 oracle on the host cores: the first `steps` steps of the
+    same workload from its initial state."""
     from oracle import pyoracle as O
     from paper_2209_09671_amd import inputs as I
     st = I.initial_state(c)
     t0 = time.perf_counter()
-    _, info, status = O.step(c, st, 0.0, dt, 1, rtol=rtol)
+    _, info, status = O.step(c, st, 0.0, c["dt"], steps, rtol=rtol)
     sec = time.perf_counter() - t0
     N = c["nx"] * c["ny"] * c["nz"]
-    return {"value": N / sec / 1e6, "unit": "Mcell-steps/s", "cores": O.num_threads(), "kind": "oracle",
-            "sample": f"1 step of the {c['nx']}x{c['ny']}x{c['nz']} workload from its initial state, "
-                      f"FP64 oracle, pressure rtol {rtol:g} ({sec:.1f} s, {info['cg_iters']} CG iterations)"}
+    model, ncpu = host_cpu()
+    return {"value": N * steps / sec / 1e6, "unit": "Mcell-steps/s", "cores": O.num_threads(), "kind": "oracle",
+            "sample": f"first {steps} steps of the {c['nx']}x{c['ny']}x{c['nz']} workload from its initial state "
+                      f"(FP64 oracle, pressure rtol {rtol:g}, {sec:.1f} s; {info['cg_iters']} CG iterations in "
+                      f"the last step)",
+            "cpu_model": model, "nproc": ncpu, "status": status}
 
 
-def run_gpu(c, st, precision, steps, warmup, family=None, family_steps=5):
-    """Warm-up, then `steps` timed steps without instrumentation; with a
-    kernel family, `family_steps` further steps in a second timed region
-    with HIP events around that family's launches (their average duration),
-    so that the events do not perturb the throughput."""
+def run_gpu(c, st, precision, spinup, warmup, steps, families=(), family_steps=4):
+    """Spin-up, warm-up, then `steps` timed steps without instrumentation;
+    then, per kernel family, `family_steps` further steps with HIP events
+    around that family's launches (their average duration), so that the
+    events do not perturb the throughput."""
     import torch
     from paper_2209_09671_amd import tcf
     g = tcf.Grid(c, precision=precision)
     g.set_state(st)
     dt = c["dt"]
+    sp_it = sp_ref = 0
+    sp_cfl = 0.0
+    for _ in range(spinup):
+        info = g.step(dt, 1)
+        sp_it += info["cg_iters"]
+        sp_ref += info["refine_iters"]
+        sp_cfl = max(sp_cfl, info["cfl_max"])
     for _ in range(warmup):
         g.step(dt, 1)
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    iters, refs, worst_res, worst_div = 0, 0, 0.0, 0.0
+    iters, refs, worst_res, worst_div, cfl = 0, 0, 0.0, 0.0, 0.0
     e0.record(stream)
     t0 = time.perf_counter()
     for _ in range(steps):
@@ -124,38 +180,67 @@ def run_gpu(c, st, precision, steps, warmup, family=None, family_steps=5):
         refs += info["refine_iters"]
         worst_res = max(worst_res, info["p_relres"])
         worst_div = max(worst_div, info["div_rel"])
+        cfl = max(cfl, info["cfl_max"])
     e1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ev_ms = e0.elapsed_time(e1)
-    kms, kn = 0.0, 0
-    if family:
-        g.profile(family)
+    fams = {}
+    for fam in families:
+        g.profile(fam)
         for _ in range(family_steps):
             g.step(dt, 1)
         torch.cuda.synchronize()
         kms, kn = g.profile_read()
+        g.profile(None)
+        fams[fam] = (kms, kn, family_steps)
     g.close()
     del g
     torch.cuda.empty_cache()
     return dict(wall=wall, ev_ms=ev_ms, iters=iters / max(steps, 1), refs=refs / max(steps, 1),
-                relres=worst_res, div=worst_div, kernel_ms=kms, kernel_launches=kn, info=info)
+                relres=worst_res, div=worst_div, cfl=cfl, info=info, fams=fams,
+                spinup=dict(steps=spinup, cg_iters_per_step=round(sp_it / max(spinup, 1), 2),
+                            refine_iters_per_step=round(sp_ref / max(spinup, 1), 2), max_cfl=round(sp_cfl, 4)))
 
 
-def adjoint_timing(c, st, steps, every):
+def kernel_table(r, c):
+    rows = {}
+    for fam, (kms, kn, nst) in r["fams"].items():
+        if not kn:
+            continue
+        avg = kms / kn
+        ab = algorithmic_bytes(fam, c)
+        ach = ab / (avg / 1e3) / 1e9
+        rows[fam] = {"kernel": KERNEL_NAMES.get(fam, fam), "avg_launch_ms": round(avg, 5),
+                     "launches_per_step": round(kn / nst, 2), "ms_per_step": round(kms / nst, 4),
+                     "algorithmic_bytes_per_launch": ab, "achieved_GBs": round(ach, 1),
+                     "frac": round(ach / HBM_PEAK_GBS, 4)}
+    return rows
+
+
+def adjoint_timing(c, spin, steps, every):
     """Seconds per adjoint step (FP64): gradient of the melt-pool kinetic
-    energy 1/2 h^3 sum_f rho_f u_f^2 after `steps` steps with respect to
-    dsigma/dT and the initial T, checkpoints every `every` steps; the time
-    includes the forward recomputation of each checkpoint segment."""
+    energy 1/2 h^3 sum_f rho_f u_f^2 after `steps` steps, started from the
+    state after `spin` steps, with respect to dsigma/dT and that state's T;
+    checkpoints every `every` steps; the time includes the forward
+    recomputation of each checkpoint segment."""
     import torch
+    from paper_2209_09671_amd import inputs as I
     from paper_2209_09671_amd import tcf
-    dv = lambda x: None if x is None else torch.as_tensor(x, dtype=torch.float64, device="cuda")
-    a0, u0, v0, w0 = dv(st["alpha"]), dv(st["u"]), dv(st["v"]), dv(st["w"])
+    g = tcf.Grid(c, precision=0)
+    g.set_state(I.initial_state(c))
+    for _ in range(spin):
+        g.step(c["dt"], 1)
+    f = g.get_fields()
+    g.close()
+    t_start = f["t"]
+    a0, u0, v0, w0, p0 = f["alpha"], f["u"], f["v"], f["w"], f["p"]
     s = torch.tensor(c["dsigma_dT"], dtype=torch.float64, requires_grad=True)
-    T0 = dv(st["T"]).requires_grad_(True)
+    T0 = f["T"].clone().requires_grad_(True)
+    del f
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    a, T, u, v, w = tcf.TcfRollout.apply(s, T0, c, a0, u0, v0, w0, steps, every)
+    a, T, u, v, w = tcf.TcfRollout.apply(s, T0, c, a0, u0, v0, w0, steps, every, t_start, p0)
     rho = c["rho1"] + a.clamp(0, 1) * (c["rho2"] - c["rho1"])
     h3 = c["h"] ** 3
     ke = 0.5 * h3 * ((0.5 * (rho[:, :, 1:] + rho[:, :, :-1]) * u[:, :, 1:-1] ** 2).sum()
@@ -168,12 +253,48 @@ def adjoint_timing(c, st, steps, every):
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     out = {"value": round((t2 - t1) / steps, 5), "unit": "s/step", "precision": "fp64",
-           "steps": steps, "checkpoint_every": every, "forward_s_per_step": round((t1 - t0) / steps, 5),
+           "steps": steps, "checkpoint_every": every, "window": f"steps {spin}..{spin + steps}",
+           "forward_s_per_step": round((t1 - t0) / steps, 5),
            "loss": "1/2 h^3 sum_f rho_f u_f^2 (melt-pool kinetic energy)",
-           "dL_dsigmaT": float(s.grad), "grad_T0_norm": float(T0.grad.norm())}
-    del a, T, u, v, w, T0
+           "dL_dsigmaT": float(s.grad), "grad_T_norm": float(T0.grad.norm())}
+    del a, T, u, v, w, T0, a0, u0, v0, w0, p0
     torch.cuda.empty_cache()
     return out
+
+
+def trace_summary(path, nsteps, marker="k_transport2<float, 3, 1>", per_step=3):
+    """Markdown table of the kernels of the last `nsteps` steps of a
+    rocprofv3 kernel trace (CSV); a step is found by its `per_step`
+    launches of `marker` (the transport stages).  Needs no GPU."""
+    import collections
+    import csv
+    rows = []
+    with open(path) as f:
+        for r in csv.DictReader(f):
+            rows.append((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), r["Kernel_Name"]))
+    rows.sort()
+    idx = [i for i, r in enumerate(rows) if marker in r[2]]
+    win = rows[idx[-nsteps * per_step]:]
+    t0, t1 = win[0][0], win[-1][1]
+    agg = collections.defaultdict(lambda: [0, 0.0])
+    for a, b, n in win:
+        n = n.replace("void ", "").replace("tcf::(anonymous namespace)::", "").split("(")[0]
+        agg[n][0] += 1
+        agg[n][1] += (b - a) / 1e3
+    tot = sum(v[1] for v in agg.values())
+    out = [f"Window: the last {nsteps} steps, {len(win)} dispatches, span {(t1 - t0) / 1e6:.3f} ms "
+           f"({(t1 - t0) / 1e6 / nsteps:.3f} ms/step), kernel time {tot / 1e3 / nsteps:.3f} ms/step.", "",
+           "| kernel | calls/step | avg us | ms/step | % |", "|---|---:|---:|---:|---:|"]
+    for n, (c, us) in sorted(agg.items(), key=lambda kv: -kv[1][1]):
+        out.append(f"| {n} | {c / nsteps:.2f} | {us / c:.2f} | {us / 1e3 / nsteps:.3f} | {100 * us / tot:.1f} |")
+    return "\n".join(out)
+
+
+def leg_summary(r, N, steps):
+    return {"value": round(N * steps / (r["ev_ms"] / 1e3) / 1e6, 3), "unit": "Mcell-steps/s",
+            "ms_per_step": round(r["ev_ms"] / steps, 4), "cg_iters_per_step": round(r["iters"], 2),
+            "refine_iters_per_step": round(r["refs"], 2), "max_div_rel": r["div"], "max_p_relres": r["relres"],
+            "max_cfl": round(r["cfl"], 4), "spinup": r["spinup"]}
 
 
 def main():
@@ -181,24 +302,33 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--spinup", type=int, default=200)
     ap.add_argument("--workload", type=int, default=4)
-    ap.add_argument("--kernel", default="smooth")
     ap.add_argument("--rtol", type=float, default=1e-8)
     ap.add_argument("--inner-rtol", type=float, default=None)
+    ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-kernels", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
-    ap.add_argument("--adjoint-steps", type=int, default=10)
+    ap.add_argument("--adjoint-steps", type=int, default=None)
+    ap.add_argument("--adjoint-spinup", type=int, default=50)
     ap.add_argument("--no-species", action="store_true")
     ap.add_argument("--no-rk3p", action="store_true")
     ap.add_argument("--no-nphase", action="store_true")
+    ap.add_argument("--trace-summary", default=None,
+                    help="print the per-kernel table of the last --trace-steps steps of a rocprofv3 "
+                         "kernel trace CSV and exit (no GPU)")
+    ap.add_argument("--trace-steps", type=int, default=20)
     args = ap.parse_args()
+    if args.trace_summary:
+        print(trace_summary(args.trace_summary, args.trace_steps))
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this path runs on one GPU; runs on several GPUs are not supported "
               "(the step is measured on one GPU's share of the grid)", file=sys.stderr)
         sys.exit(2)
 
-    import torch
     from paper_2209_09671_amd import inputs as I
 
     c = I.config(args.workload)
@@ -208,95 +338,99 @@ def main():
     st = I.initial_state(c)
     N = c["nx"] * c["ny"] * c["nz"]
     wl = c["name"]
+    K, W, S = args.steps, args.warmup, args.spinup
+    window = f"steps {S + W + 1}..{S + W + K} of a run from rest"
 
-    r32 = run_gpu(c, st, 1, args.steps, args.warmup, args.kernel)
+    r32 = run_gpu(c, st, 1, S, W, K, () if args.no_kernels else FAMILIES)
     sec = r32["ev_ms"] / 1e3
-    value = N * args.steps / sec / 1e6
+    value = N * K / sec / 1e6
+    ms = r32["ev_ms"] / K
     fp64 = None
     if not args.no_fp64:
-        r64 = run_gpu(c, st, 0, args.steps, args.warmup)
-        fp64 = {"value": N * args.steps / (r64["ev_ms"] / 1e3) / 1e6, "unit": "Mcell-steps/s",
-                "ms_per_step": r64["ev_ms"] / args.steps, "cg_iters_per_step": r64["iters"],
-                "max_div_rel": r64["div"], "max_p_relres": r64["relres"]}
+        r64 = run_gpu(c, st, 0, S, W, K)
+        fp64 = leg_summary(r64, N, K)
+        b64 = step_bytes_per_cell(r64["iters"], 0, 0)
+        fp64["step_hbm"] = {"bytes_per_cell_step": b64,
+                            "achieved_GBs": round(N * b64 / (fp64["ms_per_step"] / 1e3) / 1e9, 1),
+                            "frac": round(N * b64 / (fp64["ms_per_step"] / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
 
+    kernels = kernel_table(r32, c)
     roof = None
-    if r32["kernel_launches"]:
-        avg_ms = r32["kernel_ms"] / r32["kernel_launches"]
-        ab = algorithmic_bytes(args.kernel, c, 1)
-        ach = ab / (avg_ms / 1e3) / 1e9
-        traffic = measured_traffic(args.kernel, re.sub(r"\^\d", "", wl).replace("-", ""))
-        roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": args.kernel, "avg_launch_ms": round(avg_ms, 5),
-                "launches": r32["kernel_launches"], "algorithmic_bytes_per_launch": ab}
+    if kernels:
+        # the kernel family that takes the most time per step
+        dom = max(kernels, key=lambda f: kernels[f]["ms_per_step"])
+        k = kernels[dom]
+        workload_tag = re.sub(r"\^\d", "", wl).replace("-", "")
+        roof = {"bound": "hbm", "achieved": k["achieved_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": k["frac"], "traffic": measured_traffic(dom, workload_tag),
+                "kernel": dom, "kernel_name": k["kernel"], "avg_launch_ms": k["avg_launch_ms"],
+                "launches_per_step": k["launches_per_step"], "ms_per_step": k["ms_per_step"],
+                "algorithmic_bytes_per_launch": k["algorithmic_bytes_per_launch"]}
+    b32 = step_bytes_per_cell(r32["iters"], r32["refs"], 1)
+    step_hbm = {"model": "(42 + 26 n_it) 4 + (8 + 28 n_ref) B per cell-step",
+                "bytes_per_cell_step": round(b32, 1),
+                "achieved_GBs": round(N * b32 / (ms / 1e3) / 1e9, 1),
+                "frac": round(N * b32 / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
 
     species = None
     if not args.no_species:
         # solutal Marangoni: the same workload carrying a species field (a
         # seeded Gaussian bump of concentration) with sigma = sigma(T, c)
         cs = I.with_species(c, -0.05, "blob")
-        rs = run_gpu(cs, dict(st, c=I.species_field(cs)), 1, args.steps, args.warmup, "species")
-        avg = rs["kernel_ms"] / max(rs["kernel_launches"], 1)
-        ab = algorithmic_bytes("species", c, 1)
-        species = {"value": round(N * args.steps / (rs["ev_ms"] / 1e3) / 1e6, 3), "unit": "Mcell-steps/s",
-                   "ms_per_step": round(rs["ev_ms"] / args.steps, 4),
-                   "added_ms_per_step": round((rs["ev_ms"] - r32["ev_ms"]) / args.steps, 4),
-                   "cg_iters_per_step": round(rs["iters"], 2), "max_div_rel": rs["div"],
-                   "dsigma_dc": cs["dsigma_dc"], "species_field": "blob",
-                   "species_stage": {"kernel": "k_transport2 (species only)", "avg_launch_ms": round(avg, 5),
-                                     "launches": rs["kernel_launches"], "algorithmic_bytes_per_launch": ab,
-                                     "achieved_GBs": round(ab / (avg / 1e3) / 1e9, 1)}}
+        rs = run_gpu(cs, dict(st, c=I.species_field(cs)), 1, S, W, K, ("species",))
+        species = leg_summary(rs, N, K)
+        species.update(added_ms_per_step=round(species["ms_per_step"] - ms, 4), dsigma_dc=cs["dsigma_dc"],
+                       species_field="blob", species_stage=kernel_table(rs, c).get("species"))
 
     rk3p = None
     if not args.no_rk3p:
         # the time-accurate integrator: SSP-RK3 over the whole state with a
         # projection in every stage (three pressure solves per step)
-        rr = run_gpu(dict(c, integrator=1), st, 1, args.steps, args.warmup)
-        rk3p = {"value": round(N * args.steps / (rr["ev_ms"] / 1e3) / 1e6, 3), "unit": "Mcell-steps/s",
-                "ms_per_step": round(rr["ev_ms"] / args.steps, 4), "cg_iters_per_step": round(rr["iters"], 2),
-                "refine_iters_per_step": round(rr["refs"], 2), "max_div_rel": rr["div"],
-                "max_p_relres": rr["relres"], "integrator": "SSP-RK3, projection in every stage"}
+        rk3p = leg_summary(run_gpu(dict(c, integrator=1), st, 1, S, W, K), N, K)
+        rk3p["integrator"] = "SSP-RK3, projection in every stage"
 
     nphase = None
     if not args.no_nphase:
         # N-phase VOF: gas, a liquid pool and solid metal (three phases,
         # per-pair surface tension) on the same grid and beam
         cn = I.meltpool_phases(c)
-        rn = run_gpu(cn, I.phase_state(cn), 1, args.steps, args.warmup)
-        nphase = {"value": round(N * args.steps / (rn["ev_ms"] / 1e3) / 1e6, 3), "unit": "Mcell-steps/s",
-                  "ms_per_step": round(rn["ev_ms"] / args.steps, 4), "cg_iters_per_step": round(rn["iters"], 2),
-                  "max_div_rel": rn["div"], "phases": "gas, liquid metal, solid metal"}
+        nphase = leg_summary(run_gpu(cn, I.phase_state(cn), 1, S, W, K), N, K)
+        nphase["phases"] = "gas, liquid metal, solid metal"
 
     adj = None
     if not args.no_adjoint:
         ca = dict(c, precision=0)
-        adj = adjoint_timing(ca, st, args.adjoint_steps, max(1, args.adjoint_steps // 2))
+        n_adj = args.adjoint_steps or c.get("adjoint_steps", 200)
+        adj = adjoint_timing(ca, args.adjoint_spinup, n_adj, c.get("checkpoint_every", 25))
 
     cpu = None
     if not args.no_cpu:
-        cpu = cpu_baseline(c, c["dt"], args.rtol)
+        cpu = cpu_baseline(c, args.rtol, args.cpu_steps)
 
     out = {
         "metric": "Mcell-steps/s (FP32 stencils + FP64 refinement, divergence residual <= 1e-8)",
         "value": round(value, 3),
         "unit": "Mcell-steps/s",
         "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(r32["ev_ms"] / args.steps, 4),
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": round(ms, 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32+f64",
         "data": "synthetic",
         "config": {"workload": wl, "cells": N, "grid": [c["nx"], c["ny"], c["nz"]], "h_m": c["h"],
-                   "dt_s": c["dt"], "precision": "fp32 stencils/inner solve, fp64 refinement",
+                   "dt_s": c["dt"], "window": window, "spinup_steps": S,
+                   "precision": "fp32 stencils/inner solve, fp64 refinement",
                    "pressure_guess": f"extrapolated in time, order {c.get('p_extrapolate', 2)}",
                    "p_rtol": args.rtol, "cg_iters_per_step": round(r32["iters"], 2),
                    "refine_iters_per_step": round(r32["refs"], 2), "max_p_relres": r32["relres"],
-                   "max_div_rel": r32["div"]},
+                   "max_div_rel": r32["div"], "max_cfl": round(r32["cfl"], 4), "spinup": r32["spinup"]},
         "fp64_same_accuracy": fp64,
-        "wall_ms_per_step": round(r32["wall"] * 1e3 / args.steps, 4),
+        "wall_ms_per_step": round(r32["wall"] * 1e3 / K, 4),
+        "step_hbm": step_hbm,
+        "kernels": kernels,
         "adjoint": adj,
         "solutal_species": species,
         "time_accurate_rk3": rk3p,

@@ -37,6 +37,12 @@ tcf_status fail(tcf_status st, const std::string& msg) {
 constexpr size_t kAlign = 256;
 constexpr double kOmegaC = 1.9;  // over-correction of the piecewise-constant coarse correction
 constexpr int kCoarseSweeps = 30;
+// fraction of the FP64 target that an inner FP32 solve aims at (its
+// recurrence residual overstates the true reduction by FP32 rounding)
+#ifndef TCF_REFINE_SAFETY
+#define TCF_REFINE_SAFETY 0.5
+#endif
+constexpr double kRefineSafety = TCF_REFINE_SAFETY;
 // levels of at most this many cells (and everything below them) run as one
 // block (the coarse tail of the V-cycle)
 #ifndef TCF_MG_TAIL_CELLS
@@ -833,7 +839,7 @@ tcf_status solve_refined(tcf_grid* g, double* p, int kind, int* iters, int* nref
     // inner solve of K e = r64 / scale in FP32 from e = 0
     // reduce the scaled residual only as far as this sweep needs to reach
     // the FP64 target (never below inner_rtol)
-    const double tau = std::min(0.5, std::max(irt, 0.5 * rt * std::sqrt(bb / rr)));
+    const double tau = std::min(0.5, std::max(irt, kRefineSafety * rt * std::sqrt(bb / rr)));
     // the scaled residual r32 = r64 / scale with the partials of |r32|^2:
     // from the first sweep of a multigrid hierarchy, else in a pass of its own
     FromR64 f64{g->r64, g->part[1], tau * tau, 0};

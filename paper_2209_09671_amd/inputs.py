@@ -65,7 +65,7 @@ def _meltpool_3d(nx, ny, nz, h, steps, dt, name, seed):
              q_power=200.0, q_radius=40e-6, q_x0=lx / 4.0, q_y0=ly / 2.0,
              q_vx=0.5, q_vy=0.0,
              normal_eps=1e-6 / h, dt=dt, steps=steps, precision=1,
-             p_rtol=1e-10, seed=seed)
+             p_rtol=1e-10, inner_rtol=1e-6, seed=seed)
     return c
 
 

@@ -388,12 +388,18 @@ class TcfRollout(torch.autograd.Function):
     (alpha, T, u, v, w) (w is an empty tensor in 2D)."""
 
     @staticmethod
-    def forward(ctx, s, T0, cfg, alpha0, u0, v0, w0, nsteps, k):
+    def forward(ctx, s, T0, cfg, alpha0, u0, v0, w0, nsteps, k, *start):
+        """start: optional (t0, p0), the time of the initial state (the
+        moving heat source's position) and its pressure (the first solve's
+        initial guess); default (0, zero pressure)."""
         c = dict(cfg)
         c["dsigma_dT"] = float(s)
         g = Grid(c, precision=TCF_FP64, flags=TCF_WITH_ADJOINT, device=T0.device)
         dt = c["dt"]
-        g.set_fields(0.0, alpha0, T0, u0, v0, w0, None)
+        t0 = float(start[0]) if len(start) > 0 else 0.0
+        p0 = start[1] if len(start) > 1 else None
+        ctx.n_start = len(start)
+        g.set_fields(t0, alpha0, T0, u0, v0, w0, p0)
         ckpt = []
         for n in range(nsteps):
             if n % k == 0:
@@ -431,4 +437,4 @@ class TcfRollout(torch.autograd.Function):
             for n in reversed(range(n0, n1)):
                 st = states[n - n0]
                 lam = g.step_backward(st["t"], dt, st, lam, sbar)
-        return sbar, lam["T"], None, None, None, None, None, None, None
+        return (sbar, lam["T"], None, None, None, None, None, None, None) + (None,) * ctx.n_start
