@@ -38,8 +38,9 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 # kernel families timed with HIP events (tcf_profile), in the order tried
-FAMILIES = ("transport", "smooth", "update", "spmv", "predictor", "resid64", "project", "geometry")
-KERNEL_NAMES = {"transport": "k_transport2<float,3,1>", "smooth": "k0_smooth<float,3,*>",
+FAMILIES = ("transport", "smooth2", "smooth", "update", "spmv", "predictor", "resid64", "project", "geometry")
+KERNEL_NAMES = {"transport": "k_transport2<float,3,1>", "smooth": "k0_smooth<float,3,false>",
+                "smooth2": "k0_smooth2<float,true,8>",
                 "update": "k0_update_smooth<float,3>", "spmv": "k0_spmv_upd<float,3>",
                 "predictor": "k_pred2_f<float,3,*>", "resid64": "k0_resid64<float,3>",
                 "project": "k_project_diag<float,3>", "geometry": "k_geometry_z<float>",
@@ -55,6 +56,10 @@ def algorithmic_bytes(family: str, c: dict) -> float:
     if family == "smooth":
         # finest-level Jacobi sweep: x, b, alpha (face weights recomputed) read, x' written
         return N * w * (3 + 1)
+    if family == "smooth2":
+        # both post-smoothing sweeps in one pass: x, b, alpha and the coarse
+        # correction (1/8) read, x'' written
+        return N * w * (3 + 1 / 8 + 1)
     if family == "spmv":
         # d <- z + beta d with d'.K d': z, d, alpha read; d' written (K d' not stored)
         return N * w * (3 + 1)

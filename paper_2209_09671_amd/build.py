@@ -30,7 +30,12 @@ def build(verbose: bool = False, defines=(), out: str | None = None) -> str:
         cmd = [HIPCC] + FLAGS + ["-D" + d for d in defines] + lang + ["-c", path, "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
-        subprocess.run(cmd, check=True, stderr=subprocess.PIPE if not verbose else None)
+        try:
+            subprocess.run(cmd, check=True, stderr=subprocess.PIPE if not verbose else None, text=True)
+        except subprocess.CalledProcessError as e:
+            if e.stderr:
+                sys.stderr.write(e.stderr)
+            raise
         objs.append(obj)
     tmp = lib + ".tmp"
     subprocess.run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-Wl,-z,defs", "-o", tmp] + objs, check=True)

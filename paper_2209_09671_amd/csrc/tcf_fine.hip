@@ -421,6 +421,227 @@ __global__ __launch_bounds__(FX * FY) void k0_smooth(Op0<R> op, int kz, int ntx,
   if (part) write_partial(acc, part);
 }
 
+// Two damped-Jacobi sweeps in one z-march (temporal blocking):
+//   x1 = x0' + w1 (b - K0 x0') / diag,   x2 = x1 + w2 (b - K0 x1) / diag,
+// with x0' = x0 + omc P e under PRO (the coarse correction applied on the
+// fly).  The first sweep runs on the tile and a one-cell ring (the second
+// sweep's in-plane neighbours), one plane ahead of the second.  x0', the
+// density and b of the tile with a two-cell ring go through a four-plane
+// LDS ring (planes k-1..k+1 in use, k+2 being written), the first sweep's
+// plane through a two-plane one; a thread's own cell keeps its first-sweep
+// value, face weights and diagonal in registers for the second sweep.  The
+// face terms are summed in the order of the single sweep (k0_smooth).  One
+// barrier per plane: plane k+2 is written after it, when every thread is
+// done with plane k-2, whose slot it takes.  Tiles are 64 x TYK.  At 256^3
+// the pass takes 105 us against 59 + 66 us for the two single sweeps; it is
+// bound by its instruction stream (the ring, LDS traffic, six reciprocals
+// per first-sweep cell), not by HBM: loading two planes ahead (more
+// registers, fewer blocks per CU) measured 108 us, and 64 x 16 tiles 111 us.
+template <int TYK>
+__device__ __forceinline__ Tile tile_of_ty(int nx, int ny, int nz, int ntx, int nty, int kz) {
+  const int nb = gridDim.x, b = blockIdx.x;
+  const int t = (nb % 8 == 0) ? (b % 8) * (nb / 8) + b / 8 : b;
+  const int tx = t % ntx, rr = t / ntx;
+  const int ty = rr % nty, tz = rr / nty;
+  Tile T;
+  T.i = tx * FX + threadIdx.x;
+  T.j = ty * TYK + threadIdx.y;
+  T.k0 = tz * kz;
+  T.k1 = min(T.k0 + kz, nz);
+  T.act = T.i < nx && T.j < ny && T.k0 < nz;
+  return T;
+}
+
+constexpr int S2Y = 8;  // rows of the fused sweep's tile (16 measured slower: 111 against 105 us at 256^3)
+
+template <class R, bool PRO, int TYK>
+__global__ __launch_bounds__(FX * TYK) void k0_smooth2(Op0<R> op, int kz, int ntx, int nty, R om1, R om2,
+                                                   const R* __restrict__ b, const R* __restrict__ x,
+                                                   R* __restrict__ xo, const R* __restrict__ e, int cnx, int cny,
+                                                   R omc, double* __restrict__ part,
+                                                   const int* __restrict__ iflag) {
+  constexpr int RX2 = FX + 4, RY2 = TYK + 4, NR2 = RX2 * RY2;  // two-cell ring region
+  constexpr int NRING = 2 * (FX + 2) + 2 * TYK;                // one-cell ring of the tile
+  constexpr int NT = FX * TYK;
+  static_assert(NR2 <= 2 * NT && NRING <= NT, "two load items and one ring cell per thread");
+  if (iflag[I_DONE]) return;
+  __shared__ R sx[4][NR2];
+  __shared__ R sr[4][NR2];
+  __shared__ R sb[4][NR2];
+  __shared__ R s1[2][NR2];
+  const Tile T = tile_of_ty<TYK>(op.nx, op.ny, op.nz, ntx, nty, kz);
+  if (T.k0 >= op.nz) return;  // the same for the whole block
+  const int nx = op.nx, ny = op.ny, nz = op.nz;
+  const long pl = (long)nx * ny;
+  const int tx = threadIdx.x, ty = threadIdx.y, tid = tx + FX * ty;
+  const int i0 = T.i - tx, j0 = T.j - ty;  // tile origin
+  // load items: region cells tid and tid + NT
+  long lc[2], lec[2];
+  int lslot[2];
+  bool lon[2];
+#pragma unroll
+  for (int m = 0; m < 2; ++m) {
+    const int q = tid + NT * m;
+    lon[m] = q < NR2;
+    const int rx = q % RX2, ry = q / RX2;
+    const int gi = min(max(i0 - 2 + rx, 0), nx - 1), gj = min(max(j0 - 2 + ry, 0), ny - 1);
+    lc[m] = (long)gi + (long)nx * gj;
+    lslot[m] = lon[m] ? q : 0;
+    lec[m] = PRO ? (long)(gi >> 1) + (long)cnx * (long)(gj >> 1) : 0;
+  }
+  const long cplane = (long)cnx * cny;
+  // first-sweep items: the own cell, and for tid < NRING one ring cell
+  int qx[2], qy[2];
+  qx[0] = tx + 1;
+  qy[0] = ty + 1;
+  if (tid < FX + 2) { qx[1] = tid; qy[1] = 0; }
+  else if (tid < 2 * (FX + 2)) { qx[1] = tid - (FX + 2); qy[1] = TYK + 1; }
+  else if (tid < 2 * (FX + 2) + TYK) { qx[1] = 0; qy[1] = tid - 2 * (FX + 2) + 1; }
+  else if (tid < NRING) { qx[1] = FX + 1; qy[1] = tid - 2 * (FX + 2) - TYK + 1; }
+  else { qx[1] = 0; qy[1] = 0; }
+  int gi1[2], gj1[2], li[2];
+  bool in1[2];
+#pragma unroll
+  for (int m = 0; m < 2; ++m) {
+    gi1[m] = i0 - 1 + qx[m];
+    gj1[m] = j0 - 1 + qy[m];
+    in1[m] = (m == 0 || tid < NRING) && gi1[m] >= 0 && gi1[m] < nx && gj1[m] >= 0 && gj1[m] < ny;
+    li[m] = (qy[m] + 1) * RX2 + (qx[m] + 1);  // position in the two-cell-ring region
+  }
+  const bool own = T.act;
+  // planes: first sweep on [ks, ke], second on [k0, k1)
+  const int k0 = T.k0, k1 = T.k1;
+  const int ks = max(k0 - 1, 0), ke = min(k1, nz - 1);
+  const int kend = min(k1, nz);  // last plane step: the second sweep of k1 - 1 needs x1 of k1 (if k1 < nz)
+  R ldx[2], lda[2], ldb[2], lde[2];
+  auto issue = [&](int k) {  // loads of plane k (clamped), into the staging registers
+    const int kk = min(max(k, 0), nz - 1);
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+      const long c = lc[m] + pl * kk;
+      ldx[m] = x[c];
+      lda[m] = op.a[c];
+      ldb[m] = b[c];
+      if (PRO) lde[m] = e[lec[m] + cplane * (kk >> 1)];
+    }
+  };
+  auto store = [&](int k) {  // the staged plane k into its LDS slot
+    const int sl = k & 3;
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+      if (lon[m]) {
+        sx[sl][lslot[m]] = PRO ? ldx[m] + omc * lde[m] : ldx[m];
+        sr[sl][lslot[m]] = rho0(op, lda[m]);
+        sb[sl][lslot[m]] = ldb[m];
+      }
+    }
+  };
+  // own cell's second-sweep operands of the previous plane
+  R pw[6] = {R(0), R(0), R(0), R(0), R(0), R(0)}, pdg = R(1), pb = R(0), px1 = R(0), px1m = R(0);
+  bool pin = false;
+  double acc = 0.0;
+  if (ks > 0) {
+    issue(ks - 1);
+    store(ks - 1);
+  }
+  issue(ks);
+  store(ks);
+  if (ks + 1 <= nz - 1) {
+    issue(ks + 1);
+    store(ks + 1);
+  }
+  issue(ks + 2);
+  for (int k = ks; k <= kend; ++k) {
+    __syncthreads();
+    const int sc = k & 3, sm = (k + 3) & 3, sp = (k + 1) & 3;
+    R x1own = R(0);
+    R w[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
+    R dgo = R(1), bo = R(0);
+    bool ino = false;
+    if (k <= ke) {
+#pragma unroll
+      for (int m = 0; m < 2; ++m) {
+        if (!in1[m]) continue;
+        const int l = li[m];
+        const R rc = sr[sc][l], xc = sx[sc][l];
+        R s = R(0), d = R(0), wv[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
+        if (gi1[m] > 0) {
+          wv[0] = coef(R(op.c2), rc + sr[sc][l - 1]);
+          s += wv[0] * (xc - sx[sc][l - 1]);
+          d += wv[0];
+        }
+        if (gi1[m] < nx - 1) {
+          wv[1] = coef(R(op.c2), rc + sr[sc][l + 1]);
+          s += wv[1] * (xc - sx[sc][l + 1]);
+          d += wv[1];
+        }
+        if (gj1[m] > 0) {
+          wv[2] = coef(R(op.c2), rc + sr[sc][l - RX2]);
+          s += wv[2] * (xc - sx[sc][l - RX2]);
+          d += wv[2];
+        }
+        if (gj1[m] < ny - 1) {
+          wv[3] = coef(R(op.c2), rc + sr[sc][l + RX2]);
+          s += wv[3] * (xc - sx[sc][l + RX2]);
+          d += wv[3];
+        }
+        if (k > 0) {
+          wv[4] = coef(R(op.c2), sr[sm][l] + rc);
+          s += wv[4] * (xc - sx[sm][l]);
+          d += wv[4];
+        }
+        if (k < nz - 1) {
+          wv[5] = coef(R(op.c2), rc + sr[sp][l]);
+          s += wv[5] * (xc - sx[sp][l]);
+          d += wv[5];
+        }
+        const R bc = sb[sc][l];
+        const R x1 = xc + om1 * recip(d) * (bc - s);
+        s1[k & 1][l] = x1;
+        if (m == 0) {
+          x1own = x1;
+          dgo = d;
+          bo = bc;
+          ino = true;
+#pragma unroll
+          for (int f = 0; f < 6; ++f) w[f] = wv[f];
+        }
+      }
+    }
+    if (k + 2 <= nz - 1 && k + 2 <= kend + 1) {
+      store(k + 2);
+      issue(k + 3);
+    }
+    // second sweep of plane k - 1 (own cell)
+    const int k2 = k - 1;
+    if (own && k2 >= k0 && k2 < k1 && pin) {
+      const int l = li[0], sl = k2 & 1;
+      R s = R(0);
+      if (T.i > 0) s += pw[0] * (px1 - s1[sl][l - 1]);
+      if (T.i < nx - 1) s += pw[1] * (px1 - s1[sl][l + 1]);
+      if (T.j > 0) s += pw[2] * (px1 - s1[sl][l - RX2]);
+      if (T.j < ny - 1) s += pw[3] * (px1 - s1[sl][l + RX2]);
+      if (k2 > 0) s += pw[4] * (px1 - px1m);
+      if (k2 < nz - 1) s += pw[5] * (px1 - x1own);
+      const R x2 = px1 + om2 * recip(pdg) * (pb - s);
+      xo[(long)T.i + (long)nx * T.j + pl * k2] = x2;
+      acc += (double)pb * (double)x2;
+    }
+    px1m = px1;
+    px1 = x1own;
+    pdg = dgo;
+    pb = bo;
+    pin = ino;
+#pragma unroll
+    for (int f = 0; f < 6; ++f) pw[f] = w[f];
+  }
+  if (part) {
+    __shared__ double sh[16];
+    const double sacc = block_reduce<0>(acc, sh);
+    if (tid == 0) part[blockIdx.x] = sacc;
+  }
+}
+
 // bc = R (b - K0 x): fine cells marched like the sweeps; the 2x2 in-plane
 // sum goes through LDS, the pair of planes is summed in a register, and the
 // thread at the even corner of each 2x2(x2) group writes the coarse value.
@@ -492,10 +713,10 @@ struct Launch {
   int ntx, nty, kz, nblocks;
 };
 
-Launch plan(int nx, int ny, int nz, int target = TCF_FINE_BLOCKS) {
+Launch plan(int nx, int ny, int nz, int target = TCF_FINE_BLOCKS, int ty = FY) {
   Launch L;
   L.ntx = (nx + FX - 1) / FX;
-  L.nty = (ny + FY - 1) / FY;
+  L.nty = (ny + ty - 1) / ty;
   const int cols = L.ntx * L.nty;
   // aim for >= target blocks (TCF_FINE_BLOCKS: two full rounds of the two
   // blocks per CU that most of these kernels' register counts allow) with
@@ -624,6 +845,21 @@ int fine_smooth(hipStream_t s, int dim, const Fine<R>& F, double omega, const R*
       hipLaunchKernelGGL((k0_smooth<R, 2, false>), dim3(L.nblocks), dim3(FX, FY), 0, s, op, L.kz, L.ntx, L.nty,
                          R(omega), b, x, xo, e, cnx, cny, R(omc), part, iflag);
   }
+  return L.nblocks;
+}
+
+// Both post-smoothing sweeps (the first with the coarse correction) in one
+// pass: FP32, 3-D.
+int fine_smooth2(hipStream_t s, const Fine<float>& F, double om1, double om2, const float* b, const float* x,
+                 float* xo, const float* e, int cnx, int cny, double omc, double* part, const int* iflag) {
+  const Launch L = plan(F.nx, F.ny, F.nz, TCF_FINE_BLOCKS * FY / S2Y, S2Y);
+  const Op0<float> op = op_of(F);
+  if (e)
+    hipLaunchKernelGGL((k0_smooth2<float, true, S2Y>), dim3(L.nblocks), dim3(FX, S2Y), 0, s, op, L.kz, L.ntx, L.nty,
+                       float(om1), float(om2), b, x, xo, e, cnx, cny, float(omc), part, iflag);
+  else
+    hipLaunchKernelGGL((k0_smooth2<float, false, S2Y>), dim3(L.nblocks), dim3(FX, S2Y), 0, s, op, L.kz, L.ntx, L.nty,
+                       float(om1), float(om2), b, x, xo, e, cnx, cny, float(omc), part, iflag);
   return L.nblocks;
 }
 

@@ -43,6 +43,11 @@ constexpr int kCoarseSweeps = 30;
 #define TCF_REFINE_SAFETY 0.5
 #endif
 constexpr double kRefineSafety = TCF_REFINE_SAFETY;
+// the two finest-level post-smoothing sweeps as one pass (FP32, 3-D)
+#ifndef TCF_FUSE_POST
+#define TCF_FUSE_POST 1
+#endif
+constexpr bool kFusePost = TCF_FUSE_POST != 0;
 // levels of at most this many cells (and everything below them) run as one
 // block (the coarse tail of the V-cycle)
 #ifndef TCF_MG_TAIL_CELLS
@@ -190,9 +195,9 @@ struct tcf_grid {
 namespace {
 
 enum Family { FAM_TRANSPORT = 0, FAM_GEOMETRY, FAM_PREDICTOR, FAM_SMOOTH0, FAM_SPMV, FAM_RESID64, FAM_PROJECT,
-              FAM_SPECIES, FAM_UPDATE, FAM_N };
+              FAM_SPECIES, FAM_UPDATE, FAM_SMOOTH2, FAM_N };
 const char* kFamilyNames[FAM_N] = {"transport", "geometry", "predictor", "smooth", "spmv",
-                                   "resid64", "project", "species", "update"};
+                                   "resid64", "project", "species", "update", "smooth2"};
 constexpr size_t kProfPairs = 512;
 
 hipError_t prof_flush(tcf_grid* g) {
@@ -608,8 +613,8 @@ struct FromR64 {
 };
 
 template <class R>
-void vcycle(tcf_grid* g, Fields<R>& F, size_t l, const R* b, R* out, R* tmp, double* part, bool first_done, int* np,
-            FromR64* f64 = nullptr) {
+R* vcycle(tcf_grid* g, Fields<R>& F, size_t l, const R* b, R* out, R* tmp, double* part, bool first_done, int* np,
+          FromR64* f64 = nullptr) {
   hipStream_t s = g->stream;
   const int dim = g->D.dim;
   const int nu = g->cfg.mg_nu;
@@ -622,7 +627,7 @@ void vcycle(tcf_grid* g, Fields<R>& F, size_t l, const R* b, R* out, R* tmp, dou
     if (F.cinv) coarse_apply<R>(s, (int)L.n(), F.cinv, b, out, g->iflag);
     else mg_coarse_solve<R>(s, dim, Lc, b, out, kCoarseSweeps, jacobi_omega(dim), g->iflag);
     if (part) *np = dot_partials<R>(s, L.n(), b, out, part);
-    return;
+    return out;
   }
   R* bufs[2] = {tmp, out};
   Level<R>& C = F.lv[l + 1];
@@ -649,6 +654,18 @@ void vcycle(tcf_grid* g, Fields<R>& F, size_t l, const R* b, R* out, R* tmp, dou
     const bool cfirst = l + 2 < F.lv.size();
     fine_resid_restrict<R>(s, dim, Fd, b, cur, C.b, C.wdiag, cfirst ? C.x2 : nullptr, wpre(0), g->iflag);
     vcycle<R>(g, F, 1, C.b, C.x, C.x2, nullptr, cfirst, nullptr);
+    if constexpr (std::is_same<R, float>::value) {
+      if (kFusePost && dim == 3 && nu == 2) {
+        // both post-sweeps in one pass; it cannot write over its input, so
+        // the result lands in the other buffer
+        Prof pr(g, FAM_SMOOTH2);
+        R* dst = bufs[w & 1];
+        const int n = fine_smooth2(s, Fd, wpost(0), wpost(1), b, cur, dst, C.x, C.nx, C.ny, kOmegaC, part,
+                                   g->iflag);
+        if (np) *np = n;
+        return dst;
+      }
+    }
     int n = fine_smooth<R>(s, dim, Fd, wpost(0), b, cur, bufs[w & 1], C.x, C.nx, C.ny, kOmegaC,
                            nu == 1 ? part : nullptr, g->iflag);
     ++w;
@@ -658,7 +675,7 @@ void vcycle(tcf_grid* g, Fields<R>& F, size_t l, const R* b, R* out, R* tmp, dou
                          k == nu - 1 ? part : nullptr, g->iflag);
     }
     if (np) *np = n;
-    return;
+    return out;
   }
   long tail_lds = 0;
   for (size_t q = l; q < F.lv.size(); ++q) tail_lds += 3 * F.lv[q].n();
@@ -678,7 +695,7 @@ void vcycle(tcf_grid* g, Fields<R>& F, size_t l, const R* b, R* out, R* tmp, dou
       T.wpost[k] = wpost(k);
     }
     mg_tail<R>(s, dim, T, g->iflag);
-    return;
+    return out;
   }
   int w = 0;  // next write goes to bufs[w & 1]
   if (!first_done) mg_smooth_first<R>(s, L, b, bufs[w & 1], wpre(0), g->iflag);
@@ -693,6 +710,7 @@ void vcycle(tcf_grid* g, Fields<R>& F, size_t l, const R* b, R* out, R* tmp, dou
   ++w;
   for (int k = 1; k < nu; ++k, ++w)
     mg_smooth<R>(s, dim, L, b, bufs[(w - 1) & 1], bufs[w & 1], wpost(k), nullptr, g->iflag);
+  return out;
 }
 
 // PCG iterations on K x = rhs with r holding the initial residual and the
@@ -722,7 +740,7 @@ tcf_status pcg_iterate(tcf_grid* g, Fields<R>& F, R* x, R* r, int maxit, int kin
   const double wj = sweep_omega(dim, g->cfg.mg_nu, 0);  // first pre-smoothing sweep, fused into the update
   *converged = false;
   int np = 0;
-  vcycle<R>(g, F, 0, r, F.z, F.z2, g->part[0], false, &np, f64);
+  R* z = vcycle<R>(g, F, 0, r, F.z, F.z2, g->part[0], false, &np, f64);
   if (f64) finalize(s, f64->part, f64->np, g->scal, g->iflag, F_BB, 0, f64->tau2);
   finalize(s, g->part[0], np, g->scal, g->iflag, F_RZ_FIRST, 0, 0.0);
   R* dcur = F.d;
@@ -733,7 +751,7 @@ tcf_status pcg_iterate(tcf_grid* g, Fields<R>& F, R* x, R* r, int maxit, int kin
     last = it;
     {
       Prof pr(g, FAM_SPMV);
-      np = fine_spmv_upd<R>(s, dim, Fd, F.z, dcur, dnext, g->scal, it == 1 ? 1 : 0, g->part[0], g->iflag);
+      np = fine_spmv_upd<R>(s, dim, Fd, z, dcur, dnext, g->scal, it == 1 ? 1 : 0, g->part[0], g->iflag);
     }
     finalize(s, g->part[0], np, g->scal, g->iflag, F_ALPHA, 0, 0.0);
     std::swap(dcur, dnext);
@@ -748,7 +766,7 @@ tcf_status pcg_iterate(tcf_grid* g, Fields<R>& F, R* x, R* r, int maxit, int kin
       HIPCHECK(wait_back(g));
       if (g->hflag[I_DONE]) break;
     }
-    vcycle<R>(g, F, 0, r, F.z, F.z2, g->part[0], true, &np);
+    z = vcycle<R>(g, F, 0, r, F.z, F.z2, g->part[0], true, &np);
     finalize(s, g->part[0], np, g->scal, g->iflag, F_RZ, 0, 0.0);
     HIPCHECK(wait_back(g));
     if (g->hflag[I_DONE]) break;

@@ -164,6 +164,10 @@ void fine_smooth_first(hipStream_t s, int dim, const Fine<R>& F, double omega, c
 template <class R>
 int fine_smooth(hipStream_t s, int dim, const Fine<R>& F, double omega, const R* b, const R* x, R* xo, const R* e,
                 int cnx, int cny, double omc, double* part, const int* iflag);
+// two sweeps (om1 then om2; the first on x + omc P e when e is given) in one
+// pass, FP32 3-D; xo must not alias x
+int fine_smooth2(hipStream_t s, const Fine<float>& F, double om1, double om2, const float* b, const float* x,
+                 float* xo, const float* e, int cnx, int cny, double omc, double* part, const int* iflag);
 template <class R>
 // bc = R (b - K0 x); with x1c also x1c = om0 wdc bc (the coarse level's first sweep)
 void fine_resid_restrict(hipStream_t s, int dim, const Fine<R>& F, const R* b, const R* x, R* bc, const R* wdc, R* x1c,
