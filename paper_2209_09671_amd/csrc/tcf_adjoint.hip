@@ -209,14 +209,36 @@ __global__ __launch_bounds__(256) void ka_rhs_face(KParams P, const double* __re
 }
 
 // ===========================================================================
-// (S4-S5)^T: predictor for component D on interior faces (scatter).
+// (S4-S5)^T: the predictor on interior faces.
+// ---------------------------------------------------------------------------
+// The predictor's adjoint in two parts, with the scattered sums of the flux
+// terms gathered in LDS first (one kernel doing all of it per face issued
+// ~50 FP64 atomics per face at 176 VGPRs, two waves per SIMD).
+//
+// ka_pred_face<DIM, D>: per face, the terms that do not depend on a flux
+// direction: the direct term u*_f = u_f + ..., the CSF force (sigma kappa,
+// M and the alpha difference), and the face density 1/rho_f (whose
+// derivative needs the forward viscous term, recomputed here).
+
+// Box over a block's faces (one LDS array of doubles): origin and extent in
+// the virtual index space of the target array (ghost positions included).
+struct Box {
+  int o[3], e[3];
+  __device__ int n() const { return e[0] * e[1] * e[2]; }
+  __device__ int at(int x, int y, int z) const { return ((z - o[2]) * e[1] + (y - o[1])) * e[0] + (x - o[0]); }
+  __device__ void pos(int q, int& x, int& y, int& z) const {
+    x = o[0] + q % e[0];
+    y = o[1] + (q / e[0]) % e[1];
+    z = o[2] + q / (e[0] * e[1]);
+  }
+};
+
 template <int DIM, int D>
-__global__ __launch_bounds__(256) void ka_predictor(KParams P, const double* __restrict__ a,
+__global__ __launch_bounds__(256) void ka_pred_face(KParams P, const double* __restrict__ a,
                                                     const double* __restrict__ sk, const double* __restrict__ M,
                                                     const double* __restrict__ u, const double* __restrict__ v,
                                                     const double* __restrict__ w, const double* __restrict__ usb,
-                                                    double* __restrict__ ubar, double* __restrict__ vbar,
-                                                    double* __restrict__ wbar, double* __restrict__ abar,
+                                                    double* __restrict__ udb, double* __restrict__ abar,
                                                     double* __restrict__ skbar, double* __restrict__ Mbar) {
   const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
   const int nx = P.nx, ny = P.ny, nz = P.nz;
@@ -229,35 +251,30 @@ __global__ __launch_bounds__(256) void ka_predictor(KParams P, const double* __r
   const double ob = usb[fo];
   if (ob == 0.0) return;
   const double* vel[3] = {u, v, w};
-  double* velb[3] = {ubar, vbar, wbar};
   const double* ud = vel[D];
-  double* udb = velb[D];
-  const double eps = P.weno_eps, ih = P.ih, dt = P.dt;
+  const double ih = P.ih, dt = P.dt;
   int L[3] = {i, j, k};
   L[D] -= 1;
   const long cL = cidx(L[0], L[1], L[2], nx, ny), cR = cidx(i, j, k, nx, ny);
-  // ---- forward recompute of the face quantities
   const double aL = a[cL], aR = a[cR];
   const double fst = 0.5 * (sk[cL] + sk[cR]) * (aR - aL) * ih + 0.5 * (M[cL] + M[cR]);
   const double rhof = 0.5 * (mix1(aL, P.rho1, P.rho2) + mix1(aR, P.rho1, P.rho2));
-  // viscous term needs a forward pass
+  // forward viscous term (the same sums as the forward predictor's)
+  auto udv = [&](int e, int m) {  // component D at the face offset by m along e
+    int o[3] = {i, j, k};
+    o[e] += m;
+    double sg;
+    const long q = v_idx<D, DIM>(o[0], o[1], o[2], nx, ny, nz, sg);
+    return sg * ud[q];
+  };
   double visc = 0.0;
   for (int e = 0; e < DIM; ++e) {
-    double q[7];
-    double qs[7];
-    long qi[7];
-    for (int m = 0; m < 7; ++m) {
-      int o[3] = {0, 0, 0};
-      o[e] = m - 3;
-      if (D == 0) qi[m] = v_idx<0, DIM>(i + o[0], j + o[1], k + o[2], nx, ny, nz, qs[m]);
-      else if (D == 1) qi[m] = v_idx<1, DIM>(i + o[0], j + o[1], k + o[2], nx, ny, nz, qs[m]);
-      else qi[m] = v_idx<2, DIM>(i + o[0], j + o[1], k + o[2], nx, ny, nz, qs[m]);
-      q[m] = qs[m] * ud[qi[m]];
-    }
     if (e == D) {
       const double mL = mix1(aL, P.mu1, P.mu2), mR = mix1(aR, P.mu1, P.mu2);
-      visc += (2.0 * mR * (q[4] - q[3]) * ih - 2.0 * mL * (q[3] - q[2]) * ih) * ih;
+      const double q2 = udv(e, -1), q3 = udv(e, 0), q4 = udv(e, 1);
+      visc += (2.0 * mR * (q4 - q3) * ih - 2.0 * mL * (q3 - q2) * ih) * ih;
     } else {
+      const double* ve = vel[e];
       double tau[2];
       for (int side = 0; side < 2; ++side) {
         const int ef = id[e] + side;
@@ -266,7 +283,6 @@ __global__ __launch_bounds__(256) void ka_predictor(KParams P, const double* __r
         pR[e] = ef;
         double sL, sR;
         long iL, iR;
-        const double* ve = vel[e];
         if (e == 0) { iL = v_idx<0, DIM>(pL[0], pL[1], pL[2], nx, ny, nz, sL); iR = v_idx<0, DIM>(pR[0], pR[1], pR[2], nx, ny, nz, sR); }
         else if (e == 1) { iL = v_idx<1, DIM>(pL[0], pL[1], pL[2], nx, ny, nz, sL); iR = v_idx<1, DIM>(pR[0], pR[1], pR[2], nx, ny, nz, sR); }
         else { iL = v_idx<2, DIM>(pL[0], pL[1], pL[2], nx, ny, nz, sL); iR = v_idx<2, DIM>(pR[0], pR[1], pR[2], nx, ny, nz, sR); }
@@ -277,41 +293,102 @@ __global__ __launch_bounds__(256) void ka_predictor(KParams P, const double* __r
                                   mix1(a[a_idx<DIM>(c2[0], c2[1], c2[2], nx, ny, nz)], P.mu1, P.mu2) +
                                   mix1(a[a_idx<DIM>(c3[0], c3[1], c3[2], nx, ny, nz)], P.mu1, P.mu2) +
                                   mix1(a[a_idx<DIM>(c4[0], c4[1], c4[2], nx, ny, nz)], P.mu1, P.mu2));
-        tau[side] = me * ((q[3 + side] - q[2 + side]) * ih + (veR - veL) * ih);
+        tau[side] = me * ((udv(e, side) - udv(e, side - 1)) * ih + (veR - veL) * ih);
       }
       visc += (tau[1] - tau[0]) * ih;
     }
   }
-  // ---- reverse
-  aadd(&udb[fo], ob);  // direct term u*_f = u_f + ...
-  const double convb = -dt * ob;
-  const double viscb = dt * ob / rhof, fstb = dt * ob / rhof;
+  aadd(&udb[fo], ob);  // direct term
+  const double fstb = dt * ob / rhof;
   const double rhofb = -dt * ob * (visc + fst) / (rhof * rhof);
   double aLb = rhofb * 0.5 * (P.rho2 - P.rho1) * dclamp(aL);
   double aRb = rhofb * 0.5 * (P.rho2 - P.rho1) * dclamp(aR);
-  // CSF force
   aadd(&skbar[cL], fstb * 0.5 * (aR - aL) * ih);
   aadd(&skbar[cR], fstb * 0.5 * (aR - aL) * ih);
   aRb += fstb * 0.5 * (sk[cL] + sk[cR]) * ih;
   aLb -= fstb * 0.5 * (sk[cL] + sk[cR]) * ih;
   aadd(&Mbar[cL], 0.5 * fstb);
   aadd(&Mbar[cR], 0.5 * fstb);
-  const double dmu = P.mu2 - P.mu1;
-  for (int e = 0; e < DIM; ++e) {
-    double q[7], qs[7], qb[7];
-    long qi[7];
-    for (int m = 0; m < 7; ++m) {
-      int o[3] = {0, 0, 0};
-      o[e] = m - 3;
-      if (D == 0) qi[m] = v_idx<0, DIM>(i + o[0], j + o[1], k + o[2], nx, ny, nz, qs[m]);
-      else if (D == 1) qi[m] = v_idx<1, DIM>(i + o[0], j + o[1], k + o[2], nx, ny, nz, qs[m]);
-      else qi[m] = v_idx<2, DIM>(i + o[0], j + o[1], k + o[2], nx, ny, nz, qs[m]);
-      q[m] = qs[m] * ud[qi[m]];
-      qb[m] = 0.0;
-    }
+  aadd(&abar[cL], aLb);
+  aadd(&abar[cR], aRb);
+}
+
+// ka_pred_dir<DIM, D, E>: per face of component D, the reverse of its
+// convective and viscous fluxes along axis E: the WENO5 gradients of the
+// advected values (the seven D-faces along E), the advecting velocity of
+// component E (E != D) and the viscosities.  A block is 64 faces along x
+// times 4 along y (E = x) or 8 along E (E = y, z); the contributions to the
+// D-faces, the E-faces and the cells are gathered in LDS boxes over the
+// block's stencil (virtual positions, ghosts included) and sent to memory
+// with one global atomic per box entry through the ghost rules.
+template <int DIM, int D, int E>
+__global__ __launch_bounds__(256) void ka_pred_dir(KParams P, const double* __restrict__ a,
+                                                   const double* __restrict__ ud, const double* __restrict__ ue,
+                                                   const double* __restrict__ usb, double* __restrict__ udb,
+                                                   double* __restrict__ ueb, double* __restrict__ abar) {
+  constexpr int BYE = E == 0 ? 4 : 4;  // threads across the x rows
+  constexpr int NB = 64 * BYE;
+  // the block's faces: x in [x0, x0+64), and 4 along y (E = 0, 1) or z (E = 2)
+  const int x0 = blockIdx.x * 64;
+  const int tx = threadIdx.x, ty = threadIdx.y, tid = tx + 64 * ty;
+  const int nx = P.nx, ny = P.ny, nz = P.nz;
+  int f0[3], fe[3];  // block's face range (component D index space): origin, extent
+  f0[0] = x0;
+  fe[0] = 64;
+  if (E == 2) {
+    f0[1] = blockIdx.y; fe[1] = 1;
+    f0[2] = blockIdx.z * BYE; fe[2] = BYE;
+  } else {
+    f0[1] = blockIdx.y * BYE; fe[1] = BYE;
+    f0[2] = blockIdx.z; fe[2] = 1;
+  }
+  // boxes: D-faces extended by 3 along E; E-faces extended by -1 along D and
+  // +1 along E; cells extended by -1 along D and -1..+1 along E
+  Box bu, bv, bc;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    bu.o[d] = f0[d] - (d == E ? 3 : 0);
+    bu.e[d] = fe[d] + (d == E ? 6 : 0);
+    bv.o[d] = f0[d] - (d == D ? 1 : 0);
+    bv.e[d] = fe[d] + (d == D ? 1 : 0) + (d == E ? 1 : 0);
+    bc.o[d] = f0[d] - (d == D ? 1 : 0) - (d == E && E != D ? 1 : 0);
+    bc.e[d] = fe[d] + (d == D ? 1 : 0) + (d == E && E != D ? 2 : 0);
+  }
+  // sizes: bu <= 70 x 4 or 64 x 10; bv, bc <= 66 x 6 x 2
+  __shared__ double su[70 * 10], sv[66 * 6 * 2], sc[66 * 6 * 2];
+  const int nu = bu.n(), nvv = E != D ? bv.n() : 0, ncc = bc.n();
+  for (int q = tid; q < nu; q += NB) su[q] = 0.0;
+  for (int q = tid; q < nvv; q += NB) sv[q] = 0.0;
+  for (int q = tid; q < ncc; q += NB) sc[q] = 0.0;
+  __syncthreads();
+  const int i = x0 + tx, j = E == 2 ? f0[1] : f0[1] + ty, k = E == 2 ? f0[2] + ty : f0[2];
+  const int id[3] = {i, j, k};
+  const int fnx = nx + (D == 0), fny = ny + (D == 1), fnz = (DIM == 3 ? nz : 1) + (D == 2);
+  const int nD = D == 0 ? nx : (D == 1 ? ny : nz);
+  const bool act = i < fnx && j < fny && k < fnz && id[D] > 0 && id[D] < nD;
+  const double ob = act ? usb[fidx<D>(i, j, k, nx, ny)] : 0.0;
+  if (act && ob != 0.0) {
+    const double eps = P.weno_eps, ih = P.ih, dt = P.dt;
+    int L[3] = {i, j, k};
+    L[D] -= 1;
+    const long cL = cidx(L[0], L[1], L[2], nx, ny), cR = cidx(i, j, k, nx, ny);
+    const double aL = a[cL], aR = a[cR];
+    const double rhof = 0.5 * (mix1(aL, P.rho1, P.rho2) + mix1(aR, P.rho1, P.rho2));
+    const double convb = -dt * ob, viscb = dt * ob / rhof;
     const double Fhib = convb * ih, Flob = -convb * ih;
     const double thib = viscb * ih, tlob = -viscb * ih;
-    if (e == D) {
+    const double dmu = P.mu2 - P.mu1;
+    // the seven D-faces along E (virtual offsets -3..3) and their values
+    double q[7], qb[7];
+    for (int m = 0; m < 7; ++m) {
+      int o[3] = {i, j, k};
+      o[E] += m - 3;
+      double sg;
+      const long qi = v_idx<D, DIM>(o[0], o[1], o[2], nx, ny, nz, sg);
+      q[m] = sg * ud[qi];
+      qb[m] = 0.0;
+    }
+    if (E == D) {
       const double Ulo = 0.5 * (q[2] + q[3]), Uhi = 0.5 * (q[3] + q[4]);
       double g[6];
       double W = upwind_g(q, Ulo, eps, g);
@@ -325,41 +402,36 @@ __global__ __launch_bounds__(256) void ka_predictor(KParams P, const double* __r
       qb[3] += 0.5 * Ub;
       qb[4] += 0.5 * Ub;
       const double mL = mix1(aL, P.mu1, P.mu2), mR = mix1(aR, P.mu1, P.mu2);
-      // tlo = 2 mL (q3 - q2) ih ; thi = 2 mR (q4 - q3) ih
-      aLb += tlob * 2.0 * (q[3] - q[2]) * ih * dmu * dclamp(aL);
-      aRb += thib * 2.0 * (q[4] - q[3]) * ih * dmu * dclamp(aR);
+      atomicAdd(&sc[bc.at(L[0], L[1], L[2])], tlob * 2.0 * (q[3] - q[2]) * ih * dmu * dclamp(aL));
+      atomicAdd(&sc[bc.at(i, j, k)], thib * 2.0 * (q[4] - q[3]) * ih * dmu * dclamp(aR));
       qb[3] += tlob * 2.0 * mL * ih;
       qb[2] -= tlob * 2.0 * mL * ih;
       qb[4] += thib * 2.0 * mR * ih;
       qb[3] -= thib * 2.0 * mR * ih;
     } else {
-      double* veb = velb[e];
-      const double* ve = vel[e];
       for (int side = 0; side < 2; ++side) {
         const double Fb = side ? Fhib : Flob, tb = side ? thib : tlob;
-        const int ef = id[e] + side;
+        const int ef = id[E] + side;
         int pL[3] = {L[0], L[1], L[2]}, pR[3] = {i, j, k};
-        pL[e] = ef;
-        pR[e] = ef;
+        pL[E] = ef;
+        pR[E] = ef;
         double sL, sR;
-        long iL, iR;
-        if (e == 0) { iL = v_idx<0, DIM>(pL[0], pL[1], pL[2], nx, ny, nz, sL); iR = v_idx<0, DIM>(pR[0], pR[1], pR[2], nx, ny, nz, sR); }
-        else if (e == 1) { iL = v_idx<1, DIM>(pL[0], pL[1], pL[2], nx, ny, nz, sL); iR = v_idx<1, DIM>(pR[0], pR[1], pR[2], nx, ny, nz, sR); }
-        else { iL = v_idx<2, DIM>(pL[0], pL[1], pL[2], nx, ny, nz, sL); iR = v_idx<2, DIM>(pR[0], pR[1], pR[2], nx, ny, nz, sR); }
-        const double veL = sL * ve[iL], veR = sR * ve[iR];
+        const long iL = v_idx<E, DIM>(pL[0], pL[1], pL[2], nx, ny, nz, sL);
+        const long iR = v_idx<E, DIM>(pR[0], pR[1], pR[2], nx, ny, nz, sR);
+        const double veL = sL * ue[iL], veR = sR * ue[iR];
         const double Vb = 0.5 * (veL + veR);
         double g[6];
         const double W = upwind_g(q + side, Vb, eps, g);
-        double Vbb = Fb * W;
+        const double Vbb = Fb * W;
         for (int m = 0; m < 6; ++m) qb[m + side] += Fb * Vb * g[m];
         double veLb = 0.5 * Vbb, veRb = 0.5 * Vbb;
         int cc[4][3] = {{L[0], L[1], L[2]}, {i, j, k}, {L[0], L[1], L[2]}, {i, j, k}};
-        cc[0][e] = ef - 1; cc[1][e] = ef - 1; cc[2][e] = ef; cc[3][e] = ef;
-        long ci[4];
-        double me = 0.0;
+        cc[0][E] = ef - 1; cc[1][E] = ef - 1; cc[2][E] = ef; cc[3][E] = ef;
+        double me = 0.0, da[4];
         for (int q4 = 0; q4 < 4; ++q4) {
-          ci[q4] = a_idx<DIM>(cc[q4][0], cc[q4][1], cc[q4][2], nx, ny, nz);
-          me += 0.25 * mix1(a[ci[q4]], P.mu1, P.mu2);
+          const double av = a[a_idx<DIM>(cc[q4][0], cc[q4][1], cc[q4][2], nx, ny, nz)];
+          me += 0.25 * mix1(av, P.mu1, P.mu2);
+          da[q4] = dclamp(av);
         }
         const double dud = (q[3 + side] - q[2 + side]) * ih, dve = (veR - veL) * ih;
         const double meb = tb * (dud + dve);
@@ -368,15 +440,45 @@ __global__ __launch_bounds__(256) void ka_predictor(KParams P, const double* __r
         qb[2 + side] -= dudb * ih;
         veRb += dveb * ih;
         veLb -= dveb * ih;
-        for (int q4 = 0; q4 < 4; ++q4) aadd(&abar[ci[q4]], 0.25 * meb * dmu * dclamp(a[ci[q4]]));
-        aadd(&veb[iL], sL * veLb);
-        aadd(&veb[iR], sR * veRb);
+        for (int q4 = 0; q4 < 4; ++q4)
+          atomicAdd(&sc[bc.at(cc[q4][0], cc[q4][1], cc[q4][2])], 0.25 * meb * dmu * da[q4]);
+        atomicAdd(&sv[bv.at(pL[0], pL[1], pL[2])], veLb);
+        atomicAdd(&sv[bv.at(pR[0], pR[1], pR[2])], veRb);
       }
     }
-    for (int m = 0; m < 7; ++m) aadd(&udb[qi[m]], qs[m] * qb[m]);
+    for (int m = 0; m < 7; ++m) {
+      int o[3] = {i, j, k};
+      o[E] += m - 3;
+      atomicAdd(&su[bu.at(o[0], o[1], o[2])], qb[m]);
+    }
   }
-  aadd(&abar[cL], aLb);
-  aadd(&abar[cR], aRb);
+  __syncthreads();
+  // flush through the ghost rules: D-faces and E-faces odd, cells even
+  for (int q = tid; q < nu; q += NB) {
+    const double vq = su[q];
+    if (vq == 0.0) continue;
+    int x, y, z;
+    bu.pos(q, x, y, z);
+    double sg;
+    const long g = v_idx<D, DIM>(x, y, z, nx, ny, nz, sg);
+    atomicAdd(&udb[g], sg * vq);
+  }
+  for (int q = tid; q < nvv; q += NB) {
+    const double vq = sv[q];
+    if (vq == 0.0) continue;
+    int x, y, z;
+    bv.pos(q, x, y, z);
+    double sg;
+    const long g = v_idx<E, DIM>(x, y, z, nx, ny, nz, sg);
+    atomicAdd(&ueb[g], sg * vq);
+  }
+  for (int q = tid; q < ncc; q += NB) {
+    const double vq = sc[q];
+    if (vq == 0.0) continue;
+    int x, y, z;
+    bc.pos(q, x, y, z);
+    atomicAdd(&abar[a_idx<DIM>(x, y, z, nx, ny, nz)], vq);
+  }
 }
 
 // ===========================================================================
@@ -517,59 +619,102 @@ __global__ __launch_bounds__(256) void ka_geom_ext(KParams P, const double* __re
 // ===========================================================================
 // S1^T: one RK stage G(a, T) = (a + dt La(a), T + dt LT(a, T)) transposed,
 // applied to w = (wa, wT) and accumulated into (ab, Tb) and the face-velocity
-// adjoints.  Face part: advective fluxes and conduction across interior faces.
-template <int DIM, int D>
-__global__ __launch_bounds__(256) void ka_transport_face(KParams P, const double* __restrict__ a,
-                                                         const double* __restrict__ T, const double* __restrict__ uD,
-                                                         const double* __restrict__ wa,
-                                                         const double* __restrict__ wT, double* __restrict__ ab,
-                                                         double* __restrict__ Tb, double* __restrict__ uDb) {
-  const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
+// adjoints.  Face part: advective fluxes and conduction across interior
+// faces.  The scattered sums are gathered per block first: a block is
+// 64 x BE faces, 64 along x and BE (4 for D = x, else 8) along the next
+// axis (y for D = x and y; z for D = z, one y-row per block), and
+// every contribution of its faces to a cell of alpha or T (stencil cells
+// f-3..f+2 along D, ghosts included, and the two cells of the conduction
+// term) is added into an LDS box over those cells (LDS FP64 atomics); then
+// each box entry goes to memory with one global atomic, through the ghost
+// rule of its cell (even reflection; the sign of a Dirichlet T ghost).  This
+// replaces 16 global atomics per face by (BE + 5) / BE or 69 / 64 per cell.
+template <int DIM, int D, int BE>
+__global__ __launch_bounds__(64 * BE) void ka_transport_face_g(KParams P, const double* __restrict__ a,
+                                                               const double* __restrict__ T,
+                                                               const double* __restrict__ uD,
+                                                               const double* __restrict__ wa,
+                                                               const double* __restrict__ wT,
+                                                               double* __restrict__ ab, double* __restrict__ Tb,
+                                                               double* __restrict__ uDb) {
+  // box: along D the cells f0-3 .. f0+NF+1 of the block's faces f0 .. f0+NF-1
+  constexpr int NF = D == 0 ? 64 : BE;          // faces of the block along D
+  constexpr int NV = NF + 5;                    // box cells along D
+  constexpr int NW = D == 0 ? BE : 64;          // box width across D
+  __shared__ double bxa[NV * NW], bxt[NV * NW];
+  const int tx = threadIdx.x, ty = threadIdx.y, tid = tx + 64 * ty;
   const int nx = P.nx, ny = P.ny, nz = P.nz;
-  const int fnx = nx + (D == 0), fny = ny + (D == 1);
-  if (i >= fnx || j >= fny) return;
+  for (int q = tid; q < NV * NW; q += 64 * BE) {
+    bxa[q] = 0.0;
+    bxt[q] = 0.0;
+  }
+  int i, j, k, f0, w;  // this thread's face; first face of the block along D; its column across D
+  if (D == 0) { i = blockIdx.x * 64 + tx; j = blockIdx.y * BE + ty; k = blockIdx.z; f0 = blockIdx.x * 64; w = ty; }
+  else if (D == 1) { i = blockIdx.x * 64 + tx; j = blockIdx.y * BE + ty; k = blockIdx.z; f0 = blockIdx.y * BE; w = tx; }
+  else { i = blockIdx.x * 64 + tx; j = blockIdx.y; k = blockIdx.z * BE + ty; f0 = blockIdx.z * BE; w = tx; }
   const int id[3] = {i, j, k};
   const int nD = D == 0 ? nx : (D == 1 ? ny : nz);
-  if (id[D] == 0 || id[D] == nD) return;
-  const long f = fidx<D>(i, j, k, nx, ny);
-  int L[3] = {i, j, k};
-  L[D] -= 1;
-  const long cL = cidx(L[0], L[1], L[2], nx, ny), cR = cidx(i, j, k, nx, ny);
-  const double ih = P.ih, dt = P.dt, eps = P.weno_eps;
-  // advective fluxes: La_L -= F/h, La_R += F/h (same for T)
-  const double Fab = dt * (wa[cR] - wa[cL]) * ih;
-  const double FTb = dt * (wT[cR] - wT[cL]) * ih;
-  const double uf = uD[f];
-  double qa[6], qt[6], sgt[6];
-  long ia[6], it[6];
-  for (int m = 0; m < 6; ++m) {
-    int o[3] = {i, j, k};
-    o[D] = id[D] - 3 + m;
-    ia[m] = a_idx<DIM>(o[0], o[1], o[2], nx, ny, nz);
-    qa[m] = a[ia[m]];
-    it[m] = t_idx<DIM>(o[0], o[1], o[2], P, sgt[m]);
-    qt[m] = T_at<DIM>(T, o[0], o[1], o[2], P);
+  const int fD = id[D];
+  // box index of the cell at position c along D (this thread's column across D)
+  auto bidx = [&](int c) { return D == 0 ? w * NV + (c - (f0 - 3)) : (c - (f0 - 3)) * NW + w; };
+  const bool inr = (D == 0 ? (i <= nx && j < ny) : (D == 1 ? (i < nx && j <= ny) : (i < nx && k <= nz))) &&
+                   (DIM == 3 || k == 0);
+  const bool act = inr && fD > 0 && fD < nD;
+  __syncthreads();
+  if (act) {
+    const long f = fidx<D>(i, j, k, nx, ny);
+    int L[3] = {i, j, k};
+    L[D] -= 1;
+    const long cL = cidx(L[0], L[1], L[2], nx, ny), cR = cidx(i, j, k, nx, ny);
+    const double ih = P.ih, dt = P.dt, eps = P.weno_eps;
+    const double Fab = dt * (wa[cR] - wa[cL]) * ih;
+    const double FTb = dt * (wT[cR] - wT[cL]) * ih;
+    const double uf = uD[f];
+    double qa[6], qt[6];
+    for (int m = 0; m < 6; ++m) {
+      int o[3] = {i, j, k};
+      o[D] = fD - 3 + m;
+      qa[m] = a[a_idx<DIM>(o[0], o[1], o[2], nx, ny, nz)];
+      qt[m] = T_at<DIM>(T, o[0], o[1], o[2], P);
+    }
+    double ga[6], gt[6];
+    const double Wa = upwind_g(qa, uf, eps, ga);
+    const double Wt = upwind_g(qt, uf, eps, gt);
+    uDb[f] += Fab * Wa + FTb * Wt;
+    for (int m = 0; m < 6; ++m) {
+      const int q = bidx(fD - 3 + m);
+      const double va = Fab * uf * ga[m], vt = FTb * uf * gt[m];
+      if (va != 0.0) atomicAdd(&bxa[q], va);
+      if (vt != 0.0) atomicAdd(&bxt[q], vt);
+    }
+    const double aL = a[cL], aR = a[cR];
+    const double rcL = mix1(aL, P.rhocp1, P.rhocp2), rcR = mix1(aR, P.rhocp1, P.rhocp2);
+    const double Phib = dt * (wT[cL] / rcL - wT[cR] / rcR);
+    const double lf = 0.5 * (mix1(aL, P.lam1, P.lam2) + mix1(aR, P.lam1, P.lam2));
+    const double ih2 = ih * ih;
+    const double dTf = (T[cR] - T[cL]) * ih2;
+    const double dl = P.lam2 - P.lam1;
+    atomicAdd(&bxt[bidx(fD)], Phib * lf * ih2);
+    atomicAdd(&bxt[bidx(fD - 1)], -Phib * lf * ih2);
+    atomicAdd(&bxa[bidx(fD - 1)], Phib * dTf * 0.5 * dl * dclamp(aL));
+    atomicAdd(&bxa[bidx(fD)], Phib * dTf * 0.5 * dl * dclamp(aR));
   }
-  double ga[6], gt[6];
-  const double Wa = upwind_g(qa, uf, eps, ga);
-  const double Wt = upwind_g(qt, uf, eps, gt);
-  uDb[f] += Fab * Wa + FTb * Wt;
-  for (int m = 0; m < 6; ++m) {
-    aadd(&ab[ia[m]], Fab * uf * ga[m]);
-    aadd(&Tb[it[m]], FTb * uf * gt[m] * sgt[m]);
+  __syncthreads();
+  // flush: one global atomic per box cell, through its ghost rule
+  for (int q = tid; q < NV * NW; q += 64 * BE) {
+    const double va = bxa[q], vt = bxt[q];
+    if (va == 0.0 && vt == 0.0) continue;
+    int c[3];
+    if (D == 0) { c[0] = f0 - 3 + q % NV; c[1] = blockIdx.y * BE + q / NV; c[2] = blockIdx.z; }
+    else if (D == 1) { c[0] = blockIdx.x * 64 + q % NW; c[1] = f0 - 3 + q / NW; c[2] = blockIdx.z; }
+    else { c[0] = blockIdx.x * 64 + q % NW; c[1] = blockIdx.y; c[2] = f0 - 3 + q / NW; }
+    if (va != 0.0) atomicAdd(&ab[a_idx<DIM>(c[0], c[1], c[2], nx, ny, nz)], va);
+    if (vt != 0.0) {
+      double sg;
+      const long it = t_idx<DIM>(c[0], c[1], c[2], P, sg);
+      atomicAdd(&Tb[it], vt * sg);
+    }
   }
-  // conduction: Phi = lambda_f (T_R - T_L)/h^2 ; cond_L += Phi, cond_R -= Phi
-  const double aL = a[cL], aR = a[cR];
-  const double rcL = mix1(aL, P.rhocp1, P.rhocp2), rcR = mix1(aR, P.rhocp1, P.rhocp2);
-  const double Phib = dt * (wT[cL] / rcL - wT[cR] / rcR);
-  const double lf = 0.5 * (mix1(aL, P.lam1, P.lam2) + mix1(aR, P.lam1, P.lam2));
-  const double ih2 = ih * ih;
-  aadd(&Tb[cR], Phib * lf * ih2);
-  aadd(&Tb[cL], -Phib * lf * ih2);
-  const double dTf = (T[cR] - T[cL]) * ih2;
-  const double dl = P.lam2 - P.lam1;
-  aadd(&ab[cL], Phib * dTf * 0.5 * dl * dclamp(aL));
-  aadd(&ab[cR], Phib * dTf * 0.5 * dl * dclamp(aR));
 }
 
 // Cell part: identity, wall conduction faces, rho c_p, heat source.
@@ -685,23 +830,47 @@ void adj_rhs(const KParams& P, hipStream_t s, const double* ubp, const double* v
   }
 }
 
+// the direction kernels of component D (its x, y and z fluxes)
+template <int DIM, int D, int E>
+void pred_dir(const KParams& P, hipStream_t s, const double* a, const double* const vel[3], double* const velb[3],
+              const double* usb, double* abar) {
+  const int fnx = P.nx + (D == 0), fny = P.ny + (D == 1), fnz = (DIM == 3 ? P.nz : 1) + (D == 2);
+  const dim3 g = E == 2 ? dim3((fnx + 63) / 64, fny, (fnz + 3) / 4) : dim3((fnx + 63) / 64, (fny + 3) / 4, fnz);
+  hipLaunchKernelGGL((ka_pred_dir<DIM, D, E>), g, dim3(64, 4), 0, s, P, a, vel[D], vel[E], usb, velb[D], velb[E],
+                     abar);
+}
+template <int DIM, int D>
+void pred_dirs(const KParams& P, hipStream_t s, const double* a, const double* const vel[3], double* const velb[3],
+               const double* usb, double* abar) {
+  pred_dir<DIM, D, 0>(P, s, a, vel, velb, usb, abar);
+  pred_dir<DIM, D, 1>(P, s, a, vel, velb, usb, abar);
+  if constexpr (DIM == 3) pred_dir<DIM, D, 2>(P, s, a, vel, velb, usb, abar);
+}
+
 void adj_predictor(const KParams& P, hipStream_t s, const double* a, const double* sk, const double* Mx,
                    const double* My, const double* Mz, const double* u, const double* v, const double* w,
                    const double* usb, const double* vsb, const double* wsb, double* ubar, double* vbar,
                    double* wbar, double* abar, double* skbar, double* Mxb, double* Myb, double* Mzb) {
   dim3 b(BX, BY);
+  const double* const vel[3] = {u, v, w};
+  double* const velb[3] = {ubar, vbar, wbar};
   if (P.dim == 3) {
-    hipLaunchKernelGGL((ka_predictor<3, 0>), grid_of(P.nx + 1, P.ny, P.nz), b, 0, s, P, a, sk, Mx, u, v, w, usb, ubar,
-                       vbar, wbar, abar, skbar, Mxb);
-    hipLaunchKernelGGL((ka_predictor<3, 1>), grid_of(P.nx, P.ny + 1, P.nz), b, 0, s, P, a, sk, My, u, v, w, vsb, ubar,
-                       vbar, wbar, abar, skbar, Myb);
-    hipLaunchKernelGGL((ka_predictor<3, 2>), grid_of(P.nx, P.ny, P.nz + 1), b, 0, s, P, a, sk, Mz, u, v, w, wsb, ubar,
-                       vbar, wbar, abar, skbar, Mzb);
+    hipLaunchKernelGGL((ka_pred_face<3, 0>), grid_of(P.nx + 1, P.ny, P.nz), b, 0, s, P, a, sk, Mx, u, v, w, usb, ubar,
+                       abar, skbar, Mxb);
+    hipLaunchKernelGGL((ka_pred_face<3, 1>), grid_of(P.nx, P.ny + 1, P.nz), b, 0, s, P, a, sk, My, u, v, w, vsb, vbar,
+                       abar, skbar, Myb);
+    hipLaunchKernelGGL((ka_pred_face<3, 2>), grid_of(P.nx, P.ny, P.nz + 1), b, 0, s, P, a, sk, Mz, u, v, w, wsb, wbar,
+                       abar, skbar, Mzb);
+    pred_dirs<3, 0>(P, s, a, vel, velb, usb, abar);
+    pred_dirs<3, 1>(P, s, a, vel, velb, vsb, abar);
+    pred_dirs<3, 2>(P, s, a, vel, velb, wsb, abar);
   } else {
-    hipLaunchKernelGGL((ka_predictor<2, 0>), grid_of(P.nx + 1, P.ny, 1), b, 0, s, P, a, sk, Mx, u, v, w, usb, ubar,
-                       vbar, wbar, abar, skbar, Mxb);
-    hipLaunchKernelGGL((ka_predictor<2, 1>), grid_of(P.nx, P.ny + 1, 1), b, 0, s, P, a, sk, My, u, v, w, vsb, ubar,
-                       vbar, wbar, abar, skbar, Myb);
+    hipLaunchKernelGGL((ka_pred_face<2, 0>), grid_of(P.nx + 1, P.ny, 1), b, 0, s, P, a, sk, Mx, u, v, w, usb, ubar,
+                       abar, skbar, Mxb);
+    hipLaunchKernelGGL((ka_pred_face<2, 1>), grid_of(P.nx, P.ny + 1, 1), b, 0, s, P, a, sk, My, u, v, w, vsb, vbar,
+                       abar, skbar, Myb);
+    pred_dirs<2, 0>(P, s, a, vel, velb, usb, abar);
+    pred_dirs<2, 1>(P, s, a, vel, velb, vsb, abar);
   }
 }
 
@@ -726,14 +895,20 @@ void adj_transport_stage(const KParams& P, hipStream_t s, const double* a, const
                          const double* v, const double* w, const double* wa, const double* wT, double* ab,
                          double* Tb, double* ub, double* vb, double* wb) {
   dim3 b(BX, BY);
+  const int gx0 = (P.nx + 1 + 63) / 64, gx = (P.nx + 63) / 64;
   if (P.dim == 3) {
-    hipLaunchKernelGGL((ka_transport_face<3, 0>), grid_of(P.nx + 1, P.ny, P.nz), b, 0, s, P, a, T, u, wa, wT, ab, Tb, ub);
-    hipLaunchKernelGGL((ka_transport_face<3, 1>), grid_of(P.nx, P.ny + 1, P.nz), b, 0, s, P, a, T, v, wa, wT, ab, Tb, vb);
-    hipLaunchKernelGGL((ka_transport_face<3, 2>), grid_of(P.nx, P.ny, P.nz + 1), b, 0, s, P, a, T, w, wa, wT, ab, Tb, wb);
+    hipLaunchKernelGGL((ka_transport_face_g<3, 0, 4>), dim3(gx0, (P.ny + 3) / 4, P.nz), dim3(64, 4), 0, s, P, a, T, u,
+                       wa, wT, ab, Tb, ub);
+    hipLaunchKernelGGL((ka_transport_face_g<3, 1, 8>), dim3(gx, (P.ny + 1 + 7) / 8, P.nz), dim3(64, 8), 0, s, P, a, T,
+                       v, wa, wT, ab, Tb, vb);
+    hipLaunchKernelGGL((ka_transport_face_g<3, 2, 8>), dim3(gx, P.ny, (P.nz + 1 + 7) / 8), dim3(64, 8), 0, s, P, a, T,
+                       w, wa, wT, ab, Tb, wb);
     hipLaunchKernelGGL((ka_transport_cell<3>), grid_of(P.nx, P.ny, P.nz), b, 0, s, P, a, T, wa, wT, ab, Tb);
   } else {
-    hipLaunchKernelGGL((ka_transport_face<2, 0>), grid_of(P.nx + 1, P.ny, 1), b, 0, s, P, a, T, u, wa, wT, ab, Tb, ub);
-    hipLaunchKernelGGL((ka_transport_face<2, 1>), grid_of(P.nx, P.ny + 1, 1), b, 0, s, P, a, T, v, wa, wT, ab, Tb, vb);
+    hipLaunchKernelGGL((ka_transport_face_g<2, 0, 4>), dim3(gx0, (P.ny + 3) / 4, 1), dim3(64, 4), 0, s, P, a, T, u, wa,
+                       wT, ab, Tb, ub);
+    hipLaunchKernelGGL((ka_transport_face_g<2, 1, 8>), dim3(gx, (P.ny + 1 + 7) / 8, 1), dim3(64, 8), 0, s, P, a, T, v,
+                       wa, wT, ab, Tb, vb);
     hipLaunchKernelGGL((ka_transport_cell<2>), grid_of(P.nx, P.ny, 1), b, 0, s, P, a, T, wa, wT, ab, Tb);
   }
 }
