@@ -218,7 +218,8 @@ __global__ __launch_bounds__(256) void ka_rhs_face(KParams P, const double* __re
 // ka_pred_face<DIM, D>: per face, the terms that do not depend on a flux
 // direction: the direct term u*_f = u_f + ..., the CSF force (sigma kappa,
 // M and the alpha difference), and the face density 1/rho_f (whose
-// derivative needs the forward viscous term, recomputed here).
+// derivative needs the forward viscous term: the direction kernels below
+// leave it, summed over the directions in their order, in vsum).
 
 // Box over a block's faces (one LDS array of doubles): origin and extent in
 // the virtual index space of the target array (ghost positions included).
@@ -236,8 +237,7 @@ struct Box {
 template <int DIM, int D>
 __global__ __launch_bounds__(256) void ka_pred_face(KParams P, const double* __restrict__ a,
                                                     const double* __restrict__ sk, const double* __restrict__ M,
-                                                    const double* __restrict__ u, const double* __restrict__ v,
-                                                    const double* __restrict__ w, const double* __restrict__ usb,
+                                                    const double* __restrict__ vsum, const double* __restrict__ usb,
                                                     double* __restrict__ udb, double* __restrict__ abar,
                                                     double* __restrict__ skbar, double* __restrict__ Mbar) {
   const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
@@ -250,8 +250,6 @@ __global__ __launch_bounds__(256) void ka_pred_face(KParams P, const double* __r
   const long fo = fidx<D>(i, j, k, nx, ny);
   const double ob = usb[fo];
   if (ob == 0.0) return;
-  const double* vel[3] = {u, v, w};
-  const double* ud = vel[D];
   const double ih = P.ih, dt = P.dt;
   int L[3] = {i, j, k};
   L[D] -= 1;
@@ -259,45 +257,7 @@ __global__ __launch_bounds__(256) void ka_pred_face(KParams P, const double* __r
   const double aL = a[cL], aR = a[cR];
   const double fst = 0.5 * (sk[cL] + sk[cR]) * (aR - aL) * ih + 0.5 * (M[cL] + M[cR]);
   const double rhof = 0.5 * (mix1(aL, P.rho1, P.rho2) + mix1(aR, P.rho1, P.rho2));
-  // forward viscous term (the same sums as the forward predictor's)
-  auto udv = [&](int e, int m) {  // component D at the face offset by m along e
-    int o[3] = {i, j, k};
-    o[e] += m;
-    double sg;
-    const long q = v_idx<D, DIM>(o[0], o[1], o[2], nx, ny, nz, sg);
-    return sg * ud[q];
-  };
-  double visc = 0.0;
-  for (int e = 0; e < DIM; ++e) {
-    if (e == D) {
-      const double mL = mix1(aL, P.mu1, P.mu2), mR = mix1(aR, P.mu1, P.mu2);
-      const double q2 = udv(e, -1), q3 = udv(e, 0), q4 = udv(e, 1);
-      visc += (2.0 * mR * (q4 - q3) * ih - 2.0 * mL * (q3 - q2) * ih) * ih;
-    } else {
-      const double* ve = vel[e];
-      double tau[2];
-      for (int side = 0; side < 2; ++side) {
-        const int ef = id[e] + side;
-        int pL[3] = {L[0], L[1], L[2]}, pR[3] = {i, j, k};
-        pL[e] = ef;
-        pR[e] = ef;
-        double sL, sR;
-        long iL, iR;
-        if (e == 0) { iL = v_idx<0, DIM>(pL[0], pL[1], pL[2], nx, ny, nz, sL); iR = v_idx<0, DIM>(pR[0], pR[1], pR[2], nx, ny, nz, sR); }
-        else if (e == 1) { iL = v_idx<1, DIM>(pL[0], pL[1], pL[2], nx, ny, nz, sL); iR = v_idx<1, DIM>(pR[0], pR[1], pR[2], nx, ny, nz, sR); }
-        else { iL = v_idx<2, DIM>(pL[0], pL[1], pL[2], nx, ny, nz, sL); iR = v_idx<2, DIM>(pR[0], pR[1], pR[2], nx, ny, nz, sR); }
-        const double veL = sL * ve[iL], veR = sR * ve[iR];
-        int c1[3] = {L[0], L[1], L[2]}, c2[3] = {i, j, k}, c3[3] = {L[0], L[1], L[2]}, c4[3] = {i, j, k};
-        c1[e] = ef - 1; c2[e] = ef - 1; c3[e] = ef; c4[e] = ef;
-        const double me = 0.25 * (mix1(a[a_idx<DIM>(c1[0], c1[1], c1[2], nx, ny, nz)], P.mu1, P.mu2) +
-                                  mix1(a[a_idx<DIM>(c2[0], c2[1], c2[2], nx, ny, nz)], P.mu1, P.mu2) +
-                                  mix1(a[a_idx<DIM>(c3[0], c3[1], c3[2], nx, ny, nz)], P.mu1, P.mu2) +
-                                  mix1(a[a_idx<DIM>(c4[0], c4[1], c4[2], nx, ny, nz)], P.mu1, P.mu2));
-        tau[side] = me * ((udv(e, side) - udv(e, side - 1)) * ih + (veR - veL) * ih);
-      }
-      visc += (tau[1] - tau[0]) * ih;
-    }
-  }
+  const double visc = vsum[fo];  // the forward viscous term, summed over the directions by ka_pred_dir
   aadd(&udb[fo], ob);  // direct term
   const double fstb = dt * ob / rhof;
   const double rhofb = -dt * ob * (visc + fst) / (rhof * rhof);
@@ -325,7 +285,8 @@ template <int DIM, int D, int E>
 __global__ __launch_bounds__(256) void ka_pred_dir(KParams P, const double* __restrict__ a,
                                                    const double* __restrict__ ud, const double* __restrict__ ue,
                                                    const double* __restrict__ usb, double* __restrict__ udb,
-                                                   double* __restrict__ ueb, double* __restrict__ abar) {
+                                                   double* __restrict__ ueb, double* __restrict__ abar,
+                                                   double* __restrict__ vsum) {
   constexpr int BYE = E == 0 ? 4 : 4;  // threads across the x rows
   constexpr int NB = 64 * BYE;
   // the block's faces: x in [x0, x0+64), and 4 along y (E = 0, 1) or z (E = 2)
@@ -378,6 +339,7 @@ __global__ __launch_bounds__(256) void ka_pred_dir(KParams P, const double* __re
     const double Fhib = convb * ih, Flob = -convb * ih;
     const double thib = viscb * ih, tlob = -viscb * ih;
     const double dmu = P.mu2 - P.mu1;
+    double vpart = 0.0;  // this direction's part of the forward viscous term
     // the seven D-faces along E (virtual offsets -3..3) and their values
     double q[7], qb[7];
     for (int m = 0; m < 7; ++m) {
@@ -402,6 +364,7 @@ __global__ __launch_bounds__(256) void ka_pred_dir(KParams P, const double* __re
       qb[3] += 0.5 * Ub;
       qb[4] += 0.5 * Ub;
       const double mL = mix1(aL, P.mu1, P.mu2), mR = mix1(aR, P.mu1, P.mu2);
+      vpart = (2.0 * mR * (q[4] - q[3]) * ih - 2.0 * mL * (q[3] - q[2]) * ih) * ih;
       atomicAdd(&sc[bc.at(L[0], L[1], L[2])], tlob * 2.0 * (q[3] - q[2]) * ih * dmu * dclamp(aL));
       atomicAdd(&sc[bc.at(i, j, k)], thib * 2.0 * (q[4] - q[3]) * ih * dmu * dclamp(aR));
       qb[3] += tlob * 2.0 * mL * ih;
@@ -409,6 +372,7 @@ __global__ __launch_bounds__(256) void ka_pred_dir(KParams P, const double* __re
       qb[4] += thib * 2.0 * mR * ih;
       qb[3] -= thib * 2.0 * mR * ih;
     } else {
+      double tau[2];
       for (int side = 0; side < 2; ++side) {
         const double Fb = side ? Fhib : Flob, tb = side ? thib : tlob;
         const int ef = id[E] + side;
@@ -434,6 +398,7 @@ __global__ __launch_bounds__(256) void ka_pred_dir(KParams P, const double* __re
           da[q4] = dclamp(av);
         }
         const double dud = (q[3 + side] - q[2 + side]) * ih, dve = (veR - veL) * ih;
+        tau[side] = me * (dud + dve);
         const double meb = tb * (dud + dve);
         const double dudb = tb * me, dveb = tb * me;
         qb[3 + side] += dudb * ih;
@@ -445,7 +410,11 @@ __global__ __launch_bounds__(256) void ka_pred_dir(KParams P, const double* __re
         atomicAdd(&sv[bv.at(pL[0], pL[1], pL[2])], veLb);
         atomicAdd(&sv[bv.at(pR[0], pR[1], pR[2])], veRb);
       }
+      vpart = (tau[1] - tau[0]) * ih;
     }
+    // the forward viscous term of the face, summed over the directions in order
+    const long fo = fidx<D>(i, j, k, nx, ny);
+    vsum[fo] = E == 0 ? 0.0 + vpart : vsum[fo] + vpart;
     for (int m = 0; m < 7; ++m) {
       int o[3] = {i, j, k};
       o[E] += m - 3;
@@ -760,21 +729,23 @@ __global__ __launch_bounds__(256) void ka_transport_cell(KParams P, const double
     const double gy = (A_at<DIM>(a, i, j + 1, k, nx, ny, nz) - A_at<DIM>(a, i, j - 1, k, nx, ny, nz)) * h2;
     const double gz = DIM == 3 ? (A_at<DIM>(a, i, j, k + 1, nx, ny, nz) - A_at<DIM>(a, i, j, k - 1, nx, ny, nz)) * h2 : 0.0;
     const double g2 = gx * gx + gy * gy + gz * gz;
-    const double ne = P.neps;
-    const double ge = sqrt(g2 + ne * ne);
-    const double xl = P.qx0 + P.qvx * P.t, yl = P.qy0 + P.qvy * P.t;
-    const double x = (i + 0.5) * P.h, y = (j + 0.5) * P.h;
-    const double r2 = (x - xl) * (x - xl) + (y - yl) * (y - yl);
-    const double R2 = P.qr * P.qr;
-    const double Q = 2.0 * P.qP / (M_PI * R2) * exp(-2.0 * r2 / R2);
-    src = Q * g2 / (ge + ne);
-    // d delta_s / d g = g / ge
-    const double gb[3] = {wc * Q * gx / ge, wc * Q * gy / ge, wc * Q * gz / ge};
-    for (int d = 0; d < DIM; ++d) {
-      int o[3] = {0, 0, 0};
-      o[d] = 1;
-      aadd(&ab[a_idx<DIM>(i + o[0], j + o[1], k + o[2], nx, ny, nz)], gb[d] * h2);
-      aadd(&ab[a_idx<DIM>(i - o[0], j - o[1], k - o[2], nx, ny, nz)], -gb[d] * h2);
+    if (g2 != 0.0) {  // away from the interface delta_s and its derivative vanish
+      const double ne = P.neps;
+      const double ge = sqrt(g2 + ne * ne);
+      const double xl = P.qx0 + P.qvx * P.t, yl = P.qy0 + P.qvy * P.t;
+      const double x = (i + 0.5) * P.h, y = (j + 0.5) * P.h;
+      const double r2 = (x - xl) * (x - xl) + (y - yl) * (y - yl);
+      const double R2 = P.qr * P.qr;
+      const double Q = 2.0 * P.qP / (M_PI * R2) * exp(-2.0 * r2 / R2);
+      src = Q * g2 / (ge + ne);
+      // d delta_s / d g = g / ge
+      const double gb[3] = {wc * Q * gx / ge, wc * Q * gy / ge, wc * Q * gz / ge};
+      for (int d = 0; d < DIM; ++d) {
+        int o[3] = {0, 0, 0};
+        o[d] = 1;
+        aadd(&ab[a_idx<DIM>(i + o[0], j + o[1], k + o[2], nx, ny, nz)], gb[d] * h2);
+        aadd(&ab[a_idx<DIM>(i - o[0], j - o[1], k - o[2], nx, ny, nz)], -gb[d] * h2);
+      }
     }
   }
   // rho c_p in the denominator
@@ -833,44 +804,39 @@ void adj_rhs(const KParams& P, hipStream_t s, const double* ubp, const double* v
 // the direction kernels of component D (its x, y and z fluxes)
 template <int DIM, int D, int E>
 void pred_dir(const KParams& P, hipStream_t s, const double* a, const double* const vel[3], double* const velb[3],
-              const double* usb, double* abar) {
+              const double* usb, double* abar, double* vsum) {
   const int fnx = P.nx + (D == 0), fny = P.ny + (D == 1), fnz = (DIM == 3 ? P.nz : 1) + (D == 2);
   const dim3 g = E == 2 ? dim3((fnx + 63) / 64, fny, (fnz + 3) / 4) : dim3((fnx + 63) / 64, (fny + 3) / 4, fnz);
   hipLaunchKernelGGL((ka_pred_dir<DIM, D, E>), g, dim3(64, 4), 0, s, P, a, vel[D], vel[E], usb, velb[D], velb[E],
-                     abar);
+                     abar, vsum);
 }
+// component D: its x, y (and z) flux kernels, then the face kernel that
+// reads the viscous term they summed
 template <int DIM, int D>
-void pred_dirs(const KParams& P, hipStream_t s, const double* a, const double* const vel[3], double* const velb[3],
-               const double* usb, double* abar) {
-  pred_dir<DIM, D, 0>(P, s, a, vel, velb, usb, abar);
-  pred_dir<DIM, D, 1>(P, s, a, vel, velb, usb, abar);
-  if constexpr (DIM == 3) pred_dir<DIM, D, 2>(P, s, a, vel, velb, usb, abar);
+void pred_component(const KParams& P, hipStream_t s, const double* a, const double* sk, const double* M,
+                    const double* const vel[3], double* const velb[3], const double* usb, double* abar,
+                    double* skbar, double* Mbar, double* vsum) {
+  pred_dir<DIM, D, 0>(P, s, a, vel, velb, usb, abar, vsum);
+  pred_dir<DIM, D, 1>(P, s, a, vel, velb, usb, abar, vsum);
+  if constexpr (DIM == 3) pred_dir<DIM, D, 2>(P, s, a, vel, velb, usb, abar, vsum);
+  const dim3 g = grid_of(P.nx + (D == 0), P.ny + (D == 1), DIM == 3 ? P.nz + (D == 2) : 1);
+  hipLaunchKernelGGL((ka_pred_face<DIM, D>), g, dim3(BX, BY), 0, s, P, a, sk, M, vsum, usb, velb[D], abar, skbar,
+                     Mbar);
 }
 
 void adj_predictor(const KParams& P, hipStream_t s, const double* a, const double* sk, const double* Mx,
                    const double* My, const double* Mz, const double* u, const double* v, const double* w,
                    const double* usb, const double* vsb, const double* wsb, double* ubar, double* vbar,
-                   double* wbar, double* abar, double* skbar, double* Mxb, double* Myb, double* Mzb) {
-  dim3 b(BX, BY);
+                   double* wbar, double* abar, double* skbar, double* Mxb, double* Myb, double* Mzb, double* vsum) {
   const double* const vel[3] = {u, v, w};
   double* const velb[3] = {ubar, vbar, wbar};
   if (P.dim == 3) {
-    hipLaunchKernelGGL((ka_pred_face<3, 0>), grid_of(P.nx + 1, P.ny, P.nz), b, 0, s, P, a, sk, Mx, u, v, w, usb, ubar,
-                       abar, skbar, Mxb);
-    hipLaunchKernelGGL((ka_pred_face<3, 1>), grid_of(P.nx, P.ny + 1, P.nz), b, 0, s, P, a, sk, My, u, v, w, vsb, vbar,
-                       abar, skbar, Myb);
-    hipLaunchKernelGGL((ka_pred_face<3, 2>), grid_of(P.nx, P.ny, P.nz + 1), b, 0, s, P, a, sk, Mz, u, v, w, wsb, wbar,
-                       abar, skbar, Mzb);
-    pred_dirs<3, 0>(P, s, a, vel, velb, usb, abar);
-    pred_dirs<3, 1>(P, s, a, vel, velb, vsb, abar);
-    pred_dirs<3, 2>(P, s, a, vel, velb, wsb, abar);
+    pred_component<3, 0>(P, s, a, sk, Mx, vel, velb, usb, abar, skbar, Mxb, vsum);
+    pred_component<3, 1>(P, s, a, sk, My, vel, velb, vsb, abar, skbar, Myb, vsum);
+    pred_component<3, 2>(P, s, a, sk, Mz, vel, velb, wsb, abar, skbar, Mzb, vsum);
   } else {
-    hipLaunchKernelGGL((ka_pred_face<2, 0>), grid_of(P.nx + 1, P.ny, 1), b, 0, s, P, a, sk, Mx, u, v, w, usb, ubar,
-                       abar, skbar, Mxb);
-    hipLaunchKernelGGL((ka_pred_face<2, 1>), grid_of(P.nx, P.ny + 1, 1), b, 0, s, P, a, sk, My, u, v, w, vsb, vbar,
-                       abar, skbar, Myb);
-    pred_dirs<2, 0>(P, s, a, vel, velb, usb, abar);
-    pred_dirs<2, 1>(P, s, a, vel, velb, vsb, abar);
+    pred_component<2, 0>(P, s, a, sk, Mx, vel, velb, usb, abar, skbar, Mxb, vsum);
+    pred_component<2, 1>(P, s, a, sk, My, vel, velb, vsb, abar, skbar, Myb, vsum);
   }
 }
 

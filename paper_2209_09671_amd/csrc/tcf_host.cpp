@@ -172,6 +172,7 @@ struct tcf_grid {
   // adjoint scratch (configs with TCF_WITH_ADJOINT; FP64 only)
   struct Adj {
     double *ab, *Tb, *usb, *vsb, *wsb, *ub, *vb, *wb, *pbar, *y, *skb, *Mxb, *Myb, *Mzb;
+    double* vsum;  // the predictor's forward viscous term per face (one component at a time)
     double *nbx, *nby, *nbz, *dsb, *wa, *wT, *sa, *sT;
     double* pnext;   // the pressure of the state given to the last backward step
     double* yh[2];   // the adjoint pressures of the two calls before the last (newest first)
@@ -403,6 +404,7 @@ size_t carve(const tcf_config* c, void* base, tcf_grid* g) {
     A.nby = cv.take<double>(A.Ne);
     A.nbz = D.dim == 3 ? cv.take<double>(A.Ne) : nullptr;
     A.dsb = cv.take<double>(A.Ne);
+    A.vsum = cv.take<double>(std::max(D.Nu, std::max(D.Nv, D.Nw)));
     A.wa = cv.take<double>(N);
     A.wT = cv.take<double>(N);
     A.sa = cv.take<double>(N);
@@ -1380,7 +1382,7 @@ void predictor_reverse(tcf_grid* g, const KParams& P, const double* usb, const d
   if (g->D.dim == 3) fill_f64(s, A.Ne, A.nbz, 0.0);
   fill_f64(s, A.Ne, A.dsb, 0.0);
   adj_predictor(P, s, F.a, F.sk, F.Mx, F.My, F.Mz, F.u, F.v, F.w, usb, vsb, wsb, A.ub, A.vb, A.wb, A.ab, A.skb,
-                A.Mxb, A.Myb, A.Mzb);
+                A.Mxb, A.Myb, A.Mzb, A.vsum);
   const int np = adj_geometry(P, s, F.a, F.T, A.skb, A.Mxb, A.Myb, A.Mzb, A.Tb, A.nbx, A.nby, A.nbz, A.dsb, A.ab,
                               g->part[0]);
   finalize(s, g->part[0], np, g->scal, g->iflag, F_STORE, S_SBAR, 0.0);

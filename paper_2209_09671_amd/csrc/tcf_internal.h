@@ -224,7 +224,8 @@ void adj_rhs(const KParams& P, hipStream_t s, const double* ubp, const double* v
 void adj_predictor(const KParams& P, hipStream_t s, const double* a, const double* sk, const double* Mx,
                    const double* My, const double* Mz, const double* u, const double* v, const double* w,
                    const double* usb, const double* vsb, const double* wsb, double* ubar, double* vbar,
-                   double* wbar, double* abar, double* skbar, double* Mxb, double* Myb, double* Mzb);
+                   double* wbar, double* abar, double* skbar, double* Mxb, double* Myb, double* Mzb,
+                   double* vsum);
 int adj_geometry(const KParams& P, hipStream_t s, const double* a, const double* T, const double* skb,
                  const double* Mxb, const double* Myb, const double* Mzb, double* Tbar, double* nbx, double* nby,
                  double* nbz, double* dsb, double* abar, double* spart);
