@@ -20,7 +20,8 @@ below that.  Then --warmup W untimed and --steps K timed steps.
 Prints ONE JSON line.  Options: --steps K --warmup W --gpus 1 --spinup S
 --cpu-steps C --no-cpu --no-fp64 --no-kernels --no-adjoint --no-species
 --no-rk3p --no-nphase.  `--trace-summary CSV` prints the per-kernel table of
-the last --trace-steps steps of a rocprofv3 kernel trace instead.
+the last --trace-steps steps of a rocprofv3 kernel trace instead (with
+--trace-adjoint: the backward sweep of --trace-steps adjoint steps).
 """
 from __future__ import annotations
 
@@ -267,10 +268,12 @@ def adjoint_timing(c, spin, steps, every):
     return out
 
 
-def trace_summary(path, nsteps, marker="k_transport2<float, 3, 1>", per_step=3):
+def trace_summary(path, nsteps, marker="k_transport2<float, 3, 1>", per_step=3, adjoint=False):
     """Markdown table of the kernels of the last `nsteps` steps of a
     rocprofv3 kernel trace (CSV); a step is found by its `per_step`
-    launches of `marker` (the transport stages).  Needs no GPU."""
+    launches of `marker` (the transport stages).  With `adjoint`, the window
+    is the backward sweep instead (first to last adjoint kernel, recomputed
+    forward segments included), over `nsteps` adjoint steps.  Needs no GPU."""
     import collections
     import csv
     rows = []
@@ -278,8 +281,12 @@ def trace_summary(path, nsteps, marker="k_transport2<float, 3, 1>", per_step=3):
         for r in csv.DictReader(f):
             rows.append((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), r["Kernel_Name"]))
     rows.sort()
-    idx = [i for i, r in enumerate(rows) if marker in r[2]]
-    win = rows[idx[-nsteps * per_step]:]
+    if adjoint:
+        idx = [i for i, r in enumerate(rows) if "::ka_" in r[2]]
+        win = rows[idx[0]:idx[-1] + 1]
+    else:
+        idx = [i for i, r in enumerate(rows) if marker in r[2]]
+        win = rows[idx[-nsteps * per_step]:]
     t0, t1 = win[0][0], win[-1][1]
     agg = collections.defaultdict(lambda: [0, 0.0])
     for a, b, n in win:
@@ -287,7 +294,8 @@ def trace_summary(path, nsteps, marker="k_transport2<float, 3, 1>", per_step=3):
         agg[n][0] += 1
         agg[n][1] += (b - a) / 1e3
     tot = sum(v[1] for v in agg.values())
-    out = [f"Window: the last {nsteps} steps, {len(win)} dispatches, span {(t1 - t0) / 1e6:.3f} ms "
+    what = f"the backward sweep of {nsteps} adjoint steps" if adjoint else f"the last {nsteps} steps"
+    out = [f"Window: {what}, {len(win)} dispatches, span {(t1 - t0) / 1e6:.3f} ms "
            f"({(t1 - t0) / 1e6 / nsteps:.3f} ms/step), kernel time {tot / 1e3 / nsteps:.3f} ms/step.", "",
            "| kernel | calls/step | avg us | ms/step | % |", "|---|---:|---:|---:|---:|"]
     for n, (c, us) in sorted(agg.items(), key=lambda kv: -kv[1][1]):
@@ -325,9 +333,11 @@ def main():
                     help="print the per-kernel table of the last --trace-steps steps of a rocprofv3 "
                          "kernel trace CSV and exit (no GPU)")
     ap.add_argument("--trace-steps", type=int, default=20)
+    ap.add_argument("--trace-adjoint", action="store_true",
+                    help="with --trace-summary: tabulate the adjoint's backward sweep (--trace-steps steps)")
     args = ap.parse_args()
     if args.trace_summary:
-        print(trace_summary(args.trace_summary, args.trace_steps))
+        print(trace_summary(args.trace_summary, args.trace_steps, adjoint=args.trace_adjoint))
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this path runs on one GPU; runs on several GPUs are not supported "

@@ -19,6 +19,14 @@ constexpr int BX = 64, BY = 4;
 // (Dirichlet).  Velocity component C: odd reflection about its wall faces
 // along C (normal), odd reflection about the wall along the other axes
 // (tangential, no slip).
+// Reciprocal and reciprocal square root: the hardware instructions in FP32
+// (within about an ulp, far inside the FP32 path's error budget), correctly
+// rounded in FP64.
+__device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double frcp(double x) { return 1.0 / x; }
+__device__ __forceinline__ float frsq(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ double frsq(double x) { return 1.0 / sqrt(x); }
+
 __device__ __forceinline__ int refl(int i, int n) { return i < 0 ? -1 - i : (i >= n ? 2 * n - 1 - i : i); }
 
 __device__ __forceinline__ long cidx(int i, int j, int k, int nx, int ny) {

@@ -302,17 +302,51 @@ __device__ __forceinline__ void write_partial(double acc, double* part) {
   if (threadIdx.x == 0 && threadIdx.y == 0) part[blockIdx.x] = s;
 }
 
+// Sum of the n per-block partials of the previous pass, computed by every
+// block of a consumer kernel instead of by a reduction launch of its own:
+// 256 fixed lanes (the block's first 256 threads) each add a strided subset
+// with four accumulators, and block_reduce sums the lanes in a fixed order
+// (the other threads add exact zeros), so every block of any size >= 256
+// gets the same value, bit for bit.
+__device__ __forceinline__ double fold_partials(const double* __restrict__ part, int n) {
+  __shared__ double sh[16];
+  const int tid = threadIdx.x + blockDim.x * threadIdx.y;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  if (tid < 256) {
+    int q = tid;
+    for (; q + 768 < n; q += 1024) {
+      a0 += part[q];
+      a1 += part[q + 256];
+      a2 += part[q + 512];
+      a3 += part[q + 768];
+    }
+    for (; q < n; q += 256) a0 += part[q];
+  }
+  return block_reduce<0>((a0 + a1) + (a2 + a3), sh);
+}
+
+// PCG iteration it (1-based), first pass.  rz_(it-1) = r.z of the last
+// preconditioner application is folded from its partials (rzp, nrz) and
+// stored in rz_slot(it - 1) by block 0; beta = rz_(it-1) / rz_(it-2).
 // d' = z + beta d (d' = z on the first iteration); partial d'.K0 d' (K0 d'
 // itself is not stored: the update pass recomputes it from d')
 template <class R, int DIM>
 __global__ __launch_bounds__(FX * FY) void k0_spmv_upd(Op0<R> op, int kz, int ntx, int nty, const R* __restrict__ z,
                                                    const R* __restrict__ dold, R* __restrict__ dnew,
-                                                   const double* __restrict__ scal, int first,
+                                                   double* __restrict__ scal, int it,
+                                                   const double* __restrict__ rzp, int nrz,
                                                    double* __restrict__ part, const int* __restrict__ iflag) {
   if (iflag[I_DONE]) return;
   const Tile T = tile_of(op.nx, op.ny, op.nz, ntx, nty, kz);
+  const bool first = it == 1;
+  const double rz = fold_partials(rzp, nrz);
+  const double bd = first ? 0.0 : rz / scal[rz_slot(it - 2)];
+  if (blockIdx.x == 0 && threadIdx.x == 0 && threadIdx.y == 0) {
+    scal[rz_slot(it - 1)] = rz;
+    scal[S_BETA] = bd;
+  }
   // on the first iteration d' = z + 0 z (the old direction is not read)
-  const R beta = first ? R(0) : R(scal[S_BETA]);
+  const R beta = R(bd);
   const R* __restrict__ dsrc = first ? z : dold;
   auto X = [&](long c, int, int, int) { return Vec2<R>{z[c], dsrc[c]}; };
   auto XV = [&](const Vec2<R>& v) { return v.a + beta * v.b; };
@@ -330,15 +364,24 @@ __global__ __launch_bounds__(FX * FY) void k0_spmv_upd(Op0<R> op, int kz, int nt
 // same arithmetic as the SpMV pass; partial r.r); z1 = omega r / diag (first
 // sweep of the next V-cycle from a zero guess).  With xzero, x starts from
 // zero and is not read (x = alpha d).
+// alpha = rz_(it-1) / d'.K0 d', the latter folded from the SpMV pass's
+// partials (dqp, ndq); block 0 stores d'.K0 d' and alpha.
 template <class R, int DIM>
 __global__ __launch_bounds__(FX * FY) void k0_update_smooth(Op0<R> op, int kz, int ntx, int nty, R omega,
-                                                        const double* __restrict__ scal, int xzero, R* __restrict__ x,
-                                                        R* __restrict__ r, const R* __restrict__ d,
-                                                        R* __restrict__ z1, double* __restrict__ part,
-                                                        const int* __restrict__ iflag) {
+                                                        double* __restrict__ scal, int it, int xzero,
+                                                        R* __restrict__ x, R* __restrict__ r,
+                                                        const R* __restrict__ d, R* __restrict__ z1,
+                                                        const double* __restrict__ dqp, int ndq,
+                                                        double* __restrict__ part, const int* __restrict__ iflag) {
   if (iflag[I_DONE]) return;
   const Tile T = tile_of(op.nx, op.ny, op.nz, ntx, nty, kz);
-  const R al = R(scal[S_ALPHA]);
+  const double dq = fold_partials(dqp, ndq);
+  const double ad = scal[rz_slot(it - 1)] / dq;
+  if (blockIdx.x == 0 && threadIdx.x == 0 && threadIdx.y == 0) {
+    scal[S_DQ] = dq;
+    scal[S_ALPHA] = ad;
+  }
+  const R al = R(ad);
   double acc = 0.0;
   auto X = [&](long c, int, int, int) { return d[c]; };
   const R* __restrict__ xs = xzero ? r : x;  // from zero: a load of r, which is read anyway
@@ -749,30 +792,30 @@ Op0<R> op_of(const Fine<R>& F) {
 int fine_blocks(int nx, int ny, int nz) { return plan(nx, ny, nz).nblocks; }
 
 template <class R>
-int fine_spmv_upd(hipStream_t s, int dim, const Fine<R>& F, const R* z, const R* dold, R* dnew,
-                  const double* scal, int first, double* part, const int* iflag) {
+int fine_spmv_upd(hipStream_t s, int dim, const Fine<R>& F, const R* z, const R* dold, R* dnew, double* scal,
+                  int it, const double* rzpart, int nrz, double* part, const int* iflag) {
   const Launch L = plan(F.nx, F.ny, F.nz);
   const Op0<R> op = op_of(F);
   if (dim == 3)
     hipLaunchKernelGGL((k0_spmv_upd<R, 3>), dim3(L.nblocks), dim3(FX, FY), 0, s, op, L.kz, L.ntx, L.nty, z, dold, dnew,
-                       scal, first, part, iflag);
+                       scal, it, rzpart, nrz, part, iflag);
   else
     hipLaunchKernelGGL((k0_spmv_upd<R, 2>), dim3(L.nblocks), dim3(FX, FY), 0, s, op, L.kz, L.ntx, L.nty, z, dold, dnew,
-                       scal, first, part, iflag);
+                       scal, it, rzpart, nrz, part, iflag);
   return L.nblocks;
 }
 
 template <class R>
-int fine_update_smooth(hipStream_t s, int dim, const Fine<R>& F, double omega, const double* scal, int xzero, R* x,
-                       R* r, const R* d, R* z1, double* part, const int* iflag) {
+int fine_update_smooth(hipStream_t s, int dim, const Fine<R>& F, double omega, double* scal, int it, int xzero, R* x,
+                       R* r, const R* d, R* z1, const double* dqpart, int ndq, double* part, const int* iflag) {
   const Launch L = plan(F.nx, F.ny, F.nz);
   const Op0<R> op = op_of(F);
   if (dim == 3)
     hipLaunchKernelGGL((k0_update_smooth<R, 3>), dim3(L.nblocks), dim3(FX, FY), 0, s, op, L.kz, L.ntx, L.nty, R(omega),
-                       scal, xzero, x, r, d, z1, part, iflag);
+                       scal, it, xzero, x, r, d, z1, dqpart, ndq, part, iflag);
   else
     hipLaunchKernelGGL((k0_update_smooth<R, 2>), dim3(L.nblocks), dim3(FX, FY), 0, s, op, L.kz, L.ntx, L.nty, R(omega),
-                       scal, xzero, x, r, d, z1, part, iflag);
+                       scal, it, xzero, x, r, d, z1, dqpart, ndq, part, iflag);
   return L.nblocks;
 }
 
@@ -893,10 +936,10 @@ int resid64a(const KParams& P, hipStream_t s, const R* a, const double* b, const
 }
 
 #define TCF_FINE_INST(R)                                                                                          \
-  template int fine_spmv_upd<R>(hipStream_t, int, const Fine<R>&, const R*, const R*, R*, const double*, int,     \
-                                double*, const int*);                                                             \
-  template int fine_update_smooth<R>(hipStream_t, int, const Fine<R>&, double, const double*, int, R*, R*, const R*, \
-                                     R*, double*, const int*);                                                    \
+  template int fine_spmv_upd<R>(hipStream_t, int, const Fine<R>&, const R*, const R*, R*, double*, int,           \
+                                const double*, int, double*, const int*);                                         \
+  template int fine_update_smooth<R>(hipStream_t, int, const Fine<R>&, double, double*, int, int, R*, R*, const R*, \
+                                     R*, const double*, int, double*, const int*);                               \
   template void fine_smooth_first<R>(hipStream_t, int, const Fine<R>&, double, const R*, R*, const int*);         \
   template int fine_smooth<R>(hipStream_t, int, const Fine<R>&, double, const R*, const R*, R*, const R*, int,    \
                               int, double, double*, const int*);                                                  \

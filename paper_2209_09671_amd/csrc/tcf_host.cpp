@@ -733,6 +733,10 @@ R* vcycle(tcf_grid* g, Fields<R>& F, size_t l, const R* b, R* out, R* tmp, doubl
 // by the residual norm after it).
 // With f64, r is filled from the FP64 residual by the first preconditioner
 // application (multigrid hierarchies of two or more levels only).
+// One reduction launch per iteration: r.z and d.K d are summed from their
+// block partials by every block of the pass that needs them (the SpMV pass
+// forms beta, the update pass alpha); r.r, which the host reads, goes
+// through a finalize.
 template <class R>
 tcf_status pcg_iterate(tcf_grid* g, Fields<R>& F, R* x, R* r, int maxit, int kind, bool x_zero, int* iters,
                        bool* converged, FromR64* f64 = nullptr) {
@@ -741,10 +745,12 @@ tcf_status pcg_iterate(tcf_grid* g, Fields<R>& F, R* x, R* r, int maxit, int kin
   const Fine<R> Fd = fine_desc<R>(g);
   const double wj = sweep_omega(dim, g->cfg.mg_nu, 0);  // first pre-smoothing sweep, fused into the update
   *converged = false;
-  int np = 0;
-  R* z = vcycle<R>(g, F, 0, r, F.z, F.z2, g->part[0], false, &np, f64);
+  // partials: r.z of each preconditioner application -> part[0], folded by
+  // the next SpMV pass; d.K d of the SpMV -> part[1], folded by the update
+  // pass; r.r of the update -> part[0], reduced by the convergence test
+  int nrz = 0, ndq = 0, nrr = 0;
+  R* z = vcycle<R>(g, F, 0, r, F.z, F.z2, g->part[0], false, &nrz, f64);
   if (f64) finalize(s, f64->part, f64->np, g->scal, g->iflag, F_BB, 0, f64->tau2);
-  finalize(s, g->part[0], np, g->scal, g->iflag, F_RZ_FIRST, 0, 0.0);
   R* dcur = F.d;
   R* dnext = F.d2;
   const int expect = g->pcg_expect[kind];
@@ -753,23 +759,21 @@ tcf_status pcg_iterate(tcf_grid* g, Fields<R>& F, R* x, R* r, int maxit, int kin
     last = it;
     {
       Prof pr(g, FAM_SPMV);
-      np = fine_spmv_upd<R>(s, dim, Fd, z, dcur, dnext, g->scal, it == 1 ? 1 : 0, g->part[0], g->iflag);
+      ndq = fine_spmv_upd<R>(s, dim, Fd, z, dcur, dnext, g->scal, it, g->part[0], nrz, g->part[1], g->iflag);
     }
-    finalize(s, g->part[0], np, g->scal, g->iflag, F_ALPHA, 0, 0.0);
     std::swap(dcur, dnext);
     {
       Prof pr(g, FAM_UPDATE);
-      np = fine_update_smooth<R>(s, dim, Fd, wj, g->scal, x_zero && it == 1 ? 1 : 0, x, r, dcur, F.z2, g->part[0],
-                                 g->iflag);
+      nrr = fine_update_smooth<R>(s, dim, Fd, wj, g->scal, it, x_zero && it == 1 ? 1 : 0, x, r, dcur, F.z2,
+                                  g->part[1], ndq, g->part[0], g->iflag);
     }
-    finalize(s, g->part[0], np, g->scal, g->iflag, F_RR, 0, 1.0);
+    finalize(s, g->part[0], nrr, g->scal, g->iflag, F_RR, 0, 1.0);
     HIPCHECK(read_back_async(g));
     if (expect > 0 && it >= expect) {
       HIPCHECK(wait_back(g));
       if (g->hflag[I_DONE]) break;
     }
-    z = vcycle<R>(g, F, 0, r, F.z, F.z2, g->part[0], true, &np);
-    finalize(s, g->part[0], np, g->scal, g->iflag, F_RZ, 0, 0.0);
+    z = vcycle<R>(g, F, 0, r, F.z, F.z2, g->part[0], true, &nrz);
     HIPCHECK(wait_back(g));
     if (g->hflag[I_DONE]) break;
   }

@@ -67,10 +67,14 @@ struct Fine {
 
 // Slots of the device scalar block (FP64).
 enum Slot { S_MEAN = 0, S_BB, S_RR, S_RZ, S_DQ, S_ALPHA, S_BETA, S_TOL2, S_SCALE,
-            S_SUMA, S_AMIN, S_AMAX, S_UMAX, S_DIV2, S_NONFIN, S_RR64, S_BB64, S_PMEAN, S_SBAR, S_NSLOT = 24 };
+            S_SUMA, S_AMIN, S_AMAX, S_UMAX, S_DIV2, S_NONFIN, S_RR64, S_BB64, S_PMEAN, S_SBAR, S_RZ2, S_NSLOT = 24 };
 // Integer flags: done, iteration count.
 enum IFlag { I_DONE = 0, I_ITERS = 1, I_NFLAG = 4 };
-enum FinOp { F_STORE = 0, F_MEAN, F_BB, F_ALPHA, F_RR, F_RZ_FIRST, F_RZ, F_MIN, F_MAX, F_SCALE };
+// r.z of the k-th preconditioned residual of a PCG solve (k = 0 after the
+// first preconditioner application): the slots alternate, so that a kernel
+// can write rz_k while every block still reads rz_(k-1)
+__host__ __device__ inline int rz_slot(int k) { return (k & 1) ? S_RZ2 : S_RZ; }
+enum FinOp { F_STORE = 0, F_MEAN, F_BB, F_RR, F_MIN, F_MAX, F_SCALE };
 
 constexpr int kBlock = 256;
 constexpr int kCoarseDenseMax = 512;  // coarsest levels up to this size are solved exactly
@@ -154,11 +158,11 @@ template <class R>
 int resid64a(const KParams& P, hipStream_t s, const R* a, const double* b, const double* scal, const double* p,
              double* r, double* pbb, double* prr);
 template <class R>
-int fine_spmv_upd(hipStream_t s, int dim, const Fine<R>& F, const R* z, const R* dold, R* dnew,
-                  const double* scal, int first, double* part, const int* iflag);
+int fine_spmv_upd(hipStream_t s, int dim, const Fine<R>& F, const R* z, const R* dold, R* dnew, double* scal,
+                  int it, const double* rzpart, int nrz, double* part, const int* iflag);
 template <class R>
-int fine_update_smooth(hipStream_t s, int dim, const Fine<R>& F, double omega, const double* scal, int xzero, R* x, R* r,
-                       const R* d, R* z1, double* part, const int* iflag);
+int fine_update_smooth(hipStream_t s, int dim, const Fine<R>& F, double omega, double* scal, int it, int xzero, R* x,
+                       R* r, const R* d, R* z1, const double* dqpart, int ndq, double* part, const int* iflag);
 template <class R>
 void fine_smooth_first(hipStream_t s, int dim, const Fine<R>& F, double omega, const R* b, R* z1, const int* iflag);
 template <class R>

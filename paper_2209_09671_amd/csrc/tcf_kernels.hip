@@ -6,7 +6,8 @@
 // produced on the fly by reflected indexing (see the ghost rules below), so
 // the arrays have exactly the ABI layout and need no padding or ghost-fill
 // pass.  Reductions are deterministic: wavefront shuffles, then LDS, then one
-// FP64 partial per block, summed in a fixed order by a one-block finalize.
+// FP64 partial per block, summed in a fixed order by a one-block finalize (or
+// by every block of the consuming kernel, in the same fixed order).
 #include <algorithm>
 #include <cfloat>
 #include <cmath>
@@ -27,7 +28,7 @@ __device__ __forceinline__ void normal_at(const R* __restrict__ a, int i, int j,
   const R gx = (A_at<DIM>(a, i + 1, j, k, nx, ny, nz) - A_at<DIM>(a, i - 1, j, k, nx, ny, nz)) * ih2;
   const R gy = (A_at<DIM>(a, i, j + 1, k, nx, ny, nz) - A_at<DIM>(a, i, j - 1, k, nx, ny, nz)) * ih2;
   const R gz = DIM == 3 ? (A_at<DIM>(a, i, j, k + 1, nx, ny, nz) - A_at<DIM>(a, i, j, k - 1, nx, ny, nz)) * ih2 : R(0);
-  const R inv = R(1) / sqrt(gx * gx + gy * gy + gz * gz + ne * ne);
+  const R inv = frsq(gx * gx + gy * gy + gz * gz + ne * ne);
   n[0] = gx * inv;
   n[1] = gy * inv;
   n[2] = gz * inv;
@@ -70,9 +71,9 @@ __global__ __launch_bounds__(256) void k_geometry(KParams P, const R* __restrict
   const R gy = (A_at<DIM>(a, i, j + 1, k, nx, ny, nz) - A_at<DIM>(a, i, j - 1, k, nx, ny, nz)) * ih2;
   const R gz = DIM == 3 ? (A_at<DIM>(a, i, j, k + 1, nx, ny, nz) - A_at<DIM>(a, i, j, k - 1, nx, ny, nz)) * ih2 : R(0);
   const R g2 = gx * gx + gy * gy + gz * gz;
-  const R ge = sqrt(g2 + ne * ne);
-  const R ds = g2 / (ge + ne);
-  const R n0 = gx / ge, n1 = gy / ge, n2 = gz / ge;
+  const R q2 = g2 + ne * ne, ig = frsq(q2);  // 1 / |grad alpha|_eps
+  const R ds = g2 * frcp(q2 * ig + ne);
+  const R n0 = gx * ig, n1 = gy * ig, n2 = gz * ig;
   const long c = cidx(i, j, k, nx, ny);
   const R s = R(P.s);
   R sigma = R(P.sigma0) + s * (T[c] - R(P.T0));
@@ -164,7 +165,7 @@ __global__ __launch_bounds__(256) void k_geometry_z(KParams P, int kz, int ntx, 
       const R gx = (sa[sc][py][px + 1] - sa[sc][py][px - 1]) * ih2;
       const R gy = (sa[sc][py + 1][px] - sa[sc][py - 1][px]) * ih2;
       const R gz = (sa[sp][py][px] - sa[sm][py][px]) * ih2;
-      const R inv = R(1) / sqrt(gx * gx + gy * gy + gz * gz + ne * ne);
+      const R inv = frsq(gx * gx + gy * gy + gz * gz + ne * ne);
       snx[py - 1][px - 1] = gx * inv;
       sny[py - 1][px - 1] = gy * inv;
     }
@@ -174,7 +175,7 @@ __global__ __launch_bounds__(256) void k_geometry_z(KParams P, int kz, int ntx, 
       const R gx = (sa[sp][Y][X + 1] - sa[sp][Y][X - 1]) * ih2;
       const R gy = (sa[sp][Y + 1][X] - sa[sp][Y - 1][X]) * ih2;
       const R gz = (sa[sq][Y][X] - sa[sc][Y][X]) * ih2;
-      const R inv = R(1) / sqrt(gx * gx + gy * gy + gz * gz + ne * ne);
+      const R inv = frsq(gx * gx + gy * gy + gz * gz + ne * ne);
       nzp = gz * inv;
     }
     // plane k + 3 into the slot of plane k - 2 (no longer read), then prefetch k + 4
@@ -190,9 +191,9 @@ __global__ __launch_bounds__(256) void k_geometry_z(KParams P, int kz, int ntx, 
       const R gy = (sa[sc][Y + 1][X] - sa[sc][Y - 1][X]) * ih2;
       const R gz = (sa[sp][Y][X] - sa[sm][Y][X]) * ih2;
       const R g2 = gx * gx + gy * gy + gz * gz;
-      const R ge = sqrt(g2 + ne * ne);
-      const R ds = g2 / (ge + ne);
-      const R n0 = gx / ge, n1 = gy / ge, n2 = gz / ge;
+      const R q2 = g2 + ne * ne, ig = frsq(q2);  // 1 / |grad alpha|_eps
+      const R ds = g2 * frcp(q2 * ig + ne);
+      const R n0 = gx * ig, n1 = gy * ig, n2 = gz * ig;
       const long c = cidx(i, j, k, nx, ny);
       const R s = R(P.s);
       R sigma = R(P.sigma0) + s * (T[c] - R(P.T0));
@@ -343,21 +344,37 @@ __global__ __launch_bounds__(256) void k_coarsen_level(KParams P, const R* __res
   if (WD) wd[cidx(I, J, K, cnx, cny)] = d > R(0) ? omega / d : R(0);
 }
 
-// (K x)_c = sum_f a_f (x_c - x_nb) on a level (walls carry a_f = 0).
+// (K x)_c = sum_f a_f (x_c - x_nb) over the faces inside the domain (walls
+// carry a_f = 0 and add nothing).  Every load is issued unconditionally (a
+// neighbour beyond a wall reads the cell itself, the wall's face weight is
+// in bounds) and the wall terms are dropped by selects, so the loads go out
+// together instead of one branch, and one memory round trip, per face.
 template <class R, int DIM>
 __device__ __forceinline__ R applyK(const R* __restrict__ x, const R* __restrict__ ax, const R* __restrict__ ay,
                                     const R* __restrict__ az, int i, int j, int k, int nx, int ny, int nz) {
   const long c = cidx(i, j, k, nx, ny);
+  const long pl = (long)nx * ny;
+  const bool w = i > 0, e = i < nx - 1, so = j > 0, no = j < ny - 1;
+  const bool lo = DIM == 3 && k > 0, hi = DIM == 3 && k < nz - 1;
   const R xc = x[c];
-  R s = R(0);
-  if (i > 0) s += ax[fidx<0>(i, j, k, nx, ny)] * (xc - x[c - 1]);
-  if (i < nx - 1) s += ax[fidx<0>(i + 1, j, k, nx, ny)] * (xc - x[c + 1]);
-  if (j > 0) s += ay[fidx<1>(i, j, k, nx, ny)] * (xc - x[c - nx]);
-  if (j < ny - 1) s += ay[fidx<1>(i, j + 1, k, nx, ny)] * (xc - x[c + nx]);
+  const R xw = x[w ? c - 1 : c], xe = x[e ? c + 1 : c], xs = x[so ? c - nx : c], xn = x[no ? c + nx : c];
+  const R aw = ax[fidx<0>(i, j, k, nx, ny)], ae = ax[fidx<0>(i + 1, j, k, nx, ny)];
+  const R as = ay[fidx<1>(i, j, k, nx, ny)], an = ay[fidx<1>(i, j + 1, k, nx, ny)];
+  R xl = R(0), xh = R(0), al = R(0), ah = R(0);
   if (DIM == 3) {
-    const long pl = (long)nx * ny;
-    if (k > 0) s += az[fidx<2>(i, j, k, nx, ny)] * (xc - x[c - pl]);
-    if (k < nz - 1) s += az[fidx<2>(i, j, k + 1, nx, ny)] * (xc - x[c + pl]);
+    xl = x[lo ? c - pl : c];
+    xh = x[hi ? c + pl : c];
+    al = az[fidx<2>(i, j, k, nx, ny)];
+    ah = az[fidx<2>(i, j, k + 1, nx, ny)];
+  }
+  R s = R(0);
+  s = w ? s + aw * (xc - xw) : s;
+  s = e ? s + ae * (xc - xe) : s;
+  s = so ? s + as * (xc - xs) : s;
+  s = no ? s + an * (xc - xn) : s;
+  if (DIM == 3) {
+    s = lo ? s + al * (xc - xl) : s;
+    s = hi ? s + ah * (xc - xh) : s;
   }
   return s;
 }
@@ -447,8 +464,9 @@ __global__ __launch_bounds__(256) void k_smooth_first(long n, const R* __restric
 template <class R, int DIM>
 __device__ __forceinline__ R smooth_cell(const Level<R>& L, const R* __restrict__ b, const R* __restrict__ x, R om,
                                          int i, int j, int k, long c) {
+  const R wd = L.wdiag[c], bc = b[c];
   const R Kx = applyK<R, DIM>(x, L.ax, L.ay, L.az, i, j, k, L.nx, L.ny, L.nz);
-  return x[c] + om * L.wdiag[c] * (b[c] - Kx);
+  return x[c] + om * wd * (bc - Kx);
 }
 
 // residual b - K x of cell (i, j, k)
@@ -469,35 +487,52 @@ __device__ __forceinline__ R prolong_smooth_cell(const Level<R>& L, int cnx, int
   auto xp = [&](int ii, int jj, int kk) {
     return x[cidx(ii, jj, kk, nx, ny)] + omc * e[cidx(ii >> 1, jj >> 1, kk / kz, cnx, cny)];
   };
+  // (the loads of all faces go out together, as in applyK)
   const long c = cidx(i, j, k, nx, ny);
+  const R wd = L.wdiag[c], bc = b[c];
+  const bool w = i > 0, ea = i < nx - 1, so = j > 0, no = j < ny - 1;
+  const bool lo = DIM == 3 && k > 0, hi = DIM == 3 && k < nz - 1;
   const R xc = xp(i, j, k);
+  const R xw = xp(w ? i - 1 : i, j, k), xe = xp(ea ? i + 1 : i, j, k);
+  const R xs = xp(i, so ? j - 1 : j, k), xn = xp(i, no ? j + 1 : j, k);
+  const R aw = L.ax[fidx<0>(i, j, k, nx, ny)], ae = L.ax[fidx<0>(i + 1, j, k, nx, ny)];
+  const R as = L.ay[fidx<1>(i, j, k, nx, ny)], an = L.ay[fidx<1>(i, j + 1, k, nx, ny)];
   R s = R(0);
-  if (i > 0) s += L.ax[fidx<0>(i, j, k, nx, ny)] * (xc - xp(i - 1, j, k));
-  if (i < nx - 1) s += L.ax[fidx<0>(i + 1, j, k, nx, ny)] * (xc - xp(i + 1, j, k));
-  if (j > 0) s += L.ay[fidx<1>(i, j, k, nx, ny)] * (xc - xp(i, j - 1, k));
-  if (j < ny - 1) s += L.ay[fidx<1>(i, j + 1, k, nx, ny)] * (xc - xp(i, j + 1, k));
+  s = w ? s + aw * (xc - xw) : s;
+  s = ea ? s + ae * (xc - xe) : s;
+  s = so ? s + as * (xc - xs) : s;
+  s = no ? s + an * (xc - xn) : s;
   if (DIM == 3) {
-    if (k > 0) s += L.az[fidx<2>(i, j, k, nx, ny)] * (xc - xp(i, j, k - 1));
-    if (k < nz - 1) s += L.az[fidx<2>(i, j, k + 1, nx, ny)] * (xc - xp(i, j, k + 1));
+    const R xl = xp(i, j, lo ? k - 1 : k), xh = xp(i, j, hi ? k + 1 : k);
+    const R al = L.az[fidx<2>(i, j, k, nx, ny)], ah = L.az[fidx<2>(i, j, k + 1, nx, ny)];
+    s = lo ? s + al * (xc - xl) : s;
+    s = hi ? s + ah * (xc - xh) : s;
   }
-  return xc + om * L.wdiag[c] * (b[c] - s);
+  return xc + om * wd * (bc - s);
 }
 
 // damped Jacobi: xo = x + om wdiag (b - K x) (wdiag = 1 / diag); optional
 // partial of b.xo (= r.z on the finest level)
-template <class R, int DIM>
+template <class R, int DIM, bool LATE>
 __global__ __launch_bounds__(256) void k_smooth(Level<R> L, const R* __restrict__ b, const R* __restrict__ x,
                                                 R* __restrict__ xo, R om, double* __restrict__ part,
                                                 const int* __restrict__ iflag) {
-  if (iflag[I_DONE]) return;
+  const int done = iflag[I_DONE];
+  if (!LATE && done) return;
   __shared__ double sh[8];
   const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
+  const bool in = i < L.nx && j < L.ny;
+  const long c = in ? cidx(i, j, k, L.nx, L.ny) : 0;
+  R xn = R(0), bc = R(0);
+  if (in) {
+    xn = smooth_cell<R, DIM>(L, b, x, om, i, j, k, c);
+    bc = b[c];
+  }
+  if (done) return;
   double val = 0.0;
-  if (i < L.nx && j < L.ny) {
-    const long c = cidx(i, j, k, L.nx, L.ny);
-    const R xn = smooth_cell<R, DIM>(L, b, x, om, i, j, k, c);
+  if (in) {
     xo[c] = xn;
-    val = (double)b[c] * (double)xn;
+    val = (double)bc * (double)xn;
   }
   if (part) {
     const double s = block_reduce<0>(val, sh);
@@ -510,18 +545,23 @@ __global__ __launch_bounds__(256) void k_smooth(Level<R> L, const R* __restrict_
 // 3D): each thread computes the residuals of its column's kz cells into
 // LDS, then one thread per coarse cell of the tile (32 x 2) sums its
 // children in (dk, dj, di) order.
-template <class R, int DIM>
+template <class R, int DIM, bool LATE>
 __global__ __launch_bounds__(256) void k_resid_restrict(Level<R> F, int cnx, int cny, int cnz,
                                                         const R* __restrict__ b, const R* __restrict__ x,
                                                         R* __restrict__ bc, const R* __restrict__ wdc,
                                                         R* __restrict__ x1c, R om0, const int* __restrict__ iflag) {
-  if (iflag[I_DONE]) return;
+  const int done = iflag[I_DONE];
+  if (!LATE && done) return;
   constexpr int kz = DIM == 3 ? 2 : 1;
   __shared__ R rs[kz][BY][BX];
   const int tx = threadIdx.x, ty = threadIdx.y;
   const int i = blockIdx.x * BX + tx, j = blockIdx.y * BY + ty, K = blockIdx.z;
-  if (i < F.nx && j < F.ny)
-    for (int dk = 0; dk < kz; ++dk) rs[dk][ty][tx] = resid_cell<R, DIM>(F, b, x, i, j, kz * K + dk);
+  if (i < F.nx && j < F.ny) {
+    R rv[kz];
+    for (int dk = 0; dk < kz; ++dk) rv[dk] = resid_cell<R, DIM>(F, b, x, i, j, kz * K + dk);
+    for (int dk = 0; dk < kz; ++dk) rs[dk][ty][tx] = rv[dk];
+  }
+  if (done) return;
   __syncthreads();
   const int t = tx + BX * ty;
   if (t >= (BX / 2) * (BY / 2)) return;
@@ -538,20 +578,27 @@ __global__ __launch_bounds__(256) void k_resid_restrict(Level<R> F, int cnx, int
 }
 
 // x' = x + omega_c P e (on the fly), xo = x' + om wdiag (b - K x')
-template <class R, int DIM>
+template <class R, int DIM, bool LATE>
 __global__ __launch_bounds__(256) void k_prolong_smooth(Level<R> L, int cnx, int cny, const R* __restrict__ e,
                                                         const R* __restrict__ b, const R* __restrict__ x,
                                                         R* __restrict__ xo, R omc, R om, double* __restrict__ part,
                                                         const int* __restrict__ iflag) {
-  if (iflag[I_DONE]) return;
+  const int done = iflag[I_DONE];
+  if (!LATE && done) return;
   __shared__ double sh[8];
   const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
+  const bool in = i < L.nx && j < L.ny;
+  const long c = in ? cidx(i, j, k, L.nx, L.ny) : 0;
+  R xn = R(0), bv = R(0);
+  if (in) {
+    xn = prolong_smooth_cell<R, DIM>(L, cnx, cny, e, b, x, omc, om, i, j, k);
+    bv = b[c];
+  }
+  if (done) return;
   double val = 0.0;
-  if (i < L.nx && j < L.ny) {
-    const long c = cidx(i, j, k, L.nx, L.ny);
-    const R xn = prolong_smooth_cell<R, DIM>(L, cnx, cny, e, b, x, omc, om, i, j, k);
+  if (in) {
     xo[c] = xn;
-    val = (double)b[c] * (double)xn;
+    val = (double)bv * (double)xn;
   }
   if (part) {
     const double s = block_reduce<0>(val, sh);
@@ -763,7 +810,7 @@ static_assert(kTailPer * kTailThreads == kTailCells, "tail cells per thread");
 
 template <class R, int DIM>
 __global__ __launch_bounds__(kTailThreads) void k_mg_tail(MgTail<R> T, const int* __restrict__ iflag) {
-  if (iflag[I_DONE]) return;
+  const int done = iflag[I_DONE];  // tested after the first loads (one round trip for both)
   __shared__ R sm[kTailLds];
   const int t = threadIdx.x;
   const int kz = DIM == 3 ? 2 : 1;
@@ -804,6 +851,7 @@ __global__ __launch_bounds__(kTailThreads) void k_mg_tail(MgTail<R> T, const int
     R* b0 = Bv(0);
     R* x0 = X0(0);
     phase(n, b0, [&](int c) { return L.b[c]; });
+    if (done) return;
     if (T.first_done) phase(n, x0, [&](int c) { return L.x2[c]; });
     else phase(n, x0, [&](int c) { return R(T.wpre[0]) * L.wdiag[c] * b0[c]; });
   }
@@ -921,7 +969,9 @@ __global__ __launch_bounds__(1024) void k_finalize(const double* __restrict__ pa
                                                    double* __restrict__ scal, int* __restrict__ iflag, int op,
                                                    int slot, double arg) {
   __shared__ double sh[16];
-  if ((op == F_ALPHA || op == F_RR || op == F_RZ) && iflag[I_DONE]) return;
+  // the done flag is loaded with the partials and tested before the reduction
+  const bool gated = op == F_RR;
+  const int done = gated ? iflag[I_DONE] : 0;
   const int t = threadIdx.x, nt = blockDim.x;
   double v;
   if (op == F_MIN || op == F_MAX) {
@@ -934,6 +984,7 @@ __global__ __launch_bounds__(1024) void k_finalize(const double* __restrict__ pa
       a1 = op == F_MIN ? fmin(a1, p1) : fmax(a1, p1);
     }
     if (q < n) a0 = op == F_MIN ? fmin(a0, part[q]) : fmax(a0, part[q]);
+    if (done) return;
     v = op == F_MIN ? fmin(a0, a1) : fmax(a0, a1);
     v = op == F_MIN ? block_reduce<2>(v, sh) : block_reduce<1>(v, sh);
   } else {
@@ -946,6 +997,7 @@ __global__ __launch_bounds__(1024) void k_finalize(const double* __restrict__ pa
       a3 += part[q + 3 * nt];
     }
     for (; q < n; q += nt) a0 += part[q];
+    if (done) return;
     v = block_reduce<0>((a0 + a1) + (a2 + a3), sh);
   }
   if (t != 0) return;
@@ -953,14 +1005,11 @@ __global__ __launch_bounds__(1024) void k_finalize(const double* __restrict__ pa
     case F_STORE: case F_MIN: case F_MAX: scal[slot] = v; break;
     case F_MEAN: scal[slot] = v / arg; break;
     case F_BB: scal[S_BB] = v; scal[S_TOL2] = arg * v; break;
-    case F_ALPHA: scal[S_DQ] = v; scal[S_ALPHA] = scal[S_RZ] / v; break;
     case F_RR:
       scal[S_RR] = v;
       iflag[I_ITERS] += (int)arg;
       if (!(v > scal[S_TOL2])) iflag[I_DONE] = 1;   // also stops on NaN
       break;
-    case F_RZ_FIRST: scal[S_RZ] = v; scal[S_BETA] = 0.0; break;
-    case F_RZ: scal[S_BETA] = v / scal[S_RZ]; scal[S_RZ] = v; break;
     case F_SCALE: scal[S_RR64] = v; scal[S_SCALE] = sqrt(v / arg); break;
   }
 }
@@ -1435,6 +1484,13 @@ void update_d(hipStream_t s, long n, const double* scal, const R* z, R* d, int f
   hipLaunchKernelGGL((k_update_d<R>), dim3(nblk1(n)), dim3(256), 0, s, n, scal, z, d, first, iflag);
 }
 
+// Kernels of levels up to this many cells load the done flag together with
+// their data and test it before their first store (one memory round trip
+// before the stores instead of two); larger levels test it before loading,
+// so that a cycle queued after convergence reads nothing.
+constexpr long kLateFlagCells = 64L * 64 * 64;
+inline bool late_flag(long n) { return n <= kLateFlagCells; }
+
 template <class R>
 void mg_smooth_first(hipStream_t s, const Level<R>& L, const R* b, R* x, double om, const int* iflag) {
   hipLaunchKernelGGL((k_smooth_first<R>), dim3(nblk1(L.n())), dim3(256), 0, s, L.n(), L.wdiag, b, x, R(om), iflag);
@@ -1444,8 +1500,10 @@ template <class R>
 void mg_smooth(hipStream_t s, int dim, const Level<R>& L, const R* b, const R* x, R* xo, double om, double* part,
                const int* iflag) {
   dim3 g = grid_for(L.nx, L.ny, L.nz);
-  if (dim == 3) hipLaunchKernelGGL((k_smooth<R, 3>), g, blk(), 0, s, L, b, x, xo, R(om), part, iflag);
-  else hipLaunchKernelGGL((k_smooth<R, 2>), g, blk(), 0, s, L, b, x, xo, R(om), part, iflag);
+  auto go = [&](auto kern) { hipLaunchKernelGGL(kern, g, blk(), 0, s, L, b, x, xo, R(om), part, iflag); };
+  const bool late = late_flag(L.n());
+  if (dim == 3) late ? go(k_smooth<R, 3, true>) : go(k_smooth<R, 3, false>);
+  else late ? go(k_smooth<R, 2, true>) : go(k_smooth<R, 2, false>);
 }
 
 template <class R>
@@ -1453,22 +1511,22 @@ void mg_resid_restrict(hipStream_t s, int dim, const Level<R>& F, const R* b, co
                        R* x1c, double om0, const int* iflag) {
   const int cnx = F.nx / 2, cny = F.ny / 2, cnz = dim == 3 ? F.nz / 2 : 1;
   dim3 g = grid_for(F.nx, F.ny, cnz);  // blocks of fine tiles, one coarse plane each
-  if (dim == 3)
-    hipLaunchKernelGGL((k_resid_restrict<R, 3>), g, blk(), 0, s, F, cnx, cny, cnz, b, x, bc, wdc, x1c, R(om0), iflag);
-  else
-    hipLaunchKernelGGL((k_resid_restrict<R, 2>), g, blk(), 0, s, F, cnx, cny, cnz, b, x, bc, wdc, x1c, R(om0), iflag);
+  auto go = [&](auto kern) { hipLaunchKernelGGL(kern, g, blk(), 0, s, F, cnx, cny, cnz, b, x, bc, wdc, x1c, R(om0), iflag); };
+  const bool late = late_flag(F.n());
+  if (dim == 3) late ? go(k_resid_restrict<R, 3, true>) : go(k_resid_restrict<R, 3, false>);
+  else late ? go(k_resid_restrict<R, 2, true>) : go(k_resid_restrict<R, 2, false>);
 }
 
 template <class R>
 void mg_prolong_smooth(hipStream_t s, int dim, const Level<R>& F, const Level<R>& C, const R* b, const R* x, R* xo,
                        double omega_c, double om, double* part, const int* iflag) {
   dim3 g = grid_for(F.nx, F.ny, F.nz);
-  if (dim == 3)
-    hipLaunchKernelGGL((k_prolong_smooth<R, 3>), g, blk(), 0, s, F, C.nx, C.ny, C.x, b, x, xo, R(omega_c), R(om), part,
-                       iflag);
-  else
-    hipLaunchKernelGGL((k_prolong_smooth<R, 2>), g, blk(), 0, s, F, C.nx, C.ny, C.x, b, x, xo, R(omega_c), R(om), part,
-                       iflag);
+  auto go = [&](auto kern) {
+    hipLaunchKernelGGL(kern, g, blk(), 0, s, F, C.nx, C.ny, C.x, b, x, xo, R(omega_c), R(om), part, iflag);
+  };
+  const bool late = late_flag(F.n());
+  if (dim == 3) late ? go(k_prolong_smooth<R, 3, true>) : go(k_prolong_smooth<R, 3, false>);
+  else late ? go(k_prolong_smooth<R, 2, true>) : go(k_prolong_smooth<R, 2, false>);
 }
 
 template <class R>

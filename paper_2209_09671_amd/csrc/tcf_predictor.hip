@@ -461,7 +461,7 @@ __device__ __forceinline__ void pred_body(const PredArgs<R, DIM, D>& A, int kz, 
       const R fst = MAT ? fo.mL : R(0.5) * (fo.skL + fo.skR) * (alR - alL) * ih + R(0.5) * (fo.mL + fo.mR);
       const R rhof = MAT ? R(0.5) * (mixp(fo.skL, P.rho1, P.rho2) + mixp(fo.skR, P.rho1, P.rho2))
                          : R(0.5) * (mixp(alL, P.rho1, P.rho2) + mixp(alR, P.rho1, P.rho2));
-      A.out[fidx<D>(i, j, k, nx, ny)] = q[3] + dt * (-conv * ih + (visc * ih * ih + fst) / rhof);
+      A.out[fidx<D>(i, j, k, nx, ny)] = q[3] + dt * (-conv * ih + (visc * ih * ih + fst) * rcpx(rhof));
     } else if (act) {
       A.out[fidx<D>(i, j, k, nx, ny)] = R(0);
     }

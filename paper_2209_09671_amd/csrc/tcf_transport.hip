@@ -41,6 +41,10 @@ constexpr int NE = TY + TX;                     // tile-edge faces of a plane: x
 // FMAs per indicator.
 __device__ __forceinline__ float rcpx(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ double rcpx(double x) { return 1.0 / x; }
+// square root: the hardware instruction in FP32 (within an ulp), correctly
+// rounded in FP64
+__device__ __forceinline__ float sqrtx(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ double sqrtx(double x) { return sqrt(x); }
 
 template <class R>
 __device__ __forceinline__ R weno5x(R a, R b, R c, R d, R e, R epsw) {
@@ -376,11 +380,12 @@ __global__ __launch_bounds__(512) void k_transport2(KParams P, int kz, int ntx, 
           const R gy = (sa[buf][Y + 1][X] - sa[buf][Y - 1][X]) * h2;
           const R gz = DIM == 3 ? (qa[4] - qa[2]) * h2 : R(0);
           const R g2 = gx * gx + gy * gy + gz * gz;
-          const R ne = R(P.neps);
-          const R ds = g2 / (sqrt(g2 + ne * ne) + ne);
-          src = qcol * ds;
+          if (g2 != R(0)) {  // delta_s vanishes off the interface (skipped by whole wavefronts there)
+            const R ne = R(P.neps);
+            src = qcol * (g2 * rcpx(sqrtx(g2 + ne * ne) + ne));
+          }
         }
-        const R LT = -divt * ih + (cond + src) / (MODE == 2 ? rcc : mixp(ac, P.rhocp1, P.rhocp2));
+        const R LT = -divt * ih + (cond + src) * rcpx(MODE == 2 ? rcc : mixp(ac, P.rhocp1, P.rhocp2));
         To[c] = cb * Tbc + ci * (Tc + dt * LT);
       }
     }
