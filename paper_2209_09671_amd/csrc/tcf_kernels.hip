@@ -701,7 +701,7 @@ template <class R, int DIM>
 __global__ __launch_bounds__(1024) void k_coarse_factor_lds(Level<R> L, R* __restrict__ Minv) {
   constexpr int LD = kCoarseLdsMax + 1;
   __shared__ double A[kCoarseLdsMax * LD];
-  __shared__ double col[kCoarseLdsMax], prow[kCoarseLdsMax];
+  __shared__ double col[kCoarseLdsMax], prow[kCoarseLdsMax], spj[kCoarseLdsMax];
   __shared__ double sh[16];
   const int n = (int)L.n();
   const int t = threadIdx.x, nt = blockDim.x;
@@ -710,19 +710,28 @@ __global__ __launch_bounds__(1024) void k_coarse_factor_lds(Level<R> L, R* __res
   double dsum = 0.0;
   for (int c = t; c < n; c += nt) {
     const int i = c % L.nx, j = (c / L.nx) % L.ny, k = c / (L.nx * L.ny);
+    // all six face weights are loaded before any is used (every index is in
+    // bounds; walls are dropped below)
+    const double w0 = (double)L.ax[fidx<0>(i, j, k, L.nx, L.ny)], w1 = (double)L.ax[fidx<0>(i + 1, j, k, L.nx, L.ny)];
+    const double w2 = (double)L.ay[fidx<1>(i, j, k, L.nx, L.ny)], w3 = (double)L.ay[fidx<1>(i, j + 1, k, L.nx, L.ny)];
+    double w4 = 0.0, w5 = 0.0;
+    if (DIM == 3) {
+      w4 = (double)L.az[fidx<2>(i, j, k, L.nx, L.ny)];
+      w5 = (double)L.az[fidx<2>(i, j, k + 1, L.nx, L.ny)];
+    }
     double d = 0.0;
     auto off = [&](int nb, double w) {
       A[c * LD + nb] = -w;
       d += w;
     };
-    if (i > 0) off(c - 1, (double)L.ax[fidx<0>(i, j, k, L.nx, L.ny)]);
-    if (i < L.nx - 1) off(c + 1, (double)L.ax[fidx<0>(i + 1, j, k, L.nx, L.ny)]);
-    if (j > 0) off(c - L.nx, (double)L.ay[fidx<1>(i, j, k, L.nx, L.ny)]);
-    if (j < L.ny - 1) off(c + L.nx, (double)L.ay[fidx<1>(i, j + 1, k, L.nx, L.ny)]);
+    if (i > 0) off(c - 1, w0);
+    if (i < L.nx - 1) off(c + 1, w1);
+    if (j > 0) off(c - L.nx, w2);
+    if (j < L.ny - 1) off(c + L.nx, w3);
     if (DIM == 3) {
       const int pl = L.nx * L.ny;
-      if (k > 0) off(c - pl, (double)L.az[fidx<2>(i, j, k, L.nx, L.ny)]);
-      if (k < L.nz - 1) off(c + pl, (double)L.az[fidx<2>(i, j, k + 1, L.nx, L.ny)]);
+      if (k > 0) off(c - pl, w4);
+      if (k < L.nz - 1) off(c + pl, w5);
     }
     A[c * LD + c] = d;
     dsum += d;
@@ -741,6 +750,9 @@ __global__ __launch_bounds__(1024) void k_coarse_factor_lds(Level<R> L, R* __res
     const int i = i0 + 16 * r;
     m[r] = i < n && jj < n ? A[i * LD + jj] : 0.0;
   }
+  // The scaled pivot row is formed once per column (by the pivot row's
+  // owners) and read by all: one division per column and step instead of
+  // one per element.
   for (int p = 0; p < n; ++p) {
     const int rp = p >> 4;
     if (jj == p) {
@@ -750,8 +762,10 @@ __global__ __launch_bounds__(1024) void k_coarse_factor_lds(Level<R> L, R* __res
     }
     if ((p & 15) == i0 && jj < n) prow[jj] = rp == 0 ? m[0] : (rp == 1 ? m[1] : (rp == 2 ? m[2] : m[3]));
     __syncthreads();
+    if ((p & 15) == i0 && jj < n) spj[jj] = (jj == p ? 1.0 : prow[jj]) / col[p];
+    __syncthreads();
     if (jj < n) {
-      const double pj = (jj == p ? 1.0 : prow[jj]) / col[p];  // the scaled pivot row
+      const double pj = spj[jj];
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int i = i0 + 16 * r;
