@@ -607,36 +607,20 @@ __global__ __launch_bounds__(FX * TYK) void k0_smooth2(Op0<R> op, int kz, int nt
         if (!in1[m]) continue;
         const int l = li[m];
         const R rc = sr[sc][l], xc = sx[sc][l];
-        R s = R(0), d = R(0), wv[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
-        if (gi1[m] > 0) {
-          wv[0] = coef(R(op.c2), rc + sr[sc][l - 1]);
-          s += wv[0] * (xc - sx[sc][l - 1]);
-          d += wv[0];
-        }
-        if (gi1[m] < nx - 1) {
-          wv[1] = coef(R(op.c2), rc + sr[sc][l + 1]);
-          s += wv[1] * (xc - sx[sc][l + 1]);
-          d += wv[1];
-        }
-        if (gj1[m] > 0) {
-          wv[2] = coef(R(op.c2), rc + sr[sc][l - RX2]);
-          s += wv[2] * (xc - sx[sc][l - RX2]);
-          d += wv[2];
-        }
-        if (gj1[m] < ny - 1) {
-          wv[3] = coef(R(op.c2), rc + sr[sc][l + RX2]);
-          s += wv[3] * (xc - sx[sc][l + RX2]);
-          d += wv[3];
-        }
-        if (k > 0) {
-          wv[4] = coef(R(op.c2), sr[sm][l] + rc);
-          s += wv[4] * (xc - sx[sm][l]);
-          d += wv[4];
-        }
-        if (k < nz - 1) {
-          wv[5] = coef(R(op.c2), rc + sr[sp][l]);
-          s += wv[5] * (xc - sx[sp][l]);
-          d += wv[5];
+        // every face is evaluated (the region holds clamped values beyond a
+        // wall) and a wall face is dropped by a select, not a branch: no
+        // exec-mask updates per face
+        const bool on[6] = {gi1[m] > 0, gi1[m] < nx - 1, gj1[m] > 0, gj1[m] < ny - 1, k > 0, k < nz - 1};
+        const int off[6] = {-1, 1, -RX2, RX2, 0, 0};
+        R s = R(0), d = R(0), wv[6];
+#pragma unroll
+        for (int f = 0; f < 6; ++f) {
+          const R rn = f < 4 ? sr[sc][l + off[f]] : (f == 4 ? sr[sm][l] : sr[sp][l]);
+          const R xn = f < 4 ? sx[sc][l + off[f]] : (f == 4 ? sx[sm][l] : sx[sp][l]);
+          const R wf = coef(R(op.c2), f == 4 ? rn + rc : rc + rn);
+          wv[f] = on[f] ? wf : R(0);
+          s = on[f] ? s + wf * (xc - xn) : s;
+          d = on[f] ? d + wf : d;
         }
         const R bc = sb[sc][l];
         const R x1 = xc + om1 * recip(d) * (bc - s);
@@ -659,13 +643,15 @@ __global__ __launch_bounds__(FX * TYK) void k0_smooth2(Op0<R> op, int kz, int nt
     const int k2 = k - 1;
     if (own && k2 >= k0 && k2 < k1 && pin) {
       const int l = li[0], sl = k2 & 1;
+      // selects, as in the first sweep (a first-sweep value beyond a wall
+      // is never computed, so it must not reach the sum even times zero)
       R s = R(0);
-      if (T.i > 0) s += pw[0] * (px1 - s1[sl][l - 1]);
-      if (T.i < nx - 1) s += pw[1] * (px1 - s1[sl][l + 1]);
-      if (T.j > 0) s += pw[2] * (px1 - s1[sl][l - RX2]);
-      if (T.j < ny - 1) s += pw[3] * (px1 - s1[sl][l + RX2]);
-      if (k2 > 0) s += pw[4] * (px1 - px1m);
-      if (k2 < nz - 1) s += pw[5] * (px1 - x1own);
+      s = T.i > 0 ? s + pw[0] * (px1 - s1[sl][l - 1]) : s;
+      s = T.i < nx - 1 ? s + pw[1] * (px1 - s1[sl][l + 1]) : s;
+      s = T.j > 0 ? s + pw[2] * (px1 - s1[sl][l - RX2]) : s;
+      s = T.j < ny - 1 ? s + pw[3] * (px1 - s1[sl][l + RX2]) : s;
+      s = k2 > 0 ? s + pw[4] * (px1 - px1m) : s;
+      s = k2 < nz - 1 ? s + pw[5] * (px1 - x1own) : s;
       const R x2 = px1 + om2 * recip(pdg) * (pb - s);
       xo[(long)T.i + (long)nx * T.j + pl * k2] = x2;
       acc += (double)pb * (double)x2;
