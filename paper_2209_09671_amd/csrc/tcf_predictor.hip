@@ -389,9 +389,18 @@ __device__ __forceinline__ void pred_body(const PredArgs<R, DIM, D>& A, int kz, 
     for (int qq = 0; qq < 2; ++qq) {
       if (qq < nxi) {
         R F = R(0), T_ = R(0);
-        if (xon[qq]) {
+        if (qq == 0) {
+          // every thread's first item is evaluated (its operands and LDS
+          // row are always valid) and kept by a select: no exec-mask
+          // updates around the evaluation
+          const R* rw = &sU[buf][xr[0] + H][xm[0]];
+          R Fv, Tv;
+          flux_pair<R, D, 0>(P, xo, rw[0], rw[1], rw[2], rw[3], rw[4], rw[5], eps, Fv, Tv);
+          F = xon[0] ? Fv : R(0);
+          T_ = xon[0] ? Tv : R(0);
+        } else if (xon[qq]) {
           const R* rw = &sU[buf][xr[qq] + H][xm[qq]];
-          flux_pair<R, D, 0>(P, qq == 0 ? xo : x2, rw[0], rw[1], rw[2], rw[3], rw[4], rw[5], eps, F, T_);
+          flux_pair<R, D, 0>(P, x2, rw[0], rw[1], rw[2], rw[3], rw[4], rw[5], eps, F, T_);
         }
         if (xr[qq] < TY) {
           fxF[xr[qq]][xm[qq]] = F;
@@ -403,9 +412,15 @@ __device__ __forceinline__ void pred_body(const PredArgs<R, DIM, D>& A, int kz, 
     for (int qq = 0; qq < 2; ++qq) {
       if (qq < nyi) {
         R F = R(0), T_ = R(0);
-        if (yon[qq]) {
-          const int Y = yr[qq] + H, X = tx + H;
-          flux_pair<R, D, 1>(P, qq == 0 ? yo : y2, sU[buf][Y - 3][X], sU[buf][Y - 2][X], sU[buf][Y - 1][X], sU[buf][Y][X],
+        const int Y = yr[qq] + H, X = tx + H;
+        if (qq == 0) {  // as for the x items
+          R Fv, Tv;
+          flux_pair<R, D, 1>(P, yo, sU[buf][Y - 3][X], sU[buf][Y - 2][X], sU[buf][Y - 1][X], sU[buf][Y][X],
+                             sU[buf][Y + 1][X], sU[buf][Y + 2][X], eps, Fv, Tv);
+          F = yon[0] ? Fv : R(0);
+          T_ = yon[0] ? Tv : R(0);
+        } else if (yon[qq]) {
+          flux_pair<R, D, 1>(P, y2, sU[buf][Y - 3][X], sU[buf][Y - 2][X], sU[buf][Y - 1][X], sU[buf][Y][X],
                              sU[buf][Y + 1][X], sU[buf][Y + 2][X], eps, F, T_);
         }
         fyF[yr[qq]][tx] = F;

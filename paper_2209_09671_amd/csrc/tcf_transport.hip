@@ -284,21 +284,24 @@ __global__ __launch_bounds__(512) void k_transport2(KParams P, int kz, int ntx, 
     const size_t c = (size_t)k * pl + co;
     if (act) {
       const int X = tx + H, Y = ty + H;
-      if (i > 0) {
-        if (WA)
-          Fxa_lo = ulo * upw(sa[buf][Y][X - 3], sa[buf][Y][X - 2], sa[buf][Y][X - 1], sa[buf][Y][X], sa[buf][Y][X + 1],
-                           sa[buf][Y][X + 2], ulo, eps);
-        if (WT)
-          Fxt_lo = ulo * upw(sT[buf][Y][X - 3], sT[buf][Y][X - 2], sT[buf][Y][X - 1], sT[buf][Y][X],
-                             sT[buf][Y][X + 1], sT[buf][Y][X + 2], ulo, eps);
+      // the low x- and y-face fluxes are evaluated on every active cell (the
+      // tile holds the ghost values there) and the wall faces are dropped by
+      // selects, without exec-mask updates around the evaluations
+      if (WA) {
+        const R fx = ulo * upw(sa[buf][Y][X - 3], sa[buf][Y][X - 2], sa[buf][Y][X - 1], sa[buf][Y][X],
+                               sa[buf][Y][X + 1], sa[buf][Y][X + 2], ulo, eps);
+        const R fy = vlo * upw(sa[buf][Y - 3][X], sa[buf][Y - 2][X], sa[buf][Y - 1][X], sa[buf][Y][X],
+                               sa[buf][Y + 1][X], sa[buf][Y + 2][X], vlo, eps);
+        Fxa_lo = i > 0 ? fx : R(0);
+        Fya_lo = j > 0 ? fy : R(0);
       }
-      if (j > 0) {
-        if (WA)
-          Fya_lo = vlo * upw(sa[buf][Y - 3][X], sa[buf][Y - 2][X], sa[buf][Y - 1][X], sa[buf][Y][X], sa[buf][Y + 1][X],
-                           sa[buf][Y + 2][X], vlo, eps);
-        if (WT)
-          Fyt_lo = vlo * upw(sT[buf][Y - 3][X], sT[buf][Y - 2][X], sT[buf][Y - 1][X], sT[buf][Y][X],
-                             sT[buf][Y + 1][X], sT[buf][Y + 2][X], vlo, eps);
+      if (WT) {
+        const R fx = ulo * upw(sT[buf][Y][X - 3], sT[buf][Y][X - 2], sT[buf][Y][X - 1], sT[buf][Y][X],
+                               sT[buf][Y][X + 1], sT[buf][Y][X + 2], ulo, eps);
+        const R fy = vlo * upw(sT[buf][Y - 3][X], sT[buf][Y - 2][X], sT[buf][Y - 1][X], sT[buf][Y][X],
+                               sT[buf][Y + 1][X], sT[buf][Y + 2][X], vlo, eps);
+        Fxt_lo = i > 0 ? fx : R(0);
+        Fyt_lo = j > 0 ? fy : R(0);
       }
       if (WA) fya[ty][tx] = Fya_lo;
       if (WT) fyt[ty][tx] = Fyt_lo;
