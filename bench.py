@@ -43,7 +43,7 @@ FAMILIES = ("transport", "smooth2", "smooth", "update", "spmv", "predictor", "re
 KERNEL_NAMES = {"transport": "k_transport2<float,3,1>", "smooth": "k0_smooth<float,3,false>",
                 "smooth2": "k0_smooth2<float,true,8>",
                 "update": "k0_update_smooth<float,3>", "spmv": "k0_spmv_upd<float,3>",
-                "predictor": "k_pred2_f<float,3,*>", "resid64": "k0_resid64<float,3>",
+                "predictor": "k_pred2_f<float,3,0..2> (the three components)", "resid64": "k0_resid64<float,3>",
                 "project": "k_project_diag<float,3>", "geometry": "k_geometry_z<float>",
                 "species": "k_transport2<float,3,0>"}
 
@@ -74,8 +74,9 @@ def algorithmic_bytes(family: str, c: dict) -> float:
     if family == "species":
         return N * w * (1 + nf + 2 / 3 + 1)
     if family == "predictor":
-        # per component: alpha, sigma*kappa, M_d and the nf velocities read; u*_d written
-        return N * w * (3 + nf + 1)
+        # one timed launch is the three (two) component kernels; per component:
+        # alpha, sigma*kappa, M_d and the nf velocities read; u*_d written
+        return N * w * nf * (3 + nf + 1)
     if family == "resid64":
         # FP64 refinement residual: b, p (FP64), alpha read; r (FP64) written
         return N * (8 + 8 + w + 8)
@@ -123,6 +124,25 @@ def measured_traffic(family: str, workload: str):
     if not m or not b or m.group(1) != kernel_source_hash():
         return None
     return float(b.group(1))
+
+
+def measured_valu_busy(kernel: str, workload: str):
+    """Fraction of the SIMD cycles a kernel issues VALU work in, from the
+    committed SQ counter summary, if it was taken on the current kernel
+    sources (else None)."""
+    path = os.path.join(ROOT, "profiles", f"sq_valu_{workload}.md")
+    if not os.path.exists(path):
+        return None
+    txt = open(path).read()
+    m = re.search(r"kernel_source_sha256_16:\s*([0-9a-f]+)", txt)
+    if not m or m.group(1) != kernel_source_hash():
+        return None
+    want = kernel.replace(" ", "")
+    for line in txt.splitlines():
+        cells = [x.strip() for x in line.strip().strip("|").split("|")]
+        if len(cells) >= 5 and cells[0].replace(" ", "") == want and cells[4].endswith("%"):
+            return float(cells[4][:-1]) / 100.0
+    return None
 
 
 def host_cpu():
@@ -380,7 +400,8 @@ def main():
                 "frac": k["frac"], "traffic": measured_traffic(dom, workload_tag),
                 "kernel": dom, "kernel_name": k["kernel"], "avg_launch_ms": k["avg_launch_ms"],
                 "launches_per_step": k["launches_per_step"], "ms_per_step": k["ms_per_step"],
-                "algorithmic_bytes_per_launch": k["algorithmic_bytes_per_launch"]}
+                "algorithmic_bytes_per_launch": k["algorithmic_bytes_per_launch"],
+                "valu_busy": measured_valu_busy(k["kernel"], workload_tag)}
     b32 = step_bytes_per_cell(r32["iters"], r32["refs"], 1)
     step_hbm = {"model": "(42 + 26 n_it) 4 + (8 + 28 n_ref) B per cell-step",
                 "bytes_per_cell_step": round(b32, 1),
