@@ -71,14 +71,16 @@ __device__ double weno5_g(double a, double b, double c, double d, double e, doub
   const double e0 = eps + ((13.0 / 12.0) * t0 * t0 + 0.25 * u0 * u0);
   const double e1 = eps + ((13.0 / 12.0) * t1 * t1 + 0.25 * u1 * u1);
   const double e2 = eps + ((13.0 / 12.0) * t2 * t2 + 0.25 * u2 * u2);
-  const double a0 = 0.1 / (e0 * e0), a1 = 0.6 / (e1 * e1), a2 = 0.3 / (e2 * e2);
-  const double S = a0 + a1 + a2;
-  const double W = (a0 * q0 + a1 * q1 + a2 * q2) / S;
-  const double w0 = a0 / S, w1 = a1 / S, w2 = a2 / S;
+  // four reciprocals (1/e_k, 1/S), the rest by multiplication
+  const double ie0 = 1.0 / e0, ie1 = 1.0 / e1, ie2 = 1.0 / e2;
+  const double a0 = 0.1 * ie0 * ie0, a1 = 0.6 * ie1 * ie1, a2 = 0.3 * ie2 * ie2;
+  const double S = a0 + a1 + a2, iS = 1.0 / S;
+  const double W = (a0 * q0 + a1 * q1 + a2 * q2) * iS;
+  const double w0 = a0 * iS, w1 = a1 * iS, w2 = a2 * iS;
   // coefficients c_k = -(2/S)(q_k - W) a_k / e_k multiply dbeta_k/dx
-  const double c0 = -2.0 / S * (q0 - W) * a0 / e0;
-  const double c1 = -2.0 / S * (q1 - W) * a1 / e1;
-  const double c2 = -2.0 / S * (q2 - W) * a2 / e2;
+  const double c0 = -2.0 * iS * (q0 - W) * a0 * ie0;
+  const double c1 = -2.0 * iS * (q1 - W) * a1 * ie1;
+  const double c2 = -2.0 * iS * (q2 - W) * a2 * ie2;
   // dbeta0/d(a,b,c) = 13/6 t0 (1,-2,1) + 1/2 u0 (1,-4,3)
   const double b0a = (13.0 / 6.0) * t0 + 0.5 * u0, b0b = -(13.0 / 3.0) * t0 - 2.0 * u0,
                b0c = (13.0 / 6.0) * t0 + 1.5 * u0;
@@ -95,16 +97,20 @@ __device__ double weno5_g(double a, double b, double c, double d, double e, doub
   return W;
 }
 
-// q[k] = Q(f-3+k), k = 0..5; upwind value at face f and its gradient gq[0..5]
+// q[k] = Q(f-3+k), k = 0..5; upwind value at face f and its gradient gq[0..5].
+// The stencil is picked by the sign before the one evaluation (and the
+// gradient mapped back), so the lanes of a wavefront with both signs share it.
 __device__ __forceinline__ double upwind_g(const double* q, double vel, double eps, double gq[6]) {
   double g[5];
-  if (vel >= 0.0) {
-    const double W = weno5_g(q[0], q[1], q[2], q[3], q[4], eps, g);
-    gq[0] = g[0]; gq[1] = g[1]; gq[2] = g[2]; gq[3] = g[3]; gq[4] = g[4]; gq[5] = 0.0;
-    return W;
-  }
-  const double W = weno5_g(q[5], q[4], q[3], q[2], q[1], eps, g);
-  gq[0] = 0.0; gq[1] = g[4]; gq[2] = g[3]; gq[3] = g[2]; gq[4] = g[1]; gq[5] = g[0];
+  const bool pos = vel >= 0.0;
+  const double W = weno5_g(pos ? q[0] : q[5], pos ? q[1] : q[4], pos ? q[2] : q[3], pos ? q[3] : q[2],
+                           pos ? q[4] : q[1], eps, g);
+  gq[0] = pos ? g[0] : 0.0;
+  gq[1] = pos ? g[1] : g[4];
+  gq[2] = pos ? g[2] : g[3];
+  gq[3] = pos ? g[3] : g[2];
+  gq[4] = pos ? g[4] : g[1];
+  gq[5] = pos ? 0.0 : g[0];
   return W;
 }
 
