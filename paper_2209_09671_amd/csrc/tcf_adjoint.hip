@@ -221,11 +221,14 @@ __global__ __launch_bounds__(256) void ka_rhs_face(KParams P, const double* __re
 // terms gathered in LDS first (one kernel doing all of it per face issued
 // ~50 FP64 atomics per face at 176 VGPRs, two waves per SIMD).
 //
-// ka_pred_face<DIM, D>: per face, the terms that do not depend on a flux
-// direction: the direct term u*_f = u_f + ..., the CSF force (sigma kappa,
-// M and the alpha difference), and the face density 1/rho_f (whose
-// derivative needs the forward viscous term: the direction kernels below
-// leave it, summed over the directions in their order, in vsum).
+// ka_pred_face<DIM, D>: the terms that do not depend on a flux direction:
+// the direct term u*_f = u_f + ..., the CSF force (sigma kappa, M and the
+// alpha difference), and the face density 1/rho_f (whose derivative needs
+// the forward viscous term: the direction kernels below leave it, summed
+// over the directions in their order, in vsum).  One thread per cell
+// gathers the terms of its two D-faces into its own sigma kappa, M and
+// alpha adjoints (each face's terms recomputed by both of its cells), and
+// the cell after a face adds that face's direct term: no atomics.
 
 // Box over a block's faces (one LDS array of doubles): origin and extent in
 // the virtual index space of the target array (ghost positions included).
@@ -248,35 +251,40 @@ __global__ __launch_bounds__(256) void ka_pred_face(KParams P, const double* __r
                                                     double* __restrict__ skbar, double* __restrict__ Mbar) {
   const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
   const int nx = P.nx, ny = P.ny, nz = P.nz;
-  const int fnx = nx + (D == 0), fny = ny + (D == 1);
-  if (i >= fnx || j >= fny) return;
+  if (i >= nx || j >= ny) return;
   const int id[3] = {i, j, k};
   const int nD = D == 0 ? nx : (D == 1 ? ny : nz);
-  if (id[D] == 0 || id[D] == nD) return;
-  const long fo = fidx<D>(i, j, k, nx, ny);
-  const double ob = usb[fo];
-  if (ob == 0.0) return;
   const double ih = P.ih, dt = P.dt;
-  int L[3] = {i, j, k};
-  L[D] -= 1;
-  const long cL = cidx(L[0], L[1], L[2], nx, ny), cR = cidx(i, j, k, nx, ny);
-  const double aL = a[cL], aR = a[cR];
-  const double fst = 0.5 * (sk[cL] + sk[cR]) * (aR - aL) * ih + 0.5 * (M[cL] + M[cR]);
-  const double rhof = 0.5 * (mix1(aL, P.rho1, P.rho2) + mix1(aR, P.rho1, P.rho2));
-  const double visc = vsum[fo];  // the forward viscous term, summed over the directions by ka_pred_dir
-  aadd(&udb[fo], ob);  // direct term
-  const double fstb = dt * ob / rhof;
-  const double rhofb = -dt * ob * (visc + fst) / (rhof * rhof);
-  double aLb = rhofb * 0.5 * (P.rho2 - P.rho1) * dclamp(aL);
-  double aRb = rhofb * 0.5 * (P.rho2 - P.rho1) * dclamp(aR);
-  aadd(&skbar[cL], fstb * 0.5 * (aR - aL) * ih);
-  aadd(&skbar[cR], fstb * 0.5 * (aR - aL) * ih);
-  aRb += fstb * 0.5 * (sk[cL] + sk[cR]) * ih;
-  aLb -= fstb * 0.5 * (sk[cL] + sk[cR]) * ih;
-  aadd(&Mbar[cL], 0.5 * fstb);
-  aadd(&Mbar[cR], 0.5 * fstb);
-  aadd(&abar[cL], aLb);
-  aadd(&abar[cR], aRb);
+  const long c = cidx(i, j, k, nx, ny);
+  double skb = 0.0, Mb = 0.0, ab = 0.0;
+  // side 0: the face below the cell (the cell is its R), side 1: the face above (L)
+#pragma unroll
+  for (int side = 0; side < 2; ++side) {
+    const int fD = id[D] + side;
+    if (fD == 0 || fD == nD) continue;  // wall faces carry no terms
+    int F[3] = {i, j, k};
+    F[D] = fD;
+    const long fo = fidx<D>(F[0], F[1], F[2], nx, ny);
+    const double ob = usb[fo];
+    if (ob == 0.0) continue;
+    int L[3] = {F[0], F[1], F[2]};
+    L[D] -= 1;
+    const long cL = cidx(L[0], L[1], L[2], nx, ny), cR = cidx(F[0], F[1], F[2], nx, ny);
+    const double aL = a[cL], aR = a[cR];
+    const double fst = 0.5 * (sk[cL] + sk[cR]) * (aR - aL) * ih + 0.5 * (M[cL] + M[cR]);
+    const double rhof = 0.5 * (mix1(aL, P.rho1, P.rho2) + mix1(aR, P.rho1, P.rho2));
+    const double visc = vsum[fo];  // the forward viscous term, summed over the directions by ka_pred_dir
+    if (side == 0) udb[fo] += ob;  // direct term, added once by the cell after the face
+    const double fstb = dt * ob / rhof;
+    const double rhofb = -dt * ob * (visc + fst) / (rhof * rhof);
+    skb += fstb * 0.5 * (aR - aL) * ih;
+    Mb += 0.5 * fstb;
+    if (side == 0) ab += rhofb * 0.5 * (P.rho2 - P.rho1) * dclamp(aR) + fstb * 0.5 * (sk[cL] + sk[cR]) * ih;
+    else ab += rhofb * 0.5 * (P.rho2 - P.rho1) * dclamp(aL) - fstb * 0.5 * (sk[cL] + sk[cR]) * ih;
+  }
+  skbar[c] += skb;
+  Mbar[c] += Mb;
+  abar[c] += ab;
 }
 
 // ka_pred_dir<DIM, D, E>: per face of component D, the reverse of its
@@ -554,7 +562,7 @@ __global__ __launch_bounds__(256) void ka_geom_cell(KParams P, const double* __r
     }
     const long ec = eidx(i, j, k, nx, ny, oz);
     for (int d = 0; d < DIM; ++d) aadd(&nbs[d][ec], nb[d]);
-    aadd(&dsb[ec], dsbar);
+    dsb[ec] += dsbar;  // written by its own cell only in this kernel
   }
   const double r = block_reduce<0>(sacc, sh);
   if (threadIdx.x == 0 && threadIdx.y == 0) spart[block_linear()] = r;
@@ -703,13 +711,12 @@ __global__ __launch_bounds__(256) void ka_transport_cell(KParams P, const double
   if (i >= nx || j >= ny) return;
   const long c = cidx(i, j, k, nx, ny);
   const double dt = P.dt, ih = P.ih, ih2 = ih * ih;
-  aadd(&ab[c], wa[c]);
-  aadd(&Tb[c], wT[c]);
+  const double wac = wa[c], wTc = wT[c];
   const double ac = a[c], Tc = T[c];
   const double rcp = mix1(ac, P.rhocp1, P.rhocp2);
   const double lc = mix1(ac, P.lam1, P.lam2);
   const double dl = (P.lam2 - P.lam1) * dclamp(ac);
-  const double wc = dt * wT[c] / rcp;  // adjoint weight of cond_c and src_c
+  const double wc = dt * wTc / rcp;  // adjoint weight of cond_c and src_c
   double cond = 0.0, abc = 0.0, Tbc = 0.0;
   const int di[6] = {-1, 1, 0, 0, 0, 0}, dj[6] = {0, 0, -1, 1, 0, 0}, dk[6] = {0, 0, 0, 0, -1, 1};
   for (int f = 0; f < 2 * DIM; ++f) {
@@ -756,8 +763,11 @@ __global__ __launch_bounds__(256) void ka_transport_cell(KParams P, const double
   }
   // rho c_p in the denominator
   abc += -wc * (cond + src) * (P.rhocp2 - P.rhocp1) * dclamp(ac) / rcp;
-  aadd(&ab[c], abc);
-  aadd(&Tb[c], Tbc);
+  // the identity part and this cell's terms in one update each: in this
+  // kernel Tb[c] is written by its own thread only (a plain update), ab[c]
+  // also by the heat-source terms of the neighbours (an atomic)
+  aadd(&ab[c], wac + abc);
+  Tb[c] += wTc + Tbc;
 }
 
 // y = s * x ; y += s * x
@@ -825,7 +835,7 @@ void pred_component(const KParams& P, hipStream_t s, const double* a, const doub
   pred_dir<DIM, D, 0>(P, s, a, vel, velb, usb, abar, vsum);
   pred_dir<DIM, D, 1>(P, s, a, vel, velb, usb, abar, vsum);
   if constexpr (DIM == 3) pred_dir<DIM, D, 2>(P, s, a, vel, velb, usb, abar, vsum);
-  const dim3 g = grid_of(P.nx + (D == 0), P.ny + (D == 1), DIM == 3 ? P.nz + (D == 2) : 1);
+  const dim3 g = grid_of(P.nx, P.ny, DIM == 3 ? P.nz : 1);  // one thread per cell
   hipLaunchKernelGGL((ka_pred_face<DIM, D>), g, dim3(BX, BY), 0, s, P, a, sk, M, vsum, usb, velb[D], abar, skbar,
                      Mbar);
 }
