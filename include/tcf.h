@@ -263,6 +263,28 @@ tcf_status tcf_apply_A(tcf_grid* g, const double* x, double* y);
 tcf_status tcf_step_backward(tcf_grid* g, double t_n, double dt, const double* const state_n[6],
                              const double* const adj_np1[5], double* const adj_n[5], double* dL_dsigmaT);
 
+/* The same adjoint step with the forward step's intermediates supplied
+ * instead of recomputed (a checkpointed rollout replays each segment anyway):
+ *   tcf_step_keep: one forward step exactly as tcf_step(g, dt, 1, NULL) on a
+ *     TCF_WITH_ADJOINT grid, which also writes the transport's stage values
+ *     alpha^(1), T^(1), alpha^(2), T^(2) (SSP-RK3 stages 1 and 2, device FP64,
+ *     nx*ny*nz each, caller-owned, distinct and not the grid's own arrays)
+ *     into stages[0..3]; the transport writes them there directly.
+ *   tcf_step_backward_kept: tcf_step_backward(g, t_n, dt, state_n, adj_np1,
+ *     adj_n, dL_dsigmaT) given stages (from tcf_step_keep of this step) and
+ *     state_np1 = alpha, T, p of step n+1 (the state that step produced).
+ *     Only the interface geometry and the pressure operator of step n+1 are
+ *     recomputed; the transport, predictor and forward solve are not run.
+ *     The result equals tcf_step_backward's to rounding when the inputs are
+ *     those of one forward step (other inputs give the adjoint of a step that
+ *     did not happen).  Same errors as tcf_step_backward, and TCF_E_INVALID
+ *     for a NULL stage or state_np1 pointer; the grid's fields are left
+ *     unspecified in the same way. */
+tcf_status tcf_step_keep(tcf_grid* g, double dt, double* const stages[4]);
+tcf_status tcf_step_backward_kept(tcf_grid* g, double t_n, double dt, const double* const state_n[6],
+                                  const double* const stages[4], const double* const state_np1[3],
+                                  const double* const adj_np1[5], double* const adj_n[5], double* dL_dsigmaT);
+
 /* Adjoints of single sub-steps at the grid's current fields (checks of the
  * adjoint against finite differences of tcf_step(TCF_TRANSPORT_ONLY) and
  * tcf_predictor).  tcf_adjoint_transport: (ab_in, Tb_in) is dL/d(alpha, T)

@@ -1337,8 +1337,13 @@ void forward_transport_keep(tcf_grid* g, const KParams& P) {
 // (va, vT) of (alpha^{n+1}, T^{n+1}), write (ab, Tb) = adjoint of (alpha^n,
 // T^n) and accumulate the face-velocity adjoints.
 void rk3_reverse(tcf_grid* g, const KParams& P, const double* a0, const double* T0, const double* va,
-                 const double* vT, double* ab, double* Tb) {
+                 const double* vT, double* ab, double* Tb, const double* const stages[4] = nullptr) {
   Fields<double>& F = g->f64;
+  // the stage values: the grid's own (recomputed forward), or the caller's
+  const double* a1 = stages ? stages[0] : F.a1;
+  const double* T1 = stages ? stages[1] : F.T1;
+  const double* a2 = stages ? stages[2] : F.a2;
+  const double* T2 = stages ? stages[3] : F.T2;
   auto& A = g->adj;
   hipStream_t s = g->stream;
   const long N = g->D.N;
@@ -1347,7 +1352,7 @@ void rk3_reverse(tcf_grid* g, const KParams& P, const double* a0, const double* 
   adj_scale(s, N, 2.0 / 3.0, vT, A.wT);
   fill_f64(s, N, A.sa, 0.0);
   fill_f64(s, N, A.sT, 0.0);
-  adj_transport_stage(P, s, F.a2, F.T2, F.u, F.v, F.w, A.wa, A.wT, A.sa, A.sT, A.ub, A.vb, A.wb);
+  adj_transport_stage(P, s, a2, T2, F.u, F.v, F.w, A.wa, A.wT, A.sa, A.sT, A.ub, A.vb, A.wb);
   adj_scale(s, N, 1.0 / 3.0, va, ab);
   adj_scale(s, N, 1.0 / 3.0, vT, Tb);
   // stage 2: a2 = 3/4 base + 1/4 G(a1, T1)
@@ -1357,7 +1362,7 @@ void rk3_reverse(tcf_grid* g, const KParams& P, const double* a0, const double* 
   adj_scale(s, N, 0.25, A.sT, A.wT);
   fill_f64(s, N, A.sa, 0.0);
   fill_f64(s, N, A.sT, 0.0);
-  adj_transport_stage(P, s, F.a1, F.T1, F.u, F.v, F.w, A.wa, A.wT, A.sa, A.sT, A.ub, A.vb, A.wb);
+  adj_transport_stage(P, s, a1, T1, F.u, F.v, F.w, A.wa, A.wT, A.sa, A.sT, A.ub, A.vb, A.wb);
   // stage 1: a1 = G(a0, T0)
   adj_transport_stage(P, s, a0, T0, F.u, F.v, F.w, A.sa, A.sT, ab, Tb, A.ub, A.vb, A.wb);
 }
@@ -1809,43 +1814,19 @@ tcf_status tcf_profile_read(tcf_grid* g, double* total_ms, long* launches) {
   return TCF_OK;
 }
 
-tcf_status tcf_step_backward(tcf_grid* g, double t_n, double dt, const double* const state_n[6],
-                             const double* const adj_np1[5], double* const adj_n[5], double* dL_dsigmaT) {
-  g_err.clear();
-  tcf_status st = adj_checks(g);
-  if (st != TCF_OK) return st;
-  const Dims& D = g->D;
-  if (!state_n || !adj_np1 || !adj_n || !dL_dsigmaT) return fail(TCF_E_INVALID, "NULL argument");
-  for (int k = 0; k < 5; ++k) {
-    const bool need = k < 4 || D.dim == 3;
-    if (need && (!state_n[k] || !adj_np1[k] || !adj_n[k])) return fail(TCF_E_INVALID, "NULL field pointer");
-  }
-  if (!(dt > 0) || !std::isfinite(dt) || !std::isfinite(t_n)) return fail(TCF_E_INVALID, "bad dt or t_n");
-  st = tcf_set_fields(g, t_n, state_n[0], state_n[1], state_n[2], state_n[3], D.dim == 3 ? state_n[4] : nullptr,
-                      state_n[5]);
-  if (st != TCF_OK) return st;
+// The reverse sweep of one adjoint step (S8^T .. S1^T) once the grid holds
+// the forward step's intermediates: alpha, T, p of step n+1 in F.a, F.T,
+// p64, u^n in F.u.., the geometry of step n+1 and the pressure operator of
+// alpha^{n+1}; the transport's stage values in F.a1.. or in stages.
+static tcf_status backward_sweep(tcf_grid* g, KParams& P, double t_n, double dt, const double* const state_n[6],
+                          const double* const adj_np1[5], double* const adj_n[5], double* dL_dsigmaT,
+                          const double* const stages[4]) {
   hipStream_t s = g->stream;
   Fields<double>& F = g->f64;
   auto& A = g->adj;
-  KParams P = g->P;
-  P.dt = dt;
-  P.t = t_n;
+  const Dims& D = g->D;
   const long N = D.N;
-  // ---- forward S1..S7, keeping what the reverse sweep reads
-  forward_transport_keep(g, P);
-  geometry<double>(P, s, F.a, F.T, nullptr, F.sk, F.Mx, F.My, F.Mz);
-  predictor<double>(P, s, F.a, F.sk, F.Mx, F.My, F.Mz, F.u, F.v, F.w, F.us, F.vs, F.ws);
-  const int nbc = nblocks_cells(D.nx, D.ny, D.nz);
-  divergence_rhs<double>(P, s, F.us, F.vs, F.ws, g->b64, g->part[0]);
-  finalize(s, g->part[0], nbc, g->scal, g->iflag, F_MEAN, S_MEAN, (double)N);
-  prepare_operator<double>(g);
-  // the previous call was the step after this one: its state's pressure is
-  // what this forward solve recomputes, and its adjoint solution is close
-  // to this one (initial guesses only: both solves still run to p_rtol)
   const bool chain = A.chain && A.dt_last == dt && std::fabs(A.t_last - (t_n + dt)) <= 1e-6 * dt;
-  if (chain) copy_f64(s, N, A.pnext, g->p64);
-  st = solve(g, g->p64, nullptr);
-  if (st != TCF_OK && st != TCF_E_NOT_CONVERGED) return st;
   // ---- S8^T
   copy_f64(s, N, adj_np1[0], A.ab);
   copy_f64(s, N, adj_np1[1], A.Tb);
@@ -1871,7 +1852,7 @@ tcf_status tcf_step_backward(tcf_grid* g, double t_n, double dt, const double* c
   } else {
     copy_f64(s, N, A.y, A.yh[0]);  // keep the last one as history
   }
-  st = solve(g, A.y, nullptr);
+  tcf_status st = solve(g, A.y, nullptr);
   if (st != TCF_OK && st != TCF_E_NOT_CONVERGED) return st;
   adj_poisson_alpha(P, s, F.a, g->p64, A.y, A.ab);
   // ---- S6^T
@@ -1881,7 +1862,7 @@ tcf_status tcf_step_backward(tcf_grid* g, double t_n, double dt, const double* c
   predictor_reverse(g, P, A.usb, A.vsb, A.wsb);
   adj_add_scalar(s, dL_dsigmaT, g->scal + S_SBAR);
   // ---- S1^T
-  rk3_reverse(g, P, state_n[0], state_n[1], A.ab, A.Tb, adj_n[0], adj_n[1]);
+  rk3_reverse(g, P, state_n[0], state_n[1], A.ab, A.Tb, adj_n[0], adj_n[1], stages);
   zero_walls<double>(P, s, A.ub, A.vb, A.wb);
   copy_f64(s, D.Nu, A.ub, adj_n[2]);
   copy_f64(s, D.Nv, A.vb, adj_n[3]);
@@ -1894,6 +1875,110 @@ tcf_status tcf_step_backward(tcf_grid* g, double t_n, double dt, const double* c
   A.nchain = std::min(A.nchain + 1, 3);
   HIPCHECK(hipGetLastError());
   return st;
+}
+
+static tcf_status backward_args(tcf_grid* g, double t_n, double dt, const double* const state_n[6],
+                         const double* const adj_np1[5], double* const adj_n[5], double* dL_dsigmaT) {
+  tcf_status st = adj_checks(g);
+  if (st != TCF_OK) return st;
+  const Dims& D = g->D;
+  if (!state_n || !adj_np1 || !adj_n || !dL_dsigmaT) return fail(TCF_E_INVALID, "NULL argument");
+  for (int k = 0; k < 5; ++k) {
+    const bool need = k < 4 || D.dim == 3;
+    if (need && (!state_n[k] || !adj_np1[k] || !adj_n[k])) return fail(TCF_E_INVALID, "NULL field pointer");
+  }
+  if (!(dt > 0) || !std::isfinite(dt) || !std::isfinite(t_n)) return fail(TCF_E_INVALID, "bad dt or t_n");
+  return TCF_OK;
+}
+
+tcf_status tcf_step_backward(tcf_grid* g, double t_n, double dt, const double* const state_n[6],
+                             const double* const adj_np1[5], double* const adj_n[5], double* dL_dsigmaT) {
+  g_err.clear();
+  tcf_status st = backward_args(g, t_n, dt, state_n, adj_np1, adj_n, dL_dsigmaT);
+  if (st != TCF_OK) return st;
+  const Dims& D = g->D;
+  st = tcf_set_fields(g, t_n, state_n[0], state_n[1], state_n[2], state_n[3], D.dim == 3 ? state_n[4] : nullptr,
+                      state_n[5]);
+  if (st != TCF_OK) return st;
+  hipStream_t s = g->stream;
+  Fields<double>& F = g->f64;
+  auto& A = g->adj;
+  KParams P = g->P;
+  P.dt = dt;
+  P.t = t_n;
+  const long N = D.N;
+  // ---- forward S1..S7, keeping what the reverse sweep reads
+  forward_transport_keep(g, P);
+  geometry<double>(P, s, F.a, F.T, nullptr, F.sk, F.Mx, F.My, F.Mz);
+  predictor<double>(P, s, F.a, F.sk, F.Mx, F.My, F.Mz, F.u, F.v, F.w, F.us, F.vs, F.ws);
+  const int nbc = nblocks_cells(D.nx, D.ny, D.nz);
+  divergence_rhs<double>(P, s, F.us, F.vs, F.ws, g->b64, g->part[0]);
+  finalize(s, g->part[0], nbc, g->scal, g->iflag, F_MEAN, S_MEAN, (double)N);
+  prepare_operator<double>(g);
+  // the previous call was the step after this one: its state's pressure is
+  // what this forward solve recomputes, and its adjoint solution is close
+  // to this one (initial guesses only: both solves still run to p_rtol)
+  const bool chain = A.chain && A.dt_last == dt && std::fabs(A.t_last - (t_n + dt)) <= 1e-6 * dt;
+  if (chain) copy_f64(s, N, A.pnext, g->p64);
+  st = solve(g, g->p64, nullptr);
+  if (st != TCF_OK && st != TCF_E_NOT_CONVERGED) return st;
+  return backward_sweep(g, P, t_n, dt, state_n, adj_np1, adj_n, dL_dsigmaT, nullptr);
+}
+
+tcf_status tcf_step_keep(tcf_grid* g, double dt, double* const stages[4]) {
+  g_err.clear();
+  tcf_status st = adj_checks(g);
+  if (st != TCF_OK) return st;
+  if (!stages || !stages[0] || !stages[1] || !stages[2] || !stages[3]) return fail(TCF_E_INVALID, "NULL stage pointer");
+  // the step's transport writes its stage values into the caller's arrays
+  // (nothing else in the step uses the grid's own stage arrays)
+  Fields<double>& F = g->f64;
+  double* const own[4] = {F.a1, F.T1, F.a2, F.T2};
+  F.a1 = stages[0];
+  F.T1 = stages[1];
+  F.a2 = stages[2];
+  F.T2 = stages[3];
+  st = tcf_step(g, dt, 1, nullptr);
+  F.a1 = own[0];
+  F.T1 = own[1];
+  F.a2 = own[2];
+  F.T2 = own[3];
+  return st;
+}
+
+tcf_status tcf_step_backward_kept(tcf_grid* g, double t_n, double dt, const double* const state_n[6],
+                                  const double* const stages[4], const double* const state_np1[3],
+                                  const double* const adj_np1[5], double* const adj_n[5], double* dL_dsigmaT) {
+  g_err.clear();
+  tcf_status st = backward_args(g, t_n, dt, state_n, adj_np1, adj_n, dL_dsigmaT);
+  if (st != TCF_OK) return st;
+  if (!stages || !stages[0] || !stages[1] || !stages[2] || !stages[3]) return fail(TCF_E_INVALID, "NULL stage pointer");
+  if (!state_np1 || !state_np1[0] || !state_np1[1] || !state_np1[2])
+    return fail(TCF_E_INVALID, "NULL pointer in state_np1");
+  hipStream_t s = g->stream;
+  Fields<double>& F = g->f64;
+  const Dims& D = g->D;
+  KParams P = g->P;
+  P.dt = dt;
+  P.t = t_n;
+  const long N = D.N;
+  // u^n (walls zeroed, as tcf_set_fields does) and alpha, T, p of step n+1
+  copy_f64(s, D.Nu, state_n[2], g->u64);
+  copy_f64(s, D.Nv, state_n[3], g->v64);
+  if (D.dim == 3) copy_f64(s, D.Nw, state_n[4], g->w64);
+  zero_walls<double>(P, s, g->u64, g->v64, g->w64);
+  copy_f64(s, N, state_np1[0], F.a);
+  copy_f64(s, N, state_np1[1], F.T);
+  copy_f64(s, N, state_np1[2], g->p64);
+  g->t = t_n;
+  g->has_fields = true;
+  g->nhist = 0;
+  g->snhist = 0;
+  // the geometry of step n+1 and the operator of alpha^{n+1}; the predictor,
+  // the divergence and the forward solve are not needed
+  geometry<double>(P, s, F.a, F.T, nullptr, F.sk, F.Mx, F.My, F.Mz);
+  prepare_operator<double>(g);
+  return backward_sweep(g, P, t_n, dt, state_n, adj_np1, adj_n, dL_dsigmaT, stages);
 }
 
 tcf_status tcf_adjoint_transport(tcf_grid* g, double dt, const double* ab_in, const double* Tb_in, double* ab_out,

@@ -60,7 +60,8 @@ class TcfStepInfo(C.Structure):
 EXPORTS = ["tcf_workspace_bytes", "tcf_init_grid", "tcf_init_grid_static", "tcf_set_fields", "tcf_get_fields",
            "tcf_get_pressure_history", "tcf_set_pressure_history", "tcf_set_species",
            "tcf_get_species", "tcf_set_phases", "tcf_get_phases", "tcf_step",
-           "tcf_solve_pressure", "tcf_predictor", "tcf_apply_A", "tcf_step_backward", "tcf_adjoint_transport",
+           "tcf_solve_pressure", "tcf_predictor", "tcf_apply_A", "tcf_step_backward", "tcf_step_keep",
+           "tcf_step_backward_kept", "tcf_adjoint_transport",
            "tcf_adjoint_predictor", "tcf_profile", "tcf_profile_read", "tcf_destroy", "tcf_last_error"]
 
 _lib = None
@@ -259,7 +260,9 @@ class Grid:
         _check(load().tcf_get_species(self.h, _ptr(out)))
         return out
 
-    def get_fields(self) -> dict:
+    def get_fields(self, history=True) -> dict:
+        """Copies of the grid's fields (fresh tensors); with history, also the
+        previous pressures the extrapolated initial guess holds."""
         s = self.shapes
         out = {k: torch.empty(s[k if k in ("u", "v", "w") else "cell"], dtype=torch.float64, device=self.device)
                for k in ("alpha", "T", "u", "v", "p")}
@@ -272,7 +275,7 @@ class Grid:
         # grid keeps them (one-solve integrator) and holds any
         n = 0
         p1 = p2 = None
-        if self.cfg.p_extrapolate > 0 and self.cfg.integrator == 0:
+        if history and self.cfg.p_extrapolate > 0 and self.cfg.integrator == 0:
             p1 = torch.empty(s["cell"], dtype=torch.float64, device=self.device)
             p2 = torch.empty(s["cell"], dtype=torch.float64, device=self.device)
             held = C.c_int(0)
@@ -338,6 +341,36 @@ class Grid:
                                         C.c_void_p(sbar.data_ptr())))
         return dict(zip(keys, out))
 
+    def step_keep(self, dt):
+        """One forward step (as step(dt, 1)) that also returns the transport's
+        stage values (alpha1, T1, alpha2, T2) for step_backward_kept."""
+        stages = [self._empty("cell") for _ in range(4)]
+        arr = (C.c_void_p * 4)(*[x.data_ptr() for x in stages])
+        _check(load().tcf_step_keep(self.h, C.c_double(dt), arr))
+        return stages
+
+    def step_backward_kept(self, t_n, dt, state_n: dict, stages, state_np1: dict, adj_np1: dict, sbar):
+        """step_backward with the forward step's intermediates supplied: the
+        stages from step_keep of this step and alpha, T, p of step n+1."""
+        keys = ("alpha", "T", "u", "v", "w")
+        st = [self._t(state_n.get(k)) for k in keys] + [self._t(state_n.get("p"))]
+        stg = [self._t(x) for x in stages]
+        nxt = [self._t(state_np1[k]) for k in ("alpha", "T", "p")]
+        ad = [self._t(adj_np1.get(k)) if adj_np1.get(k) is not None else
+              (torch.zeros(self.shapes[("cell" if k in ("alpha", "T") else k)], dtype=torch.float64,
+                           device=self.device) if (k != "w" or self.shapes["w"]) else None) for k in keys]
+        out = [self._empty("cell"), self._empty("cell"), self._empty("u"), self._empty("v"), self._empty("w")]
+        arr6 = (C.c_void_p * 6)(*[None if x is None else x.data_ptr() for x in st])
+        arr4 = (C.c_void_p * 4)(*[x.data_ptr() for x in stg])
+        arr3 = (C.c_void_p * 3)(*[x.data_ptr() for x in nxt])
+        arr5a = (C.c_void_p * 5)(*[None if x is None else x.data_ptr() for x in ad])
+        arr5o = (C.c_void_p * 5)(*[None if x is None else x.data_ptr() for x in out])
+        assert sbar.dtype == torch.float64 and sbar.is_cuda and sbar.numel() == 1
+        self._keep = (st, stg, nxt, ad)
+        _check(load().tcf_step_backward_kept(self.h, C.c_double(t_n), C.c_double(dt), arr6, arr4, arr3, arr5a,
+                                             arr5o, C.c_void_p(sbar.data_ptr())))
+        return dict(zip(keys, out))
+
     def adjoint_transport(self, dt, ab, Tb):
         ab, Tb = self._t(ab), self._t(Tb)
         ao, To = self._empty("cell"), self._empty("cell")
@@ -383,9 +416,10 @@ class TcfRollout(torch.autograd.Function):
     temperature field T0.  alpha0 and the initial velocity are fixed inputs.
 
     forward stores a checkpoint of the state every k steps; backward replays
-    each segment from its checkpoint (keeping the k states of the segment)
-    and runs tcf_step_backward through it in reverse.  Outputs: final
-    (alpha, T, u, v, w) (w is an empty tensor in 2D)."""
+    each segment from its checkpoint, keeping the k states of the segment and
+    each step's transport stages (tcf_step_keep), and runs
+    tcf_step_backward_kept through it in reverse (no forward step is computed
+    twice).  Outputs: final (alpha, T, u, v, w) (w is an empty tensor in 2D)."""
 
     @staticmethod
     def forward(ctx, s, T0, cfg, alpha0, u0, v0, w0, nsteps, k, *start):
@@ -403,7 +437,7 @@ class TcfRollout(torch.autograd.Function):
         ckpt = []
         for n in range(nsteps):
             if n % k == 0:
-                ckpt.append((n, {kk: (vv.clone() if torch.is_tensor(vv) else vv) for kk, vv in g.get_fields().items()}))
+                ckpt.append((n, g.get_fields()))
             g.step(dt, 1, info=False)
         out = g.get_fields()
         ctx.grid, ctx.ckpt, ctx.nsteps, ctx.dt = g, ckpt, nsteps, dt
@@ -426,15 +460,15 @@ class TcfRollout(torch.autograd.Function):
         for seg in reversed(range(len(ctx.ckpt))):
             n0, st0 = ctx.ckpt[seg]
             n1 = bounds[seg + 1]
-            # replay the segment, keeping every state
+            # replay the segment, keeping every state and every step's stages
             g.set_state(st0, st0["t"])  # with the pressure history, so the replay repeats the forward
-            states = []
+            states, stages = [], []
             for n in range(n0, n1):
-                f = g.get_fields()
-                states.append({kk: (vv.clone() if torch.is_tensor(vv) else vv) for kk, vv in f.items()})
-                if n + 1 < n1:
-                    g.step(dt, 1, info=False)
+                states.append(g.get_fields(history=False))
+                stages.append(g.step_keep(dt))
+            states.append(g.get_fields(history=False))  # the state after the segment's last step
             for n in reversed(range(n0, n1)):
-                st = states[n - n0]
-                lam = g.step_backward(st["t"], dt, st, lam, sbar)
+                st, nxt = states[n - n0], states[n - n0 + 1]
+                lam = g.step_backward_kept(st["t"], dt, st, stages[n - n0], nxt, lam, sbar)
+                stages[n - n0] = None
         return (sbar, lam["T"], None, None, None, None, None, None, None) + (None,) * ctx.n_start

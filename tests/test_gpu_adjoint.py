@@ -189,6 +189,49 @@ def test_full_step_adjoint_matches_fd(make):
 
 @pytest.mark.parametrize("make", [lambda: I.custom(I.config(0), nx=40, ny=32),
                                   lambda: I.custom(I.config(3), nx=20, ny=16, nz=18), meltpool_small])
+def test_step_backward_kept_matches_recomputed(make):
+    """tcf_step_backward_kept, given the stages tcf_step_keep kept and the
+    state after the step, against tcf_step_backward, which recomputes that
+    forward step itself: the same adjoint up to the pressure solves'
+    tolerance (both run to p_rtol = 1e-13 from different guesses)."""
+    c = make()
+    c["p_rtol"] = 1e-13
+    melt = c["T0"] != 0
+    st = perturbed_state(c, 11, amp=3.0 if melt else 0.3)
+    dt = c["dt"]
+    rng = np.random.default_rng(12)
+    W = {k: (rng.standard_normal(st[k].shape) if st.get(k) is not None else None)
+         for k in ("alpha", "T", "u", "v", "w")}
+    _zero_walls(c, W)
+    keys = ("alpha", "T", "u", "v", "w")
+    g1 = tcf.Grid(c, precision=0, flags=tcf.TCF_WITH_ADJOINT)
+    s1 = torch.zeros((), dtype=torch.float64, device="cuda")
+    ref = g1.step_backward(0.0, dt, {k: dev(v) for k, v in st.items()}, {k: dev(v) for k, v in W.items()}, s1)
+    g2 = tcf.Grid(c, precision=0, flags=tcf.TCF_WITH_ADJOINT)
+    g2.set_state(st)
+    stages = g2.step_keep(dt)
+    nxt = {k: v.clone() for k, v in g2.get_fields().items() if k in ("alpha", "T", "p")}
+    # the next state itself: the kept step is the ordinary forward step
+    g3 = tcf.Grid(c, precision=0)
+    g3.set_state(st)
+    g3.step(dt, 1, info=False)
+    o3 = g3.get_fields()
+    for k in ("alpha", "T"):
+        assert torch.equal(nxt[k], o3[k]), k
+    s2 = torch.zeros((), dtype=torch.float64, device="cuda")
+    got = g2.step_backward_kept(0.0, dt, {k: dev(v) for k, v in st.items()}, stages, nxt,
+                                {k: dev(v) for k, v in W.items()}, s2)
+    for k in keys:
+        if ref[k] is None or ref[k].numel() == 0:
+            continue
+        a, b = host(got[k]), host(ref[k])
+        err = np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+        assert err <= 1e-9, (k, err)
+    assert abs(float(s2) - float(s1)) <= 1e-9 * abs(float(s1)), (float(s2), float(s1))
+
+
+@pytest.mark.parametrize("make", [lambda: I.custom(I.config(0), nx=40, ny=32),
+                                  lambda: I.custom(I.config(3), nx=20, ny=16, nz=18), meltpool_small])
 def test_full_step_adjoint_matches_oracle_fd(make):
     """tcf_step_backward against central differences of the ORACLE's step
     (FP64 CPU, its own pressure solve to 1e-13): the adjoint of the HIP
