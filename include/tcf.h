@@ -269,7 +269,13 @@ tcf_status tcf_step_backward(tcf_grid* g, double t_n, double dt, const double* c
  *     TCF_WITH_ADJOINT grid, which also writes the transport's stage values
  *     alpha^(1), T^(1), alpha^(2), T^(2) (SSP-RK3 stages 1 and 2, device FP64,
  *     nx*ny*nz each, caller-owned, distinct and not the grid's own arrays)
- *     into stages[0..3]; the transport writes them there directly.
+ *     into stages[0..3]; the transport writes them there directly.  With
+ *     p_np1 non-NULL (device FP64, nx*ny*nz) the pressure solve S6-S7 is
+ *     skipped and p_np1 is taken as p^{n+1}: given the pressure an earlier
+ *     run of the same step returned (tcf_get_fields after it), the new state
+ *     is bitwise that run's (a rollout that kept every step's pressure
+ *     replays its segments without solving).  The grid's pressure becomes
+ *     p_np1 and its pressure history is emptied.
  *   tcf_step_backward_kept: tcf_step_backward(g, t_n, dt, state_n, adj_np1,
  *     adj_n, dL_dsigmaT) given stages (from tcf_step_keep of this step) and
  *     state_np1 = alpha, T, p of step n+1 (the state that step produced).
@@ -280,7 +286,7 @@ tcf_status tcf_step_backward(tcf_grid* g, double t_n, double dt, const double* c
  *     did not happen).  Same errors as tcf_step_backward, and TCF_E_INVALID
  *     for a NULL stage or state_np1 pointer; the grid's fields are left
  *     unspecified in the same way. */
-tcf_status tcf_step_keep(tcf_grid* g, double dt, double* const stages[4]);
+tcf_status tcf_step_keep(tcf_grid* g, double dt, double* const stages[4], const double* p_np1);
 tcf_status tcf_step_backward_kept(tcf_grid* g, double t_n, double dt, const double* const state_n[6],
                                   const double* const stages[4], const double* const state_np1[3],
                                   const double* const adj_np1[5], double* const adj_n[5], double* dL_dsigmaT);

@@ -1925,11 +1925,39 @@ tcf_status tcf_step_backward(tcf_grid* g, double t_n, double dt, const double* c
   return backward_sweep(g, P, t_n, dt, state_n, adj_np1, adj_n, dL_dsigmaT, nullptr);
 }
 
-tcf_status tcf_step_keep(tcf_grid* g, double dt, double* const stages[4]) {
+// One step of integrator 0 (FP64, two phases, no species) whose pressure
+// p^{n+1} is given instead of solved for: S1-S5 and S8 exactly as step_once
+// runs them, so with the pressure an earlier run of this step produced the
+// state is bitwise that run's.  The pressure history is not advanced (it is
+// marked empty, so a later solve starts from p^{n+1}).
+tcf_status step_given_p(tcf_grid* g, double dt, const double* p_np1) {
+  hipStream_t s = g->stream;
+  Fields<double>& F = g->f64;
+  KParams P = g->P;
+  P.dt = dt;
+  P.t = g->t;
+  transport_stage<double>(P, s, F.a, F.T, F.a, F.T, F.u, F.v, F.w, F.a1, F.T1, 0.0, 1.0);
+  transport_stage<double>(P, s, F.a1, F.T1, F.a, F.T, F.u, F.v, F.w, F.a2, F.T2, 0.75, 0.25);
+  transport_stage<double>(P, s, F.a2, F.T2, F.a, F.T, F.u, F.v, F.w, F.a, F.T, 1.0 / 3.0, 2.0 / 3.0);
+  if (!(g->cfg.flags & TCF_TRANSPORT_ONLY)) {
+    geometry<double>(P, s, F.a, F.T, nullptr, F.sk, F.Mx, F.My, F.Mz);
+    predictor<double>(P, s, F.a, F.sk, F.Mx, F.My, F.Mz, F.u, F.v, F.w, F.us, F.vs, F.ws);
+    copy_f64(s, g->D.N, p_np1, g->p64);
+    project<double>(P, s, F.a, g->p64, F.us, F.vs, F.ws, g->u64, g->v64, g->w64, nullptr, nullptr, nullptr);
+    g->nhist = 0;
+  }
+  g->t += dt;
+  HIPCHECK(hipGetLastError());
+  return TCF_OK;
+}
+
+tcf_status tcf_step_keep(tcf_grid* g, double dt, double* const stages[4], const double* p_np1) {
   g_err.clear();
   tcf_status st = adj_checks(g);
   if (st != TCF_OK) return st;
   if (!stages || !stages[0] || !stages[1] || !stages[2] || !stages[3]) return fail(TCF_E_INVALID, "NULL stage pointer");
+  if (!(dt > 0) || !std::isfinite(dt)) return fail(TCF_E_INVALID, "dt must be positive and finite");
+  if (!g->has_fields) return fail(TCF_E_STATE, "fields not set");
   // the step's transport writes its stage values into the caller's arrays
   // (nothing else in the step uses the grid's own stage arrays)
   Fields<double>& F = g->f64;
@@ -1938,7 +1966,7 @@ tcf_status tcf_step_keep(tcf_grid* g, double dt, double* const stages[4]) {
   F.T1 = stages[1];
   F.a2 = stages[2];
   F.T2 = stages[3];
-  st = tcf_step(g, dt, 1, nullptr);
+  st = p_np1 ? step_given_p(g, dt, p_np1) : tcf_step(g, dt, 1, nullptr);
   F.a1 = own[0];
   F.T1 = own[1];
   F.a2 = own[2];

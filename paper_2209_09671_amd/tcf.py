@@ -110,6 +110,10 @@ def load():
     pp = C.POINTER(vp)
     lib.tcf_step_backward.restype = st
     lib.tcf_step_backward.argtypes = [vp, C.c_double, C.c_double, pp, pp, pp, vp]
+    lib.tcf_step_keep.restype = st
+    lib.tcf_step_keep.argtypes = [vp, C.c_double, pp, vp]
+    lib.tcf_step_backward_kept.restype = st
+    lib.tcf_step_backward_kept.argtypes = [vp, C.c_double, C.c_double, pp, pp, pp, pp, pp, vp]
     lib.tcf_adjoint_transport.restype = st
     lib.tcf_adjoint_transport.argtypes = [vp, C.c_double, vp, vp, vp, vp, vp, vp, vp]
     lib.tcf_adjoint_predictor.restype = st
@@ -341,13 +345,23 @@ class Grid:
                                         C.c_void_p(sbar.data_ptr())))
         return dict(zip(keys, out))
 
-    def step_keep(self, dt):
+    def step_keep(self, dt, p_np1=None):
         """One forward step (as step(dt, 1)) that also returns the transport's
-        stage values (alpha1, T1, alpha2, T2) for step_backward_kept."""
+        stage values (alpha1, T1, alpha2, T2) for step_backward_kept; with
+        p_np1 (the pressure an earlier run of this step returned) the step
+        takes it instead of solving for it."""
         stages = [self._empty("cell") for _ in range(4)]
         arr = (C.c_void_p * 4)(*[x.data_ptr() for x in stages])
-        _check(load().tcf_step_keep(self.h, C.c_double(dt), arr))
+        pp = self._t(p_np1)
+        self._keep = (pp,)
+        _check(load().tcf_step_keep(self.h, C.c_double(dt), arr, _ptr(pp)))
         return stages
+
+    def get_pressure(self):
+        """A copy of the grid's pressure (FP64, cell layout)."""
+        p = self._empty("cell")
+        _check(load().tcf_get_fields(self.h, None, None, None, None, None, None, _ptr(p)))
+        return p
 
     def step_backward_kept(self, t_n, dt, state_n: dict, stages, state_np1: dict, adj_np1: dict, sbar):
         """step_backward with the forward step's intermediates supplied: the
@@ -415,11 +429,13 @@ class TcfRollout(torch.autograd.Function):
     surface-tension slope s = dsigma/dT (0-d tensor) and the initial
     temperature field T0.  alpha0 and the initial velocity are fixed inputs.
 
-    forward stores a checkpoint of the state every k steps; backward replays
-    each segment from its checkpoint, keeping the k states of the segment and
-    each step's transport stages (tcf_step_keep), and runs
-    tcf_step_backward_kept through it in reverse (no forward step is computed
-    twice).  Outputs: final (alpha, T, u, v, w) (w is an empty tensor in 2D)."""
+    forward stores a checkpoint of the state every k steps and every step's
+    pressure (nx*ny*nz FP64 values per step); backward replays each segment
+    from its checkpoint with tcf_step_keep given those pressures (no solve;
+    the replayed states are bitwise the forward's), keeping the segment's
+    states and each step's transport stages, and runs tcf_step_backward_kept
+    through it in reverse.  Outputs: final (alpha, T, u, v, w) (w is an empty
+    tensor in 2D)."""
 
     @staticmethod
     def forward(ctx, s, T0, cfg, alpha0, u0, v0, w0, nsteps, k, *start):
@@ -435,12 +451,14 @@ class TcfRollout(torch.autograd.Function):
         ctx.n_start = len(start)
         g.set_fields(t0, alpha0, T0, u0, v0, w0, p0)
         ckpt = []
+        pres = [None] * (nsteps + 1)  # every step's pressure: the replay takes it instead of solving
         for n in range(nsteps):
             if n % k == 0:
                 ckpt.append((n, g.get_fields()))
             g.step(dt, 1, info=False)
+            pres[n + 1] = g.get_pressure()
         out = g.get_fields()
-        ctx.grid, ctx.ckpt, ctx.nsteps, ctx.dt = g, ckpt, nsteps, dt
+        ctx.grid, ctx.ckpt, ctx.nsteps, ctx.dt, ctx.pres = g, ckpt, nsteps, dt, pres
         ctx.has_w = out["w"] is not None
         w = out["w"] if ctx.has_w else torch.empty(0, dtype=torch.float64, device=T0.device)
         return out["alpha"], out["T"], out["u"], out["v"], w
@@ -465,10 +483,11 @@ class TcfRollout(torch.autograd.Function):
             states, stages = [], []
             for n in range(n0, n1):
                 states.append(g.get_fields(history=False))
-                stages.append(g.step_keep(dt))
+                stages.append(g.step_keep(dt, ctx.pres[n + 1]))
             states.append(g.get_fields(history=False))  # the state after the segment's last step
             for n in reversed(range(n0, n1)):
                 st, nxt = states[n - n0], states[n - n0 + 1]
                 lam = g.step_backward_kept(st["t"], dt, st, stages[n - n0], nxt, lam, sbar)
                 stages[n - n0] = None
+                ctx.pres[n + 1] = None
         return (sbar, lam["T"], None, None, None, None, None, None, None) + (None,) * ctx.n_start

@@ -193,7 +193,8 @@ def test_step_backward_kept_matches_recomputed(make):
     """tcf_step_backward_kept, given the stages tcf_step_keep kept and the
     state after the step, against tcf_step_backward, which recomputes that
     forward step itself: the same adjoint up to the pressure solves'
-    tolerance (both run to p_rtol = 1e-13 from different guesses)."""
+    tolerance (both run to p_rtol = 1e-13 from different guesses).  Also:
+    tcf_step_keep given the pressure of that step reproduces it bitwise."""
     c = make()
     c["p_rtol"] = 1e-13
     melt = c["T0"] != 0
@@ -218,6 +219,17 @@ def test_step_backward_kept_matches_recomputed(make):
     o3 = g3.get_fields()
     for k in ("alpha", "T"):
         assert torch.equal(nxt[k], o3[k]), k
+    # the same step given the pressure it produced (no solve): bitwise the
+    # same state and stages
+    g4 = tcf.Grid(c, precision=0, flags=tcf.TCF_WITH_ADJOINT)
+    g4.set_state(st)
+    stages4 = g4.step_keep(dt, g2.get_pressure())
+    f2, f4 = g2.get_fields(history=False), g4.get_fields(history=False)
+    for k in keys + ("p",):
+        if f2[k] is not None:
+            assert torch.equal(f4[k], f2[k]), k
+    for q in range(4):
+        assert torch.equal(stages4[q], stages[q]), q
     s2 = torch.zeros((), dtype=torch.float64, device="cuda")
     got = g2.step_backward_kept(0.0, dt, {k: dev(v) for k, v in st.items()}, stages, nxt,
                                 {k: dev(v) for k, v in W.items()}, s2)
