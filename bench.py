@@ -175,11 +175,14 @@ def cpu_baseline(c: dict, rtol: float, steps: int):
             "cpu_model": model, "nproc": ncpu, "status": status}
 
 
-def run_gpu(c, st, precision, spinup, warmup, steps, families=(), family_steps=4):
+def run_gpu(c, st, precision, spinup, warmup, steps, families=(), family_steps=None):
     """Spin-up, warm-up, then `steps` timed steps without instrumentation;
-    then, per kernel family, `family_steps` further steps with HIP events
-    around that family's launches (their average duration), so that the
-    events do not perturb the throughput."""
+    then, per kernel family, the first `family_steps` (default: all) steps of
+    the timed window again, from its saved start state (the replay is
+    bitwise the timed run, so every family is measured on the same steps,
+    with the window's launches per step), with HIP events around that
+    family's launches (their average duration), so that the events do not
+    perturb the throughput."""
     import torch
     from paper_2209_09671_amd import tcf
     g = tcf.Grid(c, precision=precision)
@@ -194,6 +197,11 @@ def run_gpu(c, st, precision, spinup, warmup, steps, families=(), family_steps=4
         sp_cfl = max(sp_cfl, info["cfl_max"])
     for _ in range(warmup):
         g.step(dt, 1)
+    start = g.get_fields() if families else None
+    if start is not None and c.get("species"):
+        start["c"] = g.get_species()
+    if start is not None and c.get("nphases", 0) > 2:
+        start["alpha3"], start["alpha4"] = g.get_phases()
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -212,14 +220,17 @@ def run_gpu(c, st, precision, spinup, warmup, steps, families=(), family_steps=4
     wall = time.perf_counter() - t0
     ev_ms = e0.elapsed_time(e1)
     fams = {}
+    nfam = steps if family_steps is None else min(family_steps, steps)
     for fam in families:
+        g.set_state(start, start["t"])
         g.profile(fam)
-        for _ in range(family_steps):
+        for _ in range(nfam):
             g.step(dt, 1)
         torch.cuda.synchronize()
         kms, kn = g.profile_read()
         g.profile(None)
-        fams[fam] = (kms, kn, family_steps)
+        fams[fam] = (kms, kn, nfam)
+    del start
     g.close()
     del g
     torch.cuda.empty_cache()

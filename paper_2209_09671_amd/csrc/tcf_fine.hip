@@ -475,11 +475,14 @@ __global__ __launch_bounds__(FX * FY) void k0_smooth(Op0<R> op, int kz, int ntx,
 // value, face weights and diagonal in registers for the second sweep.  The
 // face terms are summed in the order of the single sweep (k0_smooth).  One
 // barrier per plane: plane k+2 is written after it, when every thread is
-// done with plane k-2, whose slot it takes.  Tiles are 64 x TYK.  At 256^3
-// the pass takes 105 us against 59 + 66 us for the two single sweeps; it is
-// bound by its instruction stream (the ring, LDS traffic, six reciprocals
-// per first-sweep cell), not by HBM: loading two planes ahead (more
-// registers, fewer blocks per CU) measured 108 us, and 64 x 16 tiles 111 us.
+// done with plane k-2, whose slot it takes.  Tiles are 64 x TYK.  The loop
+// computes two planes per pass, the own cell's kept values alternating
+// between two register sets instead of being copied from plane to plane
+// (99 -> 93 us at 256^3, against 61 + 66 us for the two single sweeps).
+// The pass is bound by its instruction stream (the ring, LDS traffic, six
+// reciprocals per first-sweep cell), not by HBM: loading two planes ahead
+// (more registers, fewer blocks per CU) measured 108 us against 105 us of
+// the one-plane loop, and 64 x 16 tiles 111 us.
 template <int TYK>
 __device__ __forceinline__ Tile tile_of_ty(int nx, int ny, int nz, int ntx, int nty, int kz) {
   const int nb = gridDim.x, b = blockIdx.x;
@@ -579,9 +582,16 @@ __global__ __launch_bounds__(FX * TYK) void k0_smooth2(Op0<R> op, int kz, int nt
       }
     }
   };
-  // own cell's second-sweep operands of the previous plane
-  R pw[6] = {R(0), R(0), R(0), R(0), R(0), R(0)}, pdg = R(1), pb = R(0), px1 = R(0), px1m = R(0);
-  bool pin = false;
+  // the own cell's first-sweep value, face weights, diagonal and b of one
+  // plane, kept for its second sweep one plane later; two of them take
+  // turns (the loop runs two planes per pass), so nothing is copied between
+  // planes
+  struct Own {
+    R w[6], x1, dg, b;
+    bool in;
+  };
+  Own oa{{R(0), R(0), R(0), R(0), R(0), R(0)}, R(0), R(1), R(0), false}, ob = oa;
+  R px1m = R(0);  // first-sweep value of the own cell two planes back
   double acc = 0.0;
   if (ks > 0) {
     issue(ks - 1);
@@ -594,13 +604,12 @@ __global__ __launch_bounds__(FX * TYK) void k0_smooth2(Op0<R> op, int kz, int nt
     store(ks + 1);
   }
   issue(ks + 2);
-  for (int k = ks; k <= kend; ++k) {
+  // plane k: the first sweep of plane k into `now`, then the second sweep of
+  // plane k - 1 from `prev`
+  auto plane = [&](int k, Own& now, const Own& prev) {
     __syncthreads();
     const int sc = k & 3, sm = (k + 3) & 3, sp = (k + 1) & 3;
-    R x1own = R(0);
-    R w[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
-    R dgo = R(1), bo = R(0);
-    bool ino = false;
+    now.in = false;
     if (k <= ke) {
 #pragma unroll
       for (int m = 0; m < 2; ++m) {
@@ -626,12 +635,12 @@ __global__ __launch_bounds__(FX * TYK) void k0_smooth2(Op0<R> op, int kz, int nt
         const R x1 = xc + om1 * recip(d) * (bc - s);
         s1[k & 1][l] = x1;
         if (m == 0) {
-          x1own = x1;
-          dgo = d;
-          bo = bc;
-          ino = true;
+          now.x1 = x1;
+          now.dg = d;
+          now.b = bc;
+          now.in = true;
 #pragma unroll
-          for (int f = 0; f < 6; ++f) w[f] = wv[f];
+          for (int f = 0; f < 6; ++f) now.w[f] = wv[f];
         }
       }
     }
@@ -641,29 +650,34 @@ __global__ __launch_bounds__(FX * TYK) void k0_smooth2(Op0<R> op, int kz, int nt
     }
     // second sweep of plane k - 1 (own cell)
     const int k2 = k - 1;
-    if (own && k2 >= k0 && k2 < k1 && pin) {
+    if (own && k2 >= k0 && k2 < k1 && prev.in) {
       const int l = li[0], sl = k2 & 1;
       // selects, as in the first sweep (a first-sweep value beyond a wall
-      // is never computed, so it must not reach the sum even times zero)
+      // is never computed, so it must not reach the sum even times zero);
+      // the four in-plane neighbours are read before any is used (inside the
+      // tile's ring, so in bounds), so that no face becomes a branch around
+      // its own LDS read
+      const R nw = s1[sl][l - 1], ne = s1[sl][l + 1], ns = s1[sl][l - RX2], nn = s1[sl][l + RX2];
+      const R px1 = prev.x1;
       R s = R(0);
-      s = T.i > 0 ? s + pw[0] * (px1 - s1[sl][l - 1]) : s;
-      s = T.i < nx - 1 ? s + pw[1] * (px1 - s1[sl][l + 1]) : s;
-      s = T.j > 0 ? s + pw[2] * (px1 - s1[sl][l - RX2]) : s;
-      s = T.j < ny - 1 ? s + pw[3] * (px1 - s1[sl][l + RX2]) : s;
-      s = k2 > 0 ? s + pw[4] * (px1 - px1m) : s;
-      s = k2 < nz - 1 ? s + pw[5] * (px1 - x1own) : s;
-      const R x2 = px1 + om2 * recip(pdg) * (pb - s);
+      s = T.i > 0 ? s + prev.w[0] * (px1 - nw) : s;
+      s = T.i < nx - 1 ? s + prev.w[1] * (px1 - ne) : s;
+      s = T.j > 0 ? s + prev.w[2] * (px1 - ns) : s;
+      s = T.j < ny - 1 ? s + prev.w[3] * (px1 - nn) : s;
+      s = k2 > 0 ? s + prev.w[4] * (px1 - px1m) : s;
+      s = k2 < nz - 1 ? s + prev.w[5] * (px1 - now.x1) : s;
+      const R x2 = px1 + om2 * recip(prev.dg) * (prev.b - s);
       xo[(long)T.i + (long)nx * T.j + pl * k2] = x2;
-      acc += (double)pb * (double)x2;
+      acc += (double)prev.b * (double)x2;
     }
-    px1m = px1;
-    px1 = x1own;
-    pdg = dgo;
-    pb = bo;
-    pin = ino;
-#pragma unroll
-    for (int f = 0; f < 6; ++f) pw[f] = w[f];
+    px1m = prev.x1;
+  };
+  int k = ks;
+  for (; k + 1 <= kend; k += 2) {
+    plane(k, oa, ob);
+    plane(k + 1, ob, oa);
   }
+  if (k <= kend) plane(k, oa, ob);
   if (part) {
     __shared__ double sh[16];
     const double sacc = block_reduce<0>(acc, sh);

@@ -20,6 +20,8 @@
 // one passive cell field, or T alone with cell materials.
 #include <algorithm>
 
+#include <type_traits>
+
 #include "tcf_device.h"
 #include "tcf_internal.h"
 
@@ -190,33 +192,27 @@ __global__ __launch_bounds__(512) void k_transport2(KParams P, int kz, int ntx, 
   const unsigned uoL = (unsigned)(min(i, nx) + (nx + 1) * jc);
   const unsigned voL = (unsigned)(ic + nx * min(j, ny));
   const unsigned co = (unsigned)(ic + nx * jc);
-  // column queues (k-3 .. k+3); in 2D only the centre is used
-  R qa[7], qt[7];
-  for (int m = 0; m < 7; ++m) {
+  // column queues: planes k-3 .. k+4 of the pair of planes (k, k+1) the
+  // loop computes per pass (plane k reads entries 0..6, plane k+1 entries
+  // 1..7); in 2D only the centre (entry 3) is used
+  R qa[8], qt[8];
+  for (int m = 0; m < 8; ++m) {
     qa[m] = R(0);
     qt[m] = R(0);
   }
   const int kq = min(k1 + 2, nz + 2);  // last plane the queues need
-  R ia = R(0), iT = R(0);              // plane k+3 of the column, in flight
+  R ia0 = R(0), iT0 = R(0), ia1 = R(0), iT1 = R(0);  // planes k+5 and k+6 of the column, in flight
   if (DIM == 3) {
-    for (int m = 0; m < 6; ++m) {
-      qa[m + 1] = ldA(cm.off, k0 - 3 + m);
-      if (WT) qt[m + 1] = tval(cm, ldT(cm.off, k0 - 3 + m), k0 - 3 + m);
+    for (int m = 0; m < 8; ++m) {
+      const int kk = k0 - 3 + m, kl = min(kk, kq);
+      qa[m] = ldA(cm.off, kl);
+      if (WT) qt[m] = tval(cm, ldT(cm.off, kl), kk);
     }
-    ia = ldA(cm.off, min(k0 + 3, kq));
-    if (WT) iT = ldT(cm.off, min(k0 + 3, kq));
   } else {
     qa[3] = ldA(cm.off, 0);
     if (WT) qt[3] = tval(cm, ldT(cm.off, 0), 0);
   }
-  R ha = ldA(hm.off, k0), hT = WT ? ldT(hm.off, k0) : R(0);  // halo of plane k (raw T)
-  // velocities and base state of plane k (loaded one plane ahead)
-  R uL = u[(size_t)k0 * plu + uoL];
-  R vL = v[(size_t)k0 * plv + voL];
-  R wH = DIM == 3 ? w[(size_t)(k0 + 1) * pl + co] : R(0);
-  R bA = WA ? ab[(size_t)k0 * pl + co] : R(0), bT = WT ? Tb[(size_t)k0 * pl + co] : R(0);
   const bool wq = MODE == 2 && P.qP != 0.0;
-  R bR = MODE == 2 ? rc[(size_t)k0 * pl + co] : R(0), bQ = wq ? dq[(size_t)k0 * pl + co] : R(0);
   const R wL0 = DIM == 3 ? w[(size_t)k0 * pl + co] : R(0);
   // Tile-edge role: lane tid < NEF * NE computes field ef at edge face ee,
   // the high x-face of row ee (ee < TY) or the high y-face of column ee - TY.
@@ -240,45 +236,45 @@ __global__ __launch_bounds__(512) void k_transport2(KParams P, int kz, int ntx, 
     const double R2 = P.qr * P.qr;
     qcol = R(2.0 * P.qP / (M_PI * R2) * exp(-2.0 * r2 / R2));
   }
+  // One plane's operands, loaded one plane ahead: the velocities of its
+  // faces, the tile-edge face velocity, the base state, the halo (raw T).
+  // Two sets take turns (the loop computes two planes per pass), so no
+  // register is copied from plane to plane.
+  struct Pre {
+    R u, v, w, ev, ba, bT, rc, dq, ha, hT;
+  };
+  auto load_pre = [&](Pre& p, int kk) {
+    p.u = u[(size_t)kk * plu + uoL];
+    p.v = v[(size_t)kk * plv + voL];
+    p.ev = ev[(size_t)kk * epl + eoff];
+    p.w = DIM == 3 ? w[(size_t)min(kk + 1, nz) * pl + co] : R(0);
+    p.ba = WA ? ab[(size_t)kk * pl + co] : R(0);
+    p.bT = WT ? Tb[(size_t)kk * pl + co] : R(0);
+    p.rc = MODE == 2 ? rc[(size_t)kk * pl + co] : R(0);
+    p.dq = wq ? dq[(size_t)kk * pl + co] : R(0);
+    p.ha = ldA(hm.off, kk);
+    p.hT = WT ? ldT(hm.off, kk) : R(0);
+  };
   R fza_lo = R(0), fzt_lo = R(0);  // low z-face flux carried between planes
   bool have_lo = false;
-  int buf = 0;
-  for (int k = k0; k < k1; ++k) {
-    // shift the queues, insert plane k+3 (loaded one plane ago), load k+4
+  // plane k from the queue entries o .. o + 6 and the LDS buffer o
+  auto plane = [&](int k, auto oc, const Pre& cur, Pre& nxt) {
+    constexpr int o = decltype(oc)::value, buf = o;
+    // load plane k+5 of the column (it enters the queue after the pass)
     if (DIM == 3) {
-      for (int m = 0; m < 6; ++m) {
-        qa[m] = qa[m + 1];
-        qt[m] = qt[m + 1];
-      }
-      qa[6] = ia;
-      ia = ldA(cm.off, min(k + 4, kq));
-      if (WT) {
-        qt[6] = tval(cm, iT, k + 3);
-        iT = ldT(cm.off, min(k + 4, kq));
-      }
+      (o == 0 ? ia0 : ia1) = ldA(cm.off, min(k + 5, kq));
+      if (WT) (o == 0 ? iT0 : iT1) = ldT(cm.off, min(k + 5, kq));
     }
-    // publish the plane, then load the next plane's halo
+    // publish the plane, then load the next plane's operands
     if (cval) {
-      sa[buf][ty + H][tx + H] = qa[3];
-      if (WT) sT[buf][ty + H][tx + H] = qt[3];
+      sa[buf][ty + H][tx + H] = qa[o + 3];
+      if (WT) sT[buf][ty + H][tx + H] = qt[o + 3];
     }
     if (hvalid) {
-      sa[buf][hoy][hox] = ha;
-      if (WT) sT[buf][hoy][hox] = tval(hm, hT, k);
+      sa[buf][hoy][hox] = cur.ha;
+      if (WT) sT[buf][hoy][hox] = tval(hm, cur.hT, k);
     }
-    const int kn = min(k + 1, k1 - 1);
-    ha = ldA(hm.off, kn);
-    if (WT) hT = ldT(hm.off, kn);
-    // this plane's velocities and base state; prefetch the next plane's
-    const R ulo = uL, vlo = vL, whi = wH, abc = bA, Tbc = bT, rcc = bR, dqc = bQ, evel = eV;
-    uL = u[(size_t)kn * plu + uoL];
-    vL = v[(size_t)kn * plv + voL];
-    eV = ev[(size_t)kn * epl + eoff];
-    if (DIM == 3) wH = w[(size_t)min(kn + 1, nz) * pl + co];
-    if (WA) bA = ab[(size_t)kn * pl + co];
-    if (WT) bT = Tb[(size_t)kn * pl + co];
-    if (MODE == 2) bR = rc[(size_t)kn * pl + co];
-    if (wq) bQ = dq[(size_t)kn * pl + co];
+    load_pre(nxt, min(k + 1, k1 - 1));
     __syncthreads();
     R Fxa_lo = R(0), Fxt_lo = R(0), Fya_lo = R(0), Fyt_lo = R(0);
     const size_t c = (size_t)k * pl + co;
@@ -288,18 +284,18 @@ __global__ __launch_bounds__(512) void k_transport2(KParams P, int kz, int ntx, 
       // tile holds the ghost values there) and the wall faces are dropped by
       // selects, without exec-mask updates around the evaluations
       if (WA) {
-        const R fx = ulo * upw(sa[buf][Y][X - 3], sa[buf][Y][X - 2], sa[buf][Y][X - 1], sa[buf][Y][X],
-                               sa[buf][Y][X + 1], sa[buf][Y][X + 2], ulo, eps);
-        const R fy = vlo * upw(sa[buf][Y - 3][X], sa[buf][Y - 2][X], sa[buf][Y - 1][X], sa[buf][Y][X],
-                               sa[buf][Y + 1][X], sa[buf][Y + 2][X], vlo, eps);
+        const R fx = cur.u * upw(sa[buf][Y][X - 3], sa[buf][Y][X - 2], sa[buf][Y][X - 1], sa[buf][Y][X],
+                                 sa[buf][Y][X + 1], sa[buf][Y][X + 2], cur.u, eps);
+        const R fy = cur.v * upw(sa[buf][Y - 3][X], sa[buf][Y - 2][X], sa[buf][Y - 1][X], sa[buf][Y][X],
+                                 sa[buf][Y + 1][X], sa[buf][Y + 2][X], cur.v, eps);
         Fxa_lo = i > 0 ? fx : R(0);
         Fya_lo = j > 0 ? fy : R(0);
       }
       if (WT) {
-        const R fx = ulo * upw(sT[buf][Y][X - 3], sT[buf][Y][X - 2], sT[buf][Y][X - 1], sT[buf][Y][X],
-                               sT[buf][Y][X + 1], sT[buf][Y][X + 2], ulo, eps);
-        const R fy = vlo * upw(sT[buf][Y - 3][X], sT[buf][Y - 2][X], sT[buf][Y - 1][X], sT[buf][Y][X],
-                               sT[buf][Y + 1][X], sT[buf][Y + 2][X], vlo, eps);
+        const R fx = cur.u * upw(sT[buf][Y][X - 3], sT[buf][Y][X - 2], sT[buf][Y][X - 1], sT[buf][Y][X],
+                                 sT[buf][Y][X + 1], sT[buf][Y][X + 2], cur.u, eps);
+        const R fy = cur.v * upw(sT[buf][Y - 3][X], sT[buf][Y - 2][X], sT[buf][Y - 1][X], sT[buf][Y][X],
+                                 sT[buf][Y + 1][X], sT[buf][Y + 2][X], cur.v, eps);
         Fxt_lo = i > 0 ? fx : R(0);
         Fyt_lo = j > 0 ? fy : R(0);
       }
@@ -310,7 +306,7 @@ __global__ __launch_bounds__(512) void k_transport2(KParams P, int kz, int ntx, 
     // the domain; elsewhere the stencil holds stale LDS and is unused)
     if (erole) {
       const R* sb = &sq[ef][buf][0][0] + est;
-      sedge[ef][ee] = evel * upw(sb[0], sb[es], sb[2 * es], sb[3 * es], sb[4 * es], sb[5 * es], evel, eps);
+      sedge[ef][ee] = cur.ev * upw(sb[0], sb[es], sb[2 * es], sb[3 * es], sb[4 * es], sb[5 * es], cur.ev, eps);
     }
     // high x-face: next lane's low face
     R Fxa_hi = __shfl_down(Fxa_lo, 1, 64), Fxt_hi = WT ? __shfl_down(Fxt_lo, 1, 64) : R(0);
@@ -341,14 +337,18 @@ __global__ __launch_bounds__(512) void k_transport2(KParams P, int kz, int ntx, 
           fza_lo = R(0);
           fzt_lo = R(0);
           if (k > 0) {
-            if (WA) fza_lo = wL0 * upw(qa[0], qa[1], qa[2], qa[3], qa[4], qa[5], wL0, eps);
-            if (WT) fzt_lo = wL0 * upw(qt[0], qt[1], qt[2], qt[3], qt[4], qt[5], wL0, eps);
+            if (WA)
+              fza_lo = wL0 * upw(qa[o + 0], qa[o + 1], qa[o + 2], qa[o + 3], qa[o + 4], qa[o + 5], wL0, eps);
+            if (WT)
+              fzt_lo = wL0 * upw(qt[o + 0], qt[o + 1], qt[o + 2], qt[o + 3], qt[o + 4], qt[o + 5], wL0, eps);
           }
         }
         R fza_hi = R(0), fzt_hi = R(0);
         if (k + 1 < nz) {
-          if (WA) fza_hi = whi * upw(qa[1], qa[2], qa[3], qa[4], qa[5], qa[6], whi, eps);
-          if (WT) fzt_hi = whi * upw(qt[1], qt[2], qt[3], qt[4], qt[5], qt[6], whi, eps);
+          if (WA)
+            fza_hi = cur.w * upw(qa[o + 1], qa[o + 2], qa[o + 3], qa[o + 4], qa[o + 5], qa[o + 6], cur.w, eps);
+          if (WT)
+            fzt_hi = cur.w * upw(qt[o + 1], qt[o + 2], qt[o + 3], qt[o + 4], qt[o + 5], qt[o + 6], cur.w, eps);
         }
         diva += fza_hi - fza_lo;
         divt += fzt_hi - fzt_lo;
@@ -356,9 +356,9 @@ __global__ __launch_bounds__(512) void k_transport2(KParams P, int kz, int ntx, 
         fzt_lo = fzt_hi;
         have_lo = true;
       }
-      const R ac = qa[3], Tc = qt[3];
+      const R ac = qa[o + 3], Tc = qt[o + 3];
       const R La = -diva * ih;
-      if (WA) ao[c] = cb * abc + ci * (ac + dt * La);
+      if (WA) ao[c] = cb * cur.ba + ci * (ac + dt * La);
       if (WT) {
         // conduction: arithmetic-mean face conductivity, ghosts from the tile
         auto lam = [&](R x) { return MODE == 2 ? x : mixp(x, P.lam1, P.lam2); };
@@ -369,31 +369,51 @@ __global__ __launch_bounds__(512) void k_transport2(KParams P, int kz, int ntx, 
           const R tn[4] = {sT[buf][Y][X - 1], sT[buf][Y][X + 1], sT[buf][Y - 1][X], sT[buf][Y + 1][X]};
           for (int f = 0; f < 4; ++f) cond += R(0.5) * (lc + lam(an[f])) * (tn[f] - Tc);
           if (DIM == 3) {
-            cond += R(0.5) * (lc + lam(qa[2])) * (qt[2] - Tc);
-            cond += R(0.5) * (lc + lam(qa[4])) * (qt[4] - Tc);
+            cond += R(0.5) * (lc + lam(qa[o + 2])) * (qt[o + 2] - Tc);
+            cond += R(0.5) * (lc + lam(qa[o + 4])) * (qt[o + 4] - Tc);
           }
         }
         cond *= ih * ih;
         R src = R(0);
         if (MODE == 2) {
-          src = qcol * dqc;
+          src = qcol * cur.dq;
         } else if (P.qP != 0.0) {
           const R h2 = R(0.5) * ih;
           const R gx = (sa[buf][Y][X + 1] - sa[buf][Y][X - 1]) * h2;
           const R gy = (sa[buf][Y + 1][X] - sa[buf][Y - 1][X]) * h2;
-          const R gz = DIM == 3 ? (qa[4] - qa[2]) * h2 : R(0);
+          const R gz = DIM == 3 ? (qa[o + 4] - qa[o + 2]) * h2 : R(0);
           const R g2 = gx * gx + gy * gy + gz * gz;
           if (g2 != R(0)) {  // delta_s vanishes off the interface (skipped by whole wavefronts there)
             const R ne = R(P.neps);
             src = qcol * (g2 * rcpx(sqrtx(g2 + ne * ne) + ne));
           }
         }
-        const R LT = -divt * ih + (cond + src) * rcpx(MODE == 2 ? rcc : mixp(ac, P.rhocp1, P.rhocp2));
-        To[c] = cb * Tbc + ci * (Tc + dt * LT);
+        const R LT = -divt * ih + (cond + src) * rcpx(MODE == 2 ? cur.rc : mixp(ac, P.rhocp1, P.rhocp2));
+        To[c] = cb * cur.bT + ci * (Tc + dt * LT);
       }
     }
-    buf ^= 1;
+  };
+  Pre pa, pb;
+  load_pre(pa, k0);
+  int k = k0;
+  for (; k + 1 < k1; k += 2) {
+    plane(k, std::integral_constant<int, 0>(), pa, pb);
+    plane(k + 1, std::integral_constant<int, 1>(), pb, pa);
+    // the queues move on by two planes
+    if (DIM == 3) {
+      for (int m = 0; m < 6; ++m) {
+        qa[m] = qa[m + 2];
+        qt[m] = qt[m + 2];
+      }
+      qa[6] = ia0;
+      qa[7] = ia1;
+      if (WT) {
+        qt[6] = tval(cm, iT0, k + 5);
+        qt[7] = tval(cm, iT1, k + 6);
+      }
+    }
   }
+  if (k < k1) plane(k, std::integral_constant<int, 0>(), pa, pb);
 }
 
 }  // namespace
