@@ -1253,9 +1253,9 @@ __global__ __launch_bounds__(256) void k_project_diag(KParams P, int kz, int ntx
     o.wsh = DIM == 3 ? ws[c + pl] : R(0);
     o.av = a[c];
   };
-  Ops cur, nxt;
-  load(k0, cur);
-  for (int k = k0; k < k1; ++k) {
+  // plane k from `cur`, while the next plane's operands load into `nxt`; two
+  // operand sets take turns (two planes per pass), so none is copied
+  auto step = [&](int k, const Ops& cur, Ops& nxt) {
     load(min(k + 1, k1 - 1), nxt);
     const long c = col + (long)k * pl;
     const long fx = fidx<0>(ic, jc, k, nx, ny), fy = fidx<1>(ic, jc, k, nx, ny);
@@ -1316,8 +1316,15 @@ __global__ __launch_bounds__(256) void k_project_diag(KParams P, int kz, int ntx
     am = ac;
     ac = ap;
     ap = an;
-    cur = nxt;
+  };
+  Ops oa, ob;
+  load(k0, oa);
+  int k = k0;
+  for (; k + 1 < k1; k += 2) {
+    step(k, oa, ob);
+    step(k + 1, ob, oa);
   }
+  if (k < k1) step(k, oa, ob);
   diag_partials(s, mn, mx, d2, um, fin, part, stride, sh);
 }
 
