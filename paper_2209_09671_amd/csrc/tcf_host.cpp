@@ -35,7 +35,18 @@ tcf_status fail(tcf_status st, const std::string& msg) {
   } while (0)
 
 constexpr size_t kAlign = 256;
-constexpr double kOmegaC = 1.9;  // over-correction of the piecewise-constant coarse correction
+// over-correction of the piecewise-constant coarse correction
+#ifndef TCF_OMEGA_C
+#define TCF_OMEGA_C 1.9
+#endif
+constexpr double kOmegaC = TCF_OMEGA_C;
+// the Chebyshev interval [lo, hi] of D^-1 K whose nodes give the 3-D sweep weights
+#ifndef TCF_CHEB_LO
+#define TCF_CHEB_LO 0.4
+#endif
+#ifndef TCF_CHEB_HI
+#define TCF_CHEB_HI 2.0
+#endif
 constexpr int kCoarseSweeps = 30;
 // fraction of the FP64 target that an inner FP32 solve aims at (its
 // recurrence residual overstates the true reduction by FP32 rounding)
@@ -593,7 +604,7 @@ inline double jacobi_omega(int dim) { return dim == 2 ? 0.8 : 6.0 / 7.0; }
 // the V-cycle, and so the preconditioner, symmetric.
 inline double sweep_omega(int dim, int nu, int k) {
   if (dim == 2) return 0.8;
-  const double lo = 0.4, hi = 2.0;
+  const double lo = TCF_CHEB_LO, hi = TCF_CHEB_HI;
   const double lam = 0.5 * (lo + hi) + 0.5 * (hi - lo) * std::cos((2.0 * k + 1.0) * M_PI / (2.0 * nu));
   return 1.0 / lam;
 }
