@@ -259,7 +259,9 @@ tcf_status tcf_apply_A(tcf_grid* g, const double* x, double* y);
  * and the upwind side follows the sign of the advecting velocity.  Adjoint
  * sums use FP64 atomics: results agree to rounding, not bitwise, run to run.
  * Afterwards the grid's fields are unspecified: call tcf_set_fields again
- * before tcf_step.  Entries of adj_n must not alias adj_np1 or state_n. */
+ * before tcf_step.  Entries of adj_n must not alias adj_np1 or state_n.
+ * TCF_E_INVALID on a grid created with TCF_TRANSPORT_ONLY (whose step is S1
+ * alone; tcf_adjoint_transport is its adjoint). */
 tcf_status tcf_step_backward(tcf_grid* g, double t_n, double dt, const double* const state_n[6],
                              const double* const adj_np1[5], double* const adj_n[5], double* dL_dsigmaT);
 

@@ -625,6 +625,34 @@ struct FromR64 {
   int np;
 };
 
+// The rest of the V-cycle from level l runs in one block (k_mg_tail).
+template <class R>
+bool tail_at(const Fields<R>& F, size_t l, int nu) {
+  long tail_lds = 0;
+  for (size_t q = l; q < F.lv.size(); ++q) tail_lds += 3 * F.lv[q].n();
+  return F.lv[l].n() <= kMgTailCells && F.lv.size() - l <= (size_t)kTailLevels && nu <= kTailNu &&
+         tail_lds <= kTailLds;
+}
+
+// Coarse level l runs its cycle as the fused pair of launches
+// (mg_sweep_restrict, mg_prolong_sweep2): two sweeps on each side, a
+// launch-bound size, a coarser level below it and no one-block tail from it.
+// Its first pre-sweep (written by the parent's restriction) is kept in the
+// level's x instead of x2.
+template <class R>
+bool fused_level(const tcf_grid* g, const Fields<R>& F, size_t l) {
+  return l >= 1 && l + 1 < F.lv.size() && g->cfg.mg_nu == 2 && mg_fused_level(F.lv[l].n()) &&
+         !tail_at(F, l, g->cfg.mg_nu);
+}
+
+// Where the restriction into level c writes c's first pre-sweep: none if c is
+// the coarsest (solved, not smoothed), x for a fused level, else x2.
+template <class R>
+R* first_sweep_target(const tcf_grid* g, Fields<R>& F, size_t c) {
+  if (c + 1 >= F.lv.size()) return nullptr;
+  return fused_level(g, F, c) ? F.lv[c].x : F.lv[c].x2;
+}
+
 template <class R>
 R* vcycle(tcf_grid* g, Fields<R>& F, size_t l, const R* b, R* out, R* tmp, double* part, bool first_done, int* np,
           FromR64* f64 = nullptr) {
@@ -665,7 +693,7 @@ R* vcycle(tcf_grid* g, Fields<R>& F, size_t l, const R* b, R* out, R* tmp, doubl
     const R* cur = bufs[(w - 1) & 1];
     // a coarse level that smooths gets its first sweep from the restriction
     const bool cfirst = l + 2 < F.lv.size();
-    fine_resid_restrict<R>(s, dim, Fd, b, cur, C.b, C.wdiag, cfirst ? C.x2 : nullptr, wpre(0), g->iflag);
+    fine_resid_restrict<R>(s, dim, Fd, b, cur, C.b, C.wdiag, first_sweep_target(g, F, 1), wpre(0), g->iflag);
     vcycle<R>(g, F, 1, C.b, C.x, C.x2, nullptr, cfirst, nullptr);
     if constexpr (std::is_same<R, float>::value) {
       if (kFusePost && dim == 3 && nu == 2) {
@@ -690,9 +718,7 @@ R* vcycle(tcf_grid* g, Fields<R>& F, size_t l, const R* b, R* out, R* tmp, doubl
     if (np) *np = n;
     return out;
   }
-  long tail_lds = 0;
-  for (size_t q = l; q < F.lv.size(); ++q) tail_lds += 3 * F.lv[q].n();
-  if (L.n() <= kMgTailCells && F.lv.size() - l <= (size_t)kTailLevels && nu <= kTailNu && tail_lds <= kTailLds) {
+  if (tail_at(F, l, nu)) {
     // the rest of the cycle in one block (b, out, tmp are this level's b, x, x2)
     MgTail<R> T{};
     T.nl = (int)(F.lv.size() - l);
@@ -710,14 +736,22 @@ R* vcycle(tcf_grid* g, Fields<R>& F, size_t l, const R* b, R* out, R* tmp, doubl
     mg_tail<R>(s, dim, T, g->iflag);
     return out;
   }
+  const bool cfirst = l + 2 < F.lv.size();
+  if (first_done && fused_level(g, F, l)) {
+    // x1 (the first pre-sweep) is in out; x2 goes to tmp and the result to out
+    mg_sweep_restrict<R>(s, dim, L, b, out, tmp, C.b, C.wdiag, first_sweep_target(g, F, l + 1), wpre(1), wpre(0),
+                         g->iflag);
+    vcycle<R>(g, F, l + 1, C.b, C.x, C.x2, nullptr, cfirst, nullptr);
+    mg_prolong_sweep2<R>(s, dim, L, C, b, tmp, out, kOmegaC, wpost(0), wpost(1), g->iflag);
+    return out;
+  }
   int w = 0;  // next write goes to bufs[w & 1]
   if (!first_done) mg_smooth_first<R>(s, L, b, bufs[w & 1], wpre(0), g->iflag);
   ++w;
   for (int k = 1; k < nu; ++k, ++w)
     mg_smooth<R>(s, dim, L, b, bufs[(w - 1) & 1], bufs[w & 1], wpre(k), nullptr, g->iflag);
   const R* cur = bufs[(w - 1) & 1];
-  const bool cfirst = l + 2 < F.lv.size();
-  mg_resid_restrict<R>(s, dim, L, b, cur, C.b, C.wdiag, cfirst ? C.x2 : nullptr, wpre(0), g->iflag);
+  mg_resid_restrict<R>(s, dim, L, b, cur, C.b, C.wdiag, first_sweep_target(g, F, l + 1), wpre(0), g->iflag);
   vcycle<R>(g, F, l + 1, C.b, C.x, C.x2, nullptr, cfirst, nullptr);
   mg_prolong_smooth<R>(s, dim, L, C, b, cur, bufs[w & 1], kOmegaC, wpost(0), nullptr, g->iflag);
   ++w;
@@ -1892,6 +1926,8 @@ static tcf_status backward_args(tcf_grid* g, double t_n, double dt, const double
                          const double* const adj_np1[5], double* const adj_n[5], double* dL_dsigmaT) {
   tcf_status st = adj_checks(g);
   if (st != TCF_OK) return st;
+  if (g->cfg.flags & TCF_TRANSPORT_ONLY)
+    return fail(TCF_E_INVALID, "the step adjoint covers S1..S8; this grid steps with TCF_TRANSPORT_ONLY");
   const Dims& D = g->D;
   if (!state_n || !adj_np1 || !adj_n || !dL_dsigmaT) return fail(TCF_E_INVALID, "NULL argument");
   for (int k = 0; k < 5; ++k) {

@@ -141,6 +141,16 @@ void mg_resid_restrict(hipStream_t s, int dim, const Level<R>& F, const R* b, co
 template <class R>
 void mg_prolong_smooth(hipStream_t s, int dim, const Level<R>& F, const Level<R>& C, const R* b, const R* x,
                        R* xo, double omega_c, double om, double* part_rz, const int* iflag);
+// Levels whose two pre-sweeps' second sweep, residual and restriction, and
+// whose prolongation and two post-sweeps, run as one launch each (levels
+// of at most this many cells, where a kernel costs its launch)
+bool mg_fused_level(long n);
+template <class R>
+void mg_sweep_restrict(hipStream_t s, int dim, const Level<R>& F, const R* b, const R* x, R* xo, R* bc,
+                       const R* wdc, R* x1c, double om, double om0, const int* iflag);
+template <class R>
+void mg_prolong_sweep2(hipStream_t s, int dim, const Level<R>& F, const Level<R>& C, const R* b, const R* x, R* xo,
+                       double omega_c, double om1, double om2, const int* iflag);
 template <class R>
 void mg_coarse_solve(hipStream_t s, int dim, const Level<R>& L, const R* b, R* x, int sweeps, double om,
                      const int* iflag);

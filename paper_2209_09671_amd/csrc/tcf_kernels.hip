@@ -379,6 +379,38 @@ __device__ __forceinline__ R applyK(const R* __restrict__ x, const R* __restrict
   return s;
 }
 
+// applyK with the neighbours taken from X(i, j, k) (an LDS tile) instead of
+// an array: the same loads and the same order of the face terms, so the
+// result is applyK's bit for bit
+template <class R, int DIM, class XAT>
+__device__ __forceinline__ R applyK_at(const XAT& X, const R* __restrict__ ax, const R* __restrict__ ay,
+                                       const R* __restrict__ az, int i, int j, int k, int nx, int ny, int nz) {
+  const bool w = i > 0, e = i < nx - 1, so = j > 0, no = j < ny - 1;
+  const bool lo = DIM == 3 && k > 0, hi = DIM == 3 && k < nz - 1;
+  const R xc = X(i, j, k);
+  const R xw = X(w ? i - 1 : i, j, k), xe = X(e ? i + 1 : i, j, k);
+  const R xs = X(i, so ? j - 1 : j, k), xn = X(i, no ? j + 1 : j, k);
+  const R aw = ax[fidx<0>(i, j, k, nx, ny)], ae = ax[fidx<0>(i + 1, j, k, nx, ny)];
+  const R as = ay[fidx<1>(i, j, k, nx, ny)], an = ay[fidx<1>(i, j + 1, k, nx, ny)];
+  R xl = R(0), xh = R(0), al = R(0), ah = R(0);
+  if (DIM == 3) {
+    xl = X(i, j, lo ? k - 1 : k);
+    xh = X(i, j, hi ? k + 1 : k);
+    al = az[fidx<2>(i, j, k, nx, ny)];
+    ah = az[fidx<2>(i, j, k + 1, nx, ny)];
+  }
+  R s = R(0);
+  s = w ? s + aw * (xc - xw) : s;
+  s = e ? s + ae * (xc - xe) : s;
+  s = so ? s + as * (xc - xs) : s;
+  s = no ? s + an * (xc - xn) : s;
+  if (DIM == 3) {
+    s = lo ? s + al * (xc - xl) : s;
+    s = hi ? s + ah * (xc - xh) : s;
+  }
+  return s;
+}
+
 // rhs = -(b - mean); r = rhs - K x (FP64 b, level precision vectors)
 template <class R, int DIM>
 __global__ __launch_bounds__(256) void k_rhs_resid(Level<R> L, const double* __restrict__ b,
@@ -603,6 +635,118 @@ __global__ __launch_bounds__(256) void k_prolong_smooth(Level<R> L, int cnx, int
   if (part) {
     const double s = block_reduce<0>(val, sh);
     if (threadIdx.x == 0 && threadIdx.y == 0) part[block_linear()] = s;
+  }
+}
+
+// Levels of at most 64^3 cells (their kernels take about the same time
+// whatever their size: the launch, not the work) with two sweeps before
+// and after the coarse correction run two launches per V-cycle instead of
+// four.  A block owns a CTX x CTY x CTZ tile (CTZ = 1 in 2-D); its first
+// stage sweeps the tile and a one-cell ring (in the domain) into LDS, each
+// ring cell being swept again by every block that borders it, and the second
+// stage takes the tile's neighbours from there:
+//   k_sweep_restrict: x2 = sweep(x1) (written), r = b - K x2, b_c = R r, and
+//     the coarse level's first sweep x1_c = om0 b_c / diag_c;
+//   k_prolong_sweep2: x' = x + omc P e swept twice, the result written.
+// Every value is the one the per-level kernels compute (same cell bodies,
+// same order of the face terms and of the children's sum).
+constexpr int CTX = 16, CTY = 8;
+template <int DIM>
+constexpr int ctile_z() {
+  return DIM == 3 ? 4 : 1;
+}
+template <int DIM>
+constexpr int ctile_threads() {
+  return CTX * CTY * ctile_z<DIM>();
+}
+
+template <class R, int DIM>
+__global__ __launch_bounds__(ctile_threads<DIM>()) void k_sweep_restrict(Level<R> L, int cnx, int cny,
+                                                                      const R* __restrict__ b,
+                                                                      const R* __restrict__ x, R* __restrict__ xo,
+                                                                      R* __restrict__ bc, const R* __restrict__ wdc,
+                                                                      R* __restrict__ x1c, R om, R om0,
+                                                                      const int* __restrict__ iflag) {
+  constexpr int TZ = ctile_z<DIM>(), NT = ctile_threads<DIM>();
+  constexpr int RX = CTX + 2, RY = CTY + 2, RZ = DIM == 3 ? TZ + 2 : 1, NR = RX * RY * RZ;
+  constexpr int KZ = DIM == 3 ? 2 : 1;  // fine planes per coarse plane
+  __shared__ R s1[NR];
+  __shared__ R sr[NT];
+  const int done = iflag[I_DONE];
+  const int nx = L.nx, ny = L.ny, nz = L.nz;
+  const int i0 = blockIdx.x * CTX, j0 = blockIdx.y * CTY, k0 = blockIdx.z * TZ;
+  const int tid = threadIdx.x;
+  for (int q = tid; q < NR; q += NT) {
+    const int rx = q % RX, ry = (q / RX) % RY, rz = q / (RX * RY);
+    const int ii = i0 - 1 + rx, jj = j0 - 1 + ry, kk = DIM == 3 ? k0 - 1 + rz : 0;
+    if (ii >= 0 && ii < nx && jj >= 0 && jj < ny && kk >= 0 && kk < nz)
+      s1[q] = smooth_cell<R, DIM>(L, b, x, om, ii, jj, kk, cidx(ii, jj, kk, nx, ny));
+  }
+  if (done) return;  // the same for the whole block
+  __syncthreads();
+  const int tx = tid % CTX, ty = (tid / CTX) % CTY, tz = tid / (CTX * CTY);
+  const int i = i0 + tx, j = j0 + ty, k = k0 + tz;
+  // (every position X is asked for lies in the tile or its ring, in the domain)
+  auto X = [&](int ii, int jj, int kk) {
+    return s1[(ii - i0 + 1) + RX * ((jj - j0 + 1) + RY * (DIM == 3 ? kk - k0 + 1 : 0))];
+  };
+  if (i < nx && j < ny && k < nz) {
+    const long c = cidx(i, j, k, nx, ny);
+    xo[c] = X(i, j, k);
+    sr[tid] = b[c] - applyK_at<R, DIM>(X, L.ax, L.ay, L.az, i, j, k, nx, ny, nz);
+  }
+  __syncthreads();
+  // one thread per coarse cell of the tile sums its children in (dk, dj, di)
+  // order; the level's sizes are even, so a cell's children are all inside
+  // the domain or none is
+  constexpr int CX = CTX / 2, CY = CTY / 2, CZ = TZ / KZ;
+  if (tid < CX * CY * CZ) {
+    const int ti = tid % CX, tj = (tid / CX) % CY, tk = tid / (CX * CY);
+    const int I = i0 / 2 + ti, J = j0 / 2 + tj, K = k0 / KZ + tk;
+    if (2 * I < nx && 2 * J < ny && KZ * K < nz) {
+      R sum = R(0);
+      for (int dk = 0; dk < KZ; ++dk)
+        for (int dj = 0; dj < 2; ++dj)
+          for (int di = 0; di < 2; ++di) sum += sr[(2 * ti + di) + CTX * ((2 * tj + dj) + CTY * (KZ * tk + dk))];
+      const long ci = cidx(I, J, K, cnx, cny);
+      bc[ci] = sum;
+      if (x1c) x1c[ci] = om0 * wdc[ci] * sum;
+    }
+  }
+}
+
+template <class R, int DIM>
+__global__ __launch_bounds__(ctile_threads<DIM>()) void k_prolong_sweep2(Level<R> L, int cnx, int cny,
+                                                                      const R* __restrict__ e,
+                                                                      const R* __restrict__ b,
+                                                                      const R* __restrict__ x, R* __restrict__ xo,
+                                                                      R omc, R om1, R om2,
+                                                                      const int* __restrict__ iflag) {
+  constexpr int TZ = ctile_z<DIM>(), NT = ctile_threads<DIM>();
+  constexpr int RX = CTX + 2, RY = CTY + 2, RZ = DIM == 3 ? TZ + 2 : 1, NR = RX * RY * RZ;
+  __shared__ R s1[NR];
+  const int done = iflag[I_DONE];
+  const int nx = L.nx, ny = L.ny, nz = L.nz;
+  const int i0 = blockIdx.x * CTX, j0 = blockIdx.y * CTY, k0 = blockIdx.z * TZ;
+  const int tid = threadIdx.x;
+  for (int q = tid; q < NR; q += NT) {
+    const int rx = q % RX, ry = (q / RX) % RY, rz = q / (RX * RY);
+    const int ii = i0 - 1 + rx, jj = j0 - 1 + ry, kk = DIM == 3 ? k0 - 1 + rz : 0;
+    if (ii >= 0 && ii < nx && jj >= 0 && jj < ny && kk >= 0 && kk < nz)
+      s1[q] = prolong_smooth_cell<R, DIM>(L, cnx, cny, e, b, x, omc, om1, ii, jj, kk);
+  }
+  if (done) return;  // the same for the whole block
+  __syncthreads();
+  const int tx = tid % CTX, ty = (tid / CTX) % CTY, tz = tid / (CTX * CTY);
+  const int i = i0 + tx, j = j0 + ty, k = k0 + tz;
+  auto X = [&](int ii, int jj, int kk) {
+    return s1[(ii - i0 + 1) + RX * ((jj - j0 + 1) + RY * (DIM == 3 ? kk - k0 + 1 : 0))];
+  };
+  if (i < nx && j < ny && k < nz) {
+    const long c = cidx(i, j, k, nx, ny);
+    const R wd = L.wdiag[c], bv = b[c];
+    const R Kx = applyK_at<R, DIM>(X, L.ax, L.ay, L.az, i, j, k, nx, ny, nz);
+    xo[c] = X(i, j, k) + om2 * wd * (bv - Kx);
   }
 }
 
@@ -1550,6 +1694,37 @@ void mg_prolong_smooth(hipStream_t s, int dim, const Level<R>& F, const Level<R>
   else late ? go(k_prolong_smooth<R, 2, true>) : go(k_prolong_smooth<R, 2, false>);
 }
 
+bool mg_fused_level(long n) { return late_flag(n); }
+
+template <class R>
+void mg_sweep_restrict(hipStream_t s, int dim, const Level<R>& F, const R* b, const R* x, R* xo, R* bc,
+                       const R* wdc, R* x1c, double om, double om0, const int* iflag) {
+  const int cnx = F.nx / 2, cny = F.ny / 2;
+  if (dim == 3) {
+    const dim3 g((F.nx + CTX - 1) / CTX, (F.ny + CTY - 1) / CTY, (F.nz + ctile_z<3>() - 1) / ctile_z<3>());
+    hipLaunchKernelGGL((k_sweep_restrict<R, 3>), g, dim3(ctile_threads<3>()), 0, s, F, cnx, cny, b, x, xo, bc, wdc, x1c,
+                       R(om), R(om0), iflag);
+  } else {
+    const dim3 g((F.nx + CTX - 1) / CTX, (F.ny + CTY - 1) / CTY, 1);
+    hipLaunchKernelGGL((k_sweep_restrict<R, 2>), g, dim3(ctile_threads<2>()), 0, s, F, cnx, cny, b, x, xo, bc, wdc, x1c,
+                       R(om), R(om0), iflag);
+  }
+}
+
+template <class R>
+void mg_prolong_sweep2(hipStream_t s, int dim, const Level<R>& F, const Level<R>& C, const R* b, const R* x, R* xo,
+                       double omega_c, double om1, double om2, const int* iflag) {
+  if (dim == 3) {
+    const dim3 g((F.nx + CTX - 1) / CTX, (F.ny + CTY - 1) / CTY, (F.nz + ctile_z<3>() - 1) / ctile_z<3>());
+    hipLaunchKernelGGL((k_prolong_sweep2<R, 3>), g, dim3(ctile_threads<3>()), 0, s, F, C.nx, C.ny, C.x, b, x, xo,
+                       R(omega_c), R(om1), R(om2), iflag);
+  } else {
+    const dim3 g((F.nx + CTX - 1) / CTX, (F.ny + CTY - 1) / CTY, 1);
+    hipLaunchKernelGGL((k_prolong_sweep2<R, 2>), g, dim3(ctile_threads<2>()), 0, s, F, C.nx, C.ny, C.x, b, x, xo,
+                       R(omega_c), R(om1), R(om2), iflag);
+  }
+}
+
 template <class R>
 void mg_coarse_solve(hipStream_t s, int dim, const Level<R>& L, const R* b, R* x, int sweeps, double om,
                      const int* iflag) {
@@ -1740,6 +1915,10 @@ void zero_walls(const KParams& P, hipStream_t s, R* u, R* v, R* w) {
                                      double, const int*);                                                   \
   template void mg_prolong_smooth<R>(hipStream_t, int, const Level<R>&, const Level<R>&, const R*, const R*, R*,  \
                                      double, double, double*, const int*);                                  \
+  template void mg_sweep_restrict<R>(hipStream_t, int, const Level<R>&, const R*, const R*, R*, R*, const R*, R*, \
+                                     double, double, const int*);                                               \
+  template void mg_prolong_sweep2<R>(hipStream_t, int, const Level<R>&, const Level<R>&, const R*, const R*, R*,  \
+                                     double, double, double, const int*);                                       \
   template void mg_coarse_solve<R>(hipStream_t, int, const Level<R>&, const R*, R*, int, double, const int*);             \
   template void project<R>(const KParams&, hipStream_t, const R*, const double*, const R*, const R*, const R*,    \
                            double*, double*, double*, R*, R*, R*);                                                \

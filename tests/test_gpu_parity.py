@@ -261,6 +261,20 @@ def test_error_paths_on_device():
     r2 = g2.step(c2["dt"], 1, check=False)
     assert r2["status"] == tcf.TCF_E_NOT_CONVERGED
     g2.close()
+    # the step adjoint refuses a transport-only grid and NULL stage pointers
+    c3 = I.config(0)
+    g3 = tcf.Grid(c3, precision=0, flags=tcf.TCF_WITH_ADJOINT | tcf.TCF_TRANSPORT_ONLY)
+    st3 = I.initial_state(c3)
+    g3.set_state(st3)
+    sbar = torch.zeros((), dtype=torch.float64, device="cuda")
+    dev3 = {k: (None if v is None else torch.as_tensor(np.ascontiguousarray(v), dtype=torch.float64, device="cuda"))
+            for k, v in st3.items() if k in ("alpha", "T", "u", "v", "w", "p")}
+    lam = {k: (None if v is None else torch.zeros_like(v)) for k, v in dev3.items() if k != "p"}
+    with pytest.raises(tcf.TcfError) as ei:
+        g3.step_backward(0.0, c3["dt"], dev3, lam, sbar)
+    assert ei.value.status == tcf.TCF_E_INVALID
+    assert tcf.load().tcf_step_keep(g3.h, c3["dt"], None, None) == tcf.TCF_E_INVALID
+    g3.close()
 
 
 def test_full_size_meltpool_256_properties():
