@@ -148,6 +148,13 @@ struct tcf_grid {
   Dims D;
   KParams P;
   hipStream_t stream;
+  // a second stream (default priority) on which a step builds the pressure
+  // operator and its initial guess while the geometry and the predictor run
+  // on `stream`; forked and joined through the two events.  Grids from
+  // tcf_init_grid_static have none and run everything on `stream`.
+  hipStream_t side = nullptr;
+  hipEvent_t fork_ev = nullptr, join_ev = nullptr;
+  bool side_forked = false;  // the current step's side work is on `side`
   bool fp32;
   bool has_fields = false;
   bool has_species = false;  // species field set (configs with species = 1)
@@ -1134,6 +1141,38 @@ tcf_status step_np(tcf_grid* g, double dt, tcf_step_info* inf, bool want_diag) {
   return sd != TCF_OK ? sd : st;
 }
 
+void release_side(tcf_grid* g) {
+  if (g->join_ev) hipEventDestroy(g->join_ev);
+  if (g->fork_ev) hipEventDestroy(g->fork_ev);
+  if (g->side) hipStreamDestroy(g->side);
+  g->join_ev = g->fork_ev = nullptr;
+  g->side = nullptr;
+}
+
+// Run `work` (launches on g->stream) on the side stream after everything
+// queued on the main stream so far; join_side() makes the main stream wait
+// for it.  While a kernel family is being timed (tcf_profile) the work stays
+// on the main stream, so that the family's events time its kernels alone.
+template <class F>
+void on_side(tcf_grid* g, F&& work) {
+  g->side_forked = g->side && g->prof_family < 0;
+  if (!g->side_forked) {
+    work();
+    return;
+  }
+  hipEventRecord(g->fork_ev, g->stream);
+  hipStreamWaitEvent(g->side, g->fork_ev, 0);
+  hipStream_t main = g->stream;
+  g->stream = g->side;
+  work();
+  g->stream = main;
+  hipEventRecord(g->join_ev, g->side);
+}
+void join_side(tcf_grid* g) {
+  if (g->side_forked) hipStreamWaitEvent(g->stream, g->join_ev, 0);
+  g->side_forked = false;
+}
+
 // One step S1..S8 in precision R.
 template <class R>
 tcf_status step_once(tcf_grid* g, double dt, tcf_step_info* inf, bool want_diag) {
@@ -1172,6 +1211,12 @@ tcf_status step_once(tcf_grid* g, double dt, tcf_step_info* inf, bool want_diag)
   }
   tcf_status st = TCF_OK;
   if (!(g->cfg.flags & TCF_TRANSPORT_ONLY)) {
+    // the operator of alpha^{n+1} and the pressure's initial guess depend on
+    // neither the geometry nor the predictor: built beside them
+    on_side(g, [&] {
+      prepare_operator<R>(g);
+      pressure_guess(g);
+    });
     // S2-S5
     {
       Prof pr(g, FAM_GEOMETRY);
@@ -1186,8 +1231,7 @@ tcf_status step_once(tcf_grid* g, double dt, tcf_step_info* inf, bool want_diag)
     divergence_rhs<R>(P, s, F.us, F.vs, F.ws, g->b64, g->part[0]);
     finalize(s, g->part[0], nbc, g->scal, g->iflag, F_MEAN, S_MEAN, (double)D.N);
     // S7
-    prepare_operator<R>(g);
-    pressure_guess(g);
+    join_side(g);
     st = solve(g, g->p64, inf);
     if (st != TCF_OK && st != TCF_E_NOT_CONVERGED) return st;
     // S8
@@ -1528,9 +1572,19 @@ tcf_status tcf_init_grid(const tcf_config* cfg, void* workspace, size_t bytes, v
     delete g;
     return fail(TCF_E_DEVICE, "event creation failed");
   }
+  if (hipStreamCreateWithFlags(&g->side, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&g->fork_ev, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&g->join_ev, hipEventDisableTiming) != hipSuccess) {
+    release_side(g);
+    hipEventDestroy(g->rb_ev);
+    hipHostFree(g->hscal);
+    delete g;
+    return fail(TCF_E_DEVICE, "side stream creation failed");
+  }
   clear_start(g);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) {
+    release_side(g);
     hipEventDestroy(g->rb_ev);
     hipHostFree(g->hscal);
     delete g;
@@ -1825,6 +1879,8 @@ void tcf_destroy(tcf_grid* g) {
     g_static[g->static_dev].in_use = false;
     return;
   }
+  if (g->side) hipStreamSynchronize(g->side);
+  release_side(g);
   if (g->rb_ev) hipEventDestroy(g->rb_ev);
   hipHostFree(g->hscal);
   delete g;
