@@ -41,16 +41,16 @@ __device__ __forceinline__ float rcpx(float x) { return __builtin_amdgcn_rcpf(x)
 __device__ __forceinline__ double rcpx(double x) { return 1.0 / x; }
 
 // WENO5-JS reconstruction at the right edge of c, with one reciprocal for
-// the normalisation of each smoothness weight and one for the blend.  The
-// smoothness indicators beta_k = (13/12) t_k^2 + (1/4) u_k^2 and epsilon are
-// both taken times 12/13 (eps_w = (12/13) eps), which leaves the normalised
-// weights d_k / (eps + beta_k)^2 unchanged: one multiply and two FMAs per
-// indicator.
+// the normalisation of each smoothness weight and one for the blend.  With
+// t_k the second differences and u_k the one-sided differences of the three
+// candidate stencils, the candidates' values are c + (t_0 + 3 u_0)/12,
+// c + (t_1 - 3 u_1)/12 and c + (t_2 - 3 u_2)/12: the blend is c plus the
+// weighted mean of those corrections.  The smoothness indicators
+// beta_k = (13/12) t_k^2 + (1/4) u_k^2 and epsilon are both taken times
+// 12/13 (eps_w = (12/13) eps), which leaves the normalised weights
+// d_k / (eps + beta_k)^2 unchanged: one multiply and two FMAs per indicator.
 template <class R>
 __device__ __forceinline__ R weno5r(R a, R b, R c, R d, R e, R epsw) {
-  const R q0 = (R(2) * a - R(7) * b + R(11) * c);
-  const R q1 = (-b + R(5) * c + R(2) * d);
-  const R q2 = (R(2) * c + R(5) * d - e);
   const R t0 = a - R(2) * b + c, u0 = a - R(4) * b + R(3) * c;
   const R t1 = b - R(2) * c + d, u1 = b - d;
   const R t2 = c - R(2) * d + e, u2 = R(3) * c - R(4) * d + e;
@@ -59,7 +59,8 @@ __device__ __forceinline__ R weno5r(R a, R b, R c, R d, R e, R epsw) {
   const R i1 = rcpx(fma(cu * u1, u1, fma(t1, t1, epsw)));
   const R i2 = rcpx(fma(cu * u2, u2, fma(t2, t2, epsw)));
   const R a0 = R(0.1) * i0 * i0, a1 = R(0.6) * i1 * i1, a2 = R(0.3) * i2 * i2;
-  return (a0 * q0 + a1 * q1 + a2 * q2) * rcpx(R(6) * (a0 + a1 + a2));
+  const R sc = fma(a2, fma(R(-3), u2, t2), fma(a1, fma(R(-3), u1, t1), a0 * fma(R(3), u0, t0)));
+  return fma(sc, rcpx(R(12) * (a0 + a1 + a2)), c);
 }
 
 // Upwind value at the face between q2 and q3 (q0..q5 = Q(f-3..f+2)); the

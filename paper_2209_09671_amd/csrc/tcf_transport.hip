@@ -35,9 +35,13 @@ constexpr int SX = TX + 2 * H, SY = TY + 2 * H;
 constexpr int NHALO = 2 * H * TY + 2 * H * TX;  // x strips + y strips (corners unused)
 constexpr int NE = TY + TX;                     // tile-edge faces of a plane: x (one per row), y (one per column)
 
-// WENO5-JS with the normalisation folded into one reciprocal.  The
-// smoothness indicators beta_k = (13/12) t_k^2 + (1/4) u_k^2 and epsilon are
-// both taken times 12/13, which leaves the nonlinear weights
+// WENO5-JS.  With t_k the second differences and u_k the one-sided
+// differences of the three candidate stencils (a..e = Q(f-2..f+2), upwind
+// side first), the candidates' face values are c + (t_0 + 3 u_0)/12,
+// c + (t_1 - 3 u_1)/12 and c + (t_2 - 3 u_2)/12, so the blend is c plus the
+// weighted mean of those corrections and reuses the indicators' t_k and u_k.
+// The smoothness indicators beta_k = (13/12) t_k^2 + (1/4) u_k^2 and epsilon
+// are both taken times 12/13, which leaves the nonlinear weights
 // d_k / (eps + beta_k)^2 unchanged after normalisation: eps' + t_k^2 +
 // (3/13) u_k^2 with eps' = (12/13) eps (eps_w below), one multiply and two
 // FMAs per indicator.
@@ -50,9 +54,6 @@ __device__ __forceinline__ double sqrtx(double x) { return sqrt(x); }
 
 template <class R>
 __device__ __forceinline__ R weno5x(R a, R b, R c, R d, R e, R epsw) {
-  const R q0 = (R(2) * a - R(7) * b + R(11) * c);
-  const R q1 = (-b + R(5) * c + R(2) * d);
-  const R q2 = (R(2) * c + R(5) * d - e);
   const R t0 = a - R(2) * b + c, u0 = a - R(4) * b + R(3) * c;
   const R t1 = b - R(2) * c + d, u1 = b - d;
   const R t2 = c - R(2) * d + e, u2 = R(3) * c - R(4) * d + e;
@@ -61,7 +62,8 @@ __device__ __forceinline__ R weno5x(R a, R b, R c, R d, R e, R epsw) {
   const R i1 = rcpx(fma(cu * u1, u1, fma(t1, t1, epsw)));
   const R i2 = rcpx(fma(cu * u2, u2, fma(t2, t2, epsw)));
   const R a0 = R(0.1) * i0 * i0, a1 = R(0.6) * i1 * i1, a2 = R(0.3) * i2 * i2;
-  return (a0 * q0 + a1 * q1 + a2 * q2) * rcpx(R(6) * (a0 + a1 + a2));
+  const R sc = fma(a2, fma(R(-3), u2, t2), fma(a1, fma(R(-3), u1, t1), a0 * fma(R(3), u0, t0)));
+  return fma(sc, rcpx(R(12) * (a0 + a1 + a2)), c);
 }
 
 // q[m] = Q(f-3+m); value at face f, upwind by the sign of vel.  The stencil
@@ -133,7 +135,7 @@ __device__ __forceinline__ ColMap<R> col_map(const KParams& P, int ii, int jj, b
 // transported, ab and ao unused), rc the heat capacity rho c_p and dq the
 // interface delta that the heat flux is spread over.
 template <class R, int DIM, int MODE>
-__global__ __launch_bounds__(512) void k_transport2(KParams P, int kz, int ntx, int nty, const R* __restrict__ a,
+__global__ __launch_bounds__(512, sizeof(R) == 4 ? 4 : 1) void k_transport2(KParams P, int kz, int ntx, int nty, const R* __restrict__ a,
                                                     const R* __restrict__ T, const R* ab, const R* Tb,
                                                     const R* __restrict__ u, const R* __restrict__ v,
                                                     const R* __restrict__ w, R* ao, R* To, R cb, R ci,
