@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <array>
 #include <cmath>
 #include <cstdio>
@@ -182,6 +183,13 @@ struct tcf_grid {
   double* hscal;  // pinned host mirror (pageable, inside the slot, on a fixed-workspace grid)
   int* hflag;
   hipEvent_t rb_ev = nullptr;  // completion of the last copy into hscal
+  // On a grid with a host-coherent mirror the device writes the block into
+  // it (publish) followed by a ticket the host polls; pub_dev is the
+  // mirror's device address (null: the block is copied with hipMemcpyAsync).
+  void* pub_dev = nullptr;
+  unsigned* pub_dticket = nullptr;
+  volatile unsigned* pub_ticket = nullptr;
+  unsigned pub_seq = 0, pub_want = 0;
   int static_dev = -1;         // device whose fixed workspace this grid uses (-1: caller's workspace)
   // CG iterations the last solve of each kind took (0: none yet): the
   // state's pressure or another right-hand side, first or later refinement
@@ -535,7 +543,46 @@ KParams make_params(const tcf_config* c) {
 // S_NSLOT doubles) mirrored by one pinned host block: one copy per read.
 constexpr size_t kScalBlockBytes = sizeof(double) * S_NSLOT + sizeof(int) * I_NFLAG;
 
+static_assert(kScalBlockBytes % 8 == 0, "the scalar block is copied in 8-byte words");
+// host-coherent mirror: the block, then the ticket at kPubTicketOffset
+constexpr size_t kPubTicketOffset = 256, kPubBytes = 320;
+static_assert(kScalBlockBytes <= kPubTicketOffset, "the ticket follows the block");
+
+// Wait until the ticket of the publish queued last has arrived.  The stream
+// is queried now and then, so that an error on it, or a stream that has
+// drained without the ticket, ends the wait with an error instead of
+// spinning for ever.
+hipError_t wait_ticket(tcf_grid* g) {
+  const unsigned want = g->pub_want;
+  for (unsigned n = 1;; ++n) {
+    if (*g->pub_ticket == want) break;
+    if (n % 4096 == 0) {
+      const hipError_t e = hipStreamQuery(g->stream);
+      if (e == hipSuccess) {
+        // the publish has run: its stores are visible once it is complete
+        for (int r = 0; r < 1000000 && *g->pub_ticket != want; ++r) {
+        }
+        if (*g->pub_ticket != want) return hipErrorLaunchFailure;
+        break;
+      }
+      if (e != hipErrorNotReady) return e;
+    }
+  }
+  std::atomic_thread_fence(std::memory_order_acquire);
+  return hipSuccess;
+}
+
+hipError_t publish_block(tcf_grid* g) {
+  g->pub_want = ++g->pub_seq;
+  publish(g->stream, g->scal, (int)(kScalBlockBytes / 8), g->pub_dev, g->pub_dticket, g->pub_want);
+  return hipGetLastError();
+}
+
 hipError_t read_back(tcf_grid* g) {
+  if (g->pub_dev) {
+    const hipError_t e = publish_block(g);
+    return e != hipSuccess ? e : wait_ticket(g);
+  }
   hipError_t e = hipMemcpyAsync(g->hscal, g->scal, kScalBlockBytes, hipMemcpyDeviceToHost, g->stream);
   if (e != hipSuccess) return e;
   return hipStreamSynchronize(g->stream);
@@ -547,12 +594,13 @@ hipError_t read_back(tcf_grid* g) {
 // queued copy may fill after the event completes: the copy is waited for
 // on the stream there.
 hipError_t read_back_async(tcf_grid* g) {
+  if (g->pub_dev) return publish_block(g);
   hipError_t e = hipMemcpyAsync(g->hscal, g->scal, kScalBlockBytes, hipMemcpyDeviceToHost, g->stream);
   if (e != hipSuccess) return e;
   if (g->static_dev >= 0 && (e = hipStreamSynchronize(g->stream)) != hipSuccess) return e;
   return hipEventRecord(g->rb_ev, g->stream);
 }
-hipError_t wait_back(tcf_grid* g) { return hipEventSynchronize(g->rb_ev); }
+hipError_t wait_back(tcf_grid* g) { return g->pub_dev ? wait_ticket(g) : hipEventSynchronize(g->rb_ev); }
 
 // Launch constants of the pressure operator: the grid's, with the density
 // range of the operator's linear mix (no step size: for the solver only).
@@ -1563,10 +1611,18 @@ tcf_status tcf_init_grid(const tcf_config* cfg, void* workspace, size_t bytes, v
   tcf_grid* g = new (std::nothrow) tcf_grid();
   if (!g) return fail(TCF_E_INVALID, "host allocation failed");
   init_handle(g, cfg, workspace, bytes, hip_stream);
-  if (hipHostMalloc((void**)&g->hscal, kScalBlockBytes, hipHostMallocDefault) != hipSuccess) {
+  if (hipHostMalloc((void**)&g->hscal, kPubBytes, hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) {
     delete g;
     return fail(TCF_E_DEVICE, "pinned host buffer allocation failed");
   }
+  std::memset(g->hscal, 0, kPubBytes);
+  if (hipHostGetDevicePointer(&g->pub_dev, g->hscal, 0) != hipSuccess || !g->pub_dev) {
+    hipHostFree(g->hscal);
+    delete g;
+    return fail(TCF_E_DEVICE, "device address of the pinned host buffer not available");
+  }
+  g->pub_ticket = (volatile unsigned*)((char*)g->hscal + kPubTicketOffset);
+  g->pub_dticket = (unsigned*)((char*)g->pub_dev + kPubTicketOffset);
   if (hipEventCreateWithFlags(&g->rb_ev, hipEventDisableTiming) != hipSuccess) {
     hipHostFree(g->hscal);
     delete g;

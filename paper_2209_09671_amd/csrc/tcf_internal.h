@@ -198,6 +198,10 @@ void mg_tail(hipStream_t s, int dim, const MgTail<R>& T, const int* iflag);
 void finalize(hipStream_t s, const double* part, int nparts, double* scal, int* iflag, int op, int slot,
               double arg);
 void init_flags(hipStream_t s, int* iflag);
+// Copies nwords 8-byte words from device memory src to host-coherent memory
+// dst (device-visible), then stores value into *ticket (host memory), in
+// that order as seen by the host.
+void publish(hipStream_t s, const void* src, int nwords, void* dst, unsigned* ticket, unsigned value);
 
 // FP64 refinement helpers (FP32 mode)
 // r32 = r / scal[S_SCALE]; part: nblocks(256) partials of |r32|^2

@@ -1172,6 +1172,17 @@ __global__ __launch_bounds__(1024) void k_finalize(const double* __restrict__ pa
   }
 }
 
+// Copy of the scalar block (scalars and flags, nwords 8-byte words) into
+// host memory that the host polls, then the ticket it waits for.  One
+// wavefront: its fence covers every store of the copy, so the host that
+// sees the ticket sees the block.
+__global__ __launch_bounds__(64) void k_publish(const unsigned long long* __restrict__ src, int nwords,
+                                                unsigned long long* dst, unsigned* ticket, unsigned value) {
+  for (int q = threadIdx.x; q < nwords; q += 64) dst[q] = src[q];
+  __threadfence_system();
+  if (threadIdx.x == 0) __hip_atomic_store(ticket, value, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
 __global__ void k_init_flags(int* iflag) {
   if (threadIdx.x < I_NFLAG) iflag[threadIdx.x] = 0;
 }
@@ -1767,6 +1778,11 @@ void finalize(hipStream_t s, const double* part, int nparts, double* scal, int* 
 }
 
 void init_flags(hipStream_t s, int* iflag) { hipLaunchKernelGGL(k_init_flags, dim3(1), dim3(64), 0, s, iflag); }
+
+void publish(hipStream_t s, const void* src, int nwords, void* dst, unsigned* ticket, unsigned value) {
+  hipLaunchKernelGGL(k_publish, dim3(1), dim3(64), 0, s, (const unsigned long long*)src, nwords,
+                     (unsigned long long*)dst, ticket, value);
+}
 
 template <class R>
 void coarsen_from_alpha(const KParams& P, hipStream_t s, const R* a, const Level<R>& C) {
