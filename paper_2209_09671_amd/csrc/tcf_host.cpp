@@ -572,15 +572,18 @@ hipError_t wait_ticket(tcf_grid* g) {
   return hipSuccess;
 }
 
-hipError_t publish_block(tcf_grid* g) {
+hipError_t publish_block(tcf_grid* g, bool reset_flags = false) {
   g->pub_want = ++g->pub_seq;
-  publish(g->stream, g->scal, (int)(kScalBlockBytes / 8), g->pub_dev, g->pub_dticket, g->pub_want);
+  publish(g->stream, g->scal, (int)(kScalBlockBytes / 8), g->pub_dev, g->pub_dticket, g->pub_want,
+          reset_flags ? g->iflag : nullptr);
   return hipGetLastError();
 }
 
-hipError_t read_back(tcf_grid* g) {
+// reset_flags: on a grid with a host-coherent mirror, the device clears the
+// flags once they are copied (the caller needs no init_flags after it).
+hipError_t read_back(tcf_grid* g, bool reset_flags = false) {
   if (g->pub_dev) {
-    const hipError_t e = publish_block(g);
+    const hipError_t e = publish_block(g, reset_flags);
     return e != hipSuccess ? e : wait_ticket(g);
   }
   hipError_t e = hipMemcpyAsync(g->hscal, g->scal, kScalBlockBytes, hipMemcpyDeviceToHost, g->stream);
@@ -939,9 +942,11 @@ tcf_status solve_refined(tcf_grid* g, double* p, int kind, int* iters, int* nref
       nrp = resid64a<float>(op_params(g), s, fine_desc<float>(g).a, g->b64, g->scal, p, g->r64, g->part[0],
                             g->part[1]);
     }
-    finalize(s, g->part[0], nrp, g->scal, g->iflag, F_STORE, S_BB64, 0.0);
-    finalize(s, g->part[1], nrp, g->scal, g->iflag, F_SCALE, 0, (double)N);
-    HIPCHECK(read_back(g));
+    finalize2(s, g->part[0], g->part[1], nrp, g->scal, g->iflag, F_STORE, S_BB64, 0.0, F_SCALE, 0, (double)N);
+    // the read-back clears the flags for the inner solve where it can (no
+    // kernel after the solve reads them)
+    const bool cleared = g->pub_dev != nullptr;
+    HIPCHECK(read_back(g, cleared));
     bb = g->hscal[S_BB64];
     const double rr = g->hscal[S_RR64];
     if (!std::isfinite(bb) || !std::isfinite(rr)) {
@@ -968,7 +973,7 @@ tcf_status solve_refined(tcf_grid* g, double* p, int kind, int* iters, int* nref
     // from the first sweep of a multigrid hierarchy, else in a pass of its own
     FromR64 f64{g->r64, g->part[1], tau * tau, 0};
     const bool fused = F.lv.size() > 1;
-    init_flags(s, g->iflag);
+    if (!cleared) init_flags(s, g->iflag);
     if (!fused) {
       scale_to32(s, N, g->r64, g->scal, F.r, g->part[0]);
       finalize(s, g->part[0], nb1, g->scal, g->iflag, F_BB, 0, tau * tau);

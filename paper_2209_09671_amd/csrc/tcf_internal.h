@@ -197,11 +197,17 @@ void mg_tail(hipStream_t s, int dim, const MgTail<R>& T, const int* iflag);
 
 void finalize(hipStream_t s, const double* part, int nparts, double* scal, int* iflag, int op, int slot,
               double arg);
+// Two finalizes of nparts partials each in one launch (one block each); the
+// two must write different slots.
+void finalize2(hipStream_t s, const double* part0, const double* part1, int nparts, double* scal, int* iflag,
+               int op0, int slot0, double arg0, int op1, int slot1, double arg1);
 void init_flags(hipStream_t s, int* iflag);
 // Copies nwords 8-byte words from device memory src to host-coherent memory
 // dst (device-visible), then stores value into *ticket (host memory), in
-// that order as seen by the host.
-void publish(hipStream_t s, const void* src, int nwords, void* dst, unsigned* ticket, unsigned value);
+// that order as seen by the host; then clears the flags at reset_flags
+// (I_NFLAG ints, the copy holds their values before) unless it is null.
+void publish(hipStream_t s, const void* src, int nwords, void* dst, unsigned* ticket, unsigned value,
+             int* reset_flags = nullptr);
 
 // FP64 refinement helpers (FP32 mode)
 // r32 = r / scal[S_SCALE]; part: nblocks(256) partials of |r32|^2

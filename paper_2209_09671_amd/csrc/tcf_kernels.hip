@@ -1120,13 +1120,22 @@ __global__ __launch_bounds__(kTailThreads) void k_mg_tail(MgTail<R> T, const int
   }
 }
 
-// One-block deterministic finalize of per-block partials: each of the 1024
-// threads folds a fixed strided subset with four independent accumulators,
-// then the block reduces in a fixed order.
-__global__ __launch_bounds__(1024) void k_finalize(const double* __restrict__ part, int n,
-                                                   double* __restrict__ scal, int* __restrict__ iflag, int op,
-                                                   int slot, double arg) {
+// Deterministic finalize of per-block partials, one block per reduction
+// (block b takes job b): each of the 1024 threads folds a fixed strided
+// subset with four independent accumulators, then the block reduces in a
+// fixed order.  The jobs of one launch write different slots.
+struct FinJob {
+  const double* part;
+  int n, op, slot;
+  double arg;
+};
+__global__ __launch_bounds__(1024) void k_finalize(FinJob j0, FinJob j1, double* __restrict__ scal,
+                                                   int* __restrict__ iflag) {
   __shared__ double sh[16];
+  const FinJob& J = blockIdx.x == 0 ? j0 : j1;
+  const double* __restrict__ part = J.part;
+  const int n = J.n, op = J.op, slot = J.slot;
+  const double arg = J.arg;
   // the done flag is loaded with the partials and tested before the reduction
   const bool gated = op == F_RR;
   const int done = gated ? iflag[I_DONE] : 0;
@@ -1176,11 +1185,15 @@ __global__ __launch_bounds__(1024) void k_finalize(const double* __restrict__ pa
 // host memory that the host polls, then the ticket it waits for.  One
 // wavefront: its fence covers every store of the copy, so the host that
 // sees the ticket sees the block.
-__global__ __launch_bounds__(64) void k_publish(const unsigned long long* __restrict__ src, int nwords,
-                                                unsigned long long* dst, unsigned* ticket, unsigned value) {
+// With reset set, the flags (reset[0 .. I_NFLAG)) are cleared after they
+// have been copied.
+__global__ __launch_bounds__(64) void k_publish(const unsigned long long* src, int nwords,
+                                                unsigned long long* dst, unsigned* ticket, unsigned value,
+                                                int* reset) {
   for (int q = threadIdx.x; q < nwords; q += 64) dst[q] = src[q];
   __threadfence_system();
   if (threadIdx.x == 0) __hip_atomic_store(ticket, value, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  if (reset && threadIdx.x < I_NFLAG) reset[threadIdx.x] = 0;
 }
 
 __global__ void k_init_flags(int* iflag) {
@@ -1774,14 +1787,22 @@ template void coarse_apply<float>(hipStream_t, int, const float*, const float*, 
 
 void finalize(hipStream_t s, const double* part, int nparts, double* scal, int* iflag, int op, int slot,
               double arg) {
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, s, part, nparts, scal, iflag, op, slot, arg);
+  const FinJob j{part, nparts, op, slot, arg};
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, s, j, j, scal, iflag);
+}
+
+void finalize2(hipStream_t s, const double* part0, const double* part1, int nparts, double* scal, int* iflag,
+               int op0, int slot0, double arg0, int op1, int slot1, double arg1) {
+  const FinJob j0{part0, nparts, op0, slot0, arg0}, j1{part1, nparts, op1, slot1, arg1};
+  hipLaunchKernelGGL(k_finalize, dim3(2), dim3(1024), 0, s, j0, j1, scal, iflag);
 }
 
 void init_flags(hipStream_t s, int* iflag) { hipLaunchKernelGGL(k_init_flags, dim3(1), dim3(64), 0, s, iflag); }
 
-void publish(hipStream_t s, const void* src, int nwords, void* dst, unsigned* ticket, unsigned value) {
+void publish(hipStream_t s, const void* src, int nwords, void* dst, unsigned* ticket, unsigned value,
+             int* reset_flags) {
   hipLaunchKernelGGL(k_publish, dim3(1), dim3(64), 0, s, (const unsigned long long*)src, nwords,
-                     (unsigned long long*)dst, ticket, value);
+                     (unsigned long long*)dst, ticket, value, reset_flags);
 }
 
 template <class R>
