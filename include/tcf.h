@@ -165,7 +165,13 @@ size_t tcf_workspace_bytes(const tcf_config* cfg);
 
 /* Validate cfg and carve the caller's workspace (device memory, 256-byte
  * aligned, at least tcf_workspace_bytes bytes).  hip_stream is a hipStream_t
- * (NULL = default stream).  *out receives a host-side handle. */
+ * (NULL = default stream).  *out receives a host-side handle.  Besides the
+ * workspace the grid holds a 320-byte block of pinned host memory, mapped
+ * and coherent, into which the device writes the solver scalars the host
+ * reads (the host polls it, querying the stream now and then, so that a
+ * failed stream ends the wait with TCF_E_DEVICE), a second stream of the
+ * current device for work that overlaps within a step, and three events;
+ * tcf_destroy releases them.  TCF_E_DEVICE if any of them cannot be made. */
 tcf_status tcf_init_grid(const tcf_config* cfg, void* workspace, size_t bytes, void* hip_stream,
                          tcf_grid** out);
 
