@@ -1,6 +1,7 @@
 """Build libtcf.so (HIP kernels + host library + C ABI) for gfx950 in-tree."""
 from __future__ import annotations
 
+import concurrent.futures
 import os
 import subprocess
 import sys
@@ -22,8 +23,7 @@ def build(verbose: bool = False, defines=(), out: str | None = None) -> str:
     """Compile every source and link libtcf.so (or `out`); `defines` are
     extra -D options (tuning variants)."""
     lib = out or LIB
-    objs = []
-    for src in SOURCES:
+    def compile_one(src):
         path = os.path.join(CSRC, src)
         obj = os.path.join(os.path.dirname(lib), os.path.splitext(src)[0] + ".o")
         lang = ["-x", "hip"] if src.endswith(".cpp") else []
@@ -36,7 +36,12 @@ def build(verbose: bool = False, defines=(), out: str | None = None) -> str:
             if e.stderr:
                 sys.stderr.write(e.stderr)
             raise
-        objs.append(obj)
+        return obj
+
+    # the sources compile independently: one hipcc per source, side by side
+    workers = max(1, min(len(SOURCES), os.cpu_count() or 1, 8))
+    with concurrent.futures.ThreadPoolExecutor(max_workers=workers) as ex:
+        objs = list(ex.map(compile_one, SOURCES))
     tmp = lib + ".tmp"
     subprocess.run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-Wl,-z,defs", "-o", tmp] + objs, check=True)
     os.replace(tmp, lib)

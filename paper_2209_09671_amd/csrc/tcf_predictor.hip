@@ -40,8 +40,11 @@ constexpr int NHALO = 2 * H * TY + 2 * H * TX;
 __device__ __forceinline__ float rcpx(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ double rcpx(double x) { return 1.0 / x; }
 
-// WENO5-JS reconstruction at the right edge of c, with one reciprocal for
-// the normalisation of each smoothness weight and one for the blend.  With
+// WENO5-JS reconstruction at the right edge of c, with one reciprocal: the
+// nonlinear weights d_k / x_k^2 (x_k = eps + beta_k) are put over the common
+// denominator (x_0 x_1 x_2)^2 and scaled by 10 (d = 1, 6, 3); in FP32 the
+// x_k are first scaled by a power of two (wscale) that keeps the products in
+// range.  With
 // t_k the second differences and u_k the one-sided differences of the three
 // candidate stencils, the candidates' values are c + (t_0 + 3 u_0)/12,
 // c + (t_1 - 3 u_1)/12 and c + (t_2 - 3 u_2)/12: the blend is c plus the
@@ -49,16 +52,32 @@ __device__ __forceinline__ double rcpx(double x) { return 1.0 / x; }
 // beta_k = (13/12) t_k^2 + (1/4) u_k^2 and epsilon are both taken times
 // 12/13 (eps_w = (12/13) eps), which leaves the normalised weights
 // d_k / (eps + beta_k)^2 unchanged: one multiply and two FMAs per indicator.
+// FP32: the three smoothness terms are scaled by one power of two that
+// brings the largest into [1/2, 1) (exact, so the normalised weights are
+// unchanged), which keeps the products of the common denominator in range;
+// a term below 1e-19 of the largest then has a weight that underflows to
+// zero, against weights of order 1.  FP64 needs no scaling.
+__device__ __forceinline__ void wscale(float& x0, float& x1, float& x2) {
+  const int e = __builtin_amdgcn_frexp_expf(fmaxf(x0, fmaxf(x1, x2)));
+  x0 = __builtin_amdgcn_ldexpf(x0, -e);
+  x1 = __builtin_amdgcn_ldexpf(x1, -e);
+  x2 = __builtin_amdgcn_ldexpf(x2, -e);
+}
+__device__ __forceinline__ void wscale(double&, double&, double&) {}
+
 template <class R>
 __device__ __forceinline__ R weno5r(R a, R b, R c, R d, R e, R epsw) {
   const R t0 = a - R(2) * b + c, u0 = a - R(4) * b + R(3) * c;
   const R t1 = b - R(2) * c + d, u1 = b - d;
   const R t2 = c - R(2) * d + e, u2 = R(3) * c - R(4) * d + e;
   const R cu = R(3.0 / 13.0);
-  const R i0 = rcpx(fma(cu * u0, u0, fma(t0, t0, epsw)));
-  const R i1 = rcpx(fma(cu * u1, u1, fma(t1, t1, epsw)));
-  const R i2 = rcpx(fma(cu * u2, u2, fma(t2, t2, epsw)));
-  const R a0 = R(0.1) * i0 * i0, a1 = R(0.6) * i1 * i1, a2 = R(0.3) * i2 * i2;
+  const R x0 = fma(cu * u0, u0, fma(t0, t0, epsw));
+  const R x1 = fma(cu * u1, u1, fma(t1, t1, epsw));
+  const R x2 = fma(cu * u2, u2, fma(t2, t2, epsw));
+  R y0 = x0, y1 = x1, y2 = x2;
+  wscale(y0, y1, y2);
+  const R p12 = y1 * y2, p02 = y0 * y2, p01 = y0 * y1;
+  const R a0 = p12 * p12, a1 = R(6) * p02 * p02, a2 = R(3) * p01 * p01;
   const R sc = fma(a2, fma(R(-3), u2, t2), fma(a1, fma(R(-3), u1, t1), a0 * fma(R(3), u0, t0)));
   return fma(sc, rcpx(R(12) * (a0 + a1 + a2)), c);
 }
