@@ -114,6 +114,35 @@ def test_fp32_transport_only_increments(case):
         assert ef[k] <= 3e-6, (k, ef)
 
 
+def test_fp32_transport_steep_temperature_jump():
+    """The FP32 WENO5 weights are formed over a common denominator, products
+    of two smoothness terms squared, which overflow FP32 once two terms of a
+    stencil exceed about 1e9.  A temperature step of 1e5 across a plane (on
+    the ragged melt pool, advected by the 3D stream flow at CFL 0.25 for 20
+    transport-only steps) gives smoothness terms of at least the squared
+    jump, 1e10, in every stencil that crosses it, so without the
+    power-of-two scaling of the terms the products would overflow and the
+    step would fail as non-finite.  alpha and T increments within 1e-4 of the
+    oracle's, as in the transport-only test."""
+    c, dt = _meltpool_ragged()
+    st = flow_state(c, 0.25, dt)
+    T = st["T"].reshape(c["nz"], c["ny"], c["nx"]).copy()
+    T[:, :, c["nx"] // 2:] += 1e5
+    st["T"] = f32(T.reshape(st["T"].shape))
+    jump = np.abs(np.diff(T, axis=2)).max()
+    assert jump >= 1e5 - 1, jump  # smoothness terms >= jump^2 = 1e10 at the step
+    g, info = gpu_run(c, st, dt, 20, flags=tcf.TCF_TRANSPORT_ONLY)
+    assert info["status"] == 0, info
+    o, _, ost = O.step(c, st, 0.0, dt, 20, flags=O.F_TRANSPORT_ONLY)
+    assert ost == 0
+    e, sig = increment_errors(g, o, st, ("alpha", "T"))
+    print("[fp32 transport, T jump 1e5] increment errors", e, "signal", sig, flush=True)
+    for k in ("alpha", "T"):
+        assert np.isfinite(g[k]).all(), k
+        assert sig[k] >= 1e-2, (k, sig)
+        assert e[k] <= 1e-4, (k, e)
+
+
 # ---------------------------------------------------------------------------
 # S2-S5: geometry, CSF force, WENO5 momentum convection and viscous stress in
 # FP32 with a nonzero u^n (Navier-Stokes, Section "Theory"; eqs. 4-7).
