@@ -67,7 +67,10 @@ __device__ __forceinline__ void wscale(float& x0, float& x1, float& x2) {
 }
 __device__ __forceinline__ void wscale(double&, double&, double&) {}
 
-template <class R>
+// SC: scale the smoothness terms (wscale); a field of order one (the
+// two-phase volume fraction, whose terms stay below about 30) needs no
+// scaling.
+template <bool SC, class R>
 __device__ __forceinline__ R weno5x(R a, R b, R c, R d, R e, R epsw) {
   const R t0 = a - R(2) * b + c, u0 = a - R(4) * b + R(3) * c;
   const R t1 = b - R(2) * c + d, u1 = b - d;
@@ -77,7 +80,7 @@ __device__ __forceinline__ R weno5x(R a, R b, R c, R d, R e, R epsw) {
   const R x1 = fma(cu * u1, u1, fma(t1, t1, epsw));
   const R x2 = fma(cu * u2, u2, fma(t2, t2, epsw));
   R y0 = x0, y1 = x1, y2 = x2;
-  wscale(y0, y1, y2);
+  if (SC) wscale(y0, y1, y2);
   const R p12 = y1 * y2, p02 = y0 * y2, p01 = y0 * y1;
   const R a0 = p12 * p12, a1 = R(6) * p02 * p02, a2 = R(3) * p01 * p01;
   const R sc = fma(a2, fma(R(-3), u2, t2), fma(a1, fma(R(-3), u1, t1), a0 * fma(R(3), u0, t0)));
@@ -86,10 +89,10 @@ __device__ __forceinline__ R weno5x(R a, R b, R c, R d, R e, R epsw) {
 
 // q[m] = Q(f-3+m); value at face f, upwind by the sign of vel.  The stencil
 // is picked before the one WENO5 evaluation, so lanes of both signs share it.
-template <class R>
+template <bool SC = true, class R>
 __device__ __forceinline__ R upw(R q0, R q1, R q2, R q3, R q4, R q5, R vel, R eps) {
   const bool pos = vel >= R(0);
-  return weno5x(pos ? q0 : q5, pos ? q1 : q4, pos ? q2 : q3, pos ? q3 : q2, pos ? q4 : q1, eps);
+  return weno5x<SC>(pos ? q0 : q5, pos ? q1 : q4, pos ? q2 : q3, pos ? q3 : q2, pos ? q4 : q1, eps);
 }
 
 // halo slot -> (ox, oy) offset in the LDS tile (0..SX-1, 0..SY-1)
@@ -159,6 +162,7 @@ __global__ __launch_bounds__(512, sizeof(R) == 4 ? 4 : 1) void k_transport2(KPar
                                                     const R* __restrict__ w, R* ao, R* To, R cb, R ci,
                                                     const R* __restrict__ rc, const R* __restrict__ dq) {
   constexpr bool WT = MODE != 0, WA = MODE != 2;
+  constexpr bool SCA = MODE != 1;  // the two-phase alpha's WENO5 terms need no scaling
   constexpr int NF = WT ? 2 : 1;                   // LDS fields: the alpha slot, T
   constexpr int NEF = (WA ? 1 : 0) + (WT ? 1 : 0);  // transported fields
   __shared__ R sq[NF][2][SY][SX];                  // [field][buffer][row][column]
@@ -304,9 +308,9 @@ __global__ __launch_bounds__(512, sizeof(R) == 4 ? 4 : 1) void k_transport2(KPar
       // tile holds the ghost values there) and the wall faces are dropped by
       // selects, without exec-mask updates around the evaluations
       if (WA) {
-        const R fx = cur.u * upw(sa[buf][Y][X - 3], sa[buf][Y][X - 2], sa[buf][Y][X - 1], sa[buf][Y][X],
+        const R fx = cur.u * upw<SCA>(sa[buf][Y][X - 3], sa[buf][Y][X - 2], sa[buf][Y][X - 1], sa[buf][Y][X],
                                  sa[buf][Y][X + 1], sa[buf][Y][X + 2], cur.u, eps);
-        const R fy = cur.v * upw(sa[buf][Y - 3][X], sa[buf][Y - 2][X], sa[buf][Y - 1][X], sa[buf][Y][X],
+        const R fy = cur.v * upw<SCA>(sa[buf][Y - 3][X], sa[buf][Y - 2][X], sa[buf][Y - 1][X], sa[buf][Y][X],
                                  sa[buf][Y + 1][X], sa[buf][Y + 2][X], cur.v, eps);
         Fxa_lo = i > 0 ? fx : R(0);
         Fya_lo = j > 0 ? fy : R(0);
@@ -358,7 +362,7 @@ __global__ __launch_bounds__(512, sizeof(R) == 4 ? 4 : 1) void k_transport2(KPar
           fzt_lo = R(0);
           if (k > 0) {
             if (WA)
-              fza_lo = wL0 * upw(qa[o + 0], qa[o + 1], qa[o + 2], qa[o + 3], qa[o + 4], qa[o + 5], wL0, eps);
+              fza_lo = wL0 * upw<SCA>(qa[o + 0], qa[o + 1], qa[o + 2], qa[o + 3], qa[o + 4], qa[o + 5], wL0, eps);
             if (WT)
               fzt_lo = wL0 * upw(qt[o + 0], qt[o + 1], qt[o + 2], qt[o + 3], qt[o + 4], qt[o + 5], wL0, eps);
           }
@@ -366,7 +370,7 @@ __global__ __launch_bounds__(512, sizeof(R) == 4 ? 4 : 1) void k_transport2(KPar
         R fza_hi = R(0), fzt_hi = R(0);
         if (k + 1 < nz) {
           if (WA)
-            fza_hi = cur.w * upw(qa[o + 1], qa[o + 2], qa[o + 3], qa[o + 4], qa[o + 5], qa[o + 6], cur.w, eps);
+            fza_hi = cur.w * upw<SCA>(qa[o + 1], qa[o + 2], qa[o + 3], qa[o + 4], qa[o + 5], qa[o + 6], cur.w, eps);
           if (WT)
             fzt_hi = cur.w * upw(qt[o + 1], qt[o + 2], qt[o + 3], qt[o + 4], qt[o + 5], qt[o + 6], cur.w, eps);
         }
